@@ -1,0 +1,255 @@
+"""CPU oracle for the dyGRASS batched walk path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The product
+library (``paper_2505_02741_amd``) never imports, links or executes anything
+here, and this package never imports the product library: the two share no
+code.  Inputs shared by both sides come from
+``paper_2505_02741_amd.workloads`` (seeded generators that hold none of the
+method's arithmetic).
+
+What the oracle computes, and where the paper states it
+(Yuan, Aghdaei, Feng, arXiv 2505.02741):
+
+* walk rule -- non-backtracking walk (Sec. III-B, "Non-Backtracking Random
+  Walks and Approximate Resistance Distance"), accumulating the resistance
+  sum of 1/w along the path; stop when w_pq * R exceeds K, after T steps, or
+  at a leaf (Sec. III-B, the three termination conditions);
+* insertion decision -- keep the new edge iff no walker reaches q
+  (Sec. III-B bullets; Algorithm 1, insertion branch);
+* deletion repair -- walkers on the updated original graph, the minimum-
+  resistance hitting path (Eq. 12) has its edges that are not already in the
+  sparsifier recovered (Sec. III-C; Algorithm 1, deletion branch); with no
+  hit a few local edges are recovered (Sec. III-C, last paragraph);
+* batching -- updates are applied at the end of a batch (Sec. III-F).
+
+The readings of what the paper leaves open (weight bias, quantised weights,
+the random-number layout, the fallback edge choice, phase order) are fixed in
+the C source header comments and mirrored in the tests.
+
+The walk itself is in ``dyg_oracle.c`` (plain C, built by ``oracle/build.py``).
+Dense spectral quantities used by the pins live in ``oracle/spectral.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# DYG_ORACLE_LIB lets the mutation test load a deliberately broken build
+LIB_PATH = os.environ.get("DYG_ORACLE_LIB") or os.path.join(HERE, "libdyg_oracle.so")
+
+ERRORS = {
+    0: "OK",
+    -1: "INVALID_ARG",
+    -2: "SELF_LOOP",
+    -3: "VERTEX_RANGE",
+    -4: "BAD_WEIGHT",
+    -5: "EDGE_EXISTS",
+    -6: "EDGE_MISSING",
+    -7: "DUPLICATE_IN_BATCH",
+    -8: "H_NOT_SUBSET",
+    -9: "NOMEM",
+}
+
+_lib = None
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {code} ({ERRORS.get(code, '?')})")
+        self.code = code
+        self.name = ERRORS.get(code, "?")
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH) and "DYG_ORACLE_LIB" not in os.environ:
+        from . import build as _b
+
+        _b.build()
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    u8p = C.POINTER(C.c_uint8)
+    lib.orc_philox4x32_10.argtypes = [P, P, P]
+    lib.orc_philox4x64_10.argtypes = [P, P, P]
+    lib.orc_step_random.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]
+    lib.orc_step_random.restype = C.c_uint64
+    lib.orc_quantize.argtypes = [C.c_double, C.c_double, C.c_int]
+    lib.orc_quantize.restype = C.c_uint32
+    lib.orc_walk_csr.argtypes = [C.c_uint32, P, P, P, C.c_double, C.c_int, C.c_uint32,
+                                 C.c_uint32, C.c_int, C.c_double, C.c_double, C.c_uint32,
+                                 C.c_uint32, C.c_uint64, C.c_uint64, C.c_int, P, P, P, P, P]
+    lib.orc_walk_csr.restype = C.c_int
+    lib.orc_create.argtypes = [C.c_uint32, P, P, P, C.c_uint64, P, P, C.c_uint64,
+                               C.c_double, C.c_uint32, C.c_uint32, C.c_int, C.c_double,
+                               C.c_int, C.c_uint64, C.POINTER(C.c_int)]
+    lib.orc_create.restype = P
+    lib.orc_destroy.argtypes = [P]
+    lib.orc_uid_base.argtypes = [P]
+    lib.orc_uid_base.restype = C.c_uint64
+    lib.orc_w_ref.argtypes = [P]
+    lib.orc_w_ref.restype = C.c_double
+    lib.orc_apply_batch.argtypes = [P, C.c_uint64, P, P, P, C.c_uint64, P, P, P, P,
+                                    P, P, P, P, P, P, P, P, P, P]
+    lib.orc_apply_batch.restype = C.c_int
+    lib.orc_query.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(C.c_uint64), P, P, P]
+    lib.orc_query.restype = C.c_int
+    del u8p
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+# --------------------------------------------------------------------------
+# primitives
+
+
+def philox4x32_10(ctr, key):
+    lib = _load()
+    c = _arr(ctr, np.uint32)
+    k = _arr(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib.orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def philox4x64_10(ctr, key):
+    lib = _load()
+    c = _arr(ctr, np.uint64)
+    k = _arr(key, np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib.orc_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def step_random(seed: int, uid: int, walker: int, t: int) -> int:
+    return int(_load().orc_step_random(seed, uid, walker, t))
+
+
+def quantize(w: float, w_ref: float, Q: int = 24) -> int:
+    return int(_load().orc_quantize(w, w_ref, Q))
+
+
+def walk_csr(n, rowptr, col, w, p, q, *, s, L, seed=0, uid=0, K=math.inf, w_pq=1.0,
+             use_K=False, Q=24, w_ref=None, bounce=False):
+    """Run s walkers from p towards q on a static graph (symmetric CSR).
+    Returns dict of per-walker hit, steps, end, R and trajectories (s, L+1)."""
+    lib = _load()
+    rowptr = _arr(rowptr, np.uint64)
+    col = _arr(col, np.uint32)
+    w = _arr(w, np.float64)
+    if w_ref is None:
+        w_ref = float(w.max()) if w.size else 1.0
+    hit = np.zeros(s, np.uint8)
+    steps = np.zeros(s, np.uint16)
+    end = np.zeros(s, np.uint32)
+    R = np.zeros(s, np.float64)
+    traj = np.full((s, L + 1), 0xFFFFFFFF, np.uint32)
+    rc = lib.orc_walk_csr(n, _ptr(rowptr), _ptr(col), _ptr(w), float(w_ref), Q, p, q,
+                          int(use_K), float(w_pq), float(K), s, L, seed, uid, int(bounce),
+                          _ptr(hit), _ptr(steps), _ptr(end), _ptr(R), _ptr(traj))
+    if rc:
+        raise OracleError(rc)
+    return dict(hit=hit.astype(bool), steps=steps.astype(np.int64), end=end, R=R, traj=traj)
+
+
+# --------------------------------------------------------------------------
+# full state
+
+
+class Oracle:
+    """Sequence of batches on (G, H) exactly as the batch rules define them."""
+
+    def __init__(self, n, rowptr, col, w, hu, hv, *, seed, K=math.inf, s=8, L=16, Q=24,
+                 w_ref=0.0, dead_end=0, uid_base=0):
+        lib = _load()
+        self.n = int(n)
+        rowptr = _arr(rowptr, np.uint64)
+        col = _arr(col, np.uint32)
+        w = _arr(w, np.float64)
+        hu = _arr(hu, np.uint32)
+        hv = _arr(hv, np.uint32)
+        err = C.c_int(0)
+        self._h = lib.orc_create(self.n, _ptr(rowptr), _ptr(col), _ptr(w), hu.size, _ptr(hu),
+                                 _ptr(hv), int(seed), float(K), int(s), int(L), int(Q),
+                                 float(w_ref), int(dead_end), int(uid_base), C.byref(err))
+        if not self._h:
+            raise OracleError(err.value)
+        self.s = int(s)
+        self.L = int(L)
+
+    def close(self):
+        if self._h:
+            _load().orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def uid_base(self) -> int:
+        return int(_load().orc_uid_base(self._h))
+
+    @property
+    def w_ref(self) -> float:
+        return float(_load().orc_w_ref(self._h))
+
+    def apply_batch(self, iu, iv, iw, du, dv, s=None, L=None, record_walkers=False):
+        lib = _load()
+        iu = _arr(iu, np.uint32)
+        iv = _arr(iv, np.uint32)
+        iw = _arr(iw, np.float64)
+        du = _arr(du, np.uint32)
+        dv = _arr(dv, np.uint32)
+        nu = iu.size + du.size
+        s_arr = None if s is None else _arr(s, np.uint16)
+        L_arr = None if L is None else _arr(L, np.uint16)
+        out = dict(flag=np.zeros(nu, np.uint8), any_hit=np.zeros(nu, np.uint8),
+                   winner=np.zeros(nu, np.uint16), n_rec=np.zeros(nu, np.uint16),
+                   steps=np.zeros(nu, np.uint32), Rmin=np.zeros(nu, np.float64))
+        wk = None
+        if record_walkers:
+            tot = int(s_arr.astype(np.int64).sum()) if s_arr is not None else nu * self.s
+            wk = dict(hit=np.zeros(tot, np.uint8), steps=np.zeros(tot, np.uint16),
+                      end=np.zeros(tot, np.uint32), R=np.zeros(tot, np.float64))
+        rc = lib.orc_apply_batch(self._h, iu.size, _ptr(iu), _ptr(iv), _ptr(iw), du.size,
+                                 _ptr(du), _ptr(dv), _ptr(s_arr), _ptr(L_arr),
+                                 _ptr(out["flag"]), _ptr(out["any_hit"]), _ptr(out["winner"]),
+                                 _ptr(out["n_rec"]), _ptr(out["steps"]), _ptr(out["Rmin"]),
+                                 _ptr(wk["hit"]) if wk else None,
+                                 _ptr(wk["steps"]) if wk else None,
+                                 _ptr(wk["end"]) if wk else None,
+                                 _ptr(wk["R"]) if wk else None)
+        if rc:
+            raise OracleError(rc)
+        out["walkers"] = wk
+        return out
+
+    def query(self, which="H"):
+        lib = _load()
+        m = C.c_uint64(0)
+        wh = 1 if which == "H" else 0
+        lib.orc_query(self._h, wh, 0, C.byref(m), None, None, None)
+        u = np.zeros(m.value, np.uint32)
+        v = np.zeros(m.value, np.uint32)
+        w = np.zeros(m.value, np.float64)
+        rc = lib.orc_query(self._h, wh, m.value, C.byref(m), _ptr(u), _ptr(v), _ptr(w))
+        if rc:
+            raise OracleError(rc)
+        return u, v, w

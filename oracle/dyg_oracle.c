@@ -1,0 +1,768 @@
+/*
+ * dyg_oracle.c -- plain, slow CPU oracle for the dyGRASS batched walk path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header or constant table with the HIP
+ * library: every formula below is written out again from the paper
+ * (Yuan, Aghdaei, Feng, "dyGRASS: Dynamic Spectral Graph Sparsification via
+ * Localized Random Walks on GPUs", arXiv 2505.02741) and, for the random
+ * numbers, from Salmon, Moraes, Dror and Shaw, "Parallel Random Numbers: As
+ * Easy as 1, 2, 3" (SC'11).
+ *
+ * Data structures are deliberately naive: one sorted, malloc'd neighbour array
+ * per vertex, insertions and deletions by memmove.  Walk trajectories are kept
+ * whole, so the minimum-resistance path of a deletion is read back from the
+ * stored trajectory rather than replayed.
+ *
+ * Floating point: the only FP operations are 1/w, w/w_ref*2^Q (host, once per
+ * edge), R += r (strictly sequential per walker) and w*R > K.  Build with
+ * -ffp-contract=off and without fast-math.
+ *
+ * Readings of what the paper leaves open:
+ *  - neighbour choice is weight-biased, P(c) proportional to w(x,c), through
+ *    integer weights qw = round-half-even(w / w_ref * 2^Q) and an exact
+ *    integer cumulative search in ascending neighbour order; the 64-bit random
+ *    number r picks target = floor(r * total / 2^64) and the first neighbour
+ *    whose running sum exceeds target;
+ *  - random numbers are Philox-4x32-10 keyed by the seed, counter
+ *    (t/2, walker, uid), one block serving two steps;
+ *  - a walker entering a vertex whose only neighbour is the previous one stops
+ *    (the leaf condition of Sec. III-B); an optional policy steps back instead;
+ *  - when the arriving step both reaches q and makes w*R exceed K, the walker
+ *    misses: q must be reached within K; equality is within;
+ *  - all walkers start at the first endpoint as given;
+ *  - deletions walk only when the edge is in H (Sec. III-C, Algorithm 1);
+ *  - batch order: deletions leave G and H first, then every walk reads that
+ *    snapshot, then insertions, accepted edges and recovered edges are added;
+ *  - the recovered path is the winner's edges in path order, first
+ *    occurrence, without loop erasure, those not in H; the winner is the
+ *    hitting walker of least R, ties to the lower walker index;
+ *  - with no hit, per endpoint the least-resistance G edge not in H (ties to
+ *    the smaller neighbour id) is recovered: "a few local edges" (Sec. III-C).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Error codes (kept equal by name and value to the library's, the tests    */
+/* compare them; the numbers are restated here, not included).              */
+enum {
+  ORC_OK = 0,
+  ORC_INVALID_ARG = -1,
+  ORC_SELF_LOOP = -2,
+  ORC_VERTEX_RANGE = -3,
+  ORC_BAD_WEIGHT = -4,
+  ORC_EDGE_EXISTS = -5,
+  ORC_EDGE_MISSING = -6,
+  ORC_DUPLICATE_IN_BATCH = -7,
+  ORC_H_NOT_SUBSET = -8,
+  ORC_NOMEM = -9
+};
+
+#define ORC_MAX_WALKERS 1024u
+#define ORC_MAX_STEPS 1024u
+
+/* ------------------------------------------------------------------------ */
+/* Philox-4xW-10 (SC'11, Sec. 4).  One round maps counter (c0,c1,c2,c3) with */
+/* round key (k0,k1) to (hi(M1*c2)^c1^k0, lo(M1*c2), hi(M0*c0)^c3^k1,        */
+/* lo(M0*c0)); the key is bumped by the Weyl constants between rounds.       */
+
+static void mulhilo32(uint32_t a, uint32_t b, uint32_t *hi, uint32_t *lo) {
+  uint64_t p = (uint64_t)a * (uint64_t)b;
+  *hi = (uint32_t)(p >> 32);
+  *lo = (uint32_t)p;
+}
+
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
+  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                       uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint32_t hi0, lo0, hi1, lo1;
+    mulhilo32(M0, c[0], &hi0, &lo0);
+    mulhilo32(M1, c[2], &hi1, &lo1);
+    uint32_t n0 = hi1 ^ c[1] ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c[3] ^ k1;
+    uint32_t n3 = lo0;
+    c[0] = n0;
+    c[1] = n1;
+    c[2] = n2;
+    c[3] = n3;
+  }
+  memcpy(out, c, sizeof c);
+}
+
+void orc_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2],
+                       uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint64_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(M0, c[0], &hi0, &lo0);
+    mulhilo64(M1, c[2], &hi1, &lo1);
+    uint64_t n0 = hi1 ^ c[1] ^ k0;
+    uint64_t n1 = lo1;
+    uint64_t n2 = hi0 ^ c[3] ^ k1;
+    uint64_t n3 = lo0;
+    c[0] = n0;
+    c[1] = n1;
+    c[2] = n2;
+    c[3] = n3;
+  }
+  memcpy(out, c, sizeof c);
+}
+
+/* The 64-bit random number a walker draws at step t.  Counter words are     */
+/* (t/2, walker, uid low, uid high), key words (seed low, seed high); even   */
+/* steps take output words 0,1 and odd steps words 2,3 (low word first).     */
+uint64_t orc_step_random(uint64_t seed, uint64_t uid, uint32_t walker,
+                         uint32_t t) {
+  uint32_t ctr[4] = {t >> 1, walker, (uint32_t)uid, (uint32_t)(uid >> 32)};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t x[4];
+  orc_philox4x32_10(ctr, key, x);
+  uint32_t lo = x[2 * (t & 1u)], hi = x[2 * (t & 1u) + 1];
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+/* Quantised weight used for the weight-biased neighbour choice:             */
+/* round-half-even(w / w_ref * 2^Q), clamped to [1, 2^32-1].                 */
+uint32_t orc_quantize(double w, double w_ref, int Q) {
+  double y = nearbyint((w / w_ref) * ldexp(1.0, Q));
+  if (!(y >= 1.0)) return 1u;
+  if (y > 4294967295.0) return 4294967295u;
+  return (uint32_t)y;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Graph: per-vertex sorted neighbour arrays.                               */
+
+typedef struct {
+  uint32_t nbr;
+  uint32_t qw;
+  double w;
+  double r; /* 1/w */
+} oent;
+
+typedef struct {
+  oent *e;
+  uint32_t len, cap;
+} orow;
+
+typedef struct {
+  uint32_t n;
+  orow *rows;
+} ograph;
+
+static int og_init(ograph *g, uint32_t n) {
+  g->n = n;
+  g->rows = (orow *)calloc(n ? n : 1, sizeof(orow));
+  return g->rows ? 0 : -1;
+}
+
+static void og_free(ograph *g) {
+  if (!g->rows) return;
+  for (uint32_t i = 0; i < g->n; ++i) free(g->rows[i].e);
+  free(g->rows);
+  g->rows = NULL;
+}
+
+/* index of nbr v in row u, or -1 */
+static long og_find(const ograph *g, uint32_t u, uint32_t v) {
+  const orow *r = &g->rows[u];
+  long lo = 0, hi = (long)r->len - 1;
+  while (lo <= hi) {
+    long mid = (lo + hi) / 2;
+    if (r->e[mid].nbr == v) return mid;
+    if (r->e[mid].nbr < v) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+static int og_has(const ograph *g, uint32_t u, uint32_t v) {
+  return og_find(g, u, v) >= 0;
+}
+
+static int og_add_half(ograph *g, uint32_t u, const oent *x) {
+  orow *r = &g->rows[u];
+  if (r->len == r->cap) {
+    uint32_t nc = r->cap ? 2 * r->cap : 4;
+    oent *ne = (oent *)realloc(r->e, (size_t)nc * sizeof(oent));
+    if (!ne) return -1;
+    r->e = ne;
+    r->cap = nc;
+  }
+  /* first position whose neighbour id exceeds the new one */
+  uint32_t lo = 0, hi = r->len;
+  while (lo < hi) {
+    uint32_t mid = lo + (hi - lo) / 2;
+    if (r->e[mid].nbr < x->nbr) lo = mid + 1;
+    else hi = mid;
+  }
+  uint32_t pos = lo;
+  memmove(&r->e[pos + 1], &r->e[pos], (size_t)(r->len - pos) * sizeof(oent));
+  r->e[pos] = *x;
+  r->len++;
+  return 0;
+}
+
+static int og_add(ograph *g, uint32_t u, uint32_t v, double w, double r,
+                  uint32_t qw) {
+  oent a = {v, qw, w, r}, b = {u, qw, w, r};
+  if (og_add_half(g, u, &a)) return -1;
+  if (og_add_half(g, v, &b)) return -1;
+  return 0;
+}
+
+static void og_remove_half(ograph *g, uint32_t u, uint32_t v) {
+  long i = og_find(g, u, v);
+  if (i < 0) return;
+  orow *r = &g->rows[u];
+  memmove(&r->e[i], &r->e[i + 1], (size_t)(r->len - (uint32_t)i - 1) * sizeof(oent));
+  r->len--;
+}
+
+static void og_remove(ograph *g, uint32_t u, uint32_t v) {
+  og_remove_half(g, u, v);
+  og_remove_half(g, v, u);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One non-backtracking, weight-biased walker (Sec. III-B; Sec. III-C for    */
+/* the deletion mode, Sec. III-F for the per-step procedure).               */
+
+typedef struct {
+  uint8_t hit;
+  uint16_t steps;
+  uint32_t end;
+  double R;
+} owalk;
+
+/* traj (optional) receives x_0..x_steps (steps+1 vertices). */
+static void o_walk_one(const ograph *X, uint32_t p, uint32_t q, int has_K,
+                       double w_pq, double K, uint32_t L, uint64_t seed,
+                       uint64_t uid, uint32_t walker, int bounce, owalk *res,
+                       uint32_t *traj) {
+  uint32_t x = p;
+  long prev = -1; /* no previous vertex before the first step */
+  double R = 0.0;
+  uint8_t hit = 0;
+  uint32_t steps = 0;
+  if (traj) traj[0] = p;
+  for (uint32_t t = 0; t < L; ++t) {
+    const orow *row = &X->rows[x];
+    /* candidates: every neighbour except the vertex we just came from */
+    uint64_t tot = 0;
+    for (uint32_t i = 0; i < row->len; ++i)
+      if ((long)row->e[i].nbr != prev) tot += row->e[i].qw;
+    int forced_back = 0;
+    if (tot == 0) {
+      /* leaf / dead end: stop, or (optional policy) step back */
+      if (bounce && prev >= 0) forced_back = 1;
+      else break;
+    }
+    uint32_t chosen = 0;
+    double r = 0.0;
+    if (forced_back) {
+      long i = og_find(X, x, (uint32_t)prev);
+      chosen = (uint32_t)prev;
+      r = row->e[i].r;
+    } else {
+      uint64_t rnd = orc_step_random(seed, uid, walker, t);
+      uint64_t target =
+          (uint64_t)(((unsigned __int128)rnd * (unsigned __int128)tot) >> 64);
+      uint64_t run = 0;
+      int found = 0;
+      for (uint32_t i = 0; i < row->len; ++i) {
+        if ((long)row->e[i].nbr == prev) continue;
+        run += row->e[i].qw;
+        if (run > target) {
+          chosen = row->e[i].nbr;
+          r = row->e[i].r;
+          found = 1;
+          break;
+        }
+      }
+      if (!found) abort(); /* impossible: target < tot */
+    }
+    R = R + r;
+    prev = (long)x;
+    x = chosen;
+    steps++;
+    if (traj) traj[steps] = x;
+    if (has_K && w_pq * R > K) break; /* distortion threshold exceeded */
+    if (x == q) {
+      hit = 1;
+      break;
+    }
+  }
+  res->hit = hit;
+  res->steps = (uint16_t)steps;
+  res->end = x;
+  res->R = R;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Standalone walk on a static graph given as a symmetric CSR (used by the   */
+/* pins on tiny graphs).  rowptr has n+1 entries; col/w hold both directions */
+/* of every edge, each row sorted ascending.                                */
+
+int orc_walk_csr(uint32_t n, const uint64_t *rowptr, const uint32_t *col,
+                 const double *w, double w_ref, int Q, uint32_t p, uint32_t q,
+                 int has_K, double w_pq, double K, uint32_t s, uint32_t L,
+                 uint64_t seed, uint64_t uid, int bounce, uint8_t *hit,
+                 uint16_t *steps, uint32_t *end, double *R, uint32_t *traj) {
+  ograph g;
+  if (p >= n || q >= n) return ORC_VERTEX_RANGE;
+  if (og_init(&g, n)) return ORC_NOMEM;
+  for (uint32_t u = 0; u < n; ++u) {
+    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      oent e = {col[k], orc_quantize(w[k], w_ref, Q), w[k], 1.0 / w[k]};
+      if (og_add_half(&g, u, &e)) {
+        og_free(&g);
+        return ORC_NOMEM;
+      }
+    }
+  }
+  for (uint32_t k = 0; k < s; ++k) {
+    owalk res;
+    o_walk_one(&g, p, q, has_K, w_pq, K, L, seed, uid, k, bounce, &res,
+               traj ? traj + (size_t)k * (L + 1) : NULL);
+    hit[k] = res.hit;
+    steps[k] = res.steps;
+    end[k] = res.end;
+    R[k] = res.R;
+  }
+  og_free(&g);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full oracle state and Algorithm 1 with batch-deferred updates (Sec. III-F: */
+/* the GPU version applies the updates of a batch at the end of the batch).  */
+
+typedef struct {
+  uint32_t n;
+  ograph G, H;
+  uint64_t seed;
+  double K;
+  int has_K;
+  uint16_t s_def, L_def;
+  int Q;
+  double w_ref;
+  int bounce;
+  uint64_t uid_base;
+} oracle_t;
+
+static uint64_t ekey(uint32_t u, uint32_t v) {
+  uint32_t a = u < v ? u : v, b = u < v ? v : u;
+  return ((uint64_t)a << 32) | b;
+}
+
+typedef struct {
+  uint64_t key;
+  uint64_t idx;
+} okeyidx;
+
+static int cmp_keyidx(const void *a, const void *b) {
+  const okeyidx *x = (const okeyidx *)a, *y = (const okeyidx *)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+/* dup[i] = 1 iff an earlier entry of u/v (lower index) is the same edge */
+static int o_mark_repeats(uint64_t cnt, const uint32_t *u, const uint32_t *v,
+                          uint8_t *dup) {
+  okeyidx *a = (okeyidx *)malloc((cnt + 1) * sizeof(okeyidx));
+  if (!a) return -1;
+  for (uint64_t i = 0; i < cnt; ++i) {
+    a[i].key = ekey(u[i], v[i]);
+    a[i].idx = i;
+    dup[i] = 0;
+  }
+  qsort(a, cnt, sizeof(okeyidx), cmp_keyidx);
+  for (uint64_t i = 1; i < cnt; ++i)
+    if (a[i].key == a[i - 1].key) dup[a[i].idx] = 1;
+  free(a);
+  return 0;
+}
+
+/* params: seed, K (+inf => no threshold), s_def, L_def, Q, w_ref (0 => max
+ * weight of G0), dead_end (0 terminate, 1 bounce), uid_base. */
+oracle_t *orc_create(uint32_t n, const uint64_t *rowptr, const uint32_t *col,
+                     const double *w, uint64_t h_m, const uint32_t *hu,
+                     const uint32_t *hv, uint64_t seed, double K,
+                     uint32_t s_def, uint32_t L_def, int Q, double w_ref,
+                     int dead_end, uint64_t uid_base, int *err) {
+  *err = ORC_OK;
+  if (n == 0 || Q < 1 || Q > 31 || s_def > ORC_MAX_WALKERS ||
+      L_def > ORC_MAX_STEPS || dead_end < 0 || dead_end > 1 || isnan(K) ||
+      !(w_ref >= 0.0) || isinf(w_ref)) {
+    *err = ORC_INVALID_ARG;
+    return NULL;
+  }
+  /* validate the CSR: symmetric, sorted, no loops, positive finite weights */
+  if (rowptr[0] != 0) {
+    *err = ORC_INVALID_ARG;
+    return NULL;
+  }
+  double wmax = 0.0;
+  for (uint32_t u = 0; u < n; ++u) {
+    if (rowptr[u + 1] < rowptr[u]) {
+      *err = ORC_INVALID_ARG;
+      return NULL;
+    }
+    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      if (col[k] >= n) {
+        *err = ORC_VERTEX_RANGE;
+        return NULL;
+      }
+      if (col[k] == u) {
+        *err = ORC_SELF_LOOP;
+        return NULL;
+      }
+      if (!(w[k] > 0.0) || isinf(w[k])) {
+        *err = ORC_BAD_WEIGHT;
+        return NULL;
+      }
+      if (k > rowptr[u] && col[k] <= col[k - 1]) {
+        *err = ORC_INVALID_ARG; /* unsorted or repeated neighbour */
+        return NULL;
+      }
+      if (w[k] > wmax) wmax = w[k];
+    }
+  }
+  oracle_t *o = (oracle_t *)calloc(1, sizeof(oracle_t));
+  if (!o || og_init(&o->G, n) || og_init(&o->H, n)) {
+    if (o) {
+      og_free(&o->G);
+      og_free(&o->H);
+      free(o);
+    }
+    *err = ORC_NOMEM;
+    return NULL;
+  }
+  o->n = n;
+  o->seed = seed;
+  o->has_K = !(isinf(K) && K > 0); /* K = +inf disables the threshold */
+  o->K = K;
+  o->s_def = (uint16_t)s_def;
+  o->L_def = (uint16_t)L_def;
+  o->Q = Q;
+  o->w_ref = (w_ref > 0.0) ? w_ref : (wmax > 0.0 ? wmax : 1.0);
+  o->bounce = dead_end;
+  o->uid_base = uid_base;
+  for (uint32_t u = 0; u < n; ++u) {
+    uint32_t d = (uint32_t)(rowptr[u + 1] - rowptr[u]);
+    orow *row = &o->G.rows[u];
+    row->e = (oent *)malloc((size_t)(d ? d : 1) * sizeof(oent));
+    row->cap = d ? d : 1;
+    row->len = d;
+    for (uint32_t i = 0; i < d; ++i) {
+      uint64_t k = rowptr[u] + i;
+      oent e = {col[k], orc_quantize(w[k], o->w_ref, Q), w[k], 1.0 / w[k]};
+      row->e[i] = e;
+    }
+  }
+  /* symmetry: every (u,v) must have (v,u) with the same weight */
+  for (uint32_t u = 0; u < n; ++u) {
+    for (uint32_t i = 0; i < o->G.rows[u].len; ++i) {
+      const oent *e = &o->G.rows[u].e[i];
+      long j = og_find(&o->G, e->nbr, u);
+      if (j < 0 || o->G.rows[e->nbr].e[j].w != e->w) {
+        *err = ORC_INVALID_ARG;
+        og_free(&o->G);
+        og_free(&o->H);
+        free(o);
+        return NULL;
+      }
+    }
+  }
+  /* sparsifier edges: must be distinct edges of G; copied with G's weight */
+  for (uint64_t k = 0; k < h_m; ++k) {
+    uint32_t a = hu[k], b = hv[k];
+    int e = ORC_OK;
+    if (a >= n || b >= n) e = ORC_VERTEX_RANGE;
+    else if (a == b) e = ORC_SELF_LOOP;
+    else if (!og_has(&o->G, a, b)) e = ORC_H_NOT_SUBSET;
+    else if (og_has(&o->H, a, b)) e = ORC_DUPLICATE_IN_BATCH;
+    if (e != ORC_OK) {
+      *err = e;
+      og_free(&o->G);
+      og_free(&o->H);
+      free(o);
+      return NULL;
+    }
+    const oent *ge = &o->G.rows[a].e[og_find(&o->G, a, b)];
+    og_add(&o->H, a, b, ge->w, ge->r, ge->qw);
+  }
+  return o;
+}
+
+void orc_destroy(oracle_t *o) {
+  if (!o) return;
+  og_free(&o->G);
+  og_free(&o->H);
+  free(o);
+}
+
+uint64_t orc_uid_base(const oracle_t *o) { return o->uid_base; }
+double orc_w_ref(const oracle_t *o) { return o->w_ref; }
+
+/* Validation precedence: insertions in order (range, self loop, weight,
+ * already in G, repeated in batch), then deletions in order (range, self
+ * loop, not in G, repeated in batch), then per-update s and L bounds. */
+static int o_validate(const oracle_t *o, uint64_t n_ins, const uint32_t *iu,
+                      const uint32_t *iv, const double *iw, uint64_t n_del,
+                      const uint32_t *du, const uint32_t *dv,
+                      const uint16_t *s, const uint16_t *L) {
+  uint8_t *dupi = (uint8_t *)malloc(n_ins + 1);
+  uint8_t *dupd = (uint8_t *)malloc(n_del + 1);
+  if (!dupi || !dupd || o_mark_repeats(n_ins, iu, iv, dupi) ||
+      o_mark_repeats(n_del, du, dv, dupd)) {
+    free(dupi);
+    free(dupd);
+    return ORC_NOMEM;
+  }
+  int err = ORC_OK;
+  for (uint64_t i = 0; i < n_ins && err == ORC_OK; ++i) {
+    if (iu[i] >= o->n || iv[i] >= o->n) err = ORC_VERTEX_RANGE;
+    else if (iu[i] == iv[i]) err = ORC_SELF_LOOP;
+    else if (!(iw[i] > 0.0) || isinf(iw[i])) err = ORC_BAD_WEIGHT;
+    else if (og_has(&o->G, iu[i], iv[i])) err = ORC_EDGE_EXISTS;
+    else if (dupi[i]) err = ORC_DUPLICATE_IN_BATCH;
+  }
+  for (uint64_t j = 0; j < n_del && err == ORC_OK; ++j) {
+    if (du[j] >= o->n || dv[j] >= o->n) err = ORC_VERTEX_RANGE;
+    else if (du[j] == dv[j]) err = ORC_SELF_LOOP;
+    else if (!og_has(&o->G, du[j], dv[j])) err = ORC_EDGE_MISSING;
+    else if (dupd[j]) err = ORC_DUPLICATE_IN_BATCH;
+  }
+  for (uint64_t i = 0; i < n_ins + n_del && err == ORC_OK; ++i) {
+    if (s && s[i] > ORC_MAX_WALKERS) err = ORC_INVALID_ARG;
+    if (L && L[i] > ORC_MAX_STEPS) err = ORC_INVALID_ARG;
+  }
+  free(dupi);
+  free(dupd);
+  return err;
+}
+
+/*
+ * One batch.  Per-update outputs (arrays of length n_ins+n_del, insertions
+ * first, may be NULL): flag = accepted (insertion) / in H (deletion);
+ * any_hit; winner (deletion, walker of the minimum (R, index) hit, 0xFFFF if
+ * none); n_rec (deletion, edges recovered or taken by the fallback); steps
+ * (sum over walkers); Rmin (+inf if no hit).
+ * Per-walker outputs (optional, length sum of s over updates, in update
+ * order; deletions whose edge is not in H report zero steps at u).
+ */
+int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
+                    const uint32_t *iv, const double *iw, uint64_t n_del,
+                    const uint32_t *du, const uint32_t *dv, const uint16_t *s,
+                    const uint16_t *L, uint8_t *flag, uint8_t *any_hit,
+                    uint16_t *winner, uint16_t *n_rec, uint32_t *steps,
+                    double *Rmin, uint8_t *w_hit, uint16_t *w_steps,
+                    uint32_t *w_end, double *w_R) {
+  int err = o_validate(o, n_ins, iu, iv, iw, n_del, du, dv, s, L);
+  if (err != ORC_OK) return err;
+  const uint64_t nu = n_ins + n_del;
+  uint64_t *wofs = (uint64_t *)malloc((nu + 1) * sizeof(uint64_t));
+  uint8_t *inH = (uint8_t *)calloc(n_del + 1, 1);
+  uint8_t *acc = (uint8_t *)calloc(n_ins + 1, 1);
+  if (!wofs || !inH || !acc) {
+    free(wofs);
+    free(inH);
+    free(acc);
+    return ORC_NOMEM;
+  }
+  wofs[0] = 0;
+  for (uint64_t i = 0; i < nu; ++i)
+    wofs[i + 1] = wofs[i] + (s ? s[i] : o->s_def);
+
+  /* Phase 1: membership of each deleted edge in H; remove D from G and H. */
+  for (uint64_t j = 0; j < n_del; ++j) inH[j] = (uint8_t)og_has(&o->H, du[j], dv[j]);
+  for (uint64_t j = 0; j < n_del; ++j) {
+    og_remove(&o->G, du[j], dv[j]);
+    if (inH[j]) og_remove(&o->H, du[j], dv[j]);
+  }
+
+  /* recovered edges per deletion: at most L path edges or 2 fallback edges */
+  uint64_t *rofs = (uint64_t *)malloc((n_del + 1) * sizeof(uint64_t));
+  rofs[0] = 0;
+  for (uint64_t j = 0; j < n_del; ++j) {
+    uint32_t Lj = L ? L[n_ins + j] : o->L_def;
+    rofs[j + 1] = rofs[j] + (Lj > 2 ? Lj : 2);
+  }
+  uint32_t *rec_a = (uint32_t *)malloc((rofs[n_del] + 1) * sizeof(uint32_t));
+  uint32_t *rec_b = (uint32_t *)malloc((rofs[n_del] + 1) * sizeof(uint32_t));
+  uint32_t *nrec = (uint32_t *)calloc(n_del + 1, sizeof(uint32_t));
+
+  /* Phase 2: walks.  Every update reads only the batch snapshot (G_mid,
+   * H_mid), so the loop order is immaterial. */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long long ii = 0; ii < (long long)nu; ++ii) {
+    uint64_t i = (uint64_t)ii;
+    uint64_t uid = o->uid_base + i;
+    uint32_t si = s ? s[i] : o->s_def;
+    uint32_t Li = L ? L[i] : o->L_def;
+    int is_ins = i < n_ins;
+    uint64_t j = i - n_ins;
+    uint32_t p = is_ins ? iu[i] : du[j];
+    uint32_t q = is_ins ? iv[i] : dv[j];
+    uint8_t fl = 0, anyh = 0;
+    uint16_t win = 0xFFFF, nr = 0;
+    uint32_t st = 0;
+    double rmin = INFINITY;
+    if (is_ins || inH[j]) {
+      const ograph *X = is_ins ? &o->H : &o->G; /* H_mid / G_mid */
+      uint32_t *traj = (uint32_t *)malloc((size_t)si * (Li + 1) * sizeof(uint32_t) + 4);
+      owalk *res = (owalk *)malloc((size_t)si * sizeof(owalk) + 1);
+      for (uint32_t k = 0; k < si; ++k) {
+        o_walk_one(X, p, q, is_ins && o->has_K, is_ins ? iw[i] : 0.0, o->K, Li,
+                   o->seed, uid, k, o->bounce, &res[k], traj + (size_t)k * (Li + 1));
+        st += res[k].steps;
+        if (res[k].hit) {
+          anyh = 1;
+          /* minimum resistance over hitting walkers, ties to the lower index */
+          if (res[k].R < rmin) {
+            rmin = res[k].R;
+            win = (uint16_t)k;
+          }
+        }
+        if (w_hit) {
+          w_hit[wofs[i] + k] = res[k].hit;
+          w_steps[wofs[i] + k] = res[k].steps;
+          w_end[wofs[i] + k] = res[k].end;
+          w_R[wofs[i] + k] = res[k].R;
+        }
+      }
+      if (is_ins) {
+        fl = (uint8_t)!anyh; /* keep the new edge iff no walker reached q */
+        acc[i] = fl;
+      } else {
+        fl = 1;
+        uint32_t *ra = rec_a + rofs[j], *rb = rec_b + rofs[j];
+        if (anyh) {
+          /* edges of the winning path, first occurrence, not already in H */
+          const uint32_t *path = traj + (size_t)win * (Li + 1);
+          for (uint32_t t = 0; t < res[win].steps; ++t) {
+            uint32_t a = path[t], b = path[t + 1];
+            if (og_has(&o->H, a, b)) continue;
+            int seen = 0;
+            for (uint32_t z = 0; z < nr; ++z)
+              if (ekey(ra[z], rb[z]) == ekey(a, b)) seen = 1;
+            if (seen) continue;
+            ra[nr] = a;
+            rb[nr] = b;
+            nr++;
+          }
+        } else {
+          /* no hit: per endpoint, the least-resistance G edge not in H,
+           * ties to the smaller neighbour id */
+          uint32_t ends[2] = {p, q};
+          for (int z = 0; z < 2; ++z) {
+            const orow *row = &o->G.rows[ends[z]];
+            long best = -1;
+            for (uint32_t t = 0; t < row->len; ++t) {
+              if (og_has(&o->H, ends[z], row->e[t].nbr)) continue;
+              if (best < 0 || row->e[t].r < row->e[best].r) best = (long)t;
+            }
+            if (best >= 0) {
+              ra[nr] = ends[z];
+              rb[nr] = row->e[best].nbr;
+              nr++;
+            }
+          }
+        }
+        nrec[j] = nr;
+      }
+      free(traj);
+      free(res);
+    } else if (w_hit) {
+      for (uint32_t k = 0; k < si; ++k) {
+        w_hit[wofs[i] + k] = 0;
+        w_steps[wofs[i] + k] = 0;
+        w_end[wofs[i] + k] = p;
+        w_R[wofs[i] + k] = 0.0;
+      }
+    }
+    if (flag) flag[i] = fl;
+    if (any_hit) any_hit[i] = anyh;
+    if (winner) winner[i] = win;
+    if (n_rec) n_rec[i] = nr;
+    if (steps) steps[i] = st;
+    if (Rmin) Rmin[i] = rmin;
+  }
+
+  /* Phase 4: G += I; H += accepted insertions, recovered and fallback edges
+   * (a set union: an edge already present is not added twice). */
+  for (uint64_t i = 0; i < n_ins; ++i) {
+    double r = 1.0 / iw[i];
+    uint32_t qw = orc_quantize(iw[i], o->w_ref, o->Q);
+    og_add(&o->G, iu[i], iv[i], iw[i], r, qw);
+    if (acc[i]) og_add(&o->H, iu[i], iv[i], iw[i], r, qw);
+  }
+  for (uint64_t j = 0; j < n_del; ++j) {
+    for (uint32_t z = 0; z < nrec[j]; ++z) {
+      uint32_t a = rec_a[rofs[j] + z], b = rec_b[rofs[j] + z];
+      if (og_has(&o->H, a, b)) continue;
+      const oent *ge = &o->G.rows[a].e[og_find(&o->G, a, b)];
+      og_add(&o->H, a, b, ge->w, ge->r, ge->qw);
+    }
+  }
+  o->uid_base += nu;
+  free(wofs);
+  free(inH);
+  free(acc);
+  free(rofs);
+  free(rec_a);
+  free(rec_b);
+  free(nrec);
+  return ORC_OK;
+}
+
+/* Canonical edge list (u < v, sorted by (u, v)) of G (which=0) or H (1).
+ * With cap smaller than the edge count only *m is written. */
+int orc_query(const oracle_t *o, int which, uint64_t cap, uint64_t *m,
+              uint32_t *u, uint32_t *v, double *w) {
+  const ograph *g = which ? &o->H : &o->G;
+  uint64_t cnt = 0;
+  for (uint32_t a = 0; a < g->n; ++a)
+    for (uint32_t i = 0; i < g->rows[a].len; ++i)
+      if (g->rows[a].e[i].nbr > a) cnt++;
+  *m = cnt;
+  if (cap < cnt) return ORC_OK;
+  uint64_t k = 0;
+  for (uint32_t a = 0; a < g->n; ++a)
+    for (uint32_t i = 0; i < g->rows[a].len; ++i)
+      if (g->rows[a].e[i].nbr > a) {
+        u[k] = a;
+        v[k] = g->rows[a].e[i].nbr;
+        w[k] = g->rows[a].e[i].w;
+        k++;
+      }
+  return ORC_OK;
+}
