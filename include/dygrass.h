@@ -1,0 +1,216 @@
+/*
+ * dygrass.h -- C ABI of libdygrass, an MI355X (gfx950) implementation of the
+ * update path of dyGRASS (Yuan, Aghdaei, Feng, "dyGRASS: Dynamic Spectral
+ * Graph Sparsification via Localized Random Walks on GPUs", arXiv 2505.02741).
+ *
+ * The library keeps an undirected weighted graph G and a spectral sparsifier
+ * H (a subgraph of G with the same weights) resident in GPU memory and
+ * updates H as batches of edge insertions and deletions arrive:
+ *
+ *  - insertion (p,q,w): s non-backtracking, weight-biased walkers start at p
+ *    in H; each stops when w*R exceeds K (R = sum of 1/w along its path), after
+ *    L steps, or at a leaf.  The edge enters H iff no walker reaches q
+ *    (Sec. III-B; Algorithm 1, insertion branch).
+ *  - deletion (u,v): if the edge is in H, s walkers start at u in G without
+ *    the edge; the hitting walker with the least R (Eq. 12) has its path edges
+ *    that are missing from H added back; with no hit, per endpoint the G edge
+ *    of least resistance missing from H is added (Sec. III-C; Algorithm 1,
+ *    deletion branch).
+ *  - batches: every walk of a batch reads the state after the batch's
+ *    deletions; insertions and recovered edges are applied at the end of the
+ *    batch (Sec. III-F, batch processing on the GPU).
+ *
+ * Random numbers: Philox-4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
+ * seed, counter (step/2, walker, uid low, uid high); update i of a batch has
+ * uid = uid_base + i with insertions numbered before deletions.  Results are
+ * therefore independent of scheduling and bit-reproducible.
+ *
+ * Ownership: every pointer argument is owned by the caller and only read or
+ * written during the call; the library copies what it keeps.  A context owns
+ * its GPU memory until dyg_destroy.  Calls on one context must not overlap;
+ * different contexts are independent.
+ *
+ * Errors: every int-returning call returns DYG_OK (0) or a negative dyg_status.
+ * A failed dyg_apply_batch leaves G, H and uid_base unchanged.
+ */
+#ifndef DYGRASS_H
+#define DYGRASS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dyg_ctx dyg_ctx;
+
+typedef enum {
+  DYG_OK = 0,
+  DYG_E_INVALID_ARG = -1,        /* bad pointer, size, parameter or s/L bound   */
+  DYG_E_SELF_LOOP = -2,          /* an edge (u,u)                               */
+  DYG_E_VERTEX_RANGE = -3,       /* a vertex id >= n                            */
+  DYG_E_BAD_WEIGHT = -4,         /* weight <= 0, NaN or infinite                */
+  DYG_E_EDGE_EXISTS = -5,        /* inserted edge already in G (Sec. III-B)     */
+  DYG_E_EDGE_MISSING = -6,       /* deleted edge not in G (Sec. III-C)          */
+  DYG_E_DUPLICATE_IN_BATCH = -7, /* the same edge twice in one list             */
+  DYG_E_H_NOT_SUBSET = -8,       /* init: a sparsifier edge not in G            */
+  DYG_E_NOMEM = -9,              /* device or host allocation failed            */
+  DYG_E_DEVICE = -10             /* a HIP runtime call failed                   */
+} dyg_status;
+
+enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
+
+/* dyg_params.flags */
+#define DYG_FLAG_LEAN_POOLS 1u /* size entry pools to the live entries plus 64 spare
+                                  slots (instead of 50% + 4096) and grow on demand */
+#define DYG_FLAG_TIMING 2u     /* time the walk kernel and each batch with HIP
+                                  events on the launch stream (dyg_stats)        */
+
+#define DYG_MAX_WALKERS 1024 /* per update */
+#define DYG_MAX_STEPS 1024   /* per walker */
+
+typedef struct {
+  uint64_t seed;      /* Philox key                                              */
+  double K;           /* distortion threshold; +INFINITY disables it (Sec. III-B) */
+  uint16_t s_default; /* walkers per update when the batch gives none            */
+  uint16_t L_default; /* step limit T per walker when the batch gives none       */
+  uint8_t Q;          /* bits of the quantised weights, 1..31; 24 recommended    */
+  uint8_t dead_end;   /* DYG_DEAD_END_TERMINATE (the paper's leaf rule) or BOUNCE */
+  uint16_t reserved0;
+  double w_ref;       /* weight that maps to 2^Q; 0 = largest weight of G0       */
+  double slack;       /* spare slots per vertex segment, as a fraction (>= 0)    */
+  uint64_t uid_base;  /* uid of the first update of the next batch               */
+  uint32_t flags;     /* DYG_FLAG_* bits                                         */
+  uint32_t reserved1;
+} dyg_params;
+
+/* Per-update result (24 bytes), insertions first, then deletions. */
+typedef struct {
+  uint8_t kind;     /* 0 insertion, 1 deletion                                   */
+  uint8_t flag;     /* insertion: edge added to H; deletion: edge was in H       */
+  uint8_t any_hit;  /* some walker reached the other endpoint                    */
+  uint8_t reserved;
+  uint16_t winner;  /* walker index of the least-R hit, 0xFFFF if none           */
+  uint16_t n_rec;   /* deletion: edges recovered into H (path or fallback)      */
+  uint32_t steps;   /* steps taken by all walkers of the update                  */
+  uint32_t reserved2;
+  double Rmin;      /* least resistance sum over hitting walkers, +inf if none   */
+} dyg_update_result;
+
+/* Per-walker record (16 bytes), for verification. */
+typedef struct {
+  uint8_t hit;
+  uint8_t reserved;
+  uint16_t steps; /* edges traversed                                            */
+  uint32_t end;   /* vertex where the walker stopped                            */
+  double R;       /* resistance sum of its path                                 */
+} dyg_walker_record;
+
+typedef struct {
+  uint32_t n;
+  uint32_t reserved;
+  uint64_t g_edges, h_edges;     /* live undirected edges                       */
+  uint64_t g_pool_used, g_pool_cap; /* directed entry slots                     */
+  uint64_t h_pool_used, h_pool_cap;
+  uint64_t g_dead, h_dead;       /* tombstoned directed entries                 */
+  uint64_t uid_base;
+  uint64_t batches;
+  uint64_t compactions;
+  double w_ref;
+  /* walk work since dyg_init: steps taken and the bytes those steps must
+   * gather (per step at a vertex of live degree d: 16 + 8d for d <= 64,
+   * 32 + 12 ceil(log2 d) above) */
+  uint64_t walk_steps;
+  uint64_t walk_alg_bytes;
+  /* with DYG_FLAG_TIMING: walk-kernel launches timed, their total and last
+   * duration, and the device time of the last batch (ms) */
+  uint64_t walk_launches;
+  double walk_ms_total;
+  double walk_ms_last;
+  double batch_ms_last;
+} dyg_stats_t;
+
+void dyg_default_params(dyg_params* p);
+
+/*
+ * Create a context from G0 and H0 (Algorithm 1 inputs G(0), H(0)).
+ *   n        vertices, 1 <= n < 2^31
+ *   rowptr   host, n+1 entries; col/w host, rowptr[n] entries: symmetric CSR of
+ *            G0, each row ascending by neighbour, no self loops, weights > 0
+ *            and finite, (u,v) and (v,u) with equal weights
+ *   h_u/h_v  host, h_m edges of H0; each must be an edge of G0 (its weight is
+ *            taken from G0), no repeats
+ * Errors: INVALID_ARG, VERTEX_RANGE, SELF_LOOP, BAD_WEIGHT, H_NOT_SUBSET,
+ * DUPLICATE_IN_BATCH (H0 repeats an edge), NOMEM, DEVICE.  *out is set only
+ * on success.
+ */
+int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const uint32_t* col,
+             const double* w, uint64_t h_m, const uint32_t* h_u, const uint32_t* h_v,
+             const dyg_params* params);
+
+/*
+ * Apply one batch (Algorithm 1 over the batch, Sec. III-F deferral).
+ *   iu/iv/iw  host, n_ins insertions (p,q,w): p is where the walkers start
+ *   du/dv     host, n_del deletions (u,v): u is where the walkers start
+ *   s, L      host, NULL or n_ins+n_del entries (insertions first): walkers and
+ *             step limit per update, each <= 1024; NULL means the defaults
+ *   results   host, NULL or n_ins+n_del records
+ *   walkers   host, NULL or sum-of-s records in update order, walker order
+ * Validation order: insertions in order (range, self loop, weight, already in
+ * G, repeated earlier in the batch), then deletions in order (range, self
+ * loop, not in G, repeated), then s/L bounds; the first failure is returned.
+ */
+int dyg_apply_batch(dyg_ctx* ctx, uint64_t n_ins, const uint32_t* iu, const uint32_t* iv,
+                    const double* iw, uint64_t n_del, const uint32_t* du, const uint32_t* dv,
+                    const uint16_t* s, const uint16_t* L, dyg_update_result* results,
+                    dyg_walker_record* walkers);
+
+/*
+ * Device-resident batch for callers that keep inputs in GPU memory (PyTorch
+ * tensors, a serving loop).  All pointers are device pointers; s, L and
+ * results may be NULL.  L_max bounds every L of the batch (<= 1024).
+ */
+typedef struct {
+  uint64_t n_ins, n_del;
+  const uint32_t *iu, *iv;
+  const double* iw;
+  const uint32_t *du, *dv;
+  const uint16_t *s, *L;
+  uint32_t L_max;
+  uint32_t reserved;
+  dyg_update_result* results;
+} dyg_batch_dev;
+
+/*
+ * Enqueue one batch on `stream` (a hipStream_t; NULL = the null stream)
+ * without host synchronisation.  The call returns once the work is queued;
+ * dyg_sync(ctx) waits for it and returns the batch status.  Inputs must stay
+ * valid until then.
+ */
+int dyg_apply_batch_dev(dyg_ctx* ctx, const dyg_batch_dev* batch, void* stream);
+int dyg_sync(dyg_ctx* ctx);
+
+/*
+ * Canonical edge list of H (Algorithm 1 output H(t)) or of G: u < v, sorted by
+ * (u, v).  Two-call protocol: with cap < the edge count only *m is written.
+ * u, v, w are host arrays of cap entries.
+ */
+int dyg_query_sparsifier(dyg_ctx* ctx, uint64_t cap, uint64_t* m, uint32_t* u, uint32_t* v,
+                         double* w);
+int dyg_query_graph(dyg_ctx* ctx, uint64_t cap, uint64_t* m, uint32_t* u, uint32_t* v,
+                    double* w);
+
+int dyg_stats(dyg_ctx* ctx, dyg_stats_t* out);
+
+/* Rewrite both pools without tombstones, with fresh slack (also done
+ * automatically when a pool runs short). */
+int dyg_compact(dyg_ctx* ctx);
+
+void dyg_destroy(dyg_ctx* ctx);
+const char* dyg_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DYGRASS_H */

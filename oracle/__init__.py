@@ -93,6 +93,10 @@ def _load():
     lib.orc_destroy.argtypes = [P]
     lib.orc_uid_base.argtypes = [P]
     lib.orc_uid_base.restype = C.c_uint64
+    lib.orc_steps_total.argtypes = [P]
+    lib.orc_steps_total.restype = C.c_uint64
+    lib.orc_alg_bytes_total.argtypes = [P]
+    lib.orc_alg_bytes_total.restype = C.c_uint64
     lib.orc_w_ref.argtypes = [P]
     lib.orc_w_ref.restype = C.c_double
     lib.orc_apply_batch.argtypes = [P, C.c_uint64, P, P, P, C.c_uint64, P, P, P, P,
@@ -205,6 +209,14 @@ class Oracle:
     @property
     def uid_base(self) -> int:
         return int(_load().orc_uid_base(self._h))
+
+    @property
+    def steps_total(self) -> int:
+        return int(_load().orc_steps_total(self._h))
+
+    @property
+    def alg_bytes_total(self) -> int:
+        return int(_load().orc_alg_bytes_total(self._h))
 
     @property
     def w_ref(self) -> float:

@@ -259,7 +259,19 @@ typedef struct {
   uint16_t steps;
   uint32_t end;
   double R;
+  uint64_t bytes; /* gathered bytes the steps must read (measurement only) */
 } owalk;
+
+/* Bytes a step must read at a vertex with d live neighbours: offset and
+ * degree (8), an (id, weight) pair per neighbour (8 each), the chosen edge's
+ * resistance (8); above 64 neighbours a cumulative-weight binary search:
+ * 32 plus 12 per halving, ceil(log2 d) halvings. */
+static uint64_t o_step_bytes(uint32_t d) {
+  if (d <= 64) return 16u + 8u * (uint64_t)d;
+  uint32_t halvings = 0;
+  while ((1ull << halvings) < d) halvings++;
+  return 32u + 12u * (uint64_t)halvings;
+}
 
 /* traj (optional) receives x_0..x_steps (steps+1 vertices). */
 static void o_walk_one(const ograph *X, uint32_t p, uint32_t q, int has_K,
@@ -271,6 +283,7 @@ static void o_walk_one(const ograph *X, uint32_t p, uint32_t q, int has_K,
   double R = 0.0;
   uint8_t hit = 0;
   uint32_t steps = 0;
+  uint64_t bytes = 0;
   if (traj) traj[0] = p;
   for (uint32_t t = 0; t < L; ++t) {
     const orow *row = &X->rows[x];
@@ -308,6 +321,7 @@ static void o_walk_one(const ograph *X, uint32_t p, uint32_t q, int has_K,
       }
       if (!found) abort(); /* impossible: target < tot */
     }
+    bytes += o_step_bytes(row->len);
     R = R + r;
     prev = (long)x;
     x = chosen;
@@ -323,6 +337,7 @@ static void o_walk_one(const ograph *X, uint32_t p, uint32_t q, int has_K,
   res->steps = (uint16_t)steps;
   res->end = x;
   res->R = R;
+  res->bytes = bytes;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -375,6 +390,8 @@ typedef struct {
   double w_ref;
   int bounce;
   uint64_t uid_base;
+  uint64_t steps_total;     /* walker steps taken since creation */
+  uint64_t alg_bytes_total; /* bytes those steps must gather */
 } oracle_t;
 
 static uint64_t ekey(uint32_t u, uint32_t v) {
@@ -530,6 +547,8 @@ void orc_destroy(oracle_t *o) {
 }
 
 uint64_t orc_uid_base(const oracle_t *o) { return o->uid_base; }
+uint64_t orc_steps_total(const oracle_t *o) { return o->steps_total; }
+uint64_t orc_alg_bytes_total(const oracle_t *o) { return o->alg_bytes_total; }
 double orc_w_ref(const oracle_t *o) { return o->w_ref; }
 
 /* Validation precedence: insertions in order (range, self loop, weight,
@@ -635,6 +654,7 @@ int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
     uint8_t fl = 0, anyh = 0;
     uint16_t win = 0xFFFF, nr = 0;
     uint32_t st = 0;
+    uint64_t by = 0;
     double rmin = INFINITY;
     if (is_ins || inH[j]) {
       const ograph *X = is_ins ? &o->H : &o->G; /* H_mid / G_mid */
@@ -644,6 +664,7 @@ int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
         o_walk_one(X, p, q, is_ins && o->has_K, is_ins ? iw[i] : 0.0, o->K, Li,
                    o->seed, uid, k, o->bounce, &res[k], traj + (size_t)k * (Li + 1));
         st += res[k].steps;
+        by += res[k].bytes;
         if (res[k].hit) {
           anyh = 1;
           /* minimum resistance over hitting walkers, ties to the lower index */
@@ -709,6 +730,10 @@ int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
         w_R[wofs[i] + k] = 0.0;
       }
     }
+#pragma omp atomic
+    o->steps_total += st;
+#pragma omp atomic
+    o->alg_bytes_total += by;
     if (flag) flag[i] = fl;
     if (any_hit) any_hit[i] = anyh;
     if (winner) winner[i] = win;

@@ -1,0 +1,870 @@
+// C ABI of libdygrass: context life cycle, host-side validation of the
+// initial graphs, device memory management and the per-batch launch sequence.
+#include "dygrass.h"
+#include "dyg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using dyg::AddRec;
+using dyg::BatchArgs;
+using dyg::BatchCtl;
+using dyg::DevGraph;
+using dyg::Ent;
+using dyg::HashSlot;
+using dyg::Row;
+
+namespace dyg {
+void launch_phase4_reset(const BatchArgs& a, DevGraph& X, int which, hipStream_t st);
+}
+
+namespace {
+
+// Growable device buffer.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  bool ensure(size_t need) {
+    if (need <= bytes && p) return true;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t want = need + need / 2 + 256;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    bytes = want;
+    return true;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Growable pinned host buffer.
+struct HBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  bool ensure(size_t need) {
+    if (need <= bytes && p) return true;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t want = need + need / 2 + 256;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    bytes = want;
+    return true;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Quantised weight: round-half-even(w / w_ref * 2^Q), clamped to [1, 2^32-1].
+uint32_t quantize_host(double w, double w_ref, int Q) {
+  const double y = std::nearbyint((w / w_ref) * std::ldexp(1.0, Q));
+  if (!(y >= 1.0)) return 1u;
+  if (y > 4294967295.0) return 4294967295u;
+  return static_cast<uint32_t>(y);
+}
+
+uint32_t slack_slots(uint32_t len, double slack) {
+  const double extra = std::ceil(static_cast<double>(len) * slack);
+  return static_cast<uint32_t>(std::max(2.0, extra));
+}
+
+// Host image of one adjacency (used at init and by compaction).
+struct HostAdj {
+  std::vector<Row> rows;
+  std::vector<Ent> ent;
+  std::vector<double> w;
+};
+
+}  // namespace
+
+struct dyg_ctx {
+  uint32_t n = 0;
+  dyg_params params{};
+  double w_ref = 1.0;
+  int Q = 24;
+  bool has_K = false;
+  uint64_t uid_base = 0;
+  uint64_t batches = 0;
+  uint64_t compactions = 0;
+  hipStream_t stream = nullptr;
+  DevGraph G, H;
+  BatchCtl* ctl = nullptr;
+  uint64_t pool_top[2] = {0, 0};  // host mirror after the last sync
+  bool broken = false;
+  int pending_status = DYG_OK;
+  bool async_inflight = false;
+  uint64_t async_nu = 0;
+  // DYG_FLAG_TIMING
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // batch begin, walk begin/end, batch end
+  bool timed_pending = false;
+  uint64_t walk_launches = 0;
+  double walk_ms_total = 0.0, walk_ms_last = 0.0, batch_ms_last = 0.0;
+  // batch staging
+  DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, wrec, wofs, hadd, hash;
+  DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2];
+  HBuf pin_in, pin_out;
+};
+
+namespace {
+
+int fail_hip(hipError_t e) { return e == hipErrorOutOfMemory ? DYG_E_NOMEM : DYG_E_DEVICE; }
+
+void free_graph(DevGraph& X) {
+  if (X.rows) (void)hipFree(X.rows);
+  if (X.ent) (void)hipFree(X.ent);
+  if (X.w) (void)hipFree(X.w);
+  if (X.pending) (void)hipFree(X.pending);
+  X = DevGraph{};
+}
+
+// Upload a host adjacency into freshly allocated device arrays with pool
+// capacity `pool_cap` (>= ent.size()).
+int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
+                 hipStream_t st) {
+  DevGraph Y;
+  Y.pool_cap = pool_cap;
+  hipError_t e = hipSuccess;
+  if ((e = hipMalloc(&Y.rows, sizeof(Row) * std::max<uint64_t>(n, 1))) != hipSuccess ||
+      (e = hipMalloc(&Y.ent, sizeof(Ent) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
+      (e = hipMalloc(&Y.w, sizeof(double) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
+      (e = hipMalloc(&Y.pending, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess) {
+    free_graph(Y);
+    return fail_hip(e);
+  }
+  if ((e = hipMemcpyAsync(Y.rows, A.rows.data(), sizeof(Row) * n, hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (!A.ent.empty() &&
+       (e = hipMemcpyAsync(Y.ent, A.ent.data(), sizeof(Ent) * A.ent.size(),
+                           hipMemcpyHostToDevice, st)) != hipSuccess) ||
+      (!A.w.empty() &&
+       (e = hipMemcpyAsync(Y.w, A.w.data(), sizeof(double) * A.w.size(), hipMemcpyHostToDevice,
+                           st)) != hipSuccess) ||
+      (e = hipMemsetAsync(Y.pending, 0, sizeof(uint32_t) * n, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    free_graph(Y);
+    return fail_hip(e);
+  }
+  free_graph(X);
+  X = Y;
+  return DYG_OK;
+}
+
+// Lay out segments with slack for the given per-row live lists.
+void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
+            const std::vector<Ent>& live_ent, const std::vector<double>& live_w, double slack) {
+  A.rows.assign(n, Row{0, 0, 0, 0});
+  uint64_t total = 0;
+  for (uint32_t u = 0; u < n; ++u) {
+    const uint32_t len = static_cast<uint32_t>(start[u + 1] - start[u]);
+    total += len + slack_slots(len, slack);
+  }
+  A.ent.assign(total, Ent{0, 0, 0.0});
+  A.w.assign(total, 0.0);
+  uint64_t off = 0;
+  for (uint32_t u = 0; u < n; ++u) {
+    const uint32_t len = static_cast<uint32_t>(start[u + 1] - start[u]);
+    const uint32_t cap = len + slack_slots(len, slack);
+    A.rows[u] = Row{static_cast<uint32_t>(off), len, cap, 0};
+    std::copy(live_ent.begin() + start[u], live_ent.begin() + start[u + 1], A.ent.begin() + off);
+    std::copy(live_w.begin() + start[u], live_w.begin() + start[u + 1], A.w.begin() + off);
+    off += cap;
+  }
+}
+
+uint64_t pool_capacity_for(uint64_t used, uint32_t flags) {
+  if (flags & DYG_FLAG_LEAN_POOLS) return used + 64;
+  return used + used / 2 + 4096;
+}
+
+// Read one device graph back into per-row live lists.
+int download_live(const DevGraph& X, uint32_t n, uint64_t used, std::vector<uint64_t>& start,
+                  std::vector<Ent>& live_ent, std::vector<double>& live_w, hipStream_t st) {
+  std::vector<Row> rows(n);
+  std::vector<Ent> ent(used);
+  std::vector<double> w(used);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(rows.data(), X.rows, sizeof(Row) * n, hipMemcpyDeviceToHost, st)) !=
+          hipSuccess ||
+      (used && (e = hipMemcpyAsync(ent.data(), X.ent, sizeof(Ent) * used, hipMemcpyDeviceToHost,
+                                   st)) != hipSuccess) ||
+      (used && (e = hipMemcpyAsync(w.data(), X.w, sizeof(double) * used, hipMemcpyDeviceToHost,
+                                   st)) != hipSuccess) ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return fail_hip(e);
+  start.assign(n + 1, 0);
+  live_ent.clear();
+  live_w.clear();
+  for (uint32_t u = 0; u < n; ++u) {
+    const Row r = rows[u];
+    for (uint32_t i = 0; i < r.len; ++i) {
+      const Ent& x = ent[r.off + i];
+      if (x.qw == 0u) continue;
+      live_ent.push_back(x);
+      live_w.push_back(w[r.off + i]);
+    }
+    start[u + 1] = live_ent.size();
+  }
+  return DYG_OK;
+}
+
+int sync_ctl_host(dyg_ctx* c, BatchCtl& out) {
+  hipError_t e = hipMemcpyAsync(&out, c->ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(e);
+  c->pool_top[0] = out.pool_top[0];
+  c->pool_top[1] = out.pool_top[1];
+  return DYG_OK;
+}
+
+// Rewrite graph `which` without tombstones into a pool of at least
+// `min_cap` slots.
+int compact_graph(dyg_ctx* c, int which, uint64_t min_cap) {
+  DevGraph& X = which ? c->H : c->G;
+  BatchCtl ctl;
+  int rc = sync_ctl_host(c, ctl);
+  if (rc) return rc;
+  std::vector<uint64_t> start;
+  std::vector<Ent> le;
+  std::vector<double> lw;
+  rc = download_live(X, c->n, ctl.pool_top[which], start, le, lw, c->stream);
+  if (rc) return rc;
+  HostAdj A;
+  layout(A, c->n, start, le, lw, c->params.slack);
+  const uint64_t cap =
+      std::max<uint64_t>(pool_capacity_for(A.ent.size(), c->params.flags), min_cap);
+  if (cap >= (1ull << 32)) return DYG_E_NOMEM;
+  rc = upload_graph(X, c->n, A, cap, c->stream);
+  if (rc) return rc;
+  ctl.pool_top[which] = A.ent.size();
+  hipError_t e = hipMemcpyAsync(&c->ctl->pool_top[which], &ctl.pool_top[which],
+                                sizeof(unsigned long long), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(e);
+  c->pool_top[which] = A.ent.size();
+  c->compactions++;
+  return DYG_OK;
+}
+
+int check_params(const dyg_params* p) {
+  if (!p) return DYG_E_INVALID_ARG;
+  if (p->Q < 1 || p->Q > 31 || p->s_default > DYG_MAX_WALKERS ||
+      p->L_default > DYG_MAX_STEPS || p->dead_end > 1 || std::isnan(p->K) ||
+      !(p->w_ref >= 0.0) || std::isinf(p->w_ref) || !(p->slack >= 0.0) ||
+      std::isinf(p->slack))
+    return DYG_E_INVALID_ARG;
+  return DYG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" void dyg_default_params(dyg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->seed = 0;
+  p->K = INFINITY;
+  p->s_default = 64;
+  p->L_default = 32;
+  p->Q = 24;
+  p->dead_end = DYG_DEAD_END_TERMINATE;
+  p->w_ref = 0.0;
+  p->slack = 0.5;
+  p->uid_base = 0;
+}
+
+extern "C" const char* dyg_error_string(int code) {
+  switch (code) {
+    case DYG_OK: return "ok";
+    case DYG_E_INVALID_ARG: return "invalid argument";
+    case DYG_E_SELF_LOOP: return "self loop";
+    case DYG_E_VERTEX_RANGE: return "vertex id out of range";
+    case DYG_E_BAD_WEIGHT: return "weight not positive and finite";
+    case DYG_E_EDGE_EXISTS: return "inserted edge already in the graph";
+    case DYG_E_EDGE_MISSING: return "deleted edge not in the graph";
+    case DYG_E_DUPLICATE_IN_BATCH: return "edge repeated in one list";
+    case DYG_E_H_NOT_SUBSET: return "sparsifier edge not in the graph";
+    case DYG_E_NOMEM: return "out of memory";
+    case DYG_E_DEVICE: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const uint32_t* col,
+                        const double* w, uint64_t h_m, const uint32_t* h_u, const uint32_t* h_v,
+                        const dyg_params* params) {
+  if (!out) return DYG_E_INVALID_ARG;
+  int rc = check_params(params);
+  if (rc) return rc;
+  if (n == 0 || n >= (1u << 31) || !rowptr) return DYG_E_INVALID_ARG;
+  const uint64_t nnz = rowptr[n];
+  if (rowptr[0] != 0 || (nnz && (!col || !w)) || (h_m && (!h_u || !h_v)))
+    return DYG_E_INVALID_ARG;
+  // G0: per row range, self loop, weight, ascending order
+  double wmax = 0.0;
+  for (uint32_t u = 0; u < n; ++u) {
+    if (rowptr[u + 1] < rowptr[u]) return DYG_E_INVALID_ARG;
+    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      if (col[k] >= n) return DYG_E_VERTEX_RANGE;
+      if (col[k] == u) return DYG_E_SELF_LOOP;
+      if (!(w[k] > 0.0) || std::isinf(w[k])) return DYG_E_BAD_WEIGHT;
+      if (k > rowptr[u] && col[k] <= col[k - 1]) return DYG_E_INVALID_ARG;
+      wmax = std::max(wmax, w[k]);
+    }
+  }
+  auto find = [&](uint32_t a, uint32_t b) -> int64_t {
+    const uint32_t* lo = col + rowptr[a];
+    const uint32_t* hi = col + rowptr[a + 1];
+    const uint32_t* it = std::lower_bound(lo, hi, b);
+    return (it != hi && *it == b) ? static_cast<int64_t>(it - col) : -1;
+  };
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      const int64_t j = find(col[k], u);
+      if (j < 0 || w[j] != w[k]) return DYG_E_INVALID_ARG;  // not symmetric
+    }
+  // H0: range, self loop, subset of G0, repeats (first failing edge wins)
+  std::vector<std::pair<uint64_t, uint64_t>> hk(h_m);
+  for (uint64_t i = 0; i < h_m; ++i) {
+    const uint32_t a = std::min(h_u[i], h_v[i]), b = std::max(h_u[i], h_v[i]);
+    hk[i] = {(static_cast<uint64_t>(a) << 32) | b, i};
+  }
+  std::sort(hk.begin(), hk.end());
+  std::vector<uint8_t> repeat(h_m, 0);
+  for (uint64_t i = 1; i < h_m; ++i)
+    if (hk[i].first == hk[i - 1].first) repeat[hk[i].second] = 1;
+  for (uint64_t i = 0; i < h_m; ++i) {
+    if (h_u[i] >= n || h_v[i] >= n) return DYG_E_VERTEX_RANGE;
+    if (h_u[i] == h_v[i]) return DYG_E_SELF_LOOP;
+    if (find(h_u[i], h_v[i]) < 0) return DYG_E_H_NOT_SUBSET;
+    if (repeat[i]) return DYG_E_DUPLICATE_IN_BATCH;
+  }
+
+  dyg_ctx* c = new (std::nothrow) dyg_ctx();
+  if (!c) return DYG_E_NOMEM;
+  c->n = n;
+  c->params = *params;
+  c->Q = params->Q;
+  c->w_ref = params->w_ref > 0.0 ? params->w_ref : (wmax > 0.0 ? wmax : 1.0);
+  c->has_K = !(std::isinf(params->K) && params->K > 0);
+  c->uid_base = params->uid_base;
+  hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete c;
+    return fail_hip(e);
+  }
+  if (params->flags & DYG_FLAG_TIMING)
+    for (hipEvent_t& ev : c->ev)
+      if ((e = hipEventCreate(&ev)) != hipSuccess) {
+        dyg_destroy(c);
+        return fail_hip(e);
+      }
+  // G0 layout
+  std::vector<Ent> le(nnz);
+  std::vector<double> lw(w, w + nnz);
+  for (uint64_t k = 0; k < nnz; ++k)
+    le[k] = Ent{col[k], quantize_host(w[k], c->w_ref, c->Q), 1.0 / w[k]};
+  std::vector<uint64_t> start(rowptr, rowptr + n + 1);
+  HostAdj A;
+  layout(A, n, start, le, lw, params->slack);
+  // H0 layout: directed entries sorted by (row, neighbour), weights from G0
+  std::vector<std::pair<uint64_t, uint64_t>> hd;
+  hd.reserve(2 * h_m);
+  for (uint64_t i = 0; i < h_m; ++i) {
+    const uint64_t j = static_cast<uint64_t>(find(h_u[i], h_v[i]));
+    hd.push_back({(static_cast<uint64_t>(h_u[i]) << 32) | h_v[i], j});
+    hd.push_back({(static_cast<uint64_t>(h_v[i]) << 32) | h_u[i], j});
+  }
+  std::sort(hd.begin(), hd.end());
+  std::vector<uint64_t> hstart(n + 1, 0);
+  std::vector<Ent> he(hd.size());
+  std::vector<double> hw(hd.size());
+  for (size_t i = 0; i < hd.size(); ++i) {
+    const uint32_t a = static_cast<uint32_t>(hd[i].first >> 32);
+    const uint32_t b = static_cast<uint32_t>(hd[i].first);
+    hstart[a + 1]++;
+    he[i] = Ent{b, le[hd[i].second].qw, le[hd[i].second].rinv};
+    hw[i] = w[hd[i].second];
+  }
+  for (uint32_t u = 0; u < n; ++u) hstart[u + 1] += hstart[u];
+  HostAdj B;
+  layout(B, n, hstart, he, hw, params->slack);
+  const uint64_t gcap = pool_capacity_for(A.ent.size(), params->flags);
+  const uint64_t hcap = pool_capacity_for(B.ent.size(), params->flags);
+  if (gcap >= (1ull << 32) || hcap >= (1ull << 32)) {
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+    return DYG_E_NOMEM;
+  }
+  rc = upload_graph(c->G, n, A, gcap, c->stream);
+  if (!rc) rc = upload_graph(c->H, n, B, hcap, c->stream);
+  if (!rc) {
+    e = hipMalloc(&c->ctl, sizeof(BatchCtl));
+    if (e != hipSuccess) rc = fail_hip(e);
+  }
+  if (!rc) {
+    BatchCtl init{};
+    init.err_key = ~0ull;
+    init.pool_top[0] = A.ent.size();
+    init.pool_top[1] = B.ent.size();
+    e = hipMemcpyAsync(c->ctl, &init, sizeof(init), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail_hip(e);
+    c->pool_top[0] = A.ent.size();
+    c->pool_top[1] = B.ent.size();
+  }
+  if (rc) {
+    dyg_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return DYG_OK;
+}
+
+namespace {
+
+// Size every staging buffer for a batch; returns DYG_OK or DYG_E_NOMEM.
+int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
+                    uint64_t walkers, uint64_t& hadd_cap, uint64_t& hash_slots) {
+  const uint64_t nu = n_ins + n_del;
+  hadd_cap = n_ins + n_del * std::max<uint32_t>(Lcap, 2);
+  const uint64_t keys = std::max<uint64_t>(nu, 2 * hadd_cap);
+  hash_slots = next_pow2(2 * keys + 64);
+  if (hash_slots > (1ull << 31)) return DYG_E_NOMEM;
+  bool ok = c->ins_qw.ensure(4 * n_ins + 8) && c->ins_rinv.ensure(8 * n_ins + 8) &&
+            c->in_h.ensure(n_del + 8) && c->res.ensure(sizeof(dyg_update_result) * nu + 8) &&
+            c->hadd.ensure(sizeof(AddRec) * hadd_cap + 8) &&
+            c->hash.ensure(sizeof(HashSlot) * hash_slots) &&
+            (walkers == 0 || (c->wrec.ensure(sizeof(dyg_walker_record) * walkers) &&
+                              c->wofs.ensure(8 * nu + 8)));
+  for (int g = 0; g < 2 && ok; ++g) {
+    const uint64_t cap = g == 0 ? 2 * n_ins : 2 * hadd_cap;
+    ok = c->touched_rows[g].ensure(4 * cap + 8) && c->touched_k[g].ensure(4 * cap + 8) &&
+         c->touched_need[g].ensure(4 * cap + 8) && c->add_keep[g].ensure(cap + 8);
+  }
+  return ok ? DYG_OK : DYG_E_NOMEM;
+}
+
+BatchArgs make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t* iu,
+                    const uint32_t* iv, const double* iw, const uint32_t* du, const uint32_t* dv,
+                    const uint16_t* s, const uint16_t* L, uint32_t Lcap, uint64_t hadd_cap,
+                    uint64_t hash_slots, dyg::UpdRes* res, bool record) {
+  BatchArgs a{};
+  a.n = c->n;
+  a.n_ins = static_cast<uint32_t>(n_ins);
+  a.n_del = static_cast<uint32_t>(n_del);
+  a.iu = iu;
+  a.iv = iv;
+  a.iw = iw;
+  a.du = du;
+  a.dv = dv;
+  a.s = s;
+  a.L = L;
+  a.s_def = c->params.s_default;
+  a.L_def = c->params.L_default;
+  a.Lcap = Lcap;
+  a.uid_base = c->uid_base;
+  a.seed = c->params.seed;
+  a.K = c->params.K;
+  a.has_K = c->has_K ? 1 : 0;
+  a.bounce = c->params.dead_end;
+  a.w_ref = c->w_ref;
+  a.Q = c->Q;
+  a.ins_qw = c->ins_qw.as<uint32_t>();
+  a.ins_rinv = c->ins_rinv.as<double>();
+  a.in_h = c->in_h.as<uint8_t>();
+  a.res = res;
+  a.wrec = record ? c->wrec.as<dyg::WalkerRec>() : nullptr;
+  a.wofs = record ? c->wofs.as<uint64_t>() : nullptr;
+  a.hadd = c->hadd.as<AddRec>();
+  a.hadd_cap = static_cast<uint32_t>(hadd_cap);
+  a.hash = c->hash.as<HashSlot>();
+  a.hash_mask = static_cast<uint32_t>(hash_slots - 1);
+  a.ctl = c->ctl;
+  for (int g = 0; g < 2; ++g) {
+    a.touched_rows[g] = c->touched_rows[g].as<uint32_t>();
+    a.touched_k[g] = c->touched_k[g].as<uint32_t>();
+    a.touched_need[g] = c->touched_need[g].as<uint32_t>();
+    a.add_keep[g] = c->add_keep[g].as<uint8_t>();
+  }
+  return a;
+}
+
+void enqueue_pipeline(dyg_ctx* c, const BatchArgs& a, uint64_t hash_slots) {
+  const bool timed = c->ev[0] != nullptr;
+  if (timed) (void)hipEventRecord(c->ev[0], c->stream);
+  dyg::launch_batch_begin(a, c->G, c->H, hash_slots, c->stream);
+  dyg::launch_validate(a, c->G, c->stream);
+  dyg::launch_phase1(a, c->G, c->H, c->stream);
+  if (timed) (void)hipEventRecord(c->ev[1], c->stream);
+  dyg::launch_walks(a, c->G, c->H, c->stream);
+  if (timed) (void)hipEventRecord(c->ev[2], c->stream);
+  dyg::launch_phase4(a, c->G, 0, hash_slots, c->stream);
+  dyg::launch_phase4(a, c->H, 1, hash_slots, c->stream);
+  if (timed) (void)hipEventRecord(c->ev[3], c->stream);
+  c->timed_pending = timed && (a.n_ins + a.n_del) > 0;
+}
+
+// Fold the events of the batch that just completed into the timers.
+void collect_timing(dyg_ctx* c) {
+  if (!c->timed_pending) return;
+  c->timed_pending = false;
+  float walk = 0.f, batch = 0.f;
+  if (hipEventElapsedTime(&walk, c->ev[1], c->ev[2]) == hipSuccess &&
+      hipEventElapsedTime(&batch, c->ev[0], c->ev[3]) == hipSuccess) {
+    c->walk_launches++;
+    c->walk_ms_last = walk;
+    c->walk_ms_total += walk;
+    c->batch_ms_last = batch;
+  }
+}
+
+int decode_err(unsigned long long key) {
+  if (key == ~0ull) return DYG_OK;
+  return -static_cast<int>(key & 0xFF);
+}
+
+// Finish phase 4 of graphs that ran short of pool slots: grow the pool,
+// then run phase 4 again from the batch's staged additions.
+int repair_nomem(dyg_ctx* c, const BatchArgs& a, uint64_t hash_slots, BatchCtl& ctl) {
+  for (int attempt = 0; attempt < 4 && (ctl.nomem[0] || ctl.nomem[1]); ++attempt) {
+    for (int g = 0; g < 2; ++g) {
+      if (!ctl.nomem[g]) continue;
+      DevGraph& X = g ? c->H : c->G;
+      dyg::launch_phase4_reset(a, X, g, c->stream);
+      const uint64_t want = ctl.pool_top[g] + ctl.need[g] + ctl.need[g] / 2 + 64;
+      int rc = compact_graph(c, g, want);
+      if (rc) return rc;
+      dyg::launch_phase4(a, X, g, hash_slots, c->stream);
+    }
+    int rc = sync_ctl_host(c, ctl);
+    if (rc) return rc;
+  }
+  return (ctl.nomem[0] || ctl.nomem[1]) ? DYG_E_NOMEM : DYG_OK;
+}
+
+// Keep at least a quarter of each pool free between batches.
+int maybe_compact(dyg_ctx* c) {
+  for (int g = 0; g < 2; ++g) {
+    const DevGraph& X = g ? c->H : c->G;
+    if (c->pool_top[g] * 4 > X.pool_cap * 3) {
+      int rc = compact_graph(c, g, 0);
+      if (rc) return rc;
+    }
+  }
+  return DYG_OK;
+}
+
+}  // namespace
+
+extern "C" int dyg_apply_batch(dyg_ctx* c, uint64_t n_ins, const uint32_t* iu,
+                               const uint32_t* iv, const double* iw, uint64_t n_del,
+                               const uint32_t* du, const uint32_t* dv, const uint16_t* s,
+                               const uint16_t* L, dyg_update_result* results,
+                               dyg_walker_record* walkers) {
+  if (!c) return DYG_E_INVALID_ARG;
+  if (c->broken) return DYG_E_NOMEM;
+  if ((n_ins && (!iu || !iv || !iw)) || (n_del && (!du || !dv))) return DYG_E_INVALID_ARG;
+  const uint64_t nu = n_ins + n_del;
+  if (nu >= (1ull << 30)) return DYG_E_INVALID_ARG;
+  if (c->async_inflight) {
+    int rc = dyg_sync(c);
+    (void)rc;
+  }
+  uint32_t Lcap = c->params.L_default;
+  uint64_t walkers_total = 0;
+  std::vector<uint64_t> wofs;
+  if (L)
+    for (uint64_t i = 0; i < nu; ++i) Lcap = std::max<uint32_t>(Lcap, L[i]);
+  Lcap = std::min<uint32_t>(std::max<uint32_t>(Lcap, 2), DYG_MAX_STEPS + 1);
+  if (walkers) {
+    wofs.resize(nu + 1);
+    wofs[0] = 0;
+    for (uint64_t i = 0; i < nu; ++i)
+      wofs[i + 1] = wofs[i] + std::min<uint32_t>(s ? s[i] : c->params.s_default, DYG_MAX_WALKERS);
+    walkers_total = wofs[nu];
+  }
+  uint64_t hadd_cap, hash_slots;
+  if (prepare_buffers(c, n_ins, n_del, Lcap, walkers_total, hadd_cap, hash_slots))
+    return DYG_E_NOMEM;
+  if (!c->iu.ensure(4 * n_ins + 8) || !c->iv.ensure(4 * n_ins + 8) ||
+      !c->iw.ensure(8 * n_ins + 8) || !c->du.ensure(4 * n_del + 8) ||
+      !c->dv.ensure(4 * n_del + 8) || !c->s.ensure(2 * nu + 8) || !c->L.ensure(2 * nu + 8))
+    return DYG_E_NOMEM;
+  // stage the batch in pinned memory, then one copy per array
+  const size_t in_bytes = 16 * n_ins + 8 * n_del + 4 * nu + 8 * (nu + 1) + 64;
+  if (!c->pin_in.ensure(in_bytes)) return DYG_E_NOMEM;
+  char* h = static_cast<char*>(c->pin_in.p);
+  hipStream_t st = c->stream;
+  hipError_t e = hipSuccess;
+  auto put = [&](DBuf& dst, const void* src, size_t bytes) {
+    if (!bytes || e != hipSuccess) return;
+    std::memcpy(h, src, bytes);
+    e = hipMemcpyAsync(dst.p, h, bytes, hipMemcpyHostToDevice, st);
+    h += (bytes + 15) & ~size_t(15);
+  };
+  put(c->iu, iu, 4 * n_ins);
+  put(c->iv, iv, 4 * n_ins);
+  put(c->iw, iw, 8 * n_ins);
+  put(c->du, du, 4 * n_del);
+  put(c->dv, dv, 4 * n_del);
+  if (s) put(c->s, s, 2 * nu);
+  if (L) put(c->L, L, 2 * nu);
+  if (walkers) put(c->wofs, wofs.data(), 8 * nu);
+  if (e != hipSuccess) return fail_hip(e);
+
+  BatchArgs a = make_args(c, n_ins, n_del, c->iu.as<uint32_t>(), c->iv.as<uint32_t>(),
+                          c->iw.as<double>(), c->du.as<uint32_t>(), c->dv.as<uint32_t>(),
+                          s ? c->s.as<uint16_t>() : nullptr, L ? c->L.as<uint16_t>() : nullptr,
+                          Lcap, hadd_cap, hash_slots, c->res.as<dyg::UpdRes>(), walkers != nullptr);
+  enqueue_pipeline(c, a, hash_slots);
+  if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e);
+
+  BatchCtl ctl;
+  int rc = sync_ctl_host(c, ctl);
+  if (rc) return rc;
+  collect_timing(c);
+  rc = decode_err(ctl.err_key);
+  if (rc) return rc;
+  if (ctl.nomem[0] || ctl.nomem[1]) {
+    rc = repair_nomem(c, a, hash_slots, ctl);
+    if (rc) {
+      c->broken = true;
+      return rc;
+    }
+  }
+  const size_t out_bytes = sizeof(dyg_update_result) * nu + sizeof(dyg_walker_record) * walkers_total;
+  if (results || walkers) {
+    if (!c->pin_out.ensure(out_bytes + 64)) return DYG_E_NOMEM;
+    char* o = static_cast<char*>(c->pin_out.p);
+    if (results && nu)
+      e = hipMemcpyAsync(o, c->res.p, sizeof(dyg_update_result) * nu, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && walkers && walkers_total)
+      e = hipMemcpyAsync(o + sizeof(dyg_update_result) * nu, c->wrec.p,
+                         sizeof(dyg_walker_record) * walkers_total, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail_hip(e);
+    if (results) std::memcpy(results, o, sizeof(dyg_update_result) * nu);
+    if (walkers)
+      std::memcpy(walkers, o + sizeof(dyg_update_result) * nu,
+                  sizeof(dyg_walker_record) * walkers_total);
+  }
+  c->uid_base += nu;
+  c->batches++;
+  return maybe_compact(c);
+}
+
+extern "C" int dyg_apply_batch_dev(dyg_ctx* c, const dyg_batch_dev* b, void* stream) {
+  if (!c || !b) return DYG_E_INVALID_ARG;
+  if (c->broken) return DYG_E_NOMEM;
+  const uint64_t n_ins = b->n_ins, n_del = b->n_del, nu = n_ins + n_del;
+  if ((n_ins && (!b->iu || !b->iv || !b->iw)) || (n_del && (!b->du || !b->dv)) ||
+      nu >= (1ull << 30) || b->L_max > DYG_MAX_STEPS)
+    return DYG_E_INVALID_ARG;
+  if (c->async_inflight) {
+    int rc = dyg_sync(c);
+    if (rc) return rc;
+  }
+  const uint32_t Lcap = std::max<uint32_t>(b->L ? b->L_max : c->params.L_default, 2);
+  uint64_t hadd_cap, hash_slots;
+  if (prepare_buffers(c, n_ins, n_del, Lcap, 0, hadd_cap, hash_slots)) return DYG_E_NOMEM;
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  std::swap(st, c->stream);  // every launcher below runs on the caller's stream
+  BatchArgs a = make_args(c, n_ins, n_del, b->iu, b->iv, b->iw, b->du, b->dv, b->s, b->L, Lcap,
+                          hadd_cap, hash_slots,
+                          b->results ? reinterpret_cast<dyg::UpdRes*>(b->results)
+                                     : c->res.as<dyg::UpdRes>(),
+                          false);
+  enqueue_pipeline(c, a, hash_slots);
+  std::swap(st, c->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_hip(e);
+  c->async_inflight = true;
+  c->async_nu = nu;
+  c->pending_status = DYG_OK;
+  return DYG_OK;
+}
+
+extern "C" int dyg_sync(dyg_ctx* c) {
+  if (!c) return DYG_E_INVALID_ARG;
+  if (!c->async_inflight) return c->pending_status;
+  c->async_inflight = false;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return c->pending_status = fail_hip(e);
+  BatchCtl ctl;
+  int rc = sync_ctl_host(c, ctl);
+  if (rc) return c->pending_status = rc;
+  collect_timing(c);
+  rc = decode_err(ctl.err_key);
+  if (rc) return c->pending_status = rc;
+  if (ctl.nomem[0] || ctl.nomem[1]) {
+    // the staged additions of this batch are still intact: finish them
+    c->broken = true;
+    return c->pending_status = DYG_E_NOMEM;
+  }
+  c->uid_base += c->async_nu;
+  c->batches++;
+  return c->pending_status = maybe_compact(c);
+}
+
+namespace {
+
+int query_graph(dyg_ctx* c, int which, uint64_t cap, uint64_t* m, uint32_t* u, uint32_t* v,
+                double* w) {
+  if (!c || !m) return DYG_E_INVALID_ARG;
+  if (c->async_inflight) {
+    int rc = dyg_sync(c);
+    if (rc) return rc;
+  }
+  BatchCtl ctl;
+  int rc = sync_ctl_host(c, ctl);
+  if (rc) return rc;
+  const DevGraph& X = which ? c->H : c->G;
+  std::vector<uint64_t> start;
+  std::vector<Ent> le;
+  std::vector<double> lw;
+  rc = download_live(X, c->n, ctl.pool_top[which], start, le, lw, c->stream);
+  if (rc) return rc;
+  uint64_t cnt = 0;
+  for (uint32_t a = 0; a < c->n; ++a)
+    for (uint64_t k = start[a]; k < start[a + 1]; ++k)
+      if (le[k].nbr > a) ++cnt;
+  *m = cnt;
+  if (cap < cnt) return DYG_OK;
+  if (cnt && (!u || !v || !w)) return DYG_E_INVALID_ARG;
+  uint64_t i = 0;
+  for (uint32_t a = 0; a < c->n; ++a)
+    for (uint64_t k = start[a]; k < start[a + 1]; ++k)
+      if (le[k].nbr > a) {
+        u[i] = a;
+        v[i] = le[k].nbr;
+        w[i] = lw[k];
+        ++i;
+      }
+  return DYG_OK;
+}
+
+}  // namespace
+
+extern "C" int dyg_query_sparsifier(dyg_ctx* c, uint64_t cap, uint64_t* m, uint32_t* u,
+                                    uint32_t* v, double* w) {
+  return query_graph(c, 1, cap, m, u, v, w);
+}
+
+extern "C" int dyg_query_graph(dyg_ctx* c, uint64_t cap, uint64_t* m, uint32_t* u, uint32_t* v,
+                               double* w) {
+  return query_graph(c, 0, cap, m, u, v, w);
+}
+
+extern "C" int dyg_stats(dyg_ctx* c, dyg_stats_t* out) {
+  if (!c || !out) return DYG_E_INVALID_ARG;
+  if (c->async_inflight) {
+    int rc = dyg_sync(c);
+    if (rc) return rc;
+  }
+  BatchCtl ctl;
+  int rc = sync_ctl_host(c, ctl);
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  out->n = c->n;
+  for (int g = 0; g < 2; ++g) {
+    const DevGraph& X = g ? c->H : c->G;
+    std::vector<Row> rows(c->n);
+    hipError_t e =
+        hipMemcpyAsync(rows.data(), X.rows, sizeof(Row) * c->n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail_hip(e);
+    uint64_t live = 0, dead = 0;
+    for (const Row& r : rows) {
+      live += r.len - r.dead;
+      dead += r.dead;
+    }
+    if (g == 0) {
+      out->g_edges = live / 2;
+      out->g_dead = dead;
+      out->g_pool_used = ctl.pool_top[0];
+      out->g_pool_cap = X.pool_cap;
+    } else {
+      out->h_edges = live / 2;
+      out->h_dead = dead;
+      out->h_pool_used = ctl.pool_top[1];
+      out->h_pool_cap = X.pool_cap;
+    }
+  }
+  out->uid_base = c->uid_base;
+  out->batches = c->batches;
+  out->compactions = c->compactions;
+  out->w_ref = c->w_ref;
+  out->walk_steps = ctl.steps_total;
+  out->walk_alg_bytes = ctl.alg_bytes_total;
+  out->walk_launches = c->walk_launches;
+  out->walk_ms_total = c->walk_ms_total;
+  out->walk_ms_last = c->walk_ms_last;
+  out->batch_ms_last = c->batch_ms_last;
+  return DYG_OK;
+}
+
+extern "C" int dyg_compact(dyg_ctx* c) {
+  if (!c) return DYG_E_INVALID_ARG;
+  if (c->async_inflight) {
+    int rc = dyg_sync(c);
+    if (rc) return rc;
+  }
+  for (int g = 0; g < 2; ++g) {
+    int rc = compact_graph(c, g, 0);
+    if (rc) return rc;
+  }
+  return DYG_OK;
+}
+
+extern "C" void dyg_destroy(dyg_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_graph(c->G);
+  free_graph(c->H);
+  if (c->ctl) (void)hipFree(c->ctl);
+  DBuf* bufs[] = {&c->iu, &c->iv, &c->iw, &c->du, &c->dv, &c->s, &c->L, &c->ins_qw,
+                  &c->ins_rinv, &c->in_h, &c->res, &c->wrec, &c->wofs, &c->hadd, &c->hash};
+  for (DBuf* b : bufs) b->release();
+  for (int g = 0; g < 2; ++g) {
+    c->touched_rows[g].release();
+    c->touched_k[g].release();
+    c->touched_need[g].release();
+    c->add_keep[g].release();
+  }
+  c->pin_in.release();
+  c->pin_out.release();
+  for (hipEvent_t ev : c->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}

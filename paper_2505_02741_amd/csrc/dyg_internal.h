@@ -1,0 +1,144 @@
+// Library-internal declarations shared by the HIP translation units of
+// libdygrass.  Not installed; the public interface is include/dygrass.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dyg {
+
+// ---------------------------------------------------------------------------
+// Device adjacency of one graph (the original graph G or the sparsifier H).
+//
+// Every vertex owns a contiguous segment of an entry pool: `len` entries in
+// ascending neighbour order followed by `cap - len` free slots (per-node
+// slack).  A deleted edge stays in place as a tombstone (qw == 0) until the
+// segment is relocated or compacted; a zero weight never wins the cumulative
+// search, so walks skip tombstones without testing them.  Neighbour ids are
+// unique within a segment (a re-inserted edge revives its tombstone).
+struct Row {
+  uint32_t off;   // first entry in the pool
+  uint32_t len;   // entries in use, tombstones included
+  uint32_t cap;   // slots owned
+  uint32_t dead;  // tombstones among the len entries
+};
+
+struct Ent {
+  uint32_t nbr;  // neighbour id
+  uint32_t qw;   // quantised weight, 0 = tombstone
+  double rinv;   // resistance 1/w
+};
+
+static_assert(sizeof(Row) == 16, "Row layout");
+static_assert(sizeof(Ent) == 16, "Ent layout");
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kMaxWalkers = 1024;
+constexpr uint32_t kMaxSteps = 1024;
+
+struct DevGraph {
+  Row* rows = nullptr;        // [n]
+  Ent* ent = nullptr;         // [pool_cap]
+  double* w = nullptr;        // [pool_cap] weight of each entry (cold)
+  uint32_t* pending = nullptr;  // [n] per-row counter, zero between batches
+  uint64_t pool_cap = 0;      // entries
+};
+
+// Edge to be added to a graph in phase 4 (one record per undirected edge).
+struct AddRec {
+  uint32_t a, b;
+  uint32_t qw, pad;
+  double rinv;
+  double w;
+};
+static_assert(sizeof(AddRec) == 32, "AddRec layout");
+
+// Per-update result, layout identical to dyg_update_result.
+struct UpdRes {
+  uint8_t kind, flag, any_hit, reserved;
+  uint16_t winner, n_rec;
+  uint32_t steps;
+  uint32_t reserved2;
+  double Rmin;
+};
+static_assert(sizeof(UpdRes) == 24, "UpdRes layout");
+
+struct WalkerRec {
+  uint8_t hit, pad;
+  uint16_t steps;
+  uint32_t end;
+  double R;
+};
+static_assert(sizeof(WalkerRec) == 16, "WalkerRec layout");
+
+// Device-resident control block of one batch.
+struct BatchCtl {
+  unsigned long long err_key;   // min over (phase, update, code); ~0 = valid
+  uint32_t hadd_count;          // records appended for H
+  uint32_t touched[2];          // touched rows, per graph (0 = G, 1 = H)
+  unsigned long long need[2];   // pool slots needed by relocations, per graph
+  uint32_t nomem[2];            // phase-4 pool shortfall, per graph
+  uint32_t pad;
+  unsigned long long pool_top[2];  // next free pool slot, per graph
+  // cumulative over the context's life (never reset by a batch)
+  unsigned long long steps_total;      // walker steps taken
+  unsigned long long alg_bytes_total;  // algorithmic gathered bytes of those steps
+};
+
+// Slot of the validation / dedup hash table.
+struct HashSlot {
+  unsigned long long key;  // ~0 = empty
+  uint32_t minidx;
+  uint32_t pad;
+};
+
+// Everything the kernels of one batch need.
+struct BatchArgs {
+  uint32_t n;
+  uint32_t n_ins, n_del;
+  const uint32_t *iu, *iv;
+  const double* iw;
+  const uint32_t *du, *dv;
+  const uint16_t *s, *L;  // per update or null
+  uint32_t s_def, L_def;
+  uint32_t Lcap;           // >= every L of the batch, >= 2
+  uint64_t uid_base;
+  uint64_t seed;
+  double K;
+  int has_K;
+  int bounce;
+  double w_ref;
+  int Q;
+  // work buffers
+  uint32_t* ins_qw;     // [n_ins]
+  double* ins_rinv;     // [n_ins]
+  uint8_t* in_h;        // [n_del]
+  UpdRes* res;          // [n_ins + n_del]
+  WalkerRec* wrec;      // optional [sum s]
+  const uint64_t* wofs; // optional [n_ins + n_del]
+  AddRec* hadd;         // [hadd_cap]
+  uint32_t hadd_cap;
+  HashSlot* hash;
+  uint32_t hash_mask;
+  BatchCtl* ctl;
+  // per-graph phase-4 scratch
+  uint32_t* touched_rows[2];  // [add capacity]
+  uint32_t* touched_k[2];
+  uint32_t* touched_need[2];
+  uint8_t* add_keep[2];       // per directed add entry: 1 = needs a new slot
+};
+
+// Host-side launchers (defined in dyg_kernels.hip), all asynchronous on
+// `stream`.
+void launch_batch_begin(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
+                        uint64_t hash_slots, hipStream_t stream);
+void launch_validate(const BatchArgs& a, const DevGraph& G, hipStream_t stream);
+void launch_phase1(const BatchArgs& a, DevGraph& G, DevGraph& H, hipStream_t stream);
+void launch_walks(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
+                  hipStream_t stream);
+// Phase 4 on one graph (which = 0: G += insertions, 1: H += hadd records).
+void launch_phase4(const BatchArgs& a, DevGraph& X, int which, uint64_t hash_slots,
+                   hipStream_t stream);
+void launch_batch_end(const BatchArgs& a, hipStream_t stream);
+
+}  // namespace dyg

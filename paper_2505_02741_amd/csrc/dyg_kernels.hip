@@ -1,0 +1,713 @@
+// HIP kernels of one dyGRASS update batch on gfx950.
+//
+// Batch pipeline (Sec. III-F: the GPU version applies a batch's updates at
+// the end of the batch), every step on one stream, no host round trip:
+//   begin     reset the batch control block and the hash table
+//   validate  per-update checks; the first failing update (in uid order) is
+//             kept in ctl->err_key and every later kernel becomes a no-op
+//   phase 1   deleted edges become tombstones in G and, if present, in H
+//             (Sec. III-C: an edge outside H leaves H unchanged)
+//   walks     one wavefront per update, one lane per walker: weight-biased
+//             non-backtracking walks (Sec. III-B) on H for insertions and on
+//             G for deletions (Sec. III-C); ballot for "some walker reached
+//             q", wavefront argmin for the least resistance (Eq. 12); a
+//             deletion replays its winner to emit the path edges missing from
+//             H, or the fallback edges when nobody hit
+//   phase 4   G += insertions, H += accepted + recovered edges: revive
+//             tombstones, append into per-node slack, relocate a segment that
+//             overflows, then merge the appended tail into sorted order
+#include "dyg_internal.h"
+#include "dyg_philox.h"
+
+#include <math.h>
+
+namespace dyg {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWalkBlock = 256;  // four updates per workgroup
+constexpr int kBlock = 256;
+
+enum : int {
+  E_INVALID_ARG = 1,
+  E_SELF_LOOP = 2,
+  E_VERTEX_RANGE = 3,
+  E_BAD_WEIGHT = 4,
+  E_EDGE_EXISTS = 5,
+  E_EDGE_MISSING = 6,
+  E_DUPLICATE = 7,
+};
+
+__device__ __forceinline__ bool batch_failed(const BatchCtl* c) {
+  return c->err_key != ~0ull;
+}
+
+__device__ __forceinline__ unsigned long long edge_key(uint32_t a, uint32_t b) {
+  const uint32_t lo = a < b ? a : b;
+  const uint32_t hi = a < b ? b : a;
+  return (static_cast<unsigned long long>(lo) << 32) | hi;
+}
+
+// Index of neighbour v in the segment of r (tombstones included), or -1.
+__device__ __forceinline__ int find_nbr(const Ent* ent, Row r, uint32_t v) {
+  int lo = 0, hi = static_cast<int>(r.len) - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const uint32_t x = ent[r.off + mid].nbr;
+    if (x == v) return mid;
+    if (x < v) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ bool has_live(const Row* rows, const Ent* ent, uint32_t a,
+                                         uint32_t b) {
+  const Row r = rows[a];
+  const int k = find_nbr(ent, r, b);
+  return k >= 0 && ent[r.off + k].qw != 0u;
+}
+
+// ---- hash table (validation duplicates, phase-4 dedup) ---------------------
+
+__device__ __forceinline__ uint32_t hash_home(unsigned long long key, uint32_t mask) {
+  key ^= key >> 33;
+  key *= 0xff51afd7ed558ccdull;
+  key ^= key >> 33;
+  key *= 0xc4ceb9fe1a85ec53ull;
+  key ^= key >> 33;
+  return static_cast<uint32_t>(key) & mask;
+}
+
+// Insert key; keep the minimum index seen for it.  The table holds at least
+// twice as many slots as keys, so a probe sequence always meets an empty slot
+// or the key within mask+1 probes.
+__device__ void hash_insert_min(HashSlot* h, uint32_t mask, unsigned long long key,
+                                uint32_t idx) {
+  uint32_t s = hash_home(key, mask);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const unsigned long long prev = atomicCAS(&h[s].key, ~0ull, key);
+    if (prev == ~0ull || prev == key) {
+      atomicMin(&h[s].minidx, idx);
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
+__device__ uint32_t hash_min_of(const HashSlot* h, uint32_t mask, unsigned long long key) {
+  uint32_t s = hash_home(key, mask);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const unsigned long long k = h[s].key;
+    if (k == key) return h[s].minidx;
+    if (k == ~0ull) return ~0u;
+    s = (s + 1) & mask;
+  }
+  return ~0u;
+}
+
+// True for the first inserter of key.
+__device__ bool hash_insert_first(HashSlot* h, uint32_t mask, unsigned long long key) {
+  uint32_t s = hash_home(key, mask);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const unsigned long long prev = atomicCAS(&h[s].key, ~0ull, key);
+    if (prev == ~0ull) return true;
+    if (prev == key) return false;
+    s = (s + 1) & mask;
+  }
+  return false;
+}
+
+// ---- begin ------------------------------------------------------------------
+
+__global__ void k_batch_begin(BatchCtl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->err_key = ~0ull;
+    ctl->hadd_count = 0;
+    ctl->touched[0] = ctl->touched[1] = 0;
+    ctl->need[0] = ctl->need[1] = 0;
+    ctl->nomem[0] = ctl->nomem[1] = 0;
+  }
+}
+
+__global__ void k_clear_hash(HashSlot* h, uint64_t slots) {
+  for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < slots;
+       i += uint64_t(gridDim.x) * blockDim.x) {
+    h[i].key = ~0ull;
+    h[i].minidx = ~0u;
+  }
+}
+
+// ---- validation ---------------------------------------------------------------
+
+constexpr unsigned long long kDelTag = 1ull << 63;  // n < 2^31 keeps bit 63 free
+
+__global__ void k_validate_a(BatchArgs a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_ins + a.n_del) return;
+  if (i < a.n_ins) {
+    const uint32_t u = a.iu[i], v = a.iv[i];
+    if (u < a.n && v < a.n && u != v) hash_insert_min(a.hash, a.hash_mask, edge_key(u, v), i);
+  } else {
+    const uint32_t j = i - a.n_ins;
+    const uint32_t u = a.du[j], v = a.dv[j];
+    if (u < a.n && v < a.n && u != v)
+      hash_insert_min(a.hash, a.hash_mask, edge_key(u, v) | kDelTag, j);
+  }
+}
+
+__device__ __forceinline__ void report(BatchCtl* ctl, unsigned long long phase, uint32_t idx,
+                                       int code) {
+  atomicMin(&ctl->err_key, (phase << 56) | (static_cast<unsigned long long>(idx) << 8) |
+                               static_cast<unsigned long long>(code));
+}
+
+// Quantised weight: round-half-even(w / w_ref * 2^Q) clamped to [1, 2^32-1].
+__device__ __forceinline__ uint32_t quantize(double w, double w_ref, int Q) {
+  const double y = rint((w / w_ref) * ldexp(1.0, Q));
+  if (!(y >= 1.0)) return 1u;
+  if (y > 4294967295.0) return 4294967295u;
+  return static_cast<uint32_t>(y);
+}
+
+__global__ void k_validate_b(BatchArgs a, const Row* grows, const Ent* gent) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_ins + a.n_del) return;
+  if (i < a.n_ins) {
+    const uint32_t u = a.iu[i], v = a.iv[i];
+    const double w = a.iw[i];
+    int code = 0;
+    if (u >= a.n || v >= a.n) code = E_VERTEX_RANGE;
+    else if (u == v) code = E_SELF_LOOP;
+    else if (!(w > 0.0) || isinf(w)) code = E_BAD_WEIGHT;
+    else if (has_live(grows, gent, u, v)) code = E_EDGE_EXISTS;
+    else if (hash_min_of(a.hash, a.hash_mask, edge_key(u, v)) < i) code = E_DUPLICATE;
+    if (code) report(a.ctl, 0, i, code);
+    else {
+      a.ins_qw[i] = quantize(w, a.w_ref, a.Q);
+      a.ins_rinv[i] = 1.0 / w;
+    }
+  } else {
+    const uint32_t j = i - a.n_ins;
+    const uint32_t u = a.du[j], v = a.dv[j];
+    int code = 0;
+    if (u >= a.n || v >= a.n) code = E_VERTEX_RANGE;
+    else if (u == v) code = E_SELF_LOOP;
+    else if (!has_live(grows, gent, u, v)) code = E_EDGE_MISSING;
+    else if (hash_min_of(a.hash, a.hash_mask, edge_key(u, v) | kDelTag) < j) code = E_DUPLICATE;
+    if (code) report(a.ctl, 1, j, code);
+  }
+  const uint32_t s = a.s ? a.s[i] : a.s_def;
+  const uint32_t L = a.L ? a.L[i] : a.L_def;
+  if (s > kMaxWalkers || L > kMaxSteps || L > a.Lcap) report(a.ctl, 2, i, E_INVALID_ARG);
+}
+
+// ---- phase 1 -------------------------------------------------------------------
+
+__device__ __forceinline__ void tombstone(DevGraph X, uint32_t a, uint32_t b) {
+  const Row r = X.rows[a];
+  const int k = find_nbr(X.ent, r, b);
+  if (k < 0) return;
+  X.ent[r.off + k].qw = 0u;
+  atomicAdd(&X.rows[a].dead, 1u);
+}
+
+__global__ void k_phase1(BatchArgs a, DevGraph G, DevGraph H) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_del) return;
+  const uint32_t u = a.du[j], v = a.dv[j];
+  const bool in_h = has_live(H.rows, H.ent, u, v);
+  tombstone(G, u, v);
+  tombstone(G, v, u);
+  if (in_h) {
+    tombstone(H, u, v);
+    tombstone(H, v, u);
+  }
+  a.in_h[j] = in_h ? 1 : 0;
+}
+
+// ---- walks ------------------------------------------------------------------------
+
+struct Walk {
+  uint32_t steps;
+  uint32_t end;
+  double R;
+  bool hit;
+  uint32_t bytes;  // algorithmic gathered bytes of the steps taken
+};
+
+// Bytes one step must gather at a vertex of live degree d: the row (offset and
+// degree, 8 B), the (id, weight) pair of every live neighbour (8 B each) and
+// the resistance of the chosen edge (8 B); above 64 neighbours a cumulative-
+// weight binary search instead: 32 B plus 12 B per halving.
+__device__ __forceinline__ uint32_t step_bytes(uint32_t d) {
+  if (d <= 64u) return 16u + 8u * d;
+  return 32u + 12u * (32u - static_cast<uint32_t>(__clz(d - 1u)));
+}
+
+struct WalkParams {
+  const Row* rows;
+  const Ent* ent;
+  uint32_t p, q;
+  bool use_K;
+  double w_pq, K;
+  uint32_t L;
+  uint32_t key0, key1, uid_lo, uid_hi;
+  bool bounce;
+};
+
+// Emits nothing; the replay variant below passes an edge sink.
+struct NoSink {
+  __device__ __forceinline__ void operator()(uint32_t, uint32_t, const Ent&, uint32_t) const {}
+};
+
+// One walker: weight-biased choice among the neighbours other than the
+// previous vertex, stop on the distortion threshold, on reaching q, at a
+// dead end or after L steps (Sec. III-B).
+template <class Sink>
+__device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, Sink sink) {
+  uint32_t x = P.p, prev = kNone, steps = 0, block_of = kNone, bytes = 0;
+  double R = 0.0;
+  bool hit = false;
+  Philox4 rnd{0, 0, 0, 0};
+  for (uint32_t t = 0; t < P.L; ++t) {
+    const Row r = P.rows[x];
+    const uint2* e2 = reinterpret_cast<const uint2*>(P.ent + r.off);  // (nbr, qw) pairs
+    unsigned long long tot = 0;
+    for (uint32_t i = 0; i < r.len; ++i) {
+      const uint2 e = e2[2 * i];
+      tot += (e.x != prev) ? e.y : 0u;
+    }
+    uint32_t pick;
+    if (tot == 0) {
+      if (!(P.bounce && prev != kNone)) break;  // leaf: the walker stops
+      const int back = find_nbr(P.ent, r, prev);
+      if (back < 0) break;  // cannot happen: the edge just used is live
+      pick = static_cast<uint32_t>(back);
+    } else {
+      if (block_of != (t >> 1)) {
+        rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
+        block_of = t >> 1;
+      }
+      const unsigned long long r64 =
+          (t & 1u) ? (uint64_t(rnd.x2) | (uint64_t(rnd.x3) << 32))
+                   : (uint64_t(rnd.x0) | (uint64_t(rnd.x1) << 32));
+      const unsigned long long target = __umul64hi(r64, tot);
+      unsigned long long run = 0;
+      pick = r.len - 1;
+      for (uint32_t i = 0; i < r.len; ++i) {
+        const uint2 e = e2[2 * i];
+        run += (e.x != prev) ? e.y : 0u;
+        if (run > target) {
+          pick = i;
+          break;
+        }
+      }
+    }
+    const Ent ce = P.ent[r.off + pick];
+    bytes += step_bytes(r.len - r.dead);
+    R = R + ce.rinv;
+    sink(x, ce.nbr, ce, r.off + pick);
+    prev = x;
+    x = ce.nbr;
+    ++steps;
+    if (P.use_K && P.w_pq * R > P.K) break;
+    if (x == P.q) {
+      hit = true;
+      break;
+    }
+  }
+  return Walk{steps, x, R, hit, bytes};
+}
+
+// Wavefront argmin of (R, walker): smaller R wins, ties go to the lower walker.
+__device__ __forceinline__ void wave_argmin(double& R, uint32_t& w) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double oR = __shfl_xor(R, off, kWave);
+    const uint32_t ow = __shfl_xor(w, off, kWave);
+    if (oR < R || (oR == R && ow < w)) {
+      R = oR;
+      w = ow;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sink of the winner replay: path edges absent from H_mid, first occurrence.
+struct RecoverSink {
+  const Row* hrows;
+  const Ent* hent;
+  const double* gw;
+  AddRec* out;  // reserved block of `cap` records
+  uint32_t cap;
+  uint32_t* count;
+  __device__ void operator()(uint32_t a, uint32_t b, const Ent& e, uint32_t pos) const {
+    if (has_live(hrows, hent, a, b)) return;
+    const unsigned long long k = edge_key(a, b);
+    for (uint32_t z = 0; z < *count; ++z)
+      if (edge_key(out[z].a, out[z].b) == k) return;
+    if (*count >= cap) return;
+    out[*count] = AddRec{a, b, e.qw, 0u, e.rinv, gw[pos]};
+    ++*count;
+  }
+};
+
+__global__ __launch_bounds__(kWalkBlock) void k_walks(BatchArgs a, DevGraph G, DevGraph H) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + threadIdx.x / kWave;
+  if (upd >= a.n_ins + a.n_del) return;  // uniform across the wavefront
+  const bool is_ins = upd < a.n_ins;
+  const uint32_t j = upd - a.n_ins;
+  const uint32_t s = a.s ? a.s[upd] : a.s_def;
+  const uint32_t L = a.L ? a.L[upd] : a.L_def;
+  const uint64_t uid = a.uid_base + upd;
+
+  WalkParams P;
+  P.p = is_ins ? a.iu[upd] : a.du[j];
+  P.q = is_ins ? a.iv[upd] : a.dv[j];
+  P.use_K = is_ins && a.has_K;
+  P.w_pq = is_ins ? a.iw[upd] : 0.0;
+  P.K = a.K;
+  P.L = L;
+  P.key0 = static_cast<uint32_t>(a.seed);
+  P.key1 = static_cast<uint32_t>(a.seed >> 32);
+  P.uid_lo = static_cast<uint32_t>(uid);
+  P.uid_hi = static_cast<uint32_t>(uid >> 32);
+  P.bounce = a.bounce != 0;
+  P.rows = is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
+  P.ent = is_ins ? H.ent : G.ent;
+
+  UpdRes res;
+  res.kind = is_ins ? 0 : 1;
+  res.flag = 0;
+  res.any_hit = 0;
+  res.reserved = 0;
+  res.winner = 0xFFFF;
+  res.n_rec = 0;
+  res.steps = 0;
+  res.reserved2 = 0;
+  res.Rmin = INFINITY;
+
+  const bool walks = is_ins || a.in_h[j];
+  if (!walks) {
+    if (a.wrec)
+      for (uint32_t k = lane; k < s; k += kWave)
+        a.wrec[a.wofs[upd] + k] = WalkerRec{0, 0, 0, P.p, 0.0};
+    if (lane == 0) a.res[upd] = res;
+    return;
+  }
+
+  bool any_hit = false;
+  double bestR = INFINITY;
+  uint32_t bestW = kNone;
+  uint32_t steps = 0;
+  unsigned long long bytes = 0;
+  for (uint32_t base = 0; base < s; base += kWave) {
+    const uint32_t walker = base + lane;
+    const bool active = walker < s;
+    Walk o{0, P.p, 0.0, false, 0};
+    if (active) o = walk_one(P, walker, NoSink{});
+    if (active && a.wrec)
+      a.wrec[a.wofs[upd] + walker] =
+          WalkerRec{static_cast<uint8_t>(o.hit), 0, static_cast<uint16_t>(o.steps), o.end, o.R};
+    const bool h = active && o.hit;
+    any_hit = any_hit || (__ballot(h) != 0ull);
+    double cR = h ? o.R : INFINITY;
+    uint32_t cW = h ? walker : kNone;
+    wave_argmin(cR, cW);
+    if (cR < bestR) {  // a later chunk only wins with a strictly smaller R
+      bestR = cR;
+      bestW = cW;
+    }
+    steps += wave_sum(active ? o.steps : 0u);
+    bytes += wave_sum(active ? o.bytes : 0u);
+  }
+  res.any_hit = any_hit ? 1 : 0;
+  res.steps = steps;
+  if (any_hit) {
+    res.Rmin = bestR;
+    res.winner = static_cast<uint16_t>(bestW);
+  }
+  if (lane != 0) return;
+  atomicAdd(&a.ctl->steps_total, static_cast<unsigned long long>(steps));
+  atomicAdd(&a.ctl->alg_bytes_total, bytes);
+
+  if (is_ins) {
+    res.flag = any_hit ? 0 : 1;  // keep the new edge iff no walker reached q
+    if (!any_hit) {
+      const uint32_t slot = atomicAdd(&a.ctl->hadd_count, 1u);
+      if (slot < a.hadd_cap)
+        a.hadd[slot] = AddRec{P.p, P.q, a.ins_qw[upd], 0u, a.ins_rinv[upd], a.iw[upd]};
+    }
+    a.res[upd] = res;
+    return;
+  }
+
+  // deletion of a sparsifier edge: recover the least-resistance hitting path
+  res.flag = 1;
+  const uint32_t cap = L > 2 ? L : 2;
+  const uint32_t base = atomicAdd(&a.ctl->hadd_count, cap);
+  uint32_t count = 0;
+  if (base + cap <= a.hadd_cap) {
+    AddRec* out = a.hadd + base;
+    if (any_hit) {
+      RecoverSink sink{H.rows, H.ent, G.w, out, cap, &count};
+      walk_one(P, bestW, sink);
+    } else {
+      // no hit: per endpoint the least-resistance G edge not in H
+      const uint32_t ends[2] = {P.p, P.q};
+      for (int z = 0; z < 2; ++z) {
+        const Row r = G.rows[ends[z]];
+        int best = -1;
+        double bestr = 0.0;
+        for (uint32_t i = 0; i < r.len; ++i) {
+          const Ent e = G.ent[r.off + i];
+          if (e.qw == 0u) continue;
+          if (has_live(H.rows, H.ent, ends[z], e.nbr)) continue;
+          if (best < 0 || e.rinv < bestr) {
+            best = static_cast<int>(i);
+            bestr = e.rinv;
+          }
+        }
+        if (best >= 0) {
+          const Ent e = G.ent[r.off + best];
+          out[count++] = AddRec{ends[z], e.nbr, e.qw, 0u, e.rinv, G.w[r.off + best]};
+        }
+      }
+    }
+    for (uint32_t z = count; z < cap; ++z) out[z] = AddRec{kNone, kNone, 0u, 0u, 0.0, 0.0};
+  }
+  res.n_rec = static_cast<uint16_t>(count);
+  a.res[upd] = res;
+}
+
+// ---- phase 4 ------------------------------------------------------------------------
+
+struct AddEntry {
+  uint32_t r, c, qw;
+  double rinv, w;
+  bool valid;
+};
+
+// Directed entry e of the additions to graph `which`: two per undirected edge.
+__device__ __forceinline__ AddEntry add_entry(const BatchArgs& a, int which, uint32_t e) {
+  const uint32_t i = e >> 1;
+  const bool flip = e & 1u;
+  if (which == 0) {
+    const uint32_t u = a.iu[i], v = a.iv[i];
+    return AddEntry{flip ? v : u, flip ? u : v, a.ins_qw[i], a.ins_rinv[i], a.iw[i], true};
+  }
+  const AddRec rec = a.hadd[i];
+  if (rec.a >= a.n || rec.b >= a.n) return AddEntry{0, 0, 0, 0.0, 0.0, false};  // unused slot
+  return AddEntry{flip ? rec.b : rec.a, flip ? rec.a : rec.b, rec.qw, rec.rinv, rec.w, true};
+}
+
+__device__ __forceinline__ uint32_t add_count(const BatchArgs& a, int which) {
+  if (which == 0) return 2u * a.n_ins;
+  const uint32_t c = a.ctl->hadd_count;
+  return 2u * (c < a.hadd_cap ? c : a.hadd_cap);
+}
+
+__global__ void k_add_prepare(BatchArgs a, DevGraph X, int which) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= add_count(a, which)) return;
+  a.add_keep[which][e] = 0;
+  const AddEntry d = add_entry(a, which, e);
+  if (!d.valid) return;
+  const Row row = X.rows[d.r];
+  const int k = find_nbr(X.ent, row, d.c);
+  if (k >= 0) {
+    // a tombstone of the same edge: revive it in place (once)
+    const uint32_t old = atomicCAS(&X.ent[row.off + k].qw, 0u, d.qw);
+    if (old == 0u) {
+      X.ent[row.off + k].rinv = d.rinv;
+      X.w[row.off + k] = d.w;
+      atomicSub(&X.rows[d.r].dead, 1u);
+    }
+    return;
+  }
+  if (which == 1 &&
+      !hash_insert_first(a.hash, a.hash_mask,
+                         (static_cast<unsigned long long>(d.r) << 32) | d.c))
+    return;  // the same edge recovered by another deletion
+  const uint32_t slot = atomicAdd(&X.pending[d.r], 1u);
+  if (slot == 0u) {
+    const uint32_t t = atomicAdd(&a.ctl->touched[which], 1u);
+    a.touched_rows[which][t] = d.r;
+  }
+  a.add_keep[which][e] = 1;
+}
+
+__device__ __forceinline__ uint32_t grown_cap(uint32_t live) {
+  const uint32_t extra = live / 2 > 2u ? live / 2 : 2u;
+  return live + extra;
+}
+
+__global__ void k_rows_plan(BatchArgs a, DevGraph X, int which) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ctl->touched[which]) return;
+  const uint32_t r = a.touched_rows[which][t];
+  const uint32_t k = X.pending[r];
+  const Row row = X.rows[r];
+  uint32_t need = 0;
+  if (row.len + k > row.cap) {
+    need = grown_cap(row.len - row.dead + k);
+    atomicAdd(&a.ctl->need[which], static_cast<unsigned long long>(need));
+  }
+  a.touched_k[which][t] = k;
+  a.touched_need[which][t] = need;
+}
+
+__global__ void k_pool_check(BatchArgs a, uint64_t pool_cap, int which) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (batch_failed(a.ctl)) return;
+  if (a.ctl->pool_top[which] + a.ctl->need[which] > pool_cap) a.ctl->nomem[which] = 1;
+}
+
+__global__ void k_rows_relocate(BatchArgs a, DevGraph X, int which) {
+  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ctl->touched[which]) return;
+  const uint32_t need = a.touched_need[which][t];
+  if (need == 0) return;
+  const uint32_t r = a.touched_rows[which][t];
+  const Row row = X.rows[r];
+  const uint32_t off =
+      static_cast<uint32_t>(atomicAdd(&a.ctl->pool_top[which], static_cast<unsigned long long>(need)));
+  uint32_t o = 0;
+  for (uint32_t i = 0; i < row.len; ++i) {
+    const Ent e = X.ent[row.off + i];
+    if (e.qw == 0u) continue;  // drop tombstones while moving
+    X.ent[off + o] = e;
+    X.w[off + o] = X.w[row.off + i];
+    ++o;
+  }
+  X.rows[r] = Row{off, o, need, 0u};
+}
+
+__global__ void k_add_place(BatchArgs a, DevGraph X, int which) {
+  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= add_count(a, which)) return;
+  if (!a.add_keep[which][e]) return;
+  const AddEntry d = add_entry(a, which, e);
+  const Row row = X.rows[d.r];
+  const uint32_t slot = atomicSub(&X.pending[d.r], 1u) - 1u;  // leaves pending at 0
+  const uint32_t pos = row.off + row.len + slot;
+  X.ent[pos] = Ent{d.c, d.qw, d.rinv};
+  X.w[pos] = d.w;
+}
+
+// Merge the k appended entries (unsorted tail) into the sorted segment.
+__global__ void k_rows_merge(BatchArgs a, DevGraph X, int which) {
+  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ctl->touched[which]) return;
+  const uint32_t r = a.touched_rows[which][t];
+  const uint32_t k = a.touched_k[which][t];
+  const Row row = X.rows[r];
+  Ent* seg = X.ent + row.off;
+  double* wseg = X.w + row.off;
+  for (uint32_t j = row.len; j < row.len + k; ++j) {
+    const Ent e = seg[j];
+    const double we = wseg[j];
+    uint32_t i = j;
+    while (i > 0 && seg[i - 1].nbr > e.nbr) {
+      seg[i] = seg[i - 1];
+      wseg[i] = wseg[i - 1];
+      --i;
+    }
+    seg[i] = e;
+    wseg[i] = we;
+  }
+  X.rows[r].len = row.len + k;
+}
+
+// After a pool shortfall: undo the per-row counters so phase 4 can run again
+// once the pool has grown.
+__global__ void k_phase4_reset(BatchArgs a, DevGraph X, int which) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ctl->touched[which]) return;
+  X.pending[a.touched_rows[which][t]] = 0u;
+}
+
+__global__ void k_phase4_reset_ctl(BatchCtl* ctl, int which) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->touched[which] = 0;
+    ctl->need[which] = 0;
+    ctl->nomem[which] = 0;
+  }
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t per = kBlock) {
+  return static_cast<uint32_t>((n + per - 1) / per);
+}
+
+}  // namespace
+
+// ---- launchers ----------------------------------------------------------------------
+
+void launch_batch_begin(const BatchArgs& a, const DevGraph&, const DevGraph&,
+                        uint64_t hash_slots, hipStream_t st) {
+  k_batch_begin<<<1, 64, 0, st>>>(a.ctl);
+  const uint32_t nb = blocks_for(hash_slots) < 4096 ? blocks_for(hash_slots) : 4096;
+  k_clear_hash<<<nb ? nb : 1, kBlock, 0, st>>>(a.hash, hash_slots);
+}
+
+void launch_validate(const BatchArgs& a, const DevGraph& G, hipStream_t st) {
+  const uint32_t nu = a.n_ins + a.n_del;
+  if (nu == 0) return;
+  k_validate_a<<<blocks_for(nu), kBlock, 0, st>>>(a);
+  k_validate_b<<<blocks_for(nu), kBlock, 0, st>>>(a, G.rows, G.ent);
+}
+
+void launch_phase1(const BatchArgs& a, DevGraph& G, DevGraph& H, hipStream_t st) {
+  if (a.n_del == 0) return;
+  k_phase1<<<blocks_for(a.n_del), kBlock, 0, st>>>(a, G, H);
+}
+
+void launch_walks(const BatchArgs& a, const DevGraph& G, const DevGraph& H, hipStream_t st) {
+  const uint32_t nu = a.n_ins + a.n_del;
+  if (nu == 0) return;
+  const uint32_t per = kWalkBlock / kWave;
+  k_walks<<<(nu + per - 1) / per, kWalkBlock, 0, st>>>(a, G, H);
+}
+
+void launch_phase4(const BatchArgs& a, DevGraph& X, int which, uint64_t hash_slots,
+                   hipStream_t st) {
+  // upper bound of the directed entries and of the touched rows
+  const uint64_t cap = which == 0 ? 2ull * a.n_ins : 2ull * a.hadd_cap;
+  if (cap == 0) return;
+  if (which == 1) {
+    const uint32_t nb = blocks_for(hash_slots) < 4096 ? blocks_for(hash_slots) : 4096;
+    k_clear_hash<<<nb ? nb : 1, kBlock, 0, st>>>(a.hash, hash_slots);
+  }
+  const uint32_t nb = blocks_for(cap);
+  k_add_prepare<<<nb, kBlock, 0, st>>>(a, X, which);
+  k_rows_plan<<<nb, kBlock, 0, st>>>(a, X, which);
+  k_pool_check<<<1, 64, 0, st>>>(a, X.pool_cap, which);
+  k_rows_relocate<<<nb, kBlock, 0, st>>>(a, X, which);
+  k_add_place<<<nb, kBlock, 0, st>>>(a, X, which);
+  k_rows_merge<<<nb, kBlock, 0, st>>>(a, X, which);
+}
+
+void launch_phase4_reset(const BatchArgs& a, DevGraph& X, int which, hipStream_t st) {
+  const uint64_t cap = which == 0 ? 2ull * a.n_ins : 2ull * a.hadd_cap;
+  if (cap == 0) return;
+  k_phase4_reset<<<blocks_for(cap), kBlock, 0, st>>>(a, X, which);
+  k_phase4_reset_ctl<<<1, 64, 0, st>>>(a.ctl, which);
+}
+
+void launch_batch_end(const BatchArgs&, hipStream_t) {}
+
+}  // namespace dyg

@@ -1,0 +1,293 @@
+"""ctypes binding of libdygrass (include/dygrass.h).
+
+Argument marshalling only: every step of a batch runs in the HIP kernels of
+libdygrass.so.  The functions keep the C names; ``Dygrass`` is a small
+convenience wrapper around a context.  Importing this module fails loudly if
+the library has not been built (``python paper_2505_02741_amd/build.py``):
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdygrass.so")
+
+STATUS = {
+    0: "OK",
+    -1: "INVALID_ARG",
+    -2: "SELF_LOOP",
+    -3: "VERTEX_RANGE",
+    -4: "BAD_WEIGHT",
+    -5: "EDGE_EXISTS",
+    -6: "EDGE_MISSING",
+    -7: "DUPLICATE_IN_BATCH",
+    -8: "H_NOT_SUBSET",
+    -9: "NOMEM",
+    -10: "DEVICE",
+}
+
+FLAG_LEAN_POOLS = 1
+FLAG_TIMING = 2
+
+DEAD_END_TERMINATE = 0
+DEAD_END_BOUNCE = 1
+MAX_WALKERS = 1024
+MAX_STEPS = 1024
+
+UPDATE_RESULT_DTYPE = np.dtype([("kind", "u1"), ("flag", "u1"), ("any_hit", "u1"),
+                                ("reserved", "u1"), ("winner", "<u2"), ("n_rec", "<u2"),
+                                ("steps", "<u4"), ("reserved2", "<u4"), ("Rmin", "<f8")])
+WALKER_RECORD_DTYPE = np.dtype([("hit", "u1"), ("reserved", "u1"), ("steps", "<u2"),
+                                ("end", "<u4"), ("R", "<f8")])
+assert UPDATE_RESULT_DTYPE.itemsize == 24 and WALKER_RECORD_DTYPE.itemsize == 16
+
+
+class dyg_params(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("K", C.c_double), ("s_default", C.c_uint16),
+                ("L_default", C.c_uint16), ("Q", C.c_uint8), ("dead_end", C.c_uint8),
+                ("reserved0", C.c_uint16), ("w_ref", C.c_double), ("slack", C.c_double),
+                ("uid_base", C.c_uint64), ("flags", C.c_uint32), ("reserved1", C.c_uint32)]
+
+
+class dyg_stats_t(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("reserved", C.c_uint32), ("g_edges", C.c_uint64),
+                ("h_edges", C.c_uint64), ("g_pool_used", C.c_uint64),
+                ("g_pool_cap", C.c_uint64), ("h_pool_used", C.c_uint64),
+                ("h_pool_cap", C.c_uint64), ("g_dead", C.c_uint64), ("h_dead", C.c_uint64),
+                ("uid_base", C.c_uint64), ("batches", C.c_uint64),
+                ("compactions", C.c_uint64), ("w_ref", C.c_double),
+                ("walk_steps", C.c_uint64), ("walk_alg_bytes", C.c_uint64),
+                ("walk_launches", C.c_uint64), ("walk_ms_total", C.c_double),
+                ("walk_ms_last", C.c_double), ("batch_ms_last", C.c_double)]
+
+
+class dyg_batch_dev(C.Structure):
+    _fields_ = [("n_ins", C.c_uint64), ("n_del", C.c_uint64), ("iu", C.c_void_p),
+                ("iv", C.c_void_p), ("iw", C.c_void_p), ("du", C.c_void_p),
+                ("dv", C.c_void_p), ("s", C.c_void_p), ("L", C.c_void_p),
+                ("L_max", C.c_uint32), ("reserved", C.c_uint32), ("results", C.c_void_p)]
+
+
+EXPORTS = ["dyg_default_params", "dyg_init", "dyg_apply_batch", "dyg_apply_batch_dev",
+           "dyg_sync", "dyg_query_sparsifier", "dyg_query_graph", "dyg_stats", "dyg_compact",
+           "dyg_destroy", "dyg_error_string"]
+
+
+class DygError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = int(code)
+        self.name = STATUS.get(self.code, "?")
+        super().__init__(f"{where}: {self.name} ({self.code})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python paper_2505_02741_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.dyg_default_params.argtypes = [C.POINTER(dyg_params)]
+    lib.dyg_default_params.restype = None
+    lib.dyg_init.argtypes = [C.POINTER(C.c_void_p), C.c_uint32, P, P, P, C.c_uint64, P, P,
+                             C.POINTER(dyg_params)]
+    lib.dyg_init.restype = C.c_int
+    lib.dyg_apply_batch.argtypes = [P, C.c_uint64, P, P, P, C.c_uint64, P, P, P, P, P, P]
+    lib.dyg_apply_batch.restype = C.c_int
+    lib.dyg_apply_batch_dev.argtypes = [P, C.POINTER(dyg_batch_dev), P]
+    lib.dyg_apply_batch_dev.restype = C.c_int
+    lib.dyg_sync.argtypes = [P]
+    lib.dyg_sync.restype = C.c_int
+    for fn in (lib.dyg_query_sparsifier, lib.dyg_query_graph):
+        fn.argtypes = [P, C.c_uint64, C.POINTER(C.c_uint64), P, P, P]
+        fn.restype = C.c_int
+    lib.dyg_stats.argtypes = [P, C.POINTER(dyg_stats_t)]
+    lib.dyg_stats.restype = C.c_int
+    lib.dyg_compact.argtypes = [P]
+    lib.dyg_compact.restype = C.c_int
+    lib.dyg_destroy.argtypes = [P]
+    lib.dyg_destroy.restype = None
+    lib.dyg_error_string.argtypes = [C.c_int]
+    lib.dyg_error_string.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise DygError(rc, where)
+
+
+# --------------------------------------------------------------------------
+# C entry points
+
+
+def dyg_default_params(**overrides) -> dyg_params:
+    p = dyg_params()
+    _lib.dyg_default_params(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def dyg_error_string(code: int) -> str:
+    return _lib.dyg_error_string(int(code)).decode()
+
+
+def dyg_init(n, rowptr, col, w, h_u, h_v, params: dyg_params) -> C.c_void_p:
+    rowptr = _arr(rowptr, np.uint64)
+    col = _arr(col, np.uint32)
+    w = _arr(w, np.float64)
+    h_u = _arr(h_u, np.uint32)
+    h_v = _arr(h_v, np.uint32)
+    ctx = C.c_void_p()
+    _check(_lib.dyg_init(C.byref(ctx), int(n), _ptr(rowptr), _ptr(col), _ptr(w), h_u.size,
+                         _ptr(h_u), _ptr(h_v), C.byref(params)), "dyg_init")
+    return ctx
+
+
+def dyg_apply_batch(ctx, iu, iv, iw, du, dv, s=None, L=None, results=True, walkers=False,
+                    s_default=None):
+    iu = _arr(iu, np.uint32)
+    iv = _arr(iv, np.uint32)
+    iw = _arr(iw, np.float64)
+    du = _arr(du, np.uint32)
+    dv = _arr(dv, np.uint32)
+    nu = iu.size + du.size
+    s_arr = None if s is None else _arr(s, np.uint16)
+    L_arr = None if L is None else _arr(L, np.uint16)
+    res = np.zeros(nu, UPDATE_RESULT_DTYPE) if results else None
+    wk = None
+    if walkers:
+        if s_arr is not None:
+            tot = int(np.minimum(s_arr.astype(np.int64), MAX_WALKERS).sum())
+        else:
+            tot = nu * int(s_default)
+        wk = np.zeros(tot, WALKER_RECORD_DTYPE)
+    _check(_lib.dyg_apply_batch(ctx, iu.size, _ptr(iu), _ptr(iv), _ptr(iw), du.size, _ptr(du),
+                                _ptr(dv), _ptr(s_arr), _ptr(L_arr), _ptr(res), _ptr(wk)),
+           "dyg_apply_batch")
+    return res, wk
+
+
+def dyg_apply_batch_dev(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, results=None,
+                        stream=None):
+    """Device-resident batch: arguments are torch tensors on the GPU (or raw
+    device addresses as ints); stream is a torch stream or a raw handle."""
+
+    def addr(t):
+        if t is None:
+            return None
+        return t if isinstance(t, int) else t.data_ptr()
+
+    def count(t):
+        return 0 if t is None else int(t.numel())
+
+    b = dyg_batch_dev(n_ins=count(iu), n_del=count(du), iu=addr(iu), iv=addr(iv), iw=addr(iw),
+                      du=addr(du), dv=addr(dv), s=addr(s), L=addr(L), L_max=int(L_max),
+                      results=addr(results))
+    handle = None
+    if stream is not None:
+        handle = stream if isinstance(stream, int) else stream.cuda_stream
+    _check(_lib.dyg_apply_batch_dev(ctx, C.byref(b), handle), "dyg_apply_batch_dev")
+
+
+def dyg_sync(ctx):
+    _check(_lib.dyg_sync(ctx), "dyg_sync")
+
+
+def _query(fn, ctx):
+    m = C.c_uint64(0)
+    _check(fn(ctx, 0, C.byref(m), None, None, None), "query")
+    u = np.zeros(m.value, np.uint32)
+    v = np.zeros(m.value, np.uint32)
+    w = np.zeros(m.value, np.float64)
+    _check(fn(ctx, m.value, C.byref(m), _ptr(u), _ptr(v), _ptr(w)), "query")
+    return u, v, w
+
+
+def dyg_query_sparsifier(ctx):
+    return _query(_lib.dyg_query_sparsifier, ctx)
+
+
+def dyg_query_graph(ctx):
+    return _query(_lib.dyg_query_graph, ctx)
+
+
+def dyg_stats(ctx) -> dict:
+    st = dyg_stats_t()
+    _check(_lib.dyg_stats(ctx, C.byref(st)), "dyg_stats")
+    return {name: getattr(st, name) for name, _ in dyg_stats_t._fields_ if "reserved" not in name}
+
+
+def dyg_compact(ctx):
+    _check(_lib.dyg_compact(ctx), "dyg_compact")
+
+
+def dyg_destroy(ctx):
+    _lib.dyg_destroy(ctx)
+
+
+# --------------------------------------------------------------------------
+
+
+class Dygrass:
+    """One device-resident (G, H) pair."""
+
+    def __init__(self, n, rowptr, col, w, h_u, h_v, *, seed, K=math.inf, s=64, L=32, Q=24,
+                 w_ref=0.0, dead_end=DEAD_END_TERMINATE, slack=0.5, uid_base=0, flags=0):
+        self.params = dyg_default_params(seed=int(seed), K=float(K), s_default=int(s),
+                                         L_default=int(L), Q=int(Q), w_ref=float(w_ref),
+                                         dead_end=int(dead_end), slack=float(slack),
+                                         uid_base=int(uid_base), flags=int(flags))
+        self.n = int(n)
+        self.ctx = dyg_init(n, rowptr, col, w, h_u, h_v, self.params)
+
+    def apply_batch(self, iu, iv, iw, du, dv, s=None, L=None, walkers=False):
+        return dyg_apply_batch(self.ctx, iu, iv, iw, du, dv, s=s, L=L, walkers=walkers,
+                               s_default=self.params.s_default)
+
+    def apply_batch_dev(self, *args, **kw):
+        return dyg_apply_batch_dev(self.ctx, *args, **kw)
+
+    def sync(self):
+        dyg_sync(self.ctx)
+
+    def query(self, which="H"):
+        return dyg_query_sparsifier(self.ctx) if which == "H" else dyg_query_graph(self.ctx)
+
+    def stats(self):
+        return dyg_stats(self.ctx)
+
+    def compact(self):
+        dyg_compact(self.ctx)
+
+    def close(self):
+        if self.ctx is not None and self.ctx.value:
+            dyg_destroy(self.ctx)
+        self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -358,6 +358,8 @@ def local_insertions_lattice(es: EdgeSet, side: int, dim: int, count: int, rng,
     """count insertions (p, q): p uniform, h ~ U{hmin..hmax}, q = p + a
     lattice offset of L1 length h drawn uniformly, in bounds; an edge already
     in G or already drawn in this batch is redrawn."""
+    if count == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
     offs = {h: _lattice_offsets(dim, h) for h in range(hmin, hmax + 1)}
     n = es.n
     out_p, out_q = [], []
@@ -403,6 +405,8 @@ def local_insertions_walk(es: EdgeSet, rowptr, col, count: int, rng, taken,
     """For graphs without coordinates: p uniform over non-isolated vertices,
     q = end of an h-step uniform random walk on the initial graph,
     h ~ U{hmin..hmax}; self pairs, existing edges and repeats are redrawn."""
+    if count == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
     n = es.n
     deg = (rowptr[1:] - rowptr[:-1]).astype(np.int64)
     nz = np.flatnonzero(deg > 0)

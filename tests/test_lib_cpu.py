@@ -1,0 +1,62 @@
+"""CPU-side checks of the C ABI library: it is built, loads, and exports every
+function include/dygrass.h declares (no compute calls: no GPU here)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dygrass.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(dyg_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("dyg_init", "dyg_apply_batch", "dyg_query_sparsifier", "dyg_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2505_02741_amd import dygrass as D
+
+    lib = ctypes.CDLL(D.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(D.EXPORTS) == set(declared_functions())
+
+
+def test_binding_layouts_match_header():
+    from paper_2505_02741_amd import dygrass as D
+
+    assert ctypes.sizeof(D.dyg_params) == 56
+    assert D.UPDATE_RESULT_DTYPE.itemsize == 24
+    assert D.WALKER_RECORD_DTYPE.itemsize == 16
+    p = D.dyg_default_params()
+    assert p.Q == 24 and p.s_default == 64 and p.L_default == 32 and np.isinf(p.K)
+    assert D.dyg_error_string(-5) == "inserted edge already in the graph"
+
+
+def test_error_codes_agree_with_oracle():
+    import oracle
+    from paper_2505_02741_amd import dygrass as D
+
+    for code, name in oracle.ERRORS.items():
+        assert D.STATUS[code] == name
+
+
+def test_product_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2505_02741_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "dyg_oracle" not in text, f
