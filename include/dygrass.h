@@ -65,6 +65,11 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
                                   slots (instead of 50% + 4096) and grow on demand */
 #define DYG_FLAG_TIMING 2u     /* time the walk kernel and each batch with HIP
                                   events on the launch stream (dyg_stats)        */
+#define DYG_FLAG_BATCHED 4u    /* batched form: the walks of a batch run as one
+                                  persistent launch over a queue of (update,
+                                  walker) items; lanes take a new walker as soon
+                                  as theirs stops (same results as the plain
+                                  one-wavefront-per-update form)                 */
 
 #define DYG_MAX_WALKERS 1024 /* per update */
 #define DYG_MAX_STEPS 1024   /* per walker */
@@ -168,7 +173,7 @@ int dyg_apply_batch(dyg_ctx* ctx, uint64_t n_ins, const uint32_t* iu, const uint
 /*
  * Device-resident batch for callers that keep inputs in GPU memory (PyTorch
  * tensors, a serving loop).  All pointers are device pointers; s, L and
- * results may be NULL.  L_max bounds every L of the batch (<= 1024).
+ * results may be NULL.  An L or s above its stated bound fails validation.
  */
 typedef struct {
   uint64_t n_ins, n_del;
@@ -176,8 +181,8 @@ typedef struct {
   const double* iw;
   const uint32_t *du, *dv;
   const uint16_t *s, *L;
-  uint32_t L_max;
-  uint32_t reserved;
+  uint32_t L_max; /* >= every L of the batch (<= 1024); ignored when L is NULL */
+  uint32_t s_max; /* >= every s of the batch (<= 1024); ignored when s is NULL */
   dyg_update_result* results;
 } dyg_batch_dev;
 

@@ -78,6 +78,8 @@ struct HBuf {
   }
 };
 
+constexpr uint32_t kMaxWalkersHost = DYG_MAX_WALKERS;
+
 uint64_t next_pow2(uint64_t x) {
   uint64_t p = 1;
   while (p < x) p <<= 1;
@@ -131,6 +133,9 @@ struct dyg_ctx {
   // batch staging
   DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, wrec, wofs, hadd, hash;
   DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2];
+  DBuf qcount, qofs, qtile, item_upd, wres;  // batched form
+  uint32_t cus = 256;                         // compute units of the device
+  uint32_t walk_blocks_per_cu = 8;
   HBuf pin_in, pin_out;
 };
 
@@ -382,6 +387,13 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
     delete c;
     return fail_hip(e);
   }
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+      c->cus = static_cast<uint32_t>(cus);
+  }
   if (params->flags & DYG_FLAG_TIMING)
     for (hipEvent_t& ev : c->ev)
       if ((e = hipEventCreate(&ev)) != hipSuccess) {
@@ -454,7 +466,8 @@ namespace {
 
 // Size every staging buffer for a batch; returns DYG_OK or DYG_E_NOMEM.
 int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
-                    uint64_t walkers, uint64_t& hadd_cap, uint64_t& hash_slots) {
+                    uint64_t walkers, uint64_t items_cap, uint64_t& hadd_cap,
+                    uint64_t& hash_slots) {
   const uint64_t nu = n_ins + n_del;
   hadd_cap = n_ins + n_del * std::max<uint32_t>(Lcap, 2);
   const uint64_t keys = std::max<uint64_t>(nu, 2 * hadd_cap);
@@ -466,6 +479,12 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
             c->hash.ensure(sizeof(HashSlot) * hash_slots) &&
             (walkers == 0 || (c->wrec.ensure(sizeof(dyg_walker_record) * walkers) &&
                               c->wofs.ensure(8 * nu + 8)));
+  if (ok && (c->params.flags & DYG_FLAG_BATCHED)) {
+    const uint64_t tiles = (nu + 1023) / 1024 + 1;
+    ok = c->qcount.ensure(4 * nu + 8) && c->qofs.ensure(8 * nu + 8) &&
+         c->qtile.ensure(8 * tiles + 8) && c->item_upd.ensure(4 * items_cap + 8) &&
+         c->wres.ensure(sizeof(dyg_walker_record) * items_cap + 16);
+  }
   for (int g = 0; g < 2 && ok; ++g) {
     const uint64_t cap = g == 0 ? 2 * n_ins : 2 * hadd_cap;
     ok = c->touched_rows[g].ensure(4 * cap + 8) && c->touched_k[g].ensure(4 * cap + 8) &&
@@ -492,6 +511,7 @@ BatchArgs make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t* 
   a.s_def = c->params.s_default;
   a.L_def = c->params.L_default;
   a.Lcap = Lcap;
+  a.scap = kMaxWalkersHost;
   a.uid_base = c->uid_base;
   a.seed = c->params.seed;
   a.K = c->params.K;
@@ -516,6 +536,11 @@ BatchArgs make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t* 
     a.touched_need[g] = c->touched_need[g].as<uint32_t>();
     a.add_keep[g] = c->add_keep[g].as<uint8_t>();
   }
+  a.qcount = c->qcount.as<uint32_t>();
+  a.qofs = c->qofs.as<unsigned long long>();
+  a.qtile = c->qtile.as<unsigned long long>();
+  a.item_upd = c->item_upd.as<uint32_t>();
+  a.wres = c->wres.as<dyg::WalkerRec>();
   return a;
 }
 
@@ -526,7 +551,10 @@ void enqueue_pipeline(dyg_ctx* c, const BatchArgs& a, uint64_t hash_slots) {
   dyg::launch_validate(a, c->G, c->stream);
   dyg::launch_phase1(a, c->G, c->H, c->stream);
   if (timed) (void)hipEventRecord(c->ev[1], c->stream);
-  dyg::launch_walks(a, c->G, c->H, c->stream);
+  if (c->params.flags & DYG_FLAG_BATCHED)
+    dyg::launch_walks_queue(a, c->G, c->H, c->cus * c->walk_blocks_per_cu, c->stream);
+  else
+    dyg::launch_walks(a, c->G, c->H, c->stream);
   if (timed) (void)hipEventRecord(c->ev[2], c->stream);
   dyg::launch_phase4(a, c->G, 0, hash_slots, c->stream);
   dyg::launch_phase4(a, c->H, 1, hash_slots, c->stream);
@@ -613,8 +641,15 @@ extern "C" int dyg_apply_batch(dyg_ctx* c, uint64_t n_ins, const uint32_t* iu,
       wofs[i + 1] = wofs[i] + std::min<uint32_t>(s ? s[i] : c->params.s_default, DYG_MAX_WALKERS);
     walkers_total = wofs[nu];
   }
+  uint64_t items_cap = 0;
+  if (c->params.flags & DYG_FLAG_BATCHED) {
+    if (s)
+      for (uint64_t i = 0; i < nu; ++i) items_cap += std::min<uint32_t>(s[i], DYG_MAX_WALKERS);
+    else
+      items_cap = nu * c->params.s_default;
+  }
   uint64_t hadd_cap, hash_slots;
-  if (prepare_buffers(c, n_ins, n_del, Lcap, walkers_total, hadd_cap, hash_slots))
+  if (prepare_buffers(c, n_ins, n_del, Lcap, walkers_total, items_cap, hadd_cap, hash_slots))
     return DYG_E_NOMEM;
   if (!c->iu.ensure(4 * n_ins + 8) || !c->iv.ensure(4 * n_ins + 8) ||
       !c->iw.ensure(8 * n_ins + 8) || !c->du.ensure(4 * n_del + 8) ||
@@ -694,9 +729,12 @@ extern "C" int dyg_apply_batch_dev(dyg_ctx* c, const dyg_batch_dev* b, void* str
     int rc = dyg_sync(c);
     if (rc) return rc;
   }
+  if (b->s && b->s_max > DYG_MAX_WALKERS) return DYG_E_INVALID_ARG;
   const uint32_t Lcap = std::max<uint32_t>(b->L ? b->L_max : c->params.L_default, 2);
+  const uint32_t scap = b->s ? b->s_max : c->params.s_default;
   uint64_t hadd_cap, hash_slots;
-  if (prepare_buffers(c, n_ins, n_del, Lcap, 0, hadd_cap, hash_slots)) return DYG_E_NOMEM;
+  if (prepare_buffers(c, n_ins, n_del, Lcap, 0, nu * scap, hadd_cap, hash_slots))
+    return DYG_E_NOMEM;
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
   std::swap(st, c->stream);  // every launcher below runs on the caller's stream
   BatchArgs a = make_args(c, n_ins, n_del, b->iu, b->iv, b->iw, b->du, b->dv, b->s, b->L, Lcap,
@@ -704,6 +742,7 @@ extern "C" int dyg_apply_batch_dev(dyg_ctx* c, const dyg_batch_dev* b, void* str
                           b->results ? reinterpret_cast<dyg::UpdRes*>(b->results)
                                      : c->res.as<dyg::UpdRes>(),
                           false);
+  a.scap = scap;
   enqueue_pipeline(c, a, hash_slots);
   std::swap(st, c->stream);
   hipError_t e = hipGetLastError();
@@ -716,7 +755,7 @@ extern "C" int dyg_apply_batch_dev(dyg_ctx* c, const dyg_batch_dev* b, void* str
 
 extern "C" int dyg_sync(dyg_ctx* c) {
   if (!c) return DYG_E_INVALID_ARG;
-  if (!c->async_inflight) return c->pending_status;
+  if (!c->async_inflight) return DYG_OK;  // a batch's status is reported once
   c->async_inflight = false;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return c->pending_status = fail_hip(e);
@@ -855,6 +894,8 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
   DBuf* bufs[] = {&c->iu, &c->iv, &c->iw, &c->du, &c->dv, &c->s, &c->L, &c->ins_qw,
                   &c->ins_rinv, &c->in_h, &c->res, &c->wrec, &c->wofs, &c->hadd, &c->hash};
   for (DBuf* b : bufs) b->release();
+  DBuf* qbufs[] = {&c->qcount, &c->qofs, &c->qtile, &c->item_upd, &c->wres};
+  for (DBuf* b : qbufs) b->release();
   for (int g = 0; g < 2; ++g) {
     c->touched_rows[g].release();
     c->touched_k[g].release();

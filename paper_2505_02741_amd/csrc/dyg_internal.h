@@ -80,6 +80,8 @@ struct BatchCtl {
   uint32_t nomem[2];            // phase-4 pool shortfall, per graph
   uint32_t pad;
   unsigned long long pool_top[2];  // next free pool slot, per graph
+  unsigned long long walk_items;       // walkers queued this batch
+  unsigned long long queue_next;       // next queue item to hand out
   // cumulative over the context's life (never reset by a batch)
   unsigned long long steps_total;      // walker steps taken
   unsigned long long alg_bytes_total;  // algorithmic gathered bytes of those steps
@@ -102,6 +104,7 @@ struct BatchArgs {
   const uint16_t *s, *L;  // per update or null
   uint32_t s_def, L_def;
   uint32_t Lcap;           // >= every L of the batch, >= 2
+  uint32_t scap;           // >= every s of the batch
   uint64_t uid_base;
   uint64_t seed;
   double K;
@@ -126,6 +129,12 @@ struct BatchArgs {
   uint32_t* touched_k[2];
   uint32_t* touched_need[2];
   uint8_t* add_keep[2];       // per directed add entry: 1 = needs a new slot
+  // batched form: walker work queue
+  uint32_t* qcount;              // [n_ins + n_del] walkers of each update
+  unsigned long long* qofs;      // [n_ins + n_del] first item of each update
+  unsigned long long* qtile;     // [tiles] scan carry
+  uint32_t* item_upd;            // [items] update of each item
+  WalkerRec* wres;               // [items] outcome of each walker
 };
 
 // Host-side launchers (defined in dyg_kernels.hip), all asynchronous on
@@ -140,5 +149,9 @@ void launch_walks(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
 void launch_phase4(const BatchArgs& a, DevGraph& X, int which, uint64_t hash_slots,
                    hipStream_t stream);
 void launch_batch_end(const BatchArgs& a, hipStream_t stream);
+// Batched form of the walks: count, scan, expand, persistent queue walk
+// (walk_blocks workgroups of 256), per-update reduction.
+void launch_walks_queue(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
+                        uint32_t walk_blocks, hipStream_t stream);
 
 }  // namespace dyg

@@ -199,7 +199,8 @@ __global__ void k_validate_b(BatchArgs a, const Row* grows, const Ent* gent) {
   }
   const uint32_t s = a.s ? a.s[i] : a.s_def;
   const uint32_t L = a.L ? a.L[i] : a.L_def;
-  if (s > kMaxWalkers || L > kMaxSteps || L > a.Lcap) report(a.ctl, 2, i, E_INVALID_ARG);
+  if (s > kMaxWalkers || s > a.scap || L > kMaxSteps || L > a.Lcap)
+    report(a.ctl, 2, i, E_INVALID_ARG);
 }
 
 // ---- phase 1 -------------------------------------------------------------------
@@ -262,63 +263,88 @@ struct NoSink {
   __device__ __forceinline__ void operator()(uint32_t, uint32_t, const Ent&, uint32_t) const {}
 };
 
-// One walker: weight-biased choice among the neighbours other than the
-// previous vertex, stop on the distortion threshold, on reaching q, at a
-// dead end or after L steps (Sec. III-B).
+// State of one walker between steps.
+struct WState {
+  uint32_t x, prev, steps, block_of, bytes;
+  double R;
+  Philox4 rnd;
+  bool hit;
+};
+
+__device__ __forceinline__ void walker_start(WState& S, uint32_t p) {
+  S.x = p;
+  S.prev = kNone;
+  S.steps = 0;
+  S.block_of = kNone;
+  S.bytes = 0;
+  S.R = 0.0;
+  S.hit = false;
+}
+
+// One step of a walker: weight-biased choice among the neighbours other than
+// the previous vertex; stop on the distortion threshold, on reaching q, at a
+// dead end or after L steps (Sec. III-B).  Returns false once the walker has
+// stopped (then S holds its final state).
 template <class Sink>
-__device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, Sink sink) {
-  uint32_t x = P.p, prev = kNone, steps = 0, block_of = kNone, bytes = 0;
-  double R = 0.0;
-  bool hit = false;
-  Philox4 rnd{0, 0, 0, 0};
-  for (uint32_t t = 0; t < P.L; ++t) {
-    const Row r = P.rows[x];
-    const uint2* e2 = reinterpret_cast<const uint2*>(P.ent + r.off);  // (nbr, qw) pairs
-    unsigned long long tot = 0;
+__device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
+                                          Sink sink) {
+  const uint32_t t = S.steps;
+  if (t >= P.L) return false;
+  const Row r = P.rows[S.x];
+  const uint2* e2 = reinterpret_cast<const uint2*>(P.ent + r.off);  // (nbr, qw) pairs
+  unsigned long long tot = 0;
+  for (uint32_t i = 0; i < r.len; ++i) {
+    const uint2 e = e2[2 * i];
+    tot += (e.x != S.prev) ? e.y : 0u;
+  }
+  uint32_t pick;
+  if (tot == 0) {
+    if (!(P.bounce && S.prev != kNone)) return false;  // leaf: the walker stops
+    const int back = find_nbr(P.ent, r, S.prev);
+    if (back < 0) return false;  // cannot happen: the edge just used is live
+    pick = static_cast<uint32_t>(back);
+  } else {
+    if (S.block_of != (t >> 1)) {
+      S.rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
+      S.block_of = t >> 1;
+    }
+    const unsigned long long r64 =
+        (t & 1u) ? (uint64_t(S.rnd.x2) | (uint64_t(S.rnd.x3) << 32))
+                 : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
+    const unsigned long long target = __umul64hi(r64, tot);
+    unsigned long long run = 0;
+    pick = r.len - 1;
     for (uint32_t i = 0; i < r.len; ++i) {
       const uint2 e = e2[2 * i];
-      tot += (e.x != prev) ? e.y : 0u;
-    }
-    uint32_t pick;
-    if (tot == 0) {
-      if (!(P.bounce && prev != kNone)) break;  // leaf: the walker stops
-      const int back = find_nbr(P.ent, r, prev);
-      if (back < 0) break;  // cannot happen: the edge just used is live
-      pick = static_cast<uint32_t>(back);
-    } else {
-      if (block_of != (t >> 1)) {
-        rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
-        block_of = t >> 1;
+      run += (e.x != S.prev) ? e.y : 0u;
+      if (run > target) {
+        pick = i;
+        break;
       }
-      const unsigned long long r64 =
-          (t & 1u) ? (uint64_t(rnd.x2) | (uint64_t(rnd.x3) << 32))
-                   : (uint64_t(rnd.x0) | (uint64_t(rnd.x1) << 32));
-      const unsigned long long target = __umul64hi(r64, tot);
-      unsigned long long run = 0;
-      pick = r.len - 1;
-      for (uint32_t i = 0; i < r.len; ++i) {
-        const uint2 e = e2[2 * i];
-        run += (e.x != prev) ? e.y : 0u;
-        if (run > target) {
-          pick = i;
-          break;
-        }
-      }
-    }
-    const Ent ce = P.ent[r.off + pick];
-    bytes += step_bytes(r.len - r.dead);
-    R = R + ce.rinv;
-    sink(x, ce.nbr, ce, r.off + pick);
-    prev = x;
-    x = ce.nbr;
-    ++steps;
-    if (P.use_K && P.w_pq * R > P.K) break;
-    if (x == P.q) {
-      hit = true;
-      break;
     }
   }
-  return Walk{steps, x, R, hit, bytes};
+  const Ent ce = P.ent[r.off + pick];
+  S.bytes += step_bytes(r.len - r.dead);
+  S.R = S.R + ce.rinv;
+  sink(S.x, ce.nbr, ce, r.off + pick);
+  S.prev = S.x;
+  S.x = ce.nbr;
+  S.steps = t + 1;
+  if (P.use_K && P.w_pq * S.R > P.K) return false;
+  if (S.x == P.q) {
+    S.hit = true;
+    return false;
+  }
+  return true;
+}
+
+template <class Sink>
+__device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, Sink sink) {
+  WState S;
+  walker_start(S, P.p);
+  while (walk_step(P, walker, S, sink)) {
+  }
+  return Walk{S.steps, S.x, S.R, S.hit, S.bytes};
 }
 
 // Wavefront argmin of (R, walker): smaller R wins, ties go to the lower walker.
@@ -335,6 +361,12 @@ __device__ __forceinline__ void wave_argmin(double& R, uint32_t& w) {
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
@@ -359,32 +391,40 @@ struct RecoverSink {
   }
 };
 
-__global__ __launch_bounds__(kWalkBlock) void k_walks(BatchArgs a, DevGraph G, DevGraph H) {
-  if (batch_failed(a.ctl)) return;
-  const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + threadIdx.x / kWave;
-  if (upd >= a.n_ins + a.n_del) return;  // uniform across the wavefront
-  const bool is_ins = upd < a.n_ins;
-  const uint32_t j = upd - a.n_ins;
-  const uint32_t s = a.s ? a.s[upd] : a.s_def;
-  const uint32_t L = a.L ? a.L[upd] : a.L_def;
-  const uint64_t uid = a.uid_base + upd;
-
+// Update `upd` of the batch: its endpoints, walk graph and limits.
+struct UpdateView {
   WalkParams P;
-  P.p = is_ins ? a.iu[upd] : a.du[j];
-  P.q = is_ins ? a.iv[upd] : a.dv[j];
-  P.use_K = is_ins && a.has_K;
-  P.w_pq = is_ins ? a.iw[upd] : 0.0;
+  uint32_t s;
+  bool is_ins;
+  bool walks;  // insertions always; deletions only of H edges
+};
+
+__device__ __forceinline__ UpdateView view_update(const BatchArgs& a, const DevGraph& G,
+                                                  const DevGraph& H, uint32_t upd) {
+  UpdateView v;
+  v.is_ins = upd < a.n_ins;
+  const uint32_t j = upd - a.n_ins;
+  v.s = a.s ? a.s[upd] : a.s_def;
+  const uint64_t uid = a.uid_base + upd;
+  WalkParams& P = v.P;
+  P.p = v.is_ins ? a.iu[upd] : a.du[j];
+  P.q = v.is_ins ? a.iv[upd] : a.dv[j];
+  P.use_K = v.is_ins && a.has_K;
+  P.w_pq = v.is_ins ? a.iw[upd] : 0.0;
   P.K = a.K;
-  P.L = L;
+  P.L = a.L ? a.L[upd] : a.L_def;
   P.key0 = static_cast<uint32_t>(a.seed);
   P.key1 = static_cast<uint32_t>(a.seed >> 32);
   P.uid_lo = static_cast<uint32_t>(uid);
   P.uid_hi = static_cast<uint32_t>(uid >> 32);
   P.bounce = a.bounce != 0;
-  P.rows = is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
-  P.ent = is_ins ? H.ent : G.ent;
+  P.rows = v.is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
+  P.ent = v.is_ins ? H.ent : G.ent;
+  v.walks = v.is_ins || a.in_h[j];
+  return v;
+}
 
+__device__ __forceinline__ UpdRes empty_result(bool is_ins) {
   UpdRes res;
   res.kind = is_ins ? 0 : 1;
   res.flag = 0;
@@ -395,53 +435,26 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(BatchArgs a, DevGraph G, D
   res.steps = 0;
   res.reserved2 = 0;
   res.Rmin = INFINITY;
+  return res;
+}
 
-  const bool walks = is_ins || a.in_h[j];
-  if (!walks) {
-    if (a.wrec)
-      for (uint32_t k = lane; k < s; k += kWave)
-        a.wrec[a.wofs[upd] + k] = WalkerRec{0, 0, 0, P.p, 0.0};
-    if (lane == 0) a.res[upd] = res;
-    return;
-  }
-
-  bool any_hit = false;
-  double bestR = INFINITY;
-  uint32_t bestW = kNone;
-  uint32_t steps = 0;
-  unsigned long long bytes = 0;
-  for (uint32_t base = 0; base < s; base += kWave) {
-    const uint32_t walker = base + lane;
-    const bool active = walker < s;
-    Walk o{0, P.p, 0.0, false, 0};
-    if (active) o = walk_one(P, walker, NoSink{});
-    if (active && a.wrec)
-      a.wrec[a.wofs[upd] + walker] =
-          WalkerRec{static_cast<uint8_t>(o.hit), 0, static_cast<uint16_t>(o.steps), o.end, o.R};
-    const bool h = active && o.hit;
-    any_hit = any_hit || (__ballot(h) != 0ull);
-    double cR = h ? o.R : INFINITY;
-    uint32_t cW = h ? walker : kNone;
-    wave_argmin(cR, cW);
-    if (cR < bestR) {  // a later chunk only wins with a strictly smaller R
-      bestR = cR;
-      bestW = cW;
-    }
-    steps += wave_sum(active ? o.steps : 0u);
-    bytes += wave_sum(active ? o.bytes : 0u);
-  }
+// Decision of one update once its walkers are reduced (run by one lane):
+// an insertion is kept iff no walker reached q (Sec. III-B); a deletion of an
+// H edge recovers the winner's path edges missing from H, or the fallback
+// edges when nobody hit (Sec. III-C).
+__device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
+                              uint32_t upd, const UpdateView& v, bool any_hit, double bestR,
+                              uint32_t bestW, uint32_t steps) {
+  UpdRes res = empty_result(v.is_ins);
   res.any_hit = any_hit ? 1 : 0;
   res.steps = steps;
   if (any_hit) {
     res.Rmin = bestR;
     res.winner = static_cast<uint16_t>(bestW);
   }
-  if (lane != 0) return;
-  atomicAdd(&a.ctl->steps_total, static_cast<unsigned long long>(steps));
-  atomicAdd(&a.ctl->alg_bytes_total, bytes);
-
-  if (is_ins) {
-    res.flag = any_hit ? 0 : 1;  // keep the new edge iff no walker reached q
+  const WalkParams& P = v.P;
+  if (v.is_ins) {
+    res.flag = any_hit ? 0 : 1;
     if (!any_hit) {
       const uint32_t slot = atomicAdd(&a.ctl->hadd_count, 1u);
       if (slot < a.hadd_cap)
@@ -450,17 +463,15 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(BatchArgs a, DevGraph G, D
     a.res[upd] = res;
     return;
   }
-
-  // deletion of a sparsifier edge: recover the least-resistance hitting path
   res.flag = 1;
-  const uint32_t cap = L > 2 ? L : 2;
+  const uint32_t cap = P.L > 2 ? P.L : 2;
   const uint32_t base = atomicAdd(&a.ctl->hadd_count, cap);
   uint32_t count = 0;
   if (base + cap <= a.hadd_cap) {
     AddRec* out = a.hadd + base;
     if (any_hit) {
       RecoverSink sink{H.rows, H.ent, G.w, out, cap, &count};
-      walk_one(P, bestW, sink);
+      walk_one(P, bestW, sink);  // replay: same counters, same snapshot
     } else {
       // no hit: per endpoint the least-resistance G edge not in H
       const uint32_t ends[2] = {P.p, P.q};
@@ -487,6 +498,246 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(BatchArgs a, DevGraph G, D
   }
   res.n_rec = static_cast<uint16_t>(count);
   a.res[upd] = res;
+}
+
+// Plain form: one wavefront per update, one lane per walker (more walkers
+// than lanes run in successive rounds of 64).
+__global__ __launch_bounds__(kWalkBlock) void k_walks(BatchArgs a, DevGraph G, DevGraph H) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + threadIdx.x / kWave;
+  if (upd >= a.n_ins + a.n_del) return;  // uniform across the wavefront
+  const UpdateView v = view_update(a, G, H, upd);
+  if (!v.walks) {
+    if (a.wrec)
+      for (uint32_t k = lane; k < v.s; k += kWave)
+        a.wrec[a.wofs[upd] + k] = WalkerRec{0, 0, 0, v.P.p, 0.0};
+    if (lane == 0) a.res[upd] = empty_result(v.is_ins);
+    return;
+  }
+  bool any_hit = false;
+  double bestR = INFINITY;
+  uint32_t bestW = kNone;
+  uint32_t steps = 0;
+  unsigned long long bytes = 0;
+  for (uint32_t base = 0; base < v.s; base += kWave) {
+    const uint32_t walker = base + lane;
+    const bool active = walker < v.s;
+    Walk o{0, v.P.p, 0.0, false, 0};
+    if (active) o = walk_one(v.P, walker, NoSink{});
+    if (active && a.wrec)
+      a.wrec[a.wofs[upd] + walker] =
+          WalkerRec{static_cast<uint8_t>(o.hit), 0, static_cast<uint16_t>(o.steps), o.end, o.R};
+    const bool h = active && o.hit;
+    any_hit = any_hit || (__ballot(h) != 0ull);
+    double cR = h ? o.R : INFINITY;
+    uint32_t cW = h ? walker : kNone;
+    wave_argmin(cR, cW);
+    if (cR < bestR) {  // a later round only wins with a strictly smaller R
+      bestR = cR;
+      bestW = cW;
+    }
+    steps += wave_sum(active ? o.steps : 0u);
+    bytes += wave_sum(active ? o.bytes : 0u);
+  }
+  if (lane != 0) return;
+  atomicAdd(&a.ctl->steps_total, static_cast<unsigned long long>(steps));
+  atomicAdd(&a.ctl->alg_bytes_total, bytes);
+  decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps);
+}
+
+// ---- batched form: walker work queue ----------------------------------------
+
+// Walkers per update once phase 1 is known.
+__global__ void k_count_walkers(BatchArgs a, DevGraph G, DevGraph H) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t upd = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nu = a.n_ins + a.n_del;
+  if (upd >= nu) return;
+  const bool walks = upd < a.n_ins || a.in_h[upd - a.n_ins];
+  a.qcount[upd] = walks ? (a.s ? a.s[upd] : a.s_def) : 0u;
+}
+
+// Exclusive scan of qcount into qofs (u64), in three launches.
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const unsigned long long o = __shfl_up(v, off, kWave);
+    if (lane >= static_cast<uint32_t>(off)) v += o;
+  }
+  return v;
+}
+
+// Block-wide exclusive scan of one value per thread; returns the block total.
+__device__ unsigned long long block_excl_scan(unsigned long long v, unsigned long long& excl) {
+  __shared__ unsigned long long wsum[kBlock / kWave];
+  const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const unsigned long long inc = wave_incl_scan(v);
+  if (lane == kWave - 1) wsum[wv] = inc;
+  __syncthreads();
+  unsigned long long before = 0, total = 0;
+  for (uint32_t k = 0; k < kBlock / kWave; ++k) {
+    if (k < wv) before += wsum[k];
+    total += wsum[k];
+  }
+  __syncthreads();
+  excl = before + inc - v;
+  return total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(BatchArgs a) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t nu = a.n_ins + a.n_del;
+  const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
+  unsigned long long v[kScanItems], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < nu) ? a.qcount[base + k] : 0u;
+    sum += v[k];
+  }
+  unsigned long long excl;
+  const unsigned long long total = block_excl_scan(sum, excl);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < nu) a.qofs[base + k] = excl;
+    excl += v[k];
+  }
+  if (threadIdx.x == 0) a.qtile[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_top(BatchArgs a, uint32_t tiles) {
+  if (batch_failed(a.ctl)) return;
+  unsigned long long carry = 0;
+  for (uint32_t base = 0; base < tiles; base += kBlock) {
+    const uint32_t i = base + threadIdx.x;
+    const unsigned long long v = i < tiles ? a.qtile[i] : 0ull;
+    unsigned long long excl;
+    const unsigned long long total = block_excl_scan(v, excl);
+    if (i < tiles) a.qtile[i] = carry + excl;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    a.ctl->walk_items = carry;
+    a.ctl->queue_next = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(BatchArgs a) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t nu = a.n_ins + a.n_del;
+  const uint64_t base = uint64_t(blockIdx.x) * kScanTile;
+  const unsigned long long add = a.qtile[blockIdx.x];
+  for (uint32_t k = threadIdx.x; k < kScanTile; k += kBlock)
+    if (base + k < nu) a.qofs[base + k] += add;
+}
+
+// Item -> update map: one wavefront per update writes its walkers' entries.
+__global__ __launch_bounds__(kBlock) void k_expand_items(BatchArgs a) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t upd = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (upd >= a.n_ins + a.n_del) return;
+  const uint32_t cnt = a.qcount[upd];
+  const unsigned long long base = a.qofs[upd];
+  for (uint32_t k = lane; k < cnt; k += kWave) a.item_upd[base + k] = upd;
+}
+
+// Persistent walk kernel over the queue of (update, walker) items.  Every lane
+// runs one walker at a time; a lane whose walker stops takes the next item
+// (one atomic per wavefront and refill), so lanes never idle while work is
+// left.  Each walker's outcome goes to wres[item].
+__global__ __launch_bounds__(kBlock) void k_walk_queue(BatchArgs a, DevGraph G, DevGraph H) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const unsigned long long total = a.ctl->walk_items;
+  const unsigned long long lanes_below = (1ull << lane) - 1ull;
+  bool active = false, drained = false;
+  unsigned long long item = 0;
+  uint32_t walker = 0;
+  WalkParams P;
+  WState S;
+  unsigned long long steps = 0, bytes = 0;
+  while (true) {
+    if (!drained) {
+      const unsigned long long idle = __ballot(!active);
+      if (idle) {
+        const uint32_t leader = static_cast<uint32_t>(__builtin_ctzll(idle));
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(&a.ctl->queue_next, __popcll(idle));
+        base = __shfl(base, leader, kWave);
+        if (base + __popcll(idle) >= total) drained = true;
+        if (!active) {
+          item = base + __popcll(idle & lanes_below);
+          if (item < total) {
+            const uint32_t upd = a.item_upd[item];
+            const UpdateView v = view_update(a, G, H, upd);
+            P = v.P;
+            walker = static_cast<uint32_t>(item - a.qofs[upd]);
+            walker_start(S, P.p);
+            active = true;
+          }
+        }
+      }
+    }
+    if (!__ballot(active)) break;
+    if (active && !walk_step(P, walker, S, NoSink{})) {
+      a.wres[item] = WalkerRec{static_cast<uint8_t>(S.hit), 0,
+                               static_cast<uint16_t>(S.steps), S.x, S.R};
+      steps += S.steps;
+      bytes += S.bytes;
+      active = false;
+    }
+  }
+  const unsigned long long ws = wave_sum64(steps);
+  const unsigned long long wb = wave_sum64(bytes);
+  if (lane == 0) {
+    atomicAdd(&a.ctl->steps_total, ws);
+    atomicAdd(&a.ctl->alg_bytes_total, wb);
+  }
+}
+
+// Reduce each update's walker records and decide it (one wavefront per update).
+__global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(BatchArgs a, DevGraph G,
+                                                               DevGraph H) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + threadIdx.x / kWave;
+  if (upd >= a.n_ins + a.n_del) return;
+  const UpdateView v = view_update(a, G, H, upd);
+  if (!v.walks) {
+    if (a.wrec)
+      for (uint32_t k = lane; k < v.s; k += kWave)
+        a.wrec[a.wofs[upd] + k] = WalkerRec{0, 0, 0, v.P.p, 0.0};
+    if (lane == 0) a.res[upd] = empty_result(v.is_ins);
+    return;
+  }
+  const unsigned long long first = a.qofs[upd];
+  bool any_hit = false;
+  double bestR = INFINITY;
+  uint32_t bestW = kNone;
+  uint32_t steps = 0;
+  for (uint32_t base = 0; base < v.s; base += kWave) {
+    const uint32_t walker = base + lane;
+    const bool active = walker < v.s;
+    WalkerRec o{0, 0, 0, v.P.p, 0.0};
+    if (active) o = a.wres[first + walker];
+    if (active && a.wrec) a.wrec[a.wofs[upd] + walker] = o;
+    const bool h = active && o.hit;
+    any_hit = any_hit || (__ballot(h) != 0ull);
+    double cR = h ? o.R : INFINITY;
+    uint32_t cW = h ? walker : kNone;
+    wave_argmin(cR, cW);
+    if (cR < bestR) {
+      bestR = cR;
+      bestW = cW;
+    }
+    steps += wave_sum(active ? static_cast<uint32_t>(o.steps) : 0u);
+  }
+  if (lane == 0) decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps);
 }
 
 // ---- phase 4 ------------------------------------------------------------------------
@@ -681,6 +932,21 @@ void launch_walks(const BatchArgs& a, const DevGraph& G, const DevGraph& H, hipS
   if (nu == 0) return;
   const uint32_t per = kWalkBlock / kWave;
   k_walks<<<(nu + per - 1) / per, kWalkBlock, 0, st>>>(a, G, H);
+}
+
+void launch_walks_queue(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
+                        uint32_t walk_blocks, hipStream_t st) {
+  const uint32_t nu = a.n_ins + a.n_del;
+  if (nu == 0) return;
+  const uint32_t tiles = (nu + kScanTile - 1) / kScanTile;
+  const uint32_t per = kWalkBlock / kWave;
+  k_count_walkers<<<blocks_for(nu), kBlock, 0, st>>>(a, G, H);
+  k_scan_tiles<<<tiles, kBlock, 0, st>>>(a);
+  k_scan_top<<<1, kBlock, 0, st>>>(a, tiles);
+  k_scan_add<<<tiles, kBlock, 0, st>>>(a);
+  k_expand_items<<<(nu + per - 1) / per, kBlock, 0, st>>>(a);
+  k_walk_queue<<<walk_blocks, kBlock, 0, st>>>(a, G, H);
+  k_reduce_updates<<<(nu + per - 1) / per, kWalkBlock, 0, st>>>(a, G, H);
 }
 
 void launch_phase4(const BatchArgs& a, DevGraph& X, int which, uint64_t hash_slots,

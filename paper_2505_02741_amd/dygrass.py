@@ -33,6 +33,7 @@ STATUS = {
 
 FLAG_LEAN_POOLS = 1
 FLAG_TIMING = 2
+FLAG_BATCHED = 4
 
 DEAD_END_TERMINATE = 0
 DEAD_END_BOUNCE = 1
@@ -70,7 +71,7 @@ class dyg_batch_dev(C.Structure):
     _fields_ = [("n_ins", C.c_uint64), ("n_del", C.c_uint64), ("iu", C.c_void_p),
                 ("iv", C.c_void_p), ("iw", C.c_void_p), ("du", C.c_void_p),
                 ("dv", C.c_void_p), ("s", C.c_void_p), ("L", C.c_void_p),
-                ("L_max", C.c_uint32), ("reserved", C.c_uint32), ("results", C.c_void_p)]
+                ("L_max", C.c_uint32), ("s_max", C.c_uint32), ("results", C.c_void_p)]
 
 
 EXPORTS = ["dyg_default_params", "dyg_init", "dyg_apply_batch", "dyg_apply_batch_dev",
@@ -183,8 +184,8 @@ def dyg_apply_batch(ctx, iu, iv, iw, du, dv, s=None, L=None, results=True, walke
     return res, wk
 
 
-def dyg_apply_batch_dev(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, results=None,
-                        stream=None):
+def dyg_apply_batch_dev(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, s_max=0,
+                        results=None, stream=None):
     """Device-resident batch: arguments are torch tensors on the GPU (or raw
     device addresses as ints); stream is a torch stream or a raw handle."""
 
@@ -198,7 +199,7 @@ def dyg_apply_batch_dev(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, result
 
     b = dyg_batch_dev(n_ins=count(iu), n_del=count(du), iu=addr(iu), iv=addr(iv), iw=addr(iw),
                       du=addr(du), dv=addr(dv), s=addr(s), L=addr(L), L_max=int(L_max),
-                      results=addr(results))
+                      s_max=int(s_max), results=addr(results))
     handle = None
     if stream is not None:
         handle = stream if isinstance(stream, int) else stream.cuda_stream
