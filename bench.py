@@ -32,8 +32,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "updates/s + walker-steps/s (frac of HBM gather roofline); p50/p99 batch latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL = "k_walks"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic_grid1024.json")
+KERNELS = {"plain": "k_walks", "batched": "k_walk_queue"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
 
 
 def kernel_source_hash() -> str:
@@ -44,14 +44,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, form: str):
     """HBM bytes per walk launch from committed rocprofv3 counter runs, if they
     were taken on the current kernel source; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
-        d = json.load(f)
-    if d.get("kernel_source") != kernel_source_hash() or d.get("workload") != workload:
+        d = json.load(f).get(f"{workload}/{form}")
+    if not d or d.get("kernel_source") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
 
@@ -108,6 +108,12 @@ def main():
     ap.add_argument("--workload", default="grid1024")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the workload, copy this many MiB device to device once "
+                         "(a known-size kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--form", choices=["both", "plain", "batched"], default="both",
+                    help="plain: one wavefront per update; batched: persistent work-queue "
+                         "walks; both: time both, report the batched one")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -126,6 +132,16 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {nbytes} bytes read, {nbytes} bytes written",
+              file=sys.stderr, flush=True)
+        del src, dst
     n_batches = args.warmup + args.steps
     t0 = time.perf_counter()
     wl = W.make_workload(args.workload, seed=args.seed, n_batches=n_batches)
@@ -133,8 +149,6 @@ def main():
     print(f"# workload {args.workload}: n={wl.G.n} m={wl.G.m} H0={int(wl.h_mask.sum())} "
           f"batches={n_batches} gen={t_gen:.1f}s", file=sys.stderr, flush=True)
     rp, col, w = W.to_csr(wl.G.n, wl.G.u, wl.G.v, wl.G.w)
-    ctx = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
-                    L=wl.L, flags=D.FLAG_TIMING)
 
     def to_dev(a, dt):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
@@ -147,39 +161,60 @@ def main():
                   s=None if b.s is None else to_dev(b.s.astype(np.int16), np.int16),
                   L=None if b.L is None else to_dev(b.L.astype(np.int16), np.int16),
                   L_max=int(b.L.max()) if b.L is not None and b.size else 0,
+                  s_max=int(b.s.max()) if b.s is not None and b.size else 0,
                   results=torch.empty(b.size * 24, dtype=torch.uint8, device=dev))
         dev_batches.append(db)
     torch.cuda.synchronize()
 
-    def step(i):
-        db = dev_batches[i]
-        D.dyg_apply_batch_dev(ctx.ctx, db["iu"], db["iv"], db["iw"], db["du"], db["dv"],
-                              s=db["s"], L=db["L"], L_max=db["L_max"], results=db["results"])
-        D.dyg_sync(ctx.ctx)
+    def run_form(flags):
+        ctx = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
+                        L=wl.L, flags=D.FLAG_TIMING | flags)
 
-    for i in range(args.warmup):
-        step(i)
-    st0 = ctx.stats()
-    torch.cuda.synchronize()
-    lat = []
-    t_start = time.perf_counter()
-    for i in range(args.warmup, n_batches):
-        ts = time.perf_counter()
-        step(i)
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    st1 = ctx.stats()
+        def step(i):
+            db = dev_batches[i]
+            D.dyg_apply_batch_dev(ctx.ctx, db["iu"], db["iv"], db["iw"], db["du"], db["dv"],
+                                  s=db["s"], L=db["L"], L_max=db["L_max"], s_max=db["s_max"],
+                                  results=db["results"])
+            D.dyg_sync(ctx.ctx)
 
+        for i in range(args.warmup):
+            step(i)
+        st0 = ctx.stats()
+        torch.cuda.synchronize()
+        lat = []
+        t_start = time.perf_counter()
+        for i in range(args.warmup, n_batches):
+            ts = time.perf_counter()
+            step(i)
+            lat.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
+        st1 = ctx.stats()
+        ctx.close()
+        r = dict(t_total=t_total, lat=lat)
+        for k in ("walk_steps", "walk_alg_bytes", "walk_ms_total", "walk_launches"):
+            r[k] = st1[k] - st0[k]
+        return r
+
+    forms = {"plain": 0, "batched": D.FLAG_BATCHED}
+    chosen = list(forms) if args.form == "both" else [args.form]
+    runs = {}
+    for name in chosen:
+        runs[name] = run_form(forms[name])
+        print(f"# {name}: {runs[name]['t_total'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
+              flush=True)
+    head = "batched" if "batched" in runs else chosen[0]
+    R = runs[head]
     updates = sum(b.size for b in wl.batches[args.warmup:])
-    steps_walk = st1["walk_steps"] - st0["walk_steps"]
-    alg_bytes = st1["walk_alg_bytes"] - st0["walk_alg_bytes"]
-    walk_ms = st1["walk_ms_total"] - st0["walk_ms_total"]
-    launches = st1["walk_launches"] - st0["walk_launches"]
+    t_total, lat = R["t_total"], R["lat"]
+    steps_walk = R["walk_steps"]
+    alg_bytes = R["walk_alg_bytes"]
+    walk_ms = R["walk_ms_total"]
+    launches = R["walk_launches"]
     avg_walk_s = walk_ms / 1e3 / max(launches, 1)
     bytes_per_launch = alg_bytes / max(launches, 1)
     achieved = bytes_per_launch / avg_walk_s / 1e9 if avg_walk_s > 0 else 0.0
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(args.workload, head)
     cfg = wl.meta["cfg"]
     out = {
         "metric": METRIC,
@@ -198,8 +233,8 @@ def main():
             "workload": f"{args.workload}: {cfg['kind']} side {cfg.get('side')} "
                         f"(n={wl.G.n}, m={wl.G.m}), weights {cfg['weights']}, "
                         f"batches of {cfg.get('ins')} insertions + {cfg.get('dels')} deletions, "
-                        f"s={wl.s}, L={wl.L}, K=inf, plain form (one launch sequence and "
-                        f"one host sync per batch)",
+                        f"s={wl.s}, L={wl.L}, K=inf, {head} form, one launch sequence and "
+                        f"one host sync per batch",
             "global_batch": int(updates / args.steps),
             "parallelism": "single GPU",
         },
@@ -208,9 +243,16 @@ def main():
         "p50_batch_ms": percentile(lat, 0.5) * 1e3,
         "p99_batch_ms": percentile(lat, 0.99) * 1e3,
         "walk_kernel_ms_avg": avg_walk_s * 1e3,
+        "form": head,
+        "forms": {k: {"updates_per_s": updates / v["t_total"],
+                      "ms_per_step": v["t_total"] / args.steps * 1e3,
+                      "walk_kernel_ms_avg": v["walk_ms_total"] / max(v["walk_launches"], 1),
+                      "p50_batch_ms": percentile(v["lat"], 0.5) * 1e3,
+                      "p99_batch_ms": percentile(v["lat"], 0.99) * 1e3}
+                  for k, v in runs.items()},
         "roofline": {
             "bound": "hbm",
-            "kernel": KERNEL,
+            "kernel": KERNELS[head],
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -221,7 +263,6 @@ def main():
         },
         "cpu_baseline": None,
     }
-    ctx.close()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, wl.batches)
     print(json.dumps(out), flush=True)

@@ -207,9 +207,30 @@ int dyg_query_graph(dyg_ctx* ctx, uint64_t cap, uint64_t* m, uint32_t* u, uint32
 
 int dyg_stats(dyg_ctx* ctx, dyg_stats_t* out);
 
+/* Launch schedule of the batched form (results never depend on it). */
+typedef struct {
+  uint32_t walk_blocks_per_cu; /* persistent walk grid = CUs x this (1..64)       */
+  uint32_t refill_min;         /* idle lanes of a wavefront that trigger a refill
+                                  from its item pool (1..64)                       */
+  uint32_t reserved[6];
+} dyg_tuning;
+
+int dyg_get_tuning(dyg_ctx* ctx, dyg_tuning* out);
+int dyg_set_tuning(dyg_ctx* ctx, const dyg_tuning* t); /* INVALID_ARG if out of range */
+
 /* Rewrite both pools without tombstones, with fresh slack (also done
  * automatically when a pool runs short). */
 int dyg_compact(dyg_ctx* ctx);
+
+/*
+ * Consistency check of the device state (for tests and failure detection):
+ * every segment sorted with unique neighbour ids inside its slots and the
+ * pool, segments disjoint, the tombstone count of each row exact, the weight
+ * prefix of every segment longer than 64 exact, G and H symmetric, H a
+ * subgraph of G with equal weights.  Returns DYG_OK, or DYG_E_DEVICE with a
+ * description of the first violation in msg (NUL-terminated, msg_len bytes).
+ */
+int dyg_check_state(dyg_ctx* ctx, char* msg, uint64_t msg_len);
 
 void dyg_destroy(dyg_ctx* ctx);
 const char* dyg_error_string(int code);

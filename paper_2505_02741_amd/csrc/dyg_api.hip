@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -104,6 +105,7 @@ struct HostAdj {
   std::vector<Row> rows;
   std::vector<Ent> ent;
   std::vector<double> w;
+  std::vector<unsigned long long> pfx;  // inclusive qw prefix of long segments
 };
 
 }  // namespace
@@ -132,10 +134,11 @@ struct dyg_ctx {
   double walk_ms_total = 0.0, walk_ms_last = 0.0, batch_ms_last = 0.0;
   // batch staging
   DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, wrec, wofs, hadd, hash;
-  DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2];
-  DBuf qcount, qofs, qtile, item_upd, wres;  // batched form
-  uint32_t cus = 256;                         // compute units of the device
-  uint32_t walk_blocks_per_cu = 8;
+  DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2];
+  DBuf qcount, qofs, qtile, items, wres;  // batched form
+  uint32_t cus = 256;                      // compute units of the device
+  uint32_t walk_blocks_per_cu = 8;         // persistent walk grid = cus x this
+  uint32_t refill_min = 1;                 // idle lanes that trigger a refill
   HBuf pin_in, pin_out;
 };
 
@@ -148,6 +151,8 @@ void free_graph(DevGraph& X) {
   if (X.ent) (void)hipFree(X.ent);
   if (X.w) (void)hipFree(X.w);
   if (X.pending) (void)hipFree(X.pending);
+  if (X.pfx) (void)hipFree(X.pfx);
+  if (X.mark) (void)hipFree(X.mark);
   X = DevGraph{};
 }
 
@@ -161,7 +166,10 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
   if ((e = hipMalloc(&Y.rows, sizeof(Row) * std::max<uint64_t>(n, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.ent, sizeof(Ent) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.w, sizeof(double) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
-      (e = hipMalloc(&Y.pending, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess) {
+      (e = hipMalloc(&Y.pending, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
+      (e = hipMalloc(&Y.pfx, sizeof(unsigned long long) * std::max<uint64_t>(pool_cap, 1))) !=
+          hipSuccess ||
+      (e = hipMalloc(&Y.mark, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess) {
     free_graph(Y);
     return fail_hip(e);
   }
@@ -173,7 +181,11 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (!A.w.empty() &&
        (e = hipMemcpyAsync(Y.w, A.w.data(), sizeof(double) * A.w.size(), hipMemcpyHostToDevice,
                            st)) != hipSuccess) ||
+      (!A.pfx.empty() &&
+       (e = hipMemcpyAsync(Y.pfx, A.pfx.data(), sizeof(unsigned long long) * A.pfx.size(),
+                           hipMemcpyHostToDevice, st)) != hipSuccess) ||
       (e = hipMemsetAsync(Y.pending, 0, sizeof(uint32_t) * n, st)) != hipSuccess ||
+      (e = hipMemsetAsync(Y.mark, 0, sizeof(uint32_t) * n, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     free_graph(Y);
     return fail_hip(e);
@@ -187,6 +199,7 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
 void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
             const std::vector<Ent>& live_ent, const std::vector<double>& live_w, double slack) {
   A.rows.assign(n, Row{0, 0, 0, 0});
+  A.pfx.clear();
   uint64_t total = 0;
   for (uint32_t u = 0; u < n; ++u) {
     const uint32_t len = static_cast<uint32_t>(start[u + 1] - start[u]);
@@ -201,6 +214,14 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
     A.rows[u] = Row{static_cast<uint32_t>(off), len, cap, 0};
     std::copy(live_ent.begin() + start[u], live_ent.begin() + start[u + 1], A.ent.begin() + off);
     std::copy(live_w.begin() + start[u], live_w.begin() + start[u + 1], A.w.begin() + off);
+    if (len > dyg::kHub) {
+      if (A.pfx.empty()) A.pfx.assign(total, 0ull);
+      unsigned long long run = 0;
+      for (uint32_t i = 0; i < len; ++i) {
+        run += A.ent[off + i].qw;
+        A.pfx[off + i] = run;
+      }
+    }
     off += cap;
   }
 }
@@ -482,13 +503,14 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
   if (ok && (c->params.flags & DYG_FLAG_BATCHED)) {
     const uint64_t tiles = (nu + 1023) / 1024 + 1;
     ok = c->qcount.ensure(4 * nu + 8) && c->qofs.ensure(8 * nu + 8) &&
-         c->qtile.ensure(8 * tiles + 8) && c->item_upd.ensure(4 * items_cap + 8) &&
+         c->qtile.ensure(8 * tiles + 8) && c->items.ensure(sizeof(dyg::WalkItem) * items_cap + 8) &&
          c->wres.ensure(sizeof(dyg_walker_record) * items_cap + 16);
   }
   for (int g = 0; g < 2 && ok; ++g) {
     const uint64_t cap = g == 0 ? 2 * n_ins : 2 * hadd_cap;
     ok = c->touched_rows[g].ensure(4 * cap + 8) && c->touched_k[g].ensure(4 * cap + 8) &&
-         c->touched_need[g].ensure(4 * cap + 8) && c->add_keep[g].ensure(cap + 8);
+         c->touched_need[g].ensure(4 * cap + 8) && c->add_keep[g].ensure(cap + 8) &&
+         c->dirty_rows[g].ensure(4 * (cap + 2 * n_del) + 8);
   }
   return ok ? DYG_OK : DYG_E_NOMEM;
 }
@@ -535,11 +557,13 @@ BatchArgs make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t* 
     a.touched_k[g] = c->touched_k[g].as<uint32_t>();
     a.touched_need[g] = c->touched_need[g].as<uint32_t>();
     a.add_keep[g] = c->add_keep[g].as<uint8_t>();
+    a.dirty_rows[g] = c->dirty_rows[g].as<uint32_t>();
   }
   a.qcount = c->qcount.as<uint32_t>();
   a.qofs = c->qofs.as<unsigned long long>();
   a.qtile = c->qtile.as<unsigned long long>();
-  a.item_upd = c->item_upd.as<uint32_t>();
+  a.items = c->items.as<dyg::WalkItem>();
+  a.refill_min = c->refill_min;
   a.wres = c->wres.as<dyg::WalkerRec>();
   return a;
 }
@@ -872,6 +896,143 @@ extern "C" int dyg_stats(dyg_ctx* c, dyg_stats_t* out) {
   return DYG_OK;
 }
 
+namespace {
+
+struct HostImage {
+  std::vector<Row> rows;
+  std::vector<Ent> ent;
+  std::vector<double> w;
+  std::vector<unsigned long long> pfx;
+};
+
+int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, hipStream_t st) {
+  I.rows.resize(n);
+  I.ent.resize(used);
+  I.w.resize(used);
+  I.pfx.resize(used);
+  hipError_t e = hipMemcpyAsync(I.rows.data(), X.rows, sizeof(Row) * n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && used)
+    e = hipMemcpyAsync(I.ent.data(), X.ent, sizeof(Ent) * used, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && used)
+    e = hipMemcpyAsync(I.w.data(), X.w, sizeof(double) * used, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && used)
+    e = hipMemcpyAsync(I.pfx.data(), X.pfx, sizeof(unsigned long long) * used,
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? DYG_OK : fail_hip(e);
+}
+
+int find_live(const HostImage& I, uint32_t a, uint32_t b) {
+  const Row r = I.rows[a];
+  uint32_t lo = 0, hi = r.len;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (I.ent[r.off + mid].nbr < b) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < r.len && I.ent[r.off + lo].nbr == b && I.ent[r.off + lo].qw != 0u)
+    return static_cast<int>(lo);
+  return -1;
+}
+
+}  // namespace
+
+extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
+  if (!c) return DYG_E_INVALID_ARG;
+  auto fail = [&](const char* what, int g, uint64_t a, uint64_t b) {
+    if (msg && msg_len)
+      std::snprintf(msg, msg_len, "%s: graph %s row %llu item %llu", what, g ? "H" : "G",
+                    static_cast<unsigned long long>(a), static_cast<unsigned long long>(b));
+    return DYG_E_DEVICE;
+  };
+  if (msg && msg_len) msg[0] = 0;
+  if (c->async_inflight) {
+    int rc = dyg_sync(c);
+    if (rc) return rc;
+  }
+  BatchCtl ctl;
+  int rc = sync_ctl_host(c, ctl);
+  if (rc) return rc;
+  HostImage img[2];
+  for (int g = 0; g < 2; ++g) {
+    const DevGraph& X = g ? c->H : c->G;
+    rc = download_image(X, c->n, ctl.pool_top[g], img[g], c->stream);
+    if (rc) return rc;
+    const HostImage& I = img[g];
+    std::vector<std::pair<uint64_t, uint64_t>> spans;
+    for (uint32_t u = 0; u < c->n; ++u) {
+      const Row r = I.rows[u];
+      if (r.len > r.cap) return fail("len exceeds cap", g, u, r.len);
+      if (static_cast<uint64_t>(r.off) + r.cap > ctl.pool_top[g])
+        return fail("segment beyond pool top", g, u, r.off);
+      if (r.cap) spans.push_back({r.off, static_cast<uint64_t>(r.off) + r.cap});
+      uint32_t dead = 0;
+      unsigned long long run = 0;
+      for (uint32_t i = 0; i < r.len; ++i) {
+        const Ent& e = I.ent[r.off + i];
+        if (e.nbr >= c->n || e.nbr == u) return fail("bad neighbour id", g, u, i);
+        if (i && I.ent[r.off + i - 1].nbr >= e.nbr) return fail("segment not sorted", g, u, i);
+        if (e.qw == 0u) ++dead;
+        run += e.qw;
+        if (r.len > dyg::kHub && I.pfx[r.off + i] != run) return fail("stale weight prefix", g, u, i);
+        if (e.qw != 0u && !(e.rinv == 1.0 / I.w[r.off + i])) return fail("1/w mismatch", g, u, i);
+      }
+      if (dead != r.dead) {
+        if (msg && msg_len)
+          std::snprintf(msg, msg_len,
+                        "tombstone count: graph %s row %u off %u len %u cap %u dead %u counted %u",
+                        g ? "H" : "G", u, r.off, r.len, r.cap, r.dead, dead);
+        return DYG_E_DEVICE;
+      }
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+      if (spans[i].first < spans[i - 1].second) return fail("overlapping segments", g, i, 0);
+    for (uint32_t u = 0; u < c->n; ++u) {
+      const Row r = I.rows[u];
+      for (uint32_t i = 0; i < r.len; ++i) {
+        const Ent& e = I.ent[r.off + i];
+        if (e.qw == 0u) continue;
+        const int j = find_live(I, e.nbr, u);
+        if (j < 0) return fail("asymmetric edge", g, u, e.nbr);
+        const Ent& f = I.ent[I.rows[e.nbr].off + j];
+        if (f.qw != e.qw || I.w[I.rows[e.nbr].off + j] != I.w[r.off + i])
+          return fail("asymmetric weight", g, u, e.nbr);
+      }
+    }
+  }
+  for (uint32_t u = 0; u < c->n; ++u) {
+    const Row r = img[1].rows[u];
+    for (uint32_t i = 0; i < r.len; ++i) {
+      const Ent& e = img[1].ent[r.off + i];
+      if (e.qw == 0u) continue;
+      const int j = find_live(img[0], u, e.nbr);
+      if (j < 0) return fail("H edge missing from G", 1, u, e.nbr);
+      if (img[0].w[img[0].rows[u].off + j] != img[1].w[r.off + i])
+        return fail("H weight differs from G", 1, u, e.nbr);
+    }
+  }
+  return DYG_OK;
+}
+
+extern "C" int dyg_get_tuning(dyg_ctx* c, dyg_tuning* out) {
+  if (!c || !out) return DYG_E_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->walk_blocks_per_cu = c->walk_blocks_per_cu;
+  out->refill_min = c->refill_min;
+  return DYG_OK;
+}
+
+extern "C" int dyg_set_tuning(dyg_ctx* c, const dyg_tuning* t) {
+  if (!c || !t) return DYG_E_INVALID_ARG;
+  if (t->walk_blocks_per_cu < 1 || t->walk_blocks_per_cu > 64 || t->refill_min < 1 ||
+      t->refill_min > 64)
+    return DYG_E_INVALID_ARG;
+  c->walk_blocks_per_cu = t->walk_blocks_per_cu;
+  c->refill_min = t->refill_min;
+  return DYG_OK;
+}
+
 extern "C" int dyg_compact(dyg_ctx* c) {
   if (!c) return DYG_E_INVALID_ARG;
   if (c->async_inflight) {
@@ -894,13 +1055,14 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
   DBuf* bufs[] = {&c->iu, &c->iv, &c->iw, &c->du, &c->dv, &c->s, &c->L, &c->ins_qw,
                   &c->ins_rinv, &c->in_h, &c->res, &c->wrec, &c->wofs, &c->hadd, &c->hash};
   for (DBuf* b : bufs) b->release();
-  DBuf* qbufs[] = {&c->qcount, &c->qofs, &c->qtile, &c->item_upd, &c->wres};
+  DBuf* qbufs[] = {&c->qcount, &c->qofs, &c->qtile, &c->items, &c->wres};
   for (DBuf* b : qbufs) b->release();
   for (int g = 0; g < 2; ++g) {
     c->touched_rows[g].release();
     c->touched_k[g].release();
     c->touched_need[g].release();
     c->add_keep[g].release();
+    c->dirty_rows[g].release();
   }
   c->pin_in.release();
   c->pin_out.release();

@@ -33,6 +33,9 @@ static_assert(sizeof(Row) == 16, "Row layout");
 static_assert(sizeof(Ent) == 16, "Ent layout");
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// Segments longer than this keep an inclusive prefix of their quantised
+// weights, so a walker picks a neighbour by binary search instead of a scan.
+constexpr uint32_t kHub = 64;
 constexpr uint32_t kMaxWalkers = 1024;
 constexpr uint32_t kMaxSteps = 1024;
 
@@ -41,6 +44,8 @@ struct DevGraph {
   Ent* ent = nullptr;         // [pool_cap]
   double* w = nullptr;        // [pool_cap] weight of each entry (cold)
   uint32_t* pending = nullptr;  // [n] per-row counter, zero between batches
+  unsigned long long* pfx = nullptr;  // [pool_cap] inclusive qw prefix (rows with len > kHub)
+  uint32_t* mark = nullptr;     // [n] "prefix needs rebuilding" flag, zero between uses
   uint64_t pool_cap = 0;      // entries
 };
 
@@ -52,6 +57,16 @@ struct AddRec {
   double w;
 };
 static_assert(sizeof(AddRec) == 32, "AddRec layout");
+
+// One walker of the batched form's work queue.
+struct WalkItem {
+  uint32_t p, q;    // start vertex, target
+  uint32_t upd;     // update index in the batch (insertions first)
+  uint16_t walker;  // walker index within the update
+  uint16_t L;       // step limit
+  double w_pq;      // inserted edge weight (threshold test), 0 for deletions
+};
+static_assert(sizeof(WalkItem) == 24, "WalkItem layout");
 
 // Per-update result, layout identical to dyg_update_result.
 struct UpdRes {
@@ -78,7 +93,7 @@ struct BatchCtl {
   uint32_t touched[2];          // touched rows, per graph (0 = G, 1 = H)
   unsigned long long need[2];   // pool slots needed by relocations, per graph
   uint32_t nomem[2];            // phase-4 pool shortfall, per graph
-  uint32_t pad;
+  uint32_t dirty[2];            // rows whose prefix must be rebuilt, per graph
   unsigned long long pool_top[2];  // next free pool slot, per graph
   unsigned long long walk_items;       // walkers queued this batch
   unsigned long long queue_next;       // next queue item to hand out
@@ -129,11 +144,13 @@ struct BatchArgs {
   uint32_t* touched_k[2];
   uint32_t* touched_need[2];
   uint8_t* add_keep[2];       // per directed add entry: 1 = needs a new slot
+  uint32_t* dirty_rows[2];    // rows whose weight prefix must be rebuilt
   // batched form: walker work queue
   uint32_t* qcount;              // [n_ins + n_del] walkers of each update
   unsigned long long* qofs;      // [n_ins + n_del] first item of each update
   unsigned long long* qtile;     // [tiles] scan carry
-  uint32_t* item_upd;            // [items] update of each item
+  WalkItem* items;               // [items] walker of each queue item
+  uint32_t refill_min;           // idle lanes that trigger a refill (1..64)
   WalkerRec* wres;               // [items] outcome of each walker
 };
 

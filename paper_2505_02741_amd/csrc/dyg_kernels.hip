@@ -127,6 +127,7 @@ __global__ void k_batch_begin(BatchCtl* ctl) {
     ctl->touched[0] = ctl->touched[1] = 0;
     ctl->need[0] = ctl->need[1] = 0;
     ctl->nomem[0] = ctl->nomem[1] = 0;
+    ctl->dirty[0] = ctl->dirty[1] = 0;
   }
 }
 
@@ -205,12 +206,23 @@ __global__ void k_validate_b(BatchArgs a, const Row* grows, const Ent* gent) {
 
 // ---- phase 1 -------------------------------------------------------------------
 
-__device__ __forceinline__ void tombstone(DevGraph X, uint32_t a, uint32_t b) {
-  const Row r = X.rows[a];
-  const int k = find_nbr(X.ent, r, b);
+// Queue row r of graph `which` for a prefix rebuild (once per batch phase).
+__device__ __forceinline__ void mark_dirty(const BatchArgs& a, const DevGraph& X, int which,
+                                           uint32_t r) {
+  if (atomicExch(&X.mark[r], 1u) == 0u) {
+    const uint32_t t = atomicAdd(&a.ctl->dirty[which], 1u);
+    a.dirty_rows[which][t] = r;
+  }
+}
+
+__device__ __forceinline__ void tombstone(const BatchArgs& a, DevGraph X, int which, uint32_t u,
+                                          uint32_t v) {
+  const Row r = X.rows[u];
+  const int k = find_nbr(X.ent, r, v);
   if (k < 0) return;
   X.ent[r.off + k].qw = 0u;
-  atomicAdd(&X.rows[a].dead, 1u);
+  atomicAdd(&X.rows[u].dead, 1u);
+  if (r.len > kHub) mark_dirty(a, X, which, u);
 }
 
 __global__ void k_phase1(BatchArgs a, DevGraph G, DevGraph H) {
@@ -219,13 +231,41 @@ __global__ void k_phase1(BatchArgs a, DevGraph G, DevGraph H) {
   if (j >= a.n_del) return;
   const uint32_t u = a.du[j], v = a.dv[j];
   const bool in_h = has_live(H.rows, H.ent, u, v);
-  tombstone(G, u, v);
-  tombstone(G, v, u);
+  tombstone(a, G, 0, u, v);
+  tombstone(a, G, 0, v, u);
   if (in_h) {
-    tombstone(H, u, v);
-    tombstone(H, v, u);
+    tombstone(a, H, 1, u, v);
+    tombstone(a, H, 1, v, u);
   }
   a.in_h[j] = in_h ? 1 : 0;
+}
+
+// Block-wide inclusive scan helper over 64-bit values (kBlock threads).
+__device__ unsigned long long block_excl_scan(unsigned long long v, unsigned long long& excl);
+
+// Rebuild the inclusive weight prefix of every dirty row (one workgroup per
+// row), then clear its mark.
+__global__ __launch_bounds__(kBlock) void k_hub_prefix(BatchArgs a, DevGraph X, int which) {
+  if (batch_failed(a.ctl)) return;
+  const uint32_t count = a.ctl->dirty[which];
+  for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const uint32_t r = a.dirty_rows[which][t];
+    const Row row = X.rows[r];
+    unsigned long long carry = 0;
+    for (uint32_t base = 0; base < row.len; base += kBlock) {
+      const uint32_t i = base + threadIdx.x;
+      const unsigned long long q = i < row.len ? X.ent[row.off + i].qw : 0u;
+      unsigned long long excl;
+      const unsigned long long total = block_excl_scan(q, excl);
+      if (i < row.len) X.pfx[row.off + i] = carry + excl + q;
+      carry += total;
+    }
+    if (threadIdx.x == 0) X.mark[r] = 0u;
+  }
+}
+
+__global__ void k_dirty_reset(BatchCtl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->dirty[0] = ctl->dirty[1] = 0;
 }
 
 // ---- walks ------------------------------------------------------------------------
@@ -250,6 +290,7 @@ __device__ __forceinline__ uint32_t step_bytes(uint32_t d) {
 struct WalkParams {
   const Row* rows;
   const Ent* ent;
+  const unsigned long long* pfx;
   uint32_t p, q;
   bool use_K;
   double w_pq, K;
@@ -291,35 +332,69 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
   const uint32_t t = S.steps;
   if (t >= P.L) return false;
   const Row r = P.rows[S.x];
-  const uint2* e2 = reinterpret_cast<const uint2*>(P.ent + r.off);  // (nbr, qw) pairs
-  unsigned long long tot = 0;
-  for (uint32_t i = 0; i < r.len; ++i) {
-    const uint2 e = e2[2 * i];
-    tot += (e.x != S.prev) ? e.y : 0u;
-  }
   uint32_t pick;
-  if (tot == 0) {
-    if (!(P.bounce && S.prev != kNone)) return false;  // leaf: the walker stops
-    const int back = find_nbr(P.ent, r, S.prev);
-    if (back < 0) return false;  // cannot happen: the edge just used is live
-    pick = static_cast<uint32_t>(back);
-  } else {
-    if (S.block_of != (t >> 1)) {
-      S.rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
-      S.block_of = t >> 1;
+  if (r.len > kHub) {
+    // long segment: the candidates' running sums are the stored prefix with
+    // the previous vertex's weight taken out
+    const unsigned long long* pf = P.pfx + r.off;
+    int jp = -1;
+    uint32_t qprev = 0;
+    if (S.prev != kNone) {
+      jp = find_nbr(P.ent, r, S.prev);
+      if (jp >= 0) qprev = P.ent[r.off + jp].qw;
     }
-    const unsigned long long r64 =
-        (t & 1u) ? (uint64_t(S.rnd.x2) | (uint64_t(S.rnd.x3) << 32))
-                 : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
-    const unsigned long long target = __umul64hi(r64, tot);
-    unsigned long long run = 0;
-    pick = r.len - 1;
+    const unsigned long long tot = pf[r.len - 1] - qprev;
+    if (tot == 0) {
+      if (!(P.bounce && jp >= 0)) return false;
+      pick = static_cast<uint32_t>(jp);
+    } else {
+      if (S.block_of != (t >> 1)) {
+        S.rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
+        S.block_of = t >> 1;
+      }
+      const unsigned long long r64 =
+          (t & 1u) ? (uint64_t(S.rnd.x2) | (uint64_t(S.rnd.x3) << 32))
+                   : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
+      unsigned long long target = __umul64hi(r64, tot);
+      if (jp >= 0 && target >= pf[jp] - qprev) target += qprev;
+      uint32_t lo = 0, hi = r.len - 1;  // first i with pf[i] > target
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pf[mid] > target) hi = mid;
+        else lo = mid + 1;
+      }
+      pick = lo;
+    }
+  } else {
+    const uint2* e2 = reinterpret_cast<const uint2*>(P.ent + r.off);  // (nbr, qw) pairs
+    unsigned long long tot = 0;
     for (uint32_t i = 0; i < r.len; ++i) {
       const uint2 e = e2[2 * i];
-      run += (e.x != S.prev) ? e.y : 0u;
-      if (run > target) {
-        pick = i;
-        break;
+      tot += (e.x != S.prev) ? e.y : 0u;
+    }
+    if (tot == 0) {
+      if (!(P.bounce && S.prev != kNone)) return false;  // leaf: the walker stops
+      const int back = find_nbr(P.ent, r, S.prev);
+      if (back < 0) return false;  // cannot happen: the edge just used is live
+      pick = static_cast<uint32_t>(back);
+    } else {
+      if (S.block_of != (t >> 1)) {
+        S.rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
+        S.block_of = t >> 1;
+      }
+      const unsigned long long r64 =
+          (t & 1u) ? (uint64_t(S.rnd.x2) | (uint64_t(S.rnd.x3) << 32))
+                   : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
+      const unsigned long long target = __umul64hi(r64, tot);
+      unsigned long long run = 0;
+      pick = r.len - 1;
+      for (uint32_t i = 0; i < r.len; ++i) {
+        const uint2 e = e2[2 * i];
+        run += (e.x != S.prev) ? e.y : 0u;
+        if (run > target) {
+          pick = i;
+          break;
+        }
       }
     }
   }
@@ -420,6 +495,7 @@ __device__ __forceinline__ UpdateView view_update(const BatchArgs& a, const DevG
   P.bounce = a.bounce != 0;
   P.rows = v.is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
   P.ent = v.is_ins ? H.ent : G.ent;
+  P.pfx = v.is_ins ? H.pfx : G.pfx;
   v.walks = v.is_ins || a.in_h[j];
   return v;
 }
@@ -635,62 +711,116 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(BatchArgs a) {
     if (base + k < nu) a.qofs[base + k] += add;
 }
 
-// Item -> update map: one wavefront per update writes its walkers' entries.
+// Queue items: one wavefront per update writes one record per walker.
 __global__ __launch_bounds__(kBlock) void k_expand_items(BatchArgs a) {
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t upd = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
   if (upd >= a.n_ins + a.n_del) return;
   const uint32_t cnt = a.qcount[upd];
+  if (cnt == 0) return;
+  const bool is_ins = upd < a.n_ins;
+  const uint32_t j = upd - a.n_ins;
+  WalkItem it;
+  it.p = is_ins ? a.iu[upd] : a.du[j];
+  it.q = is_ins ? a.iv[upd] : a.dv[j];
+  it.upd = upd;
+  it.L = static_cast<uint16_t>(a.L ? a.L[upd] : a.L_def);
+  it.w_pq = is_ins ? a.iw[upd] : 0.0;
   const unsigned long long base = a.qofs[upd];
-  for (uint32_t k = lane; k < cnt; k += kWave) a.item_upd[base + k] = upd;
+  for (uint32_t k = lane; k < cnt; k += kWave) {
+    it.walker = static_cast<uint16_t>(k);
+    a.items[base + k] = it;
+  }
 }
 
-// Persistent walk kernel over the queue of (update, walker) items.  Every lane
-// runs one walker at a time; a lane whose walker stops takes the next item
-// (one atomic per wavefront and refill), so lanes never idle while work is
-// left.  Each walker's outcome goes to wres[item].
+// Persistent walk kernel over the queue of walker items.  A wavefront takes 64
+// items at a time with one atomic; a lane whose walker stops gets the next
+// item of that pool.  The new item's record is loaded before the other lanes'
+// step and used after it, so its latency hides behind the step's own loads.
+// Every walker's outcome goes to wres[item].
 __global__ __launch_bounds__(kBlock) void k_walk_queue(BatchArgs a, DevGraph G, DevGraph H) {
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const unsigned long long total = a.ctl->walk_items;
   const unsigned long long lanes_below = (1ull << lane) - 1ull;
-  bool active = false, drained = false;
-  unsigned long long item = 0;
-  uint32_t walker = 0;
+  const uint32_t refill_min = a.refill_min < 1 ? 1u : (a.refill_min > 64 ? 64u : a.refill_min);
+  unsigned long long pool_next = 0, pool_end = 0;  // this wavefront's items
+  bool drained = false;
+  bool active = false, pending = false;
+  unsigned long long item = 0, next_item = 0;
+  WalkItem rec{0, 0, 0, 0, 0, 0.0};
   WalkParams P;
+  P.K = a.K;
+  P.key0 = static_cast<uint32_t>(a.seed);
+  P.key1 = static_cast<uint32_t>(a.seed >> 32);
+  P.bounce = a.bounce != 0;
+  P.rows = H.rows;
+  P.ent = H.ent;
+  P.pfx = H.pfx;
+  P.p = P.q = 0;
+  P.use_K = false;
+  P.w_pq = 0.0;
+  P.L = 0;
+  P.uid_lo = P.uid_hi = 0;
+  uint32_t walker = 0;
   WState S;
+  walker_start(S, 0);
   unsigned long long steps = 0, bytes = 0;
   while (true) {
-    if (!drained) {
-      const unsigned long long idle = __ballot(!active);
-      if (idle) {
-        const uint32_t leader = static_cast<uint32_t>(__builtin_ctzll(idle));
+    // (1) hand pool items to idle lanes
+    const unsigned long long idle = __ballot(!active && !pending);
+    const uint32_t n_idle = static_cast<uint32_t>(__popcll(idle));
+    if (n_idle && (n_idle >= refill_min || n_idle == kWave)) {
+      if (pool_next >= pool_end && !drained) {
         unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&a.ctl->queue_next, __popcll(idle));
-        base = __shfl(base, leader, kWave);
-        if (base + __popcll(idle) >= total) drained = true;
-        if (!active) {
-          item = base + __popcll(idle & lanes_below);
-          if (item < total) {
-            const uint32_t upd = a.item_upd[item];
-            const UpdateView v = view_update(a, G, H, upd);
-            P = v.P;
-            walker = static_cast<uint32_t>(item - a.qofs[upd]);
-            walker_start(S, P.p);
-            active = true;
-          }
+        if (lane == 0) base = atomicAdd(&a.ctl->queue_next, static_cast<unsigned long long>(kWave));
+        base = __shfl(base, 0, kWave);
+        pool_next = base;
+        pool_end = base < total ? (base + kWave < total ? base + kWave : total) : base;
+        if (base + kWave >= total) drained = true;
+      }
+      const unsigned long long avail = pool_end - pool_next;
+      const uint32_t take = avail < n_idle ? static_cast<uint32_t>(avail) : n_idle;
+      if (!active && !pending) {
+        const uint32_t rank = static_cast<uint32_t>(__popcll(idle & lanes_below));
+        if (rank < take) {
+          next_item = pool_next + rank;
+          rec = a.items[next_item];
+          pending = true;
         }
       }
+      pool_next += take;
     }
-    if (!__ballot(active)) break;
+    // (2) one step of every running walker
     if (active && !walk_step(P, walker, S, NoSink{})) {
-      a.wres[item] = WalkerRec{static_cast<uint8_t>(S.hit), 0,
-                               static_cast<uint16_t>(S.steps), S.x, S.R};
+      a.wres[item] = WalkerRec{static_cast<uint8_t>(S.hit), 0, static_cast<uint16_t>(S.steps),
+                               S.x, S.R};
       steps += S.steps;
       bytes += S.bytes;
       active = false;
     }
+    // (3) lanes that received an item start its walker
+    if (pending) {
+      item = next_item;
+      const bool is_ins = rec.upd < a.n_ins;
+      const uint64_t uid = a.uid_base + rec.upd;
+      P.p = rec.p;
+      P.q = rec.q;
+      P.use_K = is_ins && a.has_K;
+      P.w_pq = rec.w_pq;
+      P.L = rec.L;
+      P.uid_lo = static_cast<uint32_t>(uid);
+      P.uid_hi = static_cast<uint32_t>(uid >> 32);
+      P.rows = is_ins ? H.rows : G.rows;
+      P.ent = is_ins ? H.ent : G.ent;
+      P.pfx = is_ins ? H.pfx : G.pfx;
+      walker = rec.walker;
+      walker_start(S, rec.p);
+      active = true;
+      pending = false;
+    }
+    if (!__ballot(active) && drained && pool_next >= pool_end) break;
   }
   const unsigned long long ws = wave_sum64(steps);
   const unsigned long long wb = wave_sum64(bytes);
@@ -783,6 +913,7 @@ __global__ void k_add_prepare(BatchArgs a, DevGraph X, int which) {
       X.ent[row.off + k].rinv = d.rinv;
       X.w[row.off + k] = d.w;
       atomicSub(&X.rows[d.r].dead, 1u);
+      if (row.len > kHub) mark_dirty(a, X, which, d.r);
     }
     return;
   }
@@ -803,6 +934,13 @@ __device__ __forceinline__ uint32_t grown_cap(uint32_t live) {
   return live + extra;
 }
 
+// touched_k packs the number of appended entries with two decisions taken
+// here, once, from the segment as it stands before phase 4 moves anything:
+// whether the segment is relocated by a workgroup and merged by a workgroup.
+constexpr uint32_t kWideRelocate = 1u << 30;
+constexpr uint32_t kWideMerge = 1u << 31;
+constexpr uint32_t kCountMask = kWideRelocate - 1u;
+
 __global__ void k_rows_plan(BatchArgs a, DevGraph X, int which) {
   if (batch_failed(a.ctl)) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -810,12 +948,15 @@ __global__ void k_rows_plan(BatchArgs a, DevGraph X, int which) {
   const uint32_t r = a.touched_rows[which][t];
   const uint32_t k = X.pending[r];
   const Row row = X.rows[r];
-  uint32_t need = 0;
+  uint32_t need = 0, flags = 0, merged_from = row.len;
   if (row.len + k > row.cap) {
     need = grown_cap(row.len - row.dead + k);
     atomicAdd(&a.ctl->need[which], static_cast<unsigned long long>(need));
+    if (row.len > kHub) flags |= kWideRelocate;
+    merged_from = row.len - row.dead;  // relocation drops the tombstones
   }
-  a.touched_k[which][t] = k;
+  if (merged_from + k > kHub) flags |= kWideMerge;
+  a.touched_k[which][t] = k | flags;
   a.touched_need[which][t] = need;
 }
 
@@ -831,6 +972,7 @@ __global__ void k_rows_relocate(BatchArgs a, DevGraph X, int which) {
   if (t >= a.ctl->touched[which]) return;
   const uint32_t need = a.touched_need[which][t];
   if (need == 0) return;
+  if (a.touched_k[which][t] & kWideRelocate) return;  // moved by k_rows_relocate_wide
   const uint32_t r = a.touched_rows[which][t];
   const Row row = X.rows[r];
   const uint32_t off =
@@ -846,6 +988,46 @@ __global__ void k_rows_relocate(BatchArgs a, DevGraph X, int which) {
   X.rows[r] = Row{off, o, need, 0u};
 }
 
+// Relocation of long segments: one workgroup per segment, tombstones dropped
+// through a block-wide scan of the live flags.
+__global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(BatchArgs a, DevGraph X,
+                                                               int which) {
+  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
+  __shared__ uint32_t s_off;
+  const uint32_t count = a.ctl->touched[which];
+  for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const uint32_t need = a.touched_need[which][t];
+    if (need == 0 || !(a.touched_k[which][t] & kWideRelocate)) continue;  // block-uniform
+    const uint32_t r = a.touched_rows[which][t];
+    const Row row = X.rows[r];
+    if (threadIdx.x == 0)
+      s_off = static_cast<uint32_t>(
+          atomicAdd(&a.ctl->pool_top[which], static_cast<unsigned long long>(need)));
+    __syncthreads();
+    const uint32_t off = s_off;
+    unsigned long long out = 0;
+    for (uint32_t base = 0; base < row.len; base += kBlock) {
+      const uint32_t i = base + threadIdx.x;
+      Ent e{0, 0, 0.0};
+      double we = 0.0;
+      if (i < row.len) {
+        e = X.ent[row.off + i];
+        we = X.w[row.off + i];
+      }
+      const unsigned long long live = (i < row.len && e.qw != 0u) ? 1u : 0u;
+      unsigned long long excl;
+      const unsigned long long total = block_excl_scan(live, excl);
+      if (live) {
+        X.ent[off + out + excl] = e;
+        X.w[off + out + excl] = we;
+      }
+      out += total;
+    }
+    if (threadIdx.x == 0) X.rows[r] = Row{off, static_cast<uint32_t>(out), need, 0u};
+    __syncthreads();
+  }
+}
+
 __global__ void k_add_place(BatchArgs a, DevGraph X, int which) {
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -859,13 +1041,16 @@ __global__ void k_add_place(BatchArgs a, DevGraph X, int which) {
   X.w[pos] = d.w;
 }
 
-// Merge the k appended entries (unsorted tail) into the sorted segment.
+// Merge the k appended entries (unsorted tail) into the sorted segment; one
+// thread per short segment (insertion of each new entry).
 __global__ void k_rows_merge(BatchArgs a, DevGraph X, int which) {
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
+  const uint32_t packed = a.touched_k[which][t];
+  if (packed & kWideMerge) return;  // merged by k_rows_merge_wide
   const uint32_t r = a.touched_rows[which][t];
-  const uint32_t k = a.touched_k[which][t];
+  const uint32_t k = packed & kCountMask;
   const Row row = X.rows[r];
   Ent* seg = X.ent + row.off;
   double* wseg = X.w + row.off;
@@ -884,6 +1069,119 @@ __global__ void k_rows_merge(BatchArgs a, DevGraph X, int which) {
   X.rows[r].len = row.len + k;
 }
 
+constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 KB LDS)
+
+// Merge for long segments: one workgroup per segment.  Each pass takes up to
+// kTailChunk appended entries, sorts them in LDS (bitonic), computes every
+// entry's final position (old entries shift right by the number of new
+// entries below them; new entries sit after the old entries below them) and
+// moves the old entries right to left in block-sized chunks, so no entry is
+// overwritten before it is read.
+__global__ __launch_bounds__(kBlock) void k_rows_merge_wide(BatchArgs a, DevGraph X, int which) {
+  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
+  __shared__ unsigned long long s_key[kTailChunk];  // (nbr << 32) | local index
+  __shared__ Ent s_ent[kTailChunk];
+  __shared__ double s_w[kTailChunk];
+  __shared__ uint32_t s_pos[kTailChunk];
+  const uint32_t count = a.ctl->touched[which];
+  for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const uint32_t packed = a.touched_k[which][t];
+    if (!(packed & kWideMerge)) continue;  // block-uniform
+    const uint32_t r = a.touched_rows[which][t];
+    const uint32_t k = packed & kCountMask;
+    const Row row = X.rows[r];
+    Ent* seg = X.ent + row.off;
+    double* wseg = X.w + row.off;
+    uint32_t cur = row.len;  // sorted prefix length
+    for (uint32_t c0 = 0; c0 < k; c0 += kTailChunk) {
+      const uint32_t c = (k - c0) < kTailChunk ? (k - c0) : kTailChunk;
+      uint32_t P = 1;
+      while (P < c) P <<= 1;
+      for (uint32_t j = threadIdx.x; j < P; j += kBlock) {
+        if (j < c) {
+          s_ent[j] = seg[cur + j];
+          s_w[j] = wseg[cur + j];
+          s_key[j] = (static_cast<unsigned long long>(s_ent[j].nbr) << 32) | j;
+        } else {
+          s_key[j] = ~0ull;
+        }
+      }
+      __syncthreads();
+      for (uint32_t size = 2; size <= P; size <<= 1)
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+          for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+            const uint32_t l = i ^ stride;
+            if (l > i) {
+              const bool up = (i & size) == 0;
+              const unsigned long long x = s_key[i], y = s_key[l];
+              if ((x > y) == up) {
+                s_key[i] = y;
+                s_key[l] = x;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      // final slot of each new entry: its rank plus the old entries below it
+      for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
+        const uint32_t key = static_cast<uint32_t>(s_key[j] >> 32);
+        uint32_t lo = 0, hi = cur;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (seg[mid].nbr < key) lo = mid + 1;
+          else hi = mid;
+        }
+        s_pos[j] = j + lo;
+      }
+      __syncthreads();
+      // old entries, right to left
+      for (uint32_t hi_i = cur; hi_i > 0;) {
+        const uint32_t lo_i = hi_i > kBlock ? hi_i - kBlock : 0;
+        const uint32_t i = lo_i + threadIdx.x;
+        Ent e{0, 0, 0.0};
+        double we = 0.0;
+        uint32_t shift = 0;
+        if (i < hi_i) {
+          e = seg[i];
+          we = wseg[i];
+          uint32_t lo = 0, hi = c;  // new entries below e.nbr
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (static_cast<uint32_t>(s_key[mid] >> 32) < e.nbr) lo = mid + 1;
+            else hi = mid;
+          }
+          shift = lo;
+        }
+        __syncthreads();
+        if (i < hi_i && shift) {
+          seg[i + shift] = e;
+          wseg[i + shift] = we;
+        }
+        __syncthreads();
+        hi_i = lo_i;
+      }
+      for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
+        const uint32_t src = static_cast<uint32_t>(s_key[j] & 0xFFFFFFFFull);
+        seg[s_pos[j]] = s_ent[src];
+        wseg[s_pos[j]] = s_w[src];
+      }
+      __syncthreads();
+      cur += c;
+    }
+    if (threadIdx.x == 0) X.rows[r].len = cur;
+    __syncthreads();
+  }
+}
+
+// Long segments touched by phase 4 need their prefix rebuilt.
+__global__ void k_mark_merged(BatchArgs a, DevGraph X, int which) {
+  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ctl->touched[which]) return;
+  const uint32_t r = a.touched_rows[which][t];
+  if (X.rows[r].len > kHub) mark_dirty(a, X, which, r);
+}
+
 // After a pool shortfall: undo the per-row counters so phase 4 can run again
 // once the pool has grown.
 __global__ void k_phase4_reset(BatchArgs a, DevGraph X, int which) {
@@ -899,6 +1197,8 @@ __global__ void k_phase4_reset_ctl(BatchCtl* ctl, int which) {
     ctl->nomem[which] = 0;
   }
 }
+
+constexpr uint32_t kWideBlocks = 512;  // workgroups of the per-long-segment kernels
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per = kBlock) {
   return static_cast<uint32_t>((n + per - 1) / per);
@@ -925,6 +1225,10 @@ void launch_validate(const BatchArgs& a, const DevGraph& G, hipStream_t st) {
 void launch_phase1(const BatchArgs& a, DevGraph& G, DevGraph& H, hipStream_t st) {
   if (a.n_del == 0) return;
   k_phase1<<<blocks_for(a.n_del), kBlock, 0, st>>>(a, G, H);
+  // walks read the prefix of long segments: rebuild the ones just changed
+  k_hub_prefix<<<kWideBlocks, kBlock, 0, st>>>(a, G, 0);
+  k_hub_prefix<<<kWideBlocks, kBlock, 0, st>>>(a, H, 1);
+  k_dirty_reset<<<1, 64, 0, st>>>(a.ctl);
 }
 
 void launch_walks(const BatchArgs& a, const DevGraph& G, const DevGraph& H, hipStream_t st) {
@@ -963,8 +1267,13 @@ void launch_phase4(const BatchArgs& a, DevGraph& X, int which, uint64_t hash_slo
   k_rows_plan<<<nb, kBlock, 0, st>>>(a, X, which);
   k_pool_check<<<1, 64, 0, st>>>(a, X.pool_cap, which);
   k_rows_relocate<<<nb, kBlock, 0, st>>>(a, X, which);
+  k_rows_relocate_wide<<<kWideBlocks, kBlock, 0, st>>>(a, X, which);
   k_add_place<<<nb, kBlock, 0, st>>>(a, X, which);
   k_rows_merge<<<nb, kBlock, 0, st>>>(a, X, which);
+  k_rows_merge_wide<<<kWideBlocks, kBlock, 0, st>>>(a, X, which);
+  k_mark_merged<<<nb, kBlock, 0, st>>>(a, X, which);
+  k_hub_prefix<<<kWideBlocks, kBlock, 0, st>>>(a, X, which);
+  k_dirty_reset<<<1, 64, 0, st>>>(a.ctl);
 }
 
 void launch_phase4_reset(const BatchArgs& a, DevGraph& X, int which, hipStream_t st) {

@@ -67,6 +67,11 @@ class dyg_stats_t(C.Structure):
                 ("walk_ms_last", C.c_double), ("batch_ms_last", C.c_double)]
 
 
+class dyg_tuning(C.Structure):
+    _fields_ = [("walk_blocks_per_cu", C.c_uint32), ("refill_min", C.c_uint32),
+                ("reserved", C.c_uint32 * 6)]
+
+
 class dyg_batch_dev(C.Structure):
     _fields_ = [("n_ins", C.c_uint64), ("n_del", C.c_uint64), ("iu", C.c_void_p),
                 ("iv", C.c_void_p), ("iw", C.c_void_p), ("du", C.c_void_p),
@@ -76,7 +81,8 @@ class dyg_batch_dev(C.Structure):
 
 EXPORTS = ["dyg_default_params", "dyg_init", "dyg_apply_batch", "dyg_apply_batch_dev",
            "dyg_sync", "dyg_query_sparsifier", "dyg_query_graph", "dyg_stats", "dyg_compact",
-           "dyg_destroy", "dyg_error_string"]
+           "dyg_destroy", "dyg_error_string", "dyg_get_tuning", "dyg_set_tuning",
+           "dyg_check_state"]
 
 
 class DygError(RuntimeError):
@@ -87,6 +93,14 @@ class DygError(RuntimeError):
 
 
 def _load():
+    # A process must hold one HIP runtime.  PyTorch ships its own copy; when it
+    # is installed, load it first so that libdygrass binds to the same runtime
+    # (its device pointers and streams are then valid here, and torch keeps
+    # seeing the GPU after this library has used it).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python paper_2505_02741_amd/build.py")
     lib = C.CDLL(LIB_PATH)
@@ -107,6 +121,12 @@ def _load():
         fn.restype = C.c_int
     lib.dyg_stats.argtypes = [P, C.POINTER(dyg_stats_t)]
     lib.dyg_stats.restype = C.c_int
+    lib.dyg_check_state.argtypes = [P, C.c_char_p, C.c_uint64]
+    lib.dyg_check_state.restype = C.c_int
+    lib.dyg_get_tuning.argtypes = [P, C.POINTER(dyg_tuning)]
+    lib.dyg_get_tuning.restype = C.c_int
+    lib.dyg_set_tuning.argtypes = [P, C.POINTER(dyg_tuning)]
+    lib.dyg_set_tuning.restype = C.c_int
     lib.dyg_compact.argtypes = [P]
     lib.dyg_compact.restype = C.c_int
     lib.dyg_destroy.argtypes = [P]
@@ -234,6 +254,27 @@ def dyg_stats(ctx) -> dict:
     return {name: getattr(st, name) for name, _ in dyg_stats_t._fields_ if "reserved" not in name}
 
 
+def dyg_check_state(ctx) -> str:
+    """'' if the device state is consistent, else a description of the first
+    violation."""
+    buf = C.create_string_buffer(512)
+    rc = _lib.dyg_check_state(ctx, buf, 512)
+    if rc == 0:
+        return ""
+    return buf.value.decode() or STATUS.get(rc, str(rc))
+
+
+def dyg_get_tuning(ctx) -> dict:
+    t = dyg_tuning()
+    _check(_lib.dyg_get_tuning(ctx, C.byref(t)), "dyg_get_tuning")
+    return {"walk_blocks_per_cu": t.walk_blocks_per_cu, "refill_min": t.refill_min}
+
+
+def dyg_set_tuning(ctx, walk_blocks_per_cu: int, refill_min: int):
+    t = dyg_tuning(walk_blocks_per_cu=int(walk_blocks_per_cu), refill_min=int(refill_min))
+    _check(_lib.dyg_set_tuning(ctx, C.byref(t)), "dyg_set_tuning")
+
+
 def dyg_compact(ctx):
     _check(_lib.dyg_compact(ctx), "dyg_compact")
 
@@ -272,6 +313,9 @@ class Dygrass:
 
     def stats(self):
         return dyg_stats(self.ctx)
+
+    def check_state(self) -> str:
+        return dyg_check_state(self.ctx)
 
     def compact(self):
         dyg_compact(self.ctx)

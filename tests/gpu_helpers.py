@@ -68,6 +68,8 @@ def compare_batch(o, d, b, record=True, tag=""):
 
 
 def compare_state(o, d, tag=""):
+    problem = d.check_state()
+    assert problem == "", f"{tag}: device state inconsistent: {problem}"
     for which in ("G", "H"):
         ou, ov, ow = o.query(which)
         lu, lv, lw = d.query(which)
