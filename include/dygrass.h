@@ -70,6 +70,10 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
                                   walker) items; lanes take a new walker as soon
                                   as theirs stops (same results as the plain
                                   one-wavefront-per-update form)                 */
+#define DYG_FLAG_GRAPH 8u      /* run each batch's launch sequence as a captured
+                                  HIP graph, one per power-of-two size class of
+                                  (insertions, deletions), replayed for every
+                                  batch of that class                            */
 
 #define DYG_MAX_WALKERS 1024 /* per update */
 #define DYG_MAX_STEPS 1024   /* per walker */
@@ -234,6 +238,56 @@ int dyg_check_state(dyg_ctx* ctx, char* msg, uint64_t msg_len);
 
 void dyg_destroy(dyg_ctx* ctx);
 const char* dyg_error_string(int code);
+
+/*
+ * Serving: one process keeps many graphs' G and H resident and applies update
+ * batches as they arrive.  Batches of one graph are sequential (a batch reads
+ * the state its predecessor left); batches of different graphs are
+ * independent.  Each round admits the oldest waiting batches of graphs that
+ * have none in flight, up to max_fused of them and within mem_budget bytes of
+ * batch working memory, and runs them as one fused launch sequence (one
+ * persistent walk launch over all their walkers).  Up to max_inflight rounds
+ * run at once on separate streams, so batches that arrive while others are on
+ * the GPU start as soon as slots and memory free up.  A batch's results are
+ * bit-identical to applying it alone with dyg_apply_batch.
+ */
+typedef struct dyg_server dyg_server;
+
+typedef struct {
+  uint64_t mem_budget;   /* bytes of batch working memory held by rounds in flight   */
+  uint32_t max_fused;    /* batches per round, 1..64                                  */
+  uint32_t max_inflight; /* rounds in flight, 1..8                                    */
+  uint32_t walk_blocks_per_cu; /* persistent walk grid per round, 1..64              */
+  uint32_t reserved[3];
+} dyg_server_params;
+
+typedef struct {
+  uint64_t request_id;
+  uint32_t graph_id;
+  int32_t status;        /* DYG_OK or the batch's error (state of that graph unchanged) */
+  uint64_t n_updates;
+  double t_submit;       /* seconds on the server's monotonic clock                  */
+  double t_start;        /* round launched                                           */
+  double t_done;         /* round observed complete                                  */
+} dyg_request_done;
+
+void dyg_server_default_params(dyg_server_params* p);
+int dyg_server_create(dyg_server** out, const dyg_server_params* p);
+/* Register a context (not owned; it must outlive the server and must not be
+ * used directly while the server holds work for it). */
+int dyg_server_add_graph(dyg_server* s, dyg_ctx* ctx, uint32_t* graph_id);
+/* Queue a batch (host arrays copied at the call).  results: NULL or n_ins+n_del
+ * records filled by the time the request is reported done. */
+int dyg_server_submit(dyg_server* s, uint32_t graph_id, uint64_t n_ins, const uint32_t* iu,
+                      const uint32_t* iv, const double* iw, uint64_t n_del, const uint32_t* du,
+                      const uint32_t* dv, dyg_update_result* results, uint64_t* request_id);
+/* Retire finished rounds, admit and launch new ones; never blocks on the GPU.
+ * Writes up to cap finished requests to done and their number to *n_done. */
+int dyg_server_poll(dyg_server* s, dyg_request_done* done, uint32_t cap, uint32_t* n_done);
+/* Number of requests submitted but not yet reported by dyg_server_poll. */
+uint64_t dyg_server_pending(const dyg_server* s);
+double dyg_server_now(const dyg_server* s);
+void dyg_server_destroy(dyg_server* s);
 
 #ifdef __cplusplus
 }

@@ -6,6 +6,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -20,10 +24,9 @@ using dyg::DevGraph;
 using dyg::Ent;
 using dyg::HashSlot;
 using dyg::Row;
-
-namespace dyg {
-void launch_phase4_reset(const BatchArgs& a, DevGraph& X, int which, hipStream_t st);
-}
+using dyg::RowHdr;
+using dyg::kInline;
+using dyg::kInlineOff;
 
 namespace {
 
@@ -103,9 +106,10 @@ uint32_t slack_slots(uint32_t len, double slack) {
 // Host image of one adjacency (used at init and by compaction).
 struct HostAdj {
   std::vector<Row> rows;
-  std::vector<Ent> ent;
-  std::vector<double> w;
+  std::vector<Ent> ent;                 // pool
+  std::vector<double> w;                // pool weights
   std::vector<unsigned long long> pfx;  // inclusive qw prefix of long segments
+  std::vector<double> winl;             // weights of inline entries, kInline per row
 };
 
 }  // namespace
@@ -122,6 +126,11 @@ struct dyg_ctx {
   hipStream_t stream = nullptr;
   DevGraph G, H;
   BatchCtl* ctl = nullptr;
+  BatchArgs* dargs = nullptr;  // device copy of the current batch's arguments
+  // DYG_FLAG_GRAPH: instantiated launch sequences by size class
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t>, hipGraphExec_t> graphs;
+  BatchArgs* hargs = nullptr;  // pinned host staging of the same
+  const BatchArgs** dargv = nullptr;  // device array {dargs}: a launch of one batch
   uint64_t pool_top[2] = {0, 0};  // host mirror after the last sync
   bool broken = false;
   int pending_status = DYG_OK;
@@ -153,6 +162,7 @@ void free_graph(DevGraph& X) {
   if (X.pending) (void)hipFree(X.pending);
   if (X.pfx) (void)hipFree(X.pfx);
   if (X.mark) (void)hipFree(X.mark);
+  if (X.winl) (void)hipFree(X.winl);
   X = DevGraph{};
 }
 
@@ -169,7 +179,9 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (e = hipMalloc(&Y.pending, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.pfx, sizeof(unsigned long long) * std::max<uint64_t>(pool_cap, 1))) !=
           hipSuccess ||
-      (e = hipMalloc(&Y.mark, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess) {
+      (e = hipMalloc(&Y.mark, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
+      (e = hipMalloc(&Y.winl, sizeof(double) * kInline * std::max<uint64_t>(n, 1))) !=
+          hipSuccess) {
     free_graph(Y);
     return fail_hip(e);
   }
@@ -184,6 +196,8 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (!A.pfx.empty() &&
        (e = hipMemcpyAsync(Y.pfx, A.pfx.data(), sizeof(unsigned long long) * A.pfx.size(),
                            hipMemcpyHostToDevice, st)) != hipSuccess) ||
+      (e = hipMemcpyAsync(Y.winl, A.winl.data(), sizeof(double) * A.winl.size(),
+                          hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemsetAsync(Y.pending, 0, sizeof(uint32_t) * n, st)) != hipSuccess ||
       (e = hipMemsetAsync(Y.mark, 0, sizeof(uint32_t) * n, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
@@ -195,23 +209,33 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
   return DYG_OK;
 }
 
-// Lay out segments with slack for the given per-row live lists.
+// Lay out the rows for the given per-row live lists: at most kInline entries
+// inside the row, longer lists in a pool segment with slack.
 void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
             const std::vector<Ent>& live_ent, const std::vector<double>& live_w, double slack) {
-  A.rows.assign(n, Row{0, 0, 0, 0});
+  A.rows.assign(n, Row{});
+  A.winl.assign(static_cast<size_t>(n) * kInline, 0.0);
   A.pfx.clear();
   uint64_t total = 0;
   for (uint32_t u = 0; u < n; ++u) {
     const uint32_t len = static_cast<uint32_t>(start[u + 1] - start[u]);
-    total += len + slack_slots(len, slack);
+    if (len > kInline) total += len + slack_slots(len, slack);
   }
   A.ent.assign(total, Ent{0, 0, 0.0});
   A.w.assign(total, 0.0);
   uint64_t off = 0;
   for (uint32_t u = 0; u < n; ++u) {
     const uint32_t len = static_cast<uint32_t>(start[u + 1] - start[u]);
+    if (len <= kInline) {
+      A.rows[u].h = RowHdr{kInlineOff, len, kInline, 0};
+      for (uint32_t i = 0; i < len; ++i) {
+        A.rows[u].inl[i] = live_ent[start[u] + i];
+        A.winl[static_cast<size_t>(u) * kInline + i] = live_w[start[u] + i];
+      }
+      continue;
+    }
     const uint32_t cap = len + slack_slots(len, slack);
-    A.rows[u] = Row{static_cast<uint32_t>(off), len, cap, 0};
+    A.rows[u].h = RowHdr{static_cast<uint32_t>(off), len, cap, 0};
     std::copy(live_ent.begin() + start[u], live_ent.begin() + start[u + 1], A.ent.begin() + off);
     std::copy(live_w.begin() + start[u], live_w.begin() + start[u + 1], A.w.begin() + off);
     if (len > dyg::kHub) {
@@ -226,9 +250,11 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
   }
 }
 
-uint64_t pool_capacity_for(uint64_t used, uint32_t flags) {
+// Pool capacity for `used` live slots of a graph with n vertices: half again
+// for growth plus room for every vertex to outgrow its inline entries.
+uint64_t pool_capacity_for(uint64_t used, uint32_t n, uint32_t flags) {
   if (flags & DYG_FLAG_LEAN_POOLS) return used + 64;
-  return used + used / 2 + 4096;
+  return used + used / 2 + 4ull * n + 4096;
 }
 
 // Read one device graph back into per-row live lists.
@@ -236,10 +262,12 @@ int download_live(const DevGraph& X, uint32_t n, uint64_t used, std::vector<uint
                   std::vector<Ent>& live_ent, std::vector<double>& live_w, hipStream_t st) {
   std::vector<Row> rows(n);
   std::vector<Ent> ent(used);
-  std::vector<double> w(used);
+  std::vector<double> w(used), winl(static_cast<size_t>(n) * kInline);
   hipError_t e;
   if ((e = hipMemcpyAsync(rows.data(), X.rows, sizeof(Row) * n, hipMemcpyDeviceToHost, st)) !=
           hipSuccess ||
+      (e = hipMemcpyAsync(winl.data(), X.winl, sizeof(double) * winl.size(),
+                          hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (used && (e = hipMemcpyAsync(ent.data(), X.ent, sizeof(Ent) * used, hipMemcpyDeviceToHost,
                                    st)) != hipSuccess) ||
       (used && (e = hipMemcpyAsync(w.data(), X.w, sizeof(double) * used, hipMemcpyDeviceToHost,
@@ -250,12 +278,13 @@ int download_live(const DevGraph& X, uint32_t n, uint64_t used, std::vector<uint
   live_ent.clear();
   live_w.clear();
   for (uint32_t u = 0; u < n; ++u) {
-    const Row r = rows[u];
+    const RowHdr r = rows[u].h;
+    const bool inl = r.off == kInlineOff;
     for (uint32_t i = 0; i < r.len; ++i) {
-      const Ent& x = ent[r.off + i];
+      const Ent& x = inl ? rows[u].inl[i] : ent[r.off + i];
       if (x.qw == 0u) continue;
       live_ent.push_back(x);
-      live_w.push_back(w[r.off + i]);
+      live_w.push_back(inl ? winl[static_cast<size_t>(u) * kInline + i] : w[r.off + i]);
     }
     start[u + 1] = live_ent.size();
   }
@@ -286,7 +315,7 @@ int compact_graph(dyg_ctx* c, int which, uint64_t min_cap) {
   HostAdj A;
   layout(A, c->n, start, le, lw, c->params.slack);
   const uint64_t cap =
-      std::max<uint64_t>(pool_capacity_for(A.ent.size(), c->params.flags), min_cap);
+      std::max<uint64_t>(pool_capacity_for(A.ent.size(), c->n, c->params.flags), min_cap);
   if (cap >= (1ull << 32)) return DYG_E_NOMEM;
   rc = upload_graph(X, c->n, A, cap, c->stream);
   if (rc) return rc;
@@ -451,8 +480,8 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
   for (uint32_t u = 0; u < n; ++u) hstart[u + 1] += hstart[u];
   HostAdj B;
   layout(B, n, hstart, he, hw, params->slack);
-  const uint64_t gcap = pool_capacity_for(A.ent.size(), params->flags);
-  const uint64_t hcap = pool_capacity_for(B.ent.size(), params->flags);
+  const uint64_t gcap = pool_capacity_for(A.ent.size(), n, params->flags);
+  const uint64_t hcap = pool_capacity_for(B.ent.size(), n, params->flags);
   if (gcap >= (1ull << 32) || hcap >= (1ull << 32)) {
     (void)hipStreamDestroy(c->stream);
     delete c;
@@ -462,6 +491,13 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
   if (!rc) rc = upload_graph(c->H, n, B, hcap, c->stream);
   if (!rc) {
     e = hipMalloc(&c->ctl, sizeof(BatchCtl));
+    if (e == hipSuccess) e = hipMalloc(&c->dargs, sizeof(BatchArgs));
+    if (e == hipSuccess) e = hipHostMalloc(&c->hargs, sizeof(BatchArgs), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&c->dargv, sizeof(BatchArgs*));
+    if (e == hipSuccess) {
+      const BatchArgs* p = c->dargs;
+      e = hipMemcpy(c->dargv, &p, sizeof(p), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) rc = fail_hip(e);
   }
   if (!rc) {
@@ -515,11 +551,12 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
   return ok ? DYG_OK : DYG_E_NOMEM;
 }
 
-BatchArgs make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t* iu,
+BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t* iu,
                     const uint32_t* iv, const double* iw, const uint32_t* du, const uint32_t* dv,
                     const uint16_t* s, const uint16_t* L, uint32_t Lcap, uint64_t hadd_cap,
                     uint64_t hash_slots, dyg::UpdRes* res, bool record) {
-  BatchArgs a{};
+  BatchArgs& a = *c->hargs;
+  a = BatchArgs{};
   a.n = c->n;
   a.n_ins = static_cast<uint32_t>(n_ins);
   a.n_del = static_cast<uint32_t>(n_del);
@@ -551,7 +588,11 @@ BatchArgs make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t* 
   a.hadd_cap = static_cast<uint32_t>(hadd_cap);
   a.hash = c->hash.as<HashSlot>();
   a.hash_mask = static_cast<uint32_t>(hash_slots - 1);
+  a.hash_slots = hash_slots;
+  a.g[0] = c->G;
+  a.g[1] = c->H;
   a.ctl = c->ctl;
+  a.qctl = c->ctl;
   for (int g = 0; g < 2; ++g) {
     a.touched_rows[g] = c->touched_rows[g].as<uint32_t>();
     a.touched_k[g] = c->touched_k[g].as<uint32_t>();
@@ -568,22 +609,94 @@ BatchArgs make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t* 
   return a;
 }
 
-void enqueue_pipeline(dyg_ctx* c, const BatchArgs& a, uint64_t hash_slots) {
-  const bool timed = c->ev[0] != nullptr;
-  if (timed) (void)hipEventRecord(c->ev[0], c->stream);
-  dyg::launch_batch_begin(a, c->G, c->H, hash_slots, c->stream);
-  dyg::launch_validate(a, c->G, c->stream);
-  dyg::launch_phase1(a, c->G, c->H, c->stream);
+// Launch geometry of this context's batch `a` alone.
+dyg::Launch single_launch(dyg_ctx* c, const BatchArgs& a) {
+  dyg::Launch L{};
+  L.argv = c->dargv;
+  L.F = 1;
+  L.max_nu = a.n_ins + a.n_del;
+  L.max_ins = a.n_ins;
+  L.max_del = a.n_del;
+  L.max_hadd_cap = a.hadd_cap;
+  L.max_hash_slots = a.hash_slots;
+  L.walk_blocks = c->cus * c->walk_blocks_per_cu;
+  return L;
+}
+
+// The launch sequence of one batch.  `a` gives the grid sizes (the batch
+// itself, or its size class when captured); kernels read the actual batch
+// from device memory.
+void launch_sequence(dyg_ctx* c, const BatchArgs& a, bool timed) {
+  const dyg::Launch L = single_launch(c, a);
+  dyg::launch_batch_begin(L, c->stream);
+  dyg::launch_validate(L, c->stream);
+  dyg::launch_phase1(L, c->stream);
   if (timed) (void)hipEventRecord(c->ev[1], c->stream);
   if (c->params.flags & DYG_FLAG_BATCHED)
-    dyg::launch_walks_queue(a, c->G, c->H, c->cus * c->walk_blocks_per_cu, c->stream);
+    dyg::launch_walks_queue(L, c->stream);
   else
-    dyg::launch_walks(a, c->G, c->H, c->stream);
+    dyg::launch_walks(L, c->stream);
   if (timed) (void)hipEventRecord(c->ev[2], c->stream);
-  dyg::launch_phase4(a, c->G, 0, hash_slots, c->stream);
-  dyg::launch_phase4(a, c->H, 1, hash_slots, c->stream);
+  dyg::launch_phase4(L, 0, c->stream);
+  dyg::launch_phase4(L, 1, c->stream);
+}
+
+uint64_t size_class(uint64_t x) { return x ? next_pow2(x) : 0; }
+
+// Launch sequence of the size class of `a`, captured on first use.
+int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
+  BatchArgs cls = a;
+  cls.n_ins = static_cast<uint32_t>(size_class(a.n_ins));
+  cls.n_del = static_cast<uint32_t>(size_class(a.n_del));
+  cls.hadd_cap = static_cast<uint32_t>(size_class(a.hadd_cap));
+  cls.hash_slots = a.hash_slots;  // cleared by a grid-stride loop: any grid works
+  const uint32_t wb = c->cus * c->walk_blocks_per_cu;
+  const auto key = std::make_tuple(uint64_t(cls.n_ins), uint64_t(cls.n_del),
+                                   uint64_t(cls.hadd_cap), wb);
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    *out = it->second;
+    return DYG_OK;
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return fail_hip(e);
+  launch_sequence(c, cls, false);
+  e = hipStreamEndCapture(c->stream, &graph);
+  if (e != hipSuccess) return fail_hip(e);
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail_hip(e);
+  c->graphs[key] = exec;
+  *out = exec;
+  return DYG_OK;
+}
+
+// Enqueue one batch: copy its arguments to the device, then its launch
+// sequence (directly, or as the captured graph of its size class).
+int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a) {
+  const bool timed = c->ev[0] != nullptr;
+  hipError_t e = hipSuccess;
+  if (timed) (void)hipEventRecord(c->ev[0], c->stream);
+  e = hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return fail_hip(e);
+  if (c->params.flags & DYG_FLAG_GRAPH) {
+    hipGraphExec_t exec = nullptr;
+    int rc = graph_for(c, a, &exec);
+    if (rc) return rc;
+    if ((e = hipGraphLaunch(exec, c->stream)) != hipSuccess) return fail_hip(e);
+    if (timed) {
+      // the walk kernel is inside the graph: time the whole batch only
+      (void)hipEventRecord(c->ev[1], c->stream);
+      (void)hipEventRecord(c->ev[2], c->stream);
+    }
+  } else {
+    launch_sequence(c, a, timed);
+  }
   if (timed) (void)hipEventRecord(c->ev[3], c->stream);
   c->timed_pending = timed && (a.n_ins + a.n_del) > 0;
+  return DYG_OK;
 }
 
 // Fold the events of the batch that just completed into the timers.
@@ -591,12 +704,13 @@ void collect_timing(dyg_ctx* c) {
   if (!c->timed_pending) return;
   c->timed_pending = false;
   float walk = 0.f, batch = 0.f;
-  if (hipEventElapsedTime(&walk, c->ev[1], c->ev[2]) == hipSuccess &&
-      hipEventElapsedTime(&batch, c->ev[0], c->ev[3]) == hipSuccess) {
+  if (hipEventElapsedTime(&batch, c->ev[0], c->ev[3]) != hipSuccess) return;
+  c->batch_ms_last = batch;
+  if (c->params.flags & DYG_FLAG_GRAPH) return;  // the walk kernel is inside the graph
+  if (hipEventElapsedTime(&walk, c->ev[1], c->ev[2]) == hipSuccess) {
     c->walk_launches++;
     c->walk_ms_last = walk;
     c->walk_ms_total += walk;
-    c->batch_ms_last = batch;
   }
 }
 
@@ -607,16 +721,20 @@ int decode_err(unsigned long long key) {
 
 // Finish phase 4 of graphs that ran short of pool slots: grow the pool,
 // then run phase 4 again from the batch's staged additions.
-int repair_nomem(dyg_ctx* c, const BatchArgs& a, uint64_t hash_slots, BatchCtl& ctl) {
+int repair_nomem(dyg_ctx* c, BatchArgs& a, BatchCtl& ctl) {
   for (int attempt = 0; attempt < 4 && (ctl.nomem[0] || ctl.nomem[1]); ++attempt) {
     for (int g = 0; g < 2; ++g) {
       if (!ctl.nomem[g]) continue;
-      DevGraph& X = g ? c->H : c->G;
-      dyg::launch_phase4_reset(a, X, g, c->stream);
+      dyg::launch_phase4_reset(single_launch(c, a), g, c->stream);
       const uint64_t want = ctl.pool_top[g] + ctl.need[g] + ctl.need[g] / 2 + 64;
-      int rc = compact_graph(c, g, want);
+      int rc = compact_graph(c, g, want);  // synchronises the stream
       if (rc) return rc;
-      dyg::launch_phase4(a, X, g, hash_slots, c->stream);
+      a.g[0] = c->G;
+      a.g[1] = c->H;
+      hipError_t e =
+          hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, c->stream);
+      if (e != hipSuccess) return fail_hip(e);
+      dyg::launch_phase4(single_launch(c, a), g, c->stream);
     }
     int rc = sync_ctl_host(c, ctl);
     if (rc) return rc;
@@ -624,11 +742,11 @@ int repair_nomem(dyg_ctx* c, const BatchArgs& a, uint64_t hash_slots, BatchCtl& 
   return (ctl.nomem[0] || ctl.nomem[1]) ? DYG_E_NOMEM : DYG_OK;
 }
 
-// Keep at least a quarter of each pool free between batches.
+// Keep a tenth of each pool free between batches.
 int maybe_compact(dyg_ctx* c) {
   for (int g = 0; g < 2; ++g) {
     const DevGraph& X = g ? c->H : c->G;
-    if (c->pool_top[g] * 4 > X.pool_cap * 3) {
+    if (c->pool_top[g] * 10 > X.pool_cap * 9) {
       int rc = compact_graph(c, g, 0);
       if (rc) return rc;
     }
@@ -701,11 +819,12 @@ extern "C" int dyg_apply_batch(dyg_ctx* c, uint64_t n_ins, const uint32_t* iu,
   if (walkers) put(c->wofs, wofs.data(), 8 * nu);
   if (e != hipSuccess) return fail_hip(e);
 
-  BatchArgs a = make_args(c, n_ins, n_del, c->iu.as<uint32_t>(), c->iv.as<uint32_t>(),
+  BatchArgs& a = make_args(c, n_ins, n_del, c->iu.as<uint32_t>(), c->iv.as<uint32_t>(),
                           c->iw.as<double>(), c->du.as<uint32_t>(), c->dv.as<uint32_t>(),
                           s ? c->s.as<uint16_t>() : nullptr, L ? c->L.as<uint16_t>() : nullptr,
                           Lcap, hadd_cap, hash_slots, c->res.as<dyg::UpdRes>(), walkers != nullptr);
-  enqueue_pipeline(c, a, hash_slots);
+  int prc = enqueue_pipeline(c, a);
+  if (prc) return prc;
   if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e);
 
   BatchCtl ctl;
@@ -715,7 +834,7 @@ extern "C" int dyg_apply_batch(dyg_ctx* c, uint64_t n_ins, const uint32_t* iu,
   rc = decode_err(ctl.err_key);
   if (rc) return rc;
   if (ctl.nomem[0] || ctl.nomem[1]) {
-    rc = repair_nomem(c, a, hash_slots, ctl);
+    rc = repair_nomem(c, a, ctl);
     if (rc) {
       c->broken = true;
       return rc;
@@ -761,14 +880,15 @@ extern "C" int dyg_apply_batch_dev(dyg_ctx* c, const dyg_batch_dev* b, void* str
     return DYG_E_NOMEM;
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
   std::swap(st, c->stream);  // every launcher below runs on the caller's stream
-  BatchArgs a = make_args(c, n_ins, n_del, b->iu, b->iv, b->iw, b->du, b->dv, b->s, b->L, Lcap,
+  BatchArgs& a = make_args(c, n_ins, n_del, b->iu, b->iv, b->iw, b->du, b->dv, b->s, b->L, Lcap,
                           hadd_cap, hash_slots,
                           b->results ? reinterpret_cast<dyg::UpdRes*>(b->results)
                                      : c->res.as<dyg::UpdRes>(),
                           false);
   a.scap = scap;
-  enqueue_pipeline(c, a, hash_slots);
+  int prc = enqueue_pipeline(c, a);
   std::swap(st, c->stream);
+  if (prc) return prc;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_hip(e);
   c->async_inflight = true;
@@ -868,8 +988,8 @@ extern "C" int dyg_stats(dyg_ctx* c, dyg_stats_t* out) {
     if (e != hipSuccess) return fail_hip(e);
     uint64_t live = 0, dead = 0;
     for (const Row& r : rows) {
-      live += r.len - r.dead;
-      dead += r.dead;
+      live += r.h.len - r.h.dead;
+      dead += r.h.dead;
     }
     if (g == 0) {
       out->g_edges = live / 2;
@@ -903,6 +1023,14 @@ struct HostImage {
   std::vector<Ent> ent;
   std::vector<double> w;
   std::vector<unsigned long long> pfx;
+  std::vector<double> winl;
+  const Ent* seg(uint32_t u) const {
+    return rows[u].h.off == kInlineOff ? rows[u].inl : ent.data() + rows[u].h.off;
+  }
+  double wt(uint32_t u, uint32_t i) const {
+    return rows[u].h.off == kInlineOff ? winl[static_cast<size_t>(u) * kInline + i]
+                                       : w[rows[u].h.off + i];
+  }
 };
 
 int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, hipStream_t st) {
@@ -910,7 +1038,11 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
   I.ent.resize(used);
   I.w.resize(used);
   I.pfx.resize(used);
+  I.winl.resize(static_cast<size_t>(n) * kInline);
   hipError_t e = hipMemcpyAsync(I.rows.data(), X.rows, sizeof(Row) * n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(I.winl.data(), X.winl, sizeof(double) * I.winl.size(),
+                       hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && used)
     e = hipMemcpyAsync(I.ent.data(), X.ent, sizeof(Ent) * used, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && used)
@@ -923,15 +1055,15 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
 }
 
 int find_live(const HostImage& I, uint32_t a, uint32_t b) {
-  const Row r = I.rows[a];
+  const RowHdr r = I.rows[a].h;
+  const Ent* seg = I.seg(a);
   uint32_t lo = 0, hi = r.len;
   while (lo < hi) {
     const uint32_t mid = (lo + hi) / 2;
-    if (I.ent[r.off + mid].nbr < b) lo = mid + 1;
+    if (seg[mid].nbr < b) lo = mid + 1;
     else hi = mid;
   }
-  if (lo < r.len && I.ent[r.off + lo].nbr == b && I.ent[r.off + lo].qw != 0u)
-    return static_cast<int>(lo);
+  if (lo < r.len && seg[lo].nbr == b && seg[lo].qw != 0u) return static_cast<int>(lo);
   return -1;
 }
 
@@ -961,21 +1093,25 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
     const HostImage& I = img[g];
     std::vector<std::pair<uint64_t, uint64_t>> spans;
     for (uint32_t u = 0; u < c->n; ++u) {
-      const Row r = I.rows[u];
+      const RowHdr r = I.rows[u].h;
+      const bool inl = r.off == kInlineOff;
       if (r.len > r.cap) return fail("len exceeds cap", g, u, r.len);
-      if (static_cast<uint64_t>(r.off) + r.cap > ctl.pool_top[g])
+      if (inl && r.cap != kInline) return fail("inline row capacity", g, u, r.cap);
+      if (!inl && static_cast<uint64_t>(r.off) + r.cap > ctl.pool_top[g])
         return fail("segment beyond pool top", g, u, r.off);
-      if (r.cap) spans.push_back({r.off, static_cast<uint64_t>(r.off) + r.cap});
+      if (!inl && r.cap) spans.push_back({r.off, static_cast<uint64_t>(r.off) + r.cap});
+      const Ent* seg = I.seg(u);
       uint32_t dead = 0;
       unsigned long long run = 0;
       for (uint32_t i = 0; i < r.len; ++i) {
-        const Ent& e = I.ent[r.off + i];
+        const Ent& e = seg[i];
         if (e.nbr >= c->n || e.nbr == u) return fail("bad neighbour id", g, u, i);
-        if (i && I.ent[r.off + i - 1].nbr >= e.nbr) return fail("segment not sorted", g, u, i);
+        if (i && seg[i - 1].nbr >= e.nbr) return fail("segment not sorted", g, u, i);
         if (e.qw == 0u) ++dead;
         run += e.qw;
-        if (r.len > dyg::kHub && I.pfx[r.off + i] != run) return fail("stale weight prefix", g, u, i);
-        if (e.qw != 0u && !(e.rinv == 1.0 / I.w[r.off + i])) return fail("1/w mismatch", g, u, i);
+        if (!inl && r.len > dyg::kHub && I.pfx[r.off + i] != run)
+          return fail("stale weight prefix", g, u, i);
+        if (e.qw != 0u && !(e.rinv == 1.0 / I.wt(u, i))) return fail("1/w mismatch", g, u, i);
       }
       if (dead != r.dead) {
         if (msg && msg_len)
@@ -989,27 +1125,28 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
     for (size_t i = 1; i < spans.size(); ++i)
       if (spans[i].first < spans[i - 1].second) return fail("overlapping segments", g, i, 0);
     for (uint32_t u = 0; u < c->n; ++u) {
-      const Row r = I.rows[u];
+      const RowHdr r = I.rows[u].h;
+      const Ent* seg = I.seg(u);
       for (uint32_t i = 0; i < r.len; ++i) {
-        const Ent& e = I.ent[r.off + i];
+        const Ent& e = seg[i];
         if (e.qw == 0u) continue;
         const int j = find_live(I, e.nbr, u);
         if (j < 0) return fail("asymmetric edge", g, u, e.nbr);
-        const Ent& f = I.ent[I.rows[e.nbr].off + j];
-        if (f.qw != e.qw || I.w[I.rows[e.nbr].off + j] != I.w[r.off + i])
+        const Ent& f = I.seg(e.nbr)[j];
+        if (f.qw != e.qw || I.wt(e.nbr, j) != I.wt(u, i))
           return fail("asymmetric weight", g, u, e.nbr);
       }
     }
   }
   for (uint32_t u = 0; u < c->n; ++u) {
-    const Row r = img[1].rows[u];
+    const RowHdr r = img[1].rows[u].h;
+    const Ent* seg = img[1].seg(u);
     for (uint32_t i = 0; i < r.len; ++i) {
-      const Ent& e = img[1].ent[r.off + i];
+      const Ent& e = seg[i];
       if (e.qw == 0u) continue;
       const int j = find_live(img[0], u, e.nbr);
       if (j < 0) return fail("H edge missing from G", 1, u, e.nbr);
-      if (img[0].w[img[0].rows[u].off + j] != img[1].w[r.off + i])
-        return fail("H weight differs from G", 1, u, e.nbr);
+      if (img[0].wt(u, j) != img[1].wt(u, i)) return fail("H weight differs from G", 1, u, e.nbr);
     }
   }
   return DYG_OK;
@@ -1052,6 +1189,9 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
   free_graph(c->G);
   free_graph(c->H);
   if (c->ctl) (void)hipFree(c->ctl);
+  if (c->dargs) (void)hipFree(c->dargs);
+  if (c->dargv) (void)hipFree(c->dargv);
+  if (c->hargs) (void)hipHostFree(c->hargs);
   DBuf* bufs[] = {&c->iu, &c->iv, &c->iw, &c->du, &c->dv, &c->s, &c->L, &c->ins_qw,
                   &c->ins_rinv, &c->in_h, &c->res, &c->wrec, &c->wofs, &c->hadd, &c->hash};
   for (DBuf* b : bufs) b->release();
@@ -1068,6 +1208,390 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
   c->pin_out.release();
   for (hipEvent_t ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
+}
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching over many resident graphs.
+
+namespace {
+
+struct ServerRequest {
+  uint64_t id = 0;
+  uint32_t graph = 0;
+  std::vector<uint32_t> iu, iv, du, dv;
+  std::vector<double> iw;
+  dyg_update_result* out = nullptr;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  uint64_t mem = 0;
+  int status = DYG_OK;
+  uint64_t nu() const { return iu.size() + du.size(); }
+};
+
+struct ServerRound {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  BatchCtl* qctl = nullptr;              // shared work-queue control (device)
+  const BatchArgs** argv = nullptr;      // device, kMaxFused entries
+  const BatchArgs** argv_host = nullptr; // pinned staging of argv
+  DBuf items, wres;
+  HBuf pin_out;                          // per request: control block + results
+  std::vector<ServerRequest*> reqs;
+  std::vector<size_t> out_ofs;
+  uint64_t mem = 0;
+  bool busy = false;
+};
+
+}  // namespace
+
+struct dyg_server {
+  dyg_server_params p{};
+  std::vector<dyg_ctx*> graphs;
+  std::vector<std::deque<ServerRequest*>> queues;
+  std::vector<uint8_t> busy;
+  std::vector<ServerRound> rounds;
+  uint64_t mem_in_flight = 0;
+  uint64_t next_id = 1;
+  uint64_t pending = 0;
+  std::deque<dyg_request_done> finished;
+  std::chrono::steady_clock::time_point t0;
+};
+
+namespace {
+
+double server_clock(const dyg_server* s) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+}
+
+// Working memory a batch holds while in flight (device staging, hash, queue
+// items and walker records, phase-4 scratch), for admission.
+uint64_t batch_memory(const dyg_ctx* c, uint64_t n_ins, uint64_t n_del) {
+  const uint64_t nu = n_ins + n_del;
+  const uint64_t L = std::max<uint32_t>(c->params.L_default, 2);
+  const uint64_t hadd = n_ins + n_del * L;
+  const uint64_t items = nu * c->params.s_default;
+  return 32 * nu + sizeof(AddRec) * hadd + 2 * 16 * std::max<uint64_t>(nu, 2 * hadd) +
+         (sizeof(dyg::WalkItem) + sizeof(dyg_walker_record)) * items + 30 * (2 * n_ins + 2 * hadd);
+}
+
+int round_init(ServerRound& r) {
+  hipError_t e = hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&r.qctl, sizeof(BatchCtl));
+  if (e == hipSuccess) e = hipMalloc(&r.argv, sizeof(BatchArgs*) * dyg::kMaxFused);
+  if (e == hipSuccess)
+    e = hipHostMalloc(&r.argv_host, sizeof(BatchArgs*) * dyg::kMaxFused, hipHostMallocDefault);
+  return e == hipSuccess ? DYG_OK : fail_hip(e);
+}
+
+void round_free(ServerRound& r) {
+  if (r.stream) (void)hipStreamSynchronize(r.stream);
+  r.items.release();
+  r.wres.release();
+  r.pin_out.release();
+  if (r.qctl) (void)hipFree(r.qctl);
+  if (r.argv) (void)hipFree(r.argv);
+  if (r.argv_host) (void)hipHostFree(r.argv_host);
+  if (r.done) (void)hipEventDestroy(r.done);
+  if (r.stream) (void)hipStreamDestroy(r.stream);
+  r = ServerRound{};
+}
+
+// Stage request q's batch into its context and fill the context's batch
+// arguments for a fused launch on round r.  Returns the arguments.
+int stage_request(ServerRound& r, ServerRequest* q, dyg_ctx* c, uint64_t item_cap_total,
+                  BatchArgs** out) {
+  const uint64_t n_ins = q->iu.size(), n_del = q->du.size(), nu = n_ins + n_del;
+  const uint32_t Lcap = std::max<uint32_t>(c->params.L_default, 2);
+  uint64_t hadd_cap, hash_slots;
+  if (prepare_buffers(c, n_ins, n_del, Lcap, 0, 0, hadd_cap, hash_slots)) return DYG_E_NOMEM;
+  if (c->params.flags & DYG_FLAG_BATCHED) {
+    // the context's own queue buffers are not used in a fused round
+  }
+  if (!c->iu.ensure(4 * n_ins + 8) || !c->iv.ensure(4 * n_ins + 8) ||
+      !c->iw.ensure(8 * n_ins + 8) || !c->du.ensure(4 * n_del + 8) ||
+      !c->dv.ensure(4 * n_del + 8) || !c->qcount.ensure(4 * nu + 8) ||
+      !c->qofs.ensure(8 * nu + 8) || !c->qtile.ensure(8 * ((nu + 1023) / 1024 + 1) + 8))
+    return DYG_E_NOMEM;
+  const size_t in_bytes = 16 * n_ins + 8 * n_del + 64;
+  if (!c->pin_in.ensure(in_bytes)) return DYG_E_NOMEM;
+  char* h = static_cast<char*>(c->pin_in.p);
+  hipError_t e = hipSuccess;
+  auto put = [&](DBuf& dst, const void* src, size_t bytes) {
+    if (!bytes || e != hipSuccess) return;
+    std::memcpy(h, src, bytes);
+    e = hipMemcpyAsync(dst.p, h, bytes, hipMemcpyHostToDevice, r.stream);
+    h += (bytes + 15) & ~size_t(15);
+  };
+  put(c->iu, q->iu.data(), 4 * n_ins);
+  put(c->iv, q->iv.data(), 4 * n_ins);
+  put(c->iw, q->iw.data(), 8 * n_ins);
+  put(c->du, q->du.data(), 4 * n_del);
+  put(c->dv, q->dv.data(), 4 * n_del);
+  if (e != hipSuccess) return fail_hip(e);
+  BatchArgs& a = make_args(c, n_ins, n_del, c->iu.as<uint32_t>(), c->iv.as<uint32_t>(),
+                           c->iw.as<double>(), c->du.as<uint32_t>(), c->dv.as<uint32_t>(),
+                           nullptr, nullptr, Lcap, hadd_cap, hash_slots,
+                           c->res.as<dyg::UpdRes>(), false);
+  a.qctl = r.qctl;
+  a.items = r.items.as<dyg::WalkItem>();
+  a.wres = r.wres.as<dyg::WalkerRec>();
+  (void)item_cap_total;
+  e = hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, r.stream);
+  if (e != hipSuccess) return fail_hip(e);
+  *out = &a;
+  return DYG_OK;
+}
+
+// Launch round r over its admitted requests.
+int launch_round(dyg_server* s, ServerRound& r) {
+  const uint32_t F = static_cast<uint32_t>(r.reqs.size());
+  uint64_t items = 0;
+  for (ServerRequest* q : r.reqs) items += q->nu() * s->graphs[q->graph]->params.s_default;
+  if (!r.items.ensure(sizeof(dyg::WalkItem) * items + 64) ||
+      !r.wres.ensure(sizeof(dyg_walker_record) * items + 64))
+    return DYG_E_NOMEM;
+  dyg::Launch L{};
+  L.argv = r.argv;
+  L.F = F;
+  L.walk_blocks = s->graphs[r.reqs[0]->graph]->cus * s->p.walk_blocks_per_cu;
+  size_t out_bytes = 0;
+  r.out_ofs.assign(F, 0);
+  for (uint32_t i = 0; i < F; ++i) {
+    r.out_ofs[i] = out_bytes;
+    out_bytes += sizeof(BatchCtl) + sizeof(dyg_update_result) * r.reqs[i]->nu() + 16;
+    out_bytes = (out_bytes + 15) & ~size_t(15);
+  }
+  if (!r.pin_out.ensure(out_bytes + 64)) return DYG_E_NOMEM;
+  for (uint32_t i = 0; i < F; ++i) {
+    ServerRequest* q = r.reqs[i];
+    dyg_ctx* c = s->graphs[q->graph];
+    BatchArgs* a = nullptr;
+    int rc = stage_request(r, q, c, items, &a);
+    if (rc) return rc;
+    r.argv_host[i] = c->dargs;
+    L.max_nu = std::max<uint32_t>(L.max_nu, a->n_ins + a->n_del);
+    L.max_ins = std::max<uint32_t>(L.max_ins, a->n_ins);
+    L.max_del = std::max<uint32_t>(L.max_del, a->n_del);
+    L.max_hadd_cap = std::max<uint64_t>(L.max_hadd_cap, a->hadd_cap);
+    L.max_hash_slots = std::max<uint64_t>(L.max_hash_slots, a->hash_slots);
+  }
+  hipError_t e = hipMemcpyAsync(r.argv, r.argv_host, sizeof(BatchArgs*) * F,
+                                hipMemcpyHostToDevice, r.stream);
+  if (e != hipSuccess) return fail_hip(e);
+  dyg::launch_batch_begin(L, r.stream);
+  dyg::launch_validate(L, r.stream);
+  dyg::launch_phase1(L, r.stream);
+  dyg::launch_walks_queue(L, r.stream);
+  dyg::launch_phase4(L, 0, r.stream);
+  dyg::launch_phase4(L, 1, r.stream);
+  char* o = static_cast<char*>(r.pin_out.p);
+  for (uint32_t i = 0; i < F; ++i) {
+    dyg_ctx* c = s->graphs[r.reqs[i]->graph];
+    e = hipMemcpyAsync(o + r.out_ofs[i], c->ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost,
+                       r.stream);
+    if (e == hipSuccess && r.reqs[i]->nu())
+      e = hipMemcpyAsync(o + r.out_ofs[i] + sizeof(BatchCtl), c->res.p,
+                         sizeof(dyg_update_result) * r.reqs[i]->nu(), hipMemcpyDeviceToHost,
+                         r.stream);
+    if (e != hipSuccess) return fail_hip(e);
+  }
+  if ((e = hipEventRecord(r.done, r.stream)) != hipSuccess) return fail_hip(e);
+  if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e);
+  return DYG_OK;
+}
+
+// A finished round: decide each request, finish pool repairs, report.
+void retire_round(dyg_server* s, ServerRound& r) {
+  const double now = server_clock(s);
+  const char* o = static_cast<const char*>(r.pin_out.p);
+  for (size_t i = 0; i < r.reqs.size(); ++i) {
+    ServerRequest* q = r.reqs[i];
+    dyg_ctx* c = s->graphs[q->graph];
+    BatchCtl ctl;
+    std::memcpy(&ctl, o + r.out_ofs[i], sizeof(BatchCtl));
+    int rc = decode_err(ctl.err_key);
+    if (!rc && (ctl.nomem[0] || ctl.nomem[1])) {
+      // rare: a pool ran short; finish this batch's phase 4 alone
+      rc = repair_nomem(c, *c->hargs, ctl);
+      if (!rc) {
+        const hipError_t e = hipMemcpy(const_cast<char*>(o) + r.out_ofs[i] + sizeof(BatchCtl),
+                                       c->res.p, sizeof(dyg_update_result) * q->nu(),
+                                       hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = fail_hip(e);
+      } else {
+        c->broken = true;
+      }
+    }
+    if (!rc) {
+      c->uid_base += q->nu();
+      c->batches++;
+      c->pool_top[0] = ctl.pool_top[0];
+      c->pool_top[1] = ctl.pool_top[1];
+      if (q->out && q->nu())
+        std::memcpy(q->out, o + r.out_ofs[i] + sizeof(BatchCtl),
+                    sizeof(dyg_update_result) * q->nu());
+      rc = maybe_compact(c);
+    }
+    q->status = rc;
+    q->t_done = now;
+    dyg_request_done d{q->id, q->graph, rc, q->nu(), q->t_submit, q->t_start, q->t_done};
+    s->finished.push_back(d);
+    s->busy[q->graph] = 0;
+    delete q;
+  }
+  s->mem_in_flight -= r.mem;
+  r.mem = 0;
+  r.reqs.clear();
+  r.busy = false;
+}
+
+// Admit the oldest waiting heads of idle graphs into round r.
+void admit(dyg_server* s, ServerRound& r) {
+  std::vector<uint32_t> cand;
+  for (uint32_t g = 0; g < s->graphs.size(); ++g)
+    if (!s->busy[g] && !s->queues[g].empty() && !s->graphs[g]->broken) cand.push_back(g);
+  std::sort(cand.begin(), cand.end(), [&](uint32_t a, uint32_t b) {
+    return s->queues[a].front()->id < s->queues[b].front()->id;
+  });
+  for (uint32_t g : cand) {
+    if (r.reqs.size() >= s->p.max_fused) break;
+    ServerRequest* q = s->queues[g].front();
+    const bool alone = s->mem_in_flight == 0 && r.reqs.empty();
+    if (!alone && s->mem_in_flight + r.mem + q->mem > s->p.mem_budget) continue;
+    s->queues[g].pop_front();
+    s->busy[g] = 1;
+    r.reqs.push_back(q);
+    r.mem += q->mem;
+  }
+}
+
+}  // namespace
+
+extern "C" void dyg_server_default_params(dyg_server_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->mem_budget = 8ull << 30;
+  p->max_fused = 32;
+  p->max_inflight = 2;
+  p->walk_blocks_per_cu = 4;
+}
+
+extern "C" int dyg_server_create(dyg_server** out, const dyg_server_params* p) {
+  if (!out || !p || p->max_fused < 1 || p->max_fused > dyg::kMaxFused || p->max_inflight < 1 ||
+      p->max_inflight > 8 || p->walk_blocks_per_cu < 1 || p->walk_blocks_per_cu > 64)
+    return DYG_E_INVALID_ARG;
+  dyg_server* s = new (std::nothrow) dyg_server();
+  if (!s) return DYG_E_NOMEM;
+  s->p = *p;
+  s->t0 = std::chrono::steady_clock::now();
+  s->rounds.resize(p->max_inflight);
+  for (ServerRound& r : s->rounds) {
+    int rc = round_init(r);
+    if (rc) {
+      dyg_server_destroy(s);
+      return rc;
+    }
+  }
+  *out = s;
+  return DYG_OK;
+}
+
+extern "C" int dyg_server_add_graph(dyg_server* s, dyg_ctx* ctx, uint32_t* graph_id) {
+  if (!s || !ctx || !graph_id) return DYG_E_INVALID_ARG;
+  if (ctx->async_inflight) {
+    int rc = dyg_sync(ctx);
+    if (rc) return rc;
+  }
+  *graph_id = static_cast<uint32_t>(s->graphs.size());
+  s->graphs.push_back(ctx);
+  s->queues.emplace_back();
+  s->busy.push_back(0);
+  return DYG_OK;
+}
+
+extern "C" int dyg_server_submit(dyg_server* s, uint32_t graph_id, uint64_t n_ins,
+                                 const uint32_t* iu, const uint32_t* iv, const double* iw,
+                                 uint64_t n_del, const uint32_t* du, const uint32_t* dv,
+                                 dyg_update_result* results, uint64_t* request_id) {
+  if (!s || graph_id >= s->graphs.size()) return DYG_E_INVALID_ARG;
+  if ((n_ins && (!iu || !iv || !iw)) || (n_del && (!du || !dv))) return DYG_E_INVALID_ARG;
+  if (n_ins + n_del >= (1ull << 30)) return DYG_E_INVALID_ARG;
+  ServerRequest* q = new (std::nothrow) ServerRequest();
+  if (!q) return DYG_E_NOMEM;
+  q->id = s->next_id++;
+  q->graph = graph_id;
+  q->iu.assign(iu, iu + n_ins);
+  q->iv.assign(iv, iv + n_ins);
+  q->iw.assign(iw, iw + n_ins);
+  q->du.assign(du, du + n_del);
+  q->dv.assign(dv, dv + n_del);
+  q->out = results;
+  q->t_submit = server_clock(s);
+  q->mem = batch_memory(s->graphs[graph_id], n_ins, n_del);
+  s->queues[graph_id].push_back(q);
+  s->pending++;
+  if (request_id) *request_id = q->id;
+  return DYG_OK;
+}
+
+extern "C" int dyg_server_poll(dyg_server* s, dyg_request_done* done, uint32_t cap,
+                               uint32_t* n_done) {
+  if (!s) return DYG_E_INVALID_ARG;
+  for (ServerRound& r : s->rounds) {
+    if (!r.busy) continue;
+    const hipError_t e = hipEventQuery(r.done);
+    if (e == hipErrorNotReady) continue;
+    if (e != hipSuccess) return fail_hip(e);
+    retire_round(s, r);
+  }
+  for (ServerRound& r : s->rounds) {
+    if (r.busy) continue;
+    admit(s, r);
+    if (r.reqs.empty()) break;
+    const double now = server_clock(s);
+    for (ServerRequest* q : r.reqs) q->t_start = now;
+    s->mem_in_flight += r.mem;
+    r.busy = true;
+    int rc = launch_round(s, r);
+    if (rc) {
+      (void)hipStreamSynchronize(r.stream);
+      for (ServerRequest* q : r.reqs) {
+        q->status = rc;
+        q->t_done = server_clock(s);
+        s->finished.push_back(
+            dyg_request_done{q->id, q->graph, rc, q->nu(), q->t_submit, q->t_start, q->t_done});
+        s->busy[q->graph] = 0;
+        delete q;
+      }
+      s->mem_in_flight -= r.mem;
+      r.mem = 0;
+      r.reqs.clear();
+      r.busy = false;
+      return rc;
+    }
+  }
+  uint32_t k = 0;
+  while (k < cap && !s->finished.empty()) {
+    if (done) done[k] = s->finished.front();
+    s->finished.pop_front();
+    ++k;
+    s->pending--;
+  }
+  if (n_done) *n_done = k;
+  return DYG_OK;
+}
+
+extern "C" uint64_t dyg_server_pending(const dyg_server* s) { return s ? s->pending : 0; }
+
+extern "C" double dyg_server_now(const dyg_server* s) { return s ? server_clock(s) : 0.0; }
+
+extern "C" void dyg_server_destroy(dyg_server* s) {
+  if (!s) return;
+  for (ServerRound& r : s->rounds) round_free(r);
+  for (auto& qd : s->queues)
+    for (ServerRequest* q : qd) delete q;
+  delete s;
 }

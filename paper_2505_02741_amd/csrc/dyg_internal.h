@@ -10,27 +10,39 @@ namespace dyg {
 // ---------------------------------------------------------------------------
 // Device adjacency of one graph (the original graph G or the sparsifier H).
 //
-// Every vertex owns a contiguous segment of an entry pool: `len` entries in
-// ascending neighbour order followed by `cap - len` free slots (per-node
-// slack).  A deleted edge stays in place as a tombstone (qw == 0) until the
-// segment is relocated or compacted; a zero weight never wins the cumulative
-// search, so walks skip tombstones without testing them.  Neighbour ids are
-// unique within a segment (a re-inserted edge revives its tombstone).
-struct Row {
-  uint32_t off;   // first entry in the pool
-  uint32_t len;   // entries in use, tombstones included
-  uint32_t cap;   // slots owned
-  uint32_t dead;  // tombstones among the len entries
-};
-
+// Every vertex has a 64-byte row: a header and room for kInline entries.  A
+// vertex with at most kInline neighbours keeps them inside its row (one cache
+// line per walk step); a longer one owns a segment of the entry pool: `len`
+// entries in ascending neighbour order followed by `cap - len` free slots
+// (per-node slack).  A deleted edge stays in place as a tombstone (qw == 0)
+// until its segment is relocated or compacted; a zero weight never wins the
+// cumulative search, so walks skip tombstones without testing them.
+// Neighbour ids are unique within a row (a re-inserted edge revives its
+// tombstone).
 struct Ent {
   uint32_t nbr;  // neighbour id
   uint32_t qw;   // quantised weight, 0 = tombstone
   double rinv;   // resistance 1/w
 };
 
-static_assert(sizeof(Row) == 16, "Row layout");
+constexpr uint32_t kInline = 3;              // entries stored inside the row
+constexpr uint32_t kInlineOff = 0xFFFFFFFFu;  // `off` of a row whose entries are inline
+
+struct RowHdr {
+  uint32_t off;   // first pool entry, or kInlineOff
+  uint32_t len;   // entries in use, tombstones included
+  uint32_t cap;   // slots owned (kInline for an inline row)
+  uint32_t dead;  // tombstones among the len entries
+};
+
+struct Row {
+  RowHdr h;
+  Ent inl[kInline];
+};
+
+static_assert(sizeof(RowHdr) == 16, "RowHdr layout");
 static_assert(sizeof(Ent) == 16, "Ent layout");
+static_assert(sizeof(Row) == 64, "Row layout");
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 // Segments longer than this keep an inclusive prefix of their quantised
@@ -40,9 +52,10 @@ constexpr uint32_t kMaxWalkers = 1024;
 constexpr uint32_t kMaxSteps = 1024;
 
 struct DevGraph {
-  Row* rows = nullptr;        // [n]
+  Row* rows = nullptr;        // [n] 64-byte rows
   Ent* ent = nullptr;         // [pool_cap]
-  double* w = nullptr;        // [pool_cap] weight of each entry (cold)
+  double* w = nullptr;        // [pool_cap] weight of each pool entry (cold)
+  double* winl = nullptr;     // [n * kInline] weight of each inline entry (cold)
   uint32_t* pending = nullptr;  // [n] per-row counter, zero between batches
   unsigned long long* pfx = nullptr;  // [pool_cap] inclusive qw prefix (rows with len > kHub)
   uint32_t* mark = nullptr;     // [n] "prefix needs rebuilding" flag, zero between uses
@@ -58,11 +71,16 @@ struct AddRec {
 };
 static_assert(sizeof(AddRec) == 32, "AddRec layout");
 
+// Walker index bits of WalkItem::walker; the bits above hold the batch (0..63)
+// when several batches share one queue.
+constexpr uint32_t kWalkerBits = 10;
+constexpr uint32_t kMaxFused = 64;
+
 // One walker of the batched form's work queue.
 struct WalkItem {
   uint32_t p, q;    // start vertex, target
   uint32_t upd;     // update index in the batch (insertions first)
-  uint16_t walker;  // walker index within the update
+  uint16_t walker;  // walker index within the update | batch << kWalkerBits
   uint16_t L;       // step limit
   double w_pq;      // inserted edge weight (threshold test), 0 for deletions
 };
@@ -95,8 +113,9 @@ struct BatchCtl {
   uint32_t nomem[2];            // phase-4 pool shortfall, per graph
   uint32_t dirty[2];            // rows whose prefix must be rebuilt, per graph
   unsigned long long pool_top[2];  // next free pool slot, per graph
-  unsigned long long walk_items;       // walkers queued this batch
-  unsigned long long queue_next;       // next queue item to hand out
+  unsigned long long walk_items;       // walkers queued (queue control only)
+  unsigned long long queue_next;       // next queue item to hand out (queue control only)
+  unsigned long long item_base;        // first queue item of this batch
   // cumulative over the context's life (never reset by a batch)
   unsigned long long steps_total;      // walker steps taken
   unsigned long long alg_bytes_total;  // algorithmic gathered bytes of those steps
@@ -138,7 +157,10 @@ struct BatchArgs {
   uint32_t hadd_cap;
   HashSlot* hash;
   uint32_t hash_mask;
+  uint64_t hash_slots;
+  DevGraph g[2];              // 0 = G, 1 = H
   BatchCtl* ctl;
+  BatchCtl* qctl;  // work-queue control shared by the batches of one launch
   // per-graph phase-4 scratch
   uint32_t* touched_rows[2];  // [add capacity]
   uint32_t* touched_k[2];
@@ -154,21 +176,28 @@ struct BatchArgs {
   WalkerRec* wres;               // [items] outcome of each walker
 };
 
+// One launch of F batches (F = 1 for a single context; up to kMaxFused when a
+// serving round fuses batches of different graphs).
+struct Launch {
+  const BatchArgs* const* argv;  // device array of F pointers to device BatchArgs
+  uint32_t F;
+  uint32_t max_nu, max_ins, max_del;  // largest batch of the launch (grid sizes)
+  uint64_t max_hadd_cap, max_hash_slots;
+  uint32_t walk_blocks;               // persistent walk grid
+};
+
 // Host-side launchers (defined in dyg_kernels.hip), all asynchronous on
 // `stream`.
-void launch_batch_begin(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
-                        uint64_t hash_slots, hipStream_t stream);
-void launch_validate(const BatchArgs& a, const DevGraph& G, hipStream_t stream);
-void launch_phase1(const BatchArgs& a, DevGraph& G, DevGraph& H, hipStream_t stream);
-void launch_walks(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
-                  hipStream_t stream);
+void launch_batch_begin(const Launch& L, hipStream_t stream);
+void launch_validate(const Launch& L, hipStream_t stream);
+void launch_phase1(const Launch& L, hipStream_t stream);
+// Plain form: one wavefront per update.
+void launch_walks(const Launch& L, hipStream_t stream);
+// Batched form: count, scan, expand, one persistent queue walk over every
+// walker of the F batches, per-update reduction.
+void launch_walks_queue(const Launch& L, hipStream_t stream);
 // Phase 4 on one graph (which = 0: G += insertions, 1: H += hadd records).
-void launch_phase4(const BatchArgs& a, DevGraph& X, int which, uint64_t hash_slots,
-                   hipStream_t stream);
-void launch_batch_end(const BatchArgs& a, hipStream_t stream);
-// Batched form of the walks: count, scan, expand, persistent queue walk
-// (walk_blocks workgroups of 256), per-update reduction.
-void launch_walks_queue(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
-                        uint32_t walk_blocks, hipStream_t stream);
+void launch_phase4(const Launch& L, int which, hipStream_t stream);
+void launch_phase4_reset(const Launch& L, int which, hipStream_t stream);
 
 }  // namespace dyg

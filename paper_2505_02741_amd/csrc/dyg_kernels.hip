@@ -48,12 +48,30 @@ __device__ __forceinline__ unsigned long long edge_key(uint32_t a, uint32_t b) {
   return (static_cast<unsigned long long>(lo) << 32) | hi;
 }
 
-// Index of neighbour v in the segment of r (tombstones included), or -1.
-__device__ __forceinline__ int find_nbr(const Ent* ent, Row r, uint32_t v) {
-  int lo = 0, hi = static_cast<int>(r.len) - 1;
+// Header of row u.
+__device__ __forceinline__ RowHdr row_hdr(const DevGraph& X, uint32_t u) {
+  return X.rows[u].h;
+}
+
+__device__ __forceinline__ RowHdr& row_hdr_ref(const DevGraph& X, uint32_t u) {
+  return X.rows[u].h;
+}
+
+// Entries of row u (inline or in the pool) and their weights.
+__device__ __forceinline__ Ent* seg_of(const DevGraph& X, uint32_t u, uint32_t off) {
+  return off == kInlineOff ? X.rows[u].inl : X.ent + off;
+}
+
+__device__ __forceinline__ double* wseg_of(const DevGraph& X, uint32_t u, uint32_t off) {
+  return off == kInlineOff ? X.winl + static_cast<uint64_t>(u) * kInline : X.w + off;
+}
+
+// Index of neighbour v among seg[0..len) (tombstones included), or -1.
+__device__ __forceinline__ int find_nbr(const Ent* seg, uint32_t len, uint32_t v) {
+  int lo = 0, hi = static_cast<int>(len) - 1;
   while (lo <= hi) {
     const int mid = (lo + hi) >> 1;
-    const uint32_t x = ent[r.off + mid].nbr;
+    const uint32_t x = seg[mid].nbr;
     if (x == v) return mid;
     if (x < v) lo = mid + 1;
     else hi = mid - 1;
@@ -61,11 +79,11 @@ __device__ __forceinline__ int find_nbr(const Ent* ent, Row r, uint32_t v) {
   return -1;
 }
 
-__device__ __forceinline__ bool has_live(const Row* rows, const Ent* ent, uint32_t a,
-                                         uint32_t b) {
-  const Row r = rows[a];
-  const int k = find_nbr(ent, r, b);
-  return k >= 0 && ent[r.off + k].qw != 0u;
+__device__ __forceinline__ bool has_live(const DevGraph& X, uint32_t a, uint32_t b) {
+  const RowHdr h = row_hdr(X, a);
+  const Ent* seg = seg_of(X, a, h.off);
+  const int k = find_nbr(seg, h.len, b);
+  return k >= 0 && seg[k].qw != 0u;
 }
 
 // ---- hash table (validation duplicates, phase-4 dedup) ---------------------
@@ -120,8 +138,16 @@ __device__ bool hash_insert_first(HashSlot* h, uint32_t mask, unsigned long long
 
 // ---- begin ------------------------------------------------------------------
 
-__global__ void k_batch_begin(BatchCtl* ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+// One workgroup per batch resets that batch's control block; the first also
+// resets the work-queue control the batches share.
+__global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
+  BatchCtl* ctl = argv[blockIdx.y]->ctl;
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
+    BatchCtl* q = argv[0]->qctl;
+    q->walk_items = 0;
+    q->queue_next = 0;
+  }
+  if (threadIdx.x == 0) {
     ctl->err_key = ~0ull;
     ctl->hadd_count = 0;
     ctl->touched[0] = ctl->touched[1] = 0;
@@ -131,7 +157,9 @@ __global__ void k_batch_begin(BatchCtl* ctl) {
   }
 }
 
-__global__ void k_clear_hash(HashSlot* h, uint64_t slots) {
+__global__ void k_clear_hash(const BatchArgs* const* __restrict__ argv) {
+  HashSlot* h = argv[blockIdx.y]->hash;
+  const uint64_t slots = argv[blockIdx.y]->hash_slots;
   for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < slots;
        i += uint64_t(gridDim.x) * blockDim.x) {
     h[i].key = ~0ull;
@@ -143,7 +171,8 @@ __global__ void k_clear_hash(HashSlot* h, uint64_t slots) {
 
 constexpr unsigned long long kDelTag = 1ull << 63;  // n < 2^31 keeps bit 63 free
 
-__global__ void k_validate_a(BatchArgs a) {
+__global__ void k_validate_a(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_ins + a.n_del) return;
   if (i < a.n_ins) {
@@ -171,7 +200,9 @@ __device__ __forceinline__ uint32_t quantize(double w, double w_ref, int Q) {
   return static_cast<uint32_t>(y);
 }
 
-__global__ void k_validate_b(BatchArgs a, const Row* grows, const Ent* gent) {
+__global__ void k_validate_b(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& G = a.g[0];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_ins + a.n_del) return;
   if (i < a.n_ins) {
@@ -181,7 +212,7 @@ __global__ void k_validate_b(BatchArgs a, const Row* grows, const Ent* gent) {
     if (u >= a.n || v >= a.n) code = E_VERTEX_RANGE;
     else if (u == v) code = E_SELF_LOOP;
     else if (!(w > 0.0) || isinf(w)) code = E_BAD_WEIGHT;
-    else if (has_live(grows, gent, u, v)) code = E_EDGE_EXISTS;
+    else if (has_live(G, u, v)) code = E_EDGE_EXISTS;
     else if (hash_min_of(a.hash, a.hash_mask, edge_key(u, v)) < i) code = E_DUPLICATE;
     if (code) report(a.ctl, 0, i, code);
     else {
@@ -194,7 +225,7 @@ __global__ void k_validate_b(BatchArgs a, const Row* grows, const Ent* gent) {
     int code = 0;
     if (u >= a.n || v >= a.n) code = E_VERTEX_RANGE;
     else if (u == v) code = E_SELF_LOOP;
-    else if (!has_live(grows, gent, u, v)) code = E_EDGE_MISSING;
+    else if (!has_live(G, u, v)) code = E_EDGE_MISSING;
     else if (hash_min_of(a.hash, a.hash_mask, edge_key(u, v) | kDelTag) < j) code = E_DUPLICATE;
     if (code) report(a.ctl, 1, j, code);
   }
@@ -215,22 +246,26 @@ __device__ __forceinline__ void mark_dirty(const BatchArgs& a, const DevGraph& X
   }
 }
 
-__device__ __forceinline__ void tombstone(const BatchArgs& a, DevGraph X, int which, uint32_t u,
-                                          uint32_t v) {
-  const Row r = X.rows[u];
-  const int k = find_nbr(X.ent, r, v);
+__device__ __forceinline__ void tombstone(const BatchArgs& a, const DevGraph& X, int which,
+                                          uint32_t u, uint32_t v) {
+  const RowHdr h = row_hdr(X, u);
+  Ent* seg = seg_of(X, u, h.off);
+  const int k = find_nbr(seg, h.len, v);
   if (k < 0) return;
-  X.ent[r.off + k].qw = 0u;
-  atomicAdd(&X.rows[u].dead, 1u);
-  if (r.len > kHub) mark_dirty(a, X, which, u);
+  seg[k].qw = 0u;
+  atomicAdd(&row_hdr_ref(X, u).dead, 1u);
+  if (h.len > kHub) mark_dirty(a, X, which, u);
 }
 
-__global__ void k_phase1(BatchArgs a, DevGraph G, DevGraph H) {
+__global__ void k_phase1(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& G = a.g[0];
+  const DevGraph& H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n_del) return;
   const uint32_t u = a.du[j], v = a.dv[j];
-  const bool in_h = has_live(H.rows, H.ent, u, v);
+  const bool in_h = has_live(H, u, v);
   tombstone(a, G, 0, u, v);
   tombstone(a, G, 0, v, u);
   if (in_h) {
@@ -245,12 +280,14 @@ __device__ unsigned long long block_excl_scan(unsigned long long v, unsigned lon
 
 // Rebuild the inclusive weight prefix of every dirty row (one workgroup per
 // row), then clear its mark.
-__global__ __launch_bounds__(kBlock) void k_hub_prefix(BatchArgs a, DevGraph X, int which) {
+__global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t count = a.ctl->dirty[which];
   for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
     const uint32_t r = a.dirty_rows[which][t];
-    const Row row = X.rows[r];
+    const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment
     unsigned long long carry = 0;
     for (uint32_t base = 0; base < row.len; base += kBlock) {
       const uint32_t i = base + threadIdx.x;
@@ -264,8 +301,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_prefix(BatchArgs a, DevGraph X, 
   }
 }
 
-__global__ void k_dirty_reset(BatchCtl* ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->dirty[0] = ctl->dirty[1] = 0;
+__global__ void k_dirty_reset(const BatchArgs* const* __restrict__ argv) {
+  BatchCtl* ctl = argv[blockIdx.y]->ctl;
+  if (threadIdx.x == 0) ctl->dirty[0] = ctl->dirty[1] = 0;
 }
 
 // ---- walks ------------------------------------------------------------------------
@@ -301,7 +339,7 @@ struct WalkParams {
 
 // Emits nothing; the replay variant below passes an edge sink.
 struct NoSink {
-  __device__ __forceinline__ void operator()(uint32_t, uint32_t, const Ent&, uint32_t) const {}
+  __device__ __forceinline__ void operator()(uint32_t, uint32_t, uint32_t, uint32_t) const {}
 };
 
 // State of one walker between steps.
@@ -322,88 +360,116 @@ __device__ __forceinline__ void walker_start(WState& S, uint32_t p) {
   S.hit = false;
 }
 
+__device__ __forceinline__ unsigned long long step_random(WState& S, const WalkParams& P,
+                                                          uint32_t walker, uint32_t t) {
+  if (S.block_of != (t >> 1)) {
+    S.rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
+    S.block_of = t >> 1;
+  }
+  return (t & 1u) ? (uint64_t(S.rnd.x2) | (uint64_t(S.rnd.x3) << 32))
+                  : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
+}
+
 // One step of a walker: weight-biased choice among the neighbours other than
 // the previous vertex; stop on the distortion threshold, on reaching q, at a
 // dead end or after L steps (Sec. III-B).  Returns false once the walker has
-// stopped (then S holds its final state).
+// stopped (then S holds its final state).  The whole 64-byte row is loaded at
+// once: for a vertex with at most kInline neighbours that is the only memory
+// access of the step.
 template <class Sink>
 __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
                                           Sink sink) {
   const uint32_t t = S.steps;
   if (t >= P.L) return false;
-  const Row r = P.rows[S.x];
-  uint32_t pick;
-  if (r.len > kHub) {
+  const uint4* rq = reinterpret_cast<const uint4*>(P.rows + S.x);
+  const uint4 q0 = rq[0], q1 = rq[1], q2 = rq[2], q3 = rq[3];
+  const RowHdr h{q0.x, q0.y, q0.z, q0.w};
+  uint32_t pick_nbr, pick_idx;
+  double pick_r;
+  if (h.off == kInlineOff) {
+    // inline entries: (nbr, qw, 1/w) in q1..q3
+    const uint32_t w0 = (h.len > 0 && q1.x != S.prev) ? q1.y : 0u;
+    const uint32_t w1 = (h.len > 1 && q2.x != S.prev) ? q2.y : 0u;
+    const uint32_t w2 = (h.len > 2 && q3.x != S.prev) ? q3.y : 0u;
+    const unsigned long long tot = uint64_t(w0) + w1 + w2;
+    if (tot == 0) {
+      if (!(P.bounce && S.prev != kNone)) return false;  // leaf: the walker stops
+      // step back along the edge just used
+      if (h.len > 0 && q1.x == S.prev) pick_idx = 0;
+      else if (h.len > 1 && q2.x == S.prev) pick_idx = 1;
+      else if (h.len > 2 && q3.x == S.prev) pick_idx = 2;
+      else return false;  // cannot happen: the edge just used is live
+    } else {
+      const unsigned long long target = __umul64hi(step_random(S, P, walker, t), tot);
+      pick_idx = (w0 > target) ? 0u : ((uint64_t(w0) + w1 > target) ? 1u : 2u);
+    }
+    const uint4 qe = pick_idx == 0 ? q1 : (pick_idx == 1 ? q2 : q3);
+    pick_nbr = qe.x;
+    pick_r = __hiloint2double(static_cast<int>(qe.w), static_cast<int>(qe.z));
+  } else if (h.len > kHub) {
     // long segment: the candidates' running sums are the stored prefix with
     // the previous vertex's weight taken out
-    const unsigned long long* pf = P.pfx + r.off;
+    const Ent* seg = P.ent + h.off;
+    const unsigned long long* pf = P.pfx + h.off;
     int jp = -1;
     uint32_t qprev = 0;
     if (S.prev != kNone) {
-      jp = find_nbr(P.ent, r, S.prev);
-      if (jp >= 0) qprev = P.ent[r.off + jp].qw;
+      jp = find_nbr(seg, h.len, S.prev);
+      if (jp >= 0) qprev = seg[jp].qw;
     }
-    const unsigned long long tot = pf[r.len - 1] - qprev;
+    const unsigned long long tot = pf[h.len - 1] - qprev;
     if (tot == 0) {
       if (!(P.bounce && jp >= 0)) return false;
-      pick = static_cast<uint32_t>(jp);
+      pick_idx = static_cast<uint32_t>(jp);
     } else {
-      if (S.block_of != (t >> 1)) {
-        S.rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
-        S.block_of = t >> 1;
-      }
-      const unsigned long long r64 =
-          (t & 1u) ? (uint64_t(S.rnd.x2) | (uint64_t(S.rnd.x3) << 32))
-                   : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
-      unsigned long long target = __umul64hi(r64, tot);
+      unsigned long long target = __umul64hi(step_random(S, P, walker, t), tot);
       if (jp >= 0 && target >= pf[jp] - qprev) target += qprev;
-      uint32_t lo = 0, hi = r.len - 1;  // first i with pf[i] > target
+      uint32_t lo = 0, hi = h.len - 1;  // first i with pf[i] > target
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (pf[mid] > target) hi = mid;
         else lo = mid + 1;
       }
-      pick = lo;
+      pick_idx = lo;
     }
+    const Ent ce = seg[pick_idx];
+    pick_nbr = ce.nbr;
+    pick_r = ce.rinv;
   } else {
-    const uint2* e2 = reinterpret_cast<const uint2*>(P.ent + r.off);  // (nbr, qw) pairs
+    const Ent* seg = P.ent + h.off;
+    const uint2* e2 = reinterpret_cast<const uint2*>(seg);  // (nbr, qw) pairs
     unsigned long long tot = 0;
-    for (uint32_t i = 0; i < r.len; ++i) {
+    for (uint32_t i = 0; i < h.len; ++i) {
       const uint2 e = e2[2 * i];
       tot += (e.x != S.prev) ? e.y : 0u;
     }
     if (tot == 0) {
       if (!(P.bounce && S.prev != kNone)) return false;  // leaf: the walker stops
-      const int back = find_nbr(P.ent, r, S.prev);
+      const int back = find_nbr(seg, h.len, S.prev);
       if (back < 0) return false;  // cannot happen: the edge just used is live
-      pick = static_cast<uint32_t>(back);
+      pick_idx = static_cast<uint32_t>(back);
     } else {
-      if (S.block_of != (t >> 1)) {
-        S.rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
-        S.block_of = t >> 1;
-      }
-      const unsigned long long r64 =
-          (t & 1u) ? (uint64_t(S.rnd.x2) | (uint64_t(S.rnd.x3) << 32))
-                   : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
-      const unsigned long long target = __umul64hi(r64, tot);
+      const unsigned long long target = __umul64hi(step_random(S, P, walker, t), tot);
       unsigned long long run = 0;
-      pick = r.len - 1;
-      for (uint32_t i = 0; i < r.len; ++i) {
+      pick_idx = h.len - 1;
+      for (uint32_t i = 0; i < h.len; ++i) {
         const uint2 e = e2[2 * i];
         run += (e.x != S.prev) ? e.y : 0u;
         if (run > target) {
-          pick = i;
+          pick_idx = i;
           break;
         }
       }
     }
+    const Ent ce = seg[pick_idx];
+    pick_nbr = ce.nbr;
+    pick_r = ce.rinv;
   }
-  const Ent ce = P.ent[r.off + pick];
-  S.bytes += step_bytes(r.len - r.dead);
-  S.R = S.R + ce.rinv;
-  sink(S.x, ce.nbr, ce, r.off + pick);
+  S.bytes += step_bytes(h.len - h.dead);
+  S.R = S.R + pick_r;
+  sink(S.x, pick_nbr, pick_idx, h.off);
   S.prev = S.x;
-  S.x = ce.nbr;
+  S.x = pick_nbr;
   S.steps = t + 1;
   if (P.use_K && P.w_pq * S.R > P.K) return false;
   if (S.x == P.q) {
@@ -449,19 +515,20 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 
 // Sink of the winner replay: path edges absent from H_mid, first occurrence.
 struct RecoverSink {
-  const Row* hrows;
-  const Ent* hent;
-  const double* gw;
+  const DevGraph* G;
+  const DevGraph* H;
   AddRec* out;  // reserved block of `cap` records
   uint32_t cap;
   uint32_t* count;
-  __device__ void operator()(uint32_t a, uint32_t b, const Ent& e, uint32_t pos) const {
-    if (has_live(hrows, hent, a, b)) return;
-    const unsigned long long k = edge_key(a, b);
+  // edge x -> y is entry i of x's row in G (off: that row's pool offset)
+  __device__ void operator()(uint32_t x, uint32_t y, uint32_t i, uint32_t off) const {
+    if (has_live(*H, x, y)) return;
+    const unsigned long long k = edge_key(x, y);
     for (uint32_t z = 0; z < *count; ++z)
       if (edge_key(out[z].a, out[z].b) == k) return;
     if (*count >= cap) return;
-    out[*count] = AddRec{a, b, e.qw, 0u, e.rinv, gw[pos]};
+    const Ent e = seg_of(*G, x, off)[i];
+    out[*count] = AddRec{x, y, e.qw, 0u, e.rinv, wseg_of(*G, x, off)[i]};
     ++*count;
   }
 };
@@ -546,27 +613,29 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
   if (base + cap <= a.hadd_cap) {
     AddRec* out = a.hadd + base;
     if (any_hit) {
-      RecoverSink sink{H.rows, H.ent, G.w, out, cap, &count};
+      RecoverSink sink{&G, &H, out, cap, &count};
       walk_one(P, bestW, sink);  // replay: same counters, same snapshot
     } else {
       // no hit: per endpoint the least-resistance G edge not in H
       const uint32_t ends[2] = {P.p, P.q};
       for (int z = 0; z < 2; ++z) {
-        const Row r = G.rows[ends[z]];
+        const RowHdr r = row_hdr(G, ends[z]);
+        const Ent* seg = seg_of(G, ends[z], r.off);
         int best = -1;
         double bestr = 0.0;
         for (uint32_t i = 0; i < r.len; ++i) {
-          const Ent e = G.ent[r.off + i];
+          const Ent e = seg[i];
           if (e.qw == 0u) continue;
-          if (has_live(H.rows, H.ent, ends[z], e.nbr)) continue;
+          if (has_live(H, ends[z], e.nbr)) continue;
           if (best < 0 || e.rinv < bestr) {
             best = static_cast<int>(i);
             bestr = e.rinv;
           }
         }
         if (best >= 0) {
-          const Ent e = G.ent[r.off + best];
-          out[count++] = AddRec{ends[z], e.nbr, e.qw, 0u, e.rinv, G.w[r.off + best]};
+          const Ent e = seg[best];
+          out[count++] = AddRec{ends[z], e.nbr, e.qw, 0u, e.rinv,
+                                wseg_of(G, ends[z], r.off)[best]};
         }
       }
     }
@@ -578,7 +647,10 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
 
 // Plain form: one wavefront per update, one lane per walker (more walkers
 // than lanes run in successive rounds of 64).
-__global__ __launch_bounds__(kWalkBlock) void k_walks(BatchArgs a, DevGraph G, DevGraph H) {
+__global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& G = a.g[0];
+  const DevGraph& H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + threadIdx.x / kWave;
@@ -625,7 +697,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(BatchArgs a, DevGraph G, D
 // ---- batched form: walker work queue ----------------------------------------
 
 // Walkers per update once phase 1 is known.
-__global__ void k_count_walkers(BatchArgs a, DevGraph G, DevGraph H) {
+__global__ void k_count_walkers(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
   if (batch_failed(a.ctl)) return;
   const uint32_t upd = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nu = a.n_ins + a.n_del;
@@ -665,7 +738,8 @@ __device__ unsigned long long block_excl_scan(unsigned long long v, unsigned lon
   return total;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
   if (batch_failed(a.ctl)) return;
   const uint32_t nu = a.n_ins + a.n_del;
   const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
@@ -685,7 +759,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(BatchArgs a) {
   if (threadIdx.x == 0) a.qtile[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_top(BatchArgs a, uint32_t tiles) {
+__global__ __launch_bounds__(kBlock) void k_scan_top(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const uint32_t tiles = (a.n_ins + a.n_del + kScanTile - 1) / kScanTile;
   if (batch_failed(a.ctl)) return;
   unsigned long long carry = 0;
   for (uint32_t base = 0; base < tiles; base += kBlock) {
@@ -696,13 +772,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(BatchArgs a, uint32_t tiles
     if (i < tiles) a.qtile[i] = carry + excl;
     carry += total;
   }
-  if (threadIdx.x == 0) {
-    a.ctl->walk_items = carry;
-    a.ctl->queue_next = 0;
-  }
+  // this batch's walkers take a contiguous range of the shared queue
+  if (threadIdx.x == 0) a.ctl->item_base = atomicAdd(&a.qctl->walk_items, carry);
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_add(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) void k_scan_add(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
   if (batch_failed(a.ctl)) return;
   const uint32_t nu = a.n_ins + a.n_del;
   const uint64_t base = uint64_t(blockIdx.x) * kScanTile;
@@ -712,7 +787,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(BatchArgs a) {
 }
 
 // Queue items: one wavefront per update writes one record per walker.
-__global__ __launch_bounds__(kBlock) void k_expand_items(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) void k_expand_items(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t upd = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
@@ -727,46 +803,50 @@ __global__ __launch_bounds__(kBlock) void k_expand_items(BatchArgs a) {
   it.upd = upd;
   it.L = static_cast<uint16_t>(a.L ? a.L[upd] : a.L_def);
   it.w_pq = is_ins ? a.iw[upd] : 0.0;
-  const unsigned long long base = a.qofs[upd];
+  const unsigned long long base = a.ctl->item_base + a.qofs[upd];
   for (uint32_t k = lane; k < cnt; k += kWave) {
-    it.walker = static_cast<uint16_t>(k);
+    it.walker = static_cast<uint16_t>(k | (blockIdx.y << kWalkerBits));
     a.items[base + k] = it;
   }
 }
 
-// Persistent walk kernel over the queue of walker items.  A wavefront takes 64
-// items at a time with one atomic; a lane whose walker stops gets the next
-// item of that pool.  The new item's record is loaded before the other lanes'
-// step and used after it, so its latency hides behind the step's own loads.
-// Every walker's outcome goes to wres[item].
-__global__ __launch_bounds__(kBlock) void k_walk_queue(BatchArgs a, DevGraph G, DevGraph H) {
-  if (batch_failed(a.ctl)) return;
+// Persistent walk kernel over the queue of walker items of one or more batches
+// (argv[0..F), each item tagged with its batch).  A wavefront takes 64 items
+// at a time with one atomic; a lane whose walker stops gets the next item of
+// that pool.  The new item's record is loaded before the other lanes' step
+// and used after it, so its latency hides behind the step's own loads.  Every
+// walker's outcome goes to wres[item].  A batch that failed validation queued
+// no items.
+__global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a0 = *argv[0];
+  BatchCtl* q = a0.qctl;
+  const WalkItem* __restrict__ items = a0.items;  // shared by all batches of the launch
+  WalkerRec* __restrict__ wres = a0.wres;
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const unsigned long long total = a.ctl->walk_items;
+  const unsigned long long total = q->walk_items;
   const unsigned long long lanes_below = (1ull << lane) - 1ull;
-  const uint32_t refill_min = a.refill_min < 1 ? 1u : (a.refill_min > 64 ? 64u : a.refill_min);
+  const uint32_t refill_min = a0.refill_min < 1 ? 1u : (a0.refill_min > 64 ? 64u : a0.refill_min);
   unsigned long long pool_next = 0, pool_end = 0;  // this wavefront's items
   bool drained = false;
   bool active = false, pending = false;
   unsigned long long item = 0, next_item = 0;
   WalkItem rec{0, 0, 0, 0, 0, 0.0};
   WalkParams P;
-  P.K = a.K;
-  P.key0 = static_cast<uint32_t>(a.seed);
-  P.key1 = static_cast<uint32_t>(a.seed >> 32);
-  P.bounce = a.bounce != 0;
-  P.rows = H.rows;
-  P.ent = H.ent;
-  P.pfx = H.pfx;
+  P.K = 0.0;
+  P.key0 = P.key1 = 0;
+  P.bounce = false;
+  P.rows = a0.g[1].rows;
+  P.ent = a0.g[1].ent;
+  P.pfx = a0.g[1].pfx;
   P.p = P.q = 0;
   P.use_K = false;
   P.w_pq = 0.0;
   P.L = 0;
   P.uid_lo = P.uid_hi = 0;
-  uint32_t walker = 0;
+  uint32_t walker = 0, cur_b = 0;
   WState S;
   walker_start(S, 0);
-  unsigned long long steps = 0, bytes = 0;
+  unsigned long long steps = 0, bytes = 0;  // counters of batch cur_b
   while (true) {
     // (1) hand pool items to idle lanes
     const unsigned long long idle = __ballot(!active && !pending);
@@ -774,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(BatchArgs a, DevGraph G, 
     if (n_idle && (n_idle >= refill_min || n_idle == kWave)) {
       if (pool_next >= pool_end && !drained) {
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&a.ctl->queue_next, static_cast<unsigned long long>(kWave));
+        if (lane == 0) base = atomicAdd(&q->queue_next, static_cast<unsigned long long>(kWave));
         base = __shfl(base, 0, kWave);
         pool_next = base;
         pool_end = base < total ? (base + kWave < total ? base + kWave : total) : base;
@@ -786,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(BatchArgs a, DevGraph G, 
         const uint32_t rank = static_cast<uint32_t>(__popcll(idle & lanes_below));
         if (rank < take) {
           next_item = pool_next + rank;
-          rec = a.items[next_item];
+          rec = items[next_item];
           pending = true;
         }
       }
@@ -794,45 +874,69 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(BatchArgs a, DevGraph G, 
     }
     // (2) one step of every running walker
     if (active && !walk_step(P, walker, S, NoSink{})) {
-      a.wres[item] = WalkerRec{static_cast<uint8_t>(S.hit), 0, static_cast<uint16_t>(S.steps),
-                               S.x, S.R};
+      wres[item] = WalkerRec{static_cast<uint8_t>(S.hit), 0, static_cast<uint16_t>(S.steps),
+                             S.x, S.R};
       steps += S.steps;
       bytes += S.bytes;
       active = false;
     }
     // (3) lanes that received an item start its walker
     if (pending) {
+      const uint32_t b = rec.walker >> kWalkerBits;
+      if (b != cur_b && (steps | bytes)) {
+        atomicAdd(&argv[cur_b]->ctl->steps_total, steps);
+        atomicAdd(&argv[cur_b]->ctl->alg_bytes_total, bytes);
+        steps = bytes = 0;
+      }
+      cur_b = b;
+      const BatchArgs& A = *argv[b];
       item = next_item;
-      const bool is_ins = rec.upd < a.n_ins;
-      const uint64_t uid = a.uid_base + rec.upd;
+      const bool is_ins = rec.upd < A.n_ins;
+      const uint64_t uid = A.uid_base + rec.upd;
       P.p = rec.p;
       P.q = rec.q;
-      P.use_K = is_ins && a.has_K;
+      P.use_K = is_ins && A.has_K;
       P.w_pq = rec.w_pq;
+      P.K = A.K;
       P.L = rec.L;
+      P.key0 = static_cast<uint32_t>(A.seed);
+      P.key1 = static_cast<uint32_t>(A.seed >> 32);
       P.uid_lo = static_cast<uint32_t>(uid);
       P.uid_hi = static_cast<uint32_t>(uid >> 32);
-      P.rows = is_ins ? H.rows : G.rows;
-      P.ent = is_ins ? H.ent : G.ent;
-      P.pfx = is_ins ? H.pfx : G.pfx;
-      walker = rec.walker;
+      P.bounce = A.bounce != 0;
+      const DevGraph& X = A.g[is_ins ? 1 : 0];  // H_mid for insertions, G_mid for deletions
+      P.rows = X.rows;
+      P.ent = X.ent;
+      P.pfx = X.pfx;
+      walker = rec.walker & ((1u << kWalkerBits) - 1u);
       walker_start(S, rec.p);
       active = true;
       pending = false;
     }
     if (!__ballot(active) && drained && pool_next >= pool_end) break;
   }
-  const unsigned long long ws = wave_sum64(steps);
-  const unsigned long long wb = wave_sum64(bytes);
-  if (lane == 0) {
-    atomicAdd(&a.ctl->steps_total, ws);
-    atomicAdd(&a.ctl->alg_bytes_total, wb);
+  // flush the counters: one atomic per wavefront when all lanes hold the same batch
+  const bool has = (steps | bytes) != 0;
+  const uint32_t first = static_cast<uint32_t>(__builtin_ctzll(__ballot(has) | (1ull << 63)));
+  const uint32_t b0 = __shfl(cur_b, first, kWave);
+  if (__ballot(has && cur_b != b0) == 0ull) {
+    const unsigned long long ws = wave_sum64(steps);
+    const unsigned long long wb = wave_sum64(bytes);
+    if (lane == 0 && (ws | wb)) {
+      atomicAdd(&argv[b0]->ctl->steps_total, ws);
+      atomicAdd(&argv[b0]->ctl->alg_bytes_total, wb);
+    }
+  } else if (has) {
+    atomicAdd(&argv[cur_b]->ctl->steps_total, steps);
+    atomicAdd(&argv[cur_b]->ctl->alg_bytes_total, bytes);
   }
 }
 
 // Reduce each update's walker records and decide it (one wavefront per update).
-__global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(BatchArgs a, DevGraph G,
-                                                               DevGraph H) {
+__global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& G = a.g[0];
+  const DevGraph& H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + threadIdx.x / kWave;
@@ -845,7 +949,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(BatchArgs a, DevG
     if (lane == 0) a.res[upd] = empty_result(v.is_ins);
     return;
   }
-  const unsigned long long first = a.qofs[upd];
+  const unsigned long long first = a.ctl->item_base + a.qofs[upd];
   bool any_hit = false;
   double bestR = INFINITY;
   uint32_t bestW = kNone;
@@ -897,22 +1001,25 @@ __device__ __forceinline__ uint32_t add_count(const BatchArgs& a, int which) {
   return 2u * (c < a.hadd_cap ? c : a.hadd_cap);
 }
 
-__global__ void k_add_prepare(BatchArgs a, DevGraph X, int which) {
+__global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= add_count(a, which)) return;
   a.add_keep[which][e] = 0;
   const AddEntry d = add_entry(a, which, e);
   if (!d.valid) return;
-  const Row row = X.rows[d.r];
-  const int k = find_nbr(X.ent, row, d.c);
+  const RowHdr row = row_hdr(X, d.r);
+  Ent* seg = seg_of(X, d.r, row.off);
+  const int k = find_nbr(seg, row.len, d.c);
   if (k >= 0) {
     // a tombstone of the same edge: revive it in place (once)
-    const uint32_t old = atomicCAS(&X.ent[row.off + k].qw, 0u, d.qw);
+    const uint32_t old = atomicCAS(&seg[k].qw, 0u, d.qw);
     if (old == 0u) {
-      X.ent[row.off + k].rinv = d.rinv;
-      X.w[row.off + k] = d.w;
-      atomicSub(&X.rows[d.r].dead, 1u);
+      seg[k].rinv = d.rinv;
+      wseg_of(X, d.r, row.off)[k] = d.w;
+      atomicSub(&row_hdr_ref(X, d.r).dead, 1u);
       if (row.len > kHub) mark_dirty(a, X, which, d.r);
     }
     return;
@@ -941,13 +1048,15 @@ constexpr uint32_t kWideRelocate = 1u << 30;
 constexpr uint32_t kWideMerge = 1u << 31;
 constexpr uint32_t kCountMask = kWideRelocate - 1u;
 
-__global__ void k_rows_plan(BatchArgs a, DevGraph X, int which) {
+__global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
   const uint32_t r = a.touched_rows[which][t];
   const uint32_t k = X.pending[r];
-  const Row row = X.rows[r];
+  const RowHdr row = row_hdr(X, r);
   uint32_t need = 0, flags = 0, merged_from = row.len;
   if (row.len + k > row.cap) {
     need = grown_cap(row.len - row.dead + k);
@@ -960,13 +1069,17 @@ __global__ void k_rows_plan(BatchArgs a, DevGraph X, int which) {
   a.touched_need[which][t] = need;
 }
 
-__global__ void k_pool_check(BatchArgs a, uint64_t pool_cap, int which) {
+__global__ void k_pool_check(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const uint64_t pool_cap = a.g[which].pool_cap;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (batch_failed(a.ctl)) return;
   if (a.ctl->pool_top[which] + a.ctl->need[which] > pool_cap) a.ctl->nomem[which] = 1;
 }
 
-__global__ void k_rows_relocate(BatchArgs a, DevGraph X, int which) {
+__global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
@@ -974,24 +1087,27 @@ __global__ void k_rows_relocate(BatchArgs a, DevGraph X, int which) {
   if (need == 0) return;
   if (a.touched_k[which][t] & kWideRelocate) return;  // moved by k_rows_relocate_wide
   const uint32_t r = a.touched_rows[which][t];
-  const Row row = X.rows[r];
+  const RowHdr row = row_hdr(X, r);
+  const Ent* src = seg_of(X, r, row.off);
+  const double* wsrc = wseg_of(X, r, row.off);
   const uint32_t off =
       static_cast<uint32_t>(atomicAdd(&a.ctl->pool_top[which], static_cast<unsigned long long>(need)));
   uint32_t o = 0;
   for (uint32_t i = 0; i < row.len; ++i) {
-    const Ent e = X.ent[row.off + i];
+    const Ent e = src[i];
     if (e.qw == 0u) continue;  // drop tombstones while moving
     X.ent[off + o] = e;
-    X.w[off + o] = X.w[row.off + i];
+    X.w[off + o] = wsrc[i];
     ++o;
   }
-  X.rows[r] = Row{off, o, need, 0u};
+  row_hdr_ref(X, r) = RowHdr{off, o, need, 0u};
 }
 
 // Relocation of long segments: one workgroup per segment, tombstones dropped
 // through a block-wide scan of the live flags.
-__global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(BatchArgs a, DevGraph X,
-                                                               int which) {
+__global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ uint32_t s_off;
   const uint32_t count = a.ctl->touched[which];
@@ -999,7 +1115,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(BatchArgs a, DevG
     const uint32_t need = a.touched_need[which][t];
     if (need == 0 || !(a.touched_k[which][t] & kWideRelocate)) continue;  // block-uniform
     const uint32_t r = a.touched_rows[which][t];
-    const Row row = X.rows[r];
+    const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment
     if (threadIdx.x == 0)
       s_off = static_cast<uint32_t>(
           atomicAdd(&a.ctl->pool_top[which], static_cast<unsigned long long>(need)));
@@ -1023,27 +1139,31 @@ __global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(BatchArgs a, DevG
       }
       out += total;
     }
-    if (threadIdx.x == 0) X.rows[r] = Row{off, static_cast<uint32_t>(out), need, 0u};
+    if (threadIdx.x == 0) row_hdr_ref(X, r) = RowHdr{off, static_cast<uint32_t>(out), need, 0u};
     __syncthreads();
   }
 }
 
-__global__ void k_add_place(BatchArgs a, DevGraph X, int which) {
+__global__ void k_add_place(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= add_count(a, which)) return;
   if (!a.add_keep[which][e]) return;
   const AddEntry d = add_entry(a, which, e);
-  const Row row = X.rows[d.r];
+  const RowHdr row = row_hdr(X, d.r);
   const uint32_t slot = atomicSub(&X.pending[d.r], 1u) - 1u;  // leaves pending at 0
-  const uint32_t pos = row.off + row.len + slot;
-  X.ent[pos] = Ent{d.c, d.qw, d.rinv};
-  X.w[pos] = d.w;
+  const uint32_t pos = row.len + slot;
+  seg_of(X, d.r, row.off)[pos] = Ent{d.c, d.qw, d.rinv};
+  wseg_of(X, d.r, row.off)[pos] = d.w;
 }
 
 // Merge the k appended entries (unsorted tail) into the sorted segment; one
 // thread per short segment (insertion of each new entry).
-__global__ void k_rows_merge(BatchArgs a, DevGraph X, int which) {
+__global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
@@ -1051,9 +1171,9 @@ __global__ void k_rows_merge(BatchArgs a, DevGraph X, int which) {
   if (packed & kWideMerge) return;  // merged by k_rows_merge_wide
   const uint32_t r = a.touched_rows[which][t];
   const uint32_t k = packed & kCountMask;
-  const Row row = X.rows[r];
-  Ent* seg = X.ent + row.off;
-  double* wseg = X.w + row.off;
+  const RowHdr row = row_hdr(X, r);
+  Ent* seg = seg_of(X, r, row.off);
+  double* wseg = wseg_of(X, r, row.off);
   for (uint32_t j = row.len; j < row.len + k; ++j) {
     const Ent e = seg[j];
     const double we = wseg[j];
@@ -1066,7 +1186,7 @@ __global__ void k_rows_merge(BatchArgs a, DevGraph X, int which) {
     seg[i] = e;
     wseg[i] = we;
   }
-  X.rows[r].len = row.len + k;
+  row_hdr_ref(X, r).len = row.len + k;
 }
 
 constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 KB LDS)
@@ -1077,7 +1197,9 @@ constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 K
 // entries below them; new entries sit after the old entries below them) and
 // moves the old entries right to left in block-sized chunks, so no entry is
 // overwritten before it is read.
-__global__ __launch_bounds__(kBlock) void k_rows_merge_wide(BatchArgs a, DevGraph X, int which) {
+__global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ unsigned long long s_key[kTailChunk];  // (nbr << 32) | local index
   __shared__ Ent s_ent[kTailChunk];
@@ -1089,7 +1211,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(BatchArgs a, DevGrap
     if (!(packed & kWideMerge)) continue;  // block-uniform
     const uint32_t r = a.touched_rows[which][t];
     const uint32_t k = packed & kCountMask;
-    const Row row = X.rows[r];
+    const RowHdr row = row_hdr(X, r);  // relocated or long: a pool segment
     Ent* seg = X.ent + row.off;
     double* wseg = X.w + row.off;
     uint32_t cur = row.len;  // sorted prefix length
@@ -1168,30 +1290,35 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(BatchArgs a, DevGrap
       __syncthreads();
       cur += c;
     }
-    if (threadIdx.x == 0) X.rows[r].len = cur;
+    if (threadIdx.x == 0) row_hdr_ref(X, r).len = cur;
     __syncthreads();
   }
 }
 
 // Long segments touched by phase 4 need their prefix rebuilt.
-__global__ void k_mark_merged(BatchArgs a, DevGraph X, int which) {
+__global__ void k_mark_merged(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
   const uint32_t r = a.touched_rows[which][t];
-  if (X.rows[r].len > kHub) mark_dirty(a, X, which, r);
+  if (row_hdr(X, r).len > kHub) mark_dirty(a, X, which, r);
 }
 
 // After a pool shortfall: undo the per-row counters so phase 4 can run again
 // once the pool has grown.
-__global__ void k_phase4_reset(BatchArgs a, DevGraph X, int which) {
+__global__ void k_phase4_reset(const BatchArgs* const* __restrict__ argv, int which) {
+  const BatchArgs& a = *argv[blockIdx.y];
+  const DevGraph& X = a.g[which];
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
   X.pending[a.touched_rows[which][t]] = 0u;
 }
 
-__global__ void k_phase4_reset_ctl(BatchCtl* ctl, int which) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv, int which) {
+  BatchCtl* ctl = argv[blockIdx.y]->ctl;
+  if (threadIdx.x == 0) {
     ctl->touched[which] = 0;
     ctl->need[which] = 0;
     ctl->nomem[which] = 0;
@@ -1207,82 +1334,81 @@ inline uint32_t blocks_for(uint64_t n, uint32_t per = kBlock) {
 }  // namespace
 
 // ---- launchers ----------------------------------------------------------------------
+// Per-batch kernels run on a grid of (x, F): blockIdx.y selects the batch, and
+// x covers the largest batch of the launch.
 
-void launch_batch_begin(const BatchArgs& a, const DevGraph&, const DevGraph&,
-                        uint64_t hash_slots, hipStream_t st) {
-  k_batch_begin<<<1, 64, 0, st>>>(a.ctl);
-  const uint32_t nb = blocks_for(hash_slots) < 4096 ? blocks_for(hash_slots) : 4096;
-  k_clear_hash<<<nb ? nb : 1, kBlock, 0, st>>>(a.hash, hash_slots);
+namespace {
+inline dim3 grid_of(uint64_t n, uint32_t F, uint32_t per = kBlock) {
+  const uint64_t b = (n + per - 1) / per;
+  return dim3(static_cast<uint32_t>(b ? b : 1), F);
+}
+}  // namespace
+
+void launch_batch_begin(const Launch& L, hipStream_t st) {
+  k_batch_begin<<<dim3(1, L.F), 64, 0, st>>>(L.argv);
+  const uint32_t nb = blocks_for(L.max_hash_slots) < 4096 ? blocks_for(L.max_hash_slots) : 4096;
+  k_clear_hash<<<dim3(nb ? nb : 1, L.F), kBlock, 0, st>>>(L.argv);
 }
 
-void launch_validate(const BatchArgs& a, const DevGraph& G, hipStream_t st) {
-  const uint32_t nu = a.n_ins + a.n_del;
-  if (nu == 0) return;
-  k_validate_a<<<blocks_for(nu), kBlock, 0, st>>>(a);
-  k_validate_b<<<blocks_for(nu), kBlock, 0, st>>>(a, G.rows, G.ent);
+void launch_validate(const Launch& L, hipStream_t st) {
+  if (L.max_nu == 0) return;
+  k_validate_a<<<grid_of(L.max_nu, L.F), kBlock, 0, st>>>(L.argv);
+  k_validate_b<<<grid_of(L.max_nu, L.F), kBlock, 0, st>>>(L.argv);
 }
 
-void launch_phase1(const BatchArgs& a, DevGraph& G, DevGraph& H, hipStream_t st) {
-  if (a.n_del == 0) return;
-  k_phase1<<<blocks_for(a.n_del), kBlock, 0, st>>>(a, G, H);
+void launch_phase1(const Launch& L, hipStream_t st) {
+  if (L.max_del == 0) return;
+  k_phase1<<<grid_of(L.max_del, L.F), kBlock, 0, st>>>(L.argv);
   // walks read the prefix of long segments: rebuild the ones just changed
-  k_hub_prefix<<<kWideBlocks, kBlock, 0, st>>>(a, G, 0);
-  k_hub_prefix<<<kWideBlocks, kBlock, 0, st>>>(a, H, 1);
-  k_dirty_reset<<<1, 64, 0, st>>>(a.ctl);
+  k_hub_prefix<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, 0);
+  k_hub_prefix<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, 1);
+  k_dirty_reset<<<dim3(1, L.F), 64, 0, st>>>(L.argv);
 }
 
-void launch_walks(const BatchArgs& a, const DevGraph& G, const DevGraph& H, hipStream_t st) {
-  const uint32_t nu = a.n_ins + a.n_del;
-  if (nu == 0) return;
+void launch_walks(const Launch& L, hipStream_t st) {
+  if (L.max_nu == 0) return;
+  k_walks<<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
+}
+
+void launch_walks_queue(const Launch& L, hipStream_t st) {
+  if (L.max_nu == 0) return;
   const uint32_t per = kWalkBlock / kWave;
-  k_walks<<<(nu + per - 1) / per, kWalkBlock, 0, st>>>(a, G, H);
+  k_count_walkers<<<grid_of(L.max_nu, L.F), kBlock, 0, st>>>(L.argv);
+  k_scan_tiles<<<grid_of(L.max_nu, L.F, kScanTile), kBlock, 0, st>>>(L.argv);
+  k_scan_top<<<dim3(1, L.F), kBlock, 0, st>>>(L.argv);
+  k_scan_add<<<grid_of(L.max_nu, L.F, kScanTile), kBlock, 0, st>>>(L.argv);
+  k_expand_items<<<grid_of(L.max_nu, L.F, per), kBlock, 0, st>>>(L.argv);
+  k_walk_queue<<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
+  k_reduce_updates<<<grid_of(L.max_nu, L.F, per), kWalkBlock, 0, st>>>(L.argv);
 }
 
-void launch_walks_queue(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
-                        uint32_t walk_blocks, hipStream_t st) {
-  const uint32_t nu = a.n_ins + a.n_del;
-  if (nu == 0) return;
-  const uint32_t tiles = (nu + kScanTile - 1) / kScanTile;
-  const uint32_t per = kWalkBlock / kWave;
-  k_count_walkers<<<blocks_for(nu), kBlock, 0, st>>>(a, G, H);
-  k_scan_tiles<<<tiles, kBlock, 0, st>>>(a);
-  k_scan_top<<<1, kBlock, 0, st>>>(a, tiles);
-  k_scan_add<<<tiles, kBlock, 0, st>>>(a);
-  k_expand_items<<<(nu + per - 1) / per, kBlock, 0, st>>>(a);
-  k_walk_queue<<<walk_blocks, kBlock, 0, st>>>(a, G, H);
-  k_reduce_updates<<<(nu + per - 1) / per, kWalkBlock, 0, st>>>(a, G, H);
-}
-
-void launch_phase4(const BatchArgs& a, DevGraph& X, int which, uint64_t hash_slots,
-                   hipStream_t st) {
+void launch_phase4(const Launch& L, int which, hipStream_t st) {
   // upper bound of the directed entries and of the touched rows
-  const uint64_t cap = which == 0 ? 2ull * a.n_ins : 2ull * a.hadd_cap;
+  const uint64_t cap = which == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
   if (cap == 0) return;
   if (which == 1) {
-    const uint32_t nb = blocks_for(hash_slots) < 4096 ? blocks_for(hash_slots) : 4096;
-    k_clear_hash<<<nb ? nb : 1, kBlock, 0, st>>>(a.hash, hash_slots);
+    const uint32_t nb = blocks_for(L.max_hash_slots) < 4096 ? blocks_for(L.max_hash_slots) : 4096;
+    k_clear_hash<<<dim3(nb ? nb : 1, L.F), kBlock, 0, st>>>(L.argv);
   }
-  const uint32_t nb = blocks_for(cap);
-  k_add_prepare<<<nb, kBlock, 0, st>>>(a, X, which);
-  k_rows_plan<<<nb, kBlock, 0, st>>>(a, X, which);
-  k_pool_check<<<1, 64, 0, st>>>(a, X.pool_cap, which);
-  k_rows_relocate<<<nb, kBlock, 0, st>>>(a, X, which);
-  k_rows_relocate_wide<<<kWideBlocks, kBlock, 0, st>>>(a, X, which);
-  k_add_place<<<nb, kBlock, 0, st>>>(a, X, which);
-  k_rows_merge<<<nb, kBlock, 0, st>>>(a, X, which);
-  k_rows_merge_wide<<<kWideBlocks, kBlock, 0, st>>>(a, X, which);
-  k_mark_merged<<<nb, kBlock, 0, st>>>(a, X, which);
-  k_hub_prefix<<<kWideBlocks, kBlock, 0, st>>>(a, X, which);
-  k_dirty_reset<<<1, 64, 0, st>>>(a.ctl);
+  const dim3 g = grid_of(cap, L.F);
+  k_add_prepare<<<g, kBlock, 0, st>>>(L.argv, which);
+  k_rows_plan<<<g, kBlock, 0, st>>>(L.argv, which);
+  k_pool_check<<<dim3(1, L.F), 64, 0, st>>>(L.argv, which);
+  k_rows_relocate<<<g, kBlock, 0, st>>>(L.argv, which);
+  k_rows_relocate_wide<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, which);
+  k_add_place<<<g, kBlock, 0, st>>>(L.argv, which);
+  k_rows_merge<<<g, kBlock, 0, st>>>(L.argv, which);
+  k_rows_merge_wide<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, which);
+  k_mark_merged<<<g, kBlock, 0, st>>>(L.argv, which);
+  k_hub_prefix<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, which);
+  k_dirty_reset<<<dim3(1, L.F), 64, 0, st>>>(L.argv);
 }
 
-void launch_phase4_reset(const BatchArgs& a, DevGraph& X, int which, hipStream_t st) {
-  const uint64_t cap = which == 0 ? 2ull * a.n_ins : 2ull * a.hadd_cap;
+void launch_phase4_reset(const Launch& L, int which, hipStream_t st) {
+  const uint64_t cap = which == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
   if (cap == 0) return;
-  k_phase4_reset<<<blocks_for(cap), kBlock, 0, st>>>(a, X, which);
-  k_phase4_reset_ctl<<<1, 64, 0, st>>>(a.ctl, which);
+  k_phase4_reset<<<grid_of(cap, L.F), kBlock, 0, st>>>(L.argv, which);
+  k_phase4_reset_ctl<<<dim3(1, L.F), 64, 0, st>>>(L.argv, which);
 }
-
-void launch_batch_end(const BatchArgs&, hipStream_t) {}
 
 }  // namespace dyg

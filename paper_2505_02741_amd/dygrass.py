@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdygrass.so")
+LIB_PATH = os.environ.get("DYGRASS_LIB") or os.path.join(_HERE, "libdygrass.so")
 
 STATUS = {
     0: "OK",
@@ -34,6 +34,7 @@ STATUS = {
 FLAG_LEAN_POOLS = 1
 FLAG_TIMING = 2
 FLAG_BATCHED = 4
+FLAG_GRAPH = 8
 
 DEAD_END_TERMINATE = 0
 DEAD_END_BOUNCE = 1
@@ -79,10 +80,24 @@ class dyg_batch_dev(C.Structure):
                 ("L_max", C.c_uint32), ("s_max", C.c_uint32), ("results", C.c_void_p)]
 
 
+class dyg_server_params(C.Structure):
+    _fields_ = [("mem_budget", C.c_uint64), ("max_fused", C.c_uint32),
+                ("max_inflight", C.c_uint32), ("walk_blocks_per_cu", C.c_uint32),
+                ("reserved", C.c_uint32 * 3)]
+
+
+class dyg_request_done(C.Structure):
+    _fields_ = [("request_id", C.c_uint64), ("graph_id", C.c_uint32), ("status", C.c_int32),
+                ("n_updates", C.c_uint64), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double)]
+
+
 EXPORTS = ["dyg_default_params", "dyg_init", "dyg_apply_batch", "dyg_apply_batch_dev",
            "dyg_sync", "dyg_query_sparsifier", "dyg_query_graph", "dyg_stats", "dyg_compact",
            "dyg_destroy", "dyg_error_string", "dyg_get_tuning", "dyg_set_tuning",
-           "dyg_check_state"]
+           "dyg_check_state", "dyg_server_default_params", "dyg_server_create",
+           "dyg_server_add_graph", "dyg_server_submit", "dyg_server_poll", "dyg_server_pending",
+           "dyg_server_now", "dyg_server_destroy"]
 
 
 class DygError(RuntimeError):
@@ -121,6 +136,24 @@ def _load():
         fn.restype = C.c_int
     lib.dyg_stats.argtypes = [P, C.POINTER(dyg_stats_t)]
     lib.dyg_stats.restype = C.c_int
+    lib.dyg_server_default_params.argtypes = [C.POINTER(dyg_server_params)]
+    lib.dyg_server_default_params.restype = None
+    lib.dyg_server_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(dyg_server_params)]
+    lib.dyg_server_create.restype = C.c_int
+    lib.dyg_server_add_graph.argtypes = [P, P, C.POINTER(C.c_uint32)]
+    lib.dyg_server_add_graph.restype = C.c_int
+    lib.dyg_server_submit.argtypes = [P, C.c_uint32, C.c_uint64, P, P, P, C.c_uint64, P, P, P,
+                                      C.POINTER(C.c_uint64)]
+    lib.dyg_server_submit.restype = C.c_int
+    lib.dyg_server_poll.argtypes = [P, C.POINTER(dyg_request_done), C.c_uint32,
+                                    C.POINTER(C.c_uint32)]
+    lib.dyg_server_poll.restype = C.c_int
+    lib.dyg_server_pending.argtypes = [P]
+    lib.dyg_server_pending.restype = C.c_uint64
+    lib.dyg_server_now.argtypes = [P]
+    lib.dyg_server_now.restype = C.c_double
+    lib.dyg_server_destroy.argtypes = [P]
+    lib.dyg_server_destroy.restype = None
     lib.dyg_check_state.argtypes = [P, C.c_char_p, C.c_uint64]
     lib.dyg_check_state.restype = C.c_int
     lib.dyg_get_tuning.argtypes = [P, C.POINTER(dyg_tuning)]
@@ -336,3 +369,95 @@ class Dygrass:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# serving
+
+
+def dyg_server_default_params(**overrides) -> dyg_server_params:
+    p = dyg_server_params()
+    _lib.dyg_server_default_params(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+class DygServer:
+    """Continuous batching over many resident graphs (dyg_server_*).
+
+    submit() queues a batch of one graph and returns its request id; poll()
+    launches rounds and returns finished requests as dicts; results of a
+    request (a structured array of n_ins+n_del records) are complete once it
+    is reported."""
+
+    def __init__(self, mem_budget=8 << 30, max_fused=32, max_inflight=2, walk_blocks_per_cu=4):
+        self.params = dyg_server_default_params(mem_budget=int(mem_budget),
+                                                max_fused=int(max_fused),
+                                                max_inflight=int(max_inflight),
+                                                walk_blocks_per_cu=int(walk_blocks_per_cu))
+        self.h = C.c_void_p()
+        _check(_lib.dyg_server_create(C.byref(self.h), C.byref(self.params)), "dyg_server_create")
+        self._keep = {}  # request id -> arrays the server writes or reads until done
+        self._done = (dyg_request_done * 1024)()
+
+    def add_graph(self, ctx: "Dygrass") -> int:
+        gid = C.c_uint32(0)
+        _check(_lib.dyg_server_add_graph(self.h, ctx.ctx, C.byref(gid)), "dyg_server_add_graph")
+        return int(gid.value)
+
+    def submit(self, graph_id, iu, iv, iw, du, dv, results=True) -> int:
+        iu = _arr(iu, np.uint32)
+        iv = _arr(iv, np.uint32)
+        iw = _arr(iw, np.float64)
+        du = _arr(du, np.uint32)
+        dv = _arr(dv, np.uint32)
+        res = np.zeros(iu.size + du.size, UPDATE_RESULT_DTYPE) if results else None
+        rid = C.c_uint64(0)
+        _check(_lib.dyg_server_submit(self.h, int(graph_id), iu.size, _ptr(iu), _ptr(iv),
+                                      _ptr(iw), du.size, _ptr(du), _ptr(dv), _ptr(res),
+                                      C.byref(rid)), "dyg_server_submit")
+        self._keep[int(rid.value)] = res
+        return int(rid.value)
+
+    def poll(self):
+        n = C.c_uint32(0)
+        _check(_lib.dyg_server_poll(self.h, self._done, len(self._done), C.byref(n)),
+               "dyg_server_poll")
+        out = []
+        for i in range(n.value):
+            d = self._done[i]
+            rid = int(d.request_id)
+            out.append(dict(request_id=rid, graph_id=int(d.graph_id), status=int(d.status),
+                            n_updates=int(d.n_updates), t_submit=d.t_submit,
+                            t_start=d.t_start, t_done=d.t_done,
+                            results=self._keep.pop(rid, None)))
+        return out
+
+    @property
+    def pending(self) -> int:
+        return int(_lib.dyg_server_pending(self.h))
+
+    def now(self) -> float:
+        return float(_lib.dyg_server_now(self.h))
+
+    def drain(self, sleep_s=0.0):
+        import time
+
+        out = []
+        while self.pending:
+            out += self.poll()
+            if sleep_s:
+                time.sleep(sleep_s)
+        return out
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            _lib.dyg_server_destroy(self.h)
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

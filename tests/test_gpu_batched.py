@@ -112,3 +112,51 @@ def test_device_batch_validation_error():
     finally:
         d.close()
         o.close()
+
+
+GRAPH = 8  # DYG_FLAG_GRAPH
+
+
+def _uneven_mesh_batches(seed=4):
+    """Mesh batches of varying sizes: several size classes, each seen more than
+    once, so captured graphs are both created and replayed."""
+    wl = W.make_workload("mesh128", side=12, ins=10, dels=10, batches=0)
+    es = W.EdgeSet(wl.G)
+    rng = np.random.default_rng(seed)
+    for size in (300, 40, 290, 35, 300, 9, 150, 41, 260, 8):
+        n_ins = size // 2
+        p, q = W.local_insertions_lattice(es, 12, 3, n_ins, rng, np.zeros(0, np.int64))
+        du, dv = W.uniform_deletions(es, size - n_ins, rng)
+        b = W.Batch(p.astype(np.uint32), q.astype(np.uint32), rng.uniform(0.5, 2.0, p.size),
+                    du.astype(np.uint32), dv.astype(np.uint32))
+        es.apply(es.key(b.iu, b.iv), es.key(b.du, b.dv))
+        wl.batches.append(b)
+    return wl
+
+
+@pytest.mark.parametrize("flags", [GRAPH, BATCHED | GRAPH])
+def test_graph_mode_replays(flags):
+    wl = _uneven_mesh_batches()
+    run_parity(wl, tag=f"graph flags={flags}", flags=flags)
+
+
+def test_graph_mode_error_then_valid():
+    from paper_2505_02741_amd import dygrass as D
+
+    wl = _uneven_mesh_batches()
+    o, d = make_pair(wl, flags=BATCHED | GRAPH)
+    try:
+        compare_batch(o, d, wl.batches[0], tag="graph b0")
+        b = wl.batches[1]
+        bad_iu = b.iu.copy()
+        bad_iu[3] = b.iv[3]  # a self loop inside an otherwise valid batch
+        with pytest.raises(D.DygError) as e:
+            d.apply_batch(bad_iu, b.iv, b.iw, b.du, b.dv)
+        assert e.value.name == "SELF_LOOP"
+        compare_state(o, d, "graph after error")
+        for t, bb in enumerate(wl.batches[1:]):
+            compare_batch(o, d, bb, tag=f"graph b{t + 1}")
+        compare_state(o, d, "graph end")
+    finally:
+        d.close()
+        o.close()
