@@ -38,6 +38,85 @@ enum : int {
   E_DUPLICATE = 7,
 };
 
+// ---- argument loading -------------------------------------------------------------
+
+// A pointer read from device memory is generic to the compiler, which then
+// accesses it with flat instructions and can neither keep uniform arguments
+// in scalar registers nor aggregate uniform atomics.  Every buffer of this
+// library is global memory: the argument records and the pointers they hold
+// are read here as global (address space 1) pointers, which the compiler
+// propagates to every access made through them.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+// Pointer stored at global address f, pointing to global memory.
+template <class T>
+__device__ __forceinline__ T* load_gptr(T* const __attribute__((address_space(1)))* f) {
+  const uint64_t bits = *reinterpret_cast<const uint64_t __attribute__((address_space(1)))*>(f);
+  return (T*)(gptr<T>)bits;
+}
+
+// Argument record of batch b of the launch.
+__device__ __forceinline__ gptr<const BatchArgs> args_of(const BatchArgs* const* __restrict__ argv,
+                                                        uint32_t b) {
+  return (gptr<const BatchArgs>)argv[b];
+}
+
+__device__ __forceinline__ void load_graph(DevGraph& X, gptr<const BatchArgs> ap, int w) {
+  X.rows = load_gptr(&ap->g[w].rows);
+  X.ent = load_gptr(&ap->g[w].ent);
+  X.w = load_gptr(&ap->g[w].w);
+  X.winl = load_gptr(&ap->g[w].winl);
+  X.pending = load_gptr(&ap->g[w].pending);
+  X.pfx = load_gptr(&ap->g[w].pfx);
+  X.mark = load_gptr(&ap->g[w].mark);
+}
+
+// Arguments of batch b of the launch, read once at kernel entry.
+__device__ __forceinline__ BatchArgs load_args(const BatchArgs* const* __restrict__ argv,
+                                               uint32_t b) {
+  const gptr<const BatchArgs> ap = args_of(argv, b);
+  BatchArgs a;
+  __builtin_memcpy(&a, (const BatchArgs*)ap, sizeof(BatchArgs));
+  a.iu = load_gptr(&ap->iu);
+  a.iv = load_gptr(&ap->iv);
+  a.iw = load_gptr(&ap->iw);
+  a.du = load_gptr(&ap->du);
+  a.dv = load_gptr(&ap->dv);
+  a.s = load_gptr(&ap->s);
+  a.L = load_gptr(&ap->L);
+  a.ins_qw = load_gptr(&ap->ins_qw);
+  a.ins_rinv = load_gptr(&ap->ins_rinv);
+  a.in_h = load_gptr(&ap->in_h);
+  a.res = load_gptr(&ap->res);
+  a.wrec = load_gptr(&ap->wrec);
+  a.wofs = load_gptr(&ap->wofs);
+  a.hadd = load_gptr(&ap->hadd);
+  a.hash = load_gptr(&ap->hash);
+  load_graph(a.g[0], ap, 0);
+  load_graph(a.g[1], ap, 1);
+  a.ctl = load_gptr(&ap->ctl);
+  a.qctl = load_gptr(&ap->qctl);
+  for (int w = 0; w < 2; ++w) {
+    a.touched_rows[w] = load_gptr(&ap->touched_rows[w]);
+    a.touched_k[w] = load_gptr(&ap->touched_k[w]);
+    a.touched_need[w] = load_gptr(&ap->touched_need[w]);
+    a.add_keep[w] = load_gptr(&ap->add_keep[w]);
+    a.dirty_rows[w] = load_gptr(&ap->dirty_rows[w]);
+  }
+  a.qcount = load_gptr(&ap->qcount);
+  a.qofs = load_gptr(&ap->qofs);
+  a.qtile = load_gptr(&ap->qtile);
+  a.items = load_gptr(&ap->items);
+  a.wres = load_gptr(&ap->wres);
+  return a;
+}
+
+// Control block of batch b of the launch.
+__device__ __forceinline__ BatchCtl* ctl_of(const BatchArgs* const* __restrict__ argv, uint32_t b) {
+  return load_gptr(&args_of(argv, b)->ctl);
+}
+
 __device__ __forceinline__ bool batch_failed(const BatchCtl* c) {
   return c->err_key != ~0ull;
 }
@@ -141,9 +220,9 @@ __device__ bool hash_insert_first(HashSlot* h, uint32_t mask, unsigned long long
 // One workgroup per batch resets that batch's control block; the first also
 // resets the work-queue control the batches share.
 __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
-  BatchCtl* ctl = argv[blockIdx.y]->ctl;
+  BatchCtl* ctl = ctl_of(argv, blockIdx.y);
   if (threadIdx.x == 0 && blockIdx.y == 0) {
-    BatchCtl* q = argv[0]->qctl;
+    BatchCtl* q = load_gptr(&args_of(argv, 0)->qctl);
     q->walk_items = 0;
     q->queue_next = 0;
   }
@@ -158,8 +237,8 @@ __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
 }
 
 __global__ void k_clear_hash(const BatchArgs* const* __restrict__ argv) {
-  HashSlot* h = argv[blockIdx.y]->hash;
-  const uint64_t slots = argv[blockIdx.y]->hash_slots;
+  HashSlot* h = load_gptr(&args_of(argv, blockIdx.y)->hash);
+  const uint64_t slots = args_of(argv, blockIdx.y)->hash_slots;
   for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < slots;
        i += uint64_t(gridDim.x) * blockDim.x) {
     h[i].key = ~0ull;
@@ -172,7 +251,7 @@ __global__ void k_clear_hash(const BatchArgs* const* __restrict__ argv) {
 constexpr unsigned long long kDelTag = 1ull << 63;  // n < 2^31 keeps bit 63 free
 
 __global__ void k_validate_a(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_ins + a.n_del) return;
   if (i < a.n_ins) {
@@ -201,7 +280,7 @@ __device__ __forceinline__ uint32_t quantize(double w, double w_ref, int Q) {
 }
 
 __global__ void k_validate_b(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& G = a.g[0];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_ins + a.n_del) return;
@@ -258,7 +337,7 @@ __device__ __forceinline__ void tombstone(const BatchArgs& a, const DevGraph& X,
 }
 
 __global__ void k_phase1(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& G = a.g[0];
   const DevGraph& H = a.g[1];
   if (batch_failed(a.ctl)) return;
@@ -280,8 +359,9 @@ __device__ unsigned long long block_excl_scan(unsigned long long v, unsigned lon
 
 // Rebuild the inclusive weight prefix of every dirty row (one workgroup per
 // row), then clear its mark.
-__global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t count = a.ctl->dirty[which];
@@ -302,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* _
 }
 
 __global__ void k_dirty_reset(const BatchArgs* const* __restrict__ argv) {
-  BatchCtl* ctl = argv[blockIdx.y]->ctl;
+  BatchCtl* ctl = ctl_of(argv, blockIdx.y);
   if (threadIdx.x == 0) ctl->dirty[0] = ctl->dirty[1] = 0;
 }
 
@@ -378,7 +458,7 @@ __device__ __forceinline__ unsigned long long step_random(WState& S, const WalkP
 // access of the step.
 template <class Sink>
 __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
-                                          Sink sink) {
+                                          Sink& sink) {
   const uint32_t t = S.steps;
   if (t >= P.L) return false;
   const uint4* rq = reinterpret_cast<const uint4*>(P.rows + S.x);
@@ -480,7 +560,7 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
 }
 
 template <class Sink>
-__device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, Sink sink) {
+__device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, Sink& sink) {
   WState S;
   walker_start(S, P.p);
   while (walk_step(P, walker, S, sink)) {
@@ -515,21 +595,20 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 
 // Sink of the winner replay: path edges absent from H_mid, first occurrence.
 struct RecoverSink {
-  const DevGraph* G;
-  const DevGraph* H;
+  DevGraph G, H;
   AddRec* out;  // reserved block of `cap` records
   uint32_t cap;
-  uint32_t* count;
+  uint32_t count;
   // edge x -> y is entry i of x's row in G (off: that row's pool offset)
-  __device__ void operator()(uint32_t x, uint32_t y, uint32_t i, uint32_t off) const {
-    if (has_live(*H, x, y)) return;
+  __device__ void operator()(uint32_t x, uint32_t y, uint32_t i, uint32_t off) {
+    if (has_live(H, x, y)) return;
     const unsigned long long k = edge_key(x, y);
-    for (uint32_t z = 0; z < *count; ++z)
+    for (uint32_t z = 0; z < count; ++z)
       if (edge_key(out[z].a, out[z].b) == k) return;
-    if (*count >= cap) return;
-    const Ent e = seg_of(*G, x, off)[i];
-    out[*count] = AddRec{x, y, e.qw, 0u, e.rinv, wseg_of(*G, x, off)[i]};
-    ++*count;
+    if (count >= cap) return;
+    const Ent e = seg_of(G, x, off)[i];
+    out[count] = AddRec{x, y, e.qw, 0u, e.rinv, wseg_of(G, x, off)[i]};
+    ++count;
   }
 };
 
@@ -613,20 +692,21 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
   if (base + cap <= a.hadd_cap) {
     AddRec* out = a.hadd + base;
     if (any_hit) {
-      RecoverSink sink{&G, &H, out, cap, &count};
+      RecoverSink sink{G, H, out, cap, 0u};
       walk_one(P, bestW, sink);  // replay: same counters, same snapshot
+      count = sink.count;
     } else {
       // no hit: per endpoint the least-resistance G edge not in H
-      const uint32_t ends[2] = {P.p, P.q};
       for (int z = 0; z < 2; ++z) {
-        const RowHdr r = row_hdr(G, ends[z]);
-        const Ent* seg = seg_of(G, ends[z], r.off);
+        const uint32_t end = z == 0 ? P.p : P.q;
+        const RowHdr r = row_hdr(G, end);
+        const Ent* seg = seg_of(G, end, r.off);
         int best = -1;
         double bestr = 0.0;
         for (uint32_t i = 0; i < r.len; ++i) {
           const Ent e = seg[i];
           if (e.qw == 0u) continue;
-          if (has_live(H, ends[z], e.nbr)) continue;
+          if (has_live(H, end, e.nbr)) continue;
           if (best < 0 || e.rinv < bestr) {
             best = static_cast<int>(i);
             bestr = e.rinv;
@@ -634,8 +714,8 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
         }
         if (best >= 0) {
           const Ent e = seg[best];
-          out[count++] = AddRec{ends[z], e.nbr, e.qw, 0u, e.rinv,
-                                wseg_of(G, ends[z], r.off)[best]};
+          out[count++] = AddRec{end, e.nbr, e.qw, 0u, e.rinv,
+                                wseg_of(G, end, r.off)[best]};
         }
       }
     }
@@ -648,7 +728,7 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
 // Plain form: one wavefront per update, one lane per walker (more walkers
 // than lanes run in successive rounds of 64).
 __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& G = a.g[0];
   const DevGraph& H = a.g[1];
   if (batch_failed(a.ctl)) return;
@@ -672,7 +752,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
     const uint32_t walker = base + lane;
     const bool active = walker < v.s;
     Walk o{0, v.P.p, 0.0, false, 0};
-    if (active) o = walk_one(v.P, walker, NoSink{});
+    NoSink none;
+    if (active) o = walk_one(v.P, walker, none);
     if (active && a.wrec)
       a.wrec[a.wofs[upd] + walker] =
           WalkerRec{static_cast<uint8_t>(o.hit), 0, static_cast<uint16_t>(o.steps), o.end, o.R};
@@ -698,7 +779,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
 
 // Walkers per update once phase 1 is known.
 __global__ void k_count_walkers(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   if (batch_failed(a.ctl)) return;
   const uint32_t upd = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nu = a.n_ins + a.n_del;
@@ -739,7 +820,7 @@ __device__ unsigned long long block_excl_scan(unsigned long long v, unsigned lon
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   if (batch_failed(a.ctl)) return;
   const uint32_t nu = a.n_ins + a.n_del;
   const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
@@ -760,7 +841,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const BatchArgs* const* _
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_top(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const uint32_t tiles = (a.n_ins + a.n_del + kScanTile - 1) / kScanTile;
   if (batch_failed(a.ctl)) return;
   unsigned long long carry = 0;
@@ -777,7 +858,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(const BatchArgs* const* __r
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_add(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   if (batch_failed(a.ctl)) return;
   const uint32_t nu = a.n_ins + a.n_del;
   const uint64_t base = uint64_t(blockIdx.x) * kScanTile;
@@ -788,7 +869,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(const BatchArgs* const* __r
 
 // Queue items: one wavefront per update writes one record per walker.
 __global__ __launch_bounds__(kBlock) void k_expand_items(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t upd = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
@@ -818,7 +899,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_items(const BatchArgs* const*
 // walker's outcome goes to wres[item].  A batch that failed validation queued
 // no items.
 __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a0 = *argv[0];
+  const BatchArgs a0 = load_args(argv, 0);
   BatchCtl* q = a0.qctl;
   const WalkItem* __restrict__ items = a0.items;  // shared by all batches of the launch
   WalkerRec* __restrict__ wres = a0.wres;
@@ -873,7 +954,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
       pool_next += take;
     }
     // (2) one step of every running walker
-    if (active && !walk_step(P, walker, S, NoSink{})) {
+    NoSink none;
+    if (active && !walk_step(P, walker, S, none)) {
       wres[item] = WalkerRec{static_cast<uint8_t>(S.hit), 0, static_cast<uint16_t>(S.steps),
                              S.x, S.R};
       steps += S.steps;
@@ -884,30 +966,30 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
     if (pending) {
       const uint32_t b = rec.walker >> kWalkerBits;
       if (b != cur_b && (steps | bytes)) {
-        atomicAdd(&argv[cur_b]->ctl->steps_total, steps);
-        atomicAdd(&argv[cur_b]->ctl->alg_bytes_total, bytes);
+        atomicAdd(&ctl_of(argv, cur_b)->steps_total, steps);
+        atomicAdd(&ctl_of(argv, cur_b)->alg_bytes_total, bytes);
         steps = bytes = 0;
       }
       cur_b = b;
-      const BatchArgs& A = *argv[b];
+      const gptr<const BatchArgs> A = args_of(argv, b);
       item = next_item;
-      const bool is_ins = rec.upd < A.n_ins;
-      const uint64_t uid = A.uid_base + rec.upd;
+      const bool is_ins = rec.upd < A->n_ins;
+      const uint64_t uid = A->uid_base + rec.upd;
       P.p = rec.p;
       P.q = rec.q;
-      P.use_K = is_ins && A.has_K;
+      P.use_K = is_ins && A->has_K;
       P.w_pq = rec.w_pq;
-      P.K = A.K;
+      P.K = A->K;
       P.L = rec.L;
-      P.key0 = static_cast<uint32_t>(A.seed);
-      P.key1 = static_cast<uint32_t>(A.seed >> 32);
+      P.key0 = static_cast<uint32_t>(A->seed);
+      P.key1 = static_cast<uint32_t>(A->seed >> 32);
       P.uid_lo = static_cast<uint32_t>(uid);
       P.uid_hi = static_cast<uint32_t>(uid >> 32);
-      P.bounce = A.bounce != 0;
-      const DevGraph& X = A.g[is_ins ? 1 : 0];  // H_mid for insertions, G_mid for deletions
-      P.rows = X.rows;
-      P.ent = X.ent;
-      P.pfx = X.pfx;
+      P.bounce = A->bounce != 0;
+      const int gw = is_ins ? 1 : 0;  // H_mid for insertions, G_mid for deletions
+      P.rows = load_gptr(&A->g[gw].rows);
+      P.ent = load_gptr(&A->g[gw].ent);
+      P.pfx = load_gptr(&A->g[gw].pfx);
       walker = rec.walker & ((1u << kWalkerBits) - 1u);
       walker_start(S, rec.p);
       active = true;
@@ -923,18 +1005,18 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
     const unsigned long long ws = wave_sum64(steps);
     const unsigned long long wb = wave_sum64(bytes);
     if (lane == 0 && (ws | wb)) {
-      atomicAdd(&argv[b0]->ctl->steps_total, ws);
-      atomicAdd(&argv[b0]->ctl->alg_bytes_total, wb);
+      atomicAdd(&ctl_of(argv, b0)->steps_total, ws);
+      atomicAdd(&ctl_of(argv, b0)->alg_bytes_total, wb);
     }
   } else if (has) {
-    atomicAdd(&argv[cur_b]->ctl->steps_total, steps);
-    atomicAdd(&argv[cur_b]->ctl->alg_bytes_total, bytes);
+    atomicAdd(&ctl_of(argv, cur_b)->steps_total, steps);
+    atomicAdd(&ctl_of(argv, cur_b)->alg_bytes_total, bytes);
   }
 }
 
 // Reduce each update's walker records and decide it (one wavefront per update).
 __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs& a = *argv[blockIdx.y];
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& G = a.g[0];
   const DevGraph& H = a.g[1];
   if (batch_failed(a.ctl)) return;
@@ -957,8 +1039,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
   for (uint32_t base = 0; base < v.s; base += kWave) {
     const uint32_t walker = base + lane;
     const bool active = walker < v.s;
-    WalkerRec o{0, 0, 0, v.P.p, 0.0};
-    if (active) o = a.wres[first + walker];
+    // lanes past the last walker read walker `base` (in range); every use of
+    // the record below is guarded by `active`
+    const WalkerRec o = a.wres[first + (active ? walker : base)];
     if (active && a.wrec) a.wrec[a.wofs[upd] + walker] = o;
     const bool h = active && o.hit;
     any_hit = any_hit || (__ballot(h) != 0ull);
@@ -1001,8 +1084,9 @@ __device__ __forceinline__ uint32_t add_count(const BatchArgs& a, int which) {
   return 2u * (c < a.hadd_cap ? c : a.hadd_cap);
 }
 
-__global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1048,8 +1132,9 @@ constexpr uint32_t kWideRelocate = 1u << 30;
 constexpr uint32_t kWideMerge = 1u << 31;
 constexpr uint32_t kCountMask = kWideRelocate - 1u;
 
-__global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1069,16 +1154,18 @@ __global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, int which
   a.touched_need[which][t] = need;
 }
 
-__global__ void k_pool_check(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ void k_pool_check(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const uint64_t pool_cap = a.g[which].pool_cap;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (batch_failed(a.ctl)) return;
   if (a.ctl->pool_top[which] + a.ctl->need[which] > pool_cap) a.ctl->nomem[which] = 1;
 }
 
-__global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1105,8 +1192,9 @@ __global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv, int w
 
 // Relocation of long segments: one workgroup per segment, tombstones dropped
 // through a block-wide scan of the live flags.
-__global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ uint32_t s_off;
@@ -1144,8 +1232,9 @@ __global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* 
   }
 }
 
-__global__ void k_add_place(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ void k_add_place(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1161,8 +1250,9 @@ __global__ void k_add_place(const BatchArgs* const* __restrict__ argv, int which
 
 // Merge the k appended entries (unsorted tail) into the sorted segment; one
 // thread per short segment (insertion of each new entry).
-__global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1197,8 +1287,9 @@ constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 K
 // entries below them; new entries sit after the old entries below them) and
 // moves the old entries right to left in block-sized chunks, so no entry is
 // overwritten before it is read.
-__global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ unsigned long long s_key[kTailChunk];  // (nbr << 32) | local index
@@ -1296,8 +1387,9 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* con
 }
 
 // Long segments touched by phase 4 need their prefix rebuilt.
-__global__ void k_mark_merged(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ void k_mark_merged(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1308,16 +1400,18 @@ __global__ void k_mark_merged(const BatchArgs* const* __restrict__ argv, int whi
 
 // After a pool shortfall: undo the per-row counters so phase 4 can run again
 // once the pool has grown.
-__global__ void k_phase4_reset(const BatchArgs* const* __restrict__ argv, int which) {
-  const BatchArgs& a = *argv[blockIdx.y];
+template <int which>
+__global__ void k_phase4_reset(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph& X = a.g[which];
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
   X.pending[a.touched_rows[which][t]] = 0u;
 }
 
-__global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv, int which) {
-  BatchCtl* ctl = argv[blockIdx.y]->ctl;
+template <int which>
+__global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv) {
+  BatchCtl* ctl = ctl_of(argv, blockIdx.y);
   if (threadIdx.x == 0) {
     ctl->touched[which] = 0;
     ctl->need[which] = 0;
@@ -1360,8 +1454,8 @@ void launch_phase1(const Launch& L, hipStream_t st) {
   if (L.max_del == 0) return;
   k_phase1<<<grid_of(L.max_del, L.F), kBlock, 0, st>>>(L.argv);
   // walks read the prefix of long segments: rebuild the ones just changed
-  k_hub_prefix<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, 0);
-  k_hub_prefix<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, 1);
+  k_hub_prefix<0><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
+  k_hub_prefix<1><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
   k_dirty_reset<<<dim3(1, L.F), 64, 0, st>>>(L.argv);
 }
 
@@ -1382,33 +1476,49 @@ void launch_walks_queue(const Launch& L, hipStream_t st) {
   k_reduce_updates<<<grid_of(L.max_nu, L.F, per), kWalkBlock, 0, st>>>(L.argv);
 }
 
-void launch_phase4(const Launch& L, int which, hipStream_t st) {
+namespace {
+
+template <int W>
+void phase4_sequence(const Launch& L, hipStream_t st) {
   // upper bound of the directed entries and of the touched rows
-  const uint64_t cap = which == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
+  const uint64_t cap = W == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
   if (cap == 0) return;
-  if (which == 1) {
+  if (W == 1) {
     const uint32_t nb = blocks_for(L.max_hash_slots) < 4096 ? blocks_for(L.max_hash_slots) : 4096;
     k_clear_hash<<<dim3(nb ? nb : 1, L.F), kBlock, 0, st>>>(L.argv);
   }
   const dim3 g = grid_of(cap, L.F);
-  k_add_prepare<<<g, kBlock, 0, st>>>(L.argv, which);
-  k_rows_plan<<<g, kBlock, 0, st>>>(L.argv, which);
-  k_pool_check<<<dim3(1, L.F), 64, 0, st>>>(L.argv, which);
-  k_rows_relocate<<<g, kBlock, 0, st>>>(L.argv, which);
-  k_rows_relocate_wide<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, which);
-  k_add_place<<<g, kBlock, 0, st>>>(L.argv, which);
-  k_rows_merge<<<g, kBlock, 0, st>>>(L.argv, which);
-  k_rows_merge_wide<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, which);
-  k_mark_merged<<<g, kBlock, 0, st>>>(L.argv, which);
-  k_hub_prefix<<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv, which);
+  k_add_prepare<W><<<g, kBlock, 0, st>>>(L.argv);
+  k_rows_plan<W><<<g, kBlock, 0, st>>>(L.argv);
+  k_pool_check<W><<<dim3(1, L.F), 64, 0, st>>>(L.argv);
+  k_rows_relocate<W><<<g, kBlock, 0, st>>>(L.argv);
+  k_rows_relocate_wide<W><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
+  k_add_place<W><<<g, kBlock, 0, st>>>(L.argv);
+  k_rows_merge<W><<<g, kBlock, 0, st>>>(L.argv);
+  k_rows_merge_wide<W><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
+  k_mark_merged<W><<<g, kBlock, 0, st>>>(L.argv);
+  k_hub_prefix<W><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
   k_dirty_reset<<<dim3(1, L.F), 64, 0, st>>>(L.argv);
 }
 
-void launch_phase4_reset(const Launch& L, int which, hipStream_t st) {
-  const uint64_t cap = which == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
+template <int W>
+void phase4_reset_sequence(const Launch& L, hipStream_t st) {
+  const uint64_t cap = W == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
   if (cap == 0) return;
-  k_phase4_reset<<<grid_of(cap, L.F), kBlock, 0, st>>>(L.argv, which);
-  k_phase4_reset_ctl<<<dim3(1, L.F), 64, 0, st>>>(L.argv, which);
+  k_phase4_reset<W><<<grid_of(cap, L.F), kBlock, 0, st>>>(L.argv);
+  k_phase4_reset_ctl<W><<<dim3(1, L.F), 64, 0, st>>>(L.argv);
+}
+
+}  // namespace
+
+void launch_phase4(const Launch& L, int which, hipStream_t st) {
+  if (which == 0) phase4_sequence<0>(L, st);
+  else phase4_sequence<1>(L, st);
+}
+
+void launch_phase4_reset(const Launch& L, int which, hipStream_t st) {
+  if (which == 0) phase4_reset_sequence<0>(L, st);
+  else phase4_reset_sequence<1>(L, st);
 }
 
 }  // namespace dyg
