@@ -142,7 +142,7 @@ struct dyg_ctx {
   uint64_t walk_launches = 0;
   double walk_ms_total = 0.0, walk_ms_last = 0.0, batch_ms_last = 0.0;
   // batch staging
-  DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, wrec, wofs, hadd, hash;
+  DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, ubytes, wrec, wofs, hadd, hash;
   DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2];
   DBuf qcount, qofs, qtile, items, wres;  // batched form
   uint32_t cus = 256;                      // compute units of the device
@@ -532,6 +532,7 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
   if (hash_slots > (1ull << 31)) return DYG_E_NOMEM;
   bool ok = c->ins_qw.ensure(4 * n_ins + 8) && c->ins_rinv.ensure(8 * n_ins + 8) &&
             c->in_h.ensure(n_del + 8) && c->res.ensure(sizeof(dyg_update_result) * nu + 8) &&
+            c->ubytes.ensure(4 * nu + 8) &&
             c->hadd.ensure(sizeof(AddRec) * hadd_cap + 8) &&
             c->hash.ensure(sizeof(HashSlot) * hash_slots) &&
             (walkers == 0 || (c->wrec.ensure(sizeof(dyg_walker_record) * walkers) &&
@@ -540,7 +541,7 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
     const uint64_t tiles = (nu + 1023) / 1024 + 1;
     ok = c->qcount.ensure(4 * nu + 8) && c->qofs.ensure(8 * nu + 8) &&
          c->qtile.ensure(8 * tiles + 8) && c->items.ensure(sizeof(dyg::WalkItem) * items_cap + 8) &&
-         c->wres.ensure(sizeof(dyg_walker_record) * items_cap + 16);
+         c->wres.ensure(sizeof(dyg::WalkOut) * items_cap + 16);
   }
   for (int g = 0; g < 2 && ok; ++g) {
     const uint64_t cap = g == 0 ? 2 * n_ins : 2 * hadd_cap;
@@ -585,6 +586,7 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
   a.wrec = record ? c->wrec.as<dyg::WalkerRec>() : nullptr;
   a.wofs = record ? c->wofs.as<uint64_t>() : nullptr;
   a.hadd = c->hadd.as<AddRec>();
+  a.ubytes = c->ubytes.as<uint32_t>();
   a.hadd_cap = static_cast<uint32_t>(hadd_cap);
   a.hash = c->hash.as<HashSlot>();
   a.hash_mask = static_cast<uint32_t>(hash_slots - 1);
@@ -605,7 +607,7 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
   a.qtile = c->qtile.as<unsigned long long>();
   a.items = c->items.as<dyg::WalkItem>();
   a.refill_min = c->refill_min;
-  a.wres = c->wres.as<dyg::WalkerRec>();
+  a.wres = c->wres.as<dyg::WalkOut>();
   return a;
 }
 
@@ -631,12 +633,17 @@ void launch_sequence(dyg_ctx* c, const BatchArgs& a, bool timed) {
   dyg::launch_batch_begin(L, c->stream);
   dyg::launch_validate(L, c->stream);
   dyg::launch_phase1(L, c->stream);
+  const bool batched = (c->params.flags & DYG_FLAG_BATCHED) != 0;
+  if (batched) dyg::launch_queue_prepare(L, c->stream);
+  // the timed region is the walk kernel alone
   if (timed) (void)hipEventRecord(c->ev[1], c->stream);
-  if (c->params.flags & DYG_FLAG_BATCHED)
-    dyg::launch_walks_queue(L, c->stream);
+  if (batched)
+    dyg::launch_walk_queue(L, c->stream);
   else
     dyg::launch_walks(L, c->stream);
   if (timed) (void)hipEventRecord(c->ev[2], c->stream);
+  if (batched) dyg::launch_queue_finish(L, c->stream);
+  dyg::launch_sum_counters(L, c->stream);
   dyg::launch_phase4(L, 0, c->stream);
   dyg::launch_phase4(L, 1, c->stream);
 }
@@ -1193,7 +1200,8 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
   if (c->dargv) (void)hipFree(c->dargv);
   if (c->hargs) (void)hipHostFree(c->hargs);
   DBuf* bufs[] = {&c->iu, &c->iv, &c->iw, &c->du, &c->dv, &c->s, &c->L, &c->ins_qw,
-                  &c->ins_rinv, &c->in_h, &c->res, &c->wrec, &c->wofs, &c->hadd, &c->hash};
+                  &c->ins_rinv, &c->in_h, &c->res, &c->ubytes, &c->wrec, &c->wofs, &c->hadd,
+                  &c->hash};
   for (DBuf* b : bufs) b->release();
   DBuf* qbufs[] = {&c->qcount, &c->qofs, &c->qtile, &c->items, &c->wres};
   for (DBuf* b : qbufs) b->release();
@@ -1337,7 +1345,7 @@ int stage_request(ServerRound& r, ServerRequest* q, dyg_ctx* c, uint64_t item_ca
                            c->res.as<dyg::UpdRes>(), false);
   a.qctl = r.qctl;
   a.items = r.items.as<dyg::WalkItem>();
-  a.wres = r.wres.as<dyg::WalkerRec>();
+  a.wres = r.wres.as<dyg::WalkOut>();
   (void)item_cap_total;
   e = hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, r.stream);
   if (e != hipSuccess) return fail_hip(e);
@@ -1351,7 +1359,7 @@ int launch_round(dyg_server* s, ServerRound& r) {
   uint64_t items = 0;
   for (ServerRequest* q : r.reqs) items += q->nu() * s->graphs[q->graph]->params.s_default;
   if (!r.items.ensure(sizeof(dyg::WalkItem) * items + 64) ||
-      !r.wres.ensure(sizeof(dyg_walker_record) * items + 64))
+      !r.wres.ensure(sizeof(dyg::WalkOut) * items + 64))
     return DYG_E_NOMEM;
   dyg::Launch L{};
   L.argv = r.argv;
@@ -1384,7 +1392,10 @@ int launch_round(dyg_server* s, ServerRound& r) {
   dyg::launch_batch_begin(L, r.stream);
   dyg::launch_validate(L, r.stream);
   dyg::launch_phase1(L, r.stream);
-  dyg::launch_walks_queue(L, r.stream);
+  dyg::launch_queue_prepare(L, r.stream);
+  dyg::launch_walk_queue(L, r.stream);
+  dyg::launch_queue_finish(L, r.stream);
+  dyg::launch_sum_counters(L, r.stream);
   dyg::launch_phase4(L, 0, r.stream);
   dyg::launch_phase4(L, 1, r.stream);
   char* o = static_cast<char*>(r.pin_out.p);

@@ -104,10 +104,21 @@ struct WalkerRec {
 };
 static_assert(sizeof(WalkerRec) == 16, "WalkerRec layout");
 
+// Outcome of one queued walker (batched form): the public record plus the
+// algorithmic bytes its steps gathered.
+struct WalkOut {
+  uint32_t end;
+  uint16_t steps;
+  uint8_t hit, pad;
+  uint32_t bytes;
+  uint32_t pad2;
+  double R;
+};
+static_assert(sizeof(WalkOut) == 24, "WalkOut layout");
+
 // Device-resident control block of one batch.
 struct BatchCtl {
   unsigned long long err_key;   // min over (phase, update, code); ~0 = valid
-  uint32_t hadd_count;          // records appended for H
   uint32_t touched[2];          // touched rows, per graph (0 = G, 1 = H)
   unsigned long long need[2];   // pool slots needed by relocations, per graph
   uint32_t nomem[2];            // phase-4 pool shortfall, per graph
@@ -153,7 +164,8 @@ struct BatchArgs {
   UpdRes* res;          // [n_ins + n_del]
   WalkerRec* wrec;      // optional [sum s]
   const uint64_t* wofs; // optional [n_ins + n_del]
-  AddRec* hadd;         // [hadd_cap]
+  AddRec* hadd;         // [hadd_cap]: slot i for insertion i, then Lcap slots per deletion
+  uint32_t* ubytes;     // [n_ins + n_del] algorithmic bytes gathered by each update's walks
   uint32_t hadd_cap;
   HashSlot* hash;
   uint32_t hash_mask;
@@ -173,7 +185,7 @@ struct BatchArgs {
   unsigned long long* qtile;     // [tiles] scan carry
   WalkItem* items;               // [items] walker of each queue item
   uint32_t refill_min;           // idle lanes that trigger a refill (1..64)
-  WalkerRec* wres;               // [items] outcome of each walker
+  WalkOut* wres;                 // [items] outcome of each walker
 };
 
 // One launch of F batches (F = 1 for a single context; up to kMaxFused when a
@@ -193,9 +205,13 @@ void launch_validate(const Launch& L, hipStream_t stream);
 void launch_phase1(const Launch& L, hipStream_t stream);
 // Plain form: one wavefront per update.
 void launch_walks(const Launch& L, hipStream_t stream);
-// Batched form: count, scan, expand, one persistent queue walk over every
-// walker of the F batches, per-update reduction.
-void launch_walks_queue(const Launch& L, hipStream_t stream);
+// Batched form: count, scan and expand the walker items; one persistent
+// queue walk over every walker of the F batches; per-update reduction.
+void launch_queue_prepare(const Launch& L, hipStream_t stream);
+void launch_walk_queue(const Launch& L, hipStream_t stream);
+void launch_queue_finish(const Launch& L, hipStream_t stream);
+// Either form, after the walks: batch totals of steps and algorithmic bytes.
+void launch_sum_counters(const Launch& L, hipStream_t stream);
 // Phase 4 on one graph (which = 0: G += insertions, 1: H += hadd records).
 void launch_phase4(const Launch& L, int which, hipStream_t stream);
 void launch_phase4_reset(const Launch& L, int which, hipStream_t stream);

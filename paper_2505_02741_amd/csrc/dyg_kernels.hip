@@ -92,6 +92,7 @@ __device__ __forceinline__ BatchArgs load_args(const BatchArgs* const* __restric
   a.wrec = load_gptr(&ap->wrec);
   a.wofs = load_gptr(&ap->wofs);
   a.hadd = load_gptr(&ap->hadd);
+  a.ubytes = load_gptr(&ap->ubytes);
   a.hash = load_gptr(&ap->hash);
   load_graph(a.g[0], ap, 0);
   load_graph(a.g[1], ap, 1);
@@ -228,7 +229,6 @@ __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
   }
   if (threadIdx.x == 0) {
     ctl->err_key = ~0ull;
-    ctl->hadd_count = 0;
     ctl->touched[0] = ctl->touched[1] = 0;
     ctl->need[0] = ctl->need[1] = 0;
     ctl->nomem[0] = ctl->nomem[1] = 0;
@@ -568,6 +568,12 @@ __device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, S
   return Walk{S.steps, S.x, S.R, S.hit, S.bytes};
 }
 
+// Index of this thread's wavefront in its block, as a value the compiler
+// knows to be the same on every lane (so per-wavefront data stays scalar).
+__device__ __forceinline__ uint32_t wave_in_block() {
+  return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave)));
+}
+
 // Wavefront argmin of (R, walker): smaller R wins, ties go to the lower walker.
 __device__ __forceinline__ void wave_argmin(double& R, uint32_t& w) {
 #pragma unroll
@@ -660,6 +666,31 @@ __device__ __forceinline__ UpdRes empty_result(bool is_ins) {
   return res;
 }
 
+// H additions have fixed slots: insertion i owns slot i, deletion j owns the
+// a.Lcap slots from n_ins + j * a.Lcap (unused ones hold kNoAdd).
+constexpr AddRec kNoAdd{kNone, kNone, 0u, 0u, 0.0, 0.0};
+
+__device__ __forceinline__ AddRec* del_slots(const BatchArgs& a, uint32_t upd) {
+  return a.hadd + a.n_ins + static_cast<uint64_t>(upd - a.n_ins) * a.Lcap;
+}
+
+// An update without walks (a deletion of an edge not in H): empty result and
+// empty slots, written by the lanes of one wavefront.
+__device__ __forceinline__ void no_walk_update(const BatchArgs& a, const UpdateView& v,
+                                               uint32_t upd, uint32_t lane) {
+  if (a.wrec)
+    for (uint32_t k = lane; k < v.s; k += kWave)
+      a.wrec[a.wofs[upd] + k] = WalkerRec{0, 0, 0, v.P.p, 0.0};
+  if (!v.is_ins) {
+    AddRec* out = del_slots(a, upd);
+    for (uint32_t z = lane; z < a.Lcap; z += kWave) out[z] = kNoAdd;
+  }
+  if (lane == 0) {
+    a.res[upd] = empty_result(v.is_ins);
+    a.ubytes[upd] = 0u;
+  }
+}
+
 // Decision of one update once its walkers are reduced (run by one lane):
 // an insertion is kept iff no walker reached q (Sec. III-B); a deletion of an
 // H edge recovers the winner's path edges missing from H, or the fallback
@@ -677,50 +708,43 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
   const WalkParams& P = v.P;
   if (v.is_ins) {
     res.flag = any_hit ? 0 : 1;
-    if (!any_hit) {
-      const uint32_t slot = atomicAdd(&a.ctl->hadd_count, 1u);
-      if (slot < a.hadd_cap)
-        a.hadd[slot] = AddRec{P.p, P.q, a.ins_qw[upd], 0u, a.ins_rinv[upd], a.iw[upd]};
-    }
+    a.hadd[upd] = any_hit ? kNoAdd
+                          : AddRec{P.p, P.q, a.ins_qw[upd], 0u, a.ins_rinv[upd], a.iw[upd]};
     a.res[upd] = res;
     return;
   }
   res.flag = 1;
-  const uint32_t cap = P.L > 2 ? P.L : 2;
-  const uint32_t base = atomicAdd(&a.ctl->hadd_count, cap);
+  const uint32_t cap = P.L > 2 ? P.L : 2;  // <= a.Lcap
+  AddRec* out = del_slots(a, upd);
   uint32_t count = 0;
-  if (base + cap <= a.hadd_cap) {
-    AddRec* out = a.hadd + base;
-    if (any_hit) {
-      RecoverSink sink{G, H, out, cap, 0u};
-      walk_one(P, bestW, sink);  // replay: same counters, same snapshot
-      count = sink.count;
-    } else {
-      // no hit: per endpoint the least-resistance G edge not in H
-      for (int z = 0; z < 2; ++z) {
-        const uint32_t end = z == 0 ? P.p : P.q;
-        const RowHdr r = row_hdr(G, end);
-        const Ent* seg = seg_of(G, end, r.off);
-        int best = -1;
-        double bestr = 0.0;
-        for (uint32_t i = 0; i < r.len; ++i) {
-          const Ent e = seg[i];
-          if (e.qw == 0u) continue;
-          if (has_live(H, end, e.nbr)) continue;
-          if (best < 0 || e.rinv < bestr) {
-            best = static_cast<int>(i);
-            bestr = e.rinv;
-          }
-        }
-        if (best >= 0) {
-          const Ent e = seg[best];
-          out[count++] = AddRec{end, e.nbr, e.qw, 0u, e.rinv,
-                                wseg_of(G, end, r.off)[best]};
+  if (any_hit) {
+    RecoverSink sink{G, H, out, cap, 0u};
+    walk_one(P, bestW, sink);  // replay: same counters, same snapshot
+    count = sink.count;
+  } else {
+    // no hit: per endpoint the least-resistance G edge not in H
+    for (int z = 0; z < 2; ++z) {
+      const uint32_t end = z == 0 ? P.p : P.q;
+      const RowHdr r = row_hdr(G, end);
+      const Ent* seg = seg_of(G, end, r.off);
+      int best = -1;
+      double bestr = 0.0;
+      for (uint32_t i = 0; i < r.len; ++i) {
+        const Ent e = seg[i];
+        if (e.qw == 0u) continue;
+        if (has_live(H, end, e.nbr)) continue;
+        if (best < 0 || e.rinv < bestr) {
+          best = static_cast<int>(i);
+          bestr = e.rinv;
         }
       }
+      if (best >= 0) {
+        const Ent e = seg[best];
+        out[count++] = AddRec{end, e.nbr, e.qw, 0u, e.rinv, wseg_of(G, end, r.off)[best]};
+      }
     }
-    for (uint32_t z = count; z < cap; ++z) out[z] = AddRec{kNone, kNone, 0u, 0u, 0.0, 0.0};
   }
+  for (uint32_t z = count; z < a.Lcap; ++z) out[z] = kNoAdd;
   res.n_rec = static_cast<uint16_t>(count);
   a.res[upd] = res;
 }
@@ -733,21 +757,17 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
   const DevGraph& H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + threadIdx.x / kWave;
+  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + wave_in_block();
   if (upd >= a.n_ins + a.n_del) return;  // uniform across the wavefront
   const UpdateView v = view_update(a, G, H, upd);
   if (!v.walks) {
-    if (a.wrec)
-      for (uint32_t k = lane; k < v.s; k += kWave)
-        a.wrec[a.wofs[upd] + k] = WalkerRec{0, 0, 0, v.P.p, 0.0};
-    if (lane == 0) a.res[upd] = empty_result(v.is_ins);
+    no_walk_update(a, v, upd, lane);
     return;
   }
   bool any_hit = false;
   double bestR = INFINITY;
   uint32_t bestW = kNone;
-  uint32_t steps = 0;
-  unsigned long long bytes = 0;
+  uint32_t steps = 0, bytes = 0;
   for (uint32_t base = 0; base < v.s; base += kWave) {
     const uint32_t walker = base + lane;
     const bool active = walker < v.s;
@@ -770,8 +790,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
     bytes += wave_sum(active ? o.bytes : 0u);
   }
   if (lane != 0) return;
-  atomicAdd(&a.ctl->steps_total, static_cast<unsigned long long>(steps));
-  atomicAdd(&a.ctl->alg_bytes_total, bytes);
+  a.ubytes[upd] = bytes;
   decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps);
 }
 
@@ -872,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_items(const BatchArgs* const*
   const BatchArgs a = load_args(argv, blockIdx.y);
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t upd = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const uint32_t upd = blockIdx.x * (kBlock / kWave) + wave_in_block();
   if (upd >= a.n_ins + a.n_del) return;
   const uint32_t cnt = a.qcount[upd];
   if (cnt == 0) return;
@@ -898,11 +917,17 @@ __global__ __launch_bounds__(kBlock) void k_expand_items(const BatchArgs* const*
 // and used after it, so its latency hides behind the step's own loads.  Every
 // walker's outcome goes to wres[item].  A batch that failed validation queued
 // no items.
+// Items a wavefront takes from the shared queue with one atomic.
+constexpr uint32_t kQueueChunk = 4 * kWave;
+
+// kFused: the launch carries several batches (items name theirs); otherwise
+// every item belongs to batch 0 and its per-batch values stay scalar.
+template <bool kFused>
 __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a0 = load_args(argv, 0);
   BatchCtl* q = a0.qctl;
   const WalkItem* __restrict__ items = a0.items;  // shared by all batches of the launch
-  WalkerRec* __restrict__ wres = a0.wres;
+  WalkOut* __restrict__ wres = a0.wres;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const unsigned long long total = q->walk_items;
   const unsigned long long lanes_below = (1ull << lane) - 1ull;
@@ -913,9 +938,11 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   unsigned long long item = 0, next_item = 0;
   WalkItem rec{0, 0, 0, 0, 0, 0.0};
   WalkParams P;
-  P.K = 0.0;
-  P.key0 = P.key1 = 0;
-  P.bounce = false;
+  // per-batch values: set once here for a single batch, per item when fused
+  P.K = a0.K;
+  P.key0 = static_cast<uint32_t>(a0.seed);
+  P.key1 = static_cast<uint32_t>(a0.seed >> 32);
+  P.bounce = a0.bounce != 0;
   P.rows = a0.g[1].rows;
   P.ent = a0.g[1].ent;
   P.pfx = a0.g[1].pfx;
@@ -924,10 +951,9 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   P.w_pq = 0.0;
   P.L = 0;
   P.uid_lo = P.uid_hi = 0;
-  uint32_t walker = 0, cur_b = 0;
+  uint32_t walker = 0;
   WState S;
   walker_start(S, 0);
-  unsigned long long steps = 0, bytes = 0;  // counters of batch cur_b
   while (true) {
     // (1) hand pool items to idle lanes
     const unsigned long long idle = __ballot(!active && !pending);
@@ -935,11 +961,11 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
     if (n_idle && (n_idle >= refill_min || n_idle == kWave)) {
       if (pool_next >= pool_end && !drained) {
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&q->queue_next, static_cast<unsigned long long>(kWave));
+        if (lane == 0) base = atomicAdd(&q->queue_next, static_cast<unsigned long long>(kQueueChunk));
         base = __shfl(base, 0, kWave);
         pool_next = base;
-        pool_end = base < total ? (base + kWave < total ? base + kWave : total) : base;
-        if (base + kWave >= total) drained = true;
+        pool_end = base < total ? (base + kQueueChunk < total ? base + kQueueChunk : total) : base;
+        if (base + kQueueChunk >= total) drained = true;
       }
       const unsigned long long avail = pool_end - pool_next;
       const uint32_t take = avail < n_idle ? static_cast<uint32_t>(avail) : n_idle;
@@ -956,61 +982,50 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
     // (2) one step of every running walker
     NoSink none;
     if (active && !walk_step(P, walker, S, none)) {
-      wres[item] = WalkerRec{static_cast<uint8_t>(S.hit), 0, static_cast<uint16_t>(S.steps),
-                             S.x, S.R};
-      steps += S.steps;
-      bytes += S.bytes;
+      wres[item] = WalkOut{S.x, static_cast<uint16_t>(S.steps), static_cast<uint8_t>(S.hit), 0,
+                           static_cast<uint32_t>(S.bytes), 0u, S.R};
       active = false;
     }
     // (3) lanes that received an item start its walker
     if (pending) {
-      const uint32_t b = rec.walker >> kWalkerBits;
-      if (b != cur_b && (steps | bytes)) {
-        atomicAdd(&ctl_of(argv, cur_b)->steps_total, steps);
-        atomicAdd(&ctl_of(argv, cur_b)->alg_bytes_total, bytes);
-        steps = bytes = 0;
-      }
-      cur_b = b;
-      const gptr<const BatchArgs> A = args_of(argv, b);
       item = next_item;
-      const bool is_ins = rec.upd < A->n_ins;
-      const uint64_t uid = A->uid_base + rec.upd;
+      if (kFused) {
+        const uint32_t b = rec.walker >> kWalkerBits;
+        const gptr<const BatchArgs> A = args_of(argv, b);
+        const bool is_ins = rec.upd < A->n_ins;
+        const uint64_t uid = A->uid_base + rec.upd;
+        P.use_K = is_ins && A->has_K;
+        P.K = A->K;
+        P.key0 = static_cast<uint32_t>(A->seed);
+        P.key1 = static_cast<uint32_t>(A->seed >> 32);
+        P.uid_lo = static_cast<uint32_t>(uid);
+        P.uid_hi = static_cast<uint32_t>(uid >> 32);
+        P.bounce = A->bounce != 0;
+        const int gw = is_ins ? 1 : 0;  // H_mid for insertions, G_mid for deletions
+        P.rows = load_gptr(&A->g[gw].rows);
+        P.ent = load_gptr(&A->g[gw].ent);
+        P.pfx = load_gptr(&A->g[gw].pfx);
+      } else {
+        const bool is_ins = rec.upd < a0.n_ins;
+        const uint64_t uid = a0.uid_base + rec.upd;
+        P.use_K = is_ins && a0.has_K;
+        P.uid_lo = static_cast<uint32_t>(uid);
+        P.uid_hi = static_cast<uint32_t>(uid >> 32);
+        const DevGraph& X = is_ins ? a0.g[1] : a0.g[0];  // H_mid / G_mid
+        P.rows = X.rows;
+        P.ent = X.ent;
+        P.pfx = X.pfx;
+      }
       P.p = rec.p;
       P.q = rec.q;
-      P.use_K = is_ins && A->has_K;
       P.w_pq = rec.w_pq;
-      P.K = A->K;
       P.L = rec.L;
-      P.key0 = static_cast<uint32_t>(A->seed);
-      P.key1 = static_cast<uint32_t>(A->seed >> 32);
-      P.uid_lo = static_cast<uint32_t>(uid);
-      P.uid_hi = static_cast<uint32_t>(uid >> 32);
-      P.bounce = A->bounce != 0;
-      const int gw = is_ins ? 1 : 0;  // H_mid for insertions, G_mid for deletions
-      P.rows = load_gptr(&A->g[gw].rows);
-      P.ent = load_gptr(&A->g[gw].ent);
-      P.pfx = load_gptr(&A->g[gw].pfx);
       walker = rec.walker & ((1u << kWalkerBits) - 1u);
       walker_start(S, rec.p);
       active = true;
       pending = false;
     }
     if (!__ballot(active) && drained && pool_next >= pool_end) break;
-  }
-  // flush the counters: one atomic per wavefront when all lanes hold the same batch
-  const bool has = (steps | bytes) != 0;
-  const uint32_t first = static_cast<uint32_t>(__builtin_ctzll(__ballot(has) | (1ull << 63)));
-  const uint32_t b0 = __shfl(cur_b, first, kWave);
-  if (__ballot(has && cur_b != b0) == 0ull) {
-    const unsigned long long ws = wave_sum64(steps);
-    const unsigned long long wb = wave_sum64(bytes);
-    if (lane == 0 && (ws | wb)) {
-      atomicAdd(&ctl_of(argv, b0)->steps_total, ws);
-      atomicAdd(&ctl_of(argv, b0)->alg_bytes_total, wb);
-    }
-  } else if (has) {
-    atomicAdd(&ctl_of(argv, cur_b)->steps_total, steps);
-    atomicAdd(&ctl_of(argv, cur_b)->alg_bytes_total, bytes);
   }
 }
 
@@ -1021,28 +1036,26 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
   const DevGraph& H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + threadIdx.x / kWave;
+  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + wave_in_block();
   if (upd >= a.n_ins + a.n_del) return;
   const UpdateView v = view_update(a, G, H, upd);
   if (!v.walks) {
-    if (a.wrec)
-      for (uint32_t k = lane; k < v.s; k += kWave)
-        a.wrec[a.wofs[upd] + k] = WalkerRec{0, 0, 0, v.P.p, 0.0};
-    if (lane == 0) a.res[upd] = empty_result(v.is_ins);
+    no_walk_update(a, v, upd, lane);
     return;
   }
   const unsigned long long first = a.ctl->item_base + a.qofs[upd];
   bool any_hit = false;
   double bestR = INFINITY;
   uint32_t bestW = kNone;
-  uint32_t steps = 0;
+  uint32_t steps = 0, bytes = 0;
   for (uint32_t base = 0; base < v.s; base += kWave) {
     const uint32_t walker = base + lane;
     const bool active = walker < v.s;
     // lanes past the last walker read walker `base` (in range); every use of
     // the record below is guarded by `active`
-    const WalkerRec o = a.wres[first + (active ? walker : base)];
-    if (active && a.wrec) a.wrec[a.wofs[upd] + walker] = o;
+    const WalkOut o = a.wres[first + (active ? walker : base)];
+    if (active && a.wrec)
+      a.wrec[a.wofs[upd] + walker] = WalkerRec{o.hit, 0, o.steps, o.end, o.R};
     const bool h = active && o.hit;
     any_hit = any_hit || (__ballot(h) != 0ull);
     double cR = h ? o.R : INFINITY;
@@ -1053,8 +1066,42 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
       bestW = cW;
     }
     steps += wave_sum(active ? static_cast<uint32_t>(o.steps) : 0u);
+    bytes += wave_sum(active ? o.bytes : 0u);
   }
-  if (lane == 0) decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps);
+  if (lane != 0) return;
+  a.ubytes[upd] = bytes;
+  decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps);
+}
+
+// Batch totals of walker steps and algorithmic bytes (from the per-update
+// counts), added to the context's running totals: one atomic per block.
+__global__ __launch_bounds__(kBlock) void k_sum_counters(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
+  if (batch_failed(a.ctl)) return;
+  const uint32_t nu = a.n_ins + a.n_del;
+  unsigned long long st = 0, by = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += gridDim.x * blockDim.x) {
+    st += a.res[i].steps;
+    by += a.ubytes[i];
+  }
+  __shared__ unsigned long long part[2][kBlock / kWave];
+  st = wave_sum64(st);
+  by = wave_sum64(by);
+  const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  if (lane == 0) {
+    part[0][wv] = st;
+    part[1][wv] = by;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st = by = 0;
+    for (uint32_t w = 0; w < kBlock / kWave; ++w) {
+      st += part[0][w];
+      by += part[1][w];
+    }
+    if (st) atomicAdd(&a.ctl->steps_total, st);
+    if (by) atomicAdd(&a.ctl->alg_bytes_total, by);
+  }
 }
 
 // ---- phase 4 ------------------------------------------------------------------------
@@ -1079,9 +1126,7 @@ __device__ __forceinline__ AddEntry add_entry(const BatchArgs& a, int which, uin
 }
 
 __device__ __forceinline__ uint32_t add_count(const BatchArgs& a, int which) {
-  if (which == 0) return 2u * a.n_ins;
-  const uint32_t c = a.ctl->hadd_count;
-  return 2u * (c < a.hadd_cap ? c : a.hadd_cap);
+  return which == 0 ? 2u * a.n_ins : 2u * a.hadd_cap;
 }
 
 template <int which>
@@ -1464,7 +1509,13 @@ void launch_walks(const Launch& L, hipStream_t st) {
   k_walks<<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
 }
 
-void launch_walks_queue(const Launch& L, hipStream_t st) {
+void launch_sum_counters(const Launch& L, hipStream_t st) {
+  if (L.max_nu == 0) return;
+  const uint32_t nb = blocks_for(L.max_nu) < 64 ? blocks_for(L.max_nu) : 64;
+  k_sum_counters<<<dim3(nb, L.F), kBlock, 0, st>>>(L.argv);
+}
+
+void launch_queue_prepare(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
   const uint32_t per = kWalkBlock / kWave;
   k_count_walkers<<<grid_of(L.max_nu, L.F), kBlock, 0, st>>>(L.argv);
@@ -1472,8 +1523,17 @@ void launch_walks_queue(const Launch& L, hipStream_t st) {
   k_scan_top<<<dim3(1, L.F), kBlock, 0, st>>>(L.argv);
   k_scan_add<<<grid_of(L.max_nu, L.F, kScanTile), kBlock, 0, st>>>(L.argv);
   k_expand_items<<<grid_of(L.max_nu, L.F, per), kBlock, 0, st>>>(L.argv);
-  k_walk_queue<<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
-  k_reduce_updates<<<grid_of(L.max_nu, L.F, per), kWalkBlock, 0, st>>>(L.argv);
+}
+
+void launch_walk_queue(const Launch& L, hipStream_t st) {
+  if (L.max_nu == 0) return;
+  if (L.F > 1) k_walk_queue<true><<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
+  else k_walk_queue<false><<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
+}
+
+void launch_queue_finish(const Launch& L, hipStream_t st) {
+  if (L.max_nu == 0) return;
+  k_reduce_updates<<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
 }
 
 namespace {
