@@ -27,6 +27,7 @@ using dyg::Row;
 using dyg::RowHdr;
 using dyg::kInline;
 using dyg::kInlineOff;
+using dyg::Pair;
 
 namespace {
 
@@ -109,6 +110,7 @@ struct HostAdj {
   std::vector<Ent> ent;                 // pool
   std::vector<double> w;                // pool weights
   std::vector<unsigned long long> pfx;  // inclusive qw prefix of long segments
+  std::vector<double> rinl;             // 1/w of inline entries, kInline per row
   std::vector<double> winl;             // weights of inline entries, kInline per row
 };
 
@@ -162,6 +164,7 @@ void free_graph(DevGraph& X) {
   if (X.pending) (void)hipFree(X.pending);
   if (X.pfx) (void)hipFree(X.pfx);
   if (X.mark) (void)hipFree(X.mark);
+  if (X.rinl) (void)hipFree(X.rinl);
   if (X.winl) (void)hipFree(X.winl);
   X = DevGraph{};
 }
@@ -180,6 +183,8 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (e = hipMalloc(&Y.pfx, sizeof(unsigned long long) * std::max<uint64_t>(pool_cap, 1))) !=
           hipSuccess ||
       (e = hipMalloc(&Y.mark, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
+      (e = hipMalloc(&Y.rinl, sizeof(double) * kInline * std::max<uint64_t>(n, 1))) !=
+          hipSuccess ||
       (e = hipMalloc(&Y.winl, sizeof(double) * kInline * std::max<uint64_t>(n, 1))) !=
           hipSuccess) {
     free_graph(Y);
@@ -196,6 +201,8 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (!A.pfx.empty() &&
        (e = hipMemcpyAsync(Y.pfx, A.pfx.data(), sizeof(unsigned long long) * A.pfx.size(),
                            hipMemcpyHostToDevice, st)) != hipSuccess) ||
+      (e = hipMemcpyAsync(Y.rinl, A.rinl.data(), sizeof(double) * A.rinl.size(),
+                          hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemcpyAsync(Y.winl, A.winl.data(), sizeof(double) * A.winl.size(),
                           hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemsetAsync(Y.pending, 0, sizeof(uint32_t) * n, st)) != hipSuccess ||
@@ -214,6 +221,7 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
 void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
             const std::vector<Ent>& live_ent, const std::vector<double>& live_w, double slack) {
   A.rows.assign(n, Row{});
+  A.rinl.assign(static_cast<size_t>(n) * kInline, 0.0);
   A.winl.assign(static_cast<size_t>(n) * kInline, 0.0);
   A.pfx.clear();
   uint64_t total = 0;
@@ -229,7 +237,9 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
     if (len <= kInline) {
       A.rows[u].h = RowHdr{kInlineOff, len, kInline, 0};
       for (uint32_t i = 0; i < len; ++i) {
-        A.rows[u].inl[i] = live_ent[start[u] + i];
+        const Ent& x = live_ent[start[u] + i];
+        A.rows[u].inl[i] = Pair{x.nbr, x.qw};
+        A.rinl[static_cast<size_t>(u) * kInline + i] = x.rinv;
         A.winl[static_cast<size_t>(u) * kInline + i] = live_w[start[u] + i];
       }
       continue;
@@ -262,10 +272,13 @@ int download_live(const DevGraph& X, uint32_t n, uint64_t used, std::vector<uint
                   std::vector<Ent>& live_ent, std::vector<double>& live_w, hipStream_t st) {
   std::vector<Row> rows(n);
   std::vector<Ent> ent(used);
-  std::vector<double> w(used), winl(static_cast<size_t>(n) * kInline);
+  std::vector<double> w(used), winl(static_cast<size_t>(n) * kInline),
+      rinl(static_cast<size_t>(n) * kInline);
   hipError_t e;
   if ((e = hipMemcpyAsync(rows.data(), X.rows, sizeof(Row) * n, hipMemcpyDeviceToHost, st)) !=
           hipSuccess ||
+      (e = hipMemcpyAsync(rinl.data(), X.rinl, sizeof(double) * rinl.size(),
+                          hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipMemcpyAsync(winl.data(), X.winl, sizeof(double) * winl.size(),
                           hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (used && (e = hipMemcpyAsync(ent.data(), X.ent, sizeof(Ent) * used, hipMemcpyDeviceToHost,
@@ -281,7 +294,8 @@ int download_live(const DevGraph& X, uint32_t n, uint64_t used, std::vector<uint
     const RowHdr r = rows[u].h;
     const bool inl = r.off == kInlineOff;
     for (uint32_t i = 0; i < r.len; ++i) {
-      const Ent& x = inl ? rows[u].inl[i] : ent[r.off + i];
+      const size_t k = static_cast<size_t>(u) * kInline + i;
+      const Ent x = inl ? Ent{rows[u].inl[i].nbr, rows[u].inl[i].qw, rinl[k]} : ent[r.off + i];
       if (x.qw == 0u) continue;
       live_ent.push_back(x);
       live_w.push_back(inl ? winl[static_cast<size_t>(u) * kInline + i] : w[r.off + i]);
@@ -1030,9 +1044,11 @@ struct HostImage {
   std::vector<Ent> ent;
   std::vector<double> w;
   std::vector<unsigned long long> pfx;
-  std::vector<double> winl;
-  const Ent* seg(uint32_t u) const {
-    return rows[u].h.off == kInlineOff ? rows[u].inl : ent.data() + rows[u].h.off;
+  std::vector<double> rinl, winl;
+  Ent get(uint32_t u, uint32_t i) const {
+    if (rows[u].h.off != kInlineOff) return ent[rows[u].h.off + i];
+    const Pair& p = rows[u].inl[i];
+    return Ent{p.nbr, p.qw, rinl[static_cast<size_t>(u) * kInline + i]};
   }
   double wt(uint32_t u, uint32_t i) const {
     return rows[u].h.off == kInlineOff ? winl[static_cast<size_t>(u) * kInline + i]
@@ -1045,8 +1061,12 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
   I.ent.resize(used);
   I.w.resize(used);
   I.pfx.resize(used);
+  I.rinl.resize(static_cast<size_t>(n) * kInline);
   I.winl.resize(static_cast<size_t>(n) * kInline);
   hipError_t e = hipMemcpyAsync(I.rows.data(), X.rows, sizeof(Row) * n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(I.rinl.data(), X.rinl, sizeof(double) * I.rinl.size(),
+                       hipMemcpyDeviceToHost, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(I.winl.data(), X.winl, sizeof(double) * I.winl.size(),
                        hipMemcpyDeviceToHost, st);
@@ -1063,14 +1083,13 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
 
 int find_live(const HostImage& I, uint32_t a, uint32_t b) {
   const RowHdr r = I.rows[a].h;
-  const Ent* seg = I.seg(a);
   uint32_t lo = 0, hi = r.len;
   while (lo < hi) {
     const uint32_t mid = (lo + hi) / 2;
-    if (seg[mid].nbr < b) lo = mid + 1;
+    if (I.get(a, mid).nbr < b) lo = mid + 1;
     else hi = mid;
   }
-  if (lo < r.len && seg[lo].nbr == b && seg[lo].qw != 0u) return static_cast<int>(lo);
+  if (lo < r.len && I.get(a, lo).nbr == b && I.get(a, lo).qw != 0u) return static_cast<int>(lo);
   return -1;
 }
 
@@ -1107,13 +1126,12 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
       if (!inl && static_cast<uint64_t>(r.off) + r.cap > ctl.pool_top[g])
         return fail("segment beyond pool top", g, u, r.off);
       if (!inl && r.cap) spans.push_back({r.off, static_cast<uint64_t>(r.off) + r.cap});
-      const Ent* seg = I.seg(u);
       uint32_t dead = 0;
       unsigned long long run = 0;
       for (uint32_t i = 0; i < r.len; ++i) {
-        const Ent& e = seg[i];
+        const Ent e = I.get(u, i);
         if (e.nbr >= c->n || e.nbr == u) return fail("bad neighbour id", g, u, i);
-        if (i && seg[i - 1].nbr >= e.nbr) return fail("segment not sorted", g, u, i);
+        if (i && I.get(u, i - 1).nbr >= e.nbr) return fail("segment not sorted", g, u, i);
         if (e.qw == 0u) ++dead;
         run += e.qw;
         if (!inl && r.len > dyg::kHub && I.pfx[r.off + i] != run)
@@ -1133,13 +1151,12 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
       if (spans[i].first < spans[i - 1].second) return fail("overlapping segments", g, i, 0);
     for (uint32_t u = 0; u < c->n; ++u) {
       const RowHdr r = I.rows[u].h;
-      const Ent* seg = I.seg(u);
       for (uint32_t i = 0; i < r.len; ++i) {
-        const Ent& e = seg[i];
+        const Ent e = I.get(u, i);
         if (e.qw == 0u) continue;
         const int j = find_live(I, e.nbr, u);
         if (j < 0) return fail("asymmetric edge", g, u, e.nbr);
-        const Ent& f = I.seg(e.nbr)[j];
+        const Ent f = I.get(e.nbr, j);
         if (f.qw != e.qw || I.wt(e.nbr, j) != I.wt(u, i))
           return fail("asymmetric weight", g, u, e.nbr);
       }
@@ -1147,9 +1164,8 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
   }
   for (uint32_t u = 0; u < c->n; ++u) {
     const RowHdr r = img[1].rows[u].h;
-    const Ent* seg = img[1].seg(u);
     for (uint32_t i = 0; i < r.len; ++i) {
-      const Ent& e = seg[i];
+      const Ent e = img[1].get(u, i);
       if (e.qw == 0u) continue;
       const int j = find_live(img[0], u, e.nbr);
       if (j < 0) return fail("H edge missing from G", 1, u, e.nbr);

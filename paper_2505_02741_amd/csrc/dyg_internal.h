@@ -10,13 +10,15 @@ namespace dyg {
 // ---------------------------------------------------------------------------
 // Device adjacency of one graph (the original graph G or the sparsifier H).
 //
-// Every vertex has a 64-byte row: a header and room for kInline entries.  A
-// vertex with at most kInline neighbours keeps them inside its row (one cache
-// line per walk step); a longer one owns a segment of the entry pool: `len`
-// entries in ascending neighbour order followed by `cap - len` free slots
-// (per-node slack).  A deleted edge stays in place as a tombstone (qw == 0)
-// until its segment is relocated or compacted; a zero weight never wins the
-// cumulative search, so walks skip tombstones without testing them.
+// Every vertex has a 64-byte row: a header and room for kInline (neighbour,
+// quantised weight) pairs.  A vertex with at most kInline neighbours keeps
+// those pairs inside its row, so a walk step there reads one cache line; their
+// resistances 1/w and weights sit in side arrays (rinl, winl) because a step
+// needs only the chosen one.  A longer row owns a segment of the entry pool:
+// `len` entries in ascending neighbour order followed by `cap - len` free
+// slots (per-node slack).  A deleted edge stays in place as a tombstone
+// (qw == 0) until its segment is relocated or compacted; a zero weight never
+// wins the cumulative search, so walks skip tombstones without testing them.
 // Neighbour ids are unique within a row (a re-inserted edge revives its
 // tombstone).
 struct Ent {
@@ -25,7 +27,7 @@ struct Ent {
   double rinv;   // resistance 1/w
 };
 
-constexpr uint32_t kInline = 3;              // entries stored inside the row
+constexpr uint32_t kInline = 6;              // pairs stored inside the row
 constexpr uint32_t kInlineOff = 0xFFFFFFFFu;  // `off` of a row whose entries are inline
 
 struct RowHdr {
@@ -35,9 +37,13 @@ struct RowHdr {
   uint32_t dead;  // tombstones among the len entries
 };
 
+struct Pair {
+  uint32_t nbr, qw;
+};
+
 struct Row {
   RowHdr h;
-  Ent inl[kInline];
+  Pair inl[kInline];
 };
 
 static_assert(sizeof(RowHdr) == 16, "RowHdr layout");
@@ -55,6 +61,7 @@ struct DevGraph {
   Row* rows = nullptr;        // [n] 64-byte rows
   Ent* ent = nullptr;         // [pool_cap]
   double* w = nullptr;        // [pool_cap] weight of each pool entry (cold)
+  double* rinl = nullptr;     // [n * kInline] 1/w of each inline entry
   double* winl = nullptr;     // [n * kInline] weight of each inline entry (cold)
   uint32_t* pending = nullptr;  // [n] per-row counter, zero between batches
   unsigned long long* pfx = nullptr;  // [pool_cap] inclusive qw prefix (rows with len > kHub)

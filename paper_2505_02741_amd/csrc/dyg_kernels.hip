@@ -66,6 +66,7 @@ __device__ __forceinline__ void load_graph(DevGraph& X, gptr<const BatchArgs> ap
   X.rows = load_gptr(&ap->g[w].rows);
   X.ent = load_gptr(&ap->g[w].ent);
   X.w = load_gptr(&ap->g[w].w);
+  X.rinl = load_gptr(&ap->g[w].rinl);
   X.winl = load_gptr(&ap->g[w].winl);
   X.pending = load_gptr(&ap->g[w].pending);
   X.pfx = load_gptr(&ap->g[w].pfx);
@@ -137,17 +138,51 @@ __device__ __forceinline__ RowHdr& row_hdr_ref(const DevGraph& X, uint32_t u) {
   return X.rows[u].h;
 }
 
-// Entries of row u (inline or in the pool) and their weights.
-__device__ __forceinline__ Ent* seg_of(const DevGraph& X, uint32_t u, uint32_t off) {
-  return off == kInlineOff ? X.rows[u].inl : X.ent + off;
+// Entries of one row, inline or in the pool: entry i has its (nbr, qw) pair
+// at words[i * stride], its 1/w at rinv[i * rstride] and its weight at w[i].
+struct Seg {
+  uint32_t* words;
+  uint32_t stride;   // 2 inline (Pair), 4 pool (Ent)
+  double* rinv;
+  uint32_t rstride;  // 1 inline (side array), 2 pool (Ent)
+  double* w;
+  __device__ __forceinline__ uint32_t nbr(uint32_t i) const { return words[i * stride]; }
+  __device__ __forceinline__ uint32_t& qw(uint32_t i) const { return words[i * stride + 1]; }
+  __device__ __forceinline__ double& r(uint32_t i) const { return rinv[i * rstride]; }
+  __device__ __forceinline__ Ent get(uint32_t i) const { return Ent{nbr(i), qw(i), r(i)}; }
+  __device__ __forceinline__ void put(uint32_t i, const Ent& e, double wt) const {
+    words[i * stride] = e.nbr;
+    words[i * stride + 1] = e.qw;
+    r(i) = e.rinv;
+    w[i] = wt;
+  }
+};
+
+// Row u's entries (off: its header's pool offset or kInlineOff).
+__device__ __forceinline__ Seg seg_of(const DevGraph& X, uint32_t u, uint32_t off) {
+  if (off == kInlineOff) {
+    const uint64_t b = static_cast<uint64_t>(u) * kInline;
+    return Seg{&X.rows[u].inl[0].nbr, 2u, X.rinl + b, 1u, X.winl + b};
+  }
+  Ent* e = X.ent + off;
+  return Seg{&e->nbr, 4u, &e->rinv, 2u, X.w + off};
 }
 
-__device__ __forceinline__ double* wseg_of(const DevGraph& X, uint32_t u, uint32_t off) {
-  return off == kInlineOff ? X.winl + static_cast<uint64_t>(u) * kInline : X.w + off;
+// Index of neighbour v among the first len entries (tombstones included), or -1.
+__device__ __forceinline__ int find_nbr(const Seg& seg, uint32_t len, uint32_t v) {
+  int lo = 0, hi = static_cast<int>(len) - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const uint32_t x = seg.nbr(mid);
+    if (x == v) return mid;
+    if (x < v) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
 }
 
-// Index of neighbour v among seg[0..len) (tombstones included), or -1.
-__device__ __forceinline__ int find_nbr(const Ent* seg, uint32_t len, uint32_t v) {
+// The same for a pool segment.
+__device__ __forceinline__ int find_nbr_pool(const Ent* seg, uint32_t len, uint32_t v) {
   int lo = 0, hi = static_cast<int>(len) - 1;
   while (lo <= hi) {
     const int mid = (lo + hi) >> 1;
@@ -161,9 +196,9 @@ __device__ __forceinline__ int find_nbr(const Ent* seg, uint32_t len, uint32_t v
 
 __device__ __forceinline__ bool has_live(const DevGraph& X, uint32_t a, uint32_t b) {
   const RowHdr h = row_hdr(X, a);
-  const Ent* seg = seg_of(X, a, h.off);
+  const Seg seg = seg_of(X, a, h.off);
   const int k = find_nbr(seg, h.len, b);
-  return k >= 0 && seg[k].qw != 0u;
+  return k >= 0 && seg.qw(k) != 0u;
 }
 
 // ---- hash table (validation duplicates, phase-4 dedup) ---------------------
@@ -281,7 +316,7 @@ __device__ __forceinline__ uint32_t quantize(double w, double w_ref, int Q) {
 
 __global__ void k_validate_b(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& G = a.g[0];
+  const DevGraph G = a.g[0];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_ins + a.n_del) return;
   if (i < a.n_ins) {
@@ -328,18 +363,18 @@ __device__ __forceinline__ void mark_dirty(const BatchArgs& a, const DevGraph& X
 __device__ __forceinline__ void tombstone(const BatchArgs& a, const DevGraph& X, int which,
                                           uint32_t u, uint32_t v) {
   const RowHdr h = row_hdr(X, u);
-  Ent* seg = seg_of(X, u, h.off);
+  const Seg seg = seg_of(X, u, h.off);
   const int k = find_nbr(seg, h.len, v);
   if (k < 0) return;
-  seg[k].qw = 0u;
+  seg.qw(k) = 0u;
   atomicAdd(&row_hdr_ref(X, u).dead, 1u);
   if (h.len > kHub) mark_dirty(a, X, which, u);
 }
 
 __global__ void k_phase1(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& G = a.g[0];
-  const DevGraph& H = a.g[1];
+  const DevGraph G = a.g[0];
+  const DevGraph H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n_del) return;
@@ -362,7 +397,7 @@ __device__ unsigned long long block_excl_scan(unsigned long long v, unsigned lon
 template <int which>
 __global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t count = a.ctl->dirty[which];
   for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
@@ -409,6 +444,7 @@ struct WalkParams {
   const Row* rows;
   const Ent* ent;
   const unsigned long long* pfx;
+  const double* rinl;
   uint32_t p, q;
   bool use_K;
   double w_pq, K;
@@ -426,6 +462,7 @@ struct NoSink {
 struct WState {
   uint32_t x, prev, steps, block_of, bytes;
   double R;
+  const double* rpend;  // 1/w of the last edge taken, not yet added to R
   Philox4 rnd;
   bool hit;
 };
@@ -437,6 +474,7 @@ __device__ __forceinline__ void walker_start(WState& S, uint32_t p) {
   S.block_of = kNone;
   S.bytes = 0;
   S.R = 0.0;
+  S.rpend = nullptr;
   S.hit = false;
 }
 
@@ -450,42 +488,82 @@ __device__ __forceinline__ unsigned long long step_random(WState& S, const WalkP
                   : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
 }
 
+// floor(r * tot / 2^64), the selection target.  With tot < 2^32 (every row
+// of fewer than 256 neighbours whose weights do not exceed w_ref) the high
+// half of the 128-bit product takes two 32x32 products: r*tot = rh*tot*2^32 +
+// rl*tot, and rh*tot + floor(rl*tot / 2^32) < 2^64.
+__device__ __forceinline__ unsigned long long scale_random(unsigned long long r,
+                                                           unsigned long long tot) {
+  if ((tot >> 32) == 0) {
+    const unsigned long long lo = (r & 0xFFFFFFFFull) * tot;
+    return ((r >> 32) * tot + (lo >> 32)) >> 32;
+  }
+  return __umul64hi(r, tot);
+}
+
 // One step of a walker: weight-biased choice among the neighbours other than
 // the previous vertex; stop on the distortion threshold, on reaching q, at a
 // dead end or after L steps (Sec. III-B).  Returns false once the walker has
-// stopped (then S holds its final state).  The whole 64-byte row is loaded at
-// once: for a vertex with at most kInline neighbours that is the only memory
-// access of the step.
+// stopped (then S holds its final state, R complete).  The whole 64-byte row
+// is loaded at once: for a vertex with at most kInline neighbours it is the
+// only dependent access of the step.  Without a threshold nothing decides on
+// R before the walk ends, so the 1/w of the edge taken is loaded with the next
+// step's row and added then (the additions keep their order).
 template <class Sink>
 __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
                                           Sink& sink) {
   const uint32_t t = S.steps;
-  if (t >= P.L) return false;
+  const bool has_prev = S.rpend != nullptr;
+  const double rprev = has_prev ? *S.rpend : 0.0;
+  if (t >= P.L) {
+    if (has_prev) S.R = S.R + rprev;
+    S.rpend = nullptr;
+    return false;
+  }
   const uint4* rq = reinterpret_cast<const uint4*>(P.rows + S.x);
   const uint4 q0 = rq[0], q1 = rq[1], q2 = rq[2], q3 = rq[3];
+  // the step's random number depends only on (walker, step, update): drawn
+  // while the row is in flight (a dead end leaves it unused)
+  const unsigned long long rnd = step_random(S, P, walker, t);
   const RowHdr h{q0.x, q0.y, q0.z, q0.w};
   uint32_t pick_nbr, pick_idx;
-  double pick_r;
+  const double* pick_r;
+  bool stop = false;
   if (h.off == kInlineOff) {
-    // inline entries: (nbr, qw, 1/w) in q1..q3
-    const uint32_t w0 = (h.len > 0 && q1.x != S.prev) ? q1.y : 0u;
-    const uint32_t w1 = (h.len > 1 && q2.x != S.prev) ? q2.y : 0u;
-    const uint32_t w2 = (h.len > 2 && q3.x != S.prev) ? q3.y : 0u;
-    const unsigned long long tot = uint64_t(w0) + w1 + w2;
+    // inline pairs (nbr, qw): q1 = pairs 0-1, q2 = 2-3, q3 = 4-5
+    static_assert(kInline == 6, "inline branch reads six pairs");
+    const uint32_t n0 = q1.x, n1 = q1.z, n2 = q2.x, n3 = q2.z, n4 = q3.x, n5 = q3.z;
+    const uint32_t c0 = (h.len > 0 && n0 != S.prev) ? q1.y : 0u;
+    const uint32_t c1 = (h.len > 1 && n1 != S.prev) ? q1.w : 0u;
+    const uint32_t c2 = (h.len > 2 && n2 != S.prev) ? q2.y : 0u;
+    const uint32_t c3 = (h.len > 3 && n3 != S.prev) ? q2.w : 0u;
+    const uint32_t c4 = (h.len > 4 && n4 != S.prev) ? q3.y : 0u;
+    const uint32_t c5 = (h.len > 5 && n5 != S.prev) ? q3.w : 0u;
+    // running sums (a zero weight never crosses the target)
+    const unsigned long long r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
+                             tot = r4 + c5;
     if (tot == 0) {
-      if (!(P.bounce && S.prev != kNone)) return false;  // leaf: the walker stops
-      // step back along the edge just used
-      if (h.len > 0 && q1.x == S.prev) pick_idx = 0;
-      else if (h.len > 1 && q2.x == S.prev) pick_idx = 1;
-      else if (h.len > 2 && q3.x == S.prev) pick_idx = 2;
-      else return false;  // cannot happen: the edge just used is live
+      // leaf: the walker stops, or steps back along the edge just used
+      const uint32_t back = (h.len > 0 && n0 == S.prev)   ? 0u
+                            : (h.len > 1 && n1 == S.prev) ? 1u
+                            : (h.len > 2 && n2 == S.prev) ? 2u
+                            : (h.len > 3 && n3 == S.prev) ? 3u
+                            : (h.len > 4 && n4 == S.prev) ? 4u
+                            : (h.len > 5 && n5 == S.prev) ? 5u
+                                                          : kNone;
+      stop = !(P.bounce && S.prev != kNone) || back == kNone;
+      pick_idx = back == kNone ? 0u : back;
     } else {
-      const unsigned long long target = __umul64hi(step_random(S, P, walker, t), tot);
-      pick_idx = (w0 > target) ? 0u : ((uint64_t(w0) + w1 > target) ? 1u : 2u);
+      const unsigned long long tg = scale_random(rnd, tot);
+      pick_idx = r0 > tg ? 0u : r1 > tg ? 1u : r2 > tg ? 2u : r3 > tg ? 3u : r4 > tg ? 4u : 5u;
     }
-    const uint4 qe = pick_idx == 0 ? q1 : (pick_idx == 1 ? q2 : q3);
-    pick_nbr = qe.x;
-    pick_r = __hiloint2double(static_cast<int>(qe.w), static_cast<int>(qe.z));
+    pick_nbr = pick_idx == 0   ? n0
+               : pick_idx == 1 ? n1
+               : pick_idx == 2 ? n2
+               : pick_idx == 3 ? n3
+               : pick_idx == 4 ? n4
+                               : n5;
+    pick_r = P.rinl + static_cast<uint64_t>(S.x) * kInline + pick_idx;
   } else if (h.len > kHub) {
     // long segment: the candidates' running sums are the stored prefix with
     // the previous vertex's weight taken out
@@ -494,15 +572,15 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
     int jp = -1;
     uint32_t qprev = 0;
     if (S.prev != kNone) {
-      jp = find_nbr(seg, h.len, S.prev);
+      jp = find_nbr_pool(seg, h.len, S.prev);
       if (jp >= 0) qprev = seg[jp].qw;
     }
     const unsigned long long tot = pf[h.len - 1] - qprev;
     if (tot == 0) {
-      if (!(P.bounce && jp >= 0)) return false;
-      pick_idx = static_cast<uint32_t>(jp);
+      stop = !(P.bounce && jp >= 0);
+      pick_idx = jp >= 0 ? static_cast<uint32_t>(jp) : 0u;
     } else {
-      unsigned long long target = __umul64hi(step_random(S, P, walker, t), tot);
+      unsigned long long target = scale_random(rnd, tot);
       if (jp >= 0 && target >= pf[jp] - qprev) target += qprev;
       uint32_t lo = 0, hi = h.len - 1;  // first i with pf[i] > target
       while (lo < hi) {
@@ -512,9 +590,8 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
       }
       pick_idx = lo;
     }
-    const Ent ce = seg[pick_idx];
-    pick_nbr = ce.nbr;
-    pick_r = ce.rinv;
+    pick_nbr = stop ? kNone : seg[pick_idx].nbr;
+    pick_r = &seg[pick_idx].rinv;
   } else {
     const Ent* seg = P.ent + h.off;
     const uint2* e2 = reinterpret_cast<const uint2*>(seg);  // (nbr, qw) pairs
@@ -523,13 +600,13 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
       const uint2 e = e2[2 * i];
       tot += (e.x != S.prev) ? e.y : 0u;
     }
+    pick_idx = 0;
     if (tot == 0) {
-      if (!(P.bounce && S.prev != kNone)) return false;  // leaf: the walker stops
-      const int back = find_nbr(seg, h.len, S.prev);
-      if (back < 0) return false;  // cannot happen: the edge just used is live
-      pick_idx = static_cast<uint32_t>(back);
+      const int back = (P.bounce && S.prev != kNone) ? find_nbr_pool(seg, h.len, S.prev) : -1;
+      stop = back < 0;  // leaf: the walker stops (the edge just used is always live)
+      pick_idx = back >= 0 ? static_cast<uint32_t>(back) : 0u;
     } else {
-      const unsigned long long target = __umul64hi(step_random(S, P, walker, t), tot);
+      const unsigned long long target = scale_random(rnd, tot);
       unsigned long long run = 0;
       pick_idx = h.len - 1;
       for (uint32_t i = 0; i < h.len; ++i) {
@@ -541,19 +618,27 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
         }
       }
     }
-    const Ent ce = seg[pick_idx];
-    pick_nbr = ce.nbr;
-    pick_r = ce.rinv;
+    pick_nbr = stop ? kNone : seg[pick_idx].nbr;
+    pick_r = &seg[pick_idx].rinv;
   }
+  if (has_prev) S.R = S.R + rprev;
+  S.rpend = nullptr;
+  if (stop) return false;
   S.bytes += step_bytes(h.len - h.dead);
-  S.R = S.R + pick_r;
   sink(S.x, pick_nbr, pick_idx, h.off);
   S.prev = S.x;
   S.x = pick_nbr;
   S.steps = t + 1;
-  if (P.use_K && P.w_pq * S.R > P.K) return false;
+  if (P.use_K) {
+    S.R = S.R + *pick_r;
+    if (P.w_pq * S.R > P.K) return false;
+  } else {
+    S.rpend = pick_r;
+  }
   if (S.x == P.q) {
     S.hit = true;
+    if (S.rpend) S.R = S.R + *S.rpend;
+    S.rpend = nullptr;
     return false;
   }
   return true;
@@ -612,8 +697,9 @@ struct RecoverSink {
     for (uint32_t z = 0; z < count; ++z)
       if (edge_key(out[z].a, out[z].b) == k) return;
     if (count >= cap) return;
-    const Ent e = seg_of(G, x, off)[i];
-    out[count] = AddRec{x, y, e.qw, 0u, e.rinv, wseg_of(G, x, off)[i]};
+    const Seg seg = seg_of(G, x, off);
+    const Ent e = seg.get(i);
+    out[count] = AddRec{x, y, e.qw, 0u, e.rinv, seg.w[i]};
     ++count;
   }
 };
@@ -648,6 +734,7 @@ __device__ __forceinline__ UpdateView view_update(const BatchArgs& a, const DevG
   P.rows = v.is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
   P.ent = v.is_ins ? H.ent : G.ent;
   P.pfx = v.is_ins ? H.pfx : G.pfx;
+  P.rinl = v.is_ins ? H.rinl : G.rinl;
   v.walks = v.is_ins || a.in_h[j];
   return v;
 }
@@ -695,9 +782,13 @@ __device__ __forceinline__ void no_walk_update(const BatchArgs& a, const UpdateV
 // an insertion is kept iff no walker reached q (Sec. III-B); a deletion of an
 // H edge recovers the winner's path edges missing from H, or the fallback
 // edges when nobody hit (Sec. III-C).
-__device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGraph& H,
-                              uint32_t upd, const UpdateView& v, bool any_hit, double bestR,
-                              uint32_t bestW, uint32_t steps) {
+__device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph& Gref,
+                                              const DevGraph& Href, uint32_t upd,
+                                              const UpdateView& v, bool any_hit, double bestR,
+                                              uint32_t bestW, uint32_t steps) {
+  // value copies: the inline-or-pool choices below then select between
+  // registers, not between fields of the argument record
+  const DevGraph G = Gref, H = Href;
   UpdRes res = empty_result(v.is_ins);
   res.any_hit = any_hit ? 1 : 0;
   res.steps = steps;
@@ -726,11 +817,11 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
     for (int z = 0; z < 2; ++z) {
       const uint32_t end = z == 0 ? P.p : P.q;
       const RowHdr r = row_hdr(G, end);
-      const Ent* seg = seg_of(G, end, r.off);
+      const Seg seg = seg_of(G, end, r.off);
       int best = -1;
       double bestr = 0.0;
       for (uint32_t i = 0; i < r.len; ++i) {
-        const Ent e = seg[i];
+        const Ent e = seg.get(i);
         if (e.qw == 0u) continue;
         if (has_live(H, end, e.nbr)) continue;
         if (best < 0 || e.rinv < bestr) {
@@ -739,8 +830,8 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
         }
       }
       if (best >= 0) {
-        const Ent e = seg[best];
-        out[count++] = AddRec{end, e.nbr, e.qw, 0u, e.rinv, wseg_of(G, end, r.off)[best]};
+        const Ent e = seg.get(best);
+        out[count++] = AddRec{end, e.nbr, e.qw, 0u, e.rinv, seg.w[best]};
       }
     }
   }
@@ -753,8 +844,8 @@ __device__ void decide_update(const BatchArgs& a, const DevGraph& G, const DevGr
 // than lanes run in successive rounds of 64).
 __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& G = a.g[0];
-  const DevGraph& H = a.g[1];
+  const DevGraph G = a.g[0];
+  const DevGraph H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + wave_in_block();
@@ -946,6 +1037,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   P.rows = a0.g[1].rows;
   P.ent = a0.g[1].ent;
   P.pfx = a0.g[1].pfx;
+  P.rinl = a0.g[1].rinl;
   P.p = P.q = 0;
   P.use_K = false;
   P.w_pq = 0.0;
@@ -1005,6 +1097,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         P.rows = load_gptr(&A->g[gw].rows);
         P.ent = load_gptr(&A->g[gw].ent);
         P.pfx = load_gptr(&A->g[gw].pfx);
+        P.rinl = load_gptr(&A->g[gw].rinl);
       } else {
         const bool is_ins = rec.upd < a0.n_ins;
         const uint64_t uid = a0.uid_base + rec.upd;
@@ -1015,6 +1108,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         P.rows = X.rows;
         P.ent = X.ent;
         P.pfx = X.pfx;
+        P.rinl = X.rinl;
       }
       P.p = rec.p;
       P.q = rec.q;
@@ -1032,8 +1126,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
 // Reduce each update's walker records and decide it (one wavefront per update).
 __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& G = a.g[0];
-  const DevGraph& H = a.g[1];
+  const DevGraph G = a.g[0];
+  const DevGraph H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + wave_in_block();
@@ -1132,7 +1226,7 @@ __device__ __forceinline__ uint32_t add_count(const BatchArgs& a, int which) {
 template <int which>
 __global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= add_count(a, which)) return;
@@ -1140,14 +1234,14 @@ __global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv) {
   const AddEntry d = add_entry(a, which, e);
   if (!d.valid) return;
   const RowHdr row = row_hdr(X, d.r);
-  Ent* seg = seg_of(X, d.r, row.off);
+  const Seg seg = seg_of(X, d.r, row.off);
   const int k = find_nbr(seg, row.len, d.c);
   if (k >= 0) {
     // a tombstone of the same edge: revive it in place (once)
-    const uint32_t old = atomicCAS(&seg[k].qw, 0u, d.qw);
+    const uint32_t old = atomicCAS(&seg.qw(k), 0u, d.qw);
     if (old == 0u) {
-      seg[k].rinv = d.rinv;
-      wseg_of(X, d.r, row.off)[k] = d.w;
+      seg.r(k) = d.rinv;
+      seg.w[k] = d.w;
       atomicSub(&row_hdr_ref(X, d.r).dead, 1u);
       if (row.len > kHub) mark_dirty(a, X, which, d.r);
     }
@@ -1180,7 +1274,7 @@ constexpr uint32_t kCountMask = kWideRelocate - 1u;
 template <int which>
 __global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl)) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
@@ -1211,7 +1305,7 @@ __global__ void k_pool_check(const BatchArgs* const* __restrict__ argv) {
 template <int which>
 __global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
@@ -1220,16 +1314,15 @@ __global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv) {
   if (a.touched_k[which][t] & kWideRelocate) return;  // moved by k_rows_relocate_wide
   const uint32_t r = a.touched_rows[which][t];
   const RowHdr row = row_hdr(X, r);
-  const Ent* src = seg_of(X, r, row.off);
-  const double* wsrc = wseg_of(X, r, row.off);
+  const Seg src = seg_of(X, r, row.off);
   const uint32_t off =
       static_cast<uint32_t>(atomicAdd(&a.ctl->pool_top[which], static_cast<unsigned long long>(need)));
   uint32_t o = 0;
   for (uint32_t i = 0; i < row.len; ++i) {
-    const Ent e = src[i];
+    const Ent e = src.get(i);
     if (e.qw == 0u) continue;  // drop tombstones while moving
     X.ent[off + o] = e;
-    X.w[off + o] = wsrc[i];
+    X.w[off + o] = src.w[i];
     ++o;
   }
   row_hdr_ref(X, r) = RowHdr{off, o, need, 0u};
@@ -1240,7 +1333,7 @@ __global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv) {
 template <int which>
 __global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ uint32_t s_off;
   const uint32_t count = a.ctl->touched[which];
@@ -1280,7 +1373,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* 
 template <int which>
 __global__ void k_add_place(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= add_count(a, which)) return;
@@ -1289,8 +1382,7 @@ __global__ void k_add_place(const BatchArgs* const* __restrict__ argv) {
   const RowHdr row = row_hdr(X, d.r);
   const uint32_t slot = atomicSub(&X.pending[d.r], 1u) - 1u;  // leaves pending at 0
   const uint32_t pos = row.len + slot;
-  seg_of(X, d.r, row.off)[pos] = Ent{d.c, d.qw, d.rinv};
-  wseg_of(X, d.r, row.off)[pos] = d.w;
+  seg_of(X, d.r, row.off).put(pos, Ent{d.c, d.qw, d.rinv}, d.w);
 }
 
 // Merge the k appended entries (unsorted tail) into the sorted segment; one
@@ -1298,7 +1390,7 @@ __global__ void k_add_place(const BatchArgs* const* __restrict__ argv) {
 template <int which>
 __global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
@@ -1307,19 +1399,16 @@ __global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv) {
   const uint32_t r = a.touched_rows[which][t];
   const uint32_t k = packed & kCountMask;
   const RowHdr row = row_hdr(X, r);
-  Ent* seg = seg_of(X, r, row.off);
-  double* wseg = wseg_of(X, r, row.off);
+  const Seg seg = seg_of(X, r, row.off);
   for (uint32_t j = row.len; j < row.len + k; ++j) {
-    const Ent e = seg[j];
-    const double we = wseg[j];
+    const Ent e = seg.get(j);
+    const double we = seg.w[j];
     uint32_t i = j;
-    while (i > 0 && seg[i - 1].nbr > e.nbr) {
-      seg[i] = seg[i - 1];
-      wseg[i] = wseg[i - 1];
+    while (i > 0 && seg.nbr(i - 1) > e.nbr) {
+      seg.put(i, seg.get(i - 1), seg.w[i - 1]);
       --i;
     }
-    seg[i] = e;
-    wseg[i] = we;
+    seg.put(i, e, we);
   }
   row_hdr_ref(X, r).len = row.len + k;
 }
@@ -1335,7 +1424,7 @@ constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 K
 template <int which>
 __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ unsigned long long s_key[kTailChunk];  // (nbr << 32) | local index
   __shared__ Ent s_ent[kTailChunk];
@@ -1435,7 +1524,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* con
 template <int which>
 __global__ void k_mark_merged(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
@@ -1448,7 +1537,7 @@ __global__ void k_mark_merged(const BatchArgs* const* __restrict__ argv) {
 template <int which>
 __global__ void k_phase4_reset(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph& X = a.g[which];
+  const DevGraph X = a.g[which];
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
   X.pending[a.touched_rows[which][t]] = 0u;

@@ -511,7 +511,9 @@ def make_workload(name: str, seed: int = 1, n_batches: int | None = None,
     if kind == "rmat":
         rowptr, col, _ = to_csr(n, u, v, w)
     for _ in range(cfg["batches"]):
-        if kind == "rmat":
+        if "size_lo" in cfg:
+            # uneven batches: size log-uniform in [size_lo, size_hi], each
+            # update an insertion with probability ins_frac
             size = int(math.floor(math.exp(rng.uniform(math.log(cfg["size_lo"]),
                                                        math.log(cfg["size_hi"])))))
             n_ins = int((rng.random(size) < cfg["ins_frac"]).sum())
@@ -528,7 +530,7 @@ def make_workload(name: str, seed: int = 1, n_batches: int | None = None,
         du, dv = uniform_deletions(es, n_del, rng) if n_del else (empty, empty)
         b = Batch(p.astype(np.uint32), q.astype(np.uint32), iw.astype(np.float64),
                   np.asarray(du, dtype=np.uint32), np.asarray(dv, dtype=np.uint32))
-        if "s_lo" in cfg:
+        if cfg.get("s_lo") is not None:
             b.s = rng.integers(cfg["s_lo"], cfg["s_hi"] + 1, b.size).astype(np.uint16)
             b.L = rng.integers(cfg["L_lo"], cfg["L_hi"] + 1, b.size).astype(np.uint16)
         es.apply(es.key(b.iu, b.iv), es.key(b.du, b.dv))
@@ -536,3 +538,34 @@ def make_workload(name: str, seed: int = 1, n_batches: int | None = None,
     return Workload(name=name, G=G, h_mask=h_mask, batches=batches,
                     seed_walk=walk_seed, s=cfg["s"], L=cfg["L"],
                     meta=dict(cfg=cfg, seed=seed))
+
+
+def make_fleet(n_graphs: int = 64, seed: int = 1, n_lo: int = 10_000, n_hi: int = 2_000_000,
+               batches_per_graph: int = 32, size_lo: int = 1, size_hi: int = 50_000,
+               ins_frac: float = 0.6, s: int = 64, L: int = 24) -> list:
+    """Many graphs for the serving form: kinds cycled grid / mesh / R-MAT, n
+    log-uniform in [n_lo, n_hi] (grid side sqrt(n), mesh side cbrt(n), R-MAT
+    scale ceil(log2 n)), each with its own seed and its own stream of uneven
+    batches (size log-uniform in [size_lo, min(size_hi, n/2)], ins_frac
+    insertions)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5EED]))
+    base = {"grid": "grid1024", "mesh": "mesh128", "rmat": "rmat22"}
+    out = []
+    for g in range(n_graphs):
+        kind = ("grid", "mesh", "rmat")[g % 3]
+        n = math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))
+        # batches up to half the vertex count, so small graphs are not swamped
+        hi = max(size_lo + 1, min(size_hi, int(n) // 2))
+        over = dict(size_lo=size_lo, size_hi=hi, ins_frac=ins_frac, s=s, L=L)
+        if kind == "grid":
+            over["side"] = max(8, int(round(math.sqrt(n))))
+        elif kind == "mesh":
+            over["side"] = max(6, int(round(n ** (1.0 / 3.0))))
+        else:
+            over["scale"] = max(10, int(math.ceil(math.log2(n))))
+            for k in ("s_lo", "s_hi", "L_lo", "L_hi"):
+                over[k] = None
+        wl = make_workload(base[kind], seed=seed * 1000 + g, n_batches=batches_per_graph, **over)
+        wl.name = f"{kind}{g}"
+        out.append(wl)
+    return out
