@@ -216,7 +216,11 @@ typedef struct {
   uint32_t walk_blocks_per_cu; /* persistent walk grid = CUs x this (1..64)       */
   uint32_t refill_min;         /* idle lanes of a wavefront that trigger a refill
                                   from its item pool (1..64)                       */
-  uint32_t reserved[6];
+  uint32_t updates_per_wave;   /* 0: one persistent work queue over every walker of
+                                  the launch; 1..8: each wavefront walks the walkers
+                                  of this many consecutive updates, a lane whose
+                                  walker stops taking the next one of that range   */
+  uint32_t reserved[5];
 } dyg_tuning;
 
 int dyg_get_tuning(dyg_ctx* ctx, dyg_tuning* out);

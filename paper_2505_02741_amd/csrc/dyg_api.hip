@@ -130,8 +130,10 @@ struct dyg_ctx {
   BatchCtl* ctl = nullptr;
   BatchArgs* dargs = nullptr;  // device copy of the current batch's arguments
   // DYG_FLAG_GRAPH: instantiated launch sequences by size class
-  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t>, hipGraphExec_t> graphs;
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t>, hipGraphExec_t> graphs;
   BatchArgs* hargs = nullptr;  // pinned host staging of the same
+  BatchCtl* hctl = nullptr;    // pinned copy of ctl, written at the end of each batch
+  hipEvent_t done_ev = nullptr;  // recorded after that copy
   const BatchArgs** dargv = nullptr;  // device array {dargs}: a launch of one batch
   uint64_t pool_top[2] = {0, 0};  // host mirror after the last sync
   bool broken = false;
@@ -145,11 +147,13 @@ struct dyg_ctx {
   double walk_ms_total = 0.0, walk_ms_last = 0.0, batch_ms_last = 0.0;
   // batch staging
   DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, ubytes, wrec, wofs, hadd, hash;
-  DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2];
+  DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2], wide_rows[2];
+  DBuf hash2;
   DBuf qcount, qofs, qtile, items, wres;  // batched form
   uint32_t cus = 256;                      // compute units of the device
   uint32_t walk_blocks_per_cu = 8;         // persistent walk grid = cus x this
   uint32_t refill_min = 1;                 // idle lanes that trigger a refill
+  uint32_t updates_per_wave = 4;           // range walk (0 = work queue)
   HBuf pin_in, pin_out;
 };
 
@@ -309,6 +313,16 @@ int sync_ctl_host(dyg_ctx* c, BatchCtl& out) {
   hipError_t e = hipMemcpyAsync(&out, c->ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail_hip(e);
+  c->pool_top[0] = out.pool_top[0];
+  c->pool_top[1] = out.pool_top[1];
+  return DYG_OK;
+}
+
+// Wait for the batch enqueued last and read the control block it copied back.
+int finish_ctl(dyg_ctx* c, BatchCtl& out) {
+  const hipError_t e = hipEventSynchronize(c->done_ev);
+  if (e != hipSuccess) return fail_hip(e);
+  out = *c->hctl;
   c->pool_top[0] = out.pool_top[0];
   c->pool_top[1] = out.pool_top[1];
   return DYG_OK;
@@ -507,6 +521,8 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
     e = hipMalloc(&c->ctl, sizeof(BatchCtl));
     if (e == hipSuccess) e = hipMalloc(&c->dargs, sizeof(BatchArgs));
     if (e == hipSuccess) e = hipHostMalloc(&c->hargs, sizeof(BatchArgs), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&c->hctl, sizeof(BatchCtl), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&c->dargv, sizeof(BatchArgs*));
     if (e == hipSuccess) {
       const BatchArgs* p = c->dargs;
@@ -549,6 +565,7 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
             c->ubytes.ensure(4 * nu + 8) &&
             c->hadd.ensure(sizeof(AddRec) * hadd_cap + 8) &&
             c->hash.ensure(sizeof(HashSlot) * hash_slots) &&
+            c->hash2.ensure(sizeof(HashSlot) * hash_slots) &&
             (walkers == 0 || (c->wrec.ensure(sizeof(dyg_walker_record) * walkers) &&
                               c->wofs.ensure(8 * nu + 8)));
   if (ok && (c->params.flags & DYG_FLAG_BATCHED)) {
@@ -561,7 +578,7 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
     const uint64_t cap = g == 0 ? 2 * n_ins : 2 * hadd_cap;
     ok = c->touched_rows[g].ensure(4 * cap + 8) && c->touched_k[g].ensure(4 * cap + 8) &&
          c->touched_need[g].ensure(4 * cap + 8) && c->add_keep[g].ensure(cap + 8) &&
-         c->dirty_rows[g].ensure(4 * (cap + 2 * n_del) + 8);
+         c->dirty_rows[g].ensure(4 * (cap + 2 * n_del) + 8) && c->wide_rows[g].ensure(4 * cap + 8);
   }
   return ok ? DYG_OK : DYG_E_NOMEM;
 }
@@ -603,6 +620,7 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
   a.ubytes = c->ubytes.as<uint32_t>();
   a.hadd_cap = static_cast<uint32_t>(hadd_cap);
   a.hash = c->hash.as<HashSlot>();
+  a.hash2 = c->hash2.as<HashSlot>();
   a.hash_mask = static_cast<uint32_t>(hash_slots - 1);
   a.hash_slots = hash_slots;
   a.g[0] = c->G;
@@ -615,12 +633,14 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
     a.touched_need[g] = c->touched_need[g].as<uint32_t>();
     a.add_keep[g] = c->add_keep[g].as<uint8_t>();
     a.dirty_rows[g] = c->dirty_rows[g].as<uint32_t>();
+    a.wide_rows[g] = c->wide_rows[g].as<uint32_t>();
   }
   a.qcount = c->qcount.as<uint32_t>();
   a.qofs = c->qofs.as<unsigned long long>();
   a.qtile = c->qtile.as<unsigned long long>();
   a.items = c->items.as<dyg::WalkItem>();
   a.refill_min = c->refill_min;
+  a.upw = c->updates_per_wave;
   a.wres = c->wres.as<dyg::WalkOut>();
   return a;
 }
@@ -636,6 +656,7 @@ dyg::Launch single_launch(dyg_ctx* c, const BatchArgs& a) {
   L.max_hadd_cap = a.hadd_cap;
   L.max_hash_slots = a.hash_slots;
   L.walk_blocks = c->cus * c->walk_blocks_per_cu;
+  L.upw = c->updates_per_wave;
   return L;
 }
 
@@ -658,8 +679,7 @@ void launch_sequence(dyg_ctx* c, const BatchArgs& a, bool timed) {
   if (timed) (void)hipEventRecord(c->ev[2], c->stream);
   if (batched) dyg::launch_queue_finish(L, c->stream);
   dyg::launch_sum_counters(L, c->stream);
-  dyg::launch_phase4(L, 0, c->stream);
-  dyg::launch_phase4(L, 1, c->stream);
+  dyg::launch_phase4_both(L, c->stream);
 }
 
 uint64_t size_class(uint64_t x) { return x ? next_pow2(x) : 0; }
@@ -673,7 +693,7 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
   cls.hash_slots = a.hash_slots;  // cleared by a grid-stride loop: any grid works
   const uint32_t wb = c->cus * c->walk_blocks_per_cu;
   const auto key = std::make_tuple(uint64_t(cls.n_ins), uint64_t(cls.n_del),
-                                   uint64_t(cls.hadd_cap), wb);
+                                   uint64_t(cls.hadd_cap), wb, c->updates_per_wave);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     *out = it->second;
@@ -717,6 +737,10 @@ int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a) {
   }
   if (timed) (void)hipEventRecord(c->ev[3], c->stream);
   c->timed_pending = timed && (a.n_ins + a.n_del) > 0;
+  // the batch's control block comes back with the batch: one wait at sync
+  e = hipMemcpyAsync(c->hctl, c->ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(c->done_ev, c->stream);
+  if (e != hipSuccess) return fail_hip(e);
   return DYG_OK;
 }
 
@@ -849,7 +873,7 @@ extern "C" int dyg_apply_batch(dyg_ctx* c, uint64_t n_ins, const uint32_t* iu,
   if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e);
 
   BatchCtl ctl;
-  int rc = sync_ctl_host(c, ctl);
+  int rc = finish_ctl(c, ctl);
   if (rc) return rc;
   collect_timing(c);
   rc = decode_err(ctl.err_key);
@@ -922,10 +946,8 @@ extern "C" int dyg_sync(dyg_ctx* c) {
   if (!c) return DYG_E_INVALID_ARG;
   if (!c->async_inflight) return DYG_OK;  // a batch's status is reported once
   c->async_inflight = false;
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return c->pending_status = fail_hip(e);
   BatchCtl ctl;
-  int rc = sync_ctl_host(c, ctl);
+  int rc = finish_ctl(c, ctl);
   if (rc) return c->pending_status = rc;
   collect_timing(c);
   rc = decode_err(ctl.err_key);
@@ -1180,16 +1202,18 @@ extern "C" int dyg_get_tuning(dyg_ctx* c, dyg_tuning* out) {
   std::memset(out, 0, sizeof(*out));
   out->walk_blocks_per_cu = c->walk_blocks_per_cu;
   out->refill_min = c->refill_min;
+  out->updates_per_wave = c->updates_per_wave;
   return DYG_OK;
 }
 
 extern "C" int dyg_set_tuning(dyg_ctx* c, const dyg_tuning* t) {
   if (!c || !t) return DYG_E_INVALID_ARG;
   if (t->walk_blocks_per_cu < 1 || t->walk_blocks_per_cu > 64 || t->refill_min < 1 ||
-      t->refill_min > 64)
+      t->refill_min > 64 || t->updates_per_wave > dyg::kMaxUpw)
     return DYG_E_INVALID_ARG;
   c->walk_blocks_per_cu = t->walk_blocks_per_cu;
   c->refill_min = t->refill_min;
+  c->updates_per_wave = t->updates_per_wave;
   return DYG_OK;
 }
 
@@ -1215,10 +1239,13 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
   if (c->dargs) (void)hipFree(c->dargs);
   if (c->dargv) (void)hipFree(c->dargv);
   if (c->hargs) (void)hipHostFree(c->hargs);
+  if (c->hctl) (void)hipHostFree(c->hctl);
+  if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   DBuf* bufs[] = {&c->iu, &c->iv, &c->iw, &c->du, &c->dv, &c->s, &c->L, &c->ins_qw,
                   &c->ins_rinv, &c->in_h, &c->res, &c->ubytes, &c->wrec, &c->wofs, &c->hadd,
                   &c->hash};
   for (DBuf* b : bufs) b->release();
+  c->hash2.release();
   DBuf* qbufs[] = {&c->qcount, &c->qofs, &c->qtile, &c->items, &c->wres};
   for (DBuf* b : qbufs) b->release();
   for (int g = 0; g < 2; ++g) {
@@ -1227,6 +1254,7 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
     c->touched_need[g].release();
     c->add_keep[g].release();
     c->dirty_rows[g].release();
+    c->wide_rows[g].release();
   }
   c->pin_in.release();
   c->pin_out.release();
@@ -1381,6 +1409,7 @@ int launch_round(dyg_server* s, ServerRound& r) {
   L.argv = r.argv;
   L.F = F;
   L.walk_blocks = s->graphs[r.reqs[0]->graph]->cus * s->p.walk_blocks_per_cu;
+  L.upw = s->graphs[r.reqs[0]->graph]->updates_per_wave;
   size_t out_bytes = 0;
   r.out_ofs.assign(F, 0);
   for (uint32_t i = 0; i < F; ++i) {
@@ -1412,8 +1441,7 @@ int launch_round(dyg_server* s, ServerRound& r) {
   dyg::launch_walk_queue(L, r.stream);
   dyg::launch_queue_finish(L, r.stream);
   dyg::launch_sum_counters(L, r.stream);
-  dyg::launch_phase4(L, 0, r.stream);
-  dyg::launch_phase4(L, 1, r.stream);
+  dyg::launch_phase4_both(L, r.stream);
   char* o = static_cast<char*>(r.pin_out.p);
   for (uint32_t i = 0; i < F; ++i) {
     dyg_ctx* c = s->graphs[r.reqs[i]->graph];

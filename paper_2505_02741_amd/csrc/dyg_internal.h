@@ -56,6 +56,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kHub = 64;
 constexpr uint32_t kMaxWalkers = 1024;
 constexpr uint32_t kMaxSteps = 1024;
+constexpr uint32_t kMaxUpw = 8;  // updates per wavefront of the range walk
 
 struct DevGraph {
   Row* rows = nullptr;        // [n] 64-byte rows
@@ -130,6 +131,8 @@ struct BatchCtl {
   unsigned long long need[2];   // pool slots needed by relocations, per graph
   uint32_t nomem[2];            // phase-4 pool shortfall, per graph
   uint32_t dirty[2];            // rows whose prefix must be rebuilt, per graph
+  uint32_t dirty_p1[2];         // of those, the ones listed by phase 1
+  uint32_t wide[2];             // touched rows moved or merged by a workgroup, per graph
   unsigned long long pool_top[2];  // next free pool slot, per graph
   unsigned long long walk_items;       // walkers queued (queue control only)
   unsigned long long queue_next;       // next queue item to hand out (queue control only)
@@ -174,7 +177,8 @@ struct BatchArgs {
   AddRec* hadd;         // [hadd_cap]: slot i for insertion i, then Lcap slots per deletion
   uint32_t* ubytes;     // [n_ins + n_del] algorithmic bytes gathered by each update's walks
   uint32_t hadd_cap;
-  HashSlot* hash;
+  HashSlot* hash;       // validation: repeats within the batch
+  HashSlot* hash2;      // phase 4: edges recovered more than once
   uint32_t hash_mask;
   uint64_t hash_slots;
   DevGraph g[2];              // 0 = G, 1 = H
@@ -186,12 +190,14 @@ struct BatchArgs {
   uint32_t* touched_need[2];
   uint8_t* add_keep[2];       // per directed add entry: 1 = needs a new slot
   uint32_t* dirty_rows[2];    // rows whose weight prefix must be rebuilt
+  uint32_t* wide_rows[2];     // indices into touched_* of the rows with a wide flag
   // batched form: walker work queue
   uint32_t* qcount;              // [n_ins + n_del] walkers of each update
   unsigned long long* qofs;      // [n_ins + n_del] first item of each update
   unsigned long long* qtile;     // [tiles] scan carry
   WalkItem* items;               // [items] walker of each queue item
   uint32_t refill_min;           // idle lanes that trigger a refill (1..64)
+  uint32_t upw;                  // updates per wavefront of the range walk (0 = queue)
   WalkOut* wres;                 // [items] outcome of each walker
 };
 
@@ -203,6 +209,7 @@ struct Launch {
   uint32_t max_nu, max_ins, max_del;  // largest batch of the launch (grid sizes)
   uint64_t max_hadd_cap, max_hash_slots;
   uint32_t walk_blocks;               // persistent walk grid
+  uint32_t upw;                       // updates per wavefront (0 = work queue)
 };
 
 // Host-side launchers (defined in dyg_kernels.hip), all asynchronous on
@@ -219,7 +226,9 @@ void launch_walk_queue(const Launch& L, hipStream_t stream);
 void launch_queue_finish(const Launch& L, hipStream_t stream);
 // Either form, after the walks: batch totals of steps and algorithmic bytes.
 void launch_sum_counters(const Launch& L, hipStream_t stream);
-// Phase 4 on one graph (which = 0: G += insertions, 1: H += hadd records).
+// Phase 4 on both graphs at once (G += insertions, H += hadd records), or on
+// one graph (which = 0: G, 1: H) when a pool repair re-runs it.
+void launch_phase4_both(const Launch& L, hipStream_t stream);
 void launch_phase4(const Launch& L, int which, hipStream_t stream);
 void launch_phase4_reset(const Launch& L, int which, hipStream_t stream);
 

@@ -95,6 +95,7 @@ __device__ __forceinline__ BatchArgs load_args(const BatchArgs* const* __restric
   a.hadd = load_gptr(&ap->hadd);
   a.ubytes = load_gptr(&ap->ubytes);
   a.hash = load_gptr(&ap->hash);
+  a.hash2 = load_gptr(&ap->hash2);
   load_graph(a.g[0], ap, 0);
   load_graph(a.g[1], ap, 1);
   a.ctl = load_gptr(&ap->ctl);
@@ -105,6 +106,7 @@ __device__ __forceinline__ BatchArgs load_args(const BatchArgs* const* __restric
     a.touched_need[w] = load_gptr(&ap->touched_need[w]);
     a.add_keep[w] = load_gptr(&ap->add_keep[w]);
     a.dirty_rows[w] = load_gptr(&ap->dirty_rows[w]);
+    a.wide_rows[w] = load_gptr(&ap->wide_rows[w]);
   }
   a.qcount = load_gptr(&ap->qcount);
   a.qofs = load_gptr(&ap->qofs);
@@ -255,29 +257,36 @@ __device__ bool hash_insert_first(HashSlot* h, uint32_t mask, unsigned long long
 
 // One workgroup per batch resets that batch's control block; the first also
 // resets the work-queue control the batches share.
+// Start of a batch: reset its control block (and, from batch 0, the shared
+// queue control of the launch) and clear both hash tables.
 __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
-  BatchCtl* ctl = ctl_of(argv, blockIdx.y);
-  if (threadIdx.x == 0 && blockIdx.y == 0) {
-    BatchCtl* q = load_gptr(&args_of(argv, 0)->qctl);
-    q->walk_items = 0;
-    q->queue_next = 0;
-  }
-  if (threadIdx.x == 0) {
+  const gptr<const BatchArgs> ap = args_of(argv, blockIdx.y);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    BatchCtl* ctl = load_gptr(&ap->ctl);
+    if (blockIdx.y == 0) {
+      BatchCtl* q = load_gptr(&args_of(argv, 0)->qctl);
+      q->walk_items = 0;
+      q->queue_next = 0;
+    }
     ctl->err_key = ~0ull;
-    ctl->touched[0] = ctl->touched[1] = 0;
-    ctl->need[0] = ctl->need[1] = 0;
-    ctl->nomem[0] = ctl->nomem[1] = 0;
-    ctl->dirty[0] = ctl->dirty[1] = 0;
+    for (int w = 0; w < 2; ++w) {
+      ctl->touched[w] = 0;
+      ctl->need[w] = 0;
+      ctl->nomem[w] = 0;
+      ctl->dirty[w] = 0;
+      ctl->dirty_p1[w] = 0;
+      ctl->wide[w] = 0;
+    }
   }
-}
-
-__global__ void k_clear_hash(const BatchArgs* const* __restrict__ argv) {
-  HashSlot* h = load_gptr(&args_of(argv, blockIdx.y)->hash);
-  const uint64_t slots = args_of(argv, blockIdx.y)->hash_slots;
+  HashSlot* h1 = load_gptr(&ap->hash);
+  HashSlot* h2 = load_gptr(&ap->hash2);
+  const uint64_t slots = ap->hash_slots;
   for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < slots;
        i += uint64_t(gridDim.x) * blockDim.x) {
-    h[i].key = ~0ull;
-    h[i].minidx = ~0u;
+    h1[i].key = ~0ull;
+    h1[i].minidx = ~0u;
+    h2[i].key = ~0ull;
+    h2[i].minidx = ~0u;
   }
 }
 
@@ -394,14 +403,24 @@ __device__ unsigned long long block_excl_scan(unsigned long long v, unsigned lon
 
 // Rebuild the inclusive weight prefix of every dirty row (one workgroup per
 // row), then clear its mark.
-template <int which>
-__global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
-  if (batch_failed(a.ctl)) return;
-  const uint32_t count = a.ctl->dirty[which];
-  for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
-    const uint32_t r = a.dirty_rows[which][t];
+// Rebuild the weight prefix of the long rows listed dirty since `from` (0
+// after phase 1; after phase 4, the rows phase 1 had not listed).  The graph
+// is which0 + blockIdx.z.
+__global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* __restrict__ argv,
+                                                       uint32_t which0, int after_phase1) {
+  const uint32_t which = which0 + blockIdx.z;
+  const gptr<const BatchArgs> ap = args_of(argv, blockIdx.y);
+  BatchCtl* ctl = load_gptr(&ap->ctl);
+  if (batch_failed(ctl)) return;
+  DevGraph X;
+  load_graph(X, ap, static_cast<int>(which));
+  const uint32_t* dirty_rows = load_gptr(&ap->dirty_rows[which]);
+  const uint32_t count = ctl->dirty[which];
+  const uint32_t from = after_phase1 ? ctl->dirty_p1[which] : 0u;
+  // phase 1's list ends here; phase 4 appends after it (same value from every block)
+  if (!after_phase1 && blockIdx.x == 0 && threadIdx.x == 0) ctl->dirty_p1[which] = count;
+  for (uint32_t t = from + blockIdx.x; t < count; t += gridDim.x) {
+    const uint32_t r = dirty_rows[t];
     const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment
     unsigned long long carry = 0;
     for (uint32_t base = 0; base < row.len; base += kBlock) {
@@ -414,11 +433,6 @@ __global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* _
     }
     if (threadIdx.x == 0) X.mark[r] = 0u;
   }
-}
-
-__global__ void k_dirty_reset(const BatchArgs* const* __restrict__ argv) {
-  BatchCtl* ctl = ctl_of(argv, blockIdx.y);
-  if (threadIdx.x == 0) ctl->dirty[0] = ctl->dirty[1] = 0;
 }
 
 // ---- walks ------------------------------------------------------------------------
@@ -1123,6 +1137,107 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   }
 }
 
+// Batched form, range walk: wavefront w of a batch walks every walker of
+// updates [w*upw, w*upw + upw).  Walker i of the range (updates in order,
+// qcount walkers each) goes to the next idle lane; a lane whose walker stops
+// takes the next one, so lanes stay busy until the range runs out.  A lane
+// that receives a walker loads its update's endpoints during the other lanes'
+// step and starts one iteration later.  Every walker's outcome goes to
+// wres[item_base + qofs[update] + walker] for the per-update reduction.
+__global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* __restrict__ argv,
+                                                       uint32_t upw) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
+  if (batch_failed(a.ctl)) return;
+  const uint32_t nu = a.n_ins + a.n_del;
+  const uint32_t u0 = (blockIdx.x * (kBlock / kWave) + wave_in_block()) * upw;
+  if (u0 >= nu) return;  // uniform across the wavefront
+  const uint32_t nr = (nu - u0) < upw ? (nu - u0) : upw;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const unsigned long long lanes_below = (1ull << lane) - 1ull;
+  // end (exclusive) of each update's walkers within the range
+  uint32_t endw[kMaxUpw];
+  uint32_t total = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kMaxUpw; ++j) {
+    if (j < nr) total += a.qcount[u0 + j];
+    endw[j] = total;
+  }
+  const unsigned long long base = a.ctl->item_base + a.qofs[u0];
+  const uint32_t refill_min = a.refill_min < 1 ? 1u : (a.refill_min > 64 ? 64u : a.refill_min);
+  WalkParams P;
+  P.K = a.K;
+  P.key0 = static_cast<uint32_t>(a.seed);
+  P.key1 = static_cast<uint32_t>(a.seed >> 32);
+  P.bounce = a.bounce != 0;
+  P.rows = a.g[1].rows;
+  P.ent = a.g[1].ent;
+  P.pfx = a.g[1].pfx;
+  P.rinl = a.g[1].rinl;
+  P.p = P.q = 0;
+  P.use_K = false;
+  P.w_pq = 0.0;
+  P.L = 0;
+  P.uid_lo = P.uid_hi = 0;
+  WState S;
+  walker_start(S, 0);
+  uint32_t next = 0;  // walkers of the range handed out so far (uniform)
+  uint32_t walker = 0;
+  unsigned long long item = 0;
+  bool active = false, pending = false;
+  while (true) {
+    // (1) hand the next walkers of the range to idle lanes
+    const unsigned long long idle = __ballot(!active && !pending);
+    const uint32_t n_idle = static_cast<uint32_t>(__popcll(idle));
+    if (next < total && n_idle && (n_idle >= refill_min || n_idle == kWave)) {
+      const uint32_t rank = static_cast<uint32_t>(__popcll(idle & lanes_below));
+      if (!active && !pending && next + rank < total) {
+        const uint32_t idx = next + rank;
+        uint32_t j = 0, start = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kMaxUpw; ++k)
+          if (endw[k] <= idx) {
+            j = k + 1;
+            start = endw[k];
+          }
+        const uint32_t upd = u0 + j;
+        const bool is_ins = upd < a.n_ins;
+        const uint32_t jd = upd - a.n_ins;
+        const uint64_t uid = a.uid_base + upd;
+        P.p = is_ins ? a.iu[upd] : a.du[jd];
+        P.q = is_ins ? a.iv[upd] : a.dv[jd];
+        P.w_pq = is_ins ? a.iw[upd] : 0.0;
+        P.use_K = is_ins && a.has_K;
+        P.L = a.L ? a.L[upd] : a.L_def;
+        P.uid_lo = static_cast<uint32_t>(uid);
+        P.uid_hi = static_cast<uint32_t>(uid >> 32);
+        const DevGraph& X = is_ins ? a.g[1] : a.g[0];  // H_mid for insertions, G_mid for deletions
+        P.rows = X.rows;
+        P.ent = X.ent;
+        P.pfx = X.pfx;
+        P.rinl = X.rinl;
+        walker = idx - start;
+        item = base + idx;
+        pending = true;
+      }
+      next = (next + n_idle) < total ? next + n_idle : total;
+    }
+    // (2) one step of every running walker
+    NoSink none;
+    if (active && !walk_step(P, walker, S, none)) {
+      a.wres[item] = WalkOut{S.x, static_cast<uint16_t>(S.steps), static_cast<uint8_t>(S.hit), 0,
+                             S.bytes, 0u, S.R};
+      active = false;
+    }
+    // (3) lanes that received a walker start it
+    if (pending) {
+      walker_start(S, P.p);
+      active = true;
+      pending = false;
+    }
+    if (__ballot(active) == 0ull && next >= total) break;
+  }
+}
+
 // Reduce each update's walker records and decide it (one wavefront per update).
 __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
@@ -1199,6 +1314,56 @@ __global__ __launch_bounds__(kBlock) void k_sum_counters(const BatchArgs* const*
 }
 
 // ---- phase 4 ------------------------------------------------------------------------
+//
+// One launch per step serves both graphs: blockIdx.z picks the graph (which =
+// which0 + blockIdx.z), and its per-graph state is read from the argument
+// record in global memory.
+
+struct P4 {
+  DevGraph X;
+  BatchCtl* ctl;
+  uint32_t *touched_rows, *touched_k, *touched_need, *dirty_rows, *wide_rows;
+  uint8_t* add_keep;
+  uint32_t n, n_ins, hadd_cap, hash_mask;
+  const uint32_t *iu, *iv, *ins_qw;
+  const double *iw, *ins_rinv;
+  const AddRec* hadd;
+  HashSlot* hash;  // the phase-4 dedup table
+};
+
+__device__ __forceinline__ P4 load_p4(const BatchArgs* const* __restrict__ argv, uint32_t b,
+                                      uint32_t which) {
+  const gptr<const BatchArgs> ap = args_of(argv, b);
+  P4 v;
+  load_graph(v.X, ap, static_cast<int>(which));
+  v.X.pool_cap = ap->g[which].pool_cap;
+  v.ctl = load_gptr(&ap->ctl);
+  v.touched_rows = load_gptr(&ap->touched_rows[which]);
+  v.touched_k = load_gptr(&ap->touched_k[which]);
+  v.touched_need = load_gptr(&ap->touched_need[which]);
+  v.dirty_rows = load_gptr(&ap->dirty_rows[which]);
+  v.wide_rows = load_gptr(&ap->wide_rows[which]);
+  v.add_keep = load_gptr(&ap->add_keep[which]);
+  v.n = ap->n;
+  v.n_ins = ap->n_ins;
+  v.hadd_cap = ap->hadd_cap;
+  v.hash_mask = ap->hash_mask;
+  v.iu = load_gptr(&ap->iu);
+  v.iv = load_gptr(&ap->iv);
+  v.ins_qw = load_gptr(&ap->ins_qw);
+  v.iw = load_gptr(&ap->iw);
+  v.ins_rinv = load_gptr(&ap->ins_rinv);
+  v.hadd = load_gptr(&ap->hadd);
+  v.hash = load_gptr(&ap->hash2);
+  return v;
+}
+
+__device__ __forceinline__ void mark_dirty4(const P4& a, uint32_t which, uint32_t r) {
+  if (atomicExch(&a.X.mark[r], 1u) == 0u) {
+    const uint32_t t = atomicAdd(&a.ctl->dirty[which], 1u);
+    a.dirty_rows[t] = r;
+  }
+}
 
 struct AddEntry {
   uint32_t r, c, qw;
@@ -1207,7 +1372,7 @@ struct AddEntry {
 };
 
 // Directed entry e of the additions to graph `which`: two per undirected edge.
-__device__ __forceinline__ AddEntry add_entry(const BatchArgs& a, int which, uint32_t e) {
+__device__ __forceinline__ AddEntry add_entry(const P4& a, uint32_t which, uint32_t e) {
   const uint32_t i = e >> 1;
   const bool flip = e & 1u;
   if (which == 0) {
@@ -1219,18 +1384,18 @@ __device__ __forceinline__ AddEntry add_entry(const BatchArgs& a, int which, uin
   return AddEntry{flip ? rec.b : rec.a, flip ? rec.a : rec.b, rec.qw, rec.rinv, rec.w, true};
 }
 
-__device__ __forceinline__ uint32_t add_count(const BatchArgs& a, int which) {
+__device__ __forceinline__ uint32_t add_count(const P4& a, uint32_t which) {
   return which == 0 ? 2u * a.n_ins : 2u * a.hadd_cap;
 }
 
-template <int which>
-__global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
+__global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
   if (batch_failed(a.ctl)) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= add_count(a, which)) return;
-  a.add_keep[which][e] = 0;
+  a.add_keep[e] = 0;
   const AddEntry d = add_entry(a, which, e);
   if (!d.valid) return;
   const RowHdr row = row_hdr(X, d.r);
@@ -1243,7 +1408,7 @@ __global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv) {
       seg.r(k) = d.rinv;
       seg.w[k] = d.w;
       atomicSub(&row_hdr_ref(X, d.r).dead, 1u);
-      if (row.len > kHub) mark_dirty(a, X, which, d.r);
+      if (row.len > kHub) mark_dirty4(a, which, d.r);
     }
     return;
   }
@@ -1254,9 +1419,9 @@ __global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv) {
   const uint32_t slot = atomicAdd(&X.pending[d.r], 1u);
   if (slot == 0u) {
     const uint32_t t = atomicAdd(&a.ctl->touched[which], 1u);
-    a.touched_rows[which][t] = d.r;
+    a.touched_rows[t] = d.r;
   }
-  a.add_keep[which][e] = 1;
+  a.add_keep[e] = 1;
 }
 
 __device__ __forceinline__ uint32_t grown_cap(uint32_t live) {
@@ -1271,14 +1436,14 @@ constexpr uint32_t kWideRelocate = 1u << 30;
 constexpr uint32_t kWideMerge = 1u << 31;
 constexpr uint32_t kCountMask = kWideRelocate - 1u;
 
-template <int which>
-__global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
+__global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
   if (batch_failed(a.ctl)) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
-  const uint32_t r = a.touched_rows[which][t];
+  const uint32_t r = a.touched_rows[t];
   const uint32_t k = X.pending[r];
   const RowHdr row = row_hdr(X, r);
   uint32_t need = 0, flags = 0, merged_from = row.len;
@@ -1289,30 +1454,31 @@ __global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv) {
     merged_from = row.len - row.dead;  // relocation drops the tombstones
   }
   if (merged_from + k > kHub) flags |= kWideMerge;
-  a.touched_k[which][t] = k | flags;
-  a.touched_need[which][t] = need;
+  a.touched_k[t] = k | flags;
+  a.touched_need[t] = need;
+  if (flags) a.wide_rows[atomicAdd(&a.ctl->wide[which], 1u)] = t;  // rare: long rows only
 }
 
-template <int which>
-__global__ void k_pool_check(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const uint64_t pool_cap = a.g[which].pool_cap;
+__global__ void k_pool_check(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const uint64_t pool_cap = a.X.pool_cap;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (batch_failed(a.ctl)) return;
   if (a.ctl->pool_top[which] + a.ctl->need[which] > pool_cap) a.ctl->nomem[which] = 1;
 }
 
-template <int which>
-__global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
+__global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
-  const uint32_t need = a.touched_need[which][t];
+  const uint32_t need = a.touched_need[t];
   if (need == 0) return;
-  if (a.touched_k[which][t] & kWideRelocate) return;  // moved by k_rows_relocate_wide
-  const uint32_t r = a.touched_rows[which][t];
+  if (a.touched_k[t] & kWideRelocate) return;  // moved by k_rows_relocate_wide
+  const uint32_t r = a.touched_rows[t];
   const RowHdr row = row_hdr(X, r);
   const Seg src = seg_of(X, r, row.off);
   const uint32_t off =
@@ -1330,17 +1496,18 @@ __global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv) {
 
 // Relocation of long segments: one workgroup per segment, tombstones dropped
 // through a block-wide scan of the live flags.
-template <int which>
-__global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
+__global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ uint32_t s_off;
-  const uint32_t count = a.ctl->touched[which];
-  for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
-    const uint32_t need = a.touched_need[which][t];
-    if (need == 0 || !(a.touched_k[which][t] & kWideRelocate)) continue;  // block-uniform
-    const uint32_t r = a.touched_rows[which][t];
+  const uint32_t count = a.ctl->wide[which];
+  for (uint32_t wi = blockIdx.x; wi < count; wi += gridDim.x) {
+    const uint32_t t = a.wide_rows[wi];
+    const uint32_t need = a.touched_need[t];
+    if (need == 0 || !(a.touched_k[t] & kWideRelocate)) continue;  // block-uniform
+    const uint32_t r = a.touched_rows[t];
     const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment
     if (threadIdx.x == 0)
       s_off = static_cast<uint32_t>(
@@ -1370,14 +1537,14 @@ __global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* 
   }
 }
 
-template <int which>
-__global__ void k_add_place(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
+__global__ void k_add_place(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= add_count(a, which)) return;
-  if (!a.add_keep[which][e]) return;
+  if (!a.add_keep[e]) return;
   const AddEntry d = add_entry(a, which, e);
   const RowHdr row = row_hdr(X, d.r);
   const uint32_t slot = atomicSub(&X.pending[d.r], 1u) - 1u;  // leaves pending at 0
@@ -1387,16 +1554,16 @@ __global__ void k_add_place(const BatchArgs* const* __restrict__ argv) {
 
 // Merge the k appended entries (unsorted tail) into the sorted segment; one
 // thread per short segment (insertion of each new entry).
-template <int which>
-__global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
+__global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
-  const uint32_t packed = a.touched_k[which][t];
+  const uint32_t packed = a.touched_k[t];
   if (packed & kWideMerge) return;  // merged by k_rows_merge_wide
-  const uint32_t r = a.touched_rows[which][t];
+  const uint32_t r = a.touched_rows[t];
   const uint32_t k = packed & kCountMask;
   const RowHdr row = row_hdr(X, r);
   const Seg seg = seg_of(X, r, row.off);
@@ -1411,6 +1578,7 @@ __global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv) {
     seg.put(i, e, we);
   }
   row_hdr_ref(X, r).len = row.len + k;
+  if (row.len + k > kHub) mark_dirty4(a, which, r);  // its weight prefix is rebuilt next
 }
 
 constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 KB LDS)
@@ -1421,20 +1589,21 @@ constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 K
 // entries below them; new entries sit after the old entries below them) and
 // moves the old entries right to left in block-sized chunks, so no entry is
 // overwritten before it is read.
-template <int which>
-__global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
+__global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ unsigned long long s_key[kTailChunk];  // (nbr << 32) | local index
   __shared__ Ent s_ent[kTailChunk];
   __shared__ double s_w[kTailChunk];
   __shared__ uint32_t s_pos[kTailChunk];
-  const uint32_t count = a.ctl->touched[which];
-  for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
-    const uint32_t packed = a.touched_k[which][t];
+  const uint32_t count = a.ctl->wide[which];
+  for (uint32_t wi = blockIdx.x; wi < count; wi += gridDim.x) {
+    const uint32_t t = a.wide_rows[wi];
+    const uint32_t packed = a.touched_k[t];
     if (!(packed & kWideMerge)) continue;  // block-uniform
-    const uint32_t r = a.touched_rows[which][t];
+    const uint32_t r = a.touched_rows[t];
     const uint32_t k = packed & kCountMask;
     const RowHdr row = row_hdr(X, r);  // relocated or long: a pool segment
     Ent* seg = X.ent + row.off;
@@ -1515,41 +1684,42 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* con
       __syncthreads();
       cur += c;
     }
-    if (threadIdx.x == 0) row_hdr_ref(X, r).len = cur;
+    if (threadIdx.x == 0) {
+      row_hdr_ref(X, r).len = cur;
+      if (cur > kHub) mark_dirty4(a, which, r);
+    }
     __syncthreads();
   }
 }
 
-// Long segments touched by phase 4 need their prefix rebuilt.
-template <int which>
-__global__ void k_mark_merged(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
-  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.ctl->touched[which]) return;
-  const uint32_t r = a.touched_rows[which][t];
-  if (row_hdr(X, r).len > kHub) mark_dirty(a, X, which, r);
-}
-
 // After a pool shortfall: undo the per-row counters so phase 4 can run again
 // once the pool has grown.
-template <int which>
-__global__ void k_phase4_reset(const BatchArgs* const* __restrict__ argv) {
-  const BatchArgs a = load_args(argv, blockIdx.y);
-  const DevGraph X = a.g[which];
+__global__ void k_phase4_reset(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
+  if (which == 1) {
+    // H's re-run deduplicates its additions afresh
+    const uint64_t slots = args_of(argv, blockIdx.y)->hash_slots;
+    for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < slots;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+      a.hash[i].key = ~0ull;
+      a.hash[i].minidx = ~0u;
+    }
+  }
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
-  X.pending[a.touched_rows[which][t]] = 0u;
+  X.pending[a.touched_rows[t]] = 0u;
 }
 
-template <int which>
-__global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv) {
+__global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
   BatchCtl* ctl = ctl_of(argv, blockIdx.y);
   if (threadIdx.x == 0) {
     ctl->touched[which] = 0;
     ctl->need[which] = 0;
     ctl->nomem[which] = 0;
+    ctl->wide[which] = 0;
   }
 }
 
@@ -1573,9 +1743,8 @@ inline dim3 grid_of(uint64_t n, uint32_t F, uint32_t per = kBlock) {
 }  // namespace
 
 void launch_batch_begin(const Launch& L, hipStream_t st) {
-  k_batch_begin<<<dim3(1, L.F), 64, 0, st>>>(L.argv);
   const uint32_t nb = blocks_for(L.max_hash_slots) < 4096 ? blocks_for(L.max_hash_slots) : 4096;
-  k_clear_hash<<<dim3(nb ? nb : 1, L.F), kBlock, 0, st>>>(L.argv);
+  k_batch_begin<<<dim3(nb ? nb : 1, L.F), kBlock, 0, st>>>(L.argv);
 }
 
 void launch_validate(const Launch& L, hipStream_t st) {
@@ -1588,9 +1757,7 @@ void launch_phase1(const Launch& L, hipStream_t st) {
   if (L.max_del == 0) return;
   k_phase1<<<grid_of(L.max_del, L.F), kBlock, 0, st>>>(L.argv);
   // walks read the prefix of long segments: rebuild the ones just changed
-  k_hub_prefix<0><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
-  k_hub_prefix<1><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
-  k_dirty_reset<<<dim3(1, L.F), 64, 0, st>>>(L.argv);
+  k_hub_prefix<<<dim3(kWideBlocks, L.F, 2), kBlock, 0, st>>>(L.argv, 0u, 0);
 }
 
 void launch_walks(const Launch& L, hipStream_t st) {
@@ -1611,13 +1778,20 @@ void launch_queue_prepare(const Launch& L, hipStream_t st) {
   k_scan_tiles<<<grid_of(L.max_nu, L.F, kScanTile), kBlock, 0, st>>>(L.argv);
   k_scan_top<<<dim3(1, L.F), kBlock, 0, st>>>(L.argv);
   k_scan_add<<<grid_of(L.max_nu, L.F, kScanTile), kBlock, 0, st>>>(L.argv);
-  k_expand_items<<<grid_of(L.max_nu, L.F, per), kBlock, 0, st>>>(L.argv);
+  if (L.upw == 0) k_expand_items<<<grid_of(L.max_nu, L.F, per), kBlock, 0, st>>>(L.argv);
 }
 
 void launch_walk_queue(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
-  if (L.F > 1) k_walk_queue<true><<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
-  else k_walk_queue<false><<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
+  if (L.upw > 0) {
+    const uint32_t upw = L.upw < kMaxUpw ? L.upw : kMaxUpw;
+    const uint32_t waves = (L.max_nu + upw - 1) / upw;
+    k_walk_range<<<grid_of(waves, L.F, kBlock / kWave), kBlock, 0, st>>>(L.argv, upw);
+  } else if (L.F > 1) {
+    k_walk_queue<true><<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
+  } else {
+    k_walk_queue<false><<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
+  }
 }
 
 void launch_queue_finish(const Launch& L, hipStream_t st) {
@@ -1627,47 +1801,42 @@ void launch_queue_finish(const Launch& L, hipStream_t st) {
 
 namespace {
 
-template <int W>
-void phase4_sequence(const Launch& L, hipStream_t st) {
-  // upper bound of the directed entries and of the touched rows
-  const uint64_t cap = W == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
-  if (cap == 0) return;
-  if (W == 1) {
-    const uint32_t nb = blocks_for(L.max_hash_slots) < 4096 ? blocks_for(L.max_hash_slots) : 4096;
-    k_clear_hash<<<dim3(nb ? nb : 1, L.F), kBlock, 0, st>>>(L.argv);
+// Phase 4 of graphs which0 .. which0 + nw - 1 (both graphs at once normally;
+// one when a pool repair re-runs it).
+void phase4_sequence(const Launch& L, uint32_t which0, uint32_t nw, hipStream_t st) {
+  uint64_t cap = 0;  // upper bound of the directed entries and of the touched rows
+  for (uint32_t w = which0; w < which0 + nw; ++w) {
+    const uint64_t c = w == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
+    cap = c > cap ? c : cap;
   }
-  const dim3 g = grid_of(cap, L.F);
-  k_add_prepare<W><<<g, kBlock, 0, st>>>(L.argv);
-  k_rows_plan<W><<<g, kBlock, 0, st>>>(L.argv);
-  k_pool_check<W><<<dim3(1, L.F), 64, 0, st>>>(L.argv);
-  k_rows_relocate<W><<<g, kBlock, 0, st>>>(L.argv);
-  k_rows_relocate_wide<W><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
-  k_add_place<W><<<g, kBlock, 0, st>>>(L.argv);
-  k_rows_merge<W><<<g, kBlock, 0, st>>>(L.argv);
-  k_rows_merge_wide<W><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
-  k_mark_merged<W><<<g, kBlock, 0, st>>>(L.argv);
-  k_hub_prefix<W><<<dim3(kWideBlocks, L.F), kBlock, 0, st>>>(L.argv);
-  k_dirty_reset<<<dim3(1, L.F), 64, 0, st>>>(L.argv);
-}
-
-template <int W>
-void phase4_reset_sequence(const Launch& L, hipStream_t st) {
-  const uint64_t cap = W == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
   if (cap == 0) return;
-  k_phase4_reset<W><<<grid_of(cap, L.F), kBlock, 0, st>>>(L.argv);
-  k_phase4_reset_ctl<W><<<dim3(1, L.F), 64, 0, st>>>(L.argv);
+  const dim3 g(static_cast<uint32_t>((cap + kBlock - 1) / kBlock), L.F, nw);
+  const dim3 wide(kWideBlocks, L.F, nw);
+  k_add_prepare<<<g, kBlock, 0, st>>>(L.argv, which0);
+  k_rows_plan<<<g, kBlock, 0, st>>>(L.argv, which0);
+  k_pool_check<<<dim3(1, L.F, nw), 64, 0, st>>>(L.argv, which0);
+  k_rows_relocate<<<g, kBlock, 0, st>>>(L.argv, which0);
+  k_rows_relocate_wide<<<wide, kBlock, 0, st>>>(L.argv, which0);
+  k_add_place<<<g, kBlock, 0, st>>>(L.argv, which0);
+  k_rows_merge<<<g, kBlock, 0, st>>>(L.argv, which0);
+  k_rows_merge_wide<<<wide, kBlock, 0, st>>>(L.argv, which0);
+  k_hub_prefix<<<wide, kBlock, 0, st>>>(L.argv, which0, 1);
 }
 
 }  // namespace
 
 void launch_phase4(const Launch& L, int which, hipStream_t st) {
-  if (which == 0) phase4_sequence<0>(L, st);
-  else phase4_sequence<1>(L, st);
+  phase4_sequence(L, static_cast<uint32_t>(which), 1, st);
 }
 
+void launch_phase4_both(const Launch& L, hipStream_t st) { phase4_sequence(L, 0, 2, st); }
+
 void launch_phase4_reset(const Launch& L, int which, hipStream_t st) {
-  if (which == 0) phase4_reset_sequence<0>(L, st);
-  else phase4_reset_sequence<1>(L, st);
+  const uint64_t cap = which == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;
+  if (cap == 0) return;
+  const dim3 g(static_cast<uint32_t>((cap + kBlock - 1) / kBlock), L.F, 1);
+  k_phase4_reset<<<g, kBlock, 0, st>>>(L.argv, static_cast<uint32_t>(which));
+  k_phase4_reset_ctl<<<dim3(1, L.F, 1), 64, 0, st>>>(L.argv, static_cast<uint32_t>(which));
 }
 
 }  // namespace dyg

@@ -70,7 +70,7 @@ class dyg_stats_t(C.Structure):
 
 class dyg_tuning(C.Structure):
     _fields_ = [("walk_blocks_per_cu", C.c_uint32), ("refill_min", C.c_uint32),
-                ("reserved", C.c_uint32 * 6)]
+                ("updates_per_wave", C.c_uint32), ("reserved", C.c_uint32 * 5)]
 
 
 class dyg_batch_dev(C.Structure):
@@ -303,8 +303,13 @@ def dyg_get_tuning(ctx) -> dict:
     return {"walk_blocks_per_cu": t.walk_blocks_per_cu, "refill_min": t.refill_min}
 
 
-def dyg_set_tuning(ctx, walk_blocks_per_cu: int, refill_min: int):
-    t = dyg_tuning(walk_blocks_per_cu=int(walk_blocks_per_cu), refill_min=int(refill_min))
+def dyg_set_tuning(ctx, walk_blocks_per_cu: int, refill_min: int, updates_per_wave: int = None):
+    if updates_per_wave is None:
+        cur = dyg_tuning()
+        _check(_lib.dyg_get_tuning(ctx, C.byref(cur)), "dyg_get_tuning")
+        updates_per_wave = cur.updates_per_wave
+    t = dyg_tuning(walk_blocks_per_cu=int(walk_blocks_per_cu), refill_min=int(refill_min),
+                   updates_per_wave=int(updates_per_wave))
     _check(_lib.dyg_set_tuning(ctx, C.byref(t)), "dyg_set_tuning")
 
 

@@ -160,3 +160,29 @@ def test_graph_mode_error_then_valid():
     finally:
         d.close()
         o.close()
+
+
+@pytest.mark.parametrize("upw", [0, 1, 3, 8])
+def test_walk_schedules_agree(upw):
+    """The batched form's walk schedule (one work queue, or ranges of upw
+    updates per wavefront) changes no result: uneven walker counts and step
+    limits, insertions and deletions, against the oracle."""
+    from paper_2505_02741_amd import dygrass as D
+
+    wl = W.make_workload("mesh128", side=10, ins=150, dels=120, batches=4)
+    rng = np.random.default_rng(17)
+    for b in wl.batches:
+        b.s = rng.integers(0, 150, b.size).astype(np.uint16)
+        b.L = rng.integers(1, 30, b.size).astype(np.uint16)
+    o, d = make_pair(wl, flags=BATCHED)
+    try:
+        D.dyg_set_tuning(d.ctx, 4, 1, upw)
+        for t, b in enumerate(wl.batches):
+            compare_batch(o, d, b, tag=f"upw={upw} batch {t}")
+        compare_state(o, d, f"upw={upw}")
+        st = d.stats()
+        assert st["walk_steps"] == o.steps_total
+        assert st["walk_alg_bytes"] == o.alg_bytes_total
+    finally:
+        d.close()
+        o.close()
