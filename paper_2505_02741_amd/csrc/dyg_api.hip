@@ -32,6 +32,15 @@ using dyg::Pair;
 namespace {
 
 // Growable device buffer.
+// Staging buffers grow to the next power of two (at least 64 KiB): batches of
+// varying size then reallocate rarely (freeing device memory waits for the
+// device).
+size_t grown_size(size_t need) {
+  size_t want = size_t(1) << 16;
+  while (want < need) want <<= 1;
+  return want;
+}
+
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -40,7 +49,7 @@ struct DBuf {
     if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
-    size_t want = need + need / 2 + 256;
+    const size_t want = grown_size(need);
     if (hipMalloc(&p, want) != hipSuccess) {
       p = nullptr;
       return false;
@@ -68,7 +77,7 @@ struct HBuf {
     if (p) (void)hipHostFree(p);
     p = nullptr;
     bytes = 0;
-    size_t want = need + need / 2 + 256;
+    const size_t want = grown_size(need);
     if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
       p = nullptr;
       return false;
@@ -264,11 +273,12 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
   }
 }
 
-// Pool capacity for `used` live slots of a graph with n vertices: half again
-// for growth plus room for every vertex to outgrow its inline entries.
+// Pool capacity for `used` live slots of a graph with n vertices: as much
+// again for growth plus room for every vertex to outgrow its inline entries
+// (a compaction is a host round trip; HBM is plentiful).
 uint64_t pool_capacity_for(uint64_t used, uint32_t n, uint32_t flags) {
   if (flags & DYG_FLAG_LEAN_POOLS) return used + 64;
-  return used + used / 2 + 4ull * n + 4096;
+  return 2 * used + 8ull * n + 65536;
 }
 
 // Read one device graph back into per-row live lists.

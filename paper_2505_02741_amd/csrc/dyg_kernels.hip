@@ -792,14 +792,16 @@ __device__ __forceinline__ void no_walk_update(const BatchArgs& a, const UpdateV
   }
 }
 
-// Decision of one update once its walkers are reduced (run by one lane):
-// an insertion is kept iff no walker reached q (Sec. III-B); a deletion of an
-// H edge recovers the winner's path edges missing from H, or the fallback
-// edges when nobody hit (Sec. III-C).
+// Decision of one update once its walkers are reduced, taken by the whole
+// wavefront (every lane holds the same any_hit, bestR, bestW, steps): an
+// insertion is kept iff no walker reached q (Sec. III-B); a deletion of an H
+// edge recovers the winner's path edges missing from H (one lane replays the
+// winner), or the fallback edges when nobody hit (Sec. III-C), whose search
+// over the endpoints' G rows the lanes share.
 __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph& Gref,
                                               const DevGraph& Href, uint32_t upd,
                                               const UpdateView& v, bool any_hit, double bestR,
-                                              uint32_t bestW, uint32_t steps) {
+                                              uint32_t bestW, uint32_t steps, uint32_t lane) {
   // value copies: the inline-or-pool choices below then select between
   // registers, not between fields of the argument record
   const DevGraph G = Gref, H = Href;
@@ -813,9 +815,11 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
   const WalkParams& P = v.P;
   if (v.is_ins) {
     res.flag = any_hit ? 0 : 1;
-    a.hadd[upd] = any_hit ? kNoAdd
-                          : AddRec{P.p, P.q, a.ins_qw[upd], 0u, a.ins_rinv[upd], a.iw[upd]};
-    a.res[upd] = res;
+    if (lane == 0) {
+      a.hadd[upd] = any_hit ? kNoAdd
+                            : AddRec{P.p, P.q, a.ins_qw[upd], 0u, a.ins_rinv[upd], a.iw[upd]};
+      a.res[upd] = res;
+    }
     return;
   }
   res.flag = 1;
@@ -823,35 +827,48 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
   AddRec* out = del_slots(a, upd);
   uint32_t count = 0;
   if (any_hit) {
-    RecoverSink sink{G, H, out, cap, 0u};
-    walk_one(P, bestW, sink);  // replay: same counters, same snapshot
-    count = sink.count;
+    if (lane == 0) {
+      RecoverSink sink{G, H, out, cap, 0u};
+      walk_one(P, bestW, sink);  // replay: same counters, same snapshot
+      count = sink.count;
+    }
+    count = static_cast<uint32_t>(__shfl(static_cast<int>(count), 0, kWave));
   } else {
-    // no hit: per endpoint the least-resistance G edge not in H
+    // no hit: per endpoint the least-resistance G edge not in H, ties to the
+    // smaller neighbour; lanes scan strided entries, then the wavefront's
+    // minimum of (1/w, neighbour)
     for (int z = 0; z < 2; ++z) {
       const uint32_t end = z == 0 ? P.p : P.q;
       const RowHdr r = row_hdr(G, end);
       const Seg seg = seg_of(G, end, r.off);
-      int best = -1;
-      double bestr = 0.0;
-      for (uint32_t i = 0; i < r.len; ++i) {
+      double br = INFINITY;
+      uint32_t bn = kNone, bi = 0;
+      for (uint32_t i = lane; i < r.len; i += kWave) {
         const Ent e = seg.get(i);
         if (e.qw == 0u) continue;
         if (has_live(H, end, e.nbr)) continue;
-        if (best < 0 || e.rinv < bestr) {
-          best = static_cast<int>(i);
-          bestr = e.rinv;
+        if (e.rinv < br || (e.rinv == br && e.nbr < bn)) {
+          br = e.rinv;
+          bn = e.nbr;
+          bi = i;
         }
       }
-      if (best >= 0) {
-        const Ent e = seg.get(best);
-        out[count++] = AddRec{end, e.nbr, e.qw, 0u, e.rinv, seg.w[best]};
-      }
+      double wr = br;
+      uint32_t wn = bn;
+      wave_argmin(wr, wn);
+      if (wn == kNone) continue;  // uniform: every lane holds the same minimum
+      const unsigned long long own = __ballot(bn == wn);
+      const uint32_t src = static_cast<uint32_t>(__builtin_ctzll(own));
+      bi = static_cast<uint32_t>(__shfl(static_cast<int>(bi), static_cast<int>(src), kWave));
+      if (lane == 0) out[count] = AddRec{end, wn, seg.qw(bi), 0u, seg.r(bi), seg.w[bi]};
+      ++count;
     }
   }
-  for (uint32_t z = count; z < a.Lcap; ++z) out[z] = kNoAdd;
-  res.n_rec = static_cast<uint16_t>(count);
-  a.res[upd] = res;
+  for (uint32_t z = count + lane; z < a.Lcap; z += kWave) out[z] = kNoAdd;
+  if (lane == 0) {
+    res.n_rec = static_cast<uint16_t>(count);
+    a.res[upd] = res;
+  }
 }
 
 // Plain form: one wavefront per update, one lane per walker (more walkers
@@ -894,9 +911,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
     steps += wave_sum(active ? o.steps : 0u);
     bytes += wave_sum(active ? o.bytes : 0u);
   }
-  if (lane != 0) return;
-  a.ubytes[upd] = bytes;
-  decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps);
+  if (lane == 0) a.ubytes[upd] = bytes;
+  decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps, lane);
 }
 
 // ---- batched form: walker work queue ----------------------------------------
@@ -1277,9 +1293,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
     steps += wave_sum(active ? static_cast<uint32_t>(o.steps) : 0u);
     bytes += wave_sum(active ? o.bytes : 0u);
   }
-  if (lane != 0) return;
-  a.ubytes[upd] = bytes;
-  decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps);
+  if (lane == 0) a.ubytes[upd] = bytes;
+  decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps, lane);
 }
 
 // Batch totals of walker steps and algorithmic bytes (from the per-update
