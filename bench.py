@@ -12,8 +12,9 @@ vertices, 2,095,104 edges, lognormal(0,1) weights), maximum spanning forest +
 10% off-tree edges as the initial sparsifier, batches of 20,000 local
 insertions (2-6 hops), 64 walkers per update, step limit 32, no distortion
 threshold, in the plain form (one launch sequence and one host sync per
-batch).  The batched form (range walk in a captured graph) is timed on the
-same batches for comparison.
+batch).  The batched form (each wavefront walks the walkers of a few
+consecutive updates, lanes refilled as walkers stop) is timed on the same
+batches for comparison.
 
 --form serving runs the many-graph serving workload instead (Poisson arrivals,
 fused rounds, p50/p99 latency) against the plain form on the same requests.
@@ -161,11 +162,19 @@ def to_device(np, torch, dev, b):
                 results=torch.empty(b.size * 24, dtype=torch.uint8, device=dev))
 
 
+def reserve_for(D, ctx, batches):
+    """Size the context's batch buffers for the largest batch of the stream."""
+    D.dyg_reserve(ctx.ctx, max(b.n_ins for b in batches), max(b.n_del for b in batches),
+                  max((int(b.s.max()) for b in batches if b.s is not None and b.size), default=0),
+                  max((int(b.L.max()) for b in batches if b.L is not None and b.size), default=0))
+
+
 def run_stream(D, torch, wl, rp, col, w, dev_batches, flags, warmup, tuning=None):
-    """Apply every batch in order on a fresh context; time all but the first
-    `warmup` batches."""
+    """Apply every batch in order on a fresh context (buffers reserved for the
+    largest batch); time all but the first `warmup` batches."""
     ctx = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
                     L=wl.L, flags=D.FLAG_TIMING | flags)
+    reserve_for(D, ctx, wl.batches)
     if tuning:
         D.dyg_set_tuning(ctx.ctx, *tuning)
 
@@ -236,7 +245,7 @@ def main_batches(args):
     dev_batches = [to_device(np, torch, dev, b) for b in wl.batches]
     torch.cuda.synchronize()
 
-    forms = {"plain": 0, "batched": D.FLAG_BATCHED | D.FLAG_GRAPH}
+    forms = {"plain": 0, "batched": D.FLAG_BATCHED | (D.FLAG_GRAPH if args.graph else 0)}
     head = args.form if args.form in forms else ("plain" if args.workload != "rmat22" else "batched")
     chosen = [head] if args.form in forms else list(forms)
     runs = {}
@@ -245,8 +254,8 @@ def main_batches(args):
         print(f"# {name}: {runs[name]['t_total'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
     # the walk kernel inside a captured graph is not timed: the roofline of the
-    # batched form comes from the same schedule launched directly
-    if "batched" in runs and head == "batched":
+    # batched form then comes from the same schedule launched directly
+    if "batched" in runs and head == "batched" and args.graph:
         timed = run_stream(D, torch, wl, rp, col, w, dev_batches, D.FLAG_BATCHED, args.warmup)
     else:
         timed = runs[head]
@@ -352,8 +361,11 @@ def main_serving(args):
         nxt[g] += 1
 
     def contexts(flags):
-        return [D.Dygrass(wl.G.n, *csr[g], wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
-                          L=wl.L, flags=flags) for g, wl in enumerate(fleet)]
+        out = [D.Dygrass(wl.G.n, *csr[g], wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
+                         L=wl.L, flags=flags) for g, wl in enumerate(fleet)]
+        for c, wl in zip(out, fleet):
+            reserve_for(D, c, wl.batches)
+        return out
 
     # plain: each request on its own graph, one launch sequence + host sync
     ctxs = contexts(0)
@@ -468,9 +480,12 @@ def main():
                     help="before the workload, copy this many MiB device to device once "
                          "(a known-size kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--form", choices=["both", "plain", "batched", "serving"], default="both",
-                    help="plain: one wavefront per update; batched: range walk in a captured "
-                         "graph; both: time both, report the workload's own form; serving: the "
-                         "many-graph serving workload")
+                    help="plain: one wavefront per update; batched: range walk; both: time "
+                         "both, report the workload's own form; serving: the many-graph "
+                         "serving workload")
+    ap.add_argument("--graph", action="store_true",
+                    help="batched form: replay each batch's launch sequence from a captured "
+                         "hipGraph (one per power-of-two size class)")
     ap.add_argument("--graphs", type=int, default=64, help="serving: resident graphs")
     ap.add_argument("--requests-per-graph", type=int, default=16)
     ap.add_argument("--max-nodes", type=int, default=500_000)

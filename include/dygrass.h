@@ -230,6 +230,16 @@ int dyg_set_tuning(dyg_ctx* ctx, const dyg_tuning* t); /* INVALID_ARG if out of 
  * automatically when a pool runs short). */
 int dyg_compact(dyg_ctx* ctx);
 
+/* Size the per-batch device buffers (staging, hash tables, H-addition slots,
+ * per-walker records) for batches of up to max_ins insertions and max_del
+ * deletions with at most max_s walkers and max_L steps per update, so that
+ * later batches within these bounds allocate nothing.  Optional: buffers
+ * otherwise grow on demand (a growth frees device memory, which waits for
+ * the device).  INVALID_ARG beyond DYG_MAX_WALKERS / DYG_MAX_STEPS or 2^30
+ * updates; NOMEM if the device cannot hold them. */
+int dyg_reserve(dyg_ctx* ctx, uint64_t max_ins, uint64_t max_del, uint32_t max_s,
+                uint32_t max_L);
+
 /*
  * Consistency check of the device state (for tests and failure detection):
  * every segment sorted with unique neighbour ids inside its slots and the

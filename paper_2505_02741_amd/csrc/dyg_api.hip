@@ -139,7 +139,8 @@ struct dyg_ctx {
   BatchCtl* ctl = nullptr;
   BatchArgs* dargs = nullptr;  // device copy of the current batch's arguments
   // DYG_FLAG_GRAPH: instantiated launch sequences by size class
-  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t>, hipGraphExec_t> graphs;
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t, bool>, hipGraphExec_t>
+      graphs;
   BatchArgs* hargs = nullptr;  // pinned host staging of the same
   BatchCtl* hctl = nullptr;    // pinned copy of ctl, written at the end of each batch
   hipEvent_t done_ev = nullptr;  // recorded after that copy
@@ -163,6 +164,7 @@ struct dyg_ctx {
   uint32_t walk_blocks_per_cu = 8;         // persistent walk grid = cus x this
   uint32_t refill_min = 1;                 // idle lanes that trigger a refill
   uint32_t updates_per_wave = 4;           // range walk (0 = work queue)
+  bool has_hubs = false;                   // some row longer than kHub (walk kernel choice)
   HBuf pin_in, pin_out;
 };
 
@@ -335,6 +337,7 @@ int finish_ctl(dyg_ctx* c, BatchCtl& out) {
   out = *c->hctl;
   c->pool_top[0] = out.pool_top[0];
   c->pool_top[1] = out.pool_top[1];
+  c->has_hubs = c->has_hubs || out.hubs != 0;
   return DYG_OK;
 }
 
@@ -494,6 +497,8 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
   for (uint64_t k = 0; k < nnz; ++k)
     le[k] = Ent{col[k], quantize_host(w[k], c->w_ref, c->Q), 1.0 / w[k]};
   std::vector<uint64_t> start(rowptr, rowptr + n + 1);
+  for (uint32_t u = 0; u < n && !c->has_hubs; ++u)  // H is a subgraph: G's rows bound both
+    c->has_hubs = rowptr[u + 1] - rowptr[u] > dyg::kHub;
   HostAdj A;
   layout(A, n, start, le, lw, params->slack);
   // H0 layout: directed entries sorted by (row, neighbour), weights from G0
@@ -581,7 +586,9 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
   if (ok && (c->params.flags & DYG_FLAG_BATCHED)) {
     const uint64_t tiles = (nu + 1023) / 1024 + 1;
     ok = c->qcount.ensure(4 * nu + 8) && c->qofs.ensure(8 * nu + 8) &&
-         c->qtile.ensure(8 * tiles + 8) && c->items.ensure(sizeof(dyg::WalkItem) * items_cap + 8) &&
+         c->qtile.ensure(8 * tiles + 8) &&
+         // item records only for the work queue (the range walk derives them)
+         (c->updates_per_wave > 0 || c->items.ensure(sizeof(dyg::WalkItem) * items_cap + 8)) &&
          c->wres.ensure(sizeof(dyg::WalkOut) * items_cap + 16);
   }
   for (int g = 0; g < 2 && ok; ++g) {
@@ -667,6 +674,7 @@ dyg::Launch single_launch(dyg_ctx* c, const BatchArgs& a) {
   L.max_hash_slots = a.hash_slots;
   L.walk_blocks = c->cus * c->walk_blocks_per_cu;
   L.upw = c->updates_per_wave;
+  L.hubs = c->has_hubs;
   return L;
 }
 
@@ -703,7 +711,8 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
   cls.hash_slots = a.hash_slots;  // cleared by a grid-stride loop: any grid works
   const uint32_t wb = c->cus * c->walk_blocks_per_cu;
   const auto key = std::make_tuple(uint64_t(cls.n_ins), uint64_t(cls.n_del),
-                                   uint64_t(cls.hadd_cap), wb, c->updates_per_wave);
+                                   uint64_t(cls.hadd_cap), wb, c->updates_per_wave,
+                                   c->has_hubs);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     *out = it->second;
@@ -1227,6 +1236,30 @@ extern "C" int dyg_set_tuning(dyg_ctx* c, const dyg_tuning* t) {
   return DYG_OK;
 }
 
+extern "C" int dyg_reserve(dyg_ctx* c, uint64_t max_ins, uint64_t max_del, uint32_t max_s,
+                           uint32_t max_L) {
+  if (!c || max_ins + max_del >= (1ull << 30) || max_s > DYG_MAX_WALKERS ||
+      max_L > DYG_MAX_STEPS)
+    return DYG_E_INVALID_ARG;
+  if (c->async_inflight) {
+    int rc = dyg_sync(c);
+    if (rc) return rc;
+  }
+  const uint64_t nu = max_ins + max_del;
+  const uint32_t Lcap = std::max<uint32_t>(std::max<uint32_t>(max_L, c->params.L_default), 2);
+  const uint32_t scap = std::max<uint32_t>(max_s, c->params.s_default);
+  uint64_t hadd_cap, hash_slots;
+  if (prepare_buffers(c, max_ins, max_del, Lcap, 0, nu * scap, hadd_cap, hash_slots))
+    return DYG_E_NOMEM;
+  // host-array batches stage through these
+  if (!c->iu.ensure(4 * max_ins + 8) || !c->iv.ensure(4 * max_ins + 8) ||
+      !c->iw.ensure(8 * max_ins + 8) || !c->du.ensure(4 * max_del + 8) ||
+      !c->dv.ensure(4 * max_del + 8) || !c->s.ensure(2 * nu + 8) || !c->L.ensure(2 * nu + 8) ||
+      !c->pin_in.ensure(24 * nu + 64))
+    return DYG_E_NOMEM;
+  return DYG_OK;
+}
+
 extern "C" int dyg_compact(dyg_ctx* c) {
   if (!c) return DYG_E_INVALID_ARG;
   if (c->async_inflight) {
@@ -1412,7 +1445,8 @@ int launch_round(dyg_server* s, ServerRound& r) {
   const uint32_t F = static_cast<uint32_t>(r.reqs.size());
   uint64_t items = 0;
   for (ServerRequest* q : r.reqs) items += q->nu() * s->graphs[q->graph]->params.s_default;
-  if (!r.items.ensure(sizeof(dyg::WalkItem) * items + 64) ||
+  const bool queue = s->graphs[r.reqs[0]->graph]->updates_per_wave == 0;
+  if ((queue && !r.items.ensure(sizeof(dyg::WalkItem) * items + 64)) ||
       !r.wres.ensure(sizeof(dyg::WalkOut) * items + 64))
     return DYG_E_NOMEM;
   dyg::Launch L{};
@@ -1420,6 +1454,7 @@ int launch_round(dyg_server* s, ServerRound& r) {
   L.F = F;
   L.walk_blocks = s->graphs[r.reqs[0]->graph]->cus * s->p.walk_blocks_per_cu;
   L.upw = s->graphs[r.reqs[0]->graph]->updates_per_wave;
+  for (ServerRequest* q : r.reqs) L.hubs = L.hubs || s->graphs[q->graph]->has_hubs;
   size_t out_bytes = 0;
   r.out_ofs.assign(F, 0);
   for (uint32_t i = 0; i < F; ++i) {

@@ -58,6 +58,7 @@ constexpr uint32_t kMaxWalkers = 1024;
 constexpr uint32_t kMaxSteps = 1024;
 constexpr uint32_t kMaxUpw = 8;  // updates per wavefront of the range walk
 
+
 struct DevGraph {
   Row* rows = nullptr;        // [n] 64-byte rows
   Ent* ent = nullptr;         // [pool_cap]
@@ -133,6 +134,7 @@ struct BatchCtl {
   uint32_t dirty[2];            // rows whose prefix must be rebuilt, per graph
   uint32_t dirty_p1[2];         // of those, the ones listed by phase 1
   uint32_t wide[2];             // touched rows moved or merged by a workgroup, per graph
+  uint32_t hubs;                // set when phase 4 leaves a row longer than kHub
   unsigned long long pool_top[2];  // next free pool slot, per graph
   unsigned long long walk_items;       // walkers queued (queue control only)
   unsigned long long queue_next;       // next queue item to hand out (queue control only)
@@ -210,6 +212,7 @@ struct Launch {
   uint64_t max_hadd_cap, max_hash_slots;
   uint32_t walk_blocks;               // persistent walk grid
   uint32_t upw;                       // updates per wavefront (0 = work queue)
+  bool hubs;                          // some row of a graph may be longer than kHub
 };
 
 // Host-side launchers (defined in dyg_kernels.hip), all asynchronous on

@@ -183,6 +183,17 @@ __device__ __forceinline__ int find_nbr(const Seg& seg, uint32_t len, uint32_t v
   return -1;
 }
 
+// First index among the first len entries whose neighbour is >= v.
+__device__ __forceinline__ uint32_t lower_nbr(const Seg& seg, uint32_t len, uint32_t v) {
+  uint32_t lo = 0, hi = len;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (seg.nbr(mid) < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // The same for a pool segment.
 __device__ __forceinline__ int find_nbr_pool(const Ent* seg, uint32_t len, uint32_t v) {
   int lo = 0, hi = static_cast<int>(len) - 1;
@@ -419,21 +430,36 @@ __global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* _
   const uint32_t from = after_phase1 ? ctl->dirty_p1[which] : 0u;
   // phase 1's list ends here; phase 4 appends after it (same value from every block)
   if (!after_phase1 && blockIdx.x == 0 && threadIdx.x == 0) ctl->dirty_p1[which] = count;
+  constexpr uint32_t kPer = 8;  // consecutive entries per thread per block scan
   for (uint32_t t = from + blockIdx.x; t < count; t += gridDim.x) {
     const uint32_t r = dirty_rows[t];
     const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment
+    const Ent* seg = X.ent + row.off;
+    unsigned long long* pf = X.pfx + row.off;
     unsigned long long carry = 0;
-    for (uint32_t base = 0; base < row.len; base += kBlock) {
-      const uint32_t i = base + threadIdx.x;
-      const unsigned long long q = i < row.len ? X.ent[row.off + i].qw : 0u;
+    for (uint32_t base = 0; base < row.len; base += kBlock * kPer) {
+      const uint32_t i0 = base + threadIdx.x * kPer;
+      uint32_t q[kPer];
+      unsigned long long sum = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < kPer; ++k) {
+        q[k] = i0 + k < row.len ? seg[i0 + k].qw : 0u;
+        sum += q[k];
+      }
       unsigned long long excl;
-      const unsigned long long total = block_excl_scan(q, excl);
-      if (i < row.len) X.pfx[row.off + i] = carry + excl + q;
+      const unsigned long long total = block_excl_scan(sum, excl);
+      unsigned long long run = carry + excl;
+#pragma unroll
+      for (uint32_t k = 0; k < kPer; ++k) {
+        run += q[k];
+        if (i0 + k < row.len) pf[i0 + k] = run;
+      }
       carry += total;
     }
     if (threadIdx.x == 0) X.mark[r] = 0u;
   }
 }
+
 
 // ---- walks ------------------------------------------------------------------------
 
@@ -475,6 +501,7 @@ struct NoSink {
 // State of one walker between steps.
 struct WState {
   uint32_t x, prev, steps, block_of, bytes;
+  uint32_t qprev;  // quantised weight of the edge just taken (the same both ways)
   double R;
   const double* rpend;  // 1/w of the last edge taken, not yet added to R
   Philox4 rnd;
@@ -484,6 +511,7 @@ struct WState {
 __device__ __forceinline__ void walker_start(WState& S, uint32_t p) {
   S.x = p;
   S.prev = kNone;
+  S.qprev = 0;
   S.steps = 0;
   S.block_of = kNone;
   S.bytes = 0;
@@ -523,7 +551,9 @@ __device__ __forceinline__ unsigned long long scale_random(unsigned long long r,
 // only dependent access of the step.  Without a threshold nothing decides on
 // R before the walk ends, so the 1/w of the edge taken is loaded with the next
 // step's row and added then (the additions keep their order).
-template <class Sink>
+// kHubs: the graphs may hold rows longer than kHub (else that branch, and the
+// bookkeeping it needs, are compiled out).
+template <bool kHubs, class Sink>
 __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
                                           Sink& sink) {
   const uint32_t t = S.steps;
@@ -540,7 +570,7 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
   // while the row is in flight (a dead end leaves it unused)
   const unsigned long long rnd = step_random(S, P, walker, t);
   const RowHdr h{q0.x, q0.y, q0.z, q0.w};
-  uint32_t pick_nbr, pick_idx;
+  uint32_t pick_nbr, pick_idx, pick_q;
   const double* pick_r;
   bool stop = false;
   if (h.off == kInlineOff) {
@@ -577,42 +607,72 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
                : pick_idx == 3 ? n3
                : pick_idx == 4 ? n4
                                : n5;
+    pick_q = pick_idx == 0   ? q1.y
+             : pick_idx == 1 ? q1.w
+             : pick_idx == 2 ? q2.y
+             : pick_idx == 3 ? q2.w
+             : pick_idx == 4 ? q3.y
+                             : q3.w;
     pick_r = P.rinl + static_cast<uint64_t>(S.x) * kInline + pick_idx;
-  } else if (h.len > kHub) {
+  } else if (kHubs && h.len > kHub) {
     // long segment: the candidates' running sums are the stored prefix with
-    // the previous vertex's weight taken out
+    // the previous vertex's weight (that of the edge just taken) left out.
+    // The first index whose prefix exceeds the target is found on the full
+    // prefix; if it lies at or after the previous vertex (compare ids, the
+    // row is sorted), the answer is the first index whose prefix exceeds
+    // target + that weight, a short gallop from there.
     const Ent* seg = P.ent + h.off;
     const unsigned long long* pf = P.pfx + h.off;
-    int jp = -1;
-    uint32_t qprev = 0;
-    if (S.prev != kNone) {
-      jp = find_nbr_pool(seg, h.len, S.prev);
-      if (jp >= 0) qprev = seg[jp].qw;
-    }
+    const uint32_t qprev = S.prev != kNone ? S.qprev : 0u;
     const unsigned long long tot = pf[h.len - 1] - qprev;
     if (tot == 0) {
-      stop = !(P.bounce && jp >= 0);
+      // every other entry is a tombstone
+      const int jp = (P.bounce && S.prev != kNone) ? find_nbr_pool(seg, h.len, S.prev) : -1;
+      stop = jp < 0;
       pick_idx = jp >= 0 ? static_cast<uint32_t>(jp) : 0u;
     } else {
-      unsigned long long target = scale_random(rnd, tot);
-      if (jp >= 0 && target >= pf[jp] - qprev) target += qprev;
+      const unsigned long long target = scale_random(rnd, tot);
       uint32_t lo = 0, hi = h.len - 1;  // first i with pf[i] > target
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (pf[mid] > target) hi = mid;
         else lo = mid + 1;
       }
+      if (qprev != 0u && seg[lo].nbr >= S.prev) {
+        const unsigned long long t2 = target + qprev;  // < pf[len - 1]
+        uint32_t a = lo, step = 1, b = lo;  // invariant: pf[a] <= t2 unless a == lo
+        while (pf[b] <= t2) {
+          a = b;
+          b = (h.len - 1 - b) > step ? b + step : h.len - 1;
+          step <<= 1;
+        }
+        while (a < b) {  // first i in [a, b] with pf[i] > t2
+          const uint32_t mid = (a + b) >> 1;
+          if (pf[mid] > t2) b = mid;
+          else a = mid + 1;
+        }
+        lo = a;
+      }
       pick_idx = lo;
     }
     pick_nbr = stop ? kNone : seg[pick_idx].nbr;
+    pick_q = stop ? 0u : seg[pick_idx].qw;
     pick_r = &seg[pick_idx].rinv;
   } else {
     const Ent* seg = P.ent + h.off;
     const uint2* e2 = reinterpret_cast<const uint2*>(seg);  // (nbr, qw) pairs
     unsigned long long tot = 0;
-    for (uint32_t i = 0; i < h.len; ++i) {
-      const uint2 e = e2[2 * i];
-      tot += (e.x != S.prev) ? e.y : 0u;
+    if (kHubs) {
+#pragma unroll 8
+      for (uint32_t i = 0; i < h.len; ++i) {  // unrolled: the loads go out together
+        const uint2 e = e2[2 * i];
+        tot += (e.x != S.prev) ? e.y : 0u;
+      }
+    } else {
+      for (uint32_t i = 0; i < h.len; ++i) {
+        const uint2 e = e2[2 * i];
+        tot += (e.x != S.prev) ? e.y : 0u;
+      }
     }
     pick_idx = 0;
     if (tot == 0) {
@@ -623,16 +683,30 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
       const unsigned long long target = scale_random(rnd, tot);
       unsigned long long run = 0;
       pick_idx = h.len - 1;
-      for (uint32_t i = 0; i < h.len; ++i) {
-        const uint2 e = e2[2 * i];
-        run += (e.x != S.prev) ? e.y : 0u;
-        if (run > target) {
-          pick_idx = i;
-          break;
+      if (kHubs) {
+#pragma unroll 8
+        for (uint32_t i = 0; i < h.len; ++i) {
+          const uint2 e = e2[2 * i];
+          run += (e.x != S.prev) ? e.y : 0u;
+          if (run > target) {
+            pick_idx = i;
+            break;
+          }
+        }
+      } else {
+        for (uint32_t i = 0; i < h.len; ++i) {
+          const uint2 e = e2[2 * i];
+          run += (e.x != S.prev) ? e.y : 0u;
+          if (run > target) {
+            pick_idx = i;
+            break;
+          }
         }
       }
     }
-    pick_nbr = stop ? kNone : seg[pick_idx].nbr;
+    const uint2 pe = e2[2 * pick_idx];
+    pick_nbr = stop ? kNone : pe.x;
+    pick_q = stop ? 0u : pe.y;
     pick_r = &seg[pick_idx].rinv;
   }
   if (has_prev) S.R = S.R + rprev;
@@ -641,6 +715,7 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
   S.bytes += step_bytes(h.len - h.dead);
   sink(S.x, pick_nbr, pick_idx, h.off);
   S.prev = S.x;
+  if (kHubs) S.qprev = pick_q;
   S.x = pick_nbr;
   S.steps = t + 1;
   if (P.use_K) {
@@ -658,11 +733,11 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
   return true;
 }
 
-template <class Sink>
+template <bool kHubs, class Sink>
 __device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, Sink& sink) {
   WState S;
   walker_start(S, P.p);
-  while (walk_step(P, walker, S, sink)) {
+  while (walk_step<kHubs>(P, walker, S, sink)) {
   }
   return Walk{S.steps, S.x, S.R, S.hit, S.bytes};
 }
@@ -715,6 +790,24 @@ struct RecoverSink {
     const Ent e = seg.get(i);
     out[count] = AddRec{x, y, e.qw, 0u, e.rinv, seg.w[i]};
     ++count;
+  }
+};
+
+// Sink of a replay run by every lane of a wavefront in lockstep (the same
+// walk on every lane): lane t keeps the edge of step t (walks of at most
+// kWave steps).
+struct PathSink {
+  uint32_t lane, t;
+  uint32_t x, y, i, off;
+  __device__ __forceinline__ void operator()(uint32_t x_, uint32_t y_, uint32_t i_,
+                                             uint32_t off_) {
+    if (t == lane) {
+      x = x_;
+      y = y_;
+      i = i_;
+      off = off_;
+    }
+    ++t;
   }
 };
 
@@ -798,6 +891,7 @@ __device__ __forceinline__ void no_walk_update(const BatchArgs& a, const UpdateV
 // edge recovers the winner's path edges missing from H (one lane replays the
 // winner), or the fallback edges when nobody hit (Sec. III-C), whose search
 // over the endpoints' G rows the lanes share.
+template <bool kHubs>
 __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph& Gref,
                                               const DevGraph& Href, uint32_t upd,
                                               const UpdateView& v, bool any_hit, double bestR,
@@ -826,10 +920,30 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
   const uint32_t cap = P.L > 2 ? P.L : 2;  // <= a.Lcap
   AddRec* out = del_slots(a, upd);
   uint32_t count = 0;
-  if (any_hit) {
+  if (any_hit && P.L <= kWave) {
+    // every lane replays the winner (same counters, same snapshot); lane t
+    // then checks step t's edge against H and against the earlier steps
+    PathSink ps{lane, 0u, kNone, kNone, 0u, 0u};
+    const Walk wk = walk_one<kHubs>(P, bestW, ps);
+    const bool mine = lane < wk.steps;
+    const unsigned long long key = mine ? edge_key(ps.x, ps.y) : ~0ull;
+    bool keep = mine && !has_live(H, ps.x, ps.y);
+    for (uint32_t t = 0; t < wk.steps; ++t) {  // first occurrence in path order
+      const unsigned long long k2 = __shfl(key, static_cast<int>(t), kWave);
+      if (t < lane && k2 == key) keep = false;
+    }
+    const unsigned long long kept = __ballot(keep);
+    if (keep) {
+      const Seg seg = seg_of(G, ps.x, ps.off);
+      const Ent e = seg.get(ps.i);
+      const uint32_t pos = static_cast<uint32_t>(__popcll(kept & ((1ull << lane) - 1ull)));
+      out[pos] = AddRec{ps.x, ps.y, e.qw, 0u, e.rinv, seg.w[ps.i]};
+    }
+    count = static_cast<uint32_t>(__popcll(kept));  // <= steps <= cap
+  } else if (any_hit) {
     if (lane == 0) {
       RecoverSink sink{G, H, out, cap, 0u};
-      walk_one(P, bestW, sink);  // replay: same counters, same snapshot
+      walk_one<kHubs>(P, bestW, sink);  // replay: same counters, same snapshot
       count = sink.count;
     }
     count = static_cast<uint32_t>(__shfl(static_cast<int>(count), 0, kWave));
@@ -841,12 +955,21 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
       const uint32_t end = z == 0 ? P.p : P.q;
       const RowHdr r = row_hdr(G, end);
       const Seg seg = seg_of(G, end, r.off);
+      const RowHdr hr = row_hdr(H, end);
+      const Seg hseg = seg_of(H, end, hr.off);
+      // each lane merges a contiguous slice of the G row against the H row
+      // (both sorted by neighbour): one search into H, then forward steps
+      const uint32_t per = (r.len + kWave - 1) / kWave;
+      const uint32_t a0 = lane * per < r.len ? lane * per : r.len;
+      const uint32_t a1 = a0 + per < r.len ? a0 + per : r.len;
+      uint32_t j = a0 < a1 ? lower_nbr(hseg, hr.len, seg.nbr(a0)) : hr.len;
       double br = INFINITY;
       uint32_t bn = kNone, bi = 0;
-      for (uint32_t i = lane; i < r.len; i += kWave) {
+      for (uint32_t i = a0; i < a1; ++i) {
         const Ent e = seg.get(i);
         if (e.qw == 0u) continue;
-        if (has_live(H, end, e.nbr)) continue;
+        while (j < hr.len && hseg.nbr(j) < e.nbr) ++j;
+        if (j < hr.len && hseg.nbr(j) == e.nbr && hseg.qw(j) != 0u) continue;  // live in H
         if (e.rinv < br || (e.rinv == br && e.nbr < bn)) {
           br = e.rinv;
           bn = e.nbr;
@@ -873,6 +996,7 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
 
 // Plain form: one wavefront per update, one lane per walker (more walkers
 // than lanes run in successive rounds of 64).
+template <bool kHubs>
 __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph G = a.g[0];
@@ -895,7 +1019,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
     const bool active = walker < v.s;
     Walk o{0, v.P.p, 0.0, false, 0};
     NoSink none;
-    if (active) o = walk_one(v.P, walker, none);
+    if (active) o = walk_one<kHubs>(v.P, walker, none);
     if (active && a.wrec)
       a.wrec[a.wofs[upd] + walker] =
           WalkerRec{static_cast<uint8_t>(o.hit), 0, static_cast<uint16_t>(o.steps), o.end, o.R};
@@ -912,7 +1036,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
     bytes += wave_sum(active ? o.bytes : 0u);
   }
   if (lane == 0) a.ubytes[upd] = bytes;
-  decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps, lane);
+  decide_update<kHubs>(a, G, H, upd, v, any_hit, bestR, bestW, steps, lane);
 }
 
 // ---- batched form: walker work queue ----------------------------------------
@@ -1043,7 +1167,7 @@ constexpr uint32_t kQueueChunk = 4 * kWave;
 
 // kFused: the launch carries several batches (items name theirs); otherwise
 // every item belongs to batch 0 and its per-batch values stay scalar.
-template <bool kFused>
+template <bool kFused, bool kHubs = true>
 __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a0 = load_args(argv, 0);
   BatchCtl* q = a0.qctl;
@@ -1103,7 +1227,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
     }
     // (2) one step of every running walker
     NoSink none;
-    if (active && !walk_step(P, walker, S, none)) {
+    if (active && !walk_step<kHubs>(P, walker, S, none)) {
       wres[item] = WalkOut{S.x, static_cast<uint16_t>(S.steps), static_cast<uint8_t>(S.hit), 0,
                            static_cast<uint32_t>(S.bytes), 0u, S.R};
       active = false;
@@ -1160,6 +1284,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
 // that receives a walker loads its update's endpoints during the other lanes'
 // step and starts one iteration later.  Every walker's outcome goes to
 // wres[item_base + qofs[update] + walker] for the per-update reduction.
+template <bool kHubs>
 __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* __restrict__ argv,
                                                        uint32_t upw) {
   const BatchArgs a = load_args(argv, blockIdx.y);
@@ -1239,7 +1364,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
     }
     // (2) one step of every running walker
     NoSink none;
-    if (active && !walk_step(P, walker, S, none)) {
+    if (active && !walk_step<kHubs>(P, walker, S, none)) {
       a.wres[item] = WalkOut{S.x, static_cast<uint16_t>(S.steps), static_cast<uint8_t>(S.hit), 0,
                              S.bytes, 0u, S.R};
       active = false;
@@ -1255,6 +1380,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
 }
 
 // Reduce each update's walker records and decide it (one wavefront per update).
+template <bool kHubs>
 __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph G = a.g[0];
@@ -1294,7 +1420,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
     bytes += wave_sum(active ? o.bytes : 0u);
   }
   if (lane == 0) a.ubytes[upd] = bytes;
-  decide_update(a, G, H, upd, v, any_hit, bestR, bestW, steps, lane);
+  decide_update<kHubs>(a, G, H, upd, v, any_hit, bestR, bestW, steps, lane);
 }
 
 // Batch totals of walker steps and algorithmic bytes (from the per-update
@@ -1593,7 +1719,10 @@ __global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv, uint32_t
     seg.put(i, e, we);
   }
   row_hdr_ref(X, r).len = row.len + k;
-  if (row.len + k > kHub) mark_dirty4(a, which, r);  // its weight prefix is rebuilt next
+  if (row.len + k > kHub) {  // its weight prefix is rebuilt next
+    mark_dirty4(a, which, r);
+    a.ctl->hubs = 1u;
+  }
 }
 
 constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 KB LDS)
@@ -1701,7 +1830,10 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* con
     }
     if (threadIdx.x == 0) {
       row_hdr_ref(X, r).len = cur;
-      if (cur > kHub) mark_dirty4(a, which, r);
+      if (cur > kHub) {
+        mark_dirty4(a, which, r);
+        a.ctl->hubs = 1u;
+      }
     }
     __syncthreads();
   }
@@ -1739,6 +1871,7 @@ __global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv, ui
 }
 
 constexpr uint32_t kWideBlocks = 512;  // workgroups of the per-long-segment kernels
+constexpr uint32_t kHubBlocks = 2048;  // workgroups of the prefix rebuild (memory-bound)
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per = kBlock) {
   return static_cast<uint32_t>((n + per - 1) / per);
@@ -1751,6 +1884,11 @@ inline uint32_t blocks_for(uint64_t n, uint32_t per = kBlock) {
 // x covers the largest batch of the launch.
 
 namespace {
+void launch_hub_prefix(const Launch& L, uint32_t which0, uint32_t nw, int after_phase1,
+                       hipStream_t st) {
+  k_hub_prefix<<<dim3(kHubBlocks, L.F, nw), kBlock, 0, st>>>(L.argv, which0, after_phase1);
+}
+
 inline dim3 grid_of(uint64_t n, uint32_t F, uint32_t per = kBlock) {
   const uint64_t b = (n + per - 1) / per;
   return dim3(static_cast<uint32_t>(b ? b : 1), F);
@@ -1772,12 +1910,13 @@ void launch_phase1(const Launch& L, hipStream_t st) {
   if (L.max_del == 0) return;
   k_phase1<<<grid_of(L.max_del, L.F), kBlock, 0, st>>>(L.argv);
   // walks read the prefix of long segments: rebuild the ones just changed
-  k_hub_prefix<<<dim3(kWideBlocks, L.F, 2), kBlock, 0, st>>>(L.argv, 0u, 0);
+  launch_hub_prefix(L, 0u, 2u, 0, st);
 }
 
 void launch_walks(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
-  k_walks<<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
+  if (L.hubs) k_walks<true><<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
+  else k_walks<false><<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
 }
 
 void launch_sum_counters(const Launch& L, hipStream_t st) {
@@ -1801,7 +1940,8 @@ void launch_walk_queue(const Launch& L, hipStream_t st) {
   if (L.upw > 0) {
     const uint32_t upw = L.upw < kMaxUpw ? L.upw : kMaxUpw;
     const uint32_t waves = (L.max_nu + upw - 1) / upw;
-    k_walk_range<<<grid_of(waves, L.F, kBlock / kWave), kBlock, 0, st>>>(L.argv, upw);
+    if (L.hubs) k_walk_range<true><<<grid_of(waves, L.F, kBlock / kWave), kBlock, 0, st>>>(L.argv, upw);
+    else k_walk_range<false><<<grid_of(waves, L.F, kBlock / kWave), kBlock, 0, st>>>(L.argv, upw);
   } else if (L.F > 1) {
     k_walk_queue<true><<<L.walk_blocks, kBlock, 0, st>>>(L.argv);
   } else {
@@ -1811,7 +1951,8 @@ void launch_walk_queue(const Launch& L, hipStream_t st) {
 
 void launch_queue_finish(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
-  k_reduce_updates<<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
+  if (L.hubs) k_reduce_updates<true><<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
+  else k_reduce_updates<false><<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
 }
 
 namespace {
@@ -1835,7 +1976,7 @@ void phase4_sequence(const Launch& L, uint32_t which0, uint32_t nw, hipStream_t 
   k_add_place<<<g, kBlock, 0, st>>>(L.argv, which0);
   k_rows_merge<<<g, kBlock, 0, st>>>(L.argv, which0);
   k_rows_merge_wide<<<wide, kBlock, 0, st>>>(L.argv, which0);
-  k_hub_prefix<<<wide, kBlock, 0, st>>>(L.argv, which0, 1);
+  launch_hub_prefix(L, which0, nw, 1, st);
 }
 
 }  // namespace

@@ -94,7 +94,7 @@ class dyg_request_done(C.Structure):
 
 EXPORTS = ["dyg_default_params", "dyg_init", "dyg_apply_batch", "dyg_apply_batch_dev",
            "dyg_sync", "dyg_query_sparsifier", "dyg_query_graph", "dyg_stats", "dyg_compact",
-           "dyg_destroy", "dyg_error_string", "dyg_get_tuning", "dyg_set_tuning",
+           "dyg_destroy", "dyg_error_string", "dyg_get_tuning", "dyg_set_tuning", "dyg_reserve",
            "dyg_check_state", "dyg_server_default_params", "dyg_server_create",
            "dyg_server_add_graph", "dyg_server_submit", "dyg_server_poll", "dyg_server_pending",
            "dyg_server_now", "dyg_server_destroy"]
@@ -158,6 +158,8 @@ def _load():
     lib.dyg_check_state.restype = C.c_int
     lib.dyg_get_tuning.argtypes = [P, C.POINTER(dyg_tuning)]
     lib.dyg_get_tuning.restype = C.c_int
+    lib.dyg_reserve.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]
+    lib.dyg_reserve.restype = C.c_int
     lib.dyg_set_tuning.argtypes = [P, C.POINTER(dyg_tuning)]
     lib.dyg_set_tuning.restype = C.c_int
     lib.dyg_compact.argtypes = [P]
@@ -315,6 +317,11 @@ def dyg_set_tuning(ctx, walk_blocks_per_cu: int, refill_min: int, updates_per_wa
 
 def dyg_compact(ctx):
     _check(_lib.dyg_compact(ctx), "dyg_compact")
+
+
+def dyg_reserve(ctx, max_ins: int, max_del: int, max_s: int = 0, max_L: int = 0):
+    _check(_lib.dyg_reserve(ctx, int(max_ins), int(max_del), int(max_s), int(max_L)),
+           "dyg_reserve")
 
 
 def dyg_destroy(ctx):

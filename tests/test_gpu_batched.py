@@ -186,3 +186,24 @@ def test_walk_schedules_agree(upw):
     finally:
         d.close()
         o.close()
+
+
+@pytest.mark.parametrize("flags", [0, BATCHED])
+def test_reserved_buffers(flags):
+    """dyg_reserve sizes the batch buffers up front; results stay the oracle's,
+    and out-of-range bounds are refused."""
+    from paper_2505_02741_amd import dygrass as D
+
+    wl = W.make_workload("rmat22", scale=11, batches=4, size_lo=50, size_hi=800)
+    o, d = make_pair(wl, flags=flags)
+    try:
+        D.dyg_reserve(d.ctx, 2000, 2000, 128, 32)
+        with pytest.raises(D.DygError) as e:
+            D.dyg_reserve(d.ctx, 10, 10, 5000, 8)
+        assert e.value.name == "INVALID_ARG"
+        for t, b in enumerate(wl.batches):
+            compare_batch(o, d, b, tag=f"reserved {t}")
+        compare_state(o, d, "reserved")
+    finally:
+        d.close()
+        o.close()

@@ -41,9 +41,11 @@ def _star_workload(n_leaves=300, seed=3):
     return W.Workload(name="star", G=G, h_mask=h, batches=[], seed_walk=77, s=64, L=12)
 
 
-@pytest.mark.parametrize("flags", [0, BATCHED])
-def test_star_centre_deletions_revivals_and_bounce(flags):
-    wl = _star_workload()
+@pytest.mark.parametrize("flags,leaves", [(0, 300), (BATCHED, 300), (0, 6000), (BATCHED, 6000)])
+def test_star_centre_deletions_revivals_and_bounce(flags, leaves):
+    """With 6,000 leaves the centre's weight prefix is rebuilt in several
+    chunks (after the deletions of phase 1 and after phase 4)."""
+    wl = _star_workload(n_leaves=leaves)
     n = wl.G.n
     o, d = make_pair(wl, flags=flags, dead_end=1)
     z = np.zeros(0, np.uint32)
