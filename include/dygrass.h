@@ -62,18 +62,25 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
 
 /* dyg_params.flags */
 #define DYG_FLAG_LEAN_POOLS 1u /* size entry pools to the live entries plus 64 spare
-                                  slots (instead of 50% + 4096) and grow on demand */
+                                  slots (instead of twice the live entries plus 8
+                                  per vertex) and grow on demand                 */
 #define DYG_FLAG_TIMING 2u     /* time the walk kernel and each batch with HIP
                                   events on the launch stream (dyg_stats)        */
-#define DYG_FLAG_BATCHED 4u    /* batched form: the walks of a batch run as one
-                                  persistent launch over a queue of (update,
-                                  walker) items; lanes take a new walker as soon
-                                  as theirs stops (same results as the plain
-                                  one-wavefront-per-update form)                 */
+#define DYG_FLAG_BATCHED 4u    /* batched form: walker counts are scanned on the
+                                  device and the walks run as one launch in which
+                                  a lane takes a new walker as soon as its own
+                                  stops (schedule in dyg_tuning; same results as
+                                  the plain one-wavefront-per-update form)       */
 #define DYG_FLAG_GRAPH 8u      /* run each batch's launch sequence as a captured
                                   HIP graph, one per power-of-two size class of
                                   (insertions, deletions), replayed for every
                                   batch of that class                            */
+#define DYG_FLAG_AUTOTUNE 16u  /* batched form: the first batches each try one
+                                  walk schedule from a fixed candidate list
+                                  (launched directly, walk kernel timed with HIP
+                                  events); the schedule with the least walk time
+                                  per walker step is then kept (dyg_get_tuning
+                                  reports it)                                     */
 
 #define DYG_MAX_WALKERS 1024 /* per update */
 #define DYG_MAX_STEPS 1024   /* per walker */

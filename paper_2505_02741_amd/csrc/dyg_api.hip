@@ -165,6 +165,12 @@ struct dyg_ctx {
   uint32_t refill_min = 1;                 // idle lanes that trigger a refill
   uint32_t updates_per_wave = 4;           // range walk (0 = work queue)
   bool has_hubs = false;                   // some row longer than kHub (walk kernel choice)
+  // DYG_FLAG_AUTOTUNE: candidate being tried (-1 = done), best score so far
+  int tune_next = -1;
+  int tune_best = -1;
+  double tune_best_score = 0.0;
+  unsigned long long tune_steps0 = 0;
+  bool last_graph = false;  // the batch enqueued last ran as a captured graph
   HBuf pin_in, pin_out;
 };
 
@@ -485,7 +491,8 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
         cus > 0)
       c->cus = static_cast<uint32_t>(cus);
   }
-  if (params->flags & DYG_FLAG_TIMING)
+  if (params->flags & DYG_FLAG_AUTOTUNE) c->tune_next = 0;
+  if (params->flags & (DYG_FLAG_TIMING | DYG_FLAG_AUTOTUNE))
     for (hipEvent_t& ev : c->ev)
       if ((e = hipEventCreate(&ev)) != hipSuccess) {
         dyg_destroy(c);
@@ -537,6 +544,7 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
     if (e == hipSuccess) e = hipMalloc(&c->dargs, sizeof(BatchArgs));
     if (e == hipSuccess) e = hipHostMalloc(&c->hargs, sizeof(BatchArgs), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&c->hctl, sizeof(BatchCtl), hipHostMallocDefault);
+    if (e == hipSuccess) std::memset(c->hctl, 0, sizeof(BatchCtl));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&c->dargv, sizeof(BatchArgs*));
     if (e == hipSuccess) {
@@ -735,13 +743,16 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
 
 // Enqueue one batch: copy its arguments to the device, then its launch
 // sequence (directly, or as the captured graph of its size class).
+bool tuning_now(const dyg_ctx* c);
+
 int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a) {
   const bool timed = c->ev[0] != nullptr;
   hipError_t e = hipSuccess;
   if (timed) (void)hipEventRecord(c->ev[0], c->stream);
   e = hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return fail_hip(e);
-  if (c->params.flags & DYG_FLAG_GRAPH) {
+  c->last_graph = (c->params.flags & DYG_FLAG_GRAPH) && !tuning_now(c);
+  if (c->last_graph) {
     hipGraphExec_t exec = nullptr;
     int rc = graph_for(c, a, &exec);
     if (rc) return rc;
@@ -764,17 +775,66 @@ int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a) {
 }
 
 // Fold the events of the batch that just completed into the timers.
-void collect_timing(dyg_ctx* c) {
-  if (!c->timed_pending) return;
+// Returns whether the walk kernel of the finished batch was timed.
+bool collect_timing(dyg_ctx* c) {
+  if (!c->timed_pending) return false;
   c->timed_pending = false;
   float walk = 0.f, batch = 0.f;
-  if (hipEventElapsedTime(&batch, c->ev[0], c->ev[3]) != hipSuccess) return;
+  if (hipEventElapsedTime(&batch, c->ev[0], c->ev[3]) != hipSuccess) return false;
   c->batch_ms_last = batch;
-  if (c->params.flags & DYG_FLAG_GRAPH) return;  // the walk kernel is inside the graph
-  if (hipEventElapsedTime(&walk, c->ev[1], c->ev[2]) == hipSuccess) {
-    c->walk_launches++;
-    c->walk_ms_last = walk;
-    c->walk_ms_total += walk;
+  if (c->last_graph) return false;  // the walk kernel was inside a captured graph
+  if (hipEventElapsedTime(&walk, c->ev[1], c->ev[2]) != hipSuccess) return false;
+  c->walk_launches++;
+  c->walk_ms_last = walk;
+  c->walk_ms_total += walk;
+  return true;
+}
+
+// Walk schedules the autotuner tries, one batch each: updates per wavefront
+// (0 = work queue), idle lanes that trigger a refill, queue grid per CU.
+struct TuneCandidate {
+  uint32_t upw, refill_min, blocks_per_cu;
+};
+constexpr TuneCandidate kTuneCandidates[] = {
+    {1, 1, 8}, {2, 1, 8}, {4, 1, 8}, {4, 8, 8}, {8, 1, 8}, {0, 1, 4}, {0, 16, 8},
+};
+constexpr int kTuneCount = static_cast<int>(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
+
+bool tuning_now(const dyg_ctx* c) {
+  return c->tune_next >= 0 && (c->params.flags & DYG_FLAG_BATCHED);
+}
+
+// Before a batch: put the next candidate in place.
+void tune_begin(dyg_ctx* c, unsigned long long steps_before) {
+  if (!tuning_now(c)) return;
+  const TuneCandidate& k = kTuneCandidates[c->tune_next];
+  c->updates_per_wave = k.upw;
+  c->refill_min = k.refill_min;
+  c->walk_blocks_per_cu = k.blocks_per_cu;
+  c->tune_steps0 = steps_before;
+}
+
+// After it: score the candidate (walk ms per walker step); after the last,
+// keep the best.
+void tune_end(dyg_ctx* c, unsigned long long steps_after, bool walk_timed) {
+  if (!tuning_now(c)) return;
+  const unsigned long long steps = steps_after - c->tune_steps0;
+  if (walk_timed && steps > 0) {
+    const double score = c->walk_ms_last / static_cast<double>(steps);
+    if (c->tune_best < 0 || score < c->tune_best_score) {
+      c->tune_best = c->tune_next;
+      c->tune_best_score = score;
+    }
+    ++c->tune_next;  // batches without walks do not count as a trial
+  }
+  if (c->tune_next >= kTuneCount) {
+    c->tune_next = -1;
+    if (c->tune_best >= 0) {
+      const TuneCandidate& k = kTuneCandidates[c->tune_best];
+      c->updates_per_wave = k.upw;
+      c->refill_min = k.refill_min;
+      c->walk_blocks_per_cu = k.blocks_per_cu;
+    }
   }
 }
 
@@ -847,6 +907,7 @@ extern "C" int dyg_apply_batch(dyg_ctx* c, uint64_t n_ins, const uint32_t* iu,
       wofs[i + 1] = wofs[i] + std::min<uint32_t>(s ? s[i] : c->params.s_default, DYG_MAX_WALKERS);
     walkers_total = wofs[nu];
   }
+  tune_begin(c, c->hctl->steps_total);
   uint64_t items_cap = 0;
   if (c->params.flags & DYG_FLAG_BATCHED) {
     if (s)
@@ -894,7 +955,7 @@ extern "C" int dyg_apply_batch(dyg_ctx* c, uint64_t n_ins, const uint32_t* iu,
   BatchCtl ctl;
   int rc = finish_ctl(c, ctl);
   if (rc) return rc;
-  collect_timing(c);
+  tune_end(c, ctl.steps_total, collect_timing(c));
   rc = decode_err(ctl.err_key);
   if (rc) return rc;
   if (ctl.nomem[0] || ctl.nomem[1]) {
@@ -939,6 +1000,7 @@ extern "C" int dyg_apply_batch_dev(dyg_ctx* c, const dyg_batch_dev* b, void* str
   if (b->s && b->s_max > DYG_MAX_WALKERS) return DYG_E_INVALID_ARG;
   const uint32_t Lcap = std::max<uint32_t>(b->L ? b->L_max : c->params.L_default, 2);
   const uint32_t scap = b->s ? b->s_max : c->params.s_default;
+  tune_begin(c, c->hctl->steps_total);
   uint64_t hadd_cap, hash_slots;
   if (prepare_buffers(c, n_ins, n_del, Lcap, 0, nu * scap, hadd_cap, hash_slots))
     return DYG_E_NOMEM;
@@ -968,7 +1030,7 @@ extern "C" int dyg_sync(dyg_ctx* c) {
   BatchCtl ctl;
   int rc = finish_ctl(c, ctl);
   if (rc) return c->pending_status = rc;
-  collect_timing(c);
+  tune_end(c, ctl.steps_total, collect_timing(c));
   rc = decode_err(ctl.err_key);
   if (rc) return c->pending_status = rc;
   if (ctl.nomem[0] || ctl.nomem[1]) {

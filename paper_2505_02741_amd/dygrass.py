@@ -35,6 +35,7 @@ FLAG_LEAN_POOLS = 1
 FLAG_TIMING = 2
 FLAG_BATCHED = 4
 FLAG_GRAPH = 8
+FLAG_AUTOTUNE = 16
 
 DEAD_END_TERMINATE = 0
 DEAD_END_BOUNCE = 1
@@ -302,7 +303,8 @@ def dyg_check_state(ctx) -> str:
 def dyg_get_tuning(ctx) -> dict:
     t = dyg_tuning()
     _check(_lib.dyg_get_tuning(ctx, C.byref(t)), "dyg_get_tuning")
-    return {"walk_blocks_per_cu": t.walk_blocks_per_cu, "refill_min": t.refill_min}
+    return {"walk_blocks_per_cu": t.walk_blocks_per_cu, "refill_min": t.refill_min,
+            "updates_per_wave": t.updates_per_wave}
 
 
 def dyg_set_tuning(ctx, walk_blocks_per_cu: int, refill_min: int, updates_per_wave: int = None):

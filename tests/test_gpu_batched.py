@@ -207,3 +207,24 @@ def test_reserved_buffers(flags):
     finally:
         d.close()
         o.close()
+
+
+def test_autotune_keeps_results_and_picks_a_schedule():
+    """With DYG_FLAG_AUTOTUNE the first batches each run another walk
+    schedule; every batch still matches the oracle, and after the trials the
+    context keeps one of the candidates."""
+    from paper_2505_02741_amd import dygrass as D
+
+    wl = W.make_workload("mesh128", side=10, ins=120, dels=100, batches=10)
+    o, d = make_pair(wl, flags=BATCHED | D.FLAG_AUTOTUNE)
+    try:
+        for t, b in enumerate(wl.batches):
+            compare_batch(o, d, b, record=False, tag=f"autotune {t}")
+        compare_state(o, d, "autotune")
+        t = D.dyg_get_tuning(d.ctx)
+        say("  kept schedule:", t)
+        assert t["updates_per_wave"] in (0, 1, 2, 4, 8)
+        assert d.stats()["walk_launches"] >= 7  # the trials were timed
+    finally:
+        d.close()
+        o.close()
