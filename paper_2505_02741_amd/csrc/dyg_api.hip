@@ -139,7 +139,7 @@ struct dyg_ctx {
   BatchCtl* ctl = nullptr;
   BatchArgs* dargs = nullptr;  // device copy of the current batch's arguments
   // DYG_FLAG_GRAPH: instantiated launch sequences by size class
-  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t, bool>, hipGraphExec_t>
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t, bool, bool>, hipGraphExec_t>
       graphs;
   BatchArgs* hargs = nullptr;  // pinned host staging of the same
   BatchCtl* hctl = nullptr;    // pinned copy of ctl, written at the end of each batch
@@ -165,6 +165,7 @@ struct dyg_ctx {
   uint32_t refill_min = 1;                 // idle lanes that trigger a refill
   uint32_t updates_per_wave = 4;           // range walk (0 = work queue)
   bool has_hubs = false;                   // some row longer than kHub (walk kernel choice)
+  double pool_frac[2] = {0.0, 0.0};        // share of G0 / H0 rows held in the pool (walk kernel choice)
   // DYG_FLAG_AUTOTUNE: candidate being tried (-1 = done), best score so far
   int tune_next = -1;
   int tune_best = -1;
@@ -528,6 +529,15 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
     hw[i] = w[hd[i].second];
   }
   for (uint32_t u = 0; u < n; ++u) hstart[u + 1] += hstart[u];
+  {
+    uint64_t pg = 0, ph = 0;
+    for (uint32_t u = 0; u < n; ++u) {
+      pg += rowptr[u + 1] - rowptr[u] > dyg::kInline;
+      ph += hstart[u + 1] - hstart[u] > dyg::kInline;
+    }
+    c->pool_frac[0] = n ? double(pg) / n : 0.0;
+    c->pool_frac[1] = n ? double(ph) / n : 0.0;
+  }
   HostAdj B;
   layout(B, n, hstart, he, hw, params->slack);
   const uint64_t gcap = pool_capacity_for(A.ent.size(), n, params->flags);
@@ -670,6 +680,14 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
   return a;
 }
 
+// Whether the plain walk kernel reads rows cooperatively: insertions walk H,
+// deletions walk G; worthwhile when at least 40% of the walks start in a
+// graph whose rows are mostly pool rows (by the initial degrees).
+bool use_coop(const dyg_ctx* c, uint64_t n_ins, uint64_t n_del) {
+  const double w = double(n_ins) * c->pool_frac[1] + double(n_del) * c->pool_frac[0];
+  return n_ins + n_del > 0 && w >= 0.4 * double(n_ins + n_del);
+}
+
 // Launch geometry of this context's batch `a` alone.
 dyg::Launch single_launch(dyg_ctx* c, const BatchArgs& a) {
   dyg::Launch L{};
@@ -683,6 +701,7 @@ dyg::Launch single_launch(dyg_ctx* c, const BatchArgs& a) {
   L.walk_blocks = c->cus * c->walk_blocks_per_cu;
   L.upw = c->updates_per_wave;
   L.hubs = c->has_hubs;
+  L.coop = use_coop(c, a.n_ins, a.n_del);
   return L;
 }
 
@@ -720,7 +739,7 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
   const uint32_t wb = c->cus * c->walk_blocks_per_cu;
   const auto key = std::make_tuple(uint64_t(cls.n_ins), uint64_t(cls.n_del),
                                    uint64_t(cls.hadd_cap), wb, c->updates_per_wave,
-                                   c->has_hubs);
+                                   c->has_hubs, use_coop(c, cls.n_ins, cls.n_del));
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     *out = it->second;

@@ -213,6 +213,7 @@ struct Launch {
   uint32_t walk_blocks;               // persistent walk grid
   uint32_t upw;                       // updates per wavefront (0 = work queue)
   bool hubs;                          // some row of a graph may be longer than kHub
+  bool coop;                          // plain walks: rows of the walked graphs are mostly pool rows
 };
 
 // Host-side launchers (defined in dyg_kernels.hip), all asynchronous on

@@ -553,22 +553,23 @@ __device__ __forceinline__ unsigned long long scale_random(unsigned long long r,
 // step's row and added then (the additions keep their order).
 // kHubs: the graphs may hold rows longer than kHub (else that branch, and the
 // bookkeeping it needs, are compiled out).
+//
+// walk_step_row takes the step's inputs already loaded: rprev = *S.rpend (0
+// without one), the row of S.x as four 16-byte pieces (ignored once
+// S.steps >= P.L), and the step's random number step_random(S, P, walker,
+// S.steps).  walk_step loads them itself.
 template <bool kHubs, class Sink>
-__device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
-                                          Sink& sink) {
+__device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Sink& sink,
+                                              double rprev, unsigned long long rnd,
+                                              const uint4 q0, const uint4 q1, const uint4 q2,
+                                              const uint4 q3) {
   const uint32_t t = S.steps;
   const bool has_prev = S.rpend != nullptr;
-  const double rprev = has_prev ? *S.rpend : 0.0;
   if (t >= P.L) {
     if (has_prev) S.R = S.R + rprev;
     S.rpend = nullptr;
     return false;
   }
-  const uint4* rq = reinterpret_cast<const uint4*>(P.rows + S.x);
-  const uint4 q0 = rq[0], q1 = rq[1], q2 = rq[2], q3 = rq[3];
-  // the step's random number depends only on (walker, step, update): drawn
-  // while the row is in flight (a dead end leaves it unused)
-  const unsigned long long rnd = step_random(S, P, walker, t);
   const RowHdr h{q0.x, q0.y, q0.z, q0.w};
   uint32_t pick_nbr, pick_idx, pick_q;
   const double* pick_r;
@@ -583,11 +584,36 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
     const uint32_t c3 = (h.len > 3 && n3 != S.prev) ? q2.w : 0u;
     const uint32_t c4 = (h.len > 4 && n4 != S.prev) ? q3.y : 0u;
     const uint32_t c5 = (h.len > 5 && n5 != S.prev) ? q3.w : 0u;
-    // running sums (a zero weight never crosses the target)
-    const unsigned long long r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
-                             tot = r4 + c5;
-    if (tot == 0) {
-      // leaf: the walker stops, or steps back along the edge just used
+    // Running sums r0..r4 and tot; the pick is the first index whose running
+    // sum exceeds the target, i.e. the number of running sums r0..r4 at or
+    // below it (they never decrease, and a zero weight never crosses the
+    // target).  With every weight below 2^29 the six-term sums fit 32 bits
+    // exactly; heavier rows take the 64-bit sums.
+    bool b1, b2, b3, b4, b5;  // pick index >= 1 .. >= 5
+    bool leaf;
+    if (((q1.y | q1.w | q2.y | q2.w | q3.y | q3.w) >> 29) == 0u) {
+      const uint32_t r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
+                     tot = r4 + c5;
+      const uint32_t tg = static_cast<uint32_t>(scale_random(rnd, tot));
+      leaf = tot == 0u;
+      b1 = r0 <= tg;
+      b2 = r1 <= tg;
+      b3 = r2 <= tg;
+      b4 = r3 <= tg;
+      b5 = r4 <= tg;
+    } else {
+      const unsigned long long r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
+                               tot = r4 + c5;
+      const unsigned long long tg = scale_random(rnd, tot);
+      leaf = tot == 0ull;
+      b1 = r0 <= tg;
+      b2 = r1 <= tg;
+      b3 = r2 <= tg;
+      b4 = r3 <= tg;
+      b5 = r4 <= tg;
+    }
+    if (leaf) {
+      // the walker stops, or steps back along the edge just used
       const uint32_t back = (h.len > 0 && n0 == S.prev)   ? 0u
                             : (h.len > 1 && n1 == S.prev) ? 1u
                             : (h.len > 2 && n2 == S.prev) ? 2u
@@ -596,23 +622,17 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
                             : (h.len > 5 && n5 == S.prev) ? 5u
                                                           : kNone;
       stop = !(P.bounce && S.prev != kNone) || back == kNone;
-      pick_idx = back == kNone ? 0u : back;
-    } else {
-      const unsigned long long tg = scale_random(rnd, tot);
-      pick_idx = r0 > tg ? 0u : r1 > tg ? 1u : r2 > tg ? 2u : r3 > tg ? 3u : r4 > tg ? 4u : 5u;
+      const uint32_t bi = back == kNone ? 0u : back;
+      b1 = bi >= 1u;
+      b2 = bi >= 2u;
+      b3 = bi >= 3u;
+      b4 = bi >= 4u;
+      b5 = bi >= 5u;
     }
-    pick_nbr = pick_idx == 0   ? n0
-               : pick_idx == 1 ? n1
-               : pick_idx == 2 ? n2
-               : pick_idx == 3 ? n3
-               : pick_idx == 4 ? n4
-                               : n5;
-    pick_q = pick_idx == 0   ? q1.y
-             : pick_idx == 1 ? q1.w
-             : pick_idx == 2 ? q2.y
-             : pick_idx == 3 ? q2.w
-             : pick_idx == 4 ? q3.y
-                             : q3.w;
+    pick_idx = static_cast<uint32_t>(b1) + static_cast<uint32_t>(b2) + static_cast<uint32_t>(b3) +
+               static_cast<uint32_t>(b4) + static_cast<uint32_t>(b5);
+    pick_nbr = b5 ? n5 : b4 ? n4 : b3 ? n3 : b2 ? n2 : b1 ? n1 : n0;
+    pick_q = b5 ? q3.w : b4 ? q3.y : b3 ? q2.w : b2 ? q2.y : b1 ? q1.w : q1.y;
     pick_r = P.rinl + static_cast<uint64_t>(S.x) * kInline + pick_idx;
   } else if (kHubs && h.len > kHub) {
     // long segment: the candidates' running sums are the stored prefix with
@@ -734,6 +754,19 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
 }
 
 template <bool kHubs, class Sink>
+__device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
+                                          Sink& sink) {
+  const double rprev = S.rpend != nullptr ? *S.rpend : 0.0;
+  if (S.steps >= P.L) return walk_step_row<kHubs>(P, S, sink, rprev, 0ull, {}, {}, {}, {});
+  const uint4* rq = reinterpret_cast<const uint4*>(P.rows + S.x);
+  const uint4 q0 = rq[0], q1 = rq[1], q2 = rq[2], q3 = rq[3];
+  // the step's random number depends only on (walker, step, update): drawn
+  // while the row is in flight (a dead end leaves it unused)
+  const unsigned long long rnd = step_random(S, P, walker, S.steps);
+  return walk_step_row<kHubs>(P, S, sink, rprev, rnd, q0, q1, q2, q3);
+}
+
+template <bool kHubs, class Sink>
 __device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, Sink& sink) {
   WState S;
   walker_start(S, P.p);
@@ -746,6 +779,88 @@ __device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, S
 // knows to be the same on every lane (so per-wavefront data stays scalar).
 __device__ __forceinline__ uint32_t wave_in_block() {
   return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave)));
+}
+
+// A compiler barrier for memory accesses.  Lanes of one wavefront exchange
+// data through LDS below; the hardware keeps a wavefront's LDS accesses in
+// order, so only the compiler must not move them across each other.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+__device__ __forceinline__ uint4 ld_lds4(const volatile uint4* p) {
+  return make_uint4(p->x, p->y, p->z, p->w);
+}
+
+// The walk of every lane's walker, all lanes stepping together (active =
+// the lane has a walker).  With kCoop, rows may be read cooperatively: load k fetches
+// the rows of lanes 16k..16k+15, four lanes per row and 16 bytes per lane, so
+// an instruction touches 16 cache lines instead of the 64 of a per-lane row
+// read (the vector cache looks up each line an instruction touches); the
+// pieces come back to their walkers through `st` (kStageWords uint4 of LDS,
+// private to the wavefront): piece c of lane m's row sits at c * kStagePitch
+// + m, so the reads (consecutive lanes, consecutive slots) and the writes
+// (pitch 66 spreads the four pieces of a row over distinct banks) are free of
+// bank conflicts.  Same results as walk_one.
+constexpr uint32_t kStagePitch = kWave + 2;
+constexpr uint32_t kStageWords = 4 * kStagePitch;
+// The cooperative read pays off for pool rows, whose 64-byte row is only a
+// header: a step reads it together with the segment.  It is used for a step
+// when at least kCoopLanes walkers need a row and stood at a pool row last
+// step; a launch over graphs of mostly inline rows compiles it out (kCoop),
+// as its exchange only adds latency there and its registers cost occupancy.
+constexpr int kCoopLanes = 8;
+template <bool kHubs, bool kCoop>
+__device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, bool active,
+                                          uint4* st, uint32_t lane) {
+  WState S;
+  walker_start(S, P.p);
+  bool alive = active;
+  const uint4* rows4 = reinterpret_cast<const uint4*>(P.rows);
+  const uint32_t piece = lane & 3u;
+  NoSink none;
+  bool at_pool = false;  // the lane's last row was a pool row
+  while (__ballot(alive) != 0ull) {
+    const bool need = alive && S.steps < P.L;
+    const unsigned long long needm = __ballot(need);
+    const double rprev = (alive && S.rpend != nullptr) ? *S.rpend : 0.0;
+    uint4 q0 = make_uint4(0u, 0u, 0u, 0u), q1 = q0, q2 = q0, q3 = q0;
+    unsigned long long rnd = 0;
+    if (kCoop && __popcll(__ballot(need && at_pool)) >= kCoopLanes) {
+      uint4 c[4];
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t src = 16u * k + (lane >> 2);
+        const uint32_t xs =
+            static_cast<uint32_t>(__shfl(static_cast<int>(S.x), static_cast<int>(src), kWave));
+        c[k] = make_uint4(0u, 0u, 0u, 0u);
+        if ((needm >> src) & 1ull) c[k] = rows4[static_cast<uint64_t>(xs) * 4u + piece];
+      }
+      // drawn while the rows are in flight
+      if (need) rnd = step_random(S, P, walker, S.steps);
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) st[piece * kStagePitch + 16u * k + (lane >> 2)] = c[k];
+      wave_lds_order();
+      // whole 16-byte reads (volatile: not narrowed to the fields used)
+      const volatile uint4* vs = st;
+      q0 = ld_lds4(vs + lane);
+      q1 = ld_lds4(vs + kStagePitch + lane);
+      q2 = ld_lds4(vs + 2 * kStagePitch + lane);
+      q3 = ld_lds4(vs + 3 * kStagePitch + lane);
+      wave_lds_order();
+    } else if (need) {
+      // few walkers left: each lane reads its own row (no exchange latency)
+      const uint4* rq = rows4 + static_cast<uint64_t>(S.x) * 4u;
+      q0 = rq[0];
+      q1 = rq[1];
+      q2 = rq[2];
+      q3 = rq[3];
+      rnd = step_random(S, P, walker, S.steps);
+    }
+    at_pool = need && q0.x != kInlineOff;
+    if (alive) alive = walk_step_row<kHubs>(P, S, none, rprev, rnd, q0, q1, q2, q3);
+  }
+  return Walk{S.steps, S.x, S.R, S.hit, S.bytes};
 }
 
 // Wavefront argmin of (R, walker): smaller R wins, ties go to the lower walker.
@@ -996,8 +1111,9 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
 
 // Plain form: one wavefront per update, one lane per walker (more walkers
 // than lanes run in successive rounds of 64).
-template <bool kHubs>
+template <bool kHubs, bool kCoop>
 __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv) {
+  __shared__ uint4 stage[kCoop ? kWalkBlock / kWave : 1][kCoop ? kStageWords : 1];
   const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph G = a.g[0];
   const DevGraph H = a.g[1];
@@ -1017,9 +1133,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
   for (uint32_t base = 0; base < v.s; base += kWave) {
     const uint32_t walker = base + lane;
     const bool active = walker < v.s;
-    Walk o{0, v.P.p, 0.0, false, 0};
-    NoSink none;
-    if (active) o = walk_one<kHubs>(v.P, walker, none);
+    const Walk o =
+        walk_wave<kHubs, kCoop>(v.P, walker, active, stage[kCoop ? wave_in_block() : 0], lane);
     if (active && a.wrec)
       a.wrec[a.wofs[upd] + walker] =
           WalkerRec{static_cast<uint8_t>(o.hit), 0, static_cast<uint16_t>(o.steps), o.end, o.R};
@@ -1915,8 +2030,11 @@ void launch_phase1(const Launch& L, hipStream_t st) {
 
 void launch_walks(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
-  if (L.hubs) k_walks<true><<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
-  else k_walks<false><<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
+  const dim3 g = grid_of(L.max_nu, L.F, kWalkBlock / kWave);
+  if (L.hubs && L.coop) k_walks<true, true><<<g, kWalkBlock, 0, st>>>(L.argv);
+  else if (L.hubs) k_walks<true, false><<<g, kWalkBlock, 0, st>>>(L.argv);
+  else if (L.coop) k_walks<false, true><<<g, kWalkBlock, 0, st>>>(L.argv);
+  else k_walks<false, false><<<g, kWalkBlock, 0, st>>>(L.argv);
 }
 
 void launch_sum_counters(const Launch& L, hipStream_t st) {
