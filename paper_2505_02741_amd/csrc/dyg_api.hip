@@ -1245,6 +1245,9 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
       const bool inl = r.off == kInlineOff;
       if (r.len > r.cap) return fail("len exceeds cap", g, u, r.len);
       if (inl && r.cap != kInline) return fail("inline row capacity", g, u, r.cap);
+      if (inl)  // the walk's inline selection relies on weight 0 past len
+        for (uint32_t i = r.len; i < kInline; ++i)
+          if (I.rows[u].inl[i].qw != 0u) return fail("inline slot past len in use", g, u, i);
       if (!inl && static_cast<uint64_t>(r.off) + r.cap > ctl.pool_top[g])
         return fail("segment beyond pool top", g, u, r.off);
       if (!inl && r.cap) spans.push_back({r.off, static_cast<uint64_t>(r.off) + r.cap});

@@ -19,6 +19,8 @@ namespace dyg {
 // slots (per-node slack).  A deleted edge stays in place as a tombstone
 // (qw == 0) until its segment is relocated or compacted; a zero weight never
 // wins the cumulative search, so walks skip tombstones without testing them.
+// The inline slots of a row past its len also hold qw == 0 (rows are zeroed
+// when laid out, and an inline row only grows until it moves to the pool).
 // Neighbour ids are unique within a row (a re-inserted edge revives its
 // tombstone).
 struct Ent {

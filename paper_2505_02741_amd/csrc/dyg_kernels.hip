@@ -503,10 +503,14 @@ struct WState {
   uint32_t x, prev, steps, block_of, bytes;
   uint32_t qprev;  // quantised weight of the edge just taken (the same both ways)
   double R;
-  const double* rpend;  // 1/w of the last edge taken, not yet added to R
+  const double* rpend;  // 1/w of the last edge taken, not yet added to R (else kZeroR)
   Philox4 rnd;
   bool hit;
 };
+
+// What a walker's pending resistance points to when nothing is pending:
+// adding it leaves R unchanged (R >= 0), so the pending addition needs no test.
+__device__ double kZeroR = 0.0;  // never written
 
 __device__ __forceinline__ void walker_start(WState& S, uint32_t p) {
   S.x = p;
@@ -516,7 +520,7 @@ __device__ __forceinline__ void walker_start(WState& S, uint32_t p) {
   S.block_of = kNone;
   S.bytes = 0;
   S.R = 0.0;
-  S.rpend = nullptr;
+  S.rpend = &kZeroR;
   S.hit = false;
 }
 
@@ -554,8 +558,8 @@ __device__ __forceinline__ unsigned long long scale_random(unsigned long long r,
 // kHubs: the graphs may hold rows longer than kHub (else that branch, and the
 // bookkeeping it needs, are compiled out).
 //
-// walk_step_row takes the step's inputs already loaded: rprev = *S.rpend (0
-// without one), the row of S.x as four 16-byte pieces (ignored once
+// walk_step_row takes the step's inputs already loaded: rprev = *S.rpend,
+// the row of S.x as four 16-byte pieces (ignored once
 // S.steps >= P.L), and the step's random number step_random(S, P, walker,
 // S.steps).  walk_step loads them itself.
 template <bool kHubs, class Sink>
@@ -564,76 +568,81 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
                                               const uint4 q0, const uint4 q1, const uint4 q2,
                                               const uint4 q3) {
   const uint32_t t = S.steps;
-  const bool has_prev = S.rpend != nullptr;
   if (t >= P.L) {
-    if (has_prev) S.R = S.R + rprev;
-    S.rpend = nullptr;
+    S.R = S.R + rprev;
+    S.rpend = &kZeroR;
     return false;
   }
   const RowHdr h{q0.x, q0.y, q0.z, q0.w};
-  uint32_t pick_nbr, pick_idx, pick_q;
+  uint32_t pick_nbr, pick_idx, pick_q, sbytes;
   const double* pick_r;
   bool stop = false;
   if (h.off == kInlineOff) {
-    // inline pairs (nbr, qw): q1 = pairs 0-1, q2 = 2-3, q3 = 4-5
+    // inline pairs (nbr, qw): q1 = pairs 0-1, q2 = 2-3, q3 = 4-5.  The slots
+    // at and past len hold weight 0 (an inline row is zeroed when laid out
+    // and only grows), as do tombstones, so leaving out the previous vertex
+    // is the only masking the selection needs.
     static_assert(kInline == 6, "inline branch reads six pairs");
     const uint32_t n0 = q1.x, n1 = q1.z, n2 = q2.x, n3 = q2.z, n4 = q3.x, n5 = q3.z;
-    const uint32_t c0 = (h.len > 0 && n0 != S.prev) ? q1.y : 0u;
-    const uint32_t c1 = (h.len > 1 && n1 != S.prev) ? q1.w : 0u;
-    const uint32_t c2 = (h.len > 2 && n2 != S.prev) ? q2.y : 0u;
-    const uint32_t c3 = (h.len > 3 && n3 != S.prev) ? q2.w : 0u;
-    const uint32_t c4 = (h.len > 4 && n4 != S.prev) ? q3.y : 0u;
-    const uint32_t c5 = (h.len > 5 && n5 != S.prev) ? q3.w : 0u;
+    const uint32_t c0 = n0 != S.prev ? q1.y : 0u;
+    const uint32_t c1 = n1 != S.prev ? q1.w : 0u;
+    const uint32_t c2 = n2 != S.prev ? q2.y : 0u;
+    const uint32_t c3 = n3 != S.prev ? q2.w : 0u;
+    const uint32_t c4 = n4 != S.prev ? q3.y : 0u;
+    const uint32_t c5 = n5 != S.prev ? q3.w : 0u;
     // Running sums r0..r4 and tot; the pick is the first index whose running
     // sum exceeds the target, i.e. the number of running sums r0..r4 at or
     // below it (they never decrease, and a zero weight never crosses the
     // target).  With every weight below 2^29 the six-term sums fit 32 bits
-    // exactly; heavier rows take the 64-bit sums.
-    bool b1, b2, b3, b4, b5;  // pick index >= 1 .. >= 5
+    // exactly; a wavefront with a heavier row takes the 64-bit sums.
+    const bool heavy = ((q1.y | q1.w | q2.y | q2.w | q3.y | q3.w) >> 29) != 0u;
     bool leaf;
-    if (((q1.y | q1.w | q2.y | q2.w | q3.y | q3.w) >> 29) == 0u) {
+    if (__ballot(heavy) == 0ull) {
       const uint32_t r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
                      tot = r4 + c5;
       const uint32_t tg = static_cast<uint32_t>(scale_random(rnd, tot));
       leaf = tot == 0u;
-      b1 = r0 <= tg;
-      b2 = r1 <= tg;
-      b3 = r2 <= tg;
-      b4 = r3 <= tg;
-      b5 = r4 <= tg;
+      pick_idx = static_cast<uint32_t>(r0 <= tg) + static_cast<uint32_t>(r1 <= tg) +
+                 static_cast<uint32_t>(r2 <= tg) + static_cast<uint32_t>(r3 <= tg) +
+                 static_cast<uint32_t>(r4 <= tg);
     } else {
       const unsigned long long r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
                                tot = r4 + c5;
       const unsigned long long tg = scale_random(rnd, tot);
       leaf = tot == 0ull;
-      b1 = r0 <= tg;
-      b2 = r1 <= tg;
-      b3 = r2 <= tg;
-      b4 = r3 <= tg;
-      b5 = r4 <= tg;
+      pick_idx = static_cast<uint32_t>(r0 <= tg) + static_cast<uint32_t>(r1 <= tg) +
+                 static_cast<uint32_t>(r2 <= tg) + static_cast<uint32_t>(r3 <= tg) +
+                 static_cast<uint32_t>(r4 <= tg);
     }
     if (leaf) {
       // the walker stops, or steps back along the edge just used
-      const uint32_t back = (h.len > 0 && n0 == S.prev)   ? 0u
-                            : (h.len > 1 && n1 == S.prev) ? 1u
-                            : (h.len > 2 && n2 == S.prev) ? 2u
-                            : (h.len > 3 && n3 == S.prev) ? 3u
-                            : (h.len > 4 && n4 == S.prev) ? 4u
-                            : (h.len > 5 && n5 == S.prev) ? 5u
-                                                          : kNone;
-      stop = !(P.bounce && S.prev != kNone) || back == kNone;
-      const uint32_t bi = back == kNone ? 0u : back;
-      b1 = bi >= 1u;
-      b2 = bi >= 2u;
-      b3 = bi >= 3u;
-      b4 = bi >= 4u;
-      b5 = bi >= 5u;
+      stop = true;
+      if (P.bounce && S.prev != kNone) {
+        const uint32_t back = (h.len > 0 && n0 == S.prev)   ? 0u
+                              : (h.len > 1 && n1 == S.prev) ? 1u
+                              : (h.len > 2 && n2 == S.prev) ? 2u
+                              : (h.len > 3 && n3 == S.prev) ? 3u
+                              : (h.len > 4 && n4 == S.prev) ? 4u
+                              : (h.len > 5 && n5 == S.prev) ? 5u
+                                                            : kNone;
+        stop = back == kNone;
+        pick_idx = stop ? 0u : back;
+      }
     }
-    pick_idx = static_cast<uint32_t>(b1) + static_cast<uint32_t>(b2) + static_cast<uint32_t>(b3) +
-               static_cast<uint32_t>(b4) + static_cast<uint32_t>(b5);
-    pick_nbr = b5 ? n5 : b4 ? n4 : b3 ? n3 : b2 ? n2 : b1 ? n1 : n0;
-    pick_q = b5 ? q3.w : b4 ? q3.y : b3 ? q2.w : b2 ? q2.y : b1 ? q1.w : q1.y;
-    pick_r = P.rinl + static_cast<uint64_t>(S.x) * kInline + pick_idx;
+    pick_nbr = pick_idx == 5u   ? n5
+               : pick_idx == 4u ? n4
+               : pick_idx == 3u ? n3
+               : pick_idx == 2u ? n2
+               : pick_idx == 1u ? n1
+                                : n0;
+    pick_q = pick_idx == 5u   ? q3.w
+             : pick_idx == 4u ? q3.y
+             : pick_idx == 3u ? q2.w
+             : pick_idx == 2u ? q2.y
+             : pick_idx == 1u ? q1.w
+                              : q1.y;
+    pick_r = P.rinl + (static_cast<uint64_t>(S.x) * kInline + pick_idx);
+    sbytes = 16u + 8u * (h.len - h.dead);
   } else if (kHubs && h.len > kHub) {
     // long segment: the candidates' running sums are the stored prefix with
     // the previous vertex's weight (that of the edge just taken) left out.
@@ -678,6 +687,7 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     pick_nbr = stop ? kNone : seg[pick_idx].nbr;
     pick_q = stop ? 0u : seg[pick_idx].qw;
     pick_r = &seg[pick_idx].rinv;
+    sbytes = step_bytes(h.len - h.dead);
   } else {
     const Ent* seg = P.ent + h.off;
     const uint2* e2 = reinterpret_cast<const uint2*>(seg);  // (nbr, qw) pairs
@@ -728,11 +738,12 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     pick_nbr = stop ? kNone : pe.x;
     pick_q = stop ? 0u : pe.y;
     pick_r = &seg[pick_idx].rinv;
+    sbytes = step_bytes(h.len - h.dead);
   }
-  if (has_prev) S.R = S.R + rprev;
-  S.rpend = nullptr;
+  S.R = S.R + rprev;
+  S.rpend = &kZeroR;
   if (stop) return false;
-  S.bytes += step_bytes(h.len - h.dead);
+  S.bytes += sbytes;
   sink(S.x, pick_nbr, pick_idx, h.off);
   S.prev = S.x;
   if (kHubs) S.qprev = pick_q;
@@ -746,8 +757,8 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
   }
   if (S.x == P.q) {
     S.hit = true;
-    if (S.rpend) S.R = S.R + *S.rpend;
-    S.rpend = nullptr;
+    S.R = S.R + *S.rpend;
+    S.rpend = &kZeroR;
     return false;
   }
   return true;
@@ -756,7 +767,7 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
 template <bool kHubs, class Sink>
 __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
                                           Sink& sink) {
-  const double rprev = S.rpend != nullptr ? *S.rpend : 0.0;
+  const double rprev = *S.rpend;
   if (S.steps >= P.L) return walk_step_row<kHubs>(P, S, sink, rprev, 0ull, {}, {}, {}, {});
   const uint4* rq = reinterpret_cast<const uint4*>(P.rows + S.x);
   const uint4 q0 = rq[0], q1 = rq[1], q2 = rq[2], q3 = rq[3];
@@ -823,8 +834,9 @@ __device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, 
   while (__ballot(alive) != 0ull) {
     const bool need = alive && S.steps < P.L;
     const unsigned long long needm = __ballot(need);
-    const double rprev = (alive && S.rpend != nullptr) ? *S.rpend : 0.0;
-    uint4 q0 = make_uint4(0u, 0u, 0u, 0u), q1 = q0, q2 = q0, q3 = q0;
+    const double rprev = alive ? *S.rpend : 0.0;
+    // read only by lanes that need a row (walk_step_row ignores them past L)
+    uint4 q0, q1, q2, q3;
     unsigned long long rnd = 0;
     if (kCoop && __popcll(__ballot(need && at_pool)) >= kCoopLanes) {
       uint4 c[4];
@@ -849,7 +861,7 @@ __device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, 
       q3 = ld_lds4(vs + 3 * kStagePitch + lane);
       wave_lds_order();
     } else if (need) {
-      // few walkers left: each lane reads its own row (no exchange latency)
+      // each lane reads its own row
       const uint4* rq = rows4 + static_cast<uint64_t>(S.x) * 4u;
       q0 = rq[0];
       q1 = rq[1];
