@@ -629,18 +629,19 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
         pick_idx = stop ? 0u : back;
       }
     }
-    pick_nbr = pick_idx == 5u   ? n5
-               : pick_idx == 4u ? n4
-               : pick_idx == 3u ? n3
-               : pick_idx == 2u ? n2
-               : pick_idx == 1u ? n1
-                                : n0;
-    pick_q = pick_idx == 5u   ? q3.w
-             : pick_idx == 4u ? q3.y
-             : pick_idx == 3u ? q2.w
-             : pick_idx == 2u ? q2.y
-             : pick_idx == 1u ? q1.w
-                              : q1.y;
+    // a chain of selects (an equality chain would become a branch tree)
+    pick_nbr = n0;
+    pick_q = q1.y;
+    pick_nbr = pick_idx >= 1u ? n1 : pick_nbr;
+    pick_q = pick_idx >= 1u ? q1.w : pick_q;
+    pick_nbr = pick_idx >= 2u ? n2 : pick_nbr;
+    pick_q = pick_idx >= 2u ? q2.y : pick_q;
+    pick_nbr = pick_idx >= 3u ? n3 : pick_nbr;
+    pick_q = pick_idx >= 3u ? q2.w : pick_q;
+    pick_nbr = pick_idx >= 4u ? n4 : pick_nbr;
+    pick_q = pick_idx >= 4u ? q3.y : pick_q;
+    pick_nbr = pick_idx >= 5u ? n5 : pick_nbr;
+    pick_q = pick_idx >= 5u ? q3.w : pick_q;
     pick_r = P.rinl + (static_cast<uint64_t>(S.x) * kInline + pick_idx);
     sbytes = 16u + 8u * (h.len - h.dead);
   } else if (kHubs && h.len > kHub) {
