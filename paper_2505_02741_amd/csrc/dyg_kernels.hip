@@ -534,6 +534,15 @@ __device__ __forceinline__ unsigned long long step_random(WState& S, const WalkP
                   : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
 }
 
+// step_random for lanes stepping in lockstep from step 0 (t uniform): the
+// block of steps t, t+1 is drawn at every even t.
+__device__ __forceinline__ unsigned long long step_random_lockstep(WState& S, const WalkParams& P,
+                                                                   uint32_t walker, uint32_t t) {
+  if ((t & 1u) == 0u) S.rnd = philox4x32_10(t >> 1, walker, P.uid_lo, P.uid_hi, P.key0, P.key1);
+  return (t & 1u) ? (uint64_t(S.rnd.x2) | (uint64_t(S.rnd.x3) << 32))
+                  : (uint64_t(S.rnd.x0) | (uint64_t(S.rnd.x1) << 32));
+}
+
 // floor(r * tot / 2^64), the selection target.  With tot < 2^32 (every row
 // of fewer than 256 neighbours whose weights do not exceed w_ref) the high
 // half of the 128-bit product takes two 32x32 products: r*tot = rh*tot*2^32 +
@@ -558,16 +567,17 @@ __device__ __forceinline__ unsigned long long scale_random(unsigned long long r,
 // kHubs: the graphs may hold rows longer than kHub (else that branch, and the
 // bookkeeping it needs, are compiled out).
 //
-// walk_step_row takes the step's inputs already loaded: rprev = *S.rpend,
+// walk_step_row takes the step's inputs already loaded: t = S.steps (a
+// caller stepping lanes in lockstep passes its wavefront-uniform count),
+// rprev = *S.rpend,
 // the row of S.x as four 16-byte pieces (ignored once
 // S.steps >= P.L), and the step's random number step_random(S, P, walker,
 // S.steps).  walk_step loads them itself.
 template <bool kHubs, class Sink>
 __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Sink& sink,
-                                              double rprev, unsigned long long rnd,
+                                              uint32_t t, double rprev, unsigned long long rnd,
                                               const uint4 q0, const uint4 q1, const uint4 q2,
                                               const uint4 q3) {
-  const uint32_t t = S.steps;
   if (t >= P.L) {
     S.R = S.R + rprev;
     S.rpend = &kZeroR;
@@ -769,13 +779,14 @@ template <bool kHubs, class Sink>
 __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, WState& S,
                                           Sink& sink) {
   const double rprev = *S.rpend;
-  if (S.steps >= P.L) return walk_step_row<kHubs>(P, S, sink, rprev, 0ull, {}, {}, {}, {});
+  if (S.steps >= P.L)
+    return walk_step_row<kHubs>(P, S, sink, S.steps, rprev, 0ull, {}, {}, {}, {});
   const uint4* rq = reinterpret_cast<const uint4*>(P.rows + S.x);
   const uint4 q0 = rq[0], q1 = rq[1], q2 = rq[2], q3 = rq[3];
   // the step's random number depends only on (walker, step, update): drawn
   // while the row is in flight (a dead end leaves it unused)
   const unsigned long long rnd = step_random(S, P, walker, S.steps);
-  return walk_step_row<kHubs>(P, S, sink, rprev, rnd, q0, q1, q2, q3);
+  return walk_step_row<kHubs>(P, S, sink, S.steps, rprev, rnd, q0, q1, q2, q3);
 }
 
 template <bool kHubs, class Sink>
@@ -832,13 +843,15 @@ __device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, 
   const uint32_t piece = lane & 3u;
   NoSink none;
   bool at_pool = false;  // the lane's last row was a pool row
-  while (__ballot(alive) != 0ull) {
-    const bool need = alive && S.steps < P.L;
+  // Every live lane has taken one step per iteration, so its step count is
+  // the iteration count t, which the compiler then knows to be uniform.
+  for (uint32_t t = 0; __ballot(alive) != 0ull; ++t) {
+    const bool need = alive && t < P.L;
     const unsigned long long needm = __ballot(need);
     const double rprev = alive ? *S.rpend : 0.0;
     // read only by lanes that need a row (walk_step_row ignores them past L)
     uint4 q0, q1, q2, q3;
-    unsigned long long rnd = 0;
+    unsigned long long rnd;
     if (kCoop && __popcll(__ballot(need && at_pool)) >= kCoopLanes) {
       uint4 c[4];
 #pragma unroll
@@ -850,7 +863,7 @@ __device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, 
         if ((needm >> src) & 1ull) c[k] = rows4[static_cast<uint64_t>(xs) * 4u + piece];
       }
       // drawn while the rows are in flight
-      if (need) rnd = step_random(S, P, walker, S.steps);
+      rnd = step_random_lockstep(S, P, walker, t);
 #pragma unroll
       for (uint32_t k = 0; k < 4; ++k) st[piece * kStagePitch + 16u * k + (lane >> 2)] = c[k];
       wave_lds_order();
@@ -861,17 +874,20 @@ __device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, 
       q2 = ld_lds4(vs + 2 * kStagePitch + lane);
       q3 = ld_lds4(vs + 3 * kStagePitch + lane);
       wave_lds_order();
-    } else if (need) {
+    } else {
       // each lane reads its own row
-      const uint4* rq = rows4 + static_cast<uint64_t>(S.x) * 4u;
-      q0 = rq[0];
-      q1 = rq[1];
-      q2 = rq[2];
-      q3 = rq[3];
-      rnd = step_random(S, P, walker, S.steps);
+      if (need) {
+        const uint4* rq = rows4 + static_cast<uint64_t>(S.x) * 4u;
+        q0 = rq[0];
+        q1 = rq[1];
+        q2 = rq[2];
+        q3 = rq[3];
+      }
+      // drawn on every lane (the cost is per instruction) while rows load
+      rnd = step_random_lockstep(S, P, walker, t);
     }
     at_pool = need && q0.x != kInlineOff;
-    if (alive) alive = walk_step_row<kHubs>(P, S, none, rprev, rnd, q0, q1, q2, q3);
+    if (alive) alive = walk_step_row<kHubs>(P, S, none, t, rprev, rnd, q0, q1, q2, q3);
   }
   return Walk{S.steps, S.x, S.R, S.hit, S.bytes};
 }
