@@ -39,7 +39,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "updates/s + walker-steps/s (frac of HBM gather roofline); p50/p99 batch latency"
 HBM_PEAK_GBS = 8000.0
-KERNELS = {"plain": "k_walks", "batched": "k_walk_range"}
+# the walk kernels of each form ("a+b": a walk of two launches, summed)
+KERNELS = {"plain": "k_walks", "batched": "k_walk_head+k_walk_tail"}
+TUNE_CANDIDATES = 10  # schedules the autotuner tries, one batch each
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
 
 
@@ -113,27 +115,31 @@ def traffic_from_counters(fetch_csv, write_csv, kernel, calib_bytes, workload, f
     scaled so that the copy kernel of calib_bytes (the --calibrate-copy-mib
     run) reads and writes exactly calib_bytes; written to the traffic file."""
 
+    names = kernel.split("+")
+
     def per_kernel(path, counter):
-        vals, copy = [], []
+        vals, copy = {k: [] for k in names}, []
         with open(path) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
                     continue
                 v = float(r["Counter_Value"]) * 1024.0
-                if kernel in r["Kernel_Name"]:
-                    vals.append(v)
+                hit = [k for k in names if k + "<" in r["Kernel_Name"] or k + "(" in r["Kernel_Name"]]
+                if hit:
+                    vals[hit[0]].append(v)
                 elif "copyBuffer" in r["Kernel_Name"] and v > 0.5 * calib_bytes:
                     copy.append(v)
         return vals, copy
 
     f_vals, f_copy = per_kernel(fetch_csv, "FETCH_SIZE")
     w_vals, w_copy = per_kernel(write_csv, "WRITE_SIZE")
-    if not f_vals or not w_vals or not f_copy or not w_copy:
+    if not all(f_vals.values()) or not all(w_vals.values()) or not f_copy or not w_copy:
         raise SystemExit("traffic: kernel or calibration copy missing from the counter files")
     f_scale = calib_bytes / max(f_copy)
     w_scale = calib_bytes / max(w_copy)
-    fetch = sum(f_vals) / len(f_vals) * f_scale
-    write = sum(w_vals) / len(w_vals) * w_scale
+    # one walk = one dispatch of each of its kernels
+    fetch = sum(sum(v) / len(v) for v in f_vals.values()) * f_scale
+    write = sum(sum(v) / len(v) for v in w_vals.values()) * w_scale
     d = {}
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -142,7 +148,7 @@ def traffic_from_counters(fetch_csv, write_csv, kernel, calib_bytes, workload, f
         "kernel": kernel, "kernel_source": kernel_source_hash(),
         "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
         "bytes_per_launch": fetch + write, "fetch_scale": f_scale, "write_scale": w_scale,
-        "launches": [len(f_vals), len(w_vals)],
+        "launches": [min(len(v) for v in f_vals.values()), min(len(v) for v in w_vals.values())],
     }
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
@@ -198,8 +204,9 @@ def run_stream(D, torch, wl, rp, col, w, dev_batches, flags, warmup, tuning=None
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     st1 = ctx.stats()
+    tuning_kept = D.dyg_get_tuning(ctx.ctx)
     ctx.close()
-    r = dict(t_total=t_total, lat=lat)
+    r = dict(t_total=t_total, lat=lat, tuning=tuning_kept)
     for k in ("walk_steps", "walk_alg_bytes", "walk_ms_total", "walk_launches"):
         r[k] = st1[k] - st0[k]
     return r
@@ -245,7 +252,8 @@ def main_batches(args):
     dev_batches = [to_device(np, torch, dev, b) for b in wl.batches]
     torch.cuda.synchronize()
 
-    forms = {"plain": 0, "batched": D.FLAG_BATCHED | (D.FLAG_GRAPH if args.graph else 0)}
+    forms = {"plain": 0, "batched": D.FLAG_BATCHED | (D.FLAG_GRAPH if args.graph else 0) |
+             (D.FLAG_AUTOTUNE if args.autotune else 0)}
     head = args.form if args.form in forms else ("plain" if args.workload != "rmat22" else "batched")
     chosen = [head] if args.form in forms else list(forms)
     runs = {}
@@ -256,7 +264,9 @@ def main_batches(args):
     # the walk kernel inside a captured graph is not timed: the roofline of the
     # batched form then comes from the same schedule launched directly
     if "batched" in runs and head == "batched" and args.graph:
-        timed = run_stream(D, torch, wl, rp, col, w, dev_batches, D.FLAG_BATCHED, args.warmup)
+        timed = run_stream(D, torch, wl, rp, col, w, dev_batches,
+                           D.FLAG_BATCHED | (D.FLAG_AUTOTUNE if args.autotune else 0),
+                           args.warmup)
     else:
         timed = runs[head]
     R = runs[head]
@@ -321,6 +331,8 @@ def main_batches(args):
         },
         "cpu_baseline": None,
     }
+    if "batched" in runs:
+        out["batched_schedule"] = runs["batched"]["tuning"]
     if "plain" in runs and "batched" in runs:
         out["batched_over_plain"] = runs["plain"]["t_total"] / runs["batched"]["t_total"]
     if int(os.environ.get("RANK", "0")) == 0 and not args.no_cpu_baseline:
@@ -486,6 +498,10 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="batched form: replay each batch's launch sequence from a captured "
                          "hipGraph (one per power-of-two size class)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched form: the first batches try the autotuner's schedules "
+                         f"(warmup raised to at least {TUNE_CANDIDATES} so that they are "
+                         "not timed)")
     ap.add_argument("--graphs", type=int, default=64, help="serving: resident graphs")
     ap.add_argument("--requests-per-graph", type=int, default=16)
     ap.add_argument("--max-nodes", type=int, default=500_000)
@@ -501,6 +517,8 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
               "supported (the multi-GPU sharding is a design, not a run).", file=sys.stderr)
         sys.exit(2)
+    if args.autotune and args.warmup < TUNE_CANDIDATES:
+        args.warmup = TUNE_CANDIDATES
     if args.traffic_from:
         form = args.form if args.form in KERNELS else "plain"
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], KERNELS[form],

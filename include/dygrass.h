@@ -218,7 +218,9 @@ int dyg_query_graph(dyg_ctx* ctx, uint64_t cap, uint64_t* m, uint32_t* u, uint32
 
 int dyg_stats(dyg_ctx* ctx, dyg_stats_t* out);
 
-/* Launch schedule of the batched form (results never depend on it). */
+/* Launch schedule of the batched form (results never depend on it).
+ * Defaults: walk_blocks_per_cu 8, refill_min 1, updates_per_wave 4,
+ * tail_lanes 8. */
 typedef struct {
   uint32_t walk_blocks_per_cu; /* persistent walk grid = CUs x this (1..64)       */
   uint32_t refill_min;         /* idle lanes of a wavefront that trigger a refill
@@ -227,7 +229,13 @@ typedef struct {
                                   the launch; 1..8: each wavefront walks the walkers
                                   of this many consecutive updates, a lane whose
                                   walker stops taking the next one of that range   */
-  uint32_t reserved[5];
+  uint32_t tail_lanes;         /* 0: off.  1..64: head/tail schedule (single
+                                  contexts): a head wavefront per update walks its
+                                  walkers in lockstep until at most this many (and
+                                  at most a quarter of them) still walk, then the
+                                  tail walk packs those of updates_per_wave (at
+                                  least 1) consecutive updates per wavefront      */
+  uint32_t reserved[4];
 } dyg_tuning;
 
 int dyg_get_tuning(dyg_ctx* ctx, dyg_tuning* out);

@@ -139,7 +139,8 @@ struct dyg_ctx {
   BatchCtl* ctl = nullptr;
   BatchArgs* dargs = nullptr;  // device copy of the current batch's arguments
   // DYG_FLAG_GRAPH: instantiated launch sequences by size class
-  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t, bool, bool>, hipGraphExec_t>
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t, bool, bool, uint32_t>,
+           hipGraphExec_t>
       graphs;
   BatchArgs* hargs = nullptr;  // pinned host staging of the same
   BatchCtl* hctl = nullptr;    // pinned copy of ctl, written at the end of each batch
@@ -160,10 +161,12 @@ struct dyg_ctx {
   DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2], wide_rows[2];
   DBuf hash2;
   DBuf qcount, qofs, qtile, items, wres;  // batched form
+  DBuf tstate, tcount;                     // batched form, head/tail schedule
   uint32_t cus = 256;                      // compute units of the device
   uint32_t walk_blocks_per_cu = 8;         // persistent walk grid = cus x this
   uint32_t refill_min = 1;                 // idle lanes that trigger a refill
   uint32_t updates_per_wave = 4;           // range walk (0 = work queue)
+  uint32_t tail_lanes = 8;                 // head/tail schedule (0 = off)
   bool has_hubs = false;                   // some row longer than kHub (walk kernel choice)
   double pool_frac[2] = {0.0, 0.0};        // share of G0 / H0 rows held in the pool (walk kernel choice)
   // DYG_FLAG_AUTOTUNE: candidate being tried (-1 = done), best score so far
@@ -607,7 +610,9 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
          c->qtile.ensure(8 * tiles + 8) &&
          // item records only for the work queue (the range walk derives them)
          (c->updates_per_wave > 0 || c->items.ensure(sizeof(dyg::WalkItem) * items_cap + 8)) &&
-         c->wres.ensure(sizeof(dyg::WalkOut) * items_cap + 16);
+         c->wres.ensure(sizeof(dyg::WalkOut) * items_cap + 16) &&
+         (c->tail_lanes == 0 || (c->tstate.ensure(sizeof(dyg::TailState) * items_cap + 16) &&
+                                 c->tcount.ensure(4 * nu + 8)));
   }
   for (int g = 0; g < 2 && ok; ++g) {
     const uint64_t cap = g == 0 ? 2 * n_ins : 2 * hadd_cap;
@@ -677,6 +682,9 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
   a.refill_min = c->refill_min;
   a.upw = c->updates_per_wave;
   a.wres = c->wres.as<dyg::WalkOut>();
+  a.tail_lanes = c->tail_lanes;
+  a.tstate = c->tstate.as<dyg::TailState>();
+  a.tcount = c->tcount.as<uint32_t>();
   return a;
 }
 
@@ -702,6 +710,7 @@ dyg::Launch single_launch(dyg_ctx* c, const BatchArgs& a) {
   L.upw = c->updates_per_wave;
   L.hubs = c->has_hubs;
   L.coop = use_coop(c, a.n_ins, a.n_del);
+  L.tail_lanes = c->tail_lanes;
   return L;
 }
 
@@ -739,7 +748,8 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
   const uint32_t wb = c->cus * c->walk_blocks_per_cu;
   const auto key = std::make_tuple(uint64_t(cls.n_ins), uint64_t(cls.n_del),
                                    uint64_t(cls.hadd_cap), wb, c->updates_per_wave,
-                                   c->has_hubs, use_coop(c, cls.n_ins, cls.n_del));
+                                   c->has_hubs, use_coop(c, cls.n_ins, cls.n_del),
+                                   c->tail_lanes);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     *out = it->second;
@@ -812,10 +822,11 @@ bool collect_timing(dyg_ctx* c) {
 // Walk schedules the autotuner tries, one batch each: updates per wavefront
 // (0 = work queue), idle lanes that trigger a refill, queue grid per CU.
 struct TuneCandidate {
-  uint32_t upw, refill_min, blocks_per_cu;
+  uint32_t upw, refill_min, blocks_per_cu, tail_lanes;
 };
 constexpr TuneCandidate kTuneCandidates[] = {
-    {1, 1, 8}, {2, 1, 8}, {4, 1, 8}, {4, 8, 8}, {8, 1, 8}, {0, 1, 4}, {0, 16, 8},
+    {1, 1, 8, 0},  {2, 1, 8, 0},  {4, 1, 8, 0},  {4, 8, 8, 0},  {8, 1, 8, 0},
+    {0, 1, 4, 0},  {0, 16, 8, 0}, {4, 1, 8, 8},  {4, 1, 8, 16}, {8, 1, 8, 16},
 };
 constexpr int kTuneCount = static_cast<int>(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
 
@@ -830,6 +841,7 @@ void tune_begin(dyg_ctx* c, unsigned long long steps_before) {
   c->updates_per_wave = k.upw;
   c->refill_min = k.refill_min;
   c->walk_blocks_per_cu = k.blocks_per_cu;
+  c->tail_lanes = k.tail_lanes;
   c->tune_steps0 = steps_before;
 }
 
@@ -853,6 +865,7 @@ void tune_end(dyg_ctx* c, unsigned long long steps_after, bool walk_timed) {
       c->updates_per_wave = k.upw;
       c->refill_min = k.refill_min;
       c->walk_blocks_per_cu = k.blocks_per_cu;
+      c->tail_lanes = k.tail_lanes;
     }
   }
 }
@@ -1306,17 +1319,19 @@ extern "C" int dyg_get_tuning(dyg_ctx* c, dyg_tuning* out) {
   out->walk_blocks_per_cu = c->walk_blocks_per_cu;
   out->refill_min = c->refill_min;
   out->updates_per_wave = c->updates_per_wave;
+  out->tail_lanes = c->tail_lanes;
   return DYG_OK;
 }
 
 extern "C" int dyg_set_tuning(dyg_ctx* c, const dyg_tuning* t) {
   if (!c || !t) return DYG_E_INVALID_ARG;
   if (t->walk_blocks_per_cu < 1 || t->walk_blocks_per_cu > 64 || t->refill_min < 1 ||
-      t->refill_min > 64 || t->updates_per_wave > dyg::kMaxUpw)
+      t->refill_min > 64 || t->updates_per_wave > dyg::kMaxUpw || t->tail_lanes > 64)
     return DYG_E_INVALID_ARG;
   c->walk_blocks_per_cu = t->walk_blocks_per_cu;
   c->refill_min = t->refill_min;
   c->updates_per_wave = t->updates_per_wave;
+  c->tail_lanes = t->tail_lanes;
   return DYG_OK;
 }
 
@@ -1373,7 +1388,7 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
                   &c->hash};
   for (DBuf* b : bufs) b->release();
   c->hash2.release();
-  DBuf* qbufs[] = {&c->qcount, &c->qofs, &c->qtile, &c->items, &c->wres};
+  DBuf* qbufs[] = {&c->qcount, &c->qofs, &c->qtile, &c->items, &c->wres, &c->tstate, &c->tcount};
   for (DBuf* b : qbufs) b->release();
   for (int g = 0; g < 2; ++g) {
     c->touched_rows[g].release();
@@ -1517,6 +1532,9 @@ int stage_request(ServerRound& r, ServerRequest* q, dyg_ctx* c, uint64_t item_ca
   a.qctl = r.qctl;
   a.items = r.items.as<dyg::WalkItem>();
   a.wres = r.wres.as<dyg::WalkOut>();
+  a.tail_lanes = 0;  // serving rounds use the range walk or the work queue
+  a.tstate = nullptr;
+  a.tcount = nullptr;
   (void)item_cap_total;
   e = hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, r.stream);
   if (e != hipSuccess) return fail_hip(e);

@@ -127,6 +127,16 @@ struct WalkOut {
 };
 static_assert(sizeof(WalkOut) == 24, "WalkOut layout");
 
+// A walker handed from the head walk to the tail walk (batched form, head/tail
+// schedule): its state after `t` steps.
+struct TailState {
+  uint32_t x, prev, t, bytes;
+  uint32_t qprev, walker;
+  double R;
+  const double* rpend;  // 1/w of the last edge taken, not yet added to R
+};
+static_assert(sizeof(TailState) == 40, "TailState layout");
+
 // Device-resident control block of one batch.
 struct BatchCtl {
   unsigned long long err_key;   // min over (phase, update, code); ~0 = valid
@@ -203,6 +213,11 @@ struct BatchArgs {
   uint32_t refill_min;           // idle lanes that trigger a refill (1..64)
   uint32_t upw;                  // updates per wavefront of the range walk (0 = queue)
   WalkOut* wres;                 // [items] outcome of each walker
+  // head/tail schedule (tail_lanes > 0): a head wavefront per update stops
+  // once at most tail_lanes of its lanes still walk and hands those walkers on
+  uint32_t tail_lanes;
+  TailState* tstate;             // [items] the survivors of update u from item qofs[u]
+  uint32_t* tcount;              // [n_ins + n_del] survivors of each update
 };
 
 // One launch of F batches (F = 1 for a single context; up to kMaxFused when a
@@ -216,6 +231,7 @@ struct Launch {
   uint32_t upw;                       // updates per wavefront (0 = work queue)
   bool hubs;                          // some row of a graph may be longer than kHub
   bool coop;                          // plain walks: rows of the walked graphs are mostly pool rows
+  uint32_t tail_lanes;                // batched form: head/tail schedule (0 = off)
 };
 
 // Host-side launchers (defined in dyg_kernels.hip), all asynchronous on

@@ -606,24 +606,34 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     // target).  With every weight below 2^29 the six-term sums fit 32 bits
     // exactly; a wavefront with a heavier row takes the 64-bit sums.
     const bool heavy = ((q1.y | q1.w | q2.y | q2.w | q3.y | q3.w) >> 29) != 0u;
+    bool b1, b2, b3, b4, b5;  // pick index >= 1 .. >= 5
     bool leaf;
-    if (__ballot(heavy) == 0ull) {
+    if (__ballot(heavy) == 0ull) {  // uniform: the flags need no merging
       const uint32_t r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
                      tot = r4 + c5;
       const uint32_t tg = static_cast<uint32_t>(scale_random(rnd, tot));
       leaf = tot == 0u;
-      pick_idx = static_cast<uint32_t>(r0 <= tg) + static_cast<uint32_t>(r1 <= tg) +
-                 static_cast<uint32_t>(r2 <= tg) + static_cast<uint32_t>(r3 <= tg) +
-                 static_cast<uint32_t>(r4 <= tg);
+      b1 = r0 <= tg;
+      b2 = r1 <= tg;
+      b3 = r2 <= tg;
+      b4 = r3 <= tg;
+      b5 = r4 <= tg;
     } else {
       const unsigned long long r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
                                tot = r4 + c5;
       const unsigned long long tg = scale_random(rnd, tot);
       leaf = tot == 0ull;
-      pick_idx = static_cast<uint32_t>(r0 <= tg) + static_cast<uint32_t>(r1 <= tg) +
-                 static_cast<uint32_t>(r2 <= tg) + static_cast<uint32_t>(r3 <= tg) +
-                 static_cast<uint32_t>(r4 <= tg);
+      b1 = r0 <= tg;
+      b2 = r1 <= tg;
+      b3 = r2 <= tg;
+      b4 = r3 <= tg;
+      b5 = r4 <= tg;
     }
+    // chains of selects on the monotone flags (an index compare chain would
+    // cost the compares again, an equality chain would become a branch tree)
+    pick_idx = b5 ? 5u : b4 ? 4u : b3 ? 3u : b2 ? 2u : b1 ? 1u : 0u;
+    pick_nbr = b5 ? n5 : b4 ? n4 : b3 ? n3 : b2 ? n2 : b1 ? n1 : n0;
+    pick_q = b5 ? q3.w : b4 ? q3.y : b3 ? q2.w : b2 ? q2.y : b1 ? q1.w : q1.y;
     if (leaf) {
       // the walker stops, or steps back along the edge just used
       stop = true;
@@ -637,21 +647,15 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
                                                             : kNone;
         stop = back == kNone;
         pick_idx = stop ? 0u : back;
+        pick_nbr = S.prev;
+        pick_q = pick_idx == 0u   ? q1.y
+                 : pick_idx == 1u ? q1.w
+                 : pick_idx == 2u ? q2.y
+                 : pick_idx == 3u ? q2.w
+                 : pick_idx == 4u ? q3.y
+                                  : q3.w;
       }
     }
-    // a chain of selects (an equality chain would become a branch tree)
-    pick_nbr = n0;
-    pick_q = q1.y;
-    pick_nbr = pick_idx >= 1u ? n1 : pick_nbr;
-    pick_q = pick_idx >= 1u ? q1.w : pick_q;
-    pick_nbr = pick_idx >= 2u ? n2 : pick_nbr;
-    pick_q = pick_idx >= 2u ? q2.y : pick_q;
-    pick_nbr = pick_idx >= 3u ? n3 : pick_nbr;
-    pick_q = pick_idx >= 3u ? q2.w : pick_q;
-    pick_nbr = pick_idx >= 4u ? n4 : pick_nbr;
-    pick_q = pick_idx >= 4u ? q3.y : pick_q;
-    pick_nbr = pick_idx >= 5u ? n5 : pick_nbr;
-    pick_q = pick_idx >= 5u ? q3.w : pick_q;
     pick_r = P.rinl + (static_cast<uint64_t>(S.x) * kInline + pick_idx);
     sbytes = 16u + 8u * (h.len - h.dead);
   } else if (kHubs && h.len > kHub) {
@@ -816,7 +820,10 @@ __device__ __forceinline__ uint4 ld_lds4(const volatile uint4* p) {
 }
 
 // The walk of every lane's walker, all lanes stepping together (active =
-// the lane has a walker).  With kCoop, rows may be read cooperatively: load k fetches
+// the lane has a walker), until every walker has stopped or, with handoff >
+// 0, until at most `handoff` still walk (walk_lockstep then returns true on
+// their lanes, S holding their state).  With kCoop, rows may be read
+// cooperatively: load k fetches
 // the rows of lanes 16k..16k+15, four lanes per row and 16 bytes per lane, so
 // an instruction touches 16 cache lines instead of the 64 of a per-lane row
 // read (the vector cache looks up each line an instruction touches); the
@@ -834,9 +841,9 @@ constexpr uint32_t kStageWords = 4 * kStagePitch;
 // as its exchange only adds latency there and its registers cost occupancy.
 constexpr int kCoopLanes = 8;
 template <bool kHubs, bool kCoop>
-__device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, bool active,
-                                          uint4* st, uint32_t lane) {
-  WState S;
+__device__ __forceinline__ bool walk_lockstep(const WalkParams& P, uint32_t walker, bool active,
+                                              uint4* st, uint32_t lane, uint32_t handoff,
+                                              WState& S) {
   walker_start(S, P.p);
   bool alive = active;
   const uint4* rows4 = reinterpret_cast<const uint4*>(P.rows);
@@ -845,7 +852,9 @@ __device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, 
   bool at_pool = false;  // the lane's last row was a pool row
   // Every live lane has taken one step per iteration, so its step count is
   // the iteration count t, which the compiler then knows to be uniform.
-  for (uint32_t t = 0; __ballot(alive) != 0ull; ++t) {
+  for (uint32_t t = 0;; ++t) {
+    const unsigned long long live = __ballot(alive);
+    if (live == 0ull || static_cast<uint32_t>(__popcll(live)) <= handoff) break;
     const bool need = alive && t < P.L;
     const unsigned long long needm = __ballot(need);
     const double rprev = alive ? *S.rpend : 0.0;
@@ -889,6 +898,14 @@ __device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, 
     at_pool = need && q0.x != kInlineOff;
     if (alive) alive = walk_step_row<kHubs>(P, S, none, t, rprev, rnd, q0, q1, q2, q3);
   }
+  return alive;
+}
+
+template <bool kHubs, bool kCoop>
+__device__ __forceinline__ Walk walk_wave(const WalkParams& P, uint32_t walker, bool active,
+                                          uint4* st, uint32_t lane) {
+  WState S;
+  walk_lockstep<kHubs, kCoop>(P, walker, active, st, lane, 0u, S);
   return Walk{S.steps, S.x, S.R, S.hit, S.bytes};
 }
 
@@ -1523,6 +1540,150 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
   }
 }
 
+// Batched form, head/tail schedule.  Walks are short and heavy-tailed: most
+// walkers of an update stop within a few steps while a few run to L, and a
+// wavefront's instructions cost the same however few lanes still walk.  The
+// head walk runs each update's walkers in lockstep (one wavefront per update,
+// as the plain form) until at most tail_lanes of them (and at most a quarter
+// of the round) still walk, records the finished walkers' outcomes and
+// hands the rest to the tail walk, which packs the survivors of several
+// updates into each wavefront.  Same results as the plain form.
+template <bool kHubs>
+__global__ __launch_bounds__(kWalkBlock) void k_walk_head(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
+  const DevGraph G = a.g[0];
+  const DevGraph H = a.g[1];
+  if (batch_failed(a.ctl)) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + wave_in_block();
+  if (upd >= a.n_ins + a.n_del) return;  // uniform across the wavefront
+  const UpdateView v = view_update(a, G, H, upd);
+  const unsigned long long first = a.ctl->item_base + a.qofs[upd];
+  const unsigned long long lanes_below = (1ull << lane) - 1ull;
+  uint32_t tails = 0;
+  if (v.walks) {
+    for (uint32_t base = 0; base < v.s; base += kWave) {
+      const uint32_t walker = base + lane;
+      const bool active = walker < v.s;
+      const uint32_t n_round = (v.s - base) < kWave ? (v.s - base) : kWave;
+      const uint32_t handoff = a.tail_lanes < n_round / 4 ? a.tail_lanes : n_round / 4;
+      WState S;
+      const bool more = walk_lockstep<kHubs, false>(v.P, walker, active, nullptr, lane, handoff, S);
+      const unsigned long long moving = __ballot(more);
+      if (more) {
+        const uint32_t r = tails + static_cast<uint32_t>(__popcll(moving & lanes_below));
+        a.tstate[first + r] =
+            TailState{S.x, S.prev, S.steps, S.bytes, S.qprev, walker, S.R, S.rpend};
+      } else if (active) {
+        a.wres[first + walker] = WalkOut{S.x, static_cast<uint16_t>(S.steps),
+                                         static_cast<uint8_t>(S.hit), 0, S.bytes, 0u, S.R};
+      }
+      tails += static_cast<uint32_t>(__popcll(moving));
+    }
+  }
+  if (lane == 0) a.tcount[upd] = tails;
+}
+
+// Tail walk: wavefront w walks the survivors of updates [w*upw, w*upw + upw)
+// (tcount of each, states in tstate), a lane whose walker stops taking the
+// next one; each outcome goes to its walker's slot in wres.
+template <bool kHubs>
+__global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __restrict__ argv,
+                                                      uint32_t upw) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
+  if (batch_failed(a.ctl)) return;
+  const uint32_t nu = a.n_ins + a.n_del;
+  const uint32_t u0 = (blockIdx.x * (kBlock / kWave) + wave_in_block()) * upw;
+  if (u0 >= nu) return;  // uniform across the wavefront
+  const uint32_t nr = (nu - u0) < upw ? (nu - u0) : upw;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const unsigned long long lanes_below = (1ull << lane) - 1ull;
+  uint32_t endw[kMaxUpw];  // end (exclusive) of each update's survivors within the range
+  uint32_t total = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kMaxUpw; ++j) {
+    if (j < nr) total += a.tcount[u0 + j];
+    endw[j] = total;
+  }
+  if (total == 0) return;
+  const unsigned long long item0 = a.ctl->item_base;
+  WalkParams P;
+  P.K = a.K;
+  P.key0 = static_cast<uint32_t>(a.seed);
+  P.key1 = static_cast<uint32_t>(a.seed >> 32);
+  P.bounce = a.bounce != 0;
+  P.rows = a.g[1].rows;
+  P.ent = a.g[1].ent;
+  P.pfx = a.g[1].pfx;
+  P.rinl = a.g[1].rinl;
+  P.p = P.q = 0;
+  P.use_K = false;
+  P.w_pq = 0.0;
+  P.L = 0;
+  P.uid_lo = P.uid_hi = 0;
+  WState S;
+  walker_start(S, 0);
+  uint32_t next = 0;  // survivors of the range handed out so far (uniform)
+  uint32_t walker = 0;
+  unsigned long long out = 0;
+  bool active = false;
+  while (true) {
+    // hand the next survivors of the range to idle lanes
+    const unsigned long long idle = __ballot(!active);
+    const uint32_t n_idle = static_cast<uint32_t>(__popcll(idle));
+    if (next < total && n_idle) {
+      const uint32_t rank = static_cast<uint32_t>(__popcll(idle & lanes_below));
+      if (!active && next + rank < total) {
+        const uint32_t idx = next + rank;
+        uint32_t j = 0, start = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kMaxUpw; ++k)
+          if (endw[k] <= idx) {
+            j = k + 1;
+            start = endw[k];
+          }
+        const uint32_t upd = u0 + j;
+        const bool is_ins = upd < a.n_ins;
+        const uint32_t jd = upd - a.n_ins;
+        const uint64_t uid = a.uid_base + upd;
+        P.q = is_ins ? a.iv[upd] : a.dv[jd];
+        P.w_pq = is_ins ? a.iw[upd] : 0.0;
+        P.use_K = is_ins && a.has_K;
+        P.L = a.L ? a.L[upd] : a.L_def;
+        P.uid_lo = static_cast<uint32_t>(uid);
+        P.uid_hi = static_cast<uint32_t>(uid >> 32);
+        const DevGraph& X = is_ins ? a.g[1] : a.g[0];  // H_mid for insertions, G_mid for deletions
+        P.rows = X.rows;
+        P.ent = X.ent;
+        P.pfx = X.pfx;
+        P.rinl = X.rinl;
+        const unsigned long long first = item0 + a.qofs[upd];
+        const TailState ts = a.tstate[first + (idx - start)];
+        S.x = ts.x;
+        S.prev = ts.prev;
+        S.steps = ts.t;
+        S.bytes = ts.bytes;
+        S.qprev = ts.qprev;
+        S.R = ts.R;
+        S.rpend = ts.rpend;
+        S.block_of = kNone;  // the next step draws its block afresh
+        S.hit = false;
+        walker = ts.walker;
+        out = first + ts.walker;
+        active = true;
+      }
+      next = (next + n_idle) < total ? next + n_idle : total;
+    }
+    NoSink none;
+    if (active && !walk_step<kHubs>(P, walker, S, none)) {
+      a.wres[out] = WalkOut{S.x, static_cast<uint16_t>(S.steps), static_cast<uint8_t>(S.hit), 0,
+                            S.bytes, 0u, S.R};
+      active = false;
+    }
+    if (__ballot(active) == 0ull && next >= total) break;
+  }
+}
+
 // Reduce each update's walker records and decide it (one wavefront per update).
 template <bool kHubs>
 __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* const* __restrict__ argv) {
@@ -2084,7 +2245,19 @@ void launch_queue_prepare(const Launch& L, hipStream_t st) {
 
 void launch_walk_queue(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
-  if (L.upw > 0) {
+  if (L.tail_lanes > 0) {
+    const uint32_t upw = L.upw < 1 ? 1u : (L.upw < kMaxUpw ? L.upw : kMaxUpw);
+    const uint32_t waves = (L.max_nu + upw - 1) / upw;
+    const dim3 gh = grid_of(L.max_nu, L.F, kWalkBlock / kWave);
+    const dim3 gt = grid_of(waves, L.F, kBlock / kWave);
+    if (L.hubs) {
+      k_walk_head<true><<<gh, kWalkBlock, 0, st>>>(L.argv);
+      k_walk_tail<true><<<gt, kBlock, 0, st>>>(L.argv, upw);
+    } else {
+      k_walk_head<false><<<gh, kWalkBlock, 0, st>>>(L.argv);
+      k_walk_tail<false><<<gt, kBlock, 0, st>>>(L.argv, upw);
+    }
+  } else if (L.upw > 0) {
     const uint32_t upw = L.upw < kMaxUpw ? L.upw : kMaxUpw;
     const uint32_t waves = (L.max_nu + upw - 1) / upw;
     if (L.hubs) k_walk_range<true><<<grid_of(waves, L.F, kBlock / kWave), kBlock, 0, st>>>(L.argv, upw);

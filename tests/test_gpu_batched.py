@@ -176,13 +176,58 @@ def test_walk_schedules_agree(upw):
         b.L = rng.integers(1, 30, b.size).astype(np.uint16)
     o, d = make_pair(wl, flags=BATCHED)
     try:
-        D.dyg_set_tuning(d.ctx, 4, 1, upw)
+        D.dyg_set_tuning(d.ctx, 4, 1, upw, 0)
         for t, b in enumerate(wl.batches):
             compare_batch(o, d, b, tag=f"upw={upw} batch {t}")
         compare_state(o, d, f"upw={upw}")
         st = d.stats()
         assert st["walk_steps"] == o.steps_total
         assert st["walk_alg_bytes"] == o.alg_bytes_total
+    finally:
+        d.close()
+        o.close()
+
+
+@pytest.mark.parametrize("tail_lanes,upw", [(8, 1), (16, 4), (64, 8)])
+def test_head_tail_schedule_agrees(tail_lanes, upw):
+    """The head/tail schedule (lockstep head per update, survivors packed into
+    tail wavefronts) changes no result: walker counts from 0 to 149 (rounds of
+    64, heads too small to hand anything off), uneven step limits, insertions
+    and deletions, against the oracle."""
+    from paper_2505_02741_amd import dygrass as D
+
+    wl = W.make_workload("mesh128", side=10, ins=150, dels=120, batches=4)
+    rng = np.random.default_rng(23)
+    for b in wl.batches:
+        b.s = rng.integers(0, 150, b.size).astype(np.uint16)
+        b.L = rng.integers(1, 30, b.size).astype(np.uint16)
+    o, d = make_pair(wl, flags=BATCHED)
+    try:
+        D.dyg_set_tuning(d.ctx, 8, 1, upw, tail_lanes)
+        assert D.dyg_get_tuning(d.ctx)["tail_lanes"] == tail_lanes
+        for t, b in enumerate(wl.batches):
+            compare_batch(o, d, b, tag=f"tail={tail_lanes} upw={upw} batch {t}")
+        compare_state(o, d, f"tail={tail_lanes}")
+        st = d.stats()
+        assert st["walk_steps"] == o.steps_total
+        assert st["walk_alg_bytes"] == o.alg_bytes_total
+    finally:
+        d.close()
+        o.close()
+
+
+def test_head_tail_schedule_hubs_and_graph_mode():
+    """Head/tail schedule on a power-law graph (hub rows) and replayed from
+    captured graphs: the oracle's results."""
+    from paper_2505_02741_amd import dygrass as D
+
+    wl = W.make_workload("rmat22", scale=11, batches=4, size_lo=50, size_hi=800)
+    o, d = make_pair(wl, flags=BATCHED | GRAPH)
+    try:
+        D.dyg_set_tuning(d.ctx, 8, 1, 4, 16)
+        for t, b in enumerate(wl.batches):
+            compare_batch(o, d, b, tag=f"rmat head/tail batch {t}")
+        compare_state(o, d, "rmat head/tail")
     finally:
         d.close()
         o.close()
@@ -215,7 +260,7 @@ def test_autotune_keeps_results_and_picks_a_schedule():
     context keeps one of the candidates."""
     from paper_2505_02741_amd import dygrass as D
 
-    wl = W.make_workload("mesh128", side=10, ins=120, dels=100, batches=10)
+    wl = W.make_workload("mesh128", side=10, ins=120, dels=100, batches=12)
     o, d = make_pair(wl, flags=BATCHED | D.FLAG_AUTOTUNE)
     try:
         for t, b in enumerate(wl.batches):
@@ -224,7 +269,8 @@ def test_autotune_keeps_results_and_picks_a_schedule():
         t = D.dyg_get_tuning(d.ctx)
         say("  kept schedule:", t)
         assert t["updates_per_wave"] in (0, 1, 2, 4, 8)
-        assert d.stats()["walk_launches"] >= 7  # the trials were timed
+        assert t["tail_lanes"] in (0, 8, 16)
+        assert d.stats()["walk_launches"] >= 10  # the trials were timed
     finally:
         d.close()
         o.close()
