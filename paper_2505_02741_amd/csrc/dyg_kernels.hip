@@ -430,7 +430,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* _
   const uint32_t from = after_phase1 ? ctl->dirty_p1[which] : 0u;
   // phase 1's list ends here; phase 4 appends after it (same value from every block)
   if (!after_phase1 && blockIdx.x == 0 && threadIdx.x == 0) ctl->dirty_p1[which] = count;
-  constexpr uint32_t kPer = 8;  // consecutive entries per thread per block scan
+  // consecutive entries per thread per block scan: a hub row of 10^5 entries
+  // takes a few dozen scans with many loads in flight, not hundreds
+  constexpr uint32_t kPer = 32;
   for (uint32_t t = from + blockIdx.x; t < count; t += gridDim.x) {
     const uint32_t r = dirty_rows[t];
     const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment
@@ -2038,6 +2040,8 @@ constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 K
 // entries below them; new entries sit after the old entries below them) and
 // moves the old entries right to left in block-sized chunks, so no entry is
 // overwritten before it is read.
+constexpr uint32_t kMergePer = 8;  // old entries per thread and chunk of a wide merge
+
 __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
   const uint32_t which = which0 + blockIdx.z;
   const P4 a = load_p4(argv, blockIdx.y, which);
@@ -2099,28 +2103,46 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* con
         s_pos[j] = j + lo;
       }
       __syncthreads();
-      // old entries, right to left
-      for (uint32_t hi_i = cur; hi_i > 0;) {
-        const uint32_t lo_i = hi_i > kBlock ? hi_i - kBlock : 0;
-        const uint32_t i = lo_i + threadIdx.x;
-        Ent e{0, 0, 0.0};
-        double we = 0.0;
-        uint32_t shift = 0;
-        if (i < hi_i) {
-          e = seg[i];
-          we = wseg[i];
-          uint32_t lo = 0, hi = c;  // new entries below e.nbr
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (static_cast<uint32_t>(s_key[mid] >> 32) < e.nbr) lo = mid + 1;
-            else hi = mid;
+      // Old entries move right by the number of new entries below them, in
+      // chunks from the right end (every thread reads its kMergePer entries
+      // before any writes); entries below the first new one stay put.
+      const uint32_t stay = s_pos[0];  // new entry of least id lands here
+      for (uint32_t hi_i = cur; hi_i > stay;) {
+        const uint32_t span = kBlock * kMergePer;
+        const uint32_t lo_i = hi_i - stay > span ? hi_i - span : stay;
+        Ent e[kMergePer];
+        double we[kMergePer];
+        uint32_t shift[kMergePer];
+#pragma unroll
+        for (uint32_t m = 0; m < kMergePer; ++m) {
+          const uint32_t i = lo_i + m * kBlock + threadIdx.x;
+          shift[m] = 0;
+          if (i < hi_i) {
+            e[m] = seg[i];
+            we[m] = wseg[i];
           }
-          shift = lo;
+        }
+#pragma unroll
+        for (uint32_t m = 0; m < kMergePer; ++m) {
+          const uint32_t i = lo_i + m * kBlock + threadIdx.x;
+          if (i < hi_i) {
+            uint32_t lo = 0, hi = c;  // new entries below e.nbr
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (static_cast<uint32_t>(s_key[mid] >> 32) < e[m].nbr) lo = mid + 1;
+              else hi = mid;
+            }
+            shift[m] = lo;
+          }
         }
         __syncthreads();
-        if (i < hi_i && shift) {
-          seg[i + shift] = e;
-          wseg[i + shift] = we;
+#pragma unroll
+        for (uint32_t m = 0; m < kMergePer; ++m) {
+          const uint32_t i = lo_i + m * kBlock + threadIdx.x;
+          if (i < hi_i && shift[m]) {
+            seg[i + shift[m]] = e[m];
+            wseg[i + shift[m]] = we[m];
+          }
         }
         __syncthreads();
         hi_i = lo_i;
