@@ -45,6 +45,16 @@ TUNE_CANDIDATES = 10  # schedules the autotuner tries, one batch each
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
 
 
+def walk_kernels(form: str, tuning) -> str:
+    """The walk kernels a run of this form launched (the batched form's kept
+    schedule decides which)."""
+    if form != "batched" or not tuning:
+        return KERNELS[form]
+    if tuning["tail_lanes"] > 0:
+        return "k_walk_head+k_walk_tail"
+    return "k_walk_range" if tuning["updates_per_wave"] > 0 else "k_walk_queue"
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("dyg_kernels.hip", "dyg_internal.h", "dyg_philox.h"):
@@ -320,7 +330,7 @@ def main_batches(args):
         "forms": form_summary(runs, updates, args.steps),
         "roofline": {
             "bound": "hbm",
-            "kernel": KERNELS[head],
+            "kernel": walk_kernels(head, timed.get("tuning")),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
