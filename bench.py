@@ -31,6 +31,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -55,11 +56,25 @@ def walk_kernels(form: str, tuning) -> str:
     return "k_walk_range" if tuning["updates_per_wave"] > 0 else "k_walk_queue"
 
 
-def kernel_source_hash() -> str:
+def _code_only(text: str) -> str:
+    """C++ source without comments and with whitespace collapsed (the kernel
+    sources hold no string literals), so that comment edits keep the hash."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(read=None) -> str:
+    """Hash of the walk kernels' code (comments ignored): counter runs are
+    reported only while it is unchanged."""
     h = hashlib.sha256()
     for f in ("dyg_kernels.hip", "dyg_internal.h", "dyg_philox.h"):
-        with open(os.path.join(ROOT, "paper_2505_02741_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_2505_02741_amd", "csrc", f)) as fh:
+                text = fh.read()
+        else:
+            text = read(f)
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -7,12 +7,15 @@
 //             kept in ctl->err_key and every later kernel becomes a no-op
 //   phase 1   deleted edges become tombstones in G and, if present, in H
 //             (Sec. III-C: an edge outside H leaves H unchanged)
-//   walks     one wavefront per update, one lane per walker: weight-biased
-//             non-backtracking walks (Sec. III-B) on H for insertions and on
-//             G for deletions (Sec. III-C); ballot for "some walker reached
-//             q", wavefront argmin for the least resistance (Eq. 12); a
-//             deletion replays its winner to emit the path edges missing from
-//             H, or the fallback edges when nobody hit
+//   walks     one wavefront per update, one lane per walker, lanes stepping
+//             in lockstep: weight-biased non-backtracking walks (Sec. III-B)
+//             on H for insertions and on G for deletions (Sec. III-C); ballot
+//             for "some walker reached q", wavefront argmin for the least
+//             resistance (Eq. 12); a deletion replays its winner to emit the
+//             path edges missing from H, or the fallback edges when nobody hit
+//             (the batched form splits this step: walker counts and offsets,
+//             a walk schedule — head/tail, range or work queue — and a
+//             per-update reduction that takes the decisions)
 //   phase 4   G += insertions, H += accepted + recovered edges: revive
 //             tombstones, append into per-node slack, relocate a segment that
 //             overflows, then merge the appended tail into sorted order
@@ -1158,7 +1161,8 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
 }
 
 // Plain form: one wavefront per update, one lane per walker (more walkers
-// than lanes run in successive rounds of 64).
+// than lanes run in successive rounds of 64), walks and decision in one
+// kernel, so one update's decision overlaps other updates' walks.
 template <bool kHubs, bool kCoop>
 __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv) {
   __shared__ uint4 stage[kCoop ? kWalkBlock / kWave : 1][kCoop ? kStageWords : 1];
