@@ -564,7 +564,7 @@ __device__ __forceinline__ unsigned long long scale_random(unsigned long long r,
 // One step of a walker: weight-biased choice among the neighbours other than
 // the previous vertex; stop on the distortion threshold, on reaching q, at a
 // dead end or after L steps (Sec. III-B).  Returns false once the walker has
-// stopped (then S holds its final state, R complete).  The whole 64-byte row
+// stopped (then S holds its final state; finish_walk completes R).  The whole 64-byte row
 // is loaded at once: for a vertex with at most kInline neighbours it is the
 // only dependent access of the step.  Without a threshold nothing decides on
 // R before the walk ends, so the 1/w of the edge taken is loaded with the next
@@ -776,12 +776,19 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     S.rpend = pick_r;
   }
   if (S.x == P.q) {
+    // the last 1/w stays pending: finish_walk adds it once the walker has
+    // stopped, so the wavefront does not wait for that load inside a step
     S.hit = true;
-    S.R = S.R + *S.rpend;
-    S.rpend = &kZeroR;
     return false;
   }
   return true;
+}
+
+// Complete R of a walker that has stopped: add the pending 1/w (R is final
+// after this; kZeroR when nothing is pending).
+__device__ __forceinline__ void finish_walk(WState& S) {
+  S.R = S.R + *S.rpend;
+  S.rpend = &kZeroR;
 }
 
 template <bool kHubs, class Sink>
@@ -804,6 +811,7 @@ __device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, S
   walker_start(S, P.p);
   while (walk_step<kHubs>(P, walker, S, sink)) {
   }
+  finish_walk(S);
   return Walk{S.steps, S.x, S.R, S.hit, S.bytes};
 }
 
@@ -903,6 +911,7 @@ __device__ __forceinline__ bool walk_lockstep(const WalkParams& P, uint32_t walk
     at_pool = need && q0.x != kInlineOff;
     if (alive) alive = walk_step_row<kHubs>(P, S, none, t, rprev, rnd, q0, q1, q2, q3);
   }
+  if (!alive) finish_walk(S);  // a walker handed on keeps its pending 1/w
   return alive;
 }
 
@@ -1395,6 +1404,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
     // (2) one step of every running walker
     NoSink none;
     if (active && !walk_step<kHubs>(P, walker, S, none)) {
+      finish_walk(S);
       wres[item] = WalkOut{S.x, static_cast<uint16_t>(S.steps), static_cast<uint8_t>(S.hit), 0,
                            static_cast<uint32_t>(S.bytes), 0u, S.R};
       active = false;
@@ -1532,6 +1542,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
     // (2) one step of every running walker
     NoSink none;
     if (active && !walk_step<kHubs>(P, walker, S, none)) {
+      finish_walk(S);
       a.wres[item] = WalkOut{S.x, static_cast<uint16_t>(S.steps), static_cast<uint8_t>(S.hit), 0,
                              S.bytes, 0u, S.R};
       active = false;
@@ -1682,6 +1693,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
     }
     NoSink none;
     if (active && !walk_step<kHubs>(P, walker, S, none)) {
+      finish_walk(S);
       a.wres[out] = WalkOut{S.x, static_cast<uint16_t>(S.steps), static_cast<uint8_t>(S.hit), 0,
                             S.bytes, 0u, S.R};
       active = false;
