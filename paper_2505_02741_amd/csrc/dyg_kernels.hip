@@ -1932,16 +1932,17 @@ __global__ void k_pool_check(const BatchArgs* const* __restrict__ argv, uint32_t
   if (a.ctl->pool_top[which] + a.ctl->need[which] > pool_cap) a.ctl->nomem[which] = 1;
 }
 
-__global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+__device__ __forceinline__ void rows_relocate_narrow(const BatchArgs* const* __restrict__ argv,
+                                                     uint32_t which0, uint32_t bx) {
   const uint32_t which = which0 + blockIdx.z;
   const P4 a = load_p4(argv, blockIdx.y, which);
   const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t t = bx * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
   const uint32_t need = a.touched_need[t];
   if (need == 0) return;
-  if (a.touched_k[t] & kWideRelocate) return;  // moved by k_rows_relocate_wide
+  if (a.touched_k[t] & kWideRelocate) return;  // moved by rows_relocate_wide
   const uint32_t r = a.touched_rows[t];
   const RowHdr row = row_hdr(X, r);
   const Seg src = seg_of(X, r, row.off);
@@ -1960,14 +1961,15 @@ __global__ void k_rows_relocate(const BatchArgs* const* __restrict__ argv, uint3
 
 // Relocation of long segments: one workgroup per segment, tombstones dropped
 // through a block-wide scan of the live flags.
-__global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+__device__ __forceinline__ void rows_relocate_wide(const BatchArgs* const* __restrict__ argv,
+                                                   uint32_t which0, uint32_t bx, uint32_t nbx) {
   const uint32_t which = which0 + blockIdx.z;
   const P4 a = load_p4(argv, blockIdx.y, which);
   const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ uint32_t s_off;
   const uint32_t count = a.ctl->wide[which];
-  for (uint32_t wi = blockIdx.x; wi < count; wi += gridDim.x) {
+  for (uint32_t wi = bx; wi < count; wi += nbx) {
     const uint32_t t = a.wide_rows[wi];
     const uint32_t need = a.touched_need[t];
     if (need == 0 || !(a.touched_k[t] & kWideRelocate)) continue;  // block-uniform
@@ -2001,6 +2003,15 @@ __global__ __launch_bounds__(kBlock) void k_rows_relocate_wide(const BatchArgs* 
   }
 }
 
+// Relocations of the touched rows that need more room: the first
+// narrow_blocks workgroups move short rows (a thread per row), the others
+// long ones (a workgroup per row); the two sets of rows are disjoint.
+__global__ __launch_bounds__(kBlock) void k_rows_relocate(const BatchArgs* const* __restrict__ argv,
+                                                          uint32_t which0, uint32_t narrow_blocks) {
+  if (blockIdx.x < narrow_blocks) rows_relocate_narrow(argv, which0, blockIdx.x);
+  else rows_relocate_wide(argv, which0, blockIdx.x - narrow_blocks, gridDim.x - narrow_blocks);
+}
+
 __global__ void k_add_place(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
   const uint32_t which = which0 + blockIdx.z;
   const P4 a = load_p4(argv, blockIdx.y, which);
@@ -2018,15 +2029,16 @@ __global__ void k_add_place(const BatchArgs* const* __restrict__ argv, uint32_t 
 
 // Merge the k appended entries (unsorted tail) into the sorted segment; one
 // thread per short segment (insertion of each new entry).
-__global__ void k_rows_merge(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+__device__ __forceinline__ void rows_merge_narrow(const BatchArgs* const* __restrict__ argv,
+                                                  uint32_t which0, uint32_t bx) {
   const uint32_t which = which0 + blockIdx.z;
   const P4 a = load_p4(argv, blockIdx.y, which);
   const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t t = bx * blockDim.x + threadIdx.x;
   if (t >= a.ctl->touched[which]) return;
   const uint32_t packed = a.touched_k[t];
-  if (packed & kWideMerge) return;  // merged by k_rows_merge_wide
+  if (packed & kWideMerge) return;  // merged by rows_merge_wide
   const uint32_t r = a.touched_rows[t];
   const uint32_t k = packed & kCountMask;
   const RowHdr row = row_hdr(X, r);
@@ -2058,7 +2070,8 @@ constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 K
 // overwritten before it is read.
 constexpr uint32_t kMergePer = 8;  // old entries per thread and chunk of a wide merge
 
-__global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+__device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restrict__ argv,
+                                                uint32_t which0, uint32_t bx, uint32_t nbx) {
   const uint32_t which = which0 + blockIdx.z;
   const P4 a = load_p4(argv, blockIdx.y, which);
   const DevGraph& X = a.X;
@@ -2068,7 +2081,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* con
   __shared__ double s_w[kTailChunk];
   __shared__ uint32_t s_pos[kTailChunk];
   const uint32_t count = a.ctl->wide[which];
-  for (uint32_t wi = blockIdx.x; wi < count; wi += gridDim.x) {
+  for (uint32_t wi = bx; wi < count; wi += nbx) {
     const uint32_t t = a.wide_rows[wi];
     const uint32_t packed = a.touched_k[t];
     if (!(packed & kWideMerge)) continue;  // block-uniform
@@ -2126,37 +2139,39 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* con
       for (uint32_t hi_i = cur; hi_i > stay;) {
         const uint32_t span = kBlock * kMergePer;
         const uint32_t lo_i = hi_i - stay > span ? hi_i - span : stay;
-        Ent e[kMergePer];
-        double we[kMergePer];
-        uint32_t shift[kMergePer];
+        // fields in separate arrays (registers; an array of Ent written
+        // under a condition would go to scratch)
+        uint32_t en[kMergePer], eq[kMergePer], shift[kMergePer];
+        double er[kMergePer], we[kMergePer];
 #pragma unroll
         for (uint32_t m = 0; m < kMergePer; ++m) {
           const uint32_t i = lo_i + m * kBlock + threadIdx.x;
+          const uint32_t ii = i < hi_i ? i : lo_i;  // in range either way
+          const Ent x = seg[ii];
+          en[m] = x.nbr;
+          eq[m] = x.qw;
+          er[m] = x.rinv;
+          we[m] = wseg[ii];
           shift[m] = 0;
-          if (i < hi_i) {
-            e[m] = seg[i];
-            we[m] = wseg[i];
-          }
         }
 #pragma unroll
         for (uint32_t m = 0; m < kMergePer; ++m) {
           const uint32_t i = lo_i + m * kBlock + threadIdx.x;
-          if (i < hi_i) {
-            uint32_t lo = 0, hi = c;  // new entries below e.nbr
-            while (lo < hi) {
-              const uint32_t mid = (lo + hi) >> 1;
-              if (static_cast<uint32_t>(s_key[mid] >> 32) < e[m].nbr) lo = mid + 1;
-              else hi = mid;
-            }
-            shift[m] = lo;
-          }
+          // new entries below e.nbr: a fixed-length search over the P sorted
+          // keys (padding keys are ~0), so that the arrays stay in registers
+          uint32_t below = 0;
+#pragma unroll
+          for (uint32_t w = kTailChunk; w >= 1; w >>= 1)  // counts up to P = kTailChunk
+            if (below + w <= P && static_cast<uint32_t>(s_key[below + w - 1] >> 32) < en[m])
+              below += w;
+          if (i < hi_i) shift[m] = below;
         }
         __syncthreads();
 #pragma unroll
         for (uint32_t m = 0; m < kMergePer; ++m) {
           const uint32_t i = lo_i + m * kBlock + threadIdx.x;
           if (i < hi_i && shift[m]) {
-            seg[i + shift[m]] = e[m];
+            seg[i + shift[m]] = Ent{en[m], eq[m], er[m]};
             wseg[i + shift[m]] = we[m];
           }
         }
@@ -2180,6 +2195,15 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge_wide(const BatchArgs* con
     }
     __syncthreads();
   }
+}
+
+// Merges of the appended tails into sorted order: the first narrow_blocks
+// workgroups take short rows (a thread per row), the others long ones (a
+// workgroup per row); the two sets of rows are disjoint.
+__global__ __launch_bounds__(kBlock) void k_rows_merge(const BatchArgs* const* __restrict__ argv,
+                                                       uint32_t which0, uint32_t narrow_blocks) {
+  if (blockIdx.x < narrow_blocks) rows_merge_narrow(argv, which0, blockIdx.x);
+  else rows_merge_wide(argv, which0, blockIdx.x - narrow_blocks, gridDim.x - narrow_blocks);
 }
 
 // After a pool shortfall: undo the per-row counters so phase 4 can run again
@@ -2325,15 +2349,13 @@ void phase4_sequence(const Launch& L, uint32_t which0, uint32_t nw, hipStream_t 
   }
   if (cap == 0) return;
   const dim3 g(static_cast<uint32_t>((cap + kBlock - 1) / kBlock), L.F, nw);
-  const dim3 wide(kWideBlocks, L.F, nw);
   k_add_prepare<<<g, kBlock, 0, st>>>(L.argv, which0);
   k_rows_plan<<<g, kBlock, 0, st>>>(L.argv, which0);
   k_pool_check<<<dim3(1, L.F, nw), 64, 0, st>>>(L.argv, which0);
-  k_rows_relocate<<<g, kBlock, 0, st>>>(L.argv, which0);
-  k_rows_relocate_wide<<<wide, kBlock, 0, st>>>(L.argv, which0);
+  const dim3 both(g.x + kWideBlocks, L.F, nw);  // short rows, then long rows
+  k_rows_relocate<<<both, kBlock, 0, st>>>(L.argv, which0, g.x);
   k_add_place<<<g, kBlock, 0, st>>>(L.argv, which0);
-  k_rows_merge<<<g, kBlock, 0, st>>>(L.argv, which0);
-  k_rows_merge_wide<<<wide, kBlock, 0, st>>>(L.argv, which0);
+  k_rows_merge<<<both, kBlock, 0, st>>>(L.argv, which0, g.x);
   launch_hub_prefix(L, which0, nw, 1, st);
 }
 
