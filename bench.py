@@ -138,7 +138,9 @@ def traffic_from_counters(fetch_csv, write_csv, kernel, calib_bytes, workload, f
     """Per-launch HBM bytes of `kernel` from two rocprofv3 --pmc runs of the
     same bench command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
     scaled so that the copy kernel of calib_bytes (the --calibrate-copy-mib
-    run) reads and writes exactly calib_bytes; written to the traffic file."""
+    run) reads and writes exactly calib_bytes (that copy is told from the
+    workload's small copies by size: its counters read at least a quarter of
+    calib_bytes); written to the traffic file."""
 
     names = kernel.split("+")
 
@@ -152,7 +154,7 @@ def traffic_from_counters(fetch_csv, write_csv, kernel, calib_bytes, workload, f
                 hit = [k for k in names if k + "<" in r["Kernel_Name"] or k + "(" in r["Kernel_Name"]]
                 if hit:
                     vals[hit[0]].append(v)
-                elif "copyBuffer" in r["Kernel_Name"] and v > 0.5 * calib_bytes:
+                elif "copyBuffer" in r["Kernel_Name"] and v > 0.25 * calib_bytes:
                     copy.append(v)
         return vals, copy
 
