@@ -42,10 +42,12 @@ def make_pair(wl, *, K=None, dead_end=0, slack=0.5, Q=24, s=None, L=None, w_ref=
 def close_R(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
-    both_inf = np.isinf(a) & np.isinf(b)
-    diff = np.abs(a - b)
-    tol = R_RTOL * np.maximum(np.abs(a), np.abs(b))
-    return np.all(both_inf | (diff <= tol))
+    # equal infinities (no hit) match; anything else within the relative tolerance
+    same_inf = np.isinf(a) & np.isinf(b) & (np.sign(a) == np.sign(b))
+    fin = ~same_inf
+    diff = np.abs(a[fin] - b[fin])
+    tol = R_RTOL * np.maximum(np.abs(a[fin]), np.abs(b[fin]))
+    return bool(np.all(diff <= tol))
 
 
 def compare_batch(o, d, b, record=True, tag=""):
