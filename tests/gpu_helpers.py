@@ -42,8 +42,11 @@ def make_pair(wl, *, K=None, dead_end=0, slack=0.5, Q=24, s=None, L=None, w_ref=
 def close_R(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
-    # equal infinities (no hit) match; anything else within the relative tolerance
+    # equal infinities (no hit) match; finite values within the relative
+    # tolerance; anything else (finite against infinite, NaN) does not
     same_inf = np.isinf(a) & np.isinf(b) & (np.sign(a) == np.sign(b))
+    if not np.all(same_inf | (np.isfinite(a) & np.isfinite(b))):
+        return False
     fin = ~same_inf
     diff = np.abs(a[fin] - b[fin])
     tol = R_RTOL * np.maximum(np.abs(a[fin]), np.abs(b[fin]))
