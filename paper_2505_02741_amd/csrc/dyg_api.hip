@@ -569,6 +569,7 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
   if (!rc) {
     BatchCtl init{};
     init.err_key = ~0ull;
+    for (const Ent& x : le) init.heavy |= x.qw >= dyg::kHeavyQw ? 1u : 0u;  // H's weights are G's
     init.pool_top[0] = A.ent.size();
     init.pool_top[1] = B.ent.size();
     e = hipMemcpyAsync(c->ctl, &init, sizeof(init), hipMemcpyHostToDevice, c->stream);
@@ -1258,6 +1259,9 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
       const bool inl = r.off == kInlineOff;
       if (r.len > r.cap) return fail("len exceeds cap", g, u, r.len);
       if (inl && r.cap != kInline) return fail("inline row capacity", g, u, r.cap);
+      if (!ctl.heavy)  // the walks sum in 32 bits while the flag is clear
+        for (uint32_t i = 0; i < r.len; ++i)
+          if (I.get(u, i).qw >= dyg::kHeavyQw) return fail("heavy weight, flag clear", g, u, i);
       if (inl)  // the walk's inline selection relies on weight 0 past len
         for (uint32_t i = r.len; i < kInline; ++i)
           if (I.rows[u].inl[i].qw != 0u) return fail("inline slot past len in use", g, u, i);

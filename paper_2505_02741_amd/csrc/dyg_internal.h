@@ -59,6 +59,9 @@ constexpr uint32_t kHub = 64;
 constexpr uint32_t kMaxWalkers = 1024;
 constexpr uint32_t kMaxSteps = 1024;
 constexpr uint32_t kMaxUpw = 8;  // updates per wavefront of the range walk
+// While every quantised weight stays below this, the six-term running sums
+// of an inline row fit 32 bits; the walks then use 32-bit sums.
+constexpr uint32_t kHeavyQw = 1u << 29;
 
 
 struct DevGraph {
@@ -154,6 +157,7 @@ struct BatchCtl {
   // cumulative over the context's life (never reset by a batch)
   unsigned long long steps_total;      // walker steps taken
   unsigned long long alg_bytes_total;  // algorithmic gathered bytes of those steps
+  uint32_t heavy;  // some quantised weight of G or H is >= kHeavyQw (set, never cleared)
 };
 
 // Slot of the validation / dedup hash table.

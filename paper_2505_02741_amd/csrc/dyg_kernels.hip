@@ -353,8 +353,11 @@ __global__ void k_validate_b(const BatchArgs* const* __restrict__ argv) {
     else if (hash_min_of(a.hash, a.hash_mask, edge_key(u, v)) < i) code = E_DUPLICATE;
     if (code) report(a.ctl, 0, i, code);
     else {
-      a.ins_qw[i] = quantize(w, a.w_ref, a.Q);
+      const uint32_t qw = quantize(w, a.w_ref, a.Q);
+      a.ins_qw[i] = qw;
       a.ins_rinv[i] = 1.0 / w;
+      // later walks may meet this weight (a failed batch only costs speed)
+      if (qw >= kHeavyQw) a.ctl->heavy = 1u;
     }
   } else {
     const uint32_t j = i - a.n_ins;
@@ -496,6 +499,7 @@ struct WalkParams {
   uint32_t L;
   uint32_t key0, key1, uid_lo, uid_hi;
   bool bounce;
+  bool heavy;  // a weight may reach kHeavyQw: 64-bit running sums
 };
 
 // Emits nothing; the replay variant below passes an edge sink.
@@ -608,12 +612,12 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     // Running sums r0..r4 and tot; the pick is the first index whose running
     // sum exceeds the target, i.e. the number of running sums r0..r4 at or
     // below it (they never decrease, and a zero weight never crosses the
-    // target).  With every weight below 2^29 the six-term sums fit 32 bits
-    // exactly; a wavefront with a heavier row takes the 64-bit sums.
-    const bool heavy = ((q1.y | q1.w | q2.y | q2.w | q3.y | q3.w) >> 29) != 0u;
+    // target).  With every weight below kHeavyQw = 2^29 the six-term sums
+    // fit 32 bits exactly; once the context holds a heavier weight (a
+    // context-wide flag, uniform) the walks take the 64-bit sums.
     bool b1, b2, b3, b4, b5;  // pick index >= 1 .. >= 5
     bool leaf;
-    if (__ballot(heavy) == 0ull) {  // uniform: the flags need no merging
+    if (!P.heavy) {
       const uint32_t r0 = c0, r1 = r0 + c1, r2 = r1 + c2, r3 = r2 + c3, r4 = r3 + c4,
                      tot = r4 + c5;
       const uint32_t tg = static_cast<uint32_t>(scale_random(rnd, tot));
@@ -1013,6 +1017,7 @@ __device__ __forceinline__ UpdateView view_update(const BatchArgs& a, const DevG
   P.uid_lo = static_cast<uint32_t>(uid);
   P.uid_hi = static_cast<uint32_t>(uid >> 32);
   P.bounce = a.bounce != 0;
+  P.heavy = a.ctl->heavy != 0u;
   P.rows = v.is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
   P.ent = v.is_ins ? H.ent : G.ent;
   P.pfx = v.is_ins ? H.pfx : G.pfx;
@@ -1364,6 +1369,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   P.key0 = static_cast<uint32_t>(a0.seed);
   P.key1 = static_cast<uint32_t>(a0.seed >> 32);
   P.bounce = a0.bounce != 0;
+  P.heavy = a0.ctl->heavy != 0u;
   P.rows = a0.g[1].rows;
   P.ent = a0.g[1].ent;
   P.pfx = a0.g[1].pfx;
@@ -1424,6 +1430,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         P.uid_lo = static_cast<uint32_t>(uid);
         P.uid_hi = static_cast<uint32_t>(uid >> 32);
         P.bounce = A->bounce != 0;
+        P.heavy = load_gptr(&A->ctl)->heavy != 0u;
         const int gw = is_ins ? 1 : 0;  // H_mid for insertions, G_mid for deletions
         P.rows = load_gptr(&A->g[gw].rows);
         P.ent = load_gptr(&A->g[gw].ent);
@@ -1487,6 +1494,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
   P.key0 = static_cast<uint32_t>(a.seed);
   P.key1 = static_cast<uint32_t>(a.seed >> 32);
   P.bounce = a.bounce != 0;
+  P.heavy = a.ctl->heavy != 0u;
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
   P.pfx = a.g[1].pfx;
@@ -1629,6 +1637,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
   P.key0 = static_cast<uint32_t>(a.seed);
   P.key1 = static_cast<uint32_t>(a.seed >> 32);
   P.bounce = a.bounce != 0;
+  P.heavy = a.ctl->heavy != 0u;
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
   P.pfx = a.g[1].pfx;
