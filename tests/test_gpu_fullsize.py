@@ -1,6 +1,6 @@
 """Full-size parity: the workloads at their real sizes, in the launch
-configuration the benchmark times (batched form, device-resident batches),
-against the CPU oracle on every batch.  Per-update results and the final edge
+configurations the benchmark times (plain and batched forms, device-resident
+batches), against the CPU oracle on every batch.  Per-update results and the final edge
 sets are compared exactly; per-walker records on the first batch."""
 from __future__ import annotations
 
@@ -16,6 +16,7 @@ from gpu_helpers import close_R, compare_state, make_pair, say
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 BATCHED = 4
+FORMS = pytest.mark.parametrize("flags", [0, BATCHED], ids=["plain", "batched"])
 
 
 def _device_batch(D, torch, d, b, dev):
@@ -33,7 +34,7 @@ def _device_batch(D, torch, d, b, dev):
     return res.cpu().numpy().view(D.UPDATE_RESULT_DTYPE)
 
 
-def _run_full(name, n_batches=None, walker_batches=(0,), **over):
+def _run_full(name, flags, n_batches=None, walker_batches=(0,), **over):
     import torch
 
     from paper_2505_02741_amd import dygrass as D
@@ -42,7 +43,7 @@ def _run_full(name, n_batches=None, walker_batches=(0,), **over):
     t0 = time.time()
     wl = W.make_workload(name, n_batches=n_batches, **over)
     say(f"{name}: n={wl.G.n} m={wl.G.m} H0={int(wl.h_mask.sum())} gen {time.time() - t0:.1f}s")
-    o, d = make_pair(wl, flags=BATCHED)
+    o, d = make_pair(wl, flags=flags)
     try:
         for t, b in enumerate(wl.batches):
             t1 = time.time()
@@ -72,17 +73,20 @@ def _run_full(name, n_batches=None, walker_batches=(0,), **over):
         o.close()
 
 
-def test_grid1024_all_batches():
+@FORMS
+def test_grid1024_all_batches(flags):
     """1024x1024 lognormal grid, 10 x 20,000 insertions, s=64, L=32."""
-    _run_full("grid1024")
+    _run_full("grid1024", flags)
 
 
-def test_mesh128_all_batches():
+@FORMS
+def test_mesh128_all_batches(flags):
     """128^3 FEM mesh, 20 x (10,000 insertions + 10,000 deletions), s=64, L=24."""
-    _run_full("mesh128")
+    _run_full("mesh128", flags)
 
 
-def test_rmat_scale18_uneven_batches():
+@FORMS
+def test_rmat_scale18_uneven_batches(flags):
     """R-MAT scale 18 (edge factor 16), 12 uneven batches (100..20,000
     updates, 70/30), per-update s in 16..128 and L in 8..32."""
-    _run_full("rmat22", scale=18, batches=12, size_hi=20_000)
+    _run_full("rmat22", flags, scale=18, batches=12, size_hi=20_000)
