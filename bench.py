@@ -541,8 +541,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
-              "supported (the multi-GPU sharding is a design, not a run).", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU only; --gpus {args.gpus} is not "
+              "supported (sharding over several GPUs is designed, not implemented).",
+              file=sys.stderr)
         sys.exit(2)
     if args.autotune and args.warmup < TUNE_CANDIDATES:
         args.warmup = TUNE_CANDIDATES
