@@ -60,3 +60,16 @@ def test_product_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "dyg_oracle" not in text, f
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the binding refuses to import: there is no
+    fallback path."""
+    import subprocess
+    import sys
+
+    env = dict(os.environ, DYGRASS_LIB=str(tmp_path / "absent" / "libdygrass.so"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2505_02741_amd.dygrass"], cwd=ROOT,
+                       env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "is not built" in r.stderr
