@@ -21,7 +21,8 @@ fused rounds, p50/p99 latency) against the plain form on the same requests.
 
 Prints one JSON line.  The walk kernel's roofline figure uses its algorithmic
 gathered bytes (counted per step from the live degree of the vertex left) over
-its duration measured with HIP events on its launch stream.
+its duration measured with HIP events on its launch stream (two per batch,
+around the walk kernel only: DYG_FLAG_TIMING_WALK).
 """
 from __future__ import annotations
 
@@ -206,7 +207,7 @@ def run_stream(D, torch, wl, rp, col, w, dev_batches, flags, warmup, tuning=None
     """Apply every batch in order on a fresh context (buffers reserved for the
     largest batch); time all but the first `warmup` batches."""
     ctx = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
-                    L=wl.L, flags=D.FLAG_TIMING | flags)
+                    L=wl.L, flags=D.FLAG_TIMING_WALK | flags)
     reserve_for(D, ctx, wl.batches)
     if tuning:
         D.dyg_set_tuning(ctx.ctx, *tuning)

@@ -81,6 +81,10 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
                                   events); the schedule with the least walk time
                                   per walker step is then kept (dyg_get_tuning
                                   reports it)                                     */
+#define DYG_FLAG_TIMING_WALK 32u /* time the walk kernel alone: two HIP events per
+                                  batch around it (dyg_stats walk_ms_*), none
+                                  around the batch (batch_ms_last stays 0), so
+                                  that timing disturbs the stream least          */
 
 #define DYG_MAX_WALKERS 1024 /* per update */
 #define DYG_MAX_STEPS 1024   /* per walker */
@@ -138,8 +142,9 @@ typedef struct {
    * 32 + 12 ceil(log2 d) above) */
   uint64_t walk_steps;
   uint64_t walk_alg_bytes;
-  /* with DYG_FLAG_TIMING: walk-kernel launches timed, their total and last
-   * duration, and the device time of the last batch (ms) */
+  /* with DYG_FLAG_TIMING or DYG_FLAG_TIMING_WALK: walk-kernel launches timed,
+   * their total and last duration (ms); with DYG_FLAG_TIMING also the device
+   * time of the last batch (ms) */
   uint64_t walk_launches;
   double walk_ms_total;
   double walk_ms_last;

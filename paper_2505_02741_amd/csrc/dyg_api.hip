@@ -151,7 +151,7 @@ struct dyg_ctx {
   int pending_status = DYG_OK;
   bool async_inflight = false;
   uint64_t async_nu = 0;
-  // DYG_FLAG_TIMING
+  // DYG_FLAG_TIMING, DYG_FLAG_TIMING_WALK, DYG_FLAG_AUTOTUNE
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // batch begin, walk begin/end, batch end
   bool timed_pending = false;
   uint64_t walk_launches = 0;
@@ -496,7 +496,7 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
       c->cus = static_cast<uint32_t>(cus);
   }
   if (params->flags & DYG_FLAG_AUTOTUNE) c->tune_next = 0;
-  if (params->flags & (DYG_FLAG_TIMING | DYG_FLAG_AUTOTUNE))
+  if (params->flags & (DYG_FLAG_TIMING | DYG_FLAG_TIMING_WALK | DYG_FLAG_AUTOTUNE))
     for (hipEvent_t& ev : c->ev)
       if ((e = hipEventCreate(&ev)) != hipSuccess) {
         dyg_destroy(c);
@@ -777,8 +777,10 @@ bool tuning_now(const dyg_ctx* c);
 
 int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a) {
   const bool timed = c->ev[0] != nullptr;
+  // the batch itself is bracketed only under DYG_FLAG_TIMING
+  const bool timed_batch = timed && (c->params.flags & DYG_FLAG_TIMING);
   hipError_t e = hipSuccess;
-  if (timed) (void)hipEventRecord(c->ev[0], c->stream);
+  if (timed_batch) (void)hipEventRecord(c->ev[0], c->stream);
   e = hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return fail_hip(e);
   c->last_graph = (c->params.flags & DYG_FLAG_GRAPH) && !tuning_now(c);
@@ -795,7 +797,7 @@ int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a) {
   } else {
     launch_sequence(c, a, timed);
   }
-  if (timed) (void)hipEventRecord(c->ev[3], c->stream);
+  if (timed_batch) (void)hipEventRecord(c->ev[3], c->stream);
   c->timed_pending = timed && (a.n_ins + a.n_del) > 0;
   // the batch's control block comes back with the batch: one wait at sync
   e = hipMemcpyAsync(c->hctl, c->ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, c->stream);
@@ -810,8 +812,10 @@ bool collect_timing(dyg_ctx* c) {
   if (!c->timed_pending) return false;
   c->timed_pending = false;
   float walk = 0.f, batch = 0.f;
-  if (hipEventElapsedTime(&batch, c->ev[0], c->ev[3]) != hipSuccess) return false;
-  c->batch_ms_last = batch;
+  if (c->params.flags & DYG_FLAG_TIMING) {
+    if (hipEventElapsedTime(&batch, c->ev[0], c->ev[3]) != hipSuccess) return false;
+    c->batch_ms_last = batch;
+  }
   if (c->last_graph) return false;  // the walk kernel was inside a captured graph
   if (hipEventElapsedTime(&walk, c->ev[1], c->ev[2]) != hipSuccess) return false;
   c->walk_launches++;

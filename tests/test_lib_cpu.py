@@ -73,3 +73,14 @@ def test_missing_library_fails_loudly(tmp_path):
                        env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "is not built" in r.stderr
+
+
+def test_flag_values_match_header():
+    from paper_2505_02741_amd import dygrass as D
+
+    text = open(os.path.join(ROOT, "include", "dygrass.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define DYG_FLAG_(\w+) (\d+)u", text)}
+    assert defs == {"LEAN_POOLS": 1, "TIMING": 2, "BATCHED": 4, "GRAPH": 8, "AUTOTUNE": 16,
+                    "TIMING_WALK": 32}
+    for name, v in defs.items():
+        assert getattr(D, "FLAG_" + name) == v, name
