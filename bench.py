@@ -234,7 +234,7 @@ def run_stream(D, torch, wl, rp, col, w, dev_batches, flags, warmup, tuning=None
     st1 = ctx.stats()
     tuning_kept = D.dyg_get_tuning(ctx.ctx)
     ctx.close()
-    r = dict(t_total=t_total, lat=lat, tuning=tuning_kept)
+    r = dict(t_total=t_total, lat=lat, tuning=tuning_kept, h_edges_end=st1["h_edges"])
     for k in ("walk_steps", "walk_alg_bytes", "walk_ms_total", "walk_launches"):
         r[k] = st1[k] - st0[k]
     return r
@@ -359,6 +359,10 @@ def main_batches(args):
         },
         "cpu_baseline": None,
     }
+    # off-tree density of the sparsifier, |E_H| / |V| - 1 (Sec. IV metric),
+    # before the stream and after its last batch (read after the timed region)
+    out["d_H"] = {"initial": int(wl.h_mask.sum()) / wl.G.n - 1.0,
+                  "end": R["h_edges_end"] / wl.G.n - 1.0}
     if "batched" in runs:
         out["batched_schedule"] = runs["batched"]["tuning"]
     if "plain" in runs and "batched" in runs:
