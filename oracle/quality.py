@@ -1,0 +1,104 @@
+"""Sparsifier quality at mid scale (test infrastructure only).
+
+* Off-tree density d_H = |E_H| / |V| - 1, the density measure of the
+  experiments (Sec. IV).
+* Relative condition number kappa(L_G, L_H) = lambda_max / lambda_min of the
+  pencil (L_G, L_H) on the complement of the all-ones vector (Sec. II-A,
+  Eq. 1), for connected graphs of up to ~10^5 vertices: both Laplacians are
+  grounded at one vertex (its row and column removed).  Every class x + c*1
+  holds exactly one vector that is zero at that vertex, and the Rayleigh
+  quotient x^T L_G x / x^T L_H x does not depend on c, so the grounded pencil
+  (SPD on both sides) has the same eigenvalues.  lambda_max comes from ARPACK
+  on (L_G, L_H), lambda_min as 1 / lambda_max of (L_H, L_G).
+* The trend of Tables II and III on a synthetic stream: an insertion stream
+  applied three ways -- H left alone, every inserted edge added to H (no
+  filter), and the update rule of Algorithm 1 through the CPU oracle -- with
+  d_H and kappa after the stream.
+
+Plain scipy sparse linear algebra; shares nothing with the GPU library.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as sla
+
+
+def off_tree_density(n: int, m_h: int) -> float:
+    """d_H = |E_H| / |V| - 1 (Sec. IV)."""
+    return m_h / n - 1.0
+
+
+def grounded_laplacian(n: int, u, v, w, root: int = 0) -> sp.csc_matrix:
+    """L = D - A (Sec. II-A) with row and column `root` removed."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    rows = np.concatenate([u, v, u, v])
+    cols = np.concatenate([v, u, u, v])
+    vals = np.concatenate([-w, -w, w, w])
+    Lm = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    keep = np.flatnonzero(np.arange(n) != root)
+    return Lm[keep][:, keep].tocsc()
+
+
+def _lambda_max(A: sp.csc_matrix, B: sp.csc_matrix) -> float:
+    """Largest eigenvalue of A x = lambda B x, A and B SPD."""
+    lu = sla.splu(B)
+    vals = sla.eigsh(A, k=1, M=B, Minv=sla.LinearOperator(B.shape, matvec=lu.solve),
+                     which="LA", tol=1e-10, return_eigenvectors=False)
+    return float(vals[0])
+
+
+def pencil_extremes(n: int, G, H) -> tuple[float, float]:
+    """(lambda_min, lambda_max) of the pencil (L_G, L_H), G and H given as
+    (u, v, w) edge lists of connected graphs on the same n vertices."""
+    LG = grounded_laplacian(n, *G)
+    LH = grounded_laplacian(n, *H)
+    lam_max = _lambda_max(LG, LH)
+    lam_min = 1.0 / _lambda_max(LH, LG)
+    return lam_min, lam_max
+
+
+def relative_condition_number(n: int, G, H) -> float:
+    lam_min, lam_max = pencil_extremes(n, G, H)
+    return lam_max / lam_min
+
+
+def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None = None):
+    """d_H and kappa(L_G, L_H) before and after an insertion-only stream, for
+    H left alone, H given every insertion, and H updated by the oracle with
+    threshold K (by default kappa of the initial pair, the distortion bound
+    of Eq. 11).  Returns a dict of (d_H, kappa) pairs."""
+    import oracle
+    from paper_2505_02741_amd import workloads as W
+
+    n = wl.G.n
+    G0 = (wl.G.u, wl.G.v, wl.G.w)
+    H0 = (wl.hu, wl.hv, wl.G.w[wl.h_mask])
+    kappa0 = relative_condition_number(n, G0, H0)
+    K = kappa0 if K is None else K
+    iu = np.concatenate([b.iu for b in wl.batches]).astype(np.int64)
+    iv = np.concatenate([b.iv for b in wl.batches]).astype(np.int64)
+    iw = np.concatenate([b.iw for b in wl.batches])
+    if any(b.n_del for b in wl.batches):
+        raise ValueError("stream_trend takes insertion-only streams")
+    G1 = (np.concatenate([G0[0], iu]), np.concatenate([G0[1], iv]), np.concatenate([G0[2], iw]))
+    rp, col, w = W.to_csr(n, *G0)
+    o = oracle.Oracle(n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=K,
+                      s=wl.s if s is None else s, L=wl.L if L is None else L)
+    try:
+        for b in wl.batches:
+            o.apply_batch(b.iu, b.iv, b.iw, b.du, b.dv, s=b.s, L=b.L)
+        Hd = o.query("H")
+    finally:
+        o.close()
+    Ha = (np.concatenate([H0[0], iu]), np.concatenate([H0[1], iv]), np.concatenate([H0[2], iw]))
+    out = {"initial": (off_tree_density(n, H0[0].size), kappa0)}
+    for name, H in (("no_update", H0), ("no_filter", Ha), ("dygrass", Hd)):
+        out[name] = (off_tree_density(n, np.asarray(H[0]).size),
+                     relative_condition_number(n, G1, H))
+    out["K"] = K if math.isfinite(K) else float("inf")
+    return out

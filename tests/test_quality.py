@@ -1,0 +1,84 @@
+"""The mid-scale quality harness (oracle/quality.py): the sparse relative
+condition number pinned to the dense one and to closed forms, and the trend
+of the paper's Tables II and III on a synthetic insertion stream."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2505_02741_amd import workloads as W
+
+
+def test_sparse_kappa_matches_dense():
+    from oracle import quality as Q
+    from oracle import spectral
+
+    for seed, side, extra in ((1, 6, 0.1), (2, 8, 0.3), (3, 9, 0.0)):
+        rng = np.random.default_rng(seed)
+        n, u, v = W.grid2d(side)
+        w = rng.lognormal(0.0, 1.0, u.size)
+        hm = W.max_spanning_forest(n, u, v, w) | (rng.random(u.size) < extra)
+        dense = spectral.relative_condition_number(spectral.laplacian(n, u, v, w),
+                                                   spectral.laplacian(n, u[hm], v[hm], w[hm]))
+        sparse = Q.relative_condition_number(n, (u, v, w), (u[hm], v[hm], w[hm]))
+        assert abs(sparse - dense) <= 1e-8 * dense, (seed, sparse, dense)
+
+
+def test_kappa_closed_forms():
+    from oracle import quality as Q
+
+    # unit cycle against the path left after removing one edge: kappa = m
+    for m in (50, 400):
+        cu = np.arange(m)
+        cv = (cu + 1) % m
+        k = Q.relative_condition_number(m, (cu, cv, np.ones(m)), (cu[:-1], cv[:-1], np.ones(m - 1)))
+        assert abs(k - m) < 1e-6 * m
+    # a graph against itself, and against itself with weights scaled by c:
+    # every generalized eigenvalue is 1 (resp. 1/c)
+    rng = np.random.default_rng(4)
+    n, u, v = W.grid2d(30)
+    w = rng.uniform(0.5, 2.0, u.size)
+    lo, hi = Q.pencil_extremes(n, (u, v, w), (u, v, w))
+    assert abs(lo - 1.0) < 1e-8 and abs(hi - 1.0) < 1e-8
+    lo, hi = Q.pencil_extremes(n, (u, v, w), (u, v, 4.0 * w))
+    assert abs(lo - 0.25) < 1e-8 and abs(hi - 0.25) < 1e-8
+    # a subgraph H of G with a pendant vertex of G kept in H: lambda_min = 1
+    # (Eqs. 9-10), lambda_max >= 1
+    hm = W.max_spanning_forest(n, u, v, w)
+    lu, lv, lw = np.append(u, n), np.append(v, 0), np.append(w, 1.5)
+    lm = np.append(hm, True)
+    lo, hi = Q.pencil_extremes(n + 1, (lu, lv, lw), (lu[lm], lv[lm], lw[lm]))
+    assert abs(lo - 1.0) < 1e-8 and hi > 1.0
+
+
+def test_off_tree_density():
+    from oracle import quality as Q
+
+    assert Q.off_tree_density(100, 99) == pytest.approx(-0.01)  # a spanning tree
+    assert Q.off_tree_density(100, 110) == pytest.approx(0.1)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_stream_trend_of_tables_two_and_three(seed):
+    """Ten insertion batches adding 25% of |V| edges to a 32x32 lognormal grid
+    (the stream shape of Sec. IV): with H left alone kappa grows; adding every
+    edge gives the densest H; the oracle's updates (K = kappa of the initial
+    pair) keep H far sparser than that while kappa stays at or below its
+    initial value."""
+    from oracle import quality as Q
+
+    side = 32
+    wl = W.make_workload("grid1024", seed=seed, side=side, ins=int(0.025 * side * side),
+                         batches=10)
+    r = Q.stream_trend(wl)
+    d0, k0 = r["initial"]
+    assert r["K"] == pytest.approx(k0)
+    d_none, k_none = r["no_update"]
+    d_all, k_all = r["no_filter"]
+    d_dyg, k_dyg = r["dygrass"]
+    assert d_none == pytest.approx(d0) and k_none > k0
+    assert d_all > d_dyg > d0
+    assert k_dyg <= k0 and k_dyg < k_none
+    # H with every edge contains the oracle's H, so lambda_max can only be
+    # lower; lambda_min is 1 for both (a vertex whose edges all lie in H)
+    assert k_all <= k_dyg
