@@ -10,10 +10,15 @@
   quotient x^T L_G x / x^T L_H x does not depend on c, so the grounded pencil
   (SPD on both sides) has the same eigenvalues.  lambda_max comes from ARPACK
   on (L_G, L_H), lambda_min as 1 / lambda_max of (L_H, L_G).
-* The trend of Tables II and III on a synthetic stream: an insertion stream
+* Preconditioned conjugate gradients on L_G x = b with L_H as the
+  preconditioner, stopped once the relative residual ||b - L_G x|| / ||b||
+  falls below 1e-8 (Sec. IV, Table IV): the iteration count follows
+  sqrt(kappa(L_G, L_H)).  Textbook PCG, both Laplacians grounded as above,
+  the preconditioner applied through a sparse LU of grounded L_H.
+* The trend of Tables II, III and IV on a synthetic stream: an insertion stream
   applied three ways -- H left alone, every inserted edge added to H (no
   filter), and the update rule of Algorithm 1 through the CPU oracle -- with
-  d_H and kappa after the stream.
+  d_H, kappa and the PCG iteration count after the stream.
 
 Plain scipy sparse linear algebra; shares nothing with the GPU library.
 """
@@ -67,11 +72,42 @@ def relative_condition_number(n: int, G, H) -> float:
     return lam_max / lam_min
 
 
+def pcg_iterations(n: int, G, H, b=None, rtol: float = 1e-8, max_iter: int = 100_000,
+                   seed: int = 0) -> tuple[int, np.ndarray]:
+    """Iterations of PCG on grounded L_G x = b preconditioned by grounded L_H
+    until ||r|| <= rtol ||b|| (Sec. IV); returns (iterations, x).  b defaults
+    to a seeded standard normal vector."""
+    A = grounded_laplacian(n, *G).tocsr()
+    P = sla.splu(grounded_laplacian(n, *H))
+    if b is None:
+        b = np.random.default_rng(seed).standard_normal(n - 1)
+    x = np.zeros(n - 1)
+    r = b.copy()
+    z = P.solve(r)
+    p = z.copy()
+    rz = r @ z
+    stop = rtol * np.linalg.norm(b)
+    for it in range(1, max_iter + 1):
+        Ap = A @ p
+        alpha = rz / (p @ Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        if np.linalg.norm(r) <= stop:
+            return it, x
+        z = P.solve(r)
+        rz_next = r @ z
+        p = z + (rz_next / rz) * p
+        rz = rz_next
+    raise RuntimeError("PCG did not converge")
+
+
 def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None = None):
-    """d_H and kappa(L_G, L_H) before and after an insertion-only stream, for
-    H left alone, H given every insertion, and H updated by the oracle with
-    threshold K (by default kappa of the initial pair, the distortion bound
-    of Eq. 11).  Returns a dict of (d_H, kappa) pairs."""
+    """d_H, kappa(L_G, L_H) and PCG iterations before and after an
+    insertion-only stream, for H left alone, H given every insertion, and H
+    updated by the oracle with threshold K (by default kappa of the initial
+    pair, the distortion bound of Eq. 11).  Returns a dict of (d_H, kappa,
+    iterations) triples; the initial one is taken against G before the
+    stream, the others against G after it."""
     import oracle
     from paper_2505_02741_amd import workloads as W
 
@@ -96,9 +132,9 @@ def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None
     finally:
         o.close()
     Ha = (np.concatenate([H0[0], iu]), np.concatenate([H0[1], iv]), np.concatenate([H0[2], iw]))
-    out = {"initial": (off_tree_density(n, H0[0].size), kappa0)}
+    out = {"initial": (off_tree_density(n, H0[0].size), kappa0, pcg_iterations(n, G0, H0)[0])}
     for name, H in (("no_update", H0), ("no_filter", Ha), ("dygrass", Hd)):
         out[name] = (off_tree_density(n, np.asarray(H[0]).size),
-                     relative_condition_number(n, G1, H))
+                     relative_condition_number(n, G1, H), pcg_iterations(n, G1, H)[0])
     out["K"] = K if math.isfinite(K) else float("inf")
     return out

@@ -51,6 +51,28 @@ def test_kappa_closed_forms():
     assert abs(lo - 1.0) < 1e-8 and hi > 1.0
 
 
+def test_pcg_solves_and_exact_preconditioner_takes_one_step():
+    import scipy.sparse.linalg as sla
+
+    from oracle import quality as Q
+
+    rng = np.random.default_rng(6)
+    n, u, v = W.grid2d(20)
+    w = rng.lognormal(0.0, 1.0, u.size)
+    hm = W.max_spanning_forest(n, u, v, w) | (rng.random(u.size) < 0.1)
+    b = rng.standard_normal(n - 1)
+    # preconditioned by G itself: one step
+    it, x = Q.pcg_iterations(n, (u, v, w), (u, v, w), b=b)
+    assert it == 1
+    # by a sparsifier: more steps, and x solves the grounded system
+    it, x = Q.pcg_iterations(n, (u, v, w), (u[hm], v[hm], w[hm]), b=b)
+    A = Q.grounded_laplacian(n, u, v, w)
+    assert it > 1
+    assert np.linalg.norm(A @ x - b) <= 1e-8 * np.linalg.norm(b)
+    xd = sla.splu(A).solve(b)
+    assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
+
+
 def test_off_tree_density():
     from oracle import quality as Q
 
@@ -61,22 +83,24 @@ def test_off_tree_density():
 @pytest.mark.parametrize("seed", [1, 2])
 def test_stream_trend_of_tables_two_and_three(seed):
     """Ten insertion batches adding 25% of |V| edges to a 32x32 lognormal grid
-    (the stream shape of Sec. IV): with H left alone kappa grows; adding every
-    edge gives the densest H; the oracle's updates (K = kappa of the initial
-    pair) keep H far sparser than that while kappa stays at or below its
-    initial value."""
+    (the stream shape of Sec. IV): with H left alone kappa and the PCG
+    iteration count grow; adding every edge gives the densest H; the oracle's
+    updates (K = kappa of the initial pair) keep H far sparser than that
+    while kappa stays at or below its initial value and PCG needs fewer
+    iterations than with H left alone (Tables II-IV)."""
     from oracle import quality as Q
 
     side = 32
     wl = W.make_workload("grid1024", seed=seed, side=side, ins=int(0.025 * side * side),
                          batches=10)
     r = Q.stream_trend(wl)
-    d0, k0 = r["initial"]
+    d0, k0, i0 = r["initial"]
     assert r["K"] == pytest.approx(k0)
-    d_none, k_none = r["no_update"]
-    d_all, k_all = r["no_filter"]
-    d_dyg, k_dyg = r["dygrass"]
-    assert d_none == pytest.approx(d0) and k_none > k0
+    d_none, k_none, i_none = r["no_update"]
+    d_all, k_all, i_all = r["no_filter"]
+    d_dyg, k_dyg, i_dyg = r["dygrass"]
+    assert d_none == pytest.approx(d0) and k_none > k0 and i_none > i0
+    assert i_all < i_dyg < i_none
     assert d_all > d_dyg > d0
     assert k_dyg <= k0 and k_dyg < k_none
     # H with every edge contains the oracle's H, so lambda_max can only be
