@@ -80,19 +80,22 @@ def test_off_tree_density():
     assert Q.off_tree_density(100, 110) == pytest.approx(0.1)
 
 
-@pytest.mark.parametrize("seed", [1, 2])
-def test_stream_trend_of_tables_two_and_three(seed):
+@pytest.mark.parametrize("name,seed,over", [
+    ("grid1024", 1, dict(side=32, ins=25, batches=10)),
+    ("grid1024", 2, dict(side=32, ins=25, batches=10)),
+    ("mesh128", 1, dict(side=10, ins=25, dels=0, batches=10)),
+], ids=["grid32-s1", "grid32-s2", "mesh10-s1"])
+def test_stream_trend_of_tables_two_to_four(name, seed, over):
     """Ten insertion batches adding 25% of |V| edges to a 32x32 lognormal grid
-    (the stream shape of Sec. IV): with H left alone kappa and the PCG
+    or a 10^3 FEM-like mesh (the stream shape of Sec. IV): with H left alone
+    kappa and the PCG
     iteration count grow; adding every edge gives the densest H; the oracle's
     updates (K = kappa of the initial pair) keep H far sparser than that
     while kappa stays at or below its initial value and PCG needs fewer
     iterations than with H left alone (Tables II-IV)."""
     from oracle import quality as Q
 
-    side = 32
-    wl = W.make_workload("grid1024", seed=seed, side=side, ins=int(0.025 * side * side),
-                         batches=10)
+    wl = W.make_workload(name, seed=seed, **over)
     r = Q.stream_trend(wl)
     d0, k0, i0 = r["initial"]
     assert r["K"] == pytest.approx(k0)
