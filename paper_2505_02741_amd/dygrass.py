@@ -228,6 +228,15 @@ def dyg_apply_batch(ctx, iu, iv, iw, du, dv, s=None, L=None, results=True, walke
     nu = iu.size + du.size
     s_arr = None if s is None else _arr(s, np.uint16)
     L_arr = None if L is None else _arr(L, np.uint16)
+    # the library reads n_ins entries of iu, iv, iw, n_del of du, dv and
+    # n_ins + n_del of s and L: shorter arrays would be read past their end
+    if iv.size != iu.size or iw.size != iu.size:
+        raise ValueError(f"iu, iv, iw differ in length ({iu.size}, {iv.size}, {iw.size})")
+    if dv.size != du.size:
+        raise ValueError(f"du, dv differ in length ({du.size}, {dv.size})")
+    for name, a in (("s", s_arr), ("L", L_arr)):
+        if a is not None and a.size != nu:
+            raise ValueError(f"{name} has {a.size} entries for {nu} updates")
     res = np.zeros(nu, UPDATE_RESULT_DTYPE) if results else None
     wk = None
     if walkers:
@@ -242,10 +251,44 @@ def dyg_apply_batch(ctx, iu, iv, iw, du, dv, s=None, L=None, results=True, walke
     return res, wk
 
 
+def check_dev_batch(iu, iv, iw, du, dv, s=None, L=None, results=None, on_gpu=True):
+    """Reject tensors the kernels would misread: iu, iv, du, dv with 4-byte
+    elements, iw float64, s and L with 2-byte elements, one entry per update
+    each, results at least 24 bytes per update, all contiguous and (on_gpu)
+    in GPU memory.  s, L and results may be raw device addresses (ints),
+    which are not checked."""
+    n_ins, n_del = int(iu.numel()), int(du.numel())
+    want = (("iu", iu, 4, n_ins), ("iv", iv, 4, n_ins), ("iw", iw, 8, n_ins),
+            ("du", du, 4, n_del), ("dv", dv, 4, n_del), ("s", s, 2, n_ins + n_del),
+            ("L", L, 2, n_ins + n_del))
+    for name, t, size, n in want:
+        if t is None or isinstance(t, int):
+            continue
+        if t.element_size() != size:
+            raise ValueError(f"{name}: {size}-byte elements expected, got {t.dtype}")
+        if int(t.numel()) != n:
+            raise ValueError(f"{name}: {n} entries expected, got {int(t.numel())}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if on_gpu and not t.is_cuda:
+            raise ValueError(f"{name} must be in GPU memory")
+    if not iw.is_floating_point():
+        raise ValueError(f"iw: float64 expected, got {iw.dtype}")
+    if results is not None and not isinstance(results, int):
+        if int(results.numel()) * results.element_size() < 24 * (n_ins + n_del):
+            raise ValueError(f"results: {24 * (n_ins + n_del)} bytes needed")
+        if not results.is_contiguous():
+            raise ValueError("results must be contiguous")
+        if on_gpu and not results.is_cuda:
+            raise ValueError("results must be in GPU memory")
+
+
 def dyg_apply_batch_dev(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, s_max=0,
                         results=None, stream=None):
-    """Device-resident batch: arguments are torch tensors on the GPU (or raw
-    device addresses as ints); stream is a torch stream or a raw handle."""
+    """Device-resident batch: iu, iv, iw, du, dv are torch tensors on the GPU
+    (checked by check_dev_batch); s, L and results are tensors or raw device
+    addresses as ints; stream is a torch stream or a raw handle."""
+    check_dev_batch(iu, iv, iw, du, dv, s=s, L=L, results=results)
 
     def addr(t):
         if t is None:

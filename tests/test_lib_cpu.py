@@ -84,3 +84,56 @@ def test_flag_values_match_header():
                     "TIMING_WALK": 32}
     for name, v in defs.items():
         assert getattr(D, "FLAG_" + name) == v, name
+
+
+def test_host_batch_lengths_are_checked_before_the_library_reads_them():
+    import pytest
+
+    from paper_2505_02741_amd import dygrass as D
+
+    z = np.zeros(0)
+    for args, kw in ((([0, 1], [2], [1.0, 1.0], z, z), {}),
+                     (([0], [2], [1.0, 2.0], z, z), {}),
+                     ((z, z, z, [0, 1], [2]), {}),
+                     (([0], [2], [1.0], [3], [4]), {"s": [8]}),
+                     (([0], [2], [1.0], [3], [4]), {"L": [8, 8, 8]})):
+        with pytest.raises(ValueError):
+            D.dyg_apply_batch(None, *args, **kw)  # refused before any library call
+
+
+def test_device_batch_checks():
+    import pytest
+    import torch
+
+    from paper_2505_02741_amd import dygrass as D
+
+    def batch(n_ins=3, n_del=2, **over):
+        b = dict(iu=torch.zeros(n_ins, dtype=torch.int32), iv=torch.ones(n_ins, dtype=torch.int32),
+                 iw=torch.ones(n_ins, dtype=torch.float64),
+                 du=torch.zeros(n_del, dtype=torch.int32), dv=torch.ones(n_del, dtype=torch.int32),
+                 s=torch.full((n_ins + n_del,), 8, dtype=torch.int16),
+                 L=torch.full((n_ins + n_del,), 8, dtype=torch.int16),
+                 results=torch.zeros(24 * (n_ins + n_del), dtype=torch.uint8))
+        b.update(over)
+        return b
+
+    # the forms the tests and the benchmark hand over are accepted
+    D.check_dev_batch(**batch(), on_gpu=False)
+    D.check_dev_batch(**batch(n_del=0, du=torch.zeros(0, dtype=torch.int32),
+                              dv=torch.zeros(0, dtype=torch.int32), s=None, L=None,
+                              results=None), on_gpu=False)
+    D.check_dev_batch(**batch(s=0x7000, L=0x8000, results=0x9000), on_gpu=False)  # raw addresses
+    bad = [dict(iu=torch.zeros(3, dtype=torch.int64)),          # 8-byte ids
+           dict(iv=torch.ones(2, dtype=torch.int32)),           # short
+           dict(iw=torch.ones(3, dtype=torch.float32)),         # 4-byte weights
+           dict(iw=torch.ones(3, dtype=torch.int64)),           # integer weights
+           dict(dv=torch.ones(3, dtype=torch.int32)),           # long
+           dict(s=torch.full((5,), 8, dtype=torch.int32)),      # 4-byte walker counts
+           dict(L=torch.full((4,), 8, dtype=torch.int16)),      # short
+           dict(results=torch.zeros(24 * 5 - 1, dtype=torch.uint8)),
+           dict(iu=torch.zeros(6, dtype=torch.int32)[::2])]     # not contiguous
+    for over in bad:
+        with pytest.raises(ValueError):
+            D.check_dev_batch(**batch(**over), on_gpu=False)
+    with pytest.raises(ValueError, match="GPU memory"):
+        D.check_dev_batch(**batch())  # host tensors where device memory is required
