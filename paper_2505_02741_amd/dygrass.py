@@ -212,10 +212,33 @@ def dyg_init(n, rowptr, col, w, h_u, h_v, params: dyg_params) -> C.c_void_p:
     w = _arr(w, np.float64)
     h_u = _arr(h_u, np.uint32)
     h_v = _arr(h_v, np.uint32)
+    # the library reads n + 1 row offsets, rowptr[n] entries of col and w, and
+    # h_m entries of h_u and h_v
+    if rowptr.size != int(n) + 1:
+        raise ValueError(f"rowptr has {rowptr.size} entries for n = {int(n)}")
+    if col.size != int(rowptr[-1]) or w.size != int(rowptr[-1]):
+        raise ValueError(f"col and w need rowptr[n] = {int(rowptr[-1])} entries, "
+                         f"got {col.size} and {w.size}")
+    if h_v.size != h_u.size:
+        raise ValueError(f"h_u, h_v differ in length ({h_u.size}, {h_v.size})")
     ctx = C.c_void_p()
     _check(_lib.dyg_init(C.byref(ctx), int(n), _ptr(rowptr), _ptr(col), _ptr(w), h_u.size,
                          _ptr(h_u), _ptr(h_v), C.byref(params)), "dyg_init")
     return ctx
+
+
+def _check_host_batch(iu, iv, iw, du, dv, s=None, L=None):
+    """The library reads n_ins entries of iu, iv, iw, n_del of du, dv and
+    n_ins + n_del of s and L: refuse shorter arrays before it reads past
+    their end."""
+    if iv.size != iu.size or iw.size != iu.size:
+        raise ValueError(f"iu, iv, iw differ in length ({iu.size}, {iv.size}, {iw.size})")
+    if dv.size != du.size:
+        raise ValueError(f"du, dv differ in length ({du.size}, {dv.size})")
+    nu = iu.size + du.size
+    for name, a in (("s", s), ("L", L)):
+        if a is not None and a.size != nu:
+            raise ValueError(f"{name} has {a.size} entries for {nu} updates")
 
 
 def dyg_apply_batch(ctx, iu, iv, iw, du, dv, s=None, L=None, results=True, walkers=False,
@@ -228,15 +251,7 @@ def dyg_apply_batch(ctx, iu, iv, iw, du, dv, s=None, L=None, results=True, walke
     nu = iu.size + du.size
     s_arr = None if s is None else _arr(s, np.uint16)
     L_arr = None if L is None else _arr(L, np.uint16)
-    # the library reads n_ins entries of iu, iv, iw, n_del of du, dv and
-    # n_ins + n_del of s and L: shorter arrays would be read past their end
-    if iv.size != iu.size or iw.size != iu.size:
-        raise ValueError(f"iu, iv, iw differ in length ({iu.size}, {iv.size}, {iw.size})")
-    if dv.size != du.size:
-        raise ValueError(f"du, dv differ in length ({du.size}, {dv.size})")
-    for name, a in (("s", s_arr), ("L", L_arr)):
-        if a is not None and a.size != nu:
-            raise ValueError(f"{name} has {a.size} entries for {nu} updates")
+    _check_host_batch(iu, iv, iw, du, dv, s_arr, L_arr)
     res = np.zeros(nu, UPDATE_RESULT_DTYPE) if results else None
     wk = None
     if walkers:
@@ -473,6 +488,7 @@ class DygServer:
         iw = _arr(iw, np.float64)
         du = _arr(du, np.uint32)
         dv = _arr(dv, np.uint32)
+        _check_host_batch(iu, iv, iw, du, dv)
         res = np.zeros(iu.size + du.size, UPDATE_RESULT_DTYPE) if results else None
         rid = C.c_uint64(0)
         _check(_lib.dyg_server_submit(self.h, int(graph_id), iu.size, _ptr(iu), _ptr(iv),

@@ -137,3 +137,23 @@ def test_device_batch_checks():
             D.check_dev_batch(**batch(**over), on_gpu=False)
     with pytest.raises(ValueError, match="GPU memory"):
         D.check_dev_batch(**batch())  # host tensors where device memory is required
+
+
+def test_init_and_serving_inputs_are_checked_before_the_library_reads_them():
+    import types
+
+    import pytest
+
+    from paper_2505_02741_amd import dygrass as D
+
+    p = D.dyg_default_params()
+    rp, col, w = [0, 1, 2], [1, 0], [1.0, 1.0]  # one edge on two vertices
+    for args in (([0, 1], col, w, [0], [1]),          # rowptr short of n + 1
+                 (rp, [1], w, [0], [1]),              # col short of rowptr[n]
+                 (rp, col, [1.0], [0], [1]),          # w short of rowptr[n]
+                 (rp, col, w, [0], [1, 0])):          # h_u, h_v differ
+        with pytest.raises(ValueError):
+            D.dyg_init(2, *args, p)
+    srv = types.SimpleNamespace(h=None, _keep={})  # refused before the handle is used
+    with pytest.raises(ValueError):
+        D.DygServer.submit(srv, 0, [0, 1], [2], [1.0, 1.0], [], [])
