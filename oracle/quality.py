@@ -17,8 +17,11 @@
   the preconditioner applied through a sparse LU of grounded L_H.
 * The trend of Tables II, III and IV on a synthetic stream: an insertion stream
   applied three ways -- H left alone, every inserted edge added to H (no
-  filter), and the update rule of Algorithm 1 through the CPU oracle -- with
-  d_H, kappa and the PCG iteration count after the stream.
+  filter), and the update rule of Algorithm 1 through the CPU oracle, both
+  batched (updates applied at the end of each batch, Sec. III-F) and
+  sequential (each update its own batch, so every one sees the previous
+  ones, as in the per-update loop of Algorithm 1) -- with d_H, kappa and the
+  PCG iteration count after the stream.
 
 Plain scipy sparse linear algebra; shares nothing with the GPU library.
 """
@@ -105,9 +108,10 @@ def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None
     """d_H, kappa(L_G, L_H) and PCG iterations before and after an
     insertion-only stream, for H left alone, H given every insertion, and H
     updated by the oracle with threshold K (by default kappa of the initial
-    pair, the distortion bound of Eq. 11).  Returns a dict of (d_H, kappa,
-    iterations) triples; the initial one is taken against G before the
-    stream, the others against G after it."""
+    pair, the distortion bound of Eq. 11), batched and one update per batch
+    ("sequential").  Returns a dict of (d_H, kappa, iterations) triples; the
+    initial one is taken against G before the stream, the others against G
+    after it."""
     import oracle
     from paper_2505_02741_amd import workloads as W
 
@@ -136,5 +140,20 @@ def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None
     for name, H in (("no_update", H0), ("no_filter", Ha), ("dygrass", Hd)):
         out[name] = (off_tree_density(n, np.asarray(H[0]).size),
                      relative_condition_number(n, G1, H), pcg_iterations(n, G1, H)[0])
+    # sequential semantics: the same updates, one per batch
+    o = oracle.Oracle(n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=K,
+                      s=wl.s if s is None else s, L=wl.L if L is None else L)
+    try:
+        z = np.zeros(0, np.uint32)
+        for b in wl.batches:
+            for i in range(b.n_ins):
+                o.apply_batch(b.iu[i:i + 1], b.iv[i:i + 1], b.iw[i:i + 1], z, z,
+                              s=None if b.s is None else b.s[i:i + 1],
+                              L=None if b.L is None else b.L[i:i + 1])
+        Hs = o.query("H")
+    finally:
+        o.close()
+    out["sequential"] = (off_tree_density(n, Hs[0].size), relative_condition_number(n, G1, Hs),
+                         pcg_iterations(n, G1, Hs)[0])
     out["K"] = K if math.isfinite(K) else float("inf")
     return out

@@ -109,3 +109,6 @@ def test_stream_trend_of_tables_two_to_four(name, seed, over):
     # H with every edge contains the oracle's H, so lambda_max can only be
     # lower; lambda_min is 1 for both (a vertex whose edges all lie in H)
     assert k_all <= k_dyg
+    # one update per batch (each sees the previous ones): the same picture
+    d_seq, k_seq, i_seq = r["sequential"]
+    assert d_all > d_seq > d0 and k_seq < k_none and i_seq < i_none
