@@ -104,12 +104,15 @@ def pcg_iterations(n: int, G, H, b=None, rtol: float = 1e-8, max_iter: int = 100
     raise RuntimeError("PCG did not converge")
 
 
-def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None = None):
+def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None = None,
+                 w_ref: float = 0.0):
     """d_H, kappa(L_G, L_H) and PCG iterations before and after an
     insertion-only stream, for H left alone, H given every insertion, and H
     updated by the oracle with threshold K (by default kappa of the initial
     pair, the distortion bound of Eq. 11), batched and one update per batch
-    ("sequential").  Returns a dict of (d_H, kappa, iterations) triples; the
+    ("sequential").  w_ref is the oracle's reference weight (0: its default;
+    a huge one quantises every weight to 1, i.e. unweighted selection).
+    Returns a dict of (d_H, kappa, iterations) triples; the
     initial one is taken against G before the stream, the others against G
     after it."""
     import oracle
@@ -128,7 +131,7 @@ def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None
     G1 = (np.concatenate([G0[0], iu]), np.concatenate([G0[1], iv]), np.concatenate([G0[2], iw]))
     rp, col, w = W.to_csr(n, *G0)
     o = oracle.Oracle(n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=K,
-                      s=wl.s if s is None else s, L=wl.L if L is None else L)
+                      s=wl.s if s is None else s, L=wl.L if L is None else L, w_ref=w_ref)
     try:
         for b in wl.batches:
             o.apply_batch(b.iu, b.iv, b.iw, b.du, b.dv, s=b.s, L=b.L)
@@ -142,7 +145,7 @@ def stream_trend(wl, K: float | None = None, s: int | None = None, L: int | None
                      relative_condition_number(n, G1, H), pcg_iterations(n, G1, H)[0])
     # sequential semantics: the same updates, one per batch
     o = oracle.Oracle(n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=K,
-                      s=wl.s if s is None else s, L=wl.L if L is None else L)
+                      s=wl.s if s is None else s, L=wl.L if L is None else L, w_ref=w_ref)
     try:
         z = np.zeros(0, np.uint32)
         for b in wl.batches:

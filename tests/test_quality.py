@@ -112,3 +112,20 @@ def test_stream_trend_of_tables_two_to_four(name, seed, over):
     # one update per batch (each sees the previous ones): the same picture
     d_seq, k_seq, i_seq = r["sequential"]
     assert d_all > d_seq > d0 and k_seq < k_none and i_seq < i_none
+
+
+def test_unweighted_selection_through_a_huge_reference_weight():
+    """A reference weight of 10^300 quantises every weight to the clamp
+    floor 1, so the walkers choose uniformly (resistance still uses 1/w);
+    the update rule still keeps H sparse and kappa below H left alone."""
+    import oracle
+    from oracle import quality as Q
+
+    for w in (1e-3, 0.5, 1.0, 7.0, 1e6):
+        assert oracle.quantize(w, 1e300) == 1
+    wl = W.make_workload("grid1024", seed=1, side=32, ins=25, batches=10)
+    r = Q.stream_trend(wl, w_ref=1e300)
+    d0, k0, _ = r["initial"]
+    d_dyg, k_dyg, _ = r["dygrass"]
+    assert r["no_filter"][0] > d_dyg > d0
+    assert k_dyg < r["no_update"][1]
