@@ -13,9 +13,11 @@ def test_sparse_kappa_matches_dense():
     from oracle import quality as Q
     from oracle import spectral
 
-    for seed, side, extra in ((1, 6, 0.1), (2, 8, 0.3), (3, 9, 0.0)):
+    # grids, and a mesh whose face diagonals make it non-bipartite
+    for seed, gen, side, extra in ((1, W.grid2d, 6, 0.1), (2, W.grid2d, 8, 0.3),
+                                   (3, W.grid2d, 9, 0.0), (4, W.mesh3d, 4, 0.2)):
         rng = np.random.default_rng(seed)
-        n, u, v = W.grid2d(side)
+        n, u, v = gen(side)
         w = rng.lognormal(0.0, 1.0, u.size)
         hm = W.max_spanning_forest(n, u, v, w) | (rng.random(u.size) < extra)
         dense = spectral.relative_condition_number(spectral.laplacian(n, u, v, w),
@@ -129,3 +131,53 @@ def test_unweighted_selection_through_a_huge_reference_weight():
     d_dyg, k_dyg, _ = r["dygrass"]
     assert r["no_filter"][0] > d_dyg > d0
     assert k_dyg < r["no_update"][1]
+
+
+def test_pins_reject_planted_mistakes(monkeypatch):
+    """Plausible mistakes in the grounded Laplacian (a dropped diagonal term,
+    a flipped off-diagonal sign, a row grounded without its column) change
+    the sparse kappa away from the dense one, which the first pin checks.
+    The graph has triangles: on a bipartite graph D + A = S (D - A) S for a
+    diagonal sign matrix S, so a flipped sign would leave kappa unchanged."""
+    import scipy.sparse as sp
+
+    from oracle import quality as Q
+    from oracle import spectral
+
+    rng = np.random.default_rng(2)
+    n, u, v = W.mesh3d(4)
+    w = rng.lognormal(0.0, 1.0, u.size)
+    hm = W.max_spanning_forest(n, u, v, w) | (rng.random(u.size) < 0.3)
+    dense = spectral.relative_condition_number(spectral.laplacian(n, u, v, w),
+                                               spectral.laplacian(n, u[hm], v[hm], w[hm]))
+    good = Q.grounded_laplacian
+
+    def no_v_diagonal(n_, u_, v_, w_, root=0):
+        u_, v_, w_ = (np.asarray(x) for x in (u_, v_, w_))
+        Lm = sp.coo_matrix((np.concatenate([-w_, -w_, w_]),
+                            (np.concatenate([u_, v_, u_]), np.concatenate([v_, u_, u_]))),
+                           shape=(n_, n_)).tocsr()
+        keep = np.arange(1, n_)
+        return Lm[keep][:, keep].tocsc()
+
+    def flipped_sign(n_, u_, v_, w_, root=0):
+        L = good(n_, u_, v_, w_, root)
+        d = sp.diags(L.diagonal())
+        return (2 * d - L).tocsc()
+
+    def row_only(n_, u_, v_, w_, root=0):
+        u_, v_, w_ = (np.asarray(x) for x in (u_, v_, w_))
+        Lm = sp.coo_matrix((np.concatenate([-w_, -w_, w_, w_]),
+                            (np.concatenate([u_, v_, u_, v_]), np.concatenate([v_, u_, u_, v_]))),
+                           shape=(n_, n_)).tocsr()
+        return (Lm[1:][:, :-1]).tocsc()
+
+    for bad in (no_v_diagonal, flipped_sign, row_only):
+        monkeypatch.setattr(Q, "grounded_laplacian", bad)
+        try:
+            k = Q.relative_condition_number(n, (u, v, w), (u[hm], v[hm], w[hm]))
+        except Exception:
+            continue  # failing outright is rejection too
+        finally:
+            monkeypatch.setattr(Q, "grounded_laplacian", good)
+        assert abs(k - dense) > 1e-6 * dense, bad.__name__
