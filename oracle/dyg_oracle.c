@@ -39,7 +39,9 @@
  *    occurrence, without loop erasure, those not in H; the winner is the
  *    hitting walker of least R, ties to the lower walker index;
  *  - with no hit, per endpoint the least-resistance G edge not in H (ties to
- *    the smaller neighbour id) is recovered: "a few local edges" (Sec. III-C).
+ *    the smaller neighbour id) is recovered, a reading of the local fallback
+ *    of Sec. III-C.  Parity unpinned: the paper fixes no rule this choice
+ *    could be checked against, so only oracle = GPU holds it in place.
  */
 #include <math.h>
 #include <stdint.h>
