@@ -104,6 +104,8 @@ def _load():
     lib.orc_apply_batch.restype = C.c_int
     lib.orc_query.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(C.c_uint64), P, P, P]
     lib.orc_query.restype = C.c_int
+    lib.orc_last_recovered.argtypes = [P, C.c_uint64, C.c_uint32, P, P]
+    lib.orc_last_recovered.restype = C.c_long
     del u8p
     _lib = lib
     return lib
@@ -252,6 +254,19 @@ class Oracle:
             raise OracleError(rc)
         out["walkers"] = wk
         return out
+
+    def last_recovered(self, j: int):
+        """Edges deletion j of the last batch recovered into H, in the order
+        they were taken (the winner's path order, or the fallback edges of
+        the first endpoint, then of the second)."""
+        lib = _load()
+        cnt = lib.orc_last_recovered(self._h, int(j), 0, None, None)
+        if cnt < 0:
+            raise IndexError(j)
+        a = np.zeros(max(cnt, 1), np.uint32)
+        b = np.zeros(max(cnt, 1), np.uint32)
+        lib.orc_last_recovered(self._h, int(j), cnt, _ptr(a), _ptr(b))
+        return [(int(x), int(y)) for x, y in zip(a[:cnt], b[:cnt])]
 
     def query(self, which="H"):
         lib = _load()

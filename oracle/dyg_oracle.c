@@ -37,11 +37,14 @@
  *    snapshot, then insertions, accepted edges and recovered edges are added;
  *  - the recovered path is the winner's edges in path order, first
  *    occurrence, without loop erasure, those not in H; the winner is the
- *    hitting walker of least R, ties to the lower walker index;
+ *    hitting walker of least R, ties to the lower walker index (a hit whose
+ *    sum overflowed to +inf still counts: with every hit at +inf the first
+ *    hitting walker wins);
+ *  - a weight must be positive and finite with a finite 1/w;
  *  - with no hit, per endpoint the least-resistance G edge not in H (ties to
  *    the smaller neighbour id) is recovered, a reading of the local fallback
- *    of Sec. III-C.  Parity unpinned: the paper fixes no rule this choice
- *    could be checked against, so only oracle = GPU holds it in place.
+ *    of Sec. III-C.  The paper gives no rule to check this reading against;
+ *    the tests pin the reading itself on hand-computed cases.
  */
 #include <math.h>
 #include <stdint.h>
@@ -394,7 +397,17 @@ typedef struct {
   uint64_t uid_base;
   uint64_t steps_total;     /* walker steps taken since creation */
   uint64_t alg_bytes_total; /* bytes those steps must gather */
+  /* edges each deletion of the last batch recovered into H, in the order
+   * they were taken (path order, or the endpoints' fallback edges) */
+  uint64_t last_ndel;
+  uint64_t *last_rofs; /* [last_ndel + 1] */
+  uint32_t *last_nrec; /* [last_ndel] */
+  uint32_t *last_rec_a, *last_rec_b;
 } oracle_t;
+
+/* A usable weight is positive and finite with a finite resistance 1/w
+ * (a subnormal weight's 1/w overflows). */
+static int weight_ok(double w) { return w > 0.0 && !isinf(w) && !isinf(1.0 / w); }
 
 static uint64_t ekey(uint32_t u, uint32_t v) {
   uint32_t a = u < v ? u : v, b = u < v ? v : u;
@@ -463,7 +476,7 @@ oracle_t *orc_create(uint32_t n, const uint64_t *rowptr, const uint32_t *col,
         *err = ORC_SELF_LOOP;
         return NULL;
       }
-      if (!(w[k] > 0.0) || isinf(w[k])) {
+      if (!weight_ok(w[k])) {
         *err = ORC_BAD_WEIGHT;
         return NULL;
       }
@@ -541,11 +554,37 @@ oracle_t *orc_create(uint32_t n, const uint64_t *rowptr, const uint32_t *col,
   return o;
 }
 
+static void o_free_last(oracle_t *o) {
+  free(o->last_rofs);
+  free(o->last_nrec);
+  free(o->last_rec_a);
+  free(o->last_rec_b);
+  o->last_rofs = NULL;
+  o->last_nrec = NULL;
+  o->last_rec_a = o->last_rec_b = NULL;
+  o->last_ndel = 0;
+}
+
 void orc_destroy(oracle_t *o) {
   if (!o) return;
   og_free(&o->G);
   og_free(&o->H);
+  o_free_last(o);
   free(o);
+}
+
+/* Edges deletion j of the last successful batch recovered (path or
+ * fallback), in the order taken: writes up to cap of them to a/b and
+ * returns their number, or -1 if j is out of range. */
+long orc_last_recovered(const oracle_t *o, uint64_t j, uint32_t cap, uint32_t *a,
+                        uint32_t *b) {
+  if (j >= o->last_ndel) return -1;
+  uint32_t cnt = o->last_nrec[j];
+  for (uint32_t z = 0; z < cnt && z < cap; ++z) {
+    a[z] = o->last_rec_a[o->last_rofs[j] + z];
+    b[z] = o->last_rec_b[o->last_rofs[j] + z];
+  }
+  return (long)cnt;
 }
 
 uint64_t orc_uid_base(const oracle_t *o) { return o->uid_base; }
@@ -572,7 +611,7 @@ static int o_validate(const oracle_t *o, uint64_t n_ins, const uint32_t *iu,
   for (uint64_t i = 0; i < n_ins && err == ORC_OK; ++i) {
     if (iu[i] >= o->n || iv[i] >= o->n) err = ORC_VERTEX_RANGE;
     else if (iu[i] == iv[i]) err = ORC_SELF_LOOP;
-    else if (!(iw[i] > 0.0) || isinf(iw[i])) err = ORC_BAD_WEIGHT;
+    else if (!weight_ok(iw[i])) err = ORC_BAD_WEIGHT;
     else if (og_has(&o->G, iu[i], iv[i])) err = ORC_EDGE_EXISTS;
     else if (dupi[i]) err = ORC_DUPLICATE_IN_BATCH;
   }
@@ -669,8 +708,9 @@ int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
         by += res[k].bytes;
         if (res[k].hit) {
           anyh = 1;
-          /* minimum resistance over hitting walkers, ties to the lower index */
-          if (res[k].R < rmin) {
+          /* minimum resistance over hitting walkers, ties to the lower index
+           * (a sum that overflowed to +inf still names a walker) */
+          if (win == 0xFFFF || res[k].R < rmin) {
             rmin = res[k].R;
             win = (uint16_t)k;
           }
@@ -761,13 +801,15 @@ int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
     }
   }
   o->uid_base += nu;
+  o_free_last(o);
+  o->last_ndel = n_del;
+  o->last_rofs = rofs;
+  o->last_nrec = nrec;
+  o->last_rec_a = rec_a;
+  o->last_rec_b = rec_b;
   free(wofs);
   free(inH);
   free(acc);
-  free(rofs);
-  free(rec_a);
-  free(rec_b);
-  free(nrec);
   return ORC_OK;
 }
 

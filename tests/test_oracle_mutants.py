@@ -1,8 +1,9 @@
 """The pins must catch plausible mistakes in the oracle.
 
 Each case plants one mistake in a temporary copy of the C oracle (on the CPU,
-never on a GPU), builds it, and runs the pin suite against the broken build:
-the suite must fail.  The real oracle is untouched.
+never on a GPU), builds it, and runs the pin suites (walk rules, and the
+deletion repair) against the broken build: they must fail.  The real oracle
+is untouched.
 """
 from __future__ import annotations
 
@@ -36,7 +37,8 @@ MUTANTS = {
     # conductance summed instead of resistance
     "R_adds_w": ("    R = R + r;", "    R = R + 1.0 / r;"),
     # ties of the minimum resolved to the last walker
-    "winner_last": ("if (res[k].R < rmin) {", "if (res[k].R <= rmin) {"),
+    "winner_last": ("if (win == 0xFFFF || res[k].R < rmin) {",
+                    "if (win == 0xFFFF || res[k].R <= rmin) {"),
     # decision inverted
     "accept_inverted": ("fl = (uint8_t)!anyh;", "fl = (uint8_t)anyh;"),
     # deleted sparsifier edges stay in H
@@ -46,7 +48,44 @@ MUTANTS = {
     # bounce allowed although the policy is TERMINATE
     "always_bounce": ("if (bounce && prev >= 0) forced_back = 1;",
                       "if (prev >= 0) forced_back = 1;"),
+    # --- deletion repair (Sec. III-C) ---
+    # the first hitting walker wins whatever its resistance
+    "winner_first_hit": ("if (win == 0xFFFF || res[k].R < rmin) {", "if (win == 0xFFFF) {"),
+    # a hit whose sum overflowed names no walker
+    "winner_skips_inf": ("if (win == 0xFFFF || res[k].R < rmin) {", "if (res[k].R < rmin) {"),
+    # another hitting walker's path is recovered (the last one that hit)
+    "recover_last_hitter": ("const uint32_t *path = traj + (size_t)win * (Li + 1);\n"
+                            "          for (uint32_t t = 0; t < res[win].steps; ++t) {",
+                            "uint32_t lw = win;\n"
+                            "          for (uint32_t k = 0; k < si; ++k) if (res[k].hit) lw = k;\n"
+                            "          const uint32_t *path = traj + (size_t)lw * (Li + 1);\n"
+                            "          for (uint32_t t = 0; t < res[lw].steps; ++t) {"),
+    # path edges already in H are recovered again
+    "recover_keeps_H_edges": ("            if (og_has(&o->H, a, b)) continue;\n"
+                              "            int seen = 0;",
+                              "            int seen = 0;"),
+    # an edge the path repeats is listed twice
+    "recover_no_dedup": ("            if (seen) continue;\n", ""),
+    # the path is taken from its far end
+    "recover_reversed": ("            uint32_t a = path[t], b = path[t + 1];",
+                         "            uint32_t a = path[res[win].steps - t],"
+                         " b = path[res[win].steps - t - 1];"),
+    # fallback: the least weight (largest resistance) instead of the largest
+    "fallback_min_weight": ("if (best < 0 || row->e[t].r < row->e[best].r) best = (long)t;",
+                            "if (best < 0 || row->e[t].r > row->e[best].r) best = (long)t;"),
+    # fallback: ties go to the larger neighbour id
+    "fallback_ties_larger": ("if (best < 0 || row->e[t].r < row->e[best].r) best = (long)t;",
+                             "if (best < 0 || row->e[t].r <= row->e[best].r) best = (long)t;"),
+    # fallback: edges already in H are candidates too
+    "fallback_ignores_H": ("              if (og_has(&o->H, ends[z], row->e[t].nbr)) continue;\n",
+                           ""),
+    # an inserted weight whose 1/w overflows is accepted
+    "weight_inf_resistance": ("static int weight_ok(double w) { return w > 0.0 && !isinf(w) && "
+                              "!isinf(1.0 / w); }",
+                              "static int weight_ok(double w) { return w > 0.0 && !isinf(w); }"),
 }
+
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_recovery.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -61,6 +100,6 @@ def test_pins_reject_mutant(name, tmp_path):
                     "-shared", "-o", str(lib), str(mutated), "-lm"], check=True)
     env = dict(os.environ, DYG_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        *(os.path.join(ROOT, "tests", f) for f in PIN_FILES)],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins accept mutant {name}:\n{r.stdout[-2000:]}"
