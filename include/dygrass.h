@@ -49,7 +49,8 @@ typedef enum {
   DYG_E_INVALID_ARG = -1,        /* bad pointer, size, parameter or s/L bound   */
   DYG_E_SELF_LOOP = -2,          /* an edge (u,u)                               */
   DYG_E_VERTEX_RANGE = -3,       /* a vertex id >= n                            */
-  DYG_E_BAD_WEIGHT = -4,         /* weight <= 0, NaN or infinite                */
+  DYG_E_BAD_WEIGHT = -4,         /* weight <= 0, NaN, infinite, or so small that
+                                    its resistance 1/w overflows                 */
   DYG_E_EDGE_EXISTS = -5,        /* inserted edge already in G (Sec. III-B)     */
   DYG_E_EDGE_MISSING = -6,       /* deleted edge not in G (Sec. III-C)          */
   DYG_E_DUPLICATE_IN_BATCH = -7, /* the same edge twice in one list             */
@@ -85,6 +86,10 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
                                   batch around it (dyg_stats walk_ms_*), none
                                   around the batch (batch_ms_last stays 0), so
                                   that timing disturbs the stream least          */
+#define DYG_FLAG_FAIL_POOL_GROWTH 64u /* for tests of the failure paths: growing a
+                                  pool that ran short fails as if the device had
+                                  no memory left (the batch reports DYG_E_NOMEM
+                                  and the context takes no further batches)      */
 
 #define DYG_MAX_WALKERS 1024 /* per update */
 #define DYG_MAX_STEPS 1024   /* per walker */

@@ -442,7 +442,7 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
     for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
       if (col[k] >= n) return DYG_E_VERTEX_RANGE;
       if (col[k] == u) return DYG_E_SELF_LOOP;
-      if (!(w[k] > 0.0) || std::isinf(w[k])) return DYG_E_BAD_WEIGHT;
+      if (!(w[k] > 0.0) || std::isinf(w[k]) || std::isinf(1.0 / w[k])) return DYG_E_BAD_WEIGHT;
       if (k > rowptr[u] && col[k] <= col[k - 1]) return DYG_E_INVALID_ARG;
       wmax = std::max(wmax, w[k]);
     }
@@ -883,6 +883,7 @@ int decode_err(unsigned long long key) {
 // Finish phase 4 of graphs that ran short of pool slots: grow the pool,
 // then run phase 4 again from the batch's staged additions.
 int repair_nomem(dyg_ctx* c, BatchArgs& a, BatchCtl& ctl) {
+  if (c->params.flags & DYG_FLAG_FAIL_POOL_GROWTH) return DYG_E_NOMEM;
   for (int attempt = 0; attempt < 4 && (ctl.nomem[0] || ctl.nomem[1]); ++attempt) {
     for (int g = 0; g < 2; ++g) {
       if (!ctl.nomem[g]) continue;
@@ -928,9 +929,11 @@ extern "C" int dyg_apply_batch(dyg_ctx* c, uint64_t n_ins, const uint32_t* iu,
   const uint64_t nu = n_ins + n_del;
   if (nu >= (1ull << 30)) return DYG_E_INVALID_ARG;
   if (c->async_inflight) {
+    // the device batch enqueued before this one: its failure is this call's
     int rc = dyg_sync(c);
-    (void)rc;
+    if (rc) return rc;
   }
+  if (c->broken) return DYG_E_NOMEM;
   uint32_t Lcap = c->params.L_default;
   uint64_t walkers_total = 0;
   std::vector<uint64_t> wofs;
@@ -1071,9 +1074,13 @@ extern "C" int dyg_sync(dyg_ctx* c) {
   rc = decode_err(ctl.err_key);
   if (rc) return c->pending_status = rc;
   if (ctl.nomem[0] || ctl.nomem[1]) {
-    // the staged additions of this batch are still intact: finish them
-    c->broken = true;
-    return c->pending_status = DYG_E_NOMEM;
+    // the staged additions of this batch are still intact: grow the pool and
+    // finish its phase 4 (its device arguments are still in c->hargs)
+    rc = repair_nomem(c, *c->hargs, ctl);
+    if (rc) {
+      c->broken = true;
+      return c->pending_status = rc;
+    }
   }
   c->uid_base += c->async_nu;
   c->batches++;
@@ -1613,6 +1620,19 @@ int launch_round(dyg_server* s, ServerRound& r) {
   return DYG_OK;
 }
 
+// A graph whose pool repair failed takes no more batches: its waiting
+// requests finish with `rc` at once (their state could no longer be that of
+// the requests before them applied in order).
+void fail_waiting(dyg_server* s, uint32_t g, int rc) {
+  const double now = server_clock(s);
+  while (!s->queues[g].empty()) {
+    ServerRequest* q = s->queues[g].front();
+    s->queues[g].pop_front();
+    s->finished.push_back(dyg_request_done{q->id, q->graph, rc, q->nu(), q->t_submit, now, now});
+    delete q;
+  }
+}
+
 // A finished round: decide each request, finish pool repairs, report.
 void retire_round(dyg_server* s, ServerRound& r) {
   const double now = server_clock(s);
@@ -1650,6 +1670,7 @@ void retire_round(dyg_server* s, ServerRound& r) {
     dyg_request_done d{q->id, q->graph, rc, q->nu(), q->t_submit, q->t_start, q->t_done};
     s->finished.push_back(d);
     s->busy[q->graph] = 0;
+    if (c->broken) fail_waiting(s, q->graph, rc ? rc : DYG_E_NOMEM);
     delete q;
   }
   s->mem_in_flight -= r.mem;
@@ -1757,6 +1778,10 @@ extern "C" int dyg_server_poll(dyg_server* s, dyg_request_done* done, uint32_t c
     if (e != hipSuccess) return fail_hip(e);
     retire_round(s, r);
   }
+  // graphs broken outside the server (or before their requests arrived)
+  for (uint32_t g = 0; g < s->graphs.size(); ++g)
+    if (s->graphs[g]->broken && !s->busy[g] && !s->queues[g].empty())
+      fail_waiting(s, g, DYG_E_NOMEM);
   for (ServerRound& r : s->rounds) {
     if (r.busy) continue;
     admit(s, r);

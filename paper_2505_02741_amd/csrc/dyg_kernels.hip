@@ -348,7 +348,7 @@ __global__ void k_validate_b(const BatchArgs* const* __restrict__ argv) {
     int code = 0;
     if (u >= a.n || v >= a.n) code = E_VERTEX_RANGE;
     else if (u == v) code = E_SELF_LOOP;
-    else if (!(w > 0.0) || isinf(w)) code = E_BAD_WEIGHT;
+    else if (!(w > 0.0) || isinf(w) || isinf(1.0 / w)) code = E_BAD_WEIGHT;
     else if (has_live(G, u, v)) code = E_EDGE_EXISTS;
     else if (hash_min_of(a.hash, a.hash_mask, edge_key(u, v)) < i) code = E_DUPLICATE;
     if (code) report(a.ctl, 0, i, code);
@@ -1209,7 +1209,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
     double cR = h ? o.R : INFINITY;
     uint32_t cW = h ? walker : kNone;
     wave_argmin(cR, cW);
-    if (cR < bestR) {  // a later round only wins with a strictly smaller R
+    // a later round only wins with a strictly smaller R; a hit whose sum
+    // overflowed to +inf still names its walker when nothing better exists
+    if (cW != kNone && (bestW == kNone || cR < bestR)) {
       bestR = cR;
       bestW = cW;
     }
@@ -1744,7 +1746,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
     double cR = h ? o.R : INFINITY;
     uint32_t cW = h ? walker : kNone;
     wave_argmin(cR, cW);
-    if (cR < bestR) {
+    if (cW != kNone && (bestW == kNone || cR < bestR)) {
       bestR = cR;
       bestW = cW;
     }

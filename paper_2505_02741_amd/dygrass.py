@@ -37,6 +37,7 @@ FLAG_BATCHED = 4
 FLAG_GRAPH = 8
 FLAG_AUTOTUNE = 16
 FLAG_TIMING_WALK = 32
+FLAG_FAIL_POOL_GROWTH = 64
 
 DEAD_END_TERMINATE = 0
 DEAD_END_BOUNCE = 1
