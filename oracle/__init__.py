@@ -99,6 +99,8 @@ def _load():
     lib.orc_alg_bytes_total.restype = C.c_uint64
     lib.orc_w_ref.argtypes = [P]
     lib.orc_w_ref.restype = C.c_double
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_set_threads.restype = C.c_int
     lib.orc_apply_batch.argtypes = [P, C.c_uint64, P, P, P, C.c_uint64, P, P, P, P,
                                     P, P, P, P, P, P, P, P, P, P]
     lib.orc_apply_batch.restype = C.c_int
@@ -109,6 +111,12 @@ def _load():
     del u8p
     _lib = lib
     return lib
+
+
+def set_threads(k: int = 0) -> int:
+    """Threads of the oracle's loop over a batch's updates (k <= 0: leave as
+    is); returns the count in use.  Results do not depend on it."""
+    return int(_load().orc_set_threads(int(k)))
 
 
 def _ptr(a):

@@ -47,6 +47,7 @@
  *    the tests pin the reading itself on hand-computed cases.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -591,6 +592,14 @@ uint64_t orc_uid_base(const oracle_t *o) { return o->uid_base; }
 uint64_t orc_steps_total(const oracle_t *o) { return o->steps_total; }
 uint64_t orc_alg_bytes_total(const oracle_t *o) { return o->alg_bytes_total; }
 double orc_w_ref(const oracle_t *o) { return o->w_ref; }
+
+/* Threads of the loop over a batch's updates (a timing control: phase 2
+ * reads only the batch snapshot, so results never depend on it).  k <= 0
+ * leaves the count unchanged; returns the count now in use. */
+int orc_set_threads(int k) {
+  if (k > 0) omp_set_num_threads(k);
+  return omp_get_max_threads();
+}
 
 /* Validation precedence: insertions in order (range, self loop, weight,
  * already in G, repeated in batch), then deletions in order (range, self

@@ -159,31 +159,52 @@ def mesh3d(side: int):
 
 
 def rmat(scale: int, edge_factor: int, abcd=(0.57, 0.19, 0.19, 0.05), rng=None,
-         chunk: int = 1 << 22):
-    """R-MAT by per-bit quadrant recursion, then random relabelling."""
+         chunk: int = 1 << 21, workers: int | None = None):
+    """R-MAT by per-bit quadrant recursion, then random relabelling.
+
+    Edge samples are drawn in chunks, each from its own generator seeded by
+    (a base seed drawn from rng, chunk index), so the graph depends only on
+    rng and not on how many threads draw the chunks.  Each bit of a sample
+    takes 32 random bits: quadrant (0,0) below a*2^32, (0,1) below
+    (a+b)*2^32, (1,0) below (a+b+c)*2^32, else (1,1)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     rng = np.random.default_rng(rng)
     n = 1 << scale
     total = edge_factor * n
     a, b, c, _ = abcd
-    keys = []
-    done = 0
-    while done < total:
-        cnt = min(chunk, total - done)
-        src = np.zeros(cnt, dtype=np.int64)
-        dst = np.zeros(cnt, dtype=np.int64)
-        for bit in range(scale):
-            r = rng.random(cnt)
-            # quadrant: a -> (0,0), b -> (0,1), c -> (1,0), d -> (1,1)
-            right = ((r >= a) & (r < a + b)) | (r >= a + b + c)
-            down = r >= a + b
-            src |= down.astype(np.int64) << bit
-            dst |= right.astype(np.int64) << bit
+    t_a = np.uint32(min(round(a * 2**32), 2**32 - 1))
+    t_ab = np.uint32(min(round((a + b) * 2**32), 2**32 - 1))
+    t_abc = np.uint32(min(round((a + b + c) * 2**32), 2**32 - 1))
+    base = int(rng.integers(0, 2**63))
+    counts = [min(chunk, total - s) for s in range(0, total, chunk)]
+
+    def draw(k):
+        cnt = counts[k]
+        g = np.random.default_rng([base, k])
+        src = np.zeros(cnt, dtype=np.uint32)
+        dst = np.zeros(cnt, dtype=np.uint32)
+        for bit in range(0, scale, 2):
+            raw = g.bit_generator.random_raw(cnt)
+            for half, bb in ((raw & 0xFFFFFFFF, bit), (raw >> 32, bit + 1)):
+                if bb >= scale:
+                    break
+                r = half.astype(np.uint32)
+                down = r >= t_ab
+                right = (r >= t_abc) | ((r >= t_a) & ~down)
+                src |= down.astype(np.uint32) << np.uint32(bb)
+                dst |= right.astype(np.uint32) << np.uint32(bb)
         keep = src != dst
         src, dst = src[keep], dst[keep]
-        lo = np.minimum(src, dst)
-        hi = np.maximum(src, dst)
-        keys.append(np.unique(lo * n + hi))
-        done += cnt
+        lo = np.minimum(src, dst).astype(np.int64)
+        hi = np.maximum(src, dst).astype(np.int64)
+        return np.unique(lo * n + hi)
+
+    import os
+
+    workers = workers or max(1, min(os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(workers) as ex:
+        keys = list(ex.map(draw, range(len(counts))))
     key = np.unique(np.concatenate(keys))
     perm = rng.permutation(n).astype(np.int64)
     u = perm[key // n]
@@ -205,14 +226,49 @@ def draw_weights(kind: str, m: int, rng) -> np.ndarray:
     raise ValueError(kind)
 
 
+def _stable_order(x: np.ndarray) -> np.ndarray:
+    """Stable argsort of non-negative integers below 2^32: two stable passes
+    on 16-bit digits (numpy sorts 16-bit keys by radix)."""
+    o = np.argsort((x & 0xFFFF).astype(np.uint16), kind="stable")
+    if x.size and int(x.max()) >= 1 << 16:
+        o = o[np.argsort((x[o] >> 16).astype(np.uint16), kind="stable")]
+    return o
+
+
 def to_csr(n: int, u: np.ndarray, v: np.ndarray, w: np.ndarray):
     """Symmetric CSR (rowptr uint64[n+1], col uint32, w float64), rows
     ascending by neighbour id."""
     u = np.asarray(u, dtype=np.int64)
     v = np.asarray(v, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    m = u.size
+    key = u * n + v
+    if m and np.all(u < v) and np.all(key[1:] > key[:-1]):
+        # canonical edges sorted by (u, v): row r is its smaller neighbours
+        # (edges (x, r), in the order of x) followed by its larger ones
+        # (edges (r, y), already in the order of y)
+        lower = np.bincount(v, minlength=n)  # neighbours below r
+        upper = np.bincount(u, minlength=n)  # neighbours above r
+        rowptr = np.zeros(n + 1, dtype=np.uint64)
+        rowptr[1:] = np.cumsum(lower + upper, dtype=np.uint64)
+        start = rowptr[:-1].astype(np.int64)
+        col = np.empty(2 * m, dtype=np.uint32)
+        ww = np.empty(2 * m, dtype=np.float64)
+        idx = np.arange(m, dtype=np.int64)
+        first_u = np.cumsum(upper) - upper  # first edge (r, .) in input order
+        pos = start[u] + lower[u] + (idx - first_u[u])
+        col[pos] = v
+        ww[pos] = w
+        o = _stable_order(v)  # by v, then u (input order)
+        vs = v[o]
+        first_v = np.cumsum(lower) - lower
+        pos = start[vs] + (idx - first_v[vs])
+        col[pos] = u[o]
+        ww[pos] = w[o]
+        return rowptr, col, ww
     src = np.concatenate([u, v])
     dst = np.concatenate([v, u])
-    ww = np.concatenate([w, w]).astype(np.float64)
+    ww = np.concatenate([w, w])
     order = np.lexsort((dst, src))
     src, dst, ww = src[order], dst[order], ww[order]
     counts = np.bincount(src, minlength=n)
