@@ -56,7 +56,11 @@ typedef enum {
   DYG_E_DUPLICATE_IN_BATCH = -7, /* the same edge twice in one list             */
   DYG_E_H_NOT_SUBSET = -8,       /* init: a sparsifier edge not in G            */
   DYG_E_NOMEM = -9,              /* device or host allocation failed            */
-  DYG_E_DEVICE = -10             /* a HIP runtime call failed                   */
+  DYG_E_DEVICE = -10,            /* a HIP runtime call failed                   */
+  DYG_E_TOO_LARGE = -11,         /* dyg_apply_batch_dev_static: the batch needs
+                                    more than DYG_STATIC_SCRATCH_BYTES         */
+  DYG_E_BUSY = -12               /* dyg_apply_batch_dev_static: a batch not yet
+                                    synced holds the context or the static array */
 } dyg_status;
 
 enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
@@ -215,6 +219,34 @@ typedef struct {
  */
 int dyg_apply_batch_dev(dyg_ctx* ctx, const dyg_batch_dev* batch, void* stream);
 int dyg_sync(dyg_ctx* ctx);
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): dyg_apply_batch_dev
+ * without any allocation.  Same arguments, same results and the same
+ * asynchronous contract (dyg_sync reports the batch's status), but every
+ * per-batch working buffer (hash tables, H-addition slots, phase-4 lists,
+ * walker outcomes of the batched form, and the results when batch->results
+ * is NULL) lives in one static device array of DYG_STATIC_SCRATCH_BYTES per
+ * GPU, held by the library until the process ends, and the launch sequence
+ * is never captured into a graph.  The caller still owns the inputs and the
+ * results.
+ * Limits and errors:
+ *   DYG_E_TOO_LARGE  the batch's working memory exceeds the array (roughly
+ *                    64 B per insertion plus 100 B per deletion and step of
+ *                    its largest L, plus 24 B per walker in the batched form)
+ *   DYG_E_BUSY       this context still has a batch in flight (call dyg_sync
+ *                    first: completing a batch may grow a pool, which
+ *                    allocates), or another context on the same GPU has a
+ *                    static batch not yet synced (the array is shared by
+ *                    every context on that GPU and keeps the last batch's
+ *                    contents; the library clears what must start empty)
+ * Calls that overlap on one GPU would race for the array; the library
+ * refuses the second with DYG_E_BUSY instead.  dyg_sync and the pool growth
+ * it may do are outside this no-allocation promise.
+ */
+#define DYG_STATIC_SCRATCH_BYTES (64ull << 20)
+int dyg_apply_batch_dev_static(dyg_ctx* ctx, const dyg_batch_dev* batch, void* stream);
 
 /*
  * Canonical edge list of H (Algorithm 1 output H(t)) or of G: u < v, sorted by

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <cmath>
 #include <cstdio>
@@ -125,6 +126,48 @@ struct HostAdj {
 
 }  // namespace
 
+// Working memory of dyg_apply_batch_dev_static: one array in the library's
+// code object, so every GPU the library runs on holds its own copy for the
+// life of the process.  Host code never uses the array's name as an address
+// (on the host it names a stand-in, not device memory): the device address
+// of each GPU's copy comes from hipGetSymbolAddress, taken once per device
+// at dyg_init with that device current.
+constexpr size_t kStaticScratchBytes = DYG_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct StaticScratch {
+  std::mutex mu;
+  void* addr[kMaxDevices] = {};           // device address of each GPU's copy
+  hipError_t status[kMaxDevices] = {};    // result of the address lookup
+  bool looked_up[kMaxDevices] = {};
+  const dyg_ctx* owner[kMaxDevices] = {};  // context whose batch uses it until dyg_sync
+};
+
+StaticScratch& static_scratch() {
+  static StaticScratch s;
+  return s;
+}
+
+// Device address of `dev`'s copy of the array (dev must be current).
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  StaticScratch& s = static_scratch();
+  std::lock_guard<std::mutex> lock(s.mu);
+  if (!s.looked_up[dev]) {
+    void* p = nullptr;
+    s.status[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    s.addr[dev] = s.status[dev] == hipSuccess ? p : nullptr;
+    s.looked_up[dev] = true;
+  }
+  return s.addr[dev];
+}
+
+}  // namespace
+
 struct dyg_ctx {
   uint32_t n = 0;
   dyg_params params{};
@@ -176,6 +219,9 @@ struct dyg_ctx {
   unsigned long long tune_steps0 = 0;
   bool last_graph = false;  // the batch enqueued last ran as a captured graph
   HBuf pin_in, pin_out;
+  int device = 0;                  // the GPU the context lives on
+  void* static_scratch = nullptr;  // that GPU's copy of the static working memory
+  bool static_inflight = false;    // the batch in flight uses it
 };
 
 namespace {
@@ -421,6 +467,8 @@ extern "C" const char* dyg_error_string(int code) {
     case DYG_E_H_NOT_SUBSET: return "sparsifier edge not in the graph";
     case DYG_E_NOMEM: return "out of memory";
     case DYG_E_DEVICE: return "HIP runtime error";
+    case DYG_E_TOO_LARGE: return "batch needs more working memory than the static array holds";
+    case DYG_E_BUSY: return "static working memory or context busy with a batch not yet synced";
     default: return "unknown error";
   }
 }
@@ -490,10 +538,18 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
   }
   {
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+    if ((e = hipGetDevice(&dev)) != hipSuccess) {
+      (void)hipStreamDestroy(c->stream);
+      delete c;
+      return fail_hip(e);
+    }
+    c->device = dev;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         cus > 0)
       c->cus = static_cast<uint32_t>(cus);
+    // this GPU's copy of the static working memory (null if the lookup failed:
+    // dyg_apply_batch_dev_static then reports DYG_E_DEVICE)
+    c->static_scratch = scratch_address(dev);
   }
   if (params->flags & DYG_FLAG_AUTOTUNE) c->tune_next = 0;
   if (params->flags & (DYG_FLAG_TIMING | DYG_FLAG_TIMING_WALK | DYG_FLAG_AUTOTUNE))
@@ -589,14 +645,22 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
 namespace {
 
 // Size every staging buffer for a batch; returns DYG_OK or DYG_E_NOMEM.
-int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
-                    uint64_t walkers, uint64_t items_cap, uint64_t& hadd_cap,
-                    uint64_t& hash_slots) {
+// H-addition slots and hash-table size of a batch; false if the table would
+// exceed 2^31 slots.
+bool batch_table_sizes(uint64_t n_ins, uint64_t n_del, uint32_t Lcap, uint64_t& hadd_cap,
+                       uint64_t& hash_slots) {
   const uint64_t nu = n_ins + n_del;
   hadd_cap = n_ins + n_del * std::max<uint32_t>(Lcap, 2);
   const uint64_t keys = std::max<uint64_t>(nu, 2 * hadd_cap);
   hash_slots = next_pow2(2 * keys + 64);
-  if (hash_slots > (1ull << 31)) return DYG_E_NOMEM;
+  return hash_slots <= (1ull << 31);
+}
+
+int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
+                    uint64_t walkers, uint64_t items_cap, uint64_t& hadd_cap,
+                    uint64_t& hash_slots) {
+  const uint64_t nu = n_ins + n_del;
+  if (!batch_table_sizes(n_ins, n_del, Lcap, hadd_cap, hash_slots)) return DYG_E_NOMEM;
   bool ok = c->ins_qw.ensure(4 * n_ins + 8) && c->ins_rinv.ensure(8 * n_ins + 8) &&
             c->in_h.ensure(n_del + 8) && c->res.ensure(sizeof(dyg_update_result) * nu + 8) &&
             c->ubytes.ensure(4 * nu + 8) &&
@@ -689,6 +753,70 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
   return a;
 }
 
+// Bump allocation of 256-byte aligned pieces from a fixed region; `used`
+// counts every piece asked for, so it gives the size a batch needs even
+// when the region is too small (then ok is false).
+struct Carve {
+  char* base;
+  size_t cap;
+  size_t used = 0;
+  bool ok = true;
+  template <class T>
+  T* take(size_t bytes) {
+    const size_t at = (used + 255) & ~size_t(255);
+    used = at + bytes;
+    if (used > cap) ok = false;
+    return ok ? reinterpret_cast<T*>(base + at) : nullptr;
+  }
+};
+
+// Point every per-batch buffer of `a` into region `m`, with the sizes that
+// prepare_buffers gives the context's own buffers (no per-walker records).
+// own_results: the batch keeps its results in the region too.
+void carve_batch(const dyg_ctx* c, BatchArgs& a, Carve& m, uint64_t n_ins, uint64_t n_del,
+                 uint64_t items_cap, uint64_t hadd_cap, uint64_t hash_slots, bool own_results) {
+  const uint64_t nu = n_ins + n_del;
+  a.ins_qw = m.take<uint32_t>(4 * n_ins + 8);
+  a.ins_rinv = m.take<double>(8 * n_ins + 8);
+  a.in_h = m.take<uint8_t>(n_del + 8);
+  if (own_results) a.res = m.take<dyg::UpdRes>(sizeof(dyg_update_result) * nu + 8);
+  a.ubytes = m.take<uint32_t>(4 * nu + 8);
+  a.hadd = m.take<AddRec>(sizeof(AddRec) * hadd_cap + 8);
+  a.hash = m.take<HashSlot>(sizeof(HashSlot) * hash_slots);
+  a.hash2 = m.take<HashSlot>(sizeof(HashSlot) * hash_slots);
+  a.wrec = nullptr;
+  a.wofs = nullptr;
+  if (c->params.flags & DYG_FLAG_BATCHED) {
+    const uint64_t tiles = (nu + 1023) / 1024 + 1;
+    a.qcount = m.take<uint32_t>(4 * nu + 8);
+    a.qofs = m.take<unsigned long long>(8 * nu + 8);
+    a.qtile = m.take<unsigned long long>(8 * tiles + 8);
+    a.items = c->updates_per_wave > 0 ? nullptr
+                                      : m.take<dyg::WalkItem>(sizeof(dyg::WalkItem) * items_cap + 8);
+    a.wres = m.take<dyg::WalkOut>(sizeof(dyg::WalkOut) * items_cap + 16);
+    a.tstate = c->tail_lanes == 0 ? nullptr
+                                  : m.take<dyg::TailState>(sizeof(dyg::TailState) * items_cap + 16);
+    a.tcount = c->tail_lanes == 0 ? nullptr : m.take<uint32_t>(4 * nu + 8);
+  } else {
+    a.qcount = nullptr;
+    a.qofs = nullptr;
+    a.qtile = nullptr;
+    a.items = nullptr;
+    a.wres = nullptr;
+    a.tstate = nullptr;
+    a.tcount = nullptr;
+  }
+  for (int g = 0; g < 2; ++g) {
+    const uint64_t cap = g == 0 ? 2 * n_ins : 2 * hadd_cap;
+    a.touched_rows[g] = m.take<uint32_t>(4 * cap + 8);
+    a.touched_k[g] = m.take<uint32_t>(4 * cap + 8);
+    a.touched_need[g] = m.take<uint32_t>(4 * cap + 8);
+    a.add_keep[g] = m.take<uint8_t>(cap + 8);
+    a.dirty_rows[g] = m.take<uint32_t>(4 * (cap + 2 * n_del) + 8);
+    a.wide_rows[g] = m.take<uint32_t>(4 * cap + 8);
+  }
+}
+
 // Whether the plain walk kernel reads rows cooperatively: insertions walk H,
 // deletions walk G; worthwhile when at least 40% of the walks start in a
 // graph whose rows are mostly pool rows (by the initial degrees).
@@ -772,10 +900,12 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
 }
 
 // Enqueue one batch: copy its arguments to the device, then its launch
-// sequence (directly, or as the captured graph of its size class).
+// sequence (directly, or as the captured graph of its size class; capturing
+// and instantiating a graph allocates, so allow_graph = false launches
+// directly whatever the flags say).
 bool tuning_now(const dyg_ctx* c);
 
-int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a) {
+int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a, bool allow_graph = true) {
   const bool timed = c->ev[0] != nullptr;
   // the batch itself is bracketed only under DYG_FLAG_TIMING
   const bool timed_batch = timed && (c->params.flags & DYG_FLAG_TIMING);
@@ -783,7 +913,7 @@ int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a) {
   if (timed_batch) (void)hipEventRecord(c->ev[0], c->stream);
   e = hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return fail_hip(e);
-  c->last_graph = (c->params.flags & DYG_FLAG_GRAPH) && !tuning_now(c);
+  c->last_graph = allow_graph && (c->params.flags & DYG_FLAG_GRAPH) && !tuning_now(c);
   if (c->last_graph) {
     hipGraphExec_t exec = nullptr;
     int rc = graph_for(c, a, &exec);
@@ -1063,8 +1193,71 @@ extern "C" int dyg_apply_batch_dev(dyg_ctx* c, const dyg_batch_dev* b, void* str
   return DYG_OK;
 }
 
+extern "C" int dyg_apply_batch_dev_static(dyg_ctx* c, const dyg_batch_dev* b, void* stream) {
+  if (!c || !b) return DYG_E_INVALID_ARG;
+  if (c->broken) return DYG_E_NOMEM;
+  const uint64_t n_ins = b->n_ins, n_del = b->n_del, nu = n_ins + n_del;
+  if ((n_ins && (!b->iu || !b->iv || !b->iw)) || (n_del && (!b->du || !b->dv)) ||
+      nu >= (1ull << 30) || b->L_max > DYG_MAX_STEPS || (b->s && b->s_max > DYG_MAX_WALKERS))
+    return DYG_E_INVALID_ARG;
+  // completing an earlier batch may grow a pool, which allocates: the caller
+  // does that with dyg_sync before this call
+  if (c->async_inflight) return DYG_E_BUSY;
+  if (!c->static_scratch) return DYG_E_DEVICE;
+  const uint32_t Lcap = std::max<uint32_t>(b->L ? b->L_max : c->params.L_default, 2);
+  const uint32_t scap = b->s ? b->s_max : c->params.s_default;
+  uint64_t hadd_cap, hash_slots;
+  if (!batch_table_sizes(n_ins, n_del, Lcap, hadd_cap, hash_slots)) return DYG_E_TOO_LARGE;
+  StaticScratch& ss = static_scratch();
+  std::lock_guard<std::mutex> lock(ss.mu);
+  if (ss.owner[c->device]) return DYG_E_BUSY;  // another context's batch is not synced yet
+  tune_begin(c, c->hctl->steps_total);
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  std::swap(st, c->stream);  // every launcher below runs on the caller's stream
+  BatchArgs& a = make_args(c, n_ins, n_del, b->iu, b->iv, b->iw, b->du, b->dv, b->s, b->L, Lcap,
+                          hadd_cap, hash_slots,
+                          reinterpret_cast<dyg::UpdRes*>(b->results), false);
+  a.scap = scap;
+  Carve m{static_cast<char*>(c->static_scratch), kStaticScratchBytes};
+  carve_batch(c, a, m, n_ins, n_del, nu * scap, hadd_cap, hash_slots, b->results == nullptr);
+  int prc = m.ok ? enqueue_pipeline(c, a, false) : DYG_E_TOO_LARGE;
+  std::swap(st, c->stream);
+  if (prc) return prc;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_hip(e);
+  ss.owner[c->device] = c;
+  c->static_inflight = true;
+  c->async_inflight = true;
+  c->async_nu = nu;
+  c->pending_status = DYG_OK;
+  return DYG_OK;
+}
+
+namespace {
+
+// The static working memory of c's GPU is free again (c's batch has ended).
+void release_static(dyg_ctx* c) {
+  if (!c->static_inflight) return;
+  StaticScratch& s = static_scratch();
+  std::lock_guard<std::mutex> lock(s.mu);
+  if (s.owner[c->device] == c) s.owner[c->device] = nullptr;
+  c->static_inflight = false;
+}
+
+int sync_batch(dyg_ctx* c);
+
+}  // namespace
+
 extern "C" int dyg_sync(dyg_ctx* c) {
   if (!c) return DYG_E_INVALID_ARG;
+  const int rc = sync_batch(c);
+  release_static(c);  // after any pool repair, which reads the batch's staged additions
+  return rc;
+}
+
+namespace {
+
+int sync_batch(dyg_ctx* c) {
   if (!c->async_inflight) return DYG_OK;  // a batch's status is reported once
   c->async_inflight = false;
   BatchCtl ctl;
@@ -1086,6 +1279,8 @@ extern "C" int dyg_sync(dyg_ctx* c) {
   c->batches++;
   return c->pending_status = maybe_compact(c);
 }
+
+}  // namespace
 
 namespace {
 
@@ -1390,6 +1585,11 @@ extern "C" int dyg_compact(dyg_ctx* c) {
 extern "C" void dyg_destroy(dyg_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->static_inflight) {
+    // a batch on a caller stream may still use the static working memory
+    (void)hipEventSynchronize(c->done_ev);
+    release_static(c);
+  }
   free_graph(c->G);
   free_graph(c->H);
   if (c->ctl) (void)hipFree(c->ctl);

@@ -29,7 +29,11 @@ STATUS = {
     -8: "H_NOT_SUBSET",
     -9: "NOMEM",
     -10: "DEVICE",
+    -11: "TOO_LARGE",
+    -12: "BUSY",
 }
+
+STATIC_SCRATCH_BYTES = 64 << 20  # the static working memory of dyg_apply_batch_dev_static
 
 FLAG_LEAN_POOLS = 1
 FLAG_TIMING = 2
@@ -97,6 +101,7 @@ class dyg_request_done(C.Structure):
 
 
 EXPORTS = ["dyg_default_params", "dyg_init", "dyg_apply_batch", "dyg_apply_batch_dev",
+           "dyg_apply_batch_dev_static",
            "dyg_sync", "dyg_query_sparsifier", "dyg_query_graph", "dyg_stats", "dyg_compact",
            "dyg_destroy", "dyg_error_string", "dyg_get_tuning", "dyg_set_tuning", "dyg_reserve",
            "dyg_check_state", "dyg_server_default_params", "dyg_server_create",
@@ -133,6 +138,8 @@ def _load():
     lib.dyg_apply_batch.restype = C.c_int
     lib.dyg_apply_batch_dev.argtypes = [P, C.POINTER(dyg_batch_dev), P]
     lib.dyg_apply_batch_dev.restype = C.c_int
+    lib.dyg_apply_batch_dev_static.argtypes = [P, C.POINTER(dyg_batch_dev), P]
+    lib.dyg_apply_batch_dev_static.restype = C.c_int
     lib.dyg_sync.argtypes = [P]
     lib.dyg_sync.restype = C.c_int
     for fn in (lib.dyg_query_sparsifier, lib.dyg_query_graph):
@@ -299,11 +306,7 @@ def check_dev_batch(iu, iv, iw, du, dv, s=None, L=None, results=None, on_gpu=Tru
             raise ValueError("results must be in GPU memory")
 
 
-def dyg_apply_batch_dev(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, s_max=0,
-                        results=None, stream=None):
-    """Device-resident batch: iu, iv, iw, du, dv are torch tensors on the GPU
-    (checked by check_dev_batch); s, L and results are tensors or raw device
-    addresses as ints; stream is a torch stream or a raw handle."""
+def _dev_batch(iu, iv, iw, du, dv, s, L, L_max, s_max, results, stream):
     check_dev_batch(iu, iv, iw, du, dv, s=s, L=L, results=results)
 
     def addr(t):
@@ -320,7 +323,26 @@ def dyg_apply_batch_dev(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, s_max=
     handle = None
     if stream is not None:
         handle = stream if isinstance(stream, int) else stream.cuda_stream
+    return b, handle
+
+
+def dyg_apply_batch_dev(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, s_max=0,
+                        results=None, stream=None):
+    """Device-resident batch: iu, iv, iw, du, dv are torch tensors on the GPU
+    (checked by check_dev_batch); s, L and results are tensors or raw device
+    addresses as ints; stream is a torch stream or a raw handle."""
+    b, handle = _dev_batch(iu, iv, iw, du, dv, s, L, L_max, s_max, results, stream)
     _check(_lib.dyg_apply_batch_dev(ctx, C.byref(b), handle), "dyg_apply_batch_dev")
+
+
+def dyg_apply_batch_dev_static(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0, s_max=0,
+                               results=None, stream=None):
+    """dyg_apply_batch_dev whose working memory is the library's static device
+    array (no allocation); the same arguments.  Sync the context's previous
+    batch first."""
+    b, handle = _dev_batch(iu, iv, iw, du, dv, s, L, L_max, s_max, results, stream)
+    _check(_lib.dyg_apply_batch_dev_static(ctx, C.byref(b), handle),
+           "dyg_apply_batch_dev_static")
 
 
 def dyg_sync(ctx):
