@@ -119,10 +119,46 @@ struct HostAdj {
   std::vector<Row> rows;
   std::vector<Ent> ent;                 // pool
   std::vector<double> w;                // pool weights
-  std::vector<unsigned long long> pfx;  // inclusive qw prefix of long segments
+  std::vector<unsigned long long> pfx;   // weight tree level 0 of long segments
+  std::vector<unsigned long long> tree;  // weight tree levels 1.. of long segments
   std::vector<double> rinl;             // 1/w of inline entries, kInline per row
   std::vector<double> winl;             // weights of inline entries, kInline per row
 };
+
+// Weight tree of one long segment of len entries (layout in dyg_internal.h):
+// level 0 into l0[0 .. round_fan(len)), levels 1.. into tb.
+void build_tree_host(const Ent* seg, uint32_t len, unsigned long long* l0,
+                     unsigned long long* tb) {
+  const uint32_t K = dyg::tree_top(len);
+  std::vector<unsigned long long> raw(len), up;
+  unsigned long long total = 0;
+  for (uint32_t i = 0; i < len; ++i) {
+    raw[i] = seg[i].qw;
+    total += seg[i].qw;
+  }
+  for (uint32_t l = 0; l <= K; ++l) {
+    const uint32_t n = static_cast<uint32_t>(raw.size());
+    unsigned long long* dst = l == 0 ? l0 : tb + dyg::tree_base(len, l);
+    up.assign((n + dyg::kFan - 1) / dyg::kFan, 0ull);
+    unsigned long long run = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      run += raw[i];
+      dst[i] = run;
+      if (i % dyg::kFan == dyg::kFan - 1 || i == n - 1) {
+        up[i / dyg::kFan] = run;
+        run = 0;
+      }
+    }
+    for (uint32_t i = n; i < dyg::round_fan(n); ++i) dst[i] = dyg::kTreePad;
+    if (l == K) dst[dyg::kFan - 1] = total;
+    raw.swap(up);
+  }
+}
+
+// Pool slots a long segment of len entries starts at: a multiple of kHubAlign.
+uint64_t hub_aligned(uint64_t off) {
+  return (off + dyg::kHubAlign - 1) / dyg::kHubAlign * dyg::kHubAlign;
+}
 
 }  // namespace
 
@@ -234,6 +270,7 @@ void free_graph(DevGraph& X) {
   if (X.w) (void)hipFree(X.w);
   if (X.pending) (void)hipFree(X.pending);
   if (X.pfx) (void)hipFree(X.pfx);
+  if (X.tree) (void)hipFree(X.tree);
   if (X.mark) (void)hipFree(X.mark);
   if (X.rinl) (void)hipFree(X.rinl);
   if (X.winl) (void)hipFree(X.winl);
@@ -252,6 +289,8 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (e = hipMalloc(&Y.w, sizeof(double) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.pending, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.pfx, sizeof(unsigned long long) * std::max<uint64_t>(pool_cap, 1))) !=
+          hipSuccess ||
+      (e = hipMalloc(&Y.tree, sizeof(unsigned long long) * (pool_cap / 4 + dyg::kFan))) !=
           hipSuccess ||
       (e = hipMalloc(&Y.mark, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.rinl, sizeof(double) * kInline * std::max<uint64_t>(n, 1))) !=
@@ -272,6 +311,9 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (!A.pfx.empty() &&
        (e = hipMemcpyAsync(Y.pfx, A.pfx.data(), sizeof(unsigned long long) * A.pfx.size(),
                            hipMemcpyHostToDevice, st)) != hipSuccess) ||
+      (!A.tree.empty() &&
+       (e = hipMemcpyAsync(Y.tree, A.tree.data(), sizeof(unsigned long long) * A.tree.size(),
+                           hipMemcpyHostToDevice, st)) != hipSuccess) ||
       (e = hipMemcpyAsync(Y.rinl, A.rinl.data(), sizeof(double) * A.rinl.size(),
                           hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemcpyAsync(Y.winl, A.winl.data(), sizeof(double) * A.winl.size(),
@@ -289,19 +331,37 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
 
 // Lay out the rows for the given per-row live lists: at most kInline entries
 // inside the row, longer lists in a pool segment with slack.
+// A long segment (more than kHub entries) starts at a multiple of kHubAlign
+// and owns a multiple of kFan slots, as its weight tree needs.
+uint32_t segment_cap(uint32_t len, double slack) {
+  const uint32_t cap = len + slack_slots(len, slack);
+  return len > dyg::kHub ? dyg::round_fan(cap) : cap;
+}
+
 void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
             const std::vector<Ent>& live_ent, const std::vector<double>& live_w, double slack) {
   A.rows.assign(n, Row{});
   A.rinl.assign(static_cast<size_t>(n) * kInline, 0.0);
   A.winl.assign(static_cast<size_t>(n) * kInline, 0.0);
   A.pfx.clear();
+  A.tree.clear();
   uint64_t total = 0;
+  bool hubs = false;
   for (uint32_t u = 0; u < n; ++u) {
     const uint32_t len = static_cast<uint32_t>(start[u + 1] - start[u]);
-    if (len > kInline) total += len + slack_slots(len, slack);
+    if (len <= kInline) continue;
+    if (len > dyg::kHub) {
+      total = hub_aligned(total);
+      hubs = true;
+    }
+    total += segment_cap(len, slack);
   }
   A.ent.assign(total, Ent{0, 0, 0.0});
   A.w.assign(total, 0.0);
+  if (hubs) {
+    A.pfx.assign(total, dyg::kTreePad);
+    A.tree.assign(total / 4 + dyg::kFan, dyg::kTreePad);
+  }
   uint64_t off = 0;
   for (uint32_t u = 0; u < n; ++u) {
     const uint32_t len = static_cast<uint32_t>(start[u + 1] - start[u]);
@@ -315,18 +375,12 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
       }
       continue;
     }
-    const uint32_t cap = len + slack_slots(len, slack);
+    if (len > dyg::kHub) off = hub_aligned(off);
+    const uint32_t cap = segment_cap(len, slack);
     A.rows[u].h = RowHdr{static_cast<uint32_t>(off), len, cap, 0};
     std::copy(live_ent.begin() + start[u], live_ent.begin() + start[u + 1], A.ent.begin() + off);
     std::copy(live_w.begin() + start[u], live_w.begin() + start[u + 1], A.w.begin() + off);
-    if (len > dyg::kHub) {
-      if (A.pfx.empty()) A.pfx.assign(total, 0ull);
-      unsigned long long run = 0;
-      for (uint32_t i = 0; i < len; ++i) {
-        run += A.ent[off + i].qw;
-        A.pfx[off + i] = run;
-      }
-    }
+    if (len > dyg::kHub) build_tree_host(&A.ent[off], len, &A.pfx[off], &A.tree[off / 4]);
     off += cap;
   }
 }
@@ -1385,7 +1439,7 @@ struct HostImage {
   std::vector<Row> rows;
   std::vector<Ent> ent;
   std::vector<double> w;
-  std::vector<unsigned long long> pfx;
+  std::vector<unsigned long long> pfx, tree;
   std::vector<double> rinl, winl;
   Ent get(uint32_t u, uint32_t i) const {
     if (rows[u].h.off != kInlineOff) return ent[rows[u].h.off + i];
@@ -1403,6 +1457,7 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
   I.ent.resize(used);
   I.w.resize(used);
   I.pfx.resize(used);
+  I.tree.resize(used / 4 + dyg::kFan);
   I.rinl.resize(static_cast<size_t>(n) * kInline);
   I.winl.resize(static_cast<size_t>(n) * kInline);
   hipError_t e = hipMemcpyAsync(I.rows.data(), X.rows, sizeof(Row) * n, hipMemcpyDeviceToHost, st);
@@ -1418,6 +1473,9 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
     e = hipMemcpyAsync(I.w.data(), X.w, sizeof(double) * used, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && used)
     e = hipMemcpyAsync(I.pfx.data(), X.pfx, sizeof(unsigned long long) * used,
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(I.tree.data(), X.tree, sizeof(unsigned long long) * I.tree.size(),
                        hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   return e == hipSuccess ? DYG_OK : fail_hip(e);
@@ -1475,16 +1533,24 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
         return fail("segment beyond pool top", g, u, r.off);
       if (!inl && r.cap) spans.push_back({r.off, static_cast<uint64_t>(r.off) + r.cap});
       uint32_t dead = 0;
-      unsigned long long run = 0;
       for (uint32_t i = 0; i < r.len; ++i) {
         const Ent e = I.get(u, i);
         if (e.nbr >= c->n || e.nbr == u) return fail("bad neighbour id", g, u, i);
         if (i && I.get(u, i - 1).nbr >= e.nbr) return fail("segment not sorted", g, u, i);
         if (e.qw == 0u) ++dead;
-        run += e.qw;
-        if (!inl && r.len > dyg::kHub && I.pfx[r.off + i] != run)
-          return fail("stale weight prefix", g, u, i);
         if (e.qw != 0u && !(e.rinv == 1.0 / I.wt(u, i))) return fail("1/w mismatch", g, u, i);
+      }
+      if (!inl && r.len > dyg::kHub) {
+        // the weight tree: placement, then every value of every level
+        if (r.off % dyg::kHubAlign != 0 || r.cap % dyg::kFan != 0)
+          return fail("long segment not aligned for its weight tree", g, u, r.off);
+        const uint32_t K = dyg::tree_top(r.len);
+        std::vector<unsigned long long> l0(dyg::round_fan(r.len)), tb(dyg::tree_base(r.len, K + 1));
+        build_tree_host(&I.ent[r.off], r.len, l0.data(), tb.data());
+        for (uint32_t i = 0; i < l0.size(); ++i)
+          if (I.pfx[r.off + i] != l0[i]) return fail("stale weight tree level 0", g, u, i);
+        for (uint32_t i = 0; i < tb.size(); ++i)
+          if (I.tree[r.off / 4 + i] != tb[i]) return fail("stale weight tree level >= 1", g, u, i);
       }
       if (dead != r.dead) {
         if (msg && msg_len)

@@ -53,8 +53,8 @@ static_assert(sizeof(Ent) == 16, "Ent layout");
 static_assert(sizeof(Row) == 64, "Row layout");
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-// Segments longer than this keep an inclusive prefix of their quantised
-// weights, so a walker picks a neighbour by binary search instead of a scan.
+// Segments longer than this keep a weight tree (below), so a walker picks a
+// neighbour with a few block reads instead of a scan.
 constexpr uint32_t kHub = 64;
 constexpr uint32_t kMaxWalkers = 1024;
 constexpr uint32_t kMaxSteps = 1024;
@@ -64,6 +64,47 @@ constexpr uint32_t kMaxUpw = 8;  // updates per wavefront of the range walk
 constexpr uint32_t kHeavyQw = 1u << 29;
 
 
+// ---------------------------------------------------------------------------
+// Weight tree of a long segment (len > kHub).  Such a segment starts at a
+// pool offset that is a multiple of kHubAlign and owns a multiple of kFan
+// slots.  Level 0 is pfx[off + i] (i < len): the running sum of the quantised
+// weights over entry i's block of kFan entries, from the block's first entry
+// to i.  Level l >= 1 has tree_n(len, l) values; value b is the running sum,
+// over b's block of kFan values, of the totals of the level-(l-1) blocks
+// (block b of level l-1 = values kFan*b .. kFan*b + kFan-1).  Levels 1.. are
+// stored one after another from tree[off / 4] (tree_base gives each level's
+// start), each padded to a multiple of kFan values.  The top level
+// tree_top(len) is the first with at most kFan values; slot kFan-1 of its one
+// block holds the segment total.  Every other slot past a level's last value
+// (level 0 included, up to the next multiple of kFan) holds kTreePad.
+// A walker finds the entry whose running total first exceeds a target with
+// one kFan-value (128-byte) read per level; changing one entry's weight adds
+// the difference to the rest of its block on every level.
+constexpr uint32_t kFan = 16;
+constexpr uint32_t kHubAlign = 64;           // pool offset alignment of long segments
+constexpr unsigned long long kTreePad = ~0ull;
+
+__host__ __device__ inline uint32_t round_fan(uint32_t x) { return (x + kFan - 1) & ~(kFan - 1); }
+
+// Levels above level 0 (len > kFan).
+__host__ __device__ inline uint32_t tree_top(uint32_t len) {
+  uint32_t bits = 0;
+  for (uint32_t x = len - 1; x; x >>= 1) ++bits;  // bits of len - 1
+  return (bits + 3) / 4 - 1;
+}
+
+// Values on level l.
+__host__ __device__ inline uint32_t tree_n(uint32_t len, uint32_t l) {
+  return ((len - 1) >> (4 * l)) + 1;
+}
+
+// Start of level l >= 1 within the segment's tree slots (tree + off / 4).
+__host__ __device__ inline uint32_t tree_base(uint32_t len, uint32_t l) {
+  uint32_t b = 0;
+  for (uint32_t m = 1; m < l; ++m) b += round_fan(tree_n(len, m));
+  return b;
+}
+
 struct DevGraph {
   Row* rows = nullptr;        // [n] 64-byte rows
   Ent* ent = nullptr;         // [pool_cap]
@@ -71,7 +112,8 @@ struct DevGraph {
   double* rinl = nullptr;     // [n * kInline] 1/w of each inline entry
   double* winl = nullptr;     // [n * kInline] weight of each inline entry (cold)
   uint32_t* pending = nullptr;  // [n] per-row counter, zero between batches
-  unsigned long long* pfx = nullptr;  // [pool_cap] inclusive qw prefix (rows with len > kHub)
+  unsigned long long* pfx = nullptr;  // [pool_cap] weight tree level 0 (rows with len > kHub)
+  unsigned long long* tree = nullptr; // [pool_cap / 4 + kFan] weight tree levels 1.. of the same
   uint32_t* mark = nullptr;     // [n] "prefix needs rebuilding" flag, zero between uses
   uint64_t pool_cap = 0;      // entries
 };
@@ -146,8 +188,7 @@ struct BatchCtl {
   uint32_t touched[2];          // touched rows, per graph (0 = G, 1 = H)
   unsigned long long need[2];   // pool slots needed by relocations, per graph
   uint32_t nomem[2];            // phase-4 pool shortfall, per graph
-  uint32_t dirty[2];            // rows whose prefix must be rebuilt, per graph
-  uint32_t dirty_p1[2];         // of those, the ones listed by phase 1
+  uint32_t dirty[2];            // rows whose weight tree must be rebuilt, per graph
   uint32_t wide[2];             // touched rows moved or merged by a workgroup, per graph
   uint32_t hubs;                // set when phase 4 leaves a row longer than kHub
   unsigned long long pool_top[2];  // next free pool slot, per graph

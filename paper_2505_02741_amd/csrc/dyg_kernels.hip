@@ -73,6 +73,7 @@ __device__ __forceinline__ void load_graph(DevGraph& X, gptr<const BatchArgs> ap
   X.winl = load_gptr(&ap->g[w].winl);
   X.pending = load_gptr(&ap->g[w].pending);
   X.pfx = load_gptr(&ap->g[w].pfx);
+  X.tree = load_gptr(&ap->g[w].tree);
   X.mark = load_gptr(&ap->g[w].mark);
 }
 
@@ -217,6 +218,84 @@ __device__ __forceinline__ bool has_live(const DevGraph& X, uint32_t a, uint32_t
   return k >= 0 && seg.qw(k) != 0u;
 }
 
+// ---- weight trees of long segments ---------------------------------------------
+// (layout in dyg_internal.h)
+
+// The kFan values of one tree block (128 bytes, 16-byte aligned).
+__device__ __forceinline__ void tree_block(const unsigned long long* p, unsigned long long v[kFan]) {
+  const ulonglong2* p2 = reinterpret_cast<const ulonglong2*>(p);
+#pragma unroll
+  for (uint32_t j = 0; j < kFan / 2; ++j) {
+    const ulonglong2 x = p2[j];
+    v[2 * j] = x.x;
+    v[2 * j + 1] = x.y;
+  }
+}
+
+// Child of a block for residual target r: the number of its values at or
+// below r (they never decrease along the block, and padding never counts);
+// r becomes the residual within that child.
+__device__ __forceinline__ uint32_t tree_child(const unsigned long long v[kFan],
+                                               unsigned long long& r) {
+  uint32_t c = 0;
+  unsigned long long below = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kFan; ++j) {
+    const bool le = v[j] <= r;
+    c += le ? 1u : 0u;
+    below = le ? v[j] : below;
+  }
+  r -= below;
+  return c;
+}
+
+// Number of values of a block at or below r.
+__device__ __forceinline__ uint32_t tree_count(const unsigned long long v[kFan],
+                                               unsigned long long r) {
+  uint32_t c = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kFan; ++j) c += v[j] <= r ? 1u : 0u;
+  return c;
+}
+
+// First entry of a long segment whose running weight total exceeds t
+// (t < the segment total): one block per level, top to bottom.
+__device__ __forceinline__ uint32_t tree_find(const unsigned long long* lvl0,
+                                              const unsigned long long* tb, uint32_t len,
+                                              unsigned long long t) {
+  const uint32_t K = tree_top(len);
+  unsigned long long v[kFan];
+  uint32_t node = 0;
+  for (uint32_t l = K; l >= 1; --l) {
+    tree_block(tb + tree_base(len, l) + kFan * node, v);
+    node = kFan * node + tree_child(v, t);
+  }
+  tree_block(lvl0 + kFan * node, v);
+  return kFan * node + tree_child(v, t);
+}
+
+// Add `delta` (two's complement) to every tree value that covers entry k of
+// the long segment at `off` with `len` entries: the rest of k's block on
+// every level, and the total in the top block.  Atomic, so concurrent
+// changes to one segment commute.
+__device__ void tree_add(const DevGraph& X, uint32_t off, uint32_t len, uint32_t k,
+                         unsigned long long delta) {
+  unsigned long long* l0 = X.pfx + off;
+  const uint32_t end0 = ((k | (kFan - 1)) + 1) < len ? ((k | (kFan - 1)) + 1) : len;
+  for (uint32_t j = k; j < end0; ++j) atomicAdd(&l0[j], delta);
+  const uint32_t K = tree_top(len);
+  unsigned long long* tb = X.tree + (off >> 2);
+  uint32_t b = k;
+  for (uint32_t l = 1; l <= K; ++l) {
+    b >>= 4;
+    const uint32_t n = tree_n(len, l);
+    unsigned long long* lv = tb + tree_base(len, l);
+    const uint32_t end = ((b | (kFan - 1)) + 1) < n ? ((b | (kFan - 1)) + 1) : n;
+    for (uint32_t j = b; j < end; ++j) atomicAdd(&lv[j], delta);
+    if (l == K && n < kFan) atomicAdd(&lv[kFan - 1], delta);  // the segment total
+  }
+}
+
 // ---- hash table (validation duplicates, phase-4 dedup) ---------------------
 
 __device__ __forceinline__ uint32_t hash_home(unsigned long long key, uint32_t mask) {
@@ -288,7 +367,6 @@ __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
       ctl->need[w] = 0;
       ctl->nomem[w] = 0;
       ctl->dirty[w] = 0;
-      ctl->dirty_p1[w] = 0;
       ctl->wide[w] = 0;
     }
   }
@@ -377,24 +455,18 @@ __global__ void k_validate_b(const BatchArgs* const* __restrict__ argv) {
 
 // ---- phase 1 -------------------------------------------------------------------
 
-// Queue row r of graph `which` for a prefix rebuild (once per batch phase).
-__device__ __forceinline__ void mark_dirty(const BatchArgs& a, const DevGraph& X, int which,
-                                           uint32_t r) {
-  if (atomicExch(&X.mark[r], 1u) == 0u) {
-    const uint32_t t = atomicAdd(&a.ctl->dirty[which], 1u);
-    a.dirty_rows[which][t] = r;
-  }
-}
-
-__device__ __forceinline__ void tombstone(const BatchArgs& a, const DevGraph& X, int which,
-                                          uint32_t u, uint32_t v) {
+// A deleted edge becomes a tombstone in row u (weight 0; a long segment's
+// weight tree loses its weight).
+__device__ __forceinline__ void tombstone(const DevGraph& X, uint32_t u, uint32_t v) {
   const RowHdr h = row_hdr(X, u);
   const Seg seg = seg_of(X, u, h.off);
   const int k = find_nbr(seg, h.len, v);
   if (k < 0) return;
+  const uint32_t old = seg.qw(k);  // each edge is deleted once per batch
   seg.qw(k) = 0u;
   atomicAdd(&row_hdr_ref(X, u).dead, 1u);
-  if (h.len > kHub) mark_dirty(a, X, which, u);
+  if (h.len > kHub)
+    tree_add(X, h.off, h.len, static_cast<uint32_t>(k), 0ull - static_cast<unsigned long long>(old));
 }
 
 __global__ void k_phase1(const BatchArgs* const* __restrict__ argv) {
@@ -406,25 +478,30 @@ __global__ void k_phase1(const BatchArgs* const* __restrict__ argv) {
   if (j >= a.n_del) return;
   const uint32_t u = a.du[j], v = a.dv[j];
   const bool in_h = has_live(H, u, v);
-  tombstone(a, G, 0, u, v);
-  tombstone(a, G, 0, v, u);
+  tombstone(G, u, v);
+  tombstone(G, v, u);
   if (in_h) {
-    tombstone(a, H, 1, u, v);
-    tombstone(a, H, 1, v, u);
+    tombstone(H, u, v);
+    tombstone(H, v, u);
   }
   a.in_h[j] = in_h ? 1 : 0;
 }
 
-// Block-wide inclusive scan helper over 64-bit values (kBlock threads).
-__device__ unsigned long long block_excl_scan(unsigned long long v, unsigned long long& excl);
+// Rebuild the weight tree (level 0 in pfx, levels 1.. in tree) of every long
+// segment listed dirty by phase 4 (merged or relocated), one workgroup per
+// segment, then clear its mark.  A chunk of kTreeChunk = 16^3 entries fills
+// levels 0-2 of its part of the tree on its own: the weights are staged in
+// LDS with coalesced reads, each thread sums one block of 16 entries, and the
+// level-0 values go back through LDS for coalesced writes.  Levels 3.. (rows
+// longer than one chunk) are summed from the chunk totals at the end.  The
+// graph is which0 + blockIdx.z.
+constexpr uint32_t kTreeChunk = kBlock * kFan;  // 4096 entries: one level-2 block
+static_assert(kTreeChunk == kFan * kFan * kFan, "a chunk is one level-2 block");
 
-// Rebuild the inclusive weight prefix of every dirty row (one workgroup per
-// row), then clear its mark.
-// Rebuild the weight prefix of the long rows listed dirty since `from` (0
-// after phase 1; after phase 4, the rows phase 1 had not listed).  The graph
-// is which0 + blockIdx.z.
-__global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* __restrict__ argv,
-                                                       uint32_t which0, int after_phase1) {
+__host__ __device__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
+
+__global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __restrict__ argv,
+                                                     uint32_t which0) {
   const uint32_t which = which0 + blockIdx.z;
   const gptr<const BatchArgs> ap = args_of(argv, blockIdx.y);
   BatchCtl* ctl = load_gptr(&ap->ctl);
@@ -433,41 +510,101 @@ __global__ __launch_bounds__(kBlock) void k_hub_prefix(const BatchArgs* const* _
   load_graph(X, ap, static_cast<int>(which));
   const uint32_t* dirty_rows = load_gptr(&ap->dirty_rows[which]);
   const uint32_t count = ctl->dirty[which];
-  const uint32_t from = after_phase1 ? ctl->dirty_p1[which] : 0u;
-  // phase 1's list ends here; phase 4 appends after it (same value from every block)
-  if (!after_phase1 && blockIdx.x == 0 && threadIdx.x == 0) ctl->dirty_p1[which] = count;
-  // consecutive entries per thread per block scan: a hub row of 10^5 entries
-  // takes a few dozen scans with many loads in flight, not hundreds
-  constexpr uint32_t kPer = 32;
-  for (uint32_t t = from + blockIdx.x; t < count; t += gridDim.x) {
-    const uint32_t r = dirty_rows[t];
-    const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment
+  __shared__ uint32_t s_q[lds_pad(kTreeChunk)];            // weights of the chunk
+  __shared__ unsigned long long s_v[lds_pad(kTreeChunk)];  // its level-0 values
+  __shared__ unsigned long long s_t[kBlock];               // block totals
+  const uint32_t t = threadIdx.x;
+  for (uint32_t di = blockIdx.x; di < count; di += gridDim.x) {
+    const uint32_t r = dirty_rows[di];
+    const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment, aligned
+    const uint32_t len = row.len;
+    const uint32_t K = tree_top(len);
+    const uint32_t n1 = tree_n(len, 1), n2 = tree_n(len, 2);
     const Ent* seg = X.ent + row.off;
-    unsigned long long* pf = X.pfx + row.off;
-    unsigned long long carry = 0;
-    for (uint32_t base = 0; base < row.len; base += kBlock * kPer) {
-      const uint32_t i0 = base + threadIdx.x * kPer;
-      uint32_t q[kPer];
-      unsigned long long sum = 0;
+    unsigned long long* l0 = X.pfx + row.off;
+    unsigned long long* tb = X.tree + (row.off >> 2);
+    unsigned long long* l1 = tb;  // tree_base(len, 1) == 0
+    unsigned long long* l2 = tb + tree_base(len, 2);
+    const uint32_t chunks = (len + kTreeChunk - 1) / kTreeChunk;
+    unsigned long long total = 0;  // thread 0
+    for (uint32_t ch = 0; ch < chunks; ++ch) {
+      const uint32_t e0 = ch * kTreeChunk;
+      const uint32_t ne = len - e0 < kTreeChunk ? len - e0 : kTreeChunk;
 #pragma unroll
-      for (uint32_t k = 0; k < kPer; ++k) {
-        q[k] = i0 + k < row.len ? seg[i0 + k].qw : 0u;
-        sum += q[k];
+      for (uint32_t j = 0; j < kFan; ++j) {
+        const uint32_t i = t + kBlock * j;
+        s_q[lds_pad(i)] = i < ne ? seg[e0 + i].qw : 0u;
       }
-      unsigned long long excl;
-      const unsigned long long total = block_excl_scan(sum, excl);
-      unsigned long long run = carry + excl;
+      __syncthreads();
+      // level 0: thread t sums block t of the chunk
+      unsigned long long run = 0;
 #pragma unroll
-      for (uint32_t k = 0; k < kPer; ++k) {
-        run += q[k];
-        if (i0 + k < row.len) pf[i0 + k] = run;
+      for (uint32_t j = 0; j < kFan; ++j) {
+        const uint32_t i = kFan * t + j;
+        run += s_q[lds_pad(i)];
+        s_v[lds_pad(i)] = i < ne ? run : kTreePad;
       }
-      carry += total;
+      s_t[t] = run;
+      __syncthreads();
+      const uint32_t nw = round_fan(ne);  // level-0 slots of the chunk, padding included
+#pragma unroll
+      for (uint32_t j = 0; j < kFan; ++j) {
+        const uint32_t i = t + kBlock * j;
+        if (i < nw) l0[e0 + i] = s_v[lds_pad(i)];
+      }
+      // level 1: value b = running sum of block totals within b's group of 16
+      const uint32_t b = ch * kBlock + t;  // level-1 index of block t
+      {
+        unsigned long long v1 = 0;
+        for (uint32_t j = t & ~(kFan - 1); j <= t; ++j) v1 += s_t[j];
+        if (b < round_fan(n1)) l1[b] = b < n1 ? v1 : kTreePad;
+      }
+      __syncthreads();
+      // group totals (level-2 inputs) into s_t[0..15], chunk total
+      unsigned long long gsum = 0;
+      if (t < kFan)
+        for (uint32_t j = 0; j < kFan; ++j) gsum += s_t[kFan * t + j];
+      __syncthreads();
+      if (t < kFan) s_t[t] = gsum;
+      __syncthreads();
+      unsigned long long ctot = 0;
+      for (uint32_t j = 0; j < kFan; ++j) ctot += s_t[j];
+      if (K == 1 && t == kFan - 1) l1[kFan - 1] = ctot;  // top block slot: the total
+      if (K >= 2 && t < kFan) {
+        const uint32_t c = ch * kFan + t;  // level-2 index
+        unsigned long long v2 = 0;
+        for (uint32_t j = 0; j <= t; ++j) v2 += s_t[j];
+        if (K == 2 && t == kFan - 1) l2[c] = ctot;  // top block slot: the total
+        else l2[c] = c < n2 ? v2 : kTreePad;
+      }
+      if (K >= 3 && t == 0) tb[tree_base(len, 3) + ch] = ctot;  // raw chunk total
+      if (t == 0) total += ctot;
+      __syncthreads();
     }
-    if (threadIdx.x == 0) X.mark[r] = 0u;
+    if (K >= 3 && t == 0) {
+      // levels 3..K from the raw totals on level 3: running sums within
+      // blocks of 16, each block total handed up as the next level's raw value
+      for (uint32_t l = 3; l <= K; ++l) {
+        const uint32_t n = tree_n(len, l);
+        unsigned long long* lv = tb + tree_base(len, l);
+        unsigned long long* up = l < K ? tb + tree_base(len, l + 1) : nullptr;
+        unsigned long long run = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+          run += lv[i];
+          lv[i] = run;
+          if ((i & (kFan - 1)) == kFan - 1 || i == n - 1) {
+            if (up) up[i >> 4] = run;
+            run = 0;
+          }
+        }
+        for (uint32_t i = n; i < round_fan(n); ++i) lv[i] = kTreePad;
+        if (l == K) lv[kFan - 1] = total;
+      }
+    }
+    if (t == 0) X.mark[r] = 0u;
+    __syncthreads();
   }
 }
-
 
 // ---- walks ------------------------------------------------------------------------
 
@@ -492,6 +629,7 @@ struct WalkParams {
   const Row* rows;
   const Ent* ent;
   const unsigned long long* pfx;
+  const unsigned long long* tree;
   const double* rinl;
   uint32_t p, q;
   bool use_K;
@@ -668,16 +806,22 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     pick_r = P.rinl + (static_cast<uint64_t>(S.x) * kInline + pick_idx);
     sbytes = 16u + 8u * (h.len - h.dead);
   } else if (kHubs && h.len > kHub) {
-    // long segment: the candidates' running sums are the stored prefix with
-    // the previous vertex's weight (that of the edge just taken) left out.
-    // The first index whose prefix exceeds the target is found on the full
-    // prefix; if it lies at or after the previous vertex (compare ids, the
-    // row is sorted), the answer is the first index whose prefix exceeds
-    // target + that weight, a short gallop from there.
+    // long segment: a descent of its weight tree.  The candidates are every
+    // entry but the previous vertex's, whose weight (that of the edge just
+    // taken) is qprev.  With i1 the first entry whose running total exceeds
+    // the target and i2 the first whose running total exceeds target +
+    // qprev, the pick is i1 if it lies before the previous vertex (compare
+    // ids: the row is sorted) and i2 otherwise.  i2 usually shares i1's leaf
+    // block, where the same 16 values give it; when the two agree the
+    // comparison is moot.
     const Ent* seg = P.ent + h.off;
-    const unsigned long long* pf = P.pfx + h.off;
+    const uint32_t d = h.len;
+    const uint32_t K = tree_top(d);
+    const unsigned long long* tb = P.tree + (h.off >> 2);
+    unsigned long long v[kFan];
+    tree_block(tb + tree_base(d, K), v);  // the top block; slot kFan-1 = the total
     const uint32_t qprev = S.prev != kNone ? S.qprev : 0u;
-    const unsigned long long tot = pf[h.len - 1] - qprev;
+    const unsigned long long tot = v[kFan - 1] - qprev;
     if (tot == 0) {
       // every other entry is a tombstone
       const int jp = (P.bounce && S.prev != kNone) ? find_nbr_pool(seg, h.len, S.prev) : -1;
@@ -685,28 +829,24 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
       pick_idx = jp >= 0 ? static_cast<uint32_t>(jp) : 0u;
     } else {
       const unsigned long long target = scale_random(rnd, tot);
-      uint32_t lo = 0, hi = h.len - 1;  // first i with pf[i] > target
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (pf[mid] > target) hi = mid;
-        else lo = mid + 1;
+      unsigned long long r1 = target;
+      uint32_t node = tree_child(v, r1);
+      for (uint32_t l = K - 1; l >= 1; --l) {
+        tree_block(tb + tree_base(d, l) + kFan * node, v);
+        node = kFan * node + tree_child(v, r1);
       }
-      if (qprev != 0u && seg[lo].nbr >= S.prev) {
-        const unsigned long long t2 = target + qprev;  // < pf[len - 1]
-        uint32_t a = lo, step = 1, b = lo;  // invariant: pf[a] <= t2 unless a == lo
-        while (pf[b] <= t2) {
-          a = b;
-          b = (h.len - 1 - b) > step ? b + step : h.len - 1;
-          step <<= 1;
-        }
-        while (a < b) {  // first i in [a, b] with pf[i] > t2
-          const uint32_t mid = (a + b) >> 1;
-          if (pf[mid] > t2) b = mid;
-          else a = mid + 1;
-        }
-        lo = a;
+      tree_block(P.pfx + h.off + kFan * node, v);
+      const unsigned long long r2 = r1 + qprev;  // target + qprev, if in this leaf block
+      const uint32_t c1 = tree_child(v, r1);
+      const uint32_t c2 = tree_count(v, r2);
+      const uint32_t in_leaf = d - kFan * node < kFan ? d - kFan * node : kFan;
+      const uint32_t i1 = kFan * node + c1;
+      pick_idx = i1;
+      if (c2 != c1) {
+        const uint32_t i2 = c2 < in_leaf ? kFan * node + c2
+                                         : tree_find(P.pfx + h.off, tb, d, target + qprev);
+        if (seg[i1].nbr >= S.prev) pick_idx = i2;
       }
-      pick_idx = lo;
     }
     pick_nbr = stop ? kNone : seg[pick_idx].nbr;
     pick_q = stop ? 0u : seg[pick_idx].qw;
@@ -1021,6 +1161,7 @@ __device__ __forceinline__ UpdateView view_update(const BatchArgs& a, const DevG
   P.rows = v.is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
   P.ent = v.is_ins ? H.ent : G.ent;
   P.pfx = v.is_ins ? H.pfx : G.pfx;
+  P.tree = v.is_ins ? H.tree : G.tree;
   P.rinl = v.is_ins ? H.rinl : G.rinl;
   v.walks = v.is_ins || a.in_h[j];
   return v;
@@ -1375,6 +1516,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   P.rows = a0.g[1].rows;
   P.ent = a0.g[1].ent;
   P.pfx = a0.g[1].pfx;
+  P.tree = a0.g[1].tree;
   P.rinl = a0.g[1].rinl;
   P.p = P.q = 0;
   P.use_K = false;
@@ -1437,6 +1579,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         P.rows = load_gptr(&A->g[gw].rows);
         P.ent = load_gptr(&A->g[gw].ent);
         P.pfx = load_gptr(&A->g[gw].pfx);
+        P.tree = load_gptr(&A->g[gw].tree);
         P.rinl = load_gptr(&A->g[gw].rinl);
       } else {
         const bool is_ins = rec.upd < a0.n_ins;
@@ -1448,6 +1591,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         P.rows = X.rows;
         P.ent = X.ent;
         P.pfx = X.pfx;
+        P.tree = X.tree;
         P.rinl = X.rinl;
       }
       P.p = rec.p;
@@ -1500,6 +1644,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
   P.pfx = a.g[1].pfx;
+  P.tree = a.g[1].tree;
   P.rinl = a.g[1].rinl;
   P.p = P.q = 0;
   P.use_K = false;
@@ -1542,6 +1687,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
         P.rows = X.rows;
         P.ent = X.ent;
         P.pfx = X.pfx;
+        P.tree = X.tree;
         P.rinl = X.rinl;
         walker = idx - start;
         item = base + idx;
@@ -1643,6 +1789,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
   P.pfx = a.g[1].pfx;
+  P.tree = a.g[1].tree;
   P.rinl = a.g[1].rinl;
   P.p = P.q = 0;
   P.use_K = false;
@@ -1684,6 +1831,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
         P.rows = X.rows;
         P.ent = X.ent;
         P.pfx = X.pfx;
+        P.tree = X.tree;
         P.rinl = X.rinl;
         const unsigned long long first = item0 + a.qofs[upd];
         const TailState ts = a.tstate[first + (idx - start)];
@@ -1883,7 +2031,7 @@ __global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv, uint32_
       seg.r(k) = d.rinv;
       seg.w[k] = d.w;
       atomicSub(&row_hdr_ref(X, d.r).dead, 1u);
-      if (row.len > kHub) mark_dirty4(a, which, d.r);
+      if (row.len > kHub) tree_add(X, row.off, row.len, static_cast<uint32_t>(k), d.qw);
     }
     return;
   }
@@ -1904,12 +2052,25 @@ __device__ __forceinline__ uint32_t grown_cap(uint32_t live) {
   return live + extra;
 }
 
-// touched_k packs the number of appended entries with two decisions taken
+// touched_k packs the number of appended entries with three decisions taken
 // here, once, from the segment as it stands before phase 4 moves anything:
-// whether the segment is relocated by a workgroup and merged by a workgroup.
+// whether the segment is relocated by a workgroup, merged by a workgroup, and
+// relocated to a start aligned for a weight tree.
+constexpr uint32_t kAlignHub = 1u << 29;
 constexpr uint32_t kWideRelocate = 1u << 30;
 constexpr uint32_t kWideMerge = 1u << 31;
-constexpr uint32_t kCountMask = kWideRelocate - 1u;
+constexpr uint32_t kCountMask = kAlignHub - 1u;
+
+// A segment of more than kHub entries must start at a multiple of kHubAlign
+// and own a multiple of kFan slots (its weight tree's layout).
+__device__ __forceinline__ bool tree_ready(const RowHdr& row) {
+  return row.off != kInlineOff && row.off % kHubAlign == 0 && row.cap % kFan == 0;
+}
+
+// First slot of a relocated segment reserved with reserve_slots(cap, align).
+__device__ __forceinline__ uint32_t relocated_off(unsigned long long raw, bool align) {
+  return static_cast<uint32_t>(align ? (raw + kHubAlign - 1) / kHubAlign * kHubAlign : raw);
+}
 
 __global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
   const uint32_t which = which0 + blockIdx.z;
@@ -1922,11 +2083,18 @@ __global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, uint32_t 
   const uint32_t k = X.pending[r];
   const RowHdr row = row_hdr(X, r);
   uint32_t need = 0, flags = 0, merged_from = row.len;
-  if (row.len + k > row.cap) {
-    need = grown_cap(row.len - row.dead + k);
-    atomicAdd(&a.ctl->need[which], static_cast<unsigned long long>(need));
+  // relocated when the slack cannot take the k new entries, or when the
+  // merged segment becomes long and its place does not suit a weight tree
+  if (row.len + k > row.cap || (row.len + k > kHub && !tree_ready(row))) {
+    const uint32_t live = row.len - row.dead + k;  // relocation drops the tombstones
+    const bool align = live > kHub;
+    need = align ? round_fan(grown_cap(live)) : grown_cap(live);
+    // an aligned start may skip up to kHubAlign - 1 slots
+    const uint32_t reserve = align ? need + kHubAlign - 1 : need;
+    atomicAdd(&a.ctl->need[which], static_cast<unsigned long long>(reserve));
     if (row.len > kHub) flags |= kWideRelocate;
-    merged_from = row.len - row.dead;  // relocation drops the tombstones
+    if (align) flags |= kAlignHub;
+    merged_from = row.len - row.dead;
   }
   if (merged_from + k > kHub) flags |= kWideMerge;
   a.touched_k[t] = k | flags;
@@ -1957,8 +2125,11 @@ __device__ __forceinline__ void rows_relocate_narrow(const BatchArgs* const* __r
   const uint32_t r = a.touched_rows[t];
   const RowHdr row = row_hdr(X, r);
   const Seg src = seg_of(X, r, row.off);
-  const uint32_t off =
-      static_cast<uint32_t>(atomicAdd(&a.ctl->pool_top[which], static_cast<unsigned long long>(need)));
+  const bool align = (a.touched_k[t] & kAlignHub) != 0;
+  const uint32_t off = relocated_off(
+      atomicAdd(&a.ctl->pool_top[which],
+                static_cast<unsigned long long>(align ? need + kHubAlign - 1 : need)),
+      align);
   uint32_t o = 0;
   for (uint32_t i = 0; i < row.len; ++i) {
     const Ent e = src.get(i);
@@ -1986,9 +2157,12 @@ __device__ __forceinline__ void rows_relocate_wide(const BatchArgs* const* __res
     if (need == 0 || !(a.touched_k[t] & kWideRelocate)) continue;  // block-uniform
     const uint32_t r = a.touched_rows[t];
     const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment
+    const bool align = (a.touched_k[t] & kAlignHub) != 0;
     if (threadIdx.x == 0)
-      s_off = static_cast<uint32_t>(
-          atomicAdd(&a.ctl->pool_top[which], static_cast<unsigned long long>(need)));
+      s_off = relocated_off(
+          atomicAdd(&a.ctl->pool_top[which],
+                    static_cast<unsigned long long>(align ? need + kHubAlign - 1 : need)),
+          align);
     __syncthreads();
     const uint32_t off = s_off;
     unsigned long long out = 0;
@@ -2262,9 +2436,8 @@ inline uint32_t blocks_for(uint64_t n, uint32_t per = kBlock) {
 // x covers the largest batch of the launch.
 
 namespace {
-void launch_hub_prefix(const Launch& L, uint32_t which0, uint32_t nw, int after_phase1,
-                       hipStream_t st) {
-  k_hub_prefix<<<dim3(kHubBlocks, L.F, nw), kBlock, 0, st>>>(L.argv, which0, after_phase1);
+void launch_hub_tree(const Launch& L, uint32_t which0, uint32_t nw, hipStream_t st) {
+  k_hub_tree<<<dim3(kHubBlocks, L.F, nw), kBlock, 0, st>>>(L.argv, which0);
 }
 
 inline dim3 grid_of(uint64_t n, uint32_t F, uint32_t per = kBlock) {
@@ -2286,9 +2459,8 @@ void launch_validate(const Launch& L, hipStream_t st) {
 
 void launch_phase1(const Launch& L, hipStream_t st) {
   if (L.max_del == 0) return;
+  // long segments' weight trees are updated in place by the tombstones
   k_phase1<<<grid_of(L.max_del, L.F), kBlock, 0, st>>>(L.argv);
-  // walks read the prefix of long segments: rebuild the ones just changed
-  launch_hub_prefix(L, 0u, 2u, 0, st);
 }
 
 void launch_walks(const Launch& L, hipStream_t st) {
@@ -2367,7 +2539,7 @@ void phase4_sequence(const Launch& L, uint32_t which0, uint32_t nw, hipStream_t 
   k_rows_relocate<<<both, kBlock, 0, st>>>(L.argv, which0, g.x);
   k_add_place<<<g, kBlock, 0, st>>>(L.argv, which0);
   k_rows_merge<<<both, kBlock, 0, st>>>(L.argv, which0, g.x);
-  launch_hub_prefix(L, which0, nw, 1, st);
+  launch_hub_tree(L, which0, nw, st);
 }
 
 }  // namespace
