@@ -237,6 +237,7 @@ struct dyg_ctx {
   double walk_ms_total = 0.0, walk_ms_last = 0.0, batch_ms_last = 0.0;
   // batch staging
   DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, ubytes, wrec, wofs, hadd, hash;
+  DBuf fb_list;
   DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2], wide_rows[2];
   DBuf hash2;
   DBuf qcount, qofs, qtile, items, wres;  // batched form
@@ -267,6 +268,7 @@ int fail_hip(hipError_t e) { return e == hipErrorOutOfMemory ? DYG_E_NOMEM : DYG
 void free_graph(DevGraph& X) {
   if (X.rows) (void)hipFree(X.rows);
   if (X.ent) (void)hipFree(X.ent);
+  if (X.prinv) (void)hipFree(X.prinv);
   if (X.w) (void)hipFree(X.w);
   if (X.pending) (void)hipFree(X.pending);
   if (X.pfx) (void)hipFree(X.pfx);
@@ -285,7 +287,8 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
   Y.pool_cap = pool_cap;
   hipError_t e = hipSuccess;
   if ((e = hipMalloc(&Y.rows, sizeof(Row) * std::max<uint64_t>(n, 1))) != hipSuccess ||
-      (e = hipMalloc(&Y.ent, sizeof(Ent) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
+      (e = hipMalloc(&Y.ent, sizeof(Pair) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
+      (e = hipMalloc(&Y.prinv, sizeof(double) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.w, sizeof(double) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.pending, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.pfx, sizeof(unsigned long long) * std::max<uint64_t>(pool_cap, 1))) !=
@@ -300,10 +303,20 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
     free_graph(Y);
     return fail_hip(e);
   }
+  // pool entries go up as (neighbour, weight) pairs and a 1/w array
+  std::vector<Pair> pairs(A.ent.size());
+  std::vector<double> prinv(A.ent.size());
+  for (size_t i = 0; i < A.ent.size(); ++i) {
+    pairs[i] = Pair{A.ent[i].nbr, A.ent[i].qw};
+    prinv[i] = A.ent[i].rinv;
+  }
   if ((e = hipMemcpyAsync(Y.rows, A.rows.data(), sizeof(Row) * n, hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
-      (!A.ent.empty() &&
-       (e = hipMemcpyAsync(Y.ent, A.ent.data(), sizeof(Ent) * A.ent.size(),
+      (!pairs.empty() &&
+       (e = hipMemcpyAsync(Y.ent, pairs.data(), sizeof(Pair) * pairs.size(),
+                           hipMemcpyHostToDevice, st)) != hipSuccess) ||
+      (!prinv.empty() &&
+       (e = hipMemcpyAsync(Y.prinv, prinv.data(), sizeof(double) * prinv.size(),
                            hipMemcpyHostToDevice, st)) != hipSuccess) ||
       (!A.w.empty() &&
        (e = hipMemcpyAsync(Y.w, A.w.data(), sizeof(double) * A.w.size(), hipMemcpyHostToDevice,
@@ -335,7 +348,7 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
 // and owns a multiple of kFan slots, as its weight tree needs.
 uint32_t segment_cap(uint32_t len, double slack) {
   const uint32_t cap = len + slack_slots(len, slack);
-  return len > dyg::kHub ? dyg::round_fan(cap) : cap;
+  return len > dyg::kHub ? dyg::round_fan(cap) : (cap + 1u) & ~1u;  // even: two pairs per load
 }
 
 void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
@@ -397,8 +410,8 @@ uint64_t pool_capacity_for(uint64_t used, uint32_t n, uint32_t flags) {
 int download_live(const DevGraph& X, uint32_t n, uint64_t used, std::vector<uint64_t>& start,
                   std::vector<Ent>& live_ent, std::vector<double>& live_w, hipStream_t st) {
   std::vector<Row> rows(n);
-  std::vector<Ent> ent(used);
-  std::vector<double> w(used), winl(static_cast<size_t>(n) * kInline),
+  std::vector<Pair> pairs(used);
+  std::vector<double> w(used), prinv(used), winl(static_cast<size_t>(n) * kInline),
       rinl(static_cast<size_t>(n) * kInline);
   hipError_t e;
   if ((e = hipMemcpyAsync(rows.data(), X.rows, sizeof(Row) * n, hipMemcpyDeviceToHost, st)) !=
@@ -407,8 +420,10 @@ int download_live(const DevGraph& X, uint32_t n, uint64_t used, std::vector<uint
                           hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipMemcpyAsync(winl.data(), X.winl, sizeof(double) * winl.size(),
                           hipMemcpyDeviceToHost, st)) != hipSuccess ||
-      (used && (e = hipMemcpyAsync(ent.data(), X.ent, sizeof(Ent) * used, hipMemcpyDeviceToHost,
-                                   st)) != hipSuccess) ||
+      (used && (e = hipMemcpyAsync(pairs.data(), X.ent, sizeof(Pair) * used,
+                                   hipMemcpyDeviceToHost, st)) != hipSuccess) ||
+      (used && (e = hipMemcpyAsync(prinv.data(), X.prinv, sizeof(double) * used,
+                                   hipMemcpyDeviceToHost, st)) != hipSuccess) ||
       (used && (e = hipMemcpyAsync(w.data(), X.w, sizeof(double) * used, hipMemcpyDeviceToHost,
                                    st)) != hipSuccess) ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
@@ -421,7 +436,8 @@ int download_live(const DevGraph& X, uint32_t n, uint64_t used, std::vector<uint
     const bool inl = r.off == kInlineOff;
     for (uint32_t i = 0; i < r.len; ++i) {
       const size_t k = static_cast<size_t>(u) * kInline + i;
-      const Ent x = inl ? Ent{rows[u].inl[i].nbr, rows[u].inl[i].qw, rinl[k]} : ent[r.off + i];
+      const Ent x = inl ? Ent{rows[u].inl[i].nbr, rows[u].inl[i].qw, rinl[k]}
+                        : Ent{pairs[r.off + i].nbr, pairs[r.off + i].qw, prinv[r.off + i]};
       if (x.qw == 0u) continue;
       live_ent.push_back(x);
       live_w.push_back(inl ? winl[static_cast<size_t>(u) * kInline + i] : w[r.off + i]);
@@ -717,7 +733,7 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
   if (!batch_table_sizes(n_ins, n_del, Lcap, hadd_cap, hash_slots)) return DYG_E_NOMEM;
   bool ok = c->ins_qw.ensure(4 * n_ins + 8) && c->ins_rinv.ensure(8 * n_ins + 8) &&
             c->in_h.ensure(n_del + 8) && c->res.ensure(sizeof(dyg_update_result) * nu + 8) &&
-            c->ubytes.ensure(4 * nu + 8) &&
+            c->ubytes.ensure(4 * nu + 8) && c->fb_list.ensure(4 * n_del + 8) &&
             c->hadd.ensure(sizeof(AddRec) * hadd_cap + 8) &&
             c->hash.ensure(sizeof(HashSlot) * hash_slots) &&
             c->hash2.ensure(sizeof(HashSlot) * hash_slots) &&
@@ -777,6 +793,7 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
   a.wofs = record ? c->wofs.as<uint64_t>() : nullptr;
   a.hadd = c->hadd.as<AddRec>();
   a.ubytes = c->ubytes.as<uint32_t>();
+  a.fb_list = c->fb_list.as<uint32_t>();
   a.hadd_cap = static_cast<uint32_t>(hadd_cap);
   a.hash = c->hash.as<HashSlot>();
   a.hash2 = c->hash2.as<HashSlot>();
@@ -835,6 +852,7 @@ void carve_batch(const dyg_ctx* c, BatchArgs& a, Carve& m, uint64_t n_ins, uint6
   a.in_h = m.take<uint8_t>(n_del + 8);
   if (own_results) a.res = m.take<dyg::UpdRes>(sizeof(dyg_update_result) * nu + 8);
   a.ubytes = m.take<uint32_t>(4 * nu + 8);
+  a.fb_list = m.take<uint32_t>(4 * n_del + 8);
   a.hadd = m.take<AddRec>(sizeof(AddRec) * hadd_cap + 8);
   a.hash = m.take<HashSlot>(sizeof(HashSlot) * hash_slots);
   a.hash2 = m.take<HashSlot>(sizeof(HashSlot) * hash_slots);
@@ -1467,8 +1485,12 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
   if (e == hipSuccess)
     e = hipMemcpyAsync(I.winl.data(), X.winl, sizeof(double) * I.winl.size(),
                        hipMemcpyDeviceToHost, st);
+  std::vector<Pair> pairs(used);
+  std::vector<double> prinv(used);
   if (e == hipSuccess && used)
-    e = hipMemcpyAsync(I.ent.data(), X.ent, sizeof(Ent) * used, hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(pairs.data(), X.ent, sizeof(Pair) * used, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && used)
+    e = hipMemcpyAsync(prinv.data(), X.prinv, sizeof(double) * used, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && used)
     e = hipMemcpyAsync(I.w.data(), X.w, sizeof(double) * used, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && used)
@@ -1478,6 +1500,7 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
     e = hipMemcpyAsync(I.tree.data(), X.tree, sizeof(unsigned long long) * I.tree.size(),
                        hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (uint64_t i = 0; i < used; ++i) I.ent[i] = Ent{pairs[i].nbr, pairs[i].qw, prinv[i]};
   return e == hipSuccess ? DYG_OK : fail_hip(e);
 }
 
@@ -1531,6 +1554,8 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
           if (I.rows[u].inl[i].qw != 0u) return fail("inline slot past len in use", g, u, i);
       if (!inl && static_cast<uint64_t>(r.off) + r.cap > ctl.pool_top[g])
         return fail("segment beyond pool top", g, u, r.off);
+      if (!inl && (r.off % 2 != 0 || r.cap % 2 != 0))  // the walk reads two pairs per load
+        return fail("segment start or capacity odd", g, u, r.off);
       if (!inl && r.cap) spans.push_back({r.off, static_cast<uint64_t>(r.off) + r.cap});
       uint32_t dead = 0;
       for (uint32_t i = 0; i < r.len; ++i) {
@@ -1669,6 +1694,7 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
                   &c->hash};
   for (DBuf* b : bufs) b->release();
   c->hash2.release();
+  c->fb_list.release();
   DBuf* qbufs[] = {&c->qcount, &c->qofs, &c->qtile, &c->items, &c->wres, &c->tstate, &c->tcount};
   for (DBuf* b : qbufs) b->release();
   for (int g = 0; g < 2; ++g) {

@@ -22,7 +22,11 @@ namespace dyg {
 // The inline slots of a row past its len also hold qw == 0 (rows are zeroed
 // when laid out, and an inline row only grows until it moves to the pool).
 // Neighbour ids are unique within a row (a re-inserted edge revives its
-// tombstone).
+// tombstone).  Pool entries are stored as 8-byte (neighbour, weight) pairs
+// (`ent`), with their resistances and weights in side arrays (`prinv`, `w`),
+// so a walk step's scan reads only what the choice needs; every pool segment
+// starts at an even slot, so a scan reads two pairs per 16-byte load.
+// Ent is the value of one entry as the host and phase 4 handle it.
 struct Ent {
   uint32_t nbr;  // neighbour id
   uint32_t qw;   // quantised weight, 0 = tombstone
@@ -107,7 +111,8 @@ __host__ __device__ inline uint32_t tree_base(uint32_t len, uint32_t l) {
 
 struct DevGraph {
   Row* rows = nullptr;        // [n] 64-byte rows
-  Ent* ent = nullptr;         // [pool_cap]
+  Pair* ent = nullptr;        // [pool_cap] (neighbour, quantised weight) of each pool entry
+  double* prinv = nullptr;    // [pool_cap] 1/w of each pool entry
   double* w = nullptr;        // [pool_cap] weight of each pool entry (cold)
   double* rinl = nullptr;     // [n * kInline] 1/w of each inline entry
   double* winl = nullptr;     // [n * kInline] weight of each inline entry (cold)
@@ -191,6 +196,7 @@ struct BatchCtl {
   uint32_t dirty[2];            // rows whose weight tree must be rebuilt, per graph
   uint32_t wide[2];             // touched rows moved or merged by a workgroup, per graph
   uint32_t hubs;                // set when phase 4 leaves a row longer than kHub
+  uint32_t fb_count;            // deletions whose fallback scan is left to k_fallback_wide
   unsigned long long pool_top[2];  // next free pool slot, per graph
   unsigned long long walk_items;       // walkers queued (queue control only)
   unsigned long long queue_next;       // next queue item to hand out (queue control only)
@@ -235,6 +241,7 @@ struct BatchArgs {
   const uint64_t* wofs; // optional [n_ins + n_del]
   AddRec* hadd;         // [hadd_cap]: slot i for insertion i, then Lcap slots per deletion
   uint32_t* ubytes;     // [n_ins + n_del] algorithmic bytes gathered by each update's walks
+  uint32_t* fb_list;    // [n_del] updates whose no-hit fallback scans a long row (ctl->fb_count)
   uint32_t hadd_cap;
   HashSlot* hash;       // validation: repeats within the batch
   HashSlot* hash2;      // phase 4: edges recovered more than once

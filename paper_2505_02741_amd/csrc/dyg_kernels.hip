@@ -68,6 +68,7 @@ __device__ __forceinline__ gptr<const BatchArgs> args_of(const BatchArgs* const*
 __device__ __forceinline__ void load_graph(DevGraph& X, gptr<const BatchArgs> ap, int w) {
   X.rows = load_gptr(&ap->g[w].rows);
   X.ent = load_gptr(&ap->g[w].ent);
+  X.prinv = load_gptr(&ap->g[w].prinv);
   X.w = load_gptr(&ap->g[w].w);
   X.rinl = load_gptr(&ap->g[w].rinl);
   X.winl = load_gptr(&ap->g[w].winl);
@@ -98,6 +99,7 @@ __device__ __forceinline__ BatchArgs load_args(const BatchArgs* const* __restric
   a.wofs = load_gptr(&ap->wofs);
   a.hadd = load_gptr(&ap->hadd);
   a.ubytes = load_gptr(&ap->ubytes);
+  a.fb_list = load_gptr(&ap->fb_list);
   a.hash = load_gptr(&ap->hash);
   a.hash2 = load_gptr(&ap->hash2);
   load_graph(a.g[0], ap, 0);
@@ -145,20 +147,17 @@ __device__ __forceinline__ RowHdr& row_hdr_ref(const DevGraph& X, uint32_t u) {
 }
 
 // Entries of one row, inline or in the pool: entry i has its (nbr, qw) pair
-// at words[i * stride], its 1/w at rinv[i * rstride] and its weight at w[i].
+// at pair[i], its 1/w at rinv[i] and its weight at w[i].
 struct Seg {
-  uint32_t* words;
-  uint32_t stride;   // 2 inline (Pair), 4 pool (Ent)
+  Pair* pair;
   double* rinv;
-  uint32_t rstride;  // 1 inline (side array), 2 pool (Ent)
   double* w;
-  __device__ __forceinline__ uint32_t nbr(uint32_t i) const { return words[i * stride]; }
-  __device__ __forceinline__ uint32_t& qw(uint32_t i) const { return words[i * stride + 1]; }
-  __device__ __forceinline__ double& r(uint32_t i) const { return rinv[i * rstride]; }
+  __device__ __forceinline__ uint32_t nbr(uint32_t i) const { return pair[i].nbr; }
+  __device__ __forceinline__ uint32_t& qw(uint32_t i) const { return pair[i].qw; }
+  __device__ __forceinline__ double& r(uint32_t i) const { return rinv[i]; }
   __device__ __forceinline__ Ent get(uint32_t i) const { return Ent{nbr(i), qw(i), r(i)}; }
   __device__ __forceinline__ void put(uint32_t i, const Ent& e, double wt) const {
-    words[i * stride] = e.nbr;
-    words[i * stride + 1] = e.qw;
+    pair[i] = Pair{e.nbr, e.qw};
     r(i) = e.rinv;
     w[i] = wt;
   }
@@ -168,10 +167,9 @@ struct Seg {
 __device__ __forceinline__ Seg seg_of(const DevGraph& X, uint32_t u, uint32_t off) {
   if (off == kInlineOff) {
     const uint64_t b = static_cast<uint64_t>(u) * kInline;
-    return Seg{&X.rows[u].inl[0].nbr, 2u, X.rinl + b, 1u, X.winl + b};
+    return Seg{&X.rows[u].inl[0], X.rinl + b, X.winl + b};
   }
-  Ent* e = X.ent + off;
-  return Seg{&e->nbr, 4u, &e->rinv, 2u, X.w + off};
+  return Seg{X.ent + off, X.prinv + off, X.w + off};
 }
 
 // Index of neighbour v among the first len entries (tombstones included), or -1.
@@ -199,7 +197,7 @@ __device__ __forceinline__ uint32_t lower_nbr(const Seg& seg, uint32_t len, uint
 }
 
 // The same for a pool segment.
-__device__ __forceinline__ int find_nbr_pool(const Ent* seg, uint32_t len, uint32_t v) {
+__device__ __forceinline__ int find_nbr_pool(const Pair* seg, uint32_t len, uint32_t v) {
   int lo = 0, hi = static_cast<int>(len) - 1;
   while (lo <= hi) {
     const int mid = (lo + hi) >> 1;
@@ -362,6 +360,7 @@ __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
       q->queue_next = 0;
     }
     ctl->err_key = ~0ull;
+    ctl->fb_count = 0;
     for (int w = 0; w < 2; ++w) {
       ctl->touched[w] = 0;
       ctl->need[w] = 0;
@@ -520,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
     const uint32_t len = row.len;
     const uint32_t K = tree_top(len);
     const uint32_t n1 = tree_n(len, 1), n2 = tree_n(len, 2);
-    const Ent* seg = X.ent + row.off;
+    const Pair* seg = X.ent + row.off;
     unsigned long long* l0 = X.pfx + row.off;
     unsigned long long* tb = X.tree + (row.off >> 2);
     unsigned long long* l1 = tb;  // tree_base(len, 1) == 0
@@ -627,7 +626,8 @@ __device__ __forceinline__ uint32_t step_bytes(uint32_t d) {
 
 struct WalkParams {
   const Row* rows;
-  const Ent* ent;
+  const Pair* ent;
+  const double* prinv;
   const unsigned long long* pfx;
   const unsigned long long* tree;
   const double* rinl;
@@ -814,7 +814,7 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     // ids: the row is sorted) and i2 otherwise.  i2 usually shares i1's leaf
     // block, where the same 16 values give it; when the two agree the
     // comparison is moot.
-    const Ent* seg = P.ent + h.off;
+    const Pair* seg = P.ent + h.off;
     const uint32_t d = h.len;
     const uint32_t K = tree_top(d);
     const unsigned long long* tb = P.tree + (h.off >> 2);
@@ -850,22 +850,28 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     }
     pick_nbr = stop ? kNone : seg[pick_idx].nbr;
     pick_q = stop ? 0u : seg[pick_idx].qw;
-    pick_r = &seg[pick_idx].rinv;
+    pick_r = P.prinv + h.off + pick_idx;
     sbytes = step_bytes(h.len - h.dead);
   } else {
-    const Ent* seg = P.ent + h.off;
-    const uint2* e2 = reinterpret_cast<const uint2*>(seg);  // (nbr, qw) pairs
+    // pool segment: (nbr, qw) pairs, two per 16-byte load (the segment starts
+    // at an even slot); the slot past an odd len is masked
+    const Pair* seg = P.ent + h.off;
+    const uint4* e4 = reinterpret_cast<const uint4*>(seg);
+    const uint32_t n4 = (h.len + 1) >> 1;
+    const bool odd = h.len & 1u;
     unsigned long long tot = 0;
     if (kHubs) {
 #pragma unroll 8
-      for (uint32_t i = 0; i < h.len; ++i) {  // unrolled: the loads go out together
-        const uint2 e = e2[2 * i];
+      for (uint32_t i = 0; i < n4; ++i) {  // unrolled: the loads go out together
+        const uint4 e = e4[i];
         tot += (e.x != S.prev) ? e.y : 0u;
+        tot += (e.z != S.prev && (i + 1 < n4 || !odd)) ? e.w : 0u;
       }
     } else {
-      for (uint32_t i = 0; i < h.len; ++i) {
-        const uint2 e = e2[2 * i];
+      for (uint32_t i = 0; i < n4; ++i) {
+        const uint4 e = e4[i];
         tot += (e.x != S.prev) ? e.y : 0u;
+        tot += (e.z != S.prev && (i + 1 < n4 || !odd)) ? e.w : 0u;
       }
     }
     pick_idx = 0;
@@ -879,29 +885,39 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
       pick_idx = h.len - 1;
       if (kHubs) {
 #pragma unroll 8
-        for (uint32_t i = 0; i < h.len; ++i) {
-          const uint2 e = e2[2 * i];
+        for (uint32_t i = 0; i < n4; ++i) {
+          const uint4 e = e4[i];
           run += (e.x != S.prev) ? e.y : 0u;
           if (run > target) {
-            pick_idx = i;
+            pick_idx = 2 * i;
+            break;
+          }
+          run += (e.z != S.prev && (i + 1 < n4 || !odd)) ? e.w : 0u;
+          if (run > target) {
+            pick_idx = 2 * i + 1;
             break;
           }
         }
       } else {
-        for (uint32_t i = 0; i < h.len; ++i) {
-          const uint2 e = e2[2 * i];
+        for (uint32_t i = 0; i < n4; ++i) {
+          const uint4 e = e4[i];
           run += (e.x != S.prev) ? e.y : 0u;
           if (run > target) {
-            pick_idx = i;
+            pick_idx = 2 * i;
+            break;
+          }
+          run += (e.z != S.prev && (i + 1 < n4 || !odd)) ? e.w : 0u;
+          if (run > target) {
+            pick_idx = 2 * i + 1;
             break;
           }
         }
       }
     }
-    const uint2 pe = e2[2 * pick_idx];
-    pick_nbr = stop ? kNone : pe.x;
-    pick_q = stop ? 0u : pe.y;
-    pick_r = &seg[pick_idx].rinv;
+    const Pair pe = seg[pick_idx];
+    pick_nbr = stop ? kNone : pe.nbr;
+    pick_q = stop ? 0u : pe.qw;
+    pick_r = P.prinv + h.off + pick_idx;
     sbytes = step_bytes(h.len - h.dead);
   }
   S.R = S.R + rprev;
@@ -1160,6 +1176,7 @@ __device__ __forceinline__ UpdateView view_update(const BatchArgs& a, const DevG
   P.heavy = a.ctl->heavy != 0u;
   P.rows = v.is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
   P.ent = v.is_ins ? H.ent : G.ent;
+  P.prinv = v.is_ins ? H.prinv : G.prinv;
   P.pfx = v.is_ins ? H.pfx : G.pfx;
   P.tree = v.is_ins ? H.tree : G.tree;
   P.rinl = v.is_ins ? H.rinl : G.rinl;
@@ -1203,6 +1220,54 @@ __device__ __forceinline__ void no_walk_update(const BatchArgs& a, const UpdateV
   if (lane == 0) {
     a.res[upd] = empty_result(v.is_ins);
     a.ubytes[upd] = 0u;
+  }
+}
+
+// No-hit fallback (Sec. III-C, local edges near the deleted edge): the G
+// edge at `end` of least resistance 1/w (largest weight) that is not live in
+// H, ties to the smaller neighbour.  Thread `part` of `parts` scans one
+// contiguous slice of end's G row, merging it against end's H row (both
+// sorted by neighbour), and returns its slice's best (br = INFINITY, bn =
+// kNone if none); the caller takes the minimum of (br, bn) over the parts.
+// Rows longer than kWideFallback are left to k_fallback_wide (a workgroup).
+constexpr uint32_t kWideFallback = 1024;
+constexpr uint32_t kFallbackUnroll = 8;  // G entries loaded together
+
+__device__ __forceinline__ void fallback_slice(const DevGraph& G, const DevGraph& H, uint32_t end,
+                                               uint32_t part, uint32_t parts, double& br,
+                                               uint32_t& bn, uint32_t& bi) {
+  const RowHdr r = row_hdr(G, end);
+  const Seg seg = seg_of(G, end, r.off);
+  const RowHdr hr = row_hdr(H, end);
+  const Seg hseg = seg_of(H, end, hr.off);
+  const uint32_t per = (r.len + parts - 1) / parts;
+  const uint32_t a0 = part * per < r.len ? part * per : r.len;
+  const uint32_t a1 = a0 + per < r.len ? a0 + per : r.len;
+  uint32_t j = a0 < a1 ? lower_nbr(hseg, hr.len, seg.nbr(a0)) : hr.len;
+  br = INFINITY;
+  bn = kNone;
+  bi = 0;
+  for (uint32_t i0 = a0; i0 < a1; i0 += kFallbackUnroll) {
+    uint32_t en[kFallbackUnroll], eq[kFallbackUnroll];
+    double er[kFallbackUnroll];
+#pragma unroll
+    for (uint32_t m = 0; m < kFallbackUnroll; ++m) {  // loads issued together
+      const uint32_t i = i0 + m < a1 ? i0 + m : a1 - 1;
+      en[m] = seg.nbr(i);
+      eq[m] = seg.qw(i);
+      er[m] = seg.r(i);
+    }
+#pragma unroll
+    for (uint32_t m = 0; m < kFallbackUnroll; ++m) {
+      if (i0 + m >= a1 || eq[m] == 0u) continue;
+      while (j < hr.len && hseg.nbr(j) < en[m]) ++j;
+      if (j < hr.len && hseg.nbr(j) == en[m] && hseg.qw(j) != 0u) continue;  // live in H
+      if (er[m] < br || (er[m] == br && en[m] < bn)) {
+        br = er[m];
+        bn = en[m];
+        bi = i0 + m;
+      }
+    }
   }
 }
 
@@ -1268,35 +1333,21 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
       count = sink.count;
     }
     count = static_cast<uint32_t>(__shfl(static_cast<int>(count), 0, kWave));
+  } else if (row_hdr(G, P.p).len > kWideFallback || row_hdr(G, P.q).len > kWideFallback) {
+    // no hit at a long row: the fallback scan is left to k_fallback_wide,
+    // which gives it a workgroup (n_rec and the slots are written there)
+    if (lane == 0) a.fb_list[atomicAdd(&a.ctl->fb_count, 1u)] = upd;
   } else {
     // no hit: per endpoint the least-resistance G edge not in H, ties to the
-    // smaller neighbour; lanes scan strided entries, then the wavefront's
-    // minimum of (1/w, neighbour)
+    // smaller neighbour; each lane scans a slice of the G row, then the
+    // wavefront's minimum of (1/w, neighbour)
     for (int z = 0; z < 2; ++z) {
       const uint32_t end = z == 0 ? P.p : P.q;
+      double br;
+      uint32_t bn, bi;
       const RowHdr r = row_hdr(G, end);
       const Seg seg = seg_of(G, end, r.off);
-      const RowHdr hr = row_hdr(H, end);
-      const Seg hseg = seg_of(H, end, hr.off);
-      // each lane merges a contiguous slice of the G row against the H row
-      // (both sorted by neighbour): one search into H, then forward steps
-      const uint32_t per = (r.len + kWave - 1) / kWave;
-      const uint32_t a0 = lane * per < r.len ? lane * per : r.len;
-      const uint32_t a1 = a0 + per < r.len ? a0 + per : r.len;
-      uint32_t j = a0 < a1 ? lower_nbr(hseg, hr.len, seg.nbr(a0)) : hr.len;
-      double br = INFINITY;
-      uint32_t bn = kNone, bi = 0;
-      for (uint32_t i = a0; i < a1; ++i) {
-        const Ent e = seg.get(i);
-        if (e.qw == 0u) continue;
-        while (j < hr.len && hseg.nbr(j) < e.nbr) ++j;
-        if (j < hr.len && hseg.nbr(j) == e.nbr && hseg.qw(j) != 0u) continue;  // live in H
-        if (e.rinv < br || (e.rinv == br && e.nbr < bn)) {
-          br = e.rinv;
-          bn = e.nbr;
-          bi = i;
-        }
-      }
+      fallback_slice(G, H, end, lane, kWave, br, bn, bi);
       double wr = br;
       uint32_t wn = bn;
       wave_argmin(wr, wn);
@@ -1515,6 +1566,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   P.heavy = a0.ctl->heavy != 0u;
   P.rows = a0.g[1].rows;
   P.ent = a0.g[1].ent;
+  P.prinv = a0.g[1].prinv;
   P.pfx = a0.g[1].pfx;
   P.tree = a0.g[1].tree;
   P.rinl = a0.g[1].rinl;
@@ -1578,6 +1630,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         const int gw = is_ins ? 1 : 0;  // H_mid for insertions, G_mid for deletions
         P.rows = load_gptr(&A->g[gw].rows);
         P.ent = load_gptr(&A->g[gw].ent);
+        P.prinv = load_gptr(&A->g[gw].prinv);
         P.pfx = load_gptr(&A->g[gw].pfx);
         P.tree = load_gptr(&A->g[gw].tree);
         P.rinl = load_gptr(&A->g[gw].rinl);
@@ -1590,6 +1643,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         const DevGraph& X = is_ins ? a0.g[1] : a0.g[0];  // H_mid / G_mid
         P.rows = X.rows;
         P.ent = X.ent;
+        P.prinv = X.prinv;
         P.pfx = X.pfx;
         P.tree = X.tree;
         P.rinl = X.rinl;
@@ -1643,6 +1697,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
   P.heavy = a.ctl->heavy != 0u;
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
+  P.prinv = a.g[1].prinv;
   P.pfx = a.g[1].pfx;
   P.tree = a.g[1].tree;
   P.rinl = a.g[1].rinl;
@@ -1686,6 +1741,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
         const DevGraph& X = is_ins ? a.g[1] : a.g[0];  // H_mid for insertions, G_mid for deletions
         P.rows = X.rows;
         P.ent = X.ent;
+        P.prinv = X.prinv;
         P.pfx = X.pfx;
         P.tree = X.tree;
         P.rinl = X.rinl;
@@ -1788,6 +1844,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
   P.heavy = a.ctl->heavy != 0u;
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
+  P.prinv = a.g[1].prinv;
   P.pfx = a.g[1].pfx;
   P.tree = a.g[1].tree;
   P.rinl = a.g[1].rinl;
@@ -1830,6 +1887,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
         const DevGraph& X = is_ins ? a.g[1] : a.g[0];  // H_mid for insertions, G_mid for deletions
         P.rows = X.rows;
         P.ent = X.ent;
+        P.prinv = X.prinv;
         P.pfx = X.pfx;
         P.tree = X.tree;
         P.rinl = X.rinl;
@@ -1903,6 +1961,62 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
   }
   if (lane == 0) a.ubytes[upd] = bytes;
   decide_update<kHubs>(a, G, H, upd, v, any_hit, bestR, bestW, steps, lane);
+}
+
+// No-hit fallbacks of deletions at long G rows (listed by decide_update):
+// one workgroup per deletion, its kBlock threads scanning slices of each
+// endpoint's G row, then the workgroup's minimum of (1/w, neighbour).  Writes
+// the deletion's fallback slots and n_rec (the rest of its result is final).
+__global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const* __restrict__ argv) {
+  const BatchArgs a = load_args(argv, blockIdx.y);
+  if (batch_failed(a.ctl)) return;
+  const uint32_t count = a.ctl->fb_count;
+  const DevGraph G = a.g[0];
+  const DevGraph H = a.g[1];
+  __shared__ double s_r[kBlock / kWave];
+  __shared__ uint32_t s_n[kBlock / kWave];
+  __shared__ uint32_t s_count;
+  const uint32_t t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+  for (uint32_t f = blockIdx.x; f < count; f += gridDim.x) {
+    const uint32_t upd = a.fb_list[f];
+    const uint32_t j = upd - a.n_ins;
+    const uint32_t p = a.du[j], q = a.dv[j];
+    AddRec* out = del_slots(a, upd);
+    if (t == 0) s_count = 0;
+    __syncthreads();
+    for (int z = 0; z < 2; ++z) {
+      const uint32_t end = z == 0 ? p : q;
+      double br;
+      uint32_t bn, bi;
+      fallback_slice(G, H, end, t, kBlock, br, bn, bi);
+      double wr = br;
+      uint32_t wn = bn;
+      wave_argmin(wr, wn);
+      if (lane == 0) {
+        s_r[wv] = wr;
+        s_n[wv] = wn;
+      }
+      __syncthreads();
+      for (uint32_t k = 0; k < kBlock / kWave; ++k)  // same order on every thread
+        if (s_r[k] < wr || (s_r[k] == wr && s_n[k] < wn)) {
+          wr = s_r[k];
+          wn = s_n[k];
+        }
+      const uint32_t c = s_count;
+      if (wn != kNone && bn == wn) {  // neighbour ids are unique: one owner
+        const RowHdr r = row_hdr(G, end);
+        const Seg seg = seg_of(G, end, r.off);
+        out[c] = AddRec{end, wn, seg.qw(bi), 0u, seg.r(bi), seg.w[bi]};
+      }
+      __syncthreads();
+      if (t == 0 && wn != kNone) s_count = c + 1;
+      __syncthreads();
+    }
+    const uint32_t n = s_count;
+    for (uint32_t zz = n + t; zz < a.Lcap; zz += kBlock) out[zz] = kNoAdd;
+    if (t == 0) a.res[upd].n_rec = static_cast<uint16_t>(n);
+    __syncthreads();
+  }
 }
 
 // Batch totals of walker steps and algorithmic bytes (from the per-update
@@ -2067,7 +2181,8 @@ __device__ __forceinline__ bool tree_ready(const RowHdr& row) {
   return row.off != kInlineOff && row.off % kHubAlign == 0 && row.cap % kFan == 0;
 }
 
-// First slot of a relocated segment reserved with reserve_slots(cap, align).
+// First slot of a relocated segment whose reservation starts at `raw` (an
+// aligned segment reserves kHubAlign slots more than its capacity).
 __device__ __forceinline__ uint32_t relocated_off(unsigned long long raw, bool align) {
   return static_cast<uint32_t>(align ? (raw + kHubAlign - 1) / kHubAlign * kHubAlign : raw);
 }
@@ -2088,9 +2203,10 @@ __global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, uint32_t 
   if (row.len + k > row.cap || (row.len + k > kHub && !tree_ready(row))) {
     const uint32_t live = row.len - row.dead + k;  // relocation drops the tombstones
     const bool align = live > kHub;
-    need = align ? round_fan(grown_cap(live)) : grown_cap(live);
-    // an aligned start may skip up to kHubAlign - 1 slots
-    const uint32_t reserve = align ? need + kHubAlign - 1 : need;
+    // even capacities keep every segment start even (two pairs per load)
+    need = align ? round_fan(grown_cap(live)) : (grown_cap(live) + 1u) & ~1u;
+    // an aligned start may skip up to kHubAlign - 2 slots (reserved: kHubAlign)
+    const uint32_t reserve = align ? need + kHubAlign : need;
     atomicAdd(&a.ctl->need[which], static_cast<unsigned long long>(reserve));
     if (row.len > kHub) flags |= kWideRelocate;
     if (align) flags |= kAlignHub;
@@ -2128,13 +2244,14 @@ __device__ __forceinline__ void rows_relocate_narrow(const BatchArgs* const* __r
   const bool align = (a.touched_k[t] & kAlignHub) != 0;
   const uint32_t off = relocated_off(
       atomicAdd(&a.ctl->pool_top[which],
-                static_cast<unsigned long long>(align ? need + kHubAlign - 1 : need)),
+                static_cast<unsigned long long>(align ? need + kHubAlign : need)),
       align);
   uint32_t o = 0;
   for (uint32_t i = 0; i < row.len; ++i) {
     const Ent e = src.get(i);
     if (e.qw == 0u) continue;  // drop tombstones while moving
-    X.ent[off + o] = e;
+    X.ent[off + o] = Pair{e.nbr, e.qw};
+    X.prinv[off + o] = e.rinv;
     X.w[off + o] = src.w[i];
     ++o;
   }
@@ -2161,17 +2278,18 @@ __device__ __forceinline__ void rows_relocate_wide(const BatchArgs* const* __res
     if (threadIdx.x == 0)
       s_off = relocated_off(
           atomicAdd(&a.ctl->pool_top[which],
-                    static_cast<unsigned long long>(align ? need + kHubAlign - 1 : need)),
+                    static_cast<unsigned long long>(align ? need + kHubAlign : need)),
           align);
     __syncthreads();
     const uint32_t off = s_off;
     unsigned long long out = 0;
     for (uint32_t base = 0; base < row.len; base += kBlock) {
       const uint32_t i = base + threadIdx.x;
-      Ent e{0, 0, 0.0};
-      double we = 0.0;
+      Pair e{0, 0};
+      double er = 0.0, we = 0.0;
       if (i < row.len) {
         e = X.ent[row.off + i];
+        er = X.prinv[row.off + i];
         we = X.w[row.off + i];
       }
       const unsigned long long live = (i < row.len && e.qw != 0u) ? 1u : 0u;
@@ -2179,6 +2297,7 @@ __device__ __forceinline__ void rows_relocate_wide(const BatchArgs* const* __res
       const unsigned long long total = block_excl_scan(live, excl);
       if (live) {
         X.ent[off + out + excl] = e;
+        X.prinv[off + out + excl] = er;
         X.w[off + out + excl] = we;
       }
       out += total;
@@ -2273,7 +2392,8 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
     const uint32_t r = a.touched_rows[t];
     const uint32_t k = packed & kCountMask;
     const RowHdr row = row_hdr(X, r);  // relocated or long: a pool segment
-    Ent* seg = X.ent + row.off;
+    Pair* seg = X.ent + row.off;
+    double* rseg = X.prinv + row.off;
     double* wseg = X.w + row.off;
     uint32_t cur = row.len;  // sorted prefix length
     for (uint32_t c0 = 0; c0 < k; c0 += kTailChunk) {
@@ -2282,7 +2402,7 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
       while (P < c) P <<= 1;
       for (uint32_t j = threadIdx.x; j < P; j += kBlock) {
         if (j < c) {
-          s_ent[j] = seg[cur + j];
+          s_ent[j] = Ent{seg[cur + j].nbr, seg[cur + j].qw, rseg[cur + j]};
           s_w[j] = wseg[cur + j];
           s_key[j] = (static_cast<unsigned long long>(s_ent[j].nbr) << 32) | j;
         } else {
@@ -2332,10 +2452,10 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
         for (uint32_t m = 0; m < kMergePer; ++m) {
           const uint32_t i = lo_i + m * kBlock + threadIdx.x;
           const uint32_t ii = i < hi_i ? i : lo_i;  // in range either way
-          const Ent x = seg[ii];
+          const Pair x = seg[ii];
           en[m] = x.nbr;
           eq[m] = x.qw;
-          er[m] = x.rinv;
+          er[m] = rseg[ii];
           we[m] = wseg[ii];
           shift[m] = 0;
         }
@@ -2356,7 +2476,8 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
         for (uint32_t m = 0; m < kMergePer; ++m) {
           const uint32_t i = lo_i + m * kBlock + threadIdx.x;
           if (i < hi_i && shift[m]) {
-            seg[i + shift[m]] = Ent{en[m], eq[m], er[m]};
+            seg[i + shift[m]] = Pair{en[m], eq[m]};
+            rseg[i + shift[m]] = er[m];
             wseg[i + shift[m]] = we[m];
           }
         }
@@ -2365,7 +2486,8 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
       }
       for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
         const uint32_t src = static_cast<uint32_t>(s_key[j] & 0xFFFFFFFFull);
-        seg[s_pos[j]] = s_ent[src];
+        seg[s_pos[j]] = Pair{s_ent[src].nbr, s_ent[src].qw};
+        rseg[s_pos[j]] = s_ent[src].rinv;
         wseg[s_pos[j]] = s_w[src];
       }
       __syncthreads();
@@ -2444,6 +2566,13 @@ inline dim3 grid_of(uint64_t n, uint32_t F, uint32_t per = kBlock) {
   const uint64_t b = (n + per - 1) / per;
   return dim3(static_cast<uint32_t>(b ? b : 1), F);
 }
+
+// Deferred fallbacks of the walk step (only deletions can have one).
+void launch_fallback_wide(const Launch& L, hipStream_t st) {
+  if (L.max_del == 0) return;
+  const uint32_t nb = L.max_del < kWideBlocks ? L.max_del : kWideBlocks;
+  k_fallback_wide<<<dim3(nb, L.F), kBlock, 0, st>>>(L.argv);
+}
 }  // namespace
 
 void launch_batch_begin(const Launch& L, hipStream_t st) {
@@ -2470,6 +2599,7 @@ void launch_walks(const Launch& L, hipStream_t st) {
   else if (L.hubs) k_walks<true, false><<<g, kWalkBlock, 0, st>>>(L.argv);
   else if (L.coop) k_walks<false, true><<<g, kWalkBlock, 0, st>>>(L.argv);
   else k_walks<false, false><<<g, kWalkBlock, 0, st>>>(L.argv);
+  launch_fallback_wide(L, st);
 }
 
 void launch_sum_counters(const Launch& L, hipStream_t st) {
@@ -2518,6 +2648,7 @@ void launch_queue_finish(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
   if (L.hubs) k_reduce_updates<true><<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
   else k_reduce_updates<false><<<grid_of(L.max_nu, L.F, kWalkBlock / kWave), kWalkBlock, 0, st>>>(L.argv);
+  launch_fallback_wide(L, st);
 }
 
 namespace {
