@@ -107,6 +107,10 @@ def _load():
     lib.orc_query.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(C.c_uint64), P, P, P]
     lib.orc_query.restype = C.c_int
     lib.orc_last_recovered.argtypes = [P, C.c_uint64, C.c_uint32, P, P]
+    lib.orc_sample_key.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_sample_key.restype = C.c_uint64
+    lib.orc_initial_sparsifier.argtypes = [C.c_uint32, P, P, P, C.c_uint64, C.c_uint64, P]
+    lib.orc_initial_sparsifier.restype = C.c_long
     lib.orc_last_recovered.restype = C.c_long
     del u8p
     _lib = lib
@@ -182,6 +186,37 @@ def walk_csr(n, rowptr, col, w, p, q, *, s, L, seed=0, uid=0, K=math.inf, w_pq=1
 
 # --------------------------------------------------------------------------
 # full state
+
+
+def sample_key(seed: int, e: int) -> int:
+    """Key of edge e in the off-tree sample of the initial sparsifier."""
+    return int(_load().orc_sample_key(seed, e))
+
+
+def canonical_edges(n, rowptr, col, w):
+    """The edges (u, v), u < v, of a symmetric CSR in ascending (u, v) order:
+    edge e of the initial-sparsifier rule is row e of the result."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    col = np.asarray(col)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    keep = col > src
+    return src[keep].astype(np.uint32), col[keep].astype(np.uint32), np.asarray(w)[keep]
+
+
+def initial_sparsifier(n, rowptr, col, w, n_extra, seed):
+    """H(0) = maximum spanning forest (Kruskal, ties to the smaller edge
+    index) + the n_extra off-tree edges of smallest sample key; returns the
+    flag per canonical edge (see canonical_edges)."""
+    rowptr = _arr(rowptr, np.uint64)
+    col = _arr(col, np.uint32)
+    w = _arr(w, np.float64)
+    m = int((col > np.repeat(np.arange(n, dtype=np.uint64), np.diff(rowptr.astype(np.int64)))).sum())
+    in_h = np.zeros(max(m, 1), dtype=np.uint8)
+    rc = _load().orc_initial_sparsifier(n, _ptr(rowptr), _ptr(col), _ptr(w), n_extra, seed,
+                                        _ptr(in_h))
+    if rc < 0:
+        raise OracleError(rc)
+    return in_h[:m].astype(bool)
 
 
 class Oracle:

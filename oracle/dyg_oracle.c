@@ -844,3 +844,124 @@ int orc_query(const oracle_t *o, int which, uint64_t cap, uint64_t *m,
       }
   return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Initial sparsifier (the step before the update path: H(0) of Algorithm  */
+/* 1, built here the way the experiments' synthetic stand-ins build it).    */
+/* Edges are the pairs (u,v), u < v, of the symmetric CSR in ascending      */
+/* (u,v) order; edge e is the e-th of them.                                 */
+/*  1. Maximum spanning forest: Kruskal over the edges by decreasing        */
+/*     weight, ties to the smaller edge index; an edge is kept iff its ends */
+/*     are in different components so far.  The order is strict, so the    */
+/*     forest is unique.                                                    */
+/*  2. Off-tree sample: of the edges left out, the n_extra with the         */
+/*     smallest 64-bit key, ties to the smaller edge index, where key(e) is */
+/*     output words 0-1 of Philox-4x32-10 with key (seed low, seed high)    */
+/*     and counter (e low, e high, 0, 0x53504152); i.i.d. uniform keys make */
+/*     this a uniform sample without replacement.                           */
+/* in_h[e] = 1 for the edges of H(0).  Returns the edge count of H(0), or a */
+/* negative error code.                                                     */
+
+typedef struct {
+  double w;
+  uint64_t e;
+} o_wedge;
+
+static int cmp_wdesc_idx(const void *a, const void *b) {
+  const o_wedge *x = (const o_wedge *)a, *y = (const o_wedge *)b;
+  if (x->w != y->w) return x->w > y->w ? -1 : 1;
+  return x->e < y->e ? -1 : (x->e > y->e ? 1 : 0);
+}
+
+typedef struct {
+  uint64_t key;
+  uint64_t e;
+} o_kedge;
+
+static int cmp_key_idx(const void *a, const void *b) {
+  const o_kedge *x = (const o_kedge *)a, *y = (const o_kedge *)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->e < y->e ? -1 : (x->e > y->e ? 1 : 0);
+}
+
+static uint32_t uf_find(uint32_t *parent, uint32_t x) {
+  uint32_t r = x;
+  while (parent[r] != r) r = parent[r];
+  while (parent[x] != r) {
+    uint32_t nx = parent[x];
+    parent[x] = r;
+    x = nx;
+  }
+  return r;
+}
+
+uint64_t orc_sample_key(uint64_t seed, uint64_t e) {
+  uint32_t ctr[4] = {(uint32_t)e, (uint32_t)(e >> 32), 0u, 0x53504152u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t x[4];
+  orc_philox4x32_10(ctr, key, x);
+  return (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+}
+
+long orc_initial_sparsifier(uint32_t n, const uint64_t *rowptr, const uint32_t *col,
+                            const double *w, uint64_t n_extra, uint64_t seed,
+                            uint8_t *in_h) {
+  if (!rowptr || (rowptr[n] && (!col || !w))) return ORC_INVALID_ARG;
+  uint64_t m = 0;
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k)
+      if (col[k] > u) ++m;
+  uint32_t *eu = malloc(sizeof(uint32_t) * (m ? m : 1));
+  uint32_t *ev = malloc(sizeof(uint32_t) * (m ? m : 1));
+  o_wedge *order = malloc(sizeof(o_wedge) * (m ? m : 1));
+  uint32_t *parent = malloc(sizeof(uint32_t) * (n ? n : 1));
+  if (!eu || !ev || !order || !parent) {
+    free(eu); free(ev); free(order); free(parent);
+    return ORC_NOMEM;
+  }
+  uint64_t e = 0;
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k)
+      if (col[k] > u) {
+        eu[e] = u;
+        ev[e] = col[k];
+        order[e].w = w[k];
+        order[e].e = e;
+        ++e;
+      }
+  qsort(order, m, sizeof(o_wedge), cmp_wdesc_idx);
+  for (uint32_t x = 0; x < n; ++x) parent[x] = x;
+  memset(in_h, 0, m);
+  long count = 0;
+  for (uint64_t i = 0; i < m; ++i) {
+    const uint64_t f = order[i].e;
+    const uint32_t a = uf_find(parent, eu[f]), b = uf_find(parent, ev[f]);
+    if (a == b) continue;
+    parent[a] = b;
+    in_h[f] = 1;
+    ++count;
+  }
+  free(order);
+  free(parent);
+  o_kedge *off = malloc(sizeof(o_kedge) * ((m - (uint64_t)count) ? (m - (uint64_t)count) : 1));
+  if (!off) {
+    free(eu); free(ev);
+    return ORC_NOMEM;
+  }
+  uint64_t n_off = 0;
+  for (uint64_t f = 0; f < m; ++f)
+    if (!in_h[f]) {
+      off[n_off].key = orc_sample_key(seed, f);
+      off[n_off].e = f;
+      ++n_off;
+    }
+  qsort(off, n_off, sizeof(o_kedge), cmp_key_idx);
+  for (uint64_t i = 0; i < n_off && i < n_extra; ++i) {
+    in_h[off[i].e] = 1;
+    ++count;
+  }
+  free(off);
+  free(eu);
+  free(ev);
+  return count;
+}

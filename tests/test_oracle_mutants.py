@@ -85,7 +85,30 @@ MUTANTS = {
                               "static int weight_ok(double w) { return w > 0.0 && !isinf(w); }"),
 }
 
-PIN_FILES = ("test_oracle_pins.py", "test_oracle_recovery.py")
+# --- initial sparsifier (maximum spanning forest + keyed off-tree sample) ---
+MUTANTS.update({
+    # minimum instead of maximum spanning forest
+    "forest_min_weight": ("if (x->w != y->w) return x->w > y->w ? -1 : 1;",
+                          "if (x->w != y->w) return x->w < y->w ? -1 : 1;"),
+    # weight ties to the larger edge index
+    "forest_ties_larger": ("  return x->e < y->e ? -1 : (x->e > y->e ? 1 : 0);\n}\n\ntypedef struct {\n"
+                           "  uint64_t key;",
+                           "  return x->e > y->e ? -1 : (x->e < y->e ? 1 : 0);\n}\n\ntypedef struct {\n"
+                           "  uint64_t key;"),
+    # an edge closing a cycle is kept
+    "forest_keeps_cycles": ("    if (a == b) continue;\n    parent[a] = b;",
+                            "    parent[a] = b;"),
+    # the sample takes the largest keys
+    "sample_largest": ("const o_kedge *x = (const o_kedge *)a, *y = (const o_kedge *)b;\n"
+                       "  if (x->key != y->key) return x->key < y->key ? -1 : 1;",
+                       "const o_kedge *x = (const o_kedge *)a, *y = (const o_kedge *)b;\n"
+                       "  if (x->key != y->key) return x->key > y->key ? -1 : 1;"),
+    # off by one in the sample: the smallest key is skipped
+    "sample_skips_first": ("for (uint64_t i = 0; i < n_off && i < n_extra; ++i) {",
+                           "for (uint64_t i = 1; i < n_off && i <= n_extra; ++i) {"),
+})
+
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_recovery.py", "test_oracle_sparsifier.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
