@@ -107,6 +107,8 @@ def _load():
     lib.orc_query.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(C.c_uint64), P, P, P]
     lib.orc_query.restype = C.c_int
     lib.orc_last_recovered.argtypes = [P, C.c_uint64, C.c_uint32, P, P]
+    lib.orc_set_variant.argtypes = [P, C.c_int]
+    lib.orc_set_variant.restype = C.c_int
     lib.orc_sample_key.argtypes = [C.c_uint64, C.c_uint64]
     lib.orc_sample_key.restype = C.c_uint64
     lib.orc_initial_sparsifier.argtypes = [C.c_uint32, P, P, P, C.c_uint64, C.c_uint64, P]
@@ -219,11 +221,17 @@ def initial_sparsifier(n, rowptr, col, w, n_extra, seed):
     return in_h[:m].astype(bool)
 
 
+# variants of the update rule (Sec. III-C, III-F), off by default
+BOTH_ENDS = 1     # odd walkers start at the second endpoint
+LOOP_ERASED = 2   # a hitting deletion recovers its loop-erased path
+TWO_STAGE = 4     # deletions and their recoveries before the insertion walks
+
+
 class Oracle:
     """Sequence of batches on (G, H) exactly as the batch rules define them."""
 
     def __init__(self, n, rowptr, col, w, hu, hv, *, seed, K=math.inf, s=8, L=16, Q=24,
-                 w_ref=0.0, dead_end=0, uid_base=0):
+                 w_ref=0.0, dead_end=0, uid_base=0, variant=0):
         lib = _load()
         self.n = int(n)
         rowptr = _arr(rowptr, np.uint64)
@@ -237,6 +245,12 @@ class Oracle:
                                  float(w_ref), int(dead_end), int(uid_base), C.byref(err))
         if not self._h:
             raise OracleError(err.value)
+        if variant:
+            rc = lib.orc_set_variant(self._h, int(variant))
+            if rc:
+                lib.orc_destroy(self._h)
+                self._h = None
+                raise OracleError(rc)
         self.s = int(s)
         self.L = int(L)
 

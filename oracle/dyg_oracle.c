@@ -68,6 +68,21 @@ enum {
   ORC_NOMEM = -9
 };
 
+/* Variants (all off by default):
+ *  BOTH_ENDS    walker k starts at the second endpoint and aims at the first
+ *               when k is odd (deletion walks "from p (or from q)", Sec.
+ *               III-C; insertions alike);
+ *  LOOP_ERASED  a hitting deletion recovers the edges of the chronological
+ *               loop erasure of the winner's path (not in H) instead of
+ *               every traversed edge;
+ *  TWO_STAGE    the batch's deletion walks and their recoveries come first
+ *               and enter H before the insertion walks, which then read the
+ *               repaired H (the updates stay deferred to the batch end
+ *               otherwise, Sec. III-F). */
+#define ORC_VAR_BOTH_ENDS 1
+#define ORC_VAR_LOOP_ERASED 2
+#define ORC_VAR_TWO_STAGE 4
+
 #define ORC_MAX_WALKERS 1024u
 #define ORC_MAX_STEPS 1024u
 
@@ -395,6 +410,7 @@ typedef struct {
   int Q;
   double w_ref;
   int bounce;
+  int variant; /* ORC_VAR_* bits: the alternatives of Sec. III-C and III-F */
   uint64_t uid_base;
   uint64_t steps_total;     /* walker steps taken since creation */
   uint64_t alg_bytes_total; /* bytes those steps must gather */
@@ -507,6 +523,7 @@ oracle_t *orc_create(uint32_t n, const uint64_t *rowptr, const uint32_t *col,
   o->Q = Q;
   o->w_ref = (w_ref > 0.0) ? w_ref : (wmax > 0.0 ? wmax : 1.0);
   o->bounce = dead_end;
+  o->variant = 0;
   o->uid_base = uid_base;
   for (uint32_t u = 0; u < n; ++u) {
     uint32_t d = (uint32_t)(rowptr[u + 1] - rowptr[u]);
@@ -588,6 +605,13 @@ long orc_last_recovered(const oracle_t *o, uint64_t j, uint32_t cap, uint32_t *a
   return (long)cnt;
 }
 
+int orc_set_variant(oracle_t *o, int variant) {
+  if (variant & ~(ORC_VAR_BOTH_ENDS | ORC_VAR_LOOP_ERASED | ORC_VAR_TWO_STAGE))
+    return ORC_INVALID_ARG;
+  o->variant = variant;
+  return ORC_OK;
+}
+
 uint64_t orc_uid_base(const oracle_t *o) { return o->uid_base; }
 uint64_t orc_steps_total(const oracle_t *o) { return o->steps_total; }
 uint64_t orc_alg_bytes_total(const oracle_t *o) { return o->alg_bytes_total; }
@@ -648,6 +672,150 @@ static int o_validate(const oracle_t *o, uint64_t n_ins, const uint32_t *iu,
  * Per-walker outputs (optional, length sum of s over updates, in update
  * order; deletions whose edge is not in H report zero steps at u).
  */
+/* Walks and decision of update i of the batch (phase 2), on the current
+ * G and H; writes its results, its acceptance flag or recovered edges. */
+static void o_update(oracle_t *o, uint64_t i, uint64_t n_ins, const uint32_t *iu,
+                     const uint32_t *iv, const double *iw, const uint32_t *du,
+                     const uint32_t *dv, const uint16_t *s, const uint16_t *L,
+                     const uint8_t *inH, uint8_t *acc, const uint64_t *wofs,
+                     const uint64_t *rofs, uint32_t *rec_a, uint32_t *rec_b, uint32_t *nrec,
+                     uint8_t *flag, uint8_t *any_hit, uint16_t *winner, uint16_t *n_rec,
+                     uint32_t *steps, double *Rmin, uint8_t *w_hit, uint16_t *w_steps,
+                     uint32_t *w_end, double *w_R) {
+  uint64_t uid = o->uid_base + i;
+  uint32_t si = s ? s[i] : o->s_def;
+  uint32_t Li = L ? L[i] : o->L_def;
+  int is_ins = i < n_ins;
+  uint64_t j = i - n_ins;
+  uint32_t p = is_ins ? iu[i] : du[j];
+  uint32_t q = is_ins ? iv[i] : dv[j];
+  uint8_t fl = 0, anyh = 0;
+  uint16_t win = 0xFFFF, nr = 0;
+  uint32_t st = 0;
+  uint64_t by = 0;
+  double rmin = INFINITY;
+  if (is_ins || inH[j]) {
+    const ograph *X = is_ins ? &o->H : &o->G; /* H_mid / G_mid */
+    uint32_t *traj = (uint32_t *)malloc((size_t)si * (Li + 1) * sizeof(uint32_t) + 4);
+    owalk *res = (owalk *)malloc((size_t)si * sizeof(owalk) + 1);
+    for (uint32_t k = 0; k < si; ++k) {
+      /* odd walkers from the second endpoint towards the first (variant) */
+      const int flip = (o->variant & ORC_VAR_BOTH_ENDS) && (k & 1u);
+      o_walk_one(X, flip ? q : p, flip ? p : q, is_ins && o->has_K, is_ins ? iw[i] : 0.0,
+                 o->K, Li, o->seed, uid, k, o->bounce, &res[k],
+                 traj + (size_t)k * (Li + 1));
+      st += res[k].steps;
+      by += res[k].bytes;
+      if (res[k].hit) {
+        anyh = 1;
+        /* minimum resistance over hitting walkers, ties to the lower index
+         * (a sum that overflowed to +inf still names a walker) */
+        if (win == 0xFFFF || res[k].R < rmin) {
+          rmin = res[k].R;
+          win = (uint16_t)k;
+        }
+      }
+      if (w_hit) {
+        w_hit[wofs[i] + k] = res[k].hit;
+        w_steps[wofs[i] + k] = res[k].steps;
+        w_end[wofs[i] + k] = res[k].end;
+        w_R[wofs[i] + k] = res[k].R;
+      }
+    }
+    if (is_ins) {
+      fl = (uint8_t)!anyh; /* keep the new edge iff no walker reached q */
+      acc[i] = fl;
+    } else {
+      fl = 1;
+      uint32_t *ra = rec_a + rofs[j], *rb = rec_b + rofs[j];
+      if (anyh) {
+        /* edges of the winning path, first occurrence, not already in H;
+         * with LOOP_ERASED the path is first loop-erased in time order:
+         * a vertex met again cuts the loop back to its first visit */
+        const uint32_t *path = traj + (size_t)win * (Li + 1);
+        uint32_t plen = res[win].steps + 1;
+        uint32_t *le = NULL;
+        if (o->variant & ORC_VAR_LOOP_ERASED) {
+          le = (uint32_t *)malloc(sizeof(uint32_t) * plen);
+          uint32_t len = 0;
+          for (uint32_t t = 0; t < plen; ++t) {
+            uint32_t z = 0;
+            while (z < len && le[z] != path[t]) ++z;
+            if (z < len) len = z + 1;
+            else le[len++] = path[t];
+          }
+          path = le;
+          plen = len;
+        }
+        for (uint32_t t = 0; t + 1 < plen; ++t) {
+          uint32_t a = path[t], b = path[t + 1];
+          if (og_has(&o->H, a, b)) continue;
+          int seen = 0;
+          for (uint32_t z = 0; z < nr; ++z)
+            if (ekey(ra[z], rb[z]) == ekey(a, b)) seen = 1;
+          if (seen) continue;
+          ra[nr] = a;
+          rb[nr] = b;
+          nr++;
+        }
+        free(le);
+      } else {
+        /* no hit: per endpoint, the least-resistance G edge not in H,
+         * ties to the smaller neighbour id */
+        uint32_t ends[2] = {p, q};
+        for (int z = 0; z < 2; ++z) {
+          const orow *row = &o->G.rows[ends[z]];
+          long best = -1;
+          for (uint32_t t = 0; t < row->len; ++t) {
+            if (og_has(&o->H, ends[z], row->e[t].nbr)) continue;
+            if (best < 0 || row->e[t].r < row->e[best].r) best = (long)t;
+          }
+          if (best >= 0) {
+            ra[nr] = ends[z];
+            rb[nr] = row->e[best].nbr;
+            nr++;
+          }
+        }
+      }
+      nrec[j] = nr;
+    }
+    free(traj);
+    free(res);
+  } else if (w_hit) {
+    for (uint32_t k = 0; k < si; ++k) {
+      w_hit[wofs[i] + k] = 0;
+      w_steps[wofs[i] + k] = 0;
+      w_end[wofs[i] + k] = p;
+      w_R[wofs[i] + k] = 0.0;
+    }
+  }
+#pragma omp atomic
+  o->steps_total += st;
+#pragma omp atomic
+  o->alg_bytes_total += by;
+  if (flag) flag[i] = fl;
+  if (any_hit) any_hit[i] = anyh;
+  if (winner) winner[i] = win;
+  if (n_rec) n_rec[i] = nr;
+  if (steps) steps[i] = st;
+  if (Rmin) Rmin[i] = rmin;
+}
+
+/* H += the recovered and fallback edges of the batch's deletions (a set
+ * union; their weights are G's). */
+static void o_add_recovered(oracle_t *o, uint64_t n_del, const uint64_t *rofs,
+                            const uint32_t *rec_a, const uint32_t *rec_b,
+                            const uint32_t *nrec) {
+  for (uint64_t j = 0; j < n_del; ++j) {
+    for (uint32_t z = 0; z < nrec[j]; ++z) {
+      uint32_t a = rec_a[rofs[j] + z], b = rec_b[rofs[j] + z];
+      if (og_has(&o->H, a, b)) continue;
+      const oent *ge = &o->G.rows[a].e[og_find(&o->G, a, b)];
+      og_add(&o->H, a, b, ge->w, ge->r, ge->qw);
+    }
+  }
+}
+
 int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
                     const uint32_t *iv, const double *iw, uint64_t n_del,
                     const uint32_t *du, const uint32_t *dv, const uint16_t *s,
@@ -689,109 +857,20 @@ int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
   uint32_t *rec_b = (uint32_t *)malloc((rofs[n_del] + 1) * sizeof(uint32_t));
   uint32_t *nrec = (uint32_t *)calloc(n_del + 1, sizeof(uint32_t));
 
-  /* Phase 2: walks.  Every update reads only the batch snapshot (G_mid,
-   * H_mid), so the loop order is immaterial. */
+  /* Phase 2: walks, deletions first.  Within a stage every update reads
+   * only that stage's snapshot, so the loop order is immaterial.  Single
+   * stage: the insertions also read H_mid.  TWO_STAGE: the deletions'
+   * recovered edges enter H before the insertion walks. */
+  const int two = o->variant & ORC_VAR_TWO_STAGE;
 #pragma omp parallel for schedule(dynamic, 16)
-  for (long long ii = 0; ii < (long long)nu; ++ii) {
-    uint64_t i = (uint64_t)ii;
-    uint64_t uid = o->uid_base + i;
-    uint32_t si = s ? s[i] : o->s_def;
-    uint32_t Li = L ? L[i] : o->L_def;
-    int is_ins = i < n_ins;
-    uint64_t j = i - n_ins;
-    uint32_t p = is_ins ? iu[i] : du[j];
-    uint32_t q = is_ins ? iv[i] : dv[j];
-    uint8_t fl = 0, anyh = 0;
-    uint16_t win = 0xFFFF, nr = 0;
-    uint32_t st = 0;
-    uint64_t by = 0;
-    double rmin = INFINITY;
-    if (is_ins || inH[j]) {
-      const ograph *X = is_ins ? &o->H : &o->G; /* H_mid / G_mid */
-      uint32_t *traj = (uint32_t *)malloc((size_t)si * (Li + 1) * sizeof(uint32_t) + 4);
-      owalk *res = (owalk *)malloc((size_t)si * sizeof(owalk) + 1);
-      for (uint32_t k = 0; k < si; ++k) {
-        o_walk_one(X, p, q, is_ins && o->has_K, is_ins ? iw[i] : 0.0, o->K, Li,
-                   o->seed, uid, k, o->bounce, &res[k], traj + (size_t)k * (Li + 1));
-        st += res[k].steps;
-        by += res[k].bytes;
-        if (res[k].hit) {
-          anyh = 1;
-          /* minimum resistance over hitting walkers, ties to the lower index
-           * (a sum that overflowed to +inf still names a walker) */
-          if (win == 0xFFFF || res[k].R < rmin) {
-            rmin = res[k].R;
-            win = (uint16_t)k;
-          }
-        }
-        if (w_hit) {
-          w_hit[wofs[i] + k] = res[k].hit;
-          w_steps[wofs[i] + k] = res[k].steps;
-          w_end[wofs[i] + k] = res[k].end;
-          w_R[wofs[i] + k] = res[k].R;
-        }
-      }
-      if (is_ins) {
-        fl = (uint8_t)!anyh; /* keep the new edge iff no walker reached q */
-        acc[i] = fl;
-      } else {
-        fl = 1;
-        uint32_t *ra = rec_a + rofs[j], *rb = rec_b + rofs[j];
-        if (anyh) {
-          /* edges of the winning path, first occurrence, not already in H */
-          const uint32_t *path = traj + (size_t)win * (Li + 1);
-          for (uint32_t t = 0; t < res[win].steps; ++t) {
-            uint32_t a = path[t], b = path[t + 1];
-            if (og_has(&o->H, a, b)) continue;
-            int seen = 0;
-            for (uint32_t z = 0; z < nr; ++z)
-              if (ekey(ra[z], rb[z]) == ekey(a, b)) seen = 1;
-            if (seen) continue;
-            ra[nr] = a;
-            rb[nr] = b;
-            nr++;
-          }
-        } else {
-          /* no hit: per endpoint, the least-resistance G edge not in H,
-           * ties to the smaller neighbour id */
-          uint32_t ends[2] = {p, q};
-          for (int z = 0; z < 2; ++z) {
-            const orow *row = &o->G.rows[ends[z]];
-            long best = -1;
-            for (uint32_t t = 0; t < row->len; ++t) {
-              if (og_has(&o->H, ends[z], row->e[t].nbr)) continue;
-              if (best < 0 || row->e[t].r < row->e[best].r) best = (long)t;
-            }
-            if (best >= 0) {
-              ra[nr] = ends[z];
-              rb[nr] = row->e[best].nbr;
-              nr++;
-            }
-          }
-        }
-        nrec[j] = nr;
-      }
-      free(traj);
-      free(res);
-    } else if (w_hit) {
-      for (uint32_t k = 0; k < si; ++k) {
-        w_hit[wofs[i] + k] = 0;
-        w_steps[wofs[i] + k] = 0;
-        w_end[wofs[i] + k] = p;
-        w_R[wofs[i] + k] = 0.0;
-      }
-    }
-#pragma omp atomic
-    o->steps_total += st;
-#pragma omp atomic
-    o->alg_bytes_total += by;
-    if (flag) flag[i] = fl;
-    if (any_hit) any_hit[i] = anyh;
-    if (winner) winner[i] = win;
-    if (n_rec) n_rec[i] = nr;
-    if (steps) steps[i] = st;
-    if (Rmin) Rmin[i] = rmin;
-  }
+  for (long long ii = (long long)n_ins; ii < (long long)nu; ++ii)
+    o_update(o, (uint64_t)ii, n_ins, iu, iv, iw, du, dv, s, L, inH, acc, wofs, rofs, rec_a,
+             rec_b, nrec, flag, any_hit, winner, n_rec, steps, Rmin, w_hit, w_steps, w_end, w_R);
+  if (two) o_add_recovered(o, n_del, rofs, rec_a, rec_b, nrec);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long long ii = 0; ii < (long long)n_ins; ++ii)
+    o_update(o, (uint64_t)ii, n_ins, iu, iv, iw, du, dv, s, L, inH, acc, wofs, rofs, rec_a,
+             rec_b, nrec, flag, any_hit, winner, n_rec, steps, Rmin, w_hit, w_steps, w_end, w_R);
 
   /* Phase 4: G += I; H += accepted insertions, recovered and fallback edges
    * (a set union: an edge already present is not added twice). */
@@ -801,14 +880,7 @@ int orc_apply_batch(oracle_t *o, uint64_t n_ins, const uint32_t *iu,
     og_add(&o->G, iu[i], iv[i], iw[i], r, qw);
     if (acc[i]) og_add(&o->H, iu[i], iv[i], iw[i], r, qw);
   }
-  for (uint64_t j = 0; j < n_del; ++j) {
-    for (uint32_t z = 0; z < nrec[j]; ++z) {
-      uint32_t a = rec_a[rofs[j] + z], b = rec_b[rofs[j] + z];
-      if (og_has(&o->H, a, b)) continue;
-      const oent *ge = &o->G.rows[a].e[og_find(&o->G, a, b)];
-      og_add(&o->H, a, b, ge->w, ge->r, ge->qw);
-    }
-  }
+  if (!two) o_add_recovered(o, n_del, rofs, rec_a, rec_b, nrec);
   o->uid_base += nu;
   o_free_last(o);
   o->last_ndel = n_del;

@@ -55,21 +55,20 @@ MUTANTS = {
     "winner_skips_inf": ("if (win == 0xFFFF || res[k].R < rmin) {", "if (res[k].R < rmin) {"),
     # another hitting walker's path is recovered (the last one that hit)
     "recover_last_hitter": ("const uint32_t *path = traj + (size_t)win * (Li + 1);\n"
-                            "          for (uint32_t t = 0; t < res[win].steps; ++t) {",
+                            "        uint32_t plen = res[win].steps + 1;",
                             "uint32_t lw = win;\n"
-                            "          for (uint32_t k = 0; k < si; ++k) if (res[k].hit) lw = k;\n"
-                            "          const uint32_t *path = traj + (size_t)lw * (Li + 1);\n"
-                            "          for (uint32_t t = 0; t < res[lw].steps; ++t) {"),
+                            "        for (uint32_t k = 0; k < si; ++k) if (res[k].hit) lw = k;\n"
+                            "        const uint32_t *path = traj + (size_t)lw * (Li + 1);\n"
+                            "        uint32_t plen = res[lw].steps + 1;"),
     # path edges already in H are recovered again
-    "recover_keeps_H_edges": ("            if (og_has(&o->H, a, b)) continue;\n"
-                              "            int seen = 0;",
-                              "            int seen = 0;"),
+    "recover_keeps_H_edges": ("          if (og_has(&o->H, a, b)) continue;\n"
+                              "          int seen = 0;",
+                              "          int seen = 0;"),
     # an edge the path repeats is listed twice
-    "recover_no_dedup": ("            if (seen) continue;\n", ""),
+    "recover_no_dedup": ("          if (seen) continue;\n", ""),
     # the path is taken from its far end
-    "recover_reversed": ("            uint32_t a = path[t], b = path[t + 1];",
-                         "            uint32_t a = path[res[win].steps - t],"
-                         " b = path[res[win].steps - t - 1];"),
+    "recover_reversed": ("          uint32_t a = path[t], b = path[t + 1];",
+                         "          uint32_t a = path[plen - 1 - t], b = path[plen - 2 - t];"),
     # fallback: the least weight (largest resistance) instead of the largest
     "fallback_min_weight": ("if (best < 0 || row->e[t].r < row->e[best].r) best = (long)t;",
                             "if (best < 0 || row->e[t].r > row->e[best].r) best = (long)t;"),
@@ -77,7 +76,7 @@ MUTANTS = {
     "fallback_ties_larger": ("if (best < 0 || row->e[t].r < row->e[best].r) best = (long)t;",
                              "if (best < 0 || row->e[t].r <= row->e[best].r) best = (long)t;"),
     # fallback: edges already in H are candidates too
-    "fallback_ignores_H": ("              if (og_has(&o->H, ends[z], row->e[t].nbr)) continue;\n",
+    "fallback_ignores_H": ("            if (og_has(&o->H, ends[z], row->e[t].nbr)) continue;\n",
                            ""),
     # an inserted weight whose 1/w overflows is accepted
     "weight_inf_resistance": ("static int weight_ok(double w) { return w > 0.0 && !isinf(w) && "
@@ -108,7 +107,22 @@ MUTANTS.update({
                            "for (uint64_t i = 1; i < n_off && i <= n_extra; ++i) {"),
 })
 
-PIN_FILES = ("test_oracle_pins.py", "test_oracle_recovery.py", "test_oracle_sparsifier.py")
+# --- variants of the update rule ---
+MUTANTS.update({
+    # loop erasure switched off
+    "le_noop": ("if (o->variant & ORC_VAR_LOOP_ERASED) {", "if (0) {"),
+    # the cut drops the vertex met again
+    "le_cut_short": ("if (z < len) len = z + 1;", "if (z < len) len = z;"),
+    # the even walkers are the ones that start at the second endpoint
+    "both_ends_parity": ("const int flip = (o->variant & ORC_VAR_BOTH_ENDS) && (k & 1u);",
+                         "const int flip = (o->variant & ORC_VAR_BOTH_ENDS) && !(k & 1u);"),
+    # the two-stage order never repairs H before the insertion walks
+    "two_stage_noop": ("if (two) o_add_recovered(o, n_del, rofs, rec_a, rec_b, nrec);",
+                       "if (0) o_add_recovered(o, n_del, rofs, rec_a, rec_b, nrec);"),
+})
+
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_recovery.py", "test_oracle_sparsifier.py",
+             "test_oracle_variants.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
