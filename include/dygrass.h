@@ -94,6 +94,19 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
                                   pool that ran short fails as if the device had
                                   no memory left (the batch reports DYG_E_NOMEM
                                   and the context takes no further batches)      */
+/* Variants of the update rule (the paper's alternatives; off by default): */
+#define DYG_FLAG_BOTH_ENDS 128u  /* walker k starts at the second endpoint and aims
+                                    at the first when k is odd (Sec. III-C deploys
+                                    walkers "from p (or from q)")                   */
+#define DYG_FLAG_LOOP_ERASED 256u /* a hitting deletion recovers the edges of the
+                                    chronological loop erasure of its winner's path
+                                    (those not in H) instead of every edge the path
+                                    traversed (Sec. III-C)                          */
+#define DYG_FLAG_TWO_STAGE 512u  /* a batch's deletion walks and their recovered
+                                    edges enter H before its insertion walks, which
+                                    then read the repaired H (Sec. III-F otherwise
+                                    defers every update to the batch end); plain
+                                    form only (INVALID_ARG with DYG_FLAG_BATCHED)  */
 
 #define DYG_MAX_WALKERS 1024 /* per update */
 #define DYG_MAX_STEPS 1024   /* per walker */
@@ -259,6 +272,31 @@ int dyg_query_graph(dyg_ctx* ctx, uint64_t cap, uint64_t* m, uint32_t* u, uint32
                     double* w);
 
 int dyg_stats(dyg_ctx* ctx, dyg_stats_t* out);
+
+/*
+ * Initial sparsifier H(0) of a graph G(0) -- the input Algorithm 1 starts
+ * from (the experiments take it from GRASS, Sec. IV-A; here a spanning forest
+ * plus off-tree edges of the same kind), computed on the current GPU:
+ *   1. the maximum spanning forest of G(0), edges ordered by decreasing
+ *      weight with ties to the smaller canonical index (a strict order, so
+ *      the forest is unique; Boruvka rounds on the device);
+ *   2. plus the n_extra edges outside the forest with the smallest 64-bit
+ *      keys, ties to the smaller index, where the key of edge e is words 0-1
+ *      (low first) of Philox-4x32-10 with key (seed low, seed high) and
+ *      counter (e low, e high, 0, 0x53504152): a uniform sample without
+ *      replacement (all of them if there are fewer).
+ * Canonical edges are the pairs (u, v), u < v, of the CSR in ascending
+ * (u, v) order; edge e is the e-th.  Arguments:
+ *   n, rowptr, col, w   host CSR of G(0), as for dyg_init (same checks and
+ *                       error codes; at most 2^32 - 1 edges)
+ *   cap, m, h_u, h_v    host output: *m = the edge count of H(0); when cap >=
+ *                       *m, h_u[i] < h_v[i] list H(0) in canonical order
+ *                       (two-call protocol: cap = 0 asks for the count)
+ * Allocates and frees its device memory within the call; synchronous.
+ */
+int dyg_initial_sparsifier(uint32_t n, const uint64_t* rowptr, const uint32_t* col,
+                           const double* w, uint64_t n_extra, uint64_t seed, uint64_t cap,
+                           uint64_t* m, uint32_t* h_u, uint32_t* h_v);
 
 /* Launch schedule of the batched form (results never depend on it).
  * Defaults: walk_blocks_per_cu 8, refill_min 1, updates_per_wave 4,

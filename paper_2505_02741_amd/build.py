@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdygrass.so")
-SOURCES = ["dyg_kernels.hip", "dyg_api.hip"]
+SOURCES = ["dyg_kernels.hip", "dyg_api.hip", "dyg_sparsifier.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

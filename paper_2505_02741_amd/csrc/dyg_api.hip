@@ -256,6 +256,7 @@ struct dyg_ctx {
   unsigned long long tune_steps0 = 0;
   bool last_graph = false;  // the batch enqueued last ran as a captured graph
   HBuf pin_in, pin_out;
+  uint32_t h_lo = 0, h_hi = ~0u;   // H addition slots of the phase 4 in progress (repairs)
   int device = 0;                  // the GPU the context lives on
   void* static_scratch = nullptr;  // that GPU's copy of the static working memory
   bool static_inflight = false;    // the batch in flight uses it
@@ -503,12 +504,49 @@ int check_params(const dyg_params* p) {
       !(p->w_ref >= 0.0) || std::isinf(p->w_ref) || !(p->slack >= 0.0) ||
       std::isinf(p->slack))
     return DYG_E_INVALID_ARG;
+  if ((p->flags & DYG_FLAG_TWO_STAGE) && (p->flags & DYG_FLAG_BATCHED)) return DYG_E_INVALID_ARG;
   return DYG_OK;
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
+
+namespace dyg {
+
+// Checks of a graph given as CSR (dyg_init's G0, dyg_initial_sparsifier's
+// input): n in range, rowptr from 0 and non-decreasing, every row in
+// ascending neighbour order with ids in range, no self loop, weights
+// positive and finite with a finite 1/w, and the graph symmetric with equal
+// weights both ways.  *wmax = the largest weight.
+int validate_csr(uint32_t n, const uint64_t* rowptr, const uint32_t* col, const double* w,
+                 double* wmax) {
+  if (n == 0 || n >= (1u << 31) || !rowptr) return DYG_E_INVALID_ARG;
+  const uint64_t nnz = rowptr[n];
+  if (rowptr[0] != 0 || (nnz && (!col || !w))) return DYG_E_INVALID_ARG;
+  double wm = 0.0;
+  for (uint32_t u = 0; u < n; ++u) {
+    if (rowptr[u + 1] < rowptr[u]) return DYG_E_INVALID_ARG;
+    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      if (col[k] >= n) return DYG_E_VERTEX_RANGE;
+      if (col[k] == u) return DYG_E_SELF_LOOP;
+      if (!(w[k] > 0.0) || std::isinf(w[k]) || std::isinf(1.0 / w[k])) return DYG_E_BAD_WEIGHT;
+      if (k > rowptr[u] && col[k] <= col[k - 1]) return DYG_E_INVALID_ARG;
+      wm = std::max(wm, w[k]);
+    }
+  }
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      const uint32_t* lo = col + rowptr[col[k]];
+      const uint32_t* hi = col + rowptr[col[k] + 1];
+      const uint32_t* it = std::lower_bound(lo, hi, u);
+      if (it == hi || *it != u || w[it - col] != w[k]) return DYG_E_INVALID_ARG;  // asymmetric
+    }
+  if (wmax) *wmax = wm;
+  return DYG_OK;
+}
+
+}  // namespace dyg
 
 extern "C" void dyg_default_params(dyg_params* p) {
   if (!p) return;
@@ -549,33 +587,17 @@ extern "C" int dyg_init(dyg_ctx** out, uint32_t n, const uint64_t* rowptr, const
   if (!out) return DYG_E_INVALID_ARG;
   int rc = check_params(params);
   if (rc) return rc;
-  if (n == 0 || n >= (1u << 31) || !rowptr) return DYG_E_INVALID_ARG;
-  const uint64_t nnz = rowptr[n];
-  if (rowptr[0] != 0 || (nnz && (!col || !w)) || (h_m && (!h_u || !h_v)))
-    return DYG_E_INVALID_ARG;
-  // G0: per row range, self loop, weight, ascending order
+  if (h_m && (!h_u || !h_v)) return DYG_E_INVALID_ARG;
   double wmax = 0.0;
-  for (uint32_t u = 0; u < n; ++u) {
-    if (rowptr[u + 1] < rowptr[u]) return DYG_E_INVALID_ARG;
-    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
-      if (col[k] >= n) return DYG_E_VERTEX_RANGE;
-      if (col[k] == u) return DYG_E_SELF_LOOP;
-      if (!(w[k] > 0.0) || std::isinf(w[k]) || std::isinf(1.0 / w[k])) return DYG_E_BAD_WEIGHT;
-      if (k > rowptr[u] && col[k] <= col[k - 1]) return DYG_E_INVALID_ARG;
-      wmax = std::max(wmax, w[k]);
-    }
-  }
+  rc = dyg::validate_csr(n, rowptr, col, w, &wmax);
+  if (rc) return rc;
+  const uint64_t nnz = rowptr[n];
   auto find = [&](uint32_t a, uint32_t b) -> int64_t {
     const uint32_t* lo = col + rowptr[a];
     const uint32_t* hi = col + rowptr[a + 1];
     const uint32_t* it = std::lower_bound(lo, hi, b);
     return (it != hi && *it == b) ? static_cast<int64_t>(it - col) : -1;
   };
-  for (uint32_t u = 0; u < n; ++u)
-    for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
-      const int64_t j = find(col[k], u);
-      if (j < 0 || w[j] != w[k]) return DYG_E_INVALID_ARG;  // not symmetric
-    }
   // H0: range, self loop, subset of G0, repeats (first failing edge wins)
   std::vector<std::pair<uint64_t, uint64_t>> hk(h_m);
   for (uint64_t i = 0; i < h_m; ++i) {
@@ -783,6 +805,9 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
   a.K = c->params.K;
   a.has_K = c->has_K ? 1 : 0;
   a.bounce = c->params.dead_end;
+  a.variant = ((c->params.flags & DYG_FLAG_BOTH_ENDS) ? dyg::kVarBothEnds : 0u) |
+              ((c->params.flags & DYG_FLAG_LOOP_ERASED) ? dyg::kVarLoopErased : 0u) |
+              ((c->params.flags & DYG_FLAG_TWO_STAGE) ? dyg::kVarTwoStage : 0u);
   a.w_ref = c->w_ref;
   a.Q = c->Q;
   a.ins_qw = c->ins_qw.as<uint32_t>();
@@ -900,6 +925,8 @@ bool use_coop(const dyg_ctx* c, uint64_t n_ins, uint64_t n_del) {
 // Launch geometry of this context's batch `a` alone.
 dyg::Launch single_launch(dyg_ctx* c, const BatchArgs& a) {
   dyg::Launch L{};
+  L.h_lo = c->h_lo;
+  L.h_hi = c->h_hi;
   L.argv = c->dargv;
   L.F = 1;
   L.max_nu = a.n_ins + a.n_del;
@@ -977,7 +1004,12 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
 // directly whatever the flags say).
 bool tuning_now(const dyg_ctx* c);
 
-int enqueue_pipeline(dyg_ctx* c, const BatchArgs& a, bool allow_graph = true) {
+int enqueue_two_stage(dyg_ctx* c, BatchArgs& a);
+
+int enqueue_pipeline(dyg_ctx* c, BatchArgs& a, bool allow_graph = true) {
+  if (c->params.flags & DYG_FLAG_TWO_STAGE) return enqueue_two_stage(c, a);
+  c->h_lo = 0;
+  c->h_hi = ~0u;
   const bool timed = c->ev[0] != nullptr;
   // the batch itself is bracketed only under DYG_FLAG_TIMING
   const bool timed_batch = timed && (c->params.flags & DYG_FLAG_TIMING);
@@ -1104,6 +1136,51 @@ int repair_nomem(dyg_ctx* c, BatchArgs& a, BatchCtl& ctl) {
     if (rc) return rc;
   }
   return (ctl.nomem[0] || ctl.nomem[1]) ? DYG_E_NOMEM : DYG_OK;
+}
+
+// A two-stage batch (plain form): validation, phase 1, the deletion walks
+// and decisions, and H += their recovered and fallback edges (slots n_ins..),
+// then -- after a host check of that first phase 4, growing H's pool if it
+// ran short -- the insertion walks on the repaired H, the counters, and G +=
+// insertions, H += kept insertions (slots 0..n_ins-1).  The second stage is
+// enqueued like any batch and completes at dyg_sync / in dyg_apply_batch.
+int enqueue_two_stage(dyg_ctx* c, BatchArgs& a) {
+  hipError_t e = hipMemcpyAsync(c->dargs, &a, sizeof(BatchArgs), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return fail_hip(e);
+  c->last_graph = false;
+  c->timed_pending = false;  // two walk launches: not timed
+  c->h_lo = a.n_ins;
+  c->h_hi = a.hadd_cap;
+  dyg::Launch L = single_launch(c, a);
+  dyg::launch_batch_begin(L, c->stream);
+  dyg::launch_validate(L, c->stream);
+  dyg::launch_phase1(L, c->stream);
+  L.stage = dyg::kStageDeletions;
+  dyg::launch_walks(L, c->stream);
+  dyg::launch_phase4(L, 1, c->stream);
+  BatchCtl ctl;
+  int rc = sync_ctl_host(c, ctl);
+  if (rc) return rc;
+  if (decode_err(ctl.err_key) == DYG_OK && ctl.nomem[1]) {
+    rc = repair_nomem(c, a, ctl);
+    if (rc) {
+      c->broken = true;
+      return rc;
+    }
+  }
+  c->h_lo = 0;
+  c->h_hi = a.n_ins;
+  L = single_launch(c, a);
+  dyg::launch_phase4_clear(L, 0, c->stream);
+  dyg::launch_phase4_clear(L, 1, c->stream);
+  L.stage = dyg::kStageInsertions;
+  dyg::launch_walks(L, c->stream);
+  dyg::launch_sum_counters(L, c->stream);
+  dyg::launch_phase4_both(L, c->stream);
+  e = hipMemcpyAsync(c->hctl, c->ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(c->done_ev, c->stream);
+  if (e != hipSuccess) return fail_hip(e);
+  return DYG_OK;
 }
 
 // Keep a tenth of each pool free between batches.
@@ -1275,6 +1352,8 @@ extern "C" int dyg_apply_batch_dev_static(dyg_ctx* c, const dyg_batch_dev* b, vo
   // completing an earlier batch may grow a pool, which allocates: the caller
   // does that with dyg_sync before this call
   if (c->async_inflight) return DYG_E_BUSY;
+  // a two-stage batch checks (and may grow) H's pool between its stages
+  if (c->params.flags & DYG_FLAG_TWO_STAGE) return DYG_E_INVALID_ARG;
   if (!c->static_scratch) return DYG_E_DEVICE;
   const uint32_t Lcap = std::max<uint32_t>(b->L ? b->L_max : c->params.L_default, 2);
   const uint32_t scap = b->s ? b->s_max : c->params.s_default;
@@ -2024,6 +2103,8 @@ extern "C" int dyg_server_create(dyg_server** out, const dyg_server_params* p) {
 
 extern "C" int dyg_server_add_graph(dyg_server* s, dyg_ctx* ctx, uint32_t* graph_id) {
   if (!s || !ctx || !graph_id) return DYG_E_INVALID_ARG;
+  // fused rounds run every update of a batch in one walk launch
+  if (ctx->params.flags & DYG_FLAG_TWO_STAGE) return DYG_E_INVALID_ARG;
   if (ctx->async_inflight) {
     int rc = dyg_sync(ctx);
     if (rc) return rc;

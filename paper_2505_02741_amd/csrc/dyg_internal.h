@@ -134,6 +134,16 @@ static_assert(sizeof(AddRec) == 32, "AddRec layout");
 
 // Walker index bits of WalkItem::walker; the bits above hold the batch (0..63)
 // when several batches share one queue.
+// Variants of the update rule (the paper's alternatives, off by default):
+// odd walkers start at the second endpoint and aim at the first (Sec. III-C
+// deploys walkers from p or from q); a hitting deletion recovers the loop
+// erasure of its winner's path; the deletions and their recoveries enter H
+// before the insertion walks (Sec. III-F otherwise defers every update to the
+// batch end).
+constexpr uint32_t kVarBothEnds = 1u;
+constexpr uint32_t kVarLoopErased = 2u;
+constexpr uint32_t kVarTwoStage = 4u;
+
 constexpr uint32_t kWalkerBits = 10;
 constexpr uint32_t kMaxFused = 64;
 
@@ -198,6 +208,7 @@ struct BatchCtl {
   uint32_t hubs;                // set when phase 4 leaves a row longer than kHub
   uint32_t fb_count;            // deletions whose fallback scan is left to k_fallback_wide
   unsigned long long pool_top[2];  // next free pool slot, per graph
+  unsigned long long stage_used[2];  // pool slots past pool_top used to stage wide merges
   unsigned long long walk_items;       // walkers queued (queue control only)
   unsigned long long queue_next;       // next queue item to hand out (queue control only)
   unsigned long long item_base;        // first queue item of this batch
@@ -230,6 +241,7 @@ struct BatchArgs {
   double K;
   int has_K;
   int bounce;
+  uint32_t variant;  // kVar* bits (variants of the update rule)
   double w_ref;
   int Q;
   // work buffers
@@ -284,7 +296,14 @@ struct Launch {
   bool hubs;                          // some row of a graph may be longer than kHub
   bool coop;                          // plain walks: rows of the walked graphs are mostly pool rows
   uint32_t tail_lanes;                // batched form: head/tail schedule (0 = off)
+  uint32_t stage = 0;                 // plain walks: all updates (0), deletions (1), insertions (2)
+  uint32_t h_lo = 0, h_hi = ~0u;      // phase 4: H additions from these slots only
 };
+
+// Host-side checks of a graph given as CSR (defined in dyg_api.hip): returns
+// DYG_OK or a DYG_E_* code; *wmax = the largest weight.
+int validate_csr(uint32_t n, const uint64_t* rowptr, const uint32_t* col, const double* w,
+                 double* wmax);
 
 // Host-side launchers (defined in dyg_kernels.hip), all asynchronous on
 // `stream`.
@@ -305,5 +324,10 @@ void launch_sum_counters(const Launch& L, hipStream_t stream);
 void launch_phase4_both(const Launch& L, hipStream_t stream);
 void launch_phase4(const Launch& L, int which, hipStream_t stream);
 void launch_phase4_reset(const Launch& L, int which, hipStream_t stream);
+// Phase-4 counters of graph `which` back to zero (between the two stages of
+// a two-stage batch).
+void launch_phase4_clear(const Launch& L, int which, hipStream_t stream);
+// The walk launch of the plain form takes the updates L.stage names.
+constexpr uint32_t kStageDeletions = 1, kStageInsertions = 2;
 
 }  // namespace dyg

@@ -363,6 +363,7 @@ __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
     ctl->fb_count = 0;
     for (int w = 0; w < 2; ++w) {
       ctl->touched[w] = 0;
+      ctl->stage_used[w] = 0;
       ctl->need[w] = 0;
       ctl->nomem[w] = 0;
       ctl->dirty[w] = 0;
@@ -638,7 +639,18 @@ struct WalkParams {
   uint32_t key0, key1, uid_lo, uid_hi;
   bool bounce;
   bool heavy;  // a weight may reach kHeavyQw: 64-bit running sums
+  bool both;   // odd walkers start at q and aim at p
 };
+
+// Walker `walker`'s own start (p) and target (q): the endpoints swap for odd
+// walkers under the both-ends variant.
+__device__ __forceinline__ void walker_ends(WalkParams& P, uint32_t walker) {
+  if (P.both && (walker & 1u)) {
+    const uint32_t t = P.p;
+    P.p = P.q;
+    P.q = t;
+  }
+}
 
 // Emits nothing; the replay variant below passes an edge sink.
 struct NoSink {
@@ -966,7 +978,9 @@ __device__ __forceinline__ bool walk_step(const WalkParams& P, uint32_t walker, 
 }
 
 template <bool kHubs, class Sink>
-__device__ __forceinline__ Walk walk_one(const WalkParams& P, uint32_t walker, Sink& sink) {
+__device__ __forceinline__ Walk walk_one(const WalkParams& Pu, uint32_t walker, Sink& sink) {
+  WalkParams P = Pu;
+  walker_ends(P, walker);
   WState S;
   walker_start(S, P.p);
   while (walk_step<kHubs>(P, walker, S, sink)) {
@@ -1014,9 +1028,11 @@ constexpr uint32_t kStageWords = 4 * kStagePitch;
 // as its exchange only adds latency there and its registers cost occupancy.
 constexpr int kCoopLanes = 8;
 template <bool kHubs, bool kCoop>
-__device__ __forceinline__ bool walk_lockstep(const WalkParams& P, uint32_t walker, bool active,
+__device__ __forceinline__ bool walk_lockstep(const WalkParams& Pu, uint32_t walker, bool active,
                                               uint4* st, uint32_t lane, uint32_t handoff,
                                               WState& S) {
+  WalkParams P = Pu;
+  walker_ends(P, walker);
   walker_start(S, P.p);
   bool alive = active;
   const uint4* rows4 = reinterpret_cast<const uint4*>(P.rows);
@@ -1109,13 +1125,30 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 }
 
 // Sink of the winner replay: path edges absent from H_mid, first occurrence.
+// With `erase` (loop-erased variant) it keeps the loop erasure of the path
+// instead: an edge x -> y whose head y is already on the kept path cuts the
+// path back to y (the loop is dropped), any other is appended; drop_in_h()
+// then leaves out the edges live in H.
 struct RecoverSink {
   DevGraph G, H;
   AddRec* out;  // reserved block of `cap` records
   uint32_t cap;
   uint32_t count;
+  bool erase;
   // edge x -> y is entry i of x's row in G (off: that row's pool offset)
   __device__ void operator()(uint32_t x, uint32_t y, uint32_t i, uint32_t off) {
+    if (erase) {
+      for (uint32_t z = 0; z < count; ++z)
+        if (out[z].a == y) {  // y was reached before: erase the loop since then
+          count = z;
+          return;
+        }
+      if (count >= cap) return;  // cannot happen: at most one edge per step
+      const Seg seg = seg_of(G, x, off);
+      const Ent e = seg.get(i);
+      out[count++] = AddRec{x, y, e.qw, 0u, e.rinv, seg.w[i]};
+      return;
+    }
     if (has_live(H, x, y)) return;
     const unsigned long long k = edge_key(x, y);
     for (uint32_t z = 0; z < count; ++z)
@@ -1125,6 +1158,12 @@ struct RecoverSink {
     const Ent e = seg.get(i);
     out[count] = AddRec{x, y, e.qw, 0u, e.rinv, seg.w[i]};
     ++count;
+  }
+  __device__ void drop_in_h() {
+    uint32_t o = 0;
+    for (uint32_t z = 0; z < count; ++z)
+      if (!has_live(H, out[z].a, out[z].b)) out[o++] = out[z];
+    count = o;
   }
 };
 
@@ -1174,6 +1213,7 @@ __device__ __forceinline__ UpdateView view_update(const BatchArgs& a, const DevG
   P.uid_hi = static_cast<uint32_t>(uid >> 32);
   P.bounce = a.bounce != 0;
   P.heavy = a.ctl->heavy != 0u;
+  P.both = (a.variant & kVarBothEnds) != 0;
   P.rows = v.is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
   P.ent = v.is_ins ? H.ent : G.ent;
   P.prinv = v.is_ins ? H.prinv : G.prinv;
@@ -1313,10 +1353,28 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
     const Walk wk = walk_one<kHubs>(P, bestW, ps);
     const bool mine = lane < wk.steps;
     const unsigned long long key = mine ? edge_key(ps.x, ps.y) : ~0ull;
-    bool keep = mine && !has_live(H, ps.x, ps.y);
+    unsigned long long path = wk.steps >= kWave ? ~0ull : (1ull << wk.steps) - 1ull;
+    if (a.variant & kVarLoopErased) {
+      // loop erasure: with x_t the vertex step t leaves, the erased path
+      // leaves x_0 at its last visit s0, then x_(s0+1) at its last visit,
+      // and so on up to the target (reached once, at the end)
+      uint32_t last = lane;
+      for (uint32_t t = 0; t < wk.steps; ++t)
+        if (static_cast<uint32_t>(__shfl(static_cast<int>(ps.x), static_cast<int>(t), kWave)) ==
+            ps.x)
+          last = t;
+      path = 0ull;
+      for (uint32_t i = 0; i < wk.steps;) {  // uniform
+        const uint32_t sg =
+            static_cast<uint32_t>(__shfl(static_cast<int>(last), static_cast<int>(i), kWave));
+        path |= 1ull << sg;
+        i = sg + 1;
+      }
+    }
+    bool keep = mine && ((path >> lane) & 1ull) && !has_live(H, ps.x, ps.y);
     for (uint32_t t = 0; t < wk.steps; ++t) {  // first occurrence in path order
       const unsigned long long k2 = __shfl(key, static_cast<int>(t), kWave);
-      if (t < lane && k2 == key) keep = false;
+      if (t < lane && ((path >> t) & 1ull) && k2 == key) keep = false;
     }
     const unsigned long long kept = __ballot(keep);
     if (keep) {
@@ -1328,8 +1386,9 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
     count = static_cast<uint32_t>(__popcll(kept));  // <= steps <= cap
   } else if (any_hit) {
     if (lane == 0) {
-      RecoverSink sink{G, H, out, cap, 0u};
+      RecoverSink sink{G, H, out, cap, 0u, (a.variant & kVarLoopErased) != 0};
       walk_one<kHubs>(P, bestW, sink);  // replay: same counters, same snapshot
+      if (sink.erase) sink.drop_in_h();
       count = sink.count;
     }
     count = static_cast<uint32_t>(__shfl(static_cast<int>(count), 0, kWave));
@@ -1370,7 +1429,8 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
 // than lanes run in successive rounds of 64), walks and decision in one
 // kernel, so one update's decision overlaps other updates' walks.
 template <bool kHubs, bool kCoop>
-__global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv) {
+__global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv,
+                                                      uint32_t updates) {
   __shared__ uint4 stage[kCoop ? kWalkBlock / kWave : 1][kCoop ? kStageWords : 1];
   const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph G = a.g[0];
@@ -1379,6 +1439,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + wave_in_block();
   if (upd >= a.n_ins + a.n_del) return;  // uniform across the wavefront
+  // two-stage batches: stage 1 takes the deletions, stage 2 the insertions
+  if ((updates == kStageDeletions && upd < a.n_ins) ||
+      (updates == kStageInsertions && upd >= a.n_ins))
+    return;
   const UpdateView v = view_update(a, G, H, upd);
   if (!v.walks) {
     no_walk_update(a, v, upd, lane);
@@ -1524,9 +1588,15 @@ __global__ __launch_bounds__(kBlock) void k_expand_items(const BatchArgs* const*
   it.L = static_cast<uint16_t>(a.L ? a.L[upd] : a.L_def);
   it.w_pq = is_ins ? a.iw[upd] : 0.0;
   const unsigned long long base = a.ctl->item_base + a.qofs[upd];
+  const bool both = (a.variant & kVarBothEnds) != 0;
   for (uint32_t k = lane; k < cnt; k += kWave) {
-    it.walker = static_cast<uint16_t>(k | (blockIdx.y << kWalkerBits));
-    a.items[base + k] = it;
+    WalkItem mine = it;
+    mine.walker = static_cast<uint16_t>(k | (blockIdx.y << kWalkerBits));
+    if (both && (k & 1u)) {  // odd walkers start at q and aim at p
+      mine.p = it.q;
+      mine.q = it.p;
+    }
+    a.items[base + k] = mine;
   }
 }
 
@@ -1564,6 +1634,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   P.key1 = static_cast<uint32_t>(a0.seed >> 32);
   P.bounce = a0.bounce != 0;
   P.heavy = a0.ctl->heavy != 0u;
+  P.both = false;  // each queue item already holds its walker's own ends
   P.rows = a0.g[1].rows;
   P.ent = a0.g[1].ent;
   P.prinv = a0.g[1].prinv;
@@ -1694,6 +1765,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
   P.key0 = static_cast<uint32_t>(a.seed);
   P.key1 = static_cast<uint32_t>(a.seed >> 32);
   P.bounce = a.bounce != 0;
+  P.both = (a.variant & kVarBothEnds) != 0;
   P.heavy = a.ctl->heavy != 0u;
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
@@ -1746,6 +1818,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
         P.tree = X.tree;
         P.rinl = X.rinl;
         walker = idx - start;
+        walker_ends(P, walker);
         item = base + idx;
         pending = true;
       }
@@ -1841,6 +1914,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
   P.key0 = static_cast<uint32_t>(a.seed);
   P.key1 = static_cast<uint32_t>(a.seed >> 32);
   P.bounce = a.bounce != 0;
+  P.both = (a.variant & kVarBothEnds) != 0;
   P.heavy = a.ctl->heavy != 0u;
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
@@ -1878,7 +1952,10 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
         const bool is_ins = upd < a.n_ins;
         const uint32_t jd = upd - a.n_ins;
         const uint64_t uid = a.uid_base + upd;
+        const TailState ts = a.tstate[item0 + a.qofs[upd] + (idx - start)];
+        P.p = is_ins ? a.iu[upd] : a.du[jd];  // the survivor's state holds where it is
         P.q = is_ins ? a.iv[upd] : a.dv[jd];
+        walker_ends(P, ts.walker);
         P.w_pq = is_ins ? a.iw[upd] : 0.0;
         P.use_K = is_ins && a.has_K;
         P.L = a.L ? a.L[upd] : a.L_def;
@@ -1892,7 +1969,6 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
         P.tree = X.tree;
         P.rinl = X.rinl;
         const unsigned long long first = item0 + a.qofs[upd];
-        const TailState ts = a.tstate[first + (idx - start)];
         S.x = ts.x;
         S.prev = ts.prev;
         S.steps = ts.t;
@@ -2125,7 +2201,15 @@ __device__ __forceinline__ uint32_t add_count(const P4& a, uint32_t which) {
   return which == 0 ? 2u * a.n_ins : 2u * a.hadd_cap;
 }
 
-__global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+// H additions are taken from the slots [h_lo, h_hi) only (two-stage
+// batches add the deletions' recoveries and the kept insertions apart).
+__device__ __forceinline__ bool in_window(uint32_t which, uint32_t e, uint32_t h_lo,
+                                          uint32_t h_hi) {
+  return which == 0 || ((e >> 1) >= h_lo && (e >> 1) < h_hi);
+}
+
+__global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv, uint32_t which0,
+                              uint32_t h_lo, uint32_t h_hi) {
   const uint32_t which = which0 + blockIdx.z;
   const P4 a = load_p4(argv, blockIdx.y, which);
   const DevGraph& X = a.X;
@@ -2133,6 +2217,7 @@ __global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv, uint32_
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= add_count(a, which)) return;
   a.add_keep[e] = 0;
+  if (!in_window(which, e, h_lo, h_hi)) return;
   const AddEntry d = add_entry(a, which, e);
   if (!d.valid) return;
   const RowHdr row = row_hdr(X, d.r);
@@ -2212,7 +2297,11 @@ __global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, uint32_t 
     if (align) flags |= kAlignHub;
     merged_from = row.len - row.dead;
   }
-  if (merged_from + k > kHub) flags |= kWideMerge;
+  if (merged_from + k > kHub) {
+    flags |= kWideMerge;
+    // the merge stages the k new entries past the pool top (not kept)
+    atomicAdd(&a.ctl->need[which], static_cast<unsigned long long>(k));
+  }
   a.touched_k[t] = k | flags;
   a.touched_need[t] = need;
   if (flags) a.wide_rows[atomicAdd(&a.ctl->wide[which], 1u)] = t;  // rare: long rows only
@@ -2316,14 +2405,15 @@ __global__ __launch_bounds__(kBlock) void k_rows_relocate(const BatchArgs* const
   else rows_relocate_wide(argv, which0, blockIdx.x - narrow_blocks, gridDim.x - narrow_blocks);
 }
 
-__global__ void k_add_place(const BatchArgs* const* __restrict__ argv, uint32_t which0) {
+__global__ void k_add_place(const BatchArgs* const* __restrict__ argv, uint32_t which0,
+                            uint32_t h_lo, uint32_t h_hi) {
   const uint32_t which = which0 + blockIdx.z;
   const P4 a = load_p4(argv, blockIdx.y, which);
   const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= add_count(a, which)) return;
-  if (!a.add_keep[e]) return;
+  if (!in_window(which, e, h_lo, h_hi) || !a.add_keep[e]) return;
   const AddEntry d = add_entry(a, which, e);
   const RowHdr row = row_hdr(X, d.r);
   const uint32_t slot = atomicSub(&X.pending[d.r], 1u) - 1u;  // leaves pending at 0
@@ -2364,14 +2454,16 @@ __device__ __forceinline__ void rows_merge_narrow(const BatchArgs* const* __rest
   }
 }
 
-constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (36 KB LDS)
+constexpr uint32_t kTailChunk = 4096;  // appended entries merged per pass (48 KB LDS)
 
 // Merge for long segments: one workgroup per segment.  Each pass takes up to
-// kTailChunk appended entries, sorts them in LDS (bitonic), computes every
-// entry's final position (old entries shift right by the number of new
-// entries below them; new entries sit after the old entries below them) and
-// moves the old entries right to left in block-sized chunks, so no entry is
-// overwritten before it is read.
+// kTailChunk appended entries, copies them past the pool top (slots the
+// phase-4 pool check reserved for this, given back at the end of the batch),
+// sorts their keys in LDS (bitonic), computes every entry's final position
+// (old entries shift right by the number of new entries below them; new
+// entries sit after the old entries below them), moves the old entries
+// right to left in block-sized chunks, so no entry is overwritten before it
+// is read, and finally writes the new entries from their staging copy.
 constexpr uint32_t kMergePer = 8;  // old entries per thread and chunk of a wide merge
 
 __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restrict__ argv,
@@ -2381,10 +2473,10 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
   const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   __shared__ unsigned long long s_key[kTailChunk];  // (nbr << 32) | local index
-  __shared__ Ent s_ent[kTailChunk];
-  __shared__ double s_w[kTailChunk];
   __shared__ uint32_t s_pos[kTailChunk];
+  __shared__ unsigned long long s_stage;
   const uint32_t count = a.ctl->wide[which];
+  const unsigned long long top = a.ctl->pool_top[which];  // final: relocations are done
   for (uint32_t wi = bx; wi < count; wi += nbx) {
     const uint32_t t = a.wide_rows[wi];
     const uint32_t packed = a.touched_k[t];
@@ -2396,15 +2488,20 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
     double* rseg = X.prinv + row.off;
     double* wseg = X.w + row.off;
     uint32_t cur = row.len;  // sorted prefix length
+    if (threadIdx.x == 0) s_stage = top + atomicAdd(&a.ctl->stage_used[which], k);
+    __syncthreads();
+    const unsigned long long stage = s_stage;  // k staging slots
     for (uint32_t c0 = 0; c0 < k; c0 += kTailChunk) {
       const uint32_t c = (k - c0) < kTailChunk ? (k - c0) : kTailChunk;
       uint32_t P = 1;
       while (P < c) P <<= 1;
       for (uint32_t j = threadIdx.x; j < P; j += kBlock) {
         if (j < c) {
-          s_ent[j] = Ent{seg[cur + j].nbr, seg[cur + j].qw, rseg[cur + j]};
-          s_w[j] = wseg[cur + j];
-          s_key[j] = (static_cast<unsigned long long>(s_ent[j].nbr) << 32) | j;
+          const Pair e = seg[cur + j];
+          X.ent[stage + c0 + j] = e;
+          X.prinv[stage + c0 + j] = rseg[cur + j];
+          X.w[stage + c0 + j] = wseg[cur + j];
+          s_key[j] = (static_cast<unsigned long long>(e.nbr) << 32) | j;
         } else {
           s_key[j] = ~0ull;
         }
@@ -2444,7 +2541,7 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
       for (uint32_t hi_i = cur; hi_i > stay;) {
         const uint32_t span = kBlock * kMergePer;
         const uint32_t lo_i = hi_i - stay > span ? hi_i - span : stay;
-        // fields in separate arrays (registers; an array of Ent written
+        // fields in separate arrays (registers; an array of structs written
         // under a condition would go to scratch)
         uint32_t en[kMergePer], eq[kMergePer], shift[kMergePer];
         double er[kMergePer], we[kMergePer];
@@ -2485,10 +2582,10 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
         hi_i = lo_i;
       }
       for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
-        const uint32_t src = static_cast<uint32_t>(s_key[j] & 0xFFFFFFFFull);
-        seg[s_pos[j]] = Pair{s_ent[src].nbr, s_ent[src].qw};
-        rseg[s_pos[j]] = s_ent[src].rinv;
-        wseg[s_pos[j]] = s_w[src];
+        const uint64_t src = stage + c0 + static_cast<uint32_t>(s_key[j] & 0xFFFFFFFFull);
+        seg[s_pos[j]] = X.ent[src];
+        rseg[s_pos[j]] = X.prinv[src];
+        wseg[s_pos[j]] = X.w[src];
       }
       __syncthreads();
       cur += c;
@@ -2538,9 +2635,11 @@ __global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv, ui
   BatchCtl* ctl = ctl_of(argv, blockIdx.y);
   if (threadIdx.x == 0) {
     ctl->touched[which] = 0;
+    ctl->stage_used[which] = 0;
     ctl->need[which] = 0;
     ctl->nomem[which] = 0;
     ctl->wide[which] = 0;
+    ctl->dirty[which] = 0;  // (rows listed by a finished phase 4 have their trees)
   }
 }
 
@@ -2595,11 +2694,12 @@ void launch_phase1(const Launch& L, hipStream_t st) {
 void launch_walks(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
   const dim3 g = grid_of(L.max_nu, L.F, kWalkBlock / kWave);
-  if (L.hubs && L.coop) k_walks<true, true><<<g, kWalkBlock, 0, st>>>(L.argv);
-  else if (L.hubs) k_walks<true, false><<<g, kWalkBlock, 0, st>>>(L.argv);
-  else if (L.coop) k_walks<false, true><<<g, kWalkBlock, 0, st>>>(L.argv);
-  else k_walks<false, false><<<g, kWalkBlock, 0, st>>>(L.argv);
-  launch_fallback_wide(L, st);
+  const uint32_t sg = L.stage;
+  if (L.hubs && L.coop) k_walks<true, true><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
+  else if (L.hubs) k_walks<true, false><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
+  else if (L.coop) k_walks<false, true><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
+  else k_walks<false, false><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
+  if (sg != kStageInsertions) launch_fallback_wide(L, st);  // only deletions have one
 }
 
 void launch_sum_counters(const Launch& L, hipStream_t st) {
@@ -2663,12 +2763,12 @@ void phase4_sequence(const Launch& L, uint32_t which0, uint32_t nw, hipStream_t 
   }
   if (cap == 0) return;
   const dim3 g(static_cast<uint32_t>((cap + kBlock - 1) / kBlock), L.F, nw);
-  k_add_prepare<<<g, kBlock, 0, st>>>(L.argv, which0);
+  k_add_prepare<<<g, kBlock, 0, st>>>(L.argv, which0, L.h_lo, L.h_hi);
   k_rows_plan<<<g, kBlock, 0, st>>>(L.argv, which0);
   k_pool_check<<<dim3(1, L.F, nw), 64, 0, st>>>(L.argv, which0);
   const dim3 both(g.x + kWideBlocks, L.F, nw);  // short rows, then long rows
   k_rows_relocate<<<both, kBlock, 0, st>>>(L.argv, which0, g.x);
-  k_add_place<<<g, kBlock, 0, st>>>(L.argv, which0);
+  k_add_place<<<g, kBlock, 0, st>>>(L.argv, which0, L.h_lo, L.h_hi);
   k_rows_merge<<<both, kBlock, 0, st>>>(L.argv, which0, g.x);
   launch_hub_tree(L, which0, nw, st);
 }
@@ -2680,6 +2780,10 @@ void launch_phase4(const Launch& L, int which, hipStream_t st) {
 }
 
 void launch_phase4_both(const Launch& L, hipStream_t st) { phase4_sequence(L, 0, 2, st); }
+
+void launch_phase4_clear(const Launch& L, int which, hipStream_t st) {
+  k_phase4_reset_ctl<<<dim3(1, L.F, 1), 64, 0, st>>>(L.argv, static_cast<uint32_t>(which));
+}
 
 void launch_phase4_reset(const Launch& L, int which, hipStream_t st) {
   const uint64_t cap = which == 0 ? 2ull * L.max_ins : 2ull * L.max_hadd_cap;

@@ -42,6 +42,9 @@ FLAG_GRAPH = 8
 FLAG_AUTOTUNE = 16
 FLAG_TIMING_WALK = 32
 FLAG_FAIL_POOL_GROWTH = 64
+FLAG_BOTH_ENDS = 128
+FLAG_LOOP_ERASED = 256
+FLAG_TWO_STAGE = 512
 
 DEAD_END_TERMINATE = 0
 DEAD_END_BOUNCE = 1
@@ -101,7 +104,7 @@ class dyg_request_done(C.Structure):
 
 
 EXPORTS = ["dyg_default_params", "dyg_init", "dyg_apply_batch", "dyg_apply_batch_dev",
-           "dyg_apply_batch_dev_static",
+           "dyg_apply_batch_dev_static", "dyg_initial_sparsifier",
            "dyg_sync", "dyg_query_sparsifier", "dyg_query_graph", "dyg_stats", "dyg_compact",
            "dyg_destroy", "dyg_error_string", "dyg_get_tuning", "dyg_set_tuning", "dyg_reserve",
            "dyg_check_state", "dyg_server_default_params", "dyg_server_create",
@@ -140,6 +143,9 @@ def _load():
     lib.dyg_apply_batch_dev.restype = C.c_int
     lib.dyg_apply_batch_dev_static.argtypes = [P, C.POINTER(dyg_batch_dev), P]
     lib.dyg_apply_batch_dev_static.restype = C.c_int
+    lib.dyg_initial_sparsifier.argtypes = [C.c_uint32, P, P, P, C.c_uint64, C.c_uint64,
+                                           C.c_uint64, C.POINTER(C.c_uint64), P, P]
+    lib.dyg_initial_sparsifier.restype = C.c_int
     lib.dyg_sync.argtypes = [P]
     lib.dyg_sync.restype = C.c_int
     for fn in (lib.dyg_query_sparsifier, lib.dyg_query_graph):
@@ -343,6 +349,25 @@ def dyg_apply_batch_dev_static(ctx, iu, iv, iw, du, dv, s=None, L=None, L_max=0,
     b, handle = _dev_batch(iu, iv, iw, du, dv, s, L, L_max, s_max, results, stream)
     _check(_lib.dyg_apply_batch_dev_static(ctx, C.byref(b), handle),
            "dyg_apply_batch_dev_static")
+
+
+def dyg_initial_sparsifier(n, rowptr, col, w, n_extra, seed):
+    """H(0) of the CSR graph (maximum spanning forest + n_extra keyed off-tree
+    edges, computed on the GPU): (h_u, h_v) in canonical order."""
+    rowptr = _arr(rowptr, np.uint64)
+    col = _arr(col, np.uint32)
+    w = _arr(w, np.float64)
+    m = C.c_uint64(0)
+    _check(_lib.dyg_initial_sparsifier(int(n), _ptr(rowptr), _ptr(col), _ptr(w), int(n_extra),
+                                       int(seed), 0, C.byref(m), None, None),
+           "dyg_initial_sparsifier")
+    u = np.zeros(max(m.value, 1), np.uint32)
+    v = np.zeros(max(m.value, 1), np.uint32)
+    cnt = m.value
+    _check(_lib.dyg_initial_sparsifier(int(n), _ptr(rowptr), _ptr(col), _ptr(w), int(n_extra),
+                                       int(seed), cnt, C.byref(m), _ptr(u), _ptr(v)),
+           "dyg_initial_sparsifier")
+    return u[:m.value], v[:m.value]
 
 
 def dyg_sync(ctx):
