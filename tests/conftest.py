@@ -19,3 +19,15 @@ def oracle_mod():
 
     oracle._load()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _live_progress(request):
+    """Let gpu_helpers.say print past pytest's output capture."""
+    try:
+        import gpu_helpers
+    except ImportError:
+        yield
+        return
+    gpu_helpers.CAPMAN = request.config.pluginmanager.getplugin("capturemanager")
+    yield

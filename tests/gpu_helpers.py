@@ -14,13 +14,27 @@ from paper_2505_02741_amd import workloads as W
 R_RTOL = 1e-12
 
 
+# pytest's capture manager (set by the conftest fixture): progress lines of
+# long GPU tests go straight to the real stdout, so a slow test shows that it
+# is alive while pytest captures everything else
+CAPMAN = None
+
+
 def say(*a):
-    print(*a, flush=True)
+    if CAPMAN is not None:
+        with CAPMAN.global_and_fixture_disabled():
+            print(*a, flush=True)
+    else:
+        print(*a, flush=True)
     sys.stdout.flush()
 
 
+# oracle variant bit -> library flag
+VARIANT_FLAGS = {1: 128, 2: 256, 4: 512}
+
+
 def make_pair(wl, *, K=None, dead_end=0, slack=0.5, Q=24, s=None, L=None, w_ref=0.0,
-              uid_base=0, G=None, H=None, flags=0):
+              uid_base=0, G=None, H=None, flags=0, variant=0):
     import oracle
     from paper_2505_02741_amd import dygrass as D
 
@@ -33,7 +47,10 @@ def make_pair(wl, *, K=None, dead_end=0, slack=0.5, Q=24, s=None, L=None, w_ref=
     s = wl.s if s is None else s
     L = wl.L if L is None else L
     o = oracle.Oracle(wl.G.n, rp, col, w, H[0], H[1], seed=wl.seed_walk, K=K, s=s, L=L, Q=Q,
-                      w_ref=w_ref, dead_end=dead_end, uid_base=uid_base)
+                      w_ref=w_ref, dead_end=dead_end, uid_base=uid_base, variant=variant)
+    for bit, flag in VARIANT_FLAGS.items():
+        if variant & bit:
+            flags |= flag
     d = D.Dygrass(wl.G.n, rp, col, w, H[0], H[1], seed=wl.seed_walk, K=K, s=s, L=L, Q=Q,
                   w_ref=w_ref, dead_end=dead_end, slack=slack, uid_base=uid_base, flags=flags)
     return o, d

@@ -64,6 +64,24 @@ def test_traffic_from_counters_scales_by_the_copy(bench, tmp_path, monkeypatch):
     assert d["kernel_source"] == bench.kernel_source_hash()
 
 
+def test_traffic_window_takes_the_last_dispatches(bench, tmp_path, monkeypatch):
+    """The timed batches are the last ones: a window of 1 reads only the last
+    dispatch of the kernel (warmup dispatches before it are ignored)."""
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    calib = 256 << 20
+    k = "void dyg::k_walks<false, false>(dyg::BatchArgs const* const*)"
+    fetch = [("__amd_rocclr_copyBuffer", calib / 1024), (k, 1000.0), (k, 3000.0)]
+    write = [("__amd_rocclr_copyBuffer", calib / 1024), (k, 10.0), (k, 30.0)]
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_counters(fp, "FETCH_SIZE", fetch)
+    write_counters(wp, "WRITE_SIZE", write)
+    bench.traffic_from_counters(str(fp), str(wp), "k_walks", calib, "grid1024", "plain", window=1)
+    d = json.load(open(tmp_path / "traffic.json"))["grid1024/plain"]
+    assert d["fetch_bytes_per_launch"] == pytest.approx(3000.0 * 1024)
+    assert d["write_bytes_per_launch"] == pytest.approx(30.0 * 1024)
+    assert d["launches"] == [1, 1]
+
+
 def test_traffic_of_a_two_kernel_walk_sums_per_launch(bench, tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
     calib = 1 << 20

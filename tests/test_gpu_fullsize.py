@@ -90,3 +90,61 @@ def test_rmat_scale18_uneven_batches(flags):
     """R-MAT scale 18 (edge factor 16), 12 uneven batches (100..20,000
     updates, 70/30), per-update s in 16..128 and L in 8..32."""
     _run_full("rmat22", flags, scale=18, batches=12, size_hi=20_000)
+
+
+@pytest.mark.timeout(1200)
+def test_rmat22_full_scale_first_batches():
+    """R-MAT scale 22 at its real size (4,194,304 vertices, 64M edges, rows up
+    to ~163k entries, above 65,535), the first four batches of its stream
+    (238, 191, 382 and 172,011 updates: a batch of more than 150,000, with
+    hash tables and fallback slots at that size), in the plain and the
+    batched form side by side, against one oracle, per-update results of
+    every batch and both edge sets at the end."""
+    import torch
+
+    from paper_2505_02741_amd import dygrass as D
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    wl = W.make_workload("rmat22", n_batches=4)
+    deg = np.bincount(np.r_[wl.G.u, wl.G.v], minlength=wl.G.n)
+    say(f"rmat22: n={wl.G.n} m={wl.G.m} max degree {int(deg.max())} H0={int(wl.h_mask.sum())} "
+        f"batches {[b.size for b in wl.batches]} gen {time.time() - t0:.1f}s")
+    assert deg.max() > 65535
+    assert max(b.size for b in wl.batches) >= 150_000
+    import oracle
+
+    rp, col, w = W.to_csr(wl.G.n, wl.G.u, wl.G.v, wl.G.w)
+    say(f"  CSR built ({time.time() - t0:.1f}s)")
+    o = oracle.Oracle(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
+                      L=wl.L)
+    say(f"  oracle ready ({time.time() - t0:.1f}s)")
+    d_plain = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
+                        L=wl.L, flags=0)
+    say(f"  plain context ready ({time.time() - t0:.1f}s)")
+    d_batched = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
+                          L=wl.L, flags=BATCHED)
+    say(f"  batched context ready ({time.time() - t0:.1f}s)")
+    try:
+        for t, b in enumerate(wl.batches):
+            t1 = time.time()
+            ro = o.apply_batch(b.iu, b.iv, b.iw, b.du, b.dv, s=b.s, L=b.L)
+            for tag, d in (("plain", d_plain), ("batched", d_batched)):
+                rl = _device_batch(D, torch, d, b, dev)
+                for key in ("flag", "any_hit", "winner", "n_rec", "steps"):
+                    bad = np.flatnonzero(rl[key] != ro[key])
+                    assert bad.size == 0, f"{tag} batch {t} {key} differs at {bad[:8]}"
+                assert close_R(rl["Rmin"], ro["Rmin"]), (tag, t)
+            say(f"  batch {t}: ins {b.n_ins} del {b.n_del} kept "
+                f"{int(ro['flag'][:b.n_ins].sum())} recovered {int(ro['n_rec'].sum())} "
+                f"steps {int(ro['steps'].sum())} ({time.time() - t1:.1f}s)")
+        for tag, d in (("plain", d_plain), ("batched", d_batched)):
+            compare_state(o, d, f"rmat22 {tag}")
+            st = d.stats()
+            assert st["walk_steps"] == o.steps_total
+            assert st["walk_alg_bytes"] == o.alg_bytes_total
+            say(f"  {tag}: state equal to the oracle's ({time.time() - t0:.1f}s)")
+    finally:
+        d_plain.close()
+        d_batched.close()
+        o.close()

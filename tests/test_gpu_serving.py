@@ -138,3 +138,51 @@ def test_serving_bad_request_leaves_its_graph_and_the_others_intact():
         for o, d in pairs:
             d.close()
             o.close()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_serving_fleet_with_a_two_million_vertex_graph():
+    """A fleet at the serving configuration's sizes: a 1448x1448 grid (about
+    2.1M vertices), a 3D mesh of 64^3, an R-MAT graph of scale 17 and two
+    small graphs, with requests of up to 50,000 updates (60% insertions)
+    fused across graphs; every request's results and every graph's final
+    edge sets against the oracle run on that graph's stream alone."""
+    from paper_2505_02741_amd import dygrass as D
+
+    over = dict(size_lo=1, ins_frac=0.6, s=64, L=24)
+    wls = [
+        W.make_workload("grid1024", seed=21, side=1448, batches=3, size_hi=50_000, **over),
+        W.make_workload("mesh128", seed=22, side=64, batches=3, size_hi=50_000, **over),
+        W.make_workload("rmat22", seed=23, scale=17, batches=3, size_hi=50_000, s_lo=None,
+                        s_hi=None, L_lo=None, L_hi=None, **over),
+        W.make_workload("grid64", seed=24, side=100, batches=4, size_hi=2_000, **over),
+        W.make_workload("mesh128", seed=25, side=16, batches=4, size_hi=1_000, **over),
+    ]
+    say(f"  fleet: {[wl.G.n for wl in wls]} vertices, "
+        f"{[[b.size for b in wl.batches] for wl in wls]} updates")
+    assert max(wl.G.n for wl in wls) >= 2_000_000
+    pairs = [make_pair(wl, flags=BATCHED) for wl in wls]
+    try:
+        expect = [_oracle_stream(o, wl.batches) for (o, _), wl in zip(pairs, wls)]
+        say("  oracle streams done")
+        order = _interleave([len(wl.batches) for wl in wls], np.random.default_rng(5))
+        with D.DygServer(mem_budget=16 << 30, max_fused=8, max_inflight=2) as srv:
+            gids = [srv.add_graph(d) for _, d in pairs]
+            owner = {}
+            for g, t in order:
+                b = wls[g].batches[t]
+                owner[srv.submit(gids[g], b.iu, b.iv, b.iw, b.du, b.dv)] = (g, t)
+            done = srv.drain()
+        assert sorted(owner) == sorted(r["request_id"] for r in done)
+        for r in done:
+            g, t = owner[r["request_id"]]
+            assert r["status"] == 0, (g, t, D.STATUS.get(r["status"]))
+            _check(r["results"], expect[g][t], f"graph {g} batch {t}")
+        for g, (o, d) in enumerate(pairs):
+            compare_state(o, d, f"served graph {g}")
+        say(f"  served {len(done)} requests, all equal to the oracle")
+    finally:
+        for o, d in pairs:
+            d.close()
+            o.close()

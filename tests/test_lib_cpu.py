@@ -81,7 +81,8 @@ def test_flag_values_match_header():
     text = open(os.path.join(ROOT, "include", "dygrass.h")).read()
     defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define DYG_FLAG_(\w+) (\d+)u", text)}
     assert defs == {"LEAN_POOLS": 1, "TIMING": 2, "BATCHED": 4, "GRAPH": 8, "AUTOTUNE": 16,
-                    "TIMING_WALK": 32, "FAIL_POOL_GROWTH": 64}
+                    "TIMING_WALK": 32, "FAIL_POOL_GROWTH": 64, "BOTH_ENDS": 128,
+                    "LOOP_ERASED": 256, "TWO_STAGE": 512}
     for name, v in defs.items():
         assert getattr(D, "FLAG_" + name) == v, name
 
