@@ -4,25 +4,32 @@
 A step is one batch through the whole path: validation, phase 1 (deletions
 leave G and H), the walk kernel (insertion walks on H, deletion walks on G),
 recovery/fallback, and phase 4 (G += insertions, H += accepted + recovered).
-Batches are uploaded to GPU memory before timing (device-resident batches via
-dyg_apply_batch_dev); every step ends with a host synchronisation.
+The batches are in GPU memory before the timed region starts (device-resident
+batches via dyg_apply_batch_dev); every step ends with a host
+synchronisation.  The same batches are also run through dyg_apply_batch from
+host arrays (upload and result download inside each step) and reported
+beside the headline as the PCIe-inclusive rate.
 
-Default workload (the headline line): 1024x1024 circuit-like grid (1,048,576
-vertices, 2,095,104 edges, lognormal(0,1) weights), maximum spanning forest +
-10% off-tree edges as the initial sparsifier, batches of 20,000 local
-insertions (2-6 hops), 64 walkers per update, step limit 32, no distortion
-threshold, in the plain form (one launch sequence and one host sync per
-batch).  The batched form (each wavefront walks the walkers of a few
-consecutive updates, lanes refilled as walkers stop) is timed on the same
-batches for comparison.
+Default workload (the headline line): R-MAT scale 22 (4,194,304 vertices,
+edge factor 16, a=0.57 b=0.19 c=0.19, deduplicated, undirected), weights
+U[1,10), maximum spanning forest + 10% off-tree edges as the initial
+sparsifier, batches of log-uniform size 100..200,000 (70% local insertions,
+30% deletions), walkers 16..128 and step limits 8..32 drawn per update, no
+distortion threshold, in its own form: batched (walker-packed walk launch,
+schedule picked by the autotuner on the warmup batches, each batch's launch
+sequence replayed from a captured hipGraph).  The plain form (one wavefront
+per update, one launch sequence per batch) is timed on the same batches.
+--workload grid1024 / mesh128 run the other configurations (plain form).
 
 --form serving runs the many-graph serving workload instead (Poisson arrivals,
 fused rounds, p50/p99 latency) against the plain form on the same requests.
+--gwalk-stress runs one synthetic batch of 200,000 deletions of sparsifier
+edges on the R-MAT graph: every deletion walks the 2 GB original graph.
 
 Prints one JSON line.  The walk kernel's roofline figure uses its algorithmic
 gathered bytes (counted per step from the live degree of the vertex left) over
 its duration measured with HIP events on its launch stream (two per batch,
-around the walk kernel only: DYG_FLAG_TIMING_WALK).
+around the walk kernel only: DYG_FLAG_TIMING_WALK), over the timed batches.
 """
 from __future__ import annotations
 
@@ -44,6 +51,8 @@ HBM_PEAK_GBS = 8000.0
 # the walk kernels of each form ("a+b": a walk of two launches, summed)
 KERNELS = {"plain": "k_walks", "batched": "k_walk_head+k_walk_tail"}
 TUNE_CANDIDATES = 10  # schedules the autotuner tries, one batch each
+# each configuration's own execution form
+OWN_FORM = {"grid64": "plain", "grid1024": "plain", "mesh128": "plain", "rmat22": "batched"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
 
 
@@ -100,48 +109,88 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(wl, batches, budget_s=20.0):
-    """The CPU oracle as it stands, timed on this host's cores over the first
-    batches of the same stream (as many as fit in about budget_s)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, batches, budget_s=15.0):
+    """The CPU oracle as it stands, timed on this host: first with every
+    thread OpenMP is given (OMP_NUM_THREADS, else all cores), then with one
+    thread, each leg over the next batches of the same stream from the
+    initial state until about budget_s of CPU work."""
     import oracle
     from paper_2505_02741_amd import workloads as W
 
     rp, col, w = W.to_csr(wl.G.n, wl.G.u, wl.G.v, wl.G.w)
+    t0 = time.perf_counter()
     o = oracle.Oracle(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, s=wl.s, L=wl.L,
                       K=wl.K)
-    n_upd = 0
-    t_all = 0.0
-    done = 0
-    for b in batches:
-        t0 = time.perf_counter()
-        o.apply_batch(b.iu, b.iv, b.iw, b.du, b.dv, s=b.s, L=b.L)
-        t_all += time.perf_counter() - t0
-        n_upd += b.size
-        done += 1
-        if t_all > budget_s:
+    t_init = time.perf_counter() - t0
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads_all = int(os.environ.get("OMP_NUM_THREADS", nproc or 1))
+    legs = []
+    it = iter(enumerate(batches))
+    for threads in (threads_all, 1):
+        oracle.set_threads(threads)
+        n_upd = steps0 = 0
+        t_all = 0.0
+        first = last = None
+        steps0 = o.steps_total
+        for i, b in it:
+            t1 = time.perf_counter()
+            o.apply_batch(b.iu, b.iv, b.iw, b.du, b.dv, s=b.s, L=b.L)
+            t_all += time.perf_counter() - t1
+            n_upd += b.size
+            first = i if first is None else first
+            last = i
+            if t_all > budget_s:
+                break
+        if first is None:
             break
-    steps = o.steps_total
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        legs.append(dict(threads=threads, updates=n_upd, seconds=t_all,
+                         steps=o.steps_total - steps0, batches=(first, last)))
     o.close()
-    return {
-        "value": n_upd / t_all,
+    main = legs[0]
+    out = {
+        "value": main["updates"] / main["seconds"],
         "unit": "updates/s",
-        "cores": threads,
+        "cores": main["threads"],
         "kind": "oracle",
-        "sample": f"first {done} batches ({n_upd} updates, {steps} walker steps) of the "
-                  f"same stream from the initial state; C oracle, OpenMP over updates",
-        "walker_steps_per_s": steps / t_all,
-        "seconds": t_all,
+        "sample": f"batches {main['batches'][0]}-{main['batches'][1]} ({main['updates']} "
+                  f"updates, {main['steps']} walker steps) of the same stream from the initial "
+                  f"state; C oracle, OpenMP over the updates of a batch, "
+                  f"{main['threads']} threads",
+        "walker_steps_per_s": main["steps"] / main["seconds"],
+        "seconds": main["seconds"],
+        "nproc": nproc,
+        "cpu_model": cpu_model(),
+        "oracle_init_s": t_init,
     }
+    if len(legs) > 1:
+        one = legs[1]
+        out["one_thread"] = {
+            "value": one["updates"] / one["seconds"], "unit": "updates/s", "cores": 1,
+            "sample": f"batches {one['batches'][0]}-{one['batches'][1]} ({one['updates']} "
+                      f"updates, {one['steps']} walker steps), continuing the same stream",
+            "walker_steps_per_s": one["steps"] / one["seconds"], "seconds": one["seconds"]}
+    return out
 
 
-def traffic_from_counters(fetch_csv, write_csv, kernel, calib_bytes, workload, form):
+def traffic_from_counters(fetch_csv, write_csv, kernel, calib_bytes, workload, form, window=0):
     """Per-launch HBM bytes of `kernel` from two rocprofv3 --pmc runs of the
     same bench command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
     scaled so that the copy kernel of calib_bytes (the --calibrate-copy-mib
     run) reads and writes exactly calib_bytes (that copy is told from the
     workload's small copies by size: its counters read at least a quarter of
-    calib_bytes); written to the traffic file."""
+    calib_bytes); averaged over the last `window` dispatches of the kernel
+    (the bench's timed batches; 0 = all), written to the traffic file."""
 
     names = kernel.split("+")
 
@@ -161,6 +210,10 @@ def traffic_from_counters(fetch_csv, write_csv, kernel, calib_bytes, workload, f
 
     f_vals, f_copy = per_kernel(fetch_csv, "FETCH_SIZE")
     w_vals, w_copy = per_kernel(write_csv, "WRITE_SIZE")
+    if window:
+        # rows come in dispatch order: the timed batches are the last ones
+        f_vals = {k: v[-window:] for k, v in f_vals.items()}
+        w_vals = {k: v[-window:] for k, v in w_vals.items()}
     if not all(f_vals.values()) or not all(w_vals.values()) or not f_copy or not w_copy:
         raise SystemExit("traffic: kernel or calibration copy missing from the counter files")
     f_scale = calib_bytes / max(f_copy)
@@ -203,16 +256,24 @@ def reserve_for(D, ctx, batches):
                   max((int(b.L.max()) for b in batches if b.L is not None and b.size), default=0))
 
 
-def run_stream(D, torch, wl, rp, col, w, dev_batches, flags, warmup, tuning=None):
+def run_stream(D, torch, wl, rp, col, w, dev_batches, flags, warmup, tuning=None, host=False):
     """Apply every batch in order on a fresh context (buffers reserved for the
-    largest batch); time all but the first `warmup` batches."""
+    largest batch); time all but the first `warmup` batches.  host: each step
+    hands host arrays to dyg_apply_batch, which uploads the batch and
+    downloads its per-update results inside the step."""
+    t0 = time.perf_counter()
     ctx = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
                     L=wl.L, flags=D.FLAG_TIMING_WALK | flags)
     reserve_for(D, ctx, wl.batches)
+    t_init = time.perf_counter() - t0
     if tuning:
         D.dyg_set_tuning(ctx.ctx, *tuning)
 
     def step(i):
+        if host:
+            b = wl.batches[i]
+            ctx.apply_batch(b.iu, b.iv, b.iw, b.du, b.dv, s=b.s, L=b.L)
+            return
         db = dev_batches[i]
         D.dyg_apply_batch_dev(ctx.ctx, db["iu"], db["iv"], db["iw"], db["du"], db["dv"],
                               s=db["s"], L=db["L"], L_max=db["L_max"], s_max=db["s_max"],
@@ -234,7 +295,8 @@ def run_stream(D, torch, wl, rp, col, w, dev_batches, flags, warmup, tuning=None
     st1 = ctx.stats()
     tuning_kept = D.dyg_get_tuning(ctx.ctx)
     ctx.close()
-    r = dict(t_total=t_total, lat=lat, tuning=tuning_kept, h_edges_end=st1["h_edges"])
+    r = dict(t_total=t_total, lat=lat, tuning=tuning_kept, h_edges_end=st1["h_edges"],
+             t_init=t_init)
     for k in ("walk_steps", "walk_alg_bytes", "walk_ms_total", "walk_launches"):
         r[k] = st1[k] - st0[k]
     return r
@@ -271,6 +333,12 @@ def main_batches(args):
         print(f"# copy calibration: {nbytes} bytes read, {nbytes} bytes written",
               file=sys.stderr, flush=True)
         del src, dst
+    own = OWN_FORM[args.workload]
+    head = args.form if args.form in ("plain", "batched") else own
+    graph = args.graph if args.graph is not None else (head == "batched")
+    autotune = args.autotune if args.autotune is not None else (head == "batched")
+    if autotune and head == "batched" and args.warmup < TUNE_CANDIDATES:
+        args.warmup = TUNE_CANDIDATES
     n_batches = args.warmup + args.steps
     t0 = time.perf_counter()
     wl = W.make_workload(args.workload, seed=args.seed, n_batches=n_batches)
@@ -280,23 +348,28 @@ def main_batches(args):
     dev_batches = [to_device(np, torch, dev, b) for b in wl.batches]
     torch.cuda.synchronize()
 
-    forms = {"plain": 0, "batched": D.FLAG_BATCHED | (D.FLAG_GRAPH if args.graph else 0) |
-             (D.FLAG_AUTOTUNE if args.autotune else 0)}
-    head = args.form if args.form in forms else ("plain" if args.workload != "rmat22" else "batched")
-    chosen = [head] if args.form in forms else list(forms)
+    batched_flags = D.FLAG_BATCHED | (D.FLAG_AUTOTUNE if autotune else 0)
+    flags = {"plain": 0, "batched": batched_flags | (D.FLAG_GRAPH if graph else 0)}
+    chosen = [head] if args.form in ("plain", "batched") else ["plain", "batched"]
     runs = {}
     for name in chosen:
-        runs[name] = run_stream(D, torch, wl, rp, col, w, dev_batches, forms[name], args.warmup)
-        print(f"# {name}: {runs[name]['t_total'] / args.steps * 1e3:.3f} ms/step",
-              file=sys.stderr, flush=True)
+        runs[name] = run_stream(D, torch, wl, rp, col, w, dev_batches, flags[name], args.warmup)
+        print(f"# {name}: {runs[name]['t_total'] / args.steps * 1e3:.3f} ms/step "
+              f"(context init {runs[name]['t_init']:.1f}s)", file=sys.stderr, flush=True)
     # the walk kernel inside a captured graph is not timed: the roofline of the
     # batched form then comes from the same schedule launched directly
-    if "batched" in runs and head == "batched" and args.graph:
-        timed = run_stream(D, torch, wl, rp, col, w, dev_batches,
-                           D.FLAG_BATCHED | (D.FLAG_AUTOTUNE if args.autotune else 0),
-                           args.warmup)
+    if head == "batched" and graph:
+        timed = run_stream(D, torch, wl, rp, col, w, dev_batches, batched_flags, args.warmup)
+        print(f"# batched, direct launches (walk timing): "
+              f"{timed['t_total'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     else:
         timed = runs[head]
+    pcie = None
+    if not args.no_pcie:
+        pcie = run_stream(D, torch, wl, rp, col, w, dev_batches, flags[head], args.warmup,
+                          host=True)
+        print(f"# {head}, host arrays (PCIe inside each step): "
+              f"{pcie['t_total'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     R = runs[head]
     updates = sum(b.size for b in wl.batches[args.warmup:])
     t_total, lat = R["t_total"], R["lat"]
@@ -307,6 +380,7 @@ def main_batches(args):
     avg_walk_s = walk_ms / 1e3 / max(launches, 1)
     bytes_per_launch = alg_bytes / max(launches, 1)
     achieved = bytes_per_launch / avg_walk_s / 1e9 if avg_walk_s > 0 else 0.0
+    kernel = walk_kernels(head, timed.get("tuning"))
     cfg = wl.meta["cfg"]
     if cfg["kind"] == "rmat":
         shape = f"R-MAT scale {cfg['scale']} edge factor {cfg['ef']}"
@@ -319,6 +393,13 @@ def main_batches(args):
         stream = f"batches of {cfg.get('ins')} insertions + {cfg.get('dels')} deletions"
     walk = (f"s={cfg['s_lo']}-{cfg['s_hi']}, L={cfg['L_lo']}-{cfg['L_hi']} per update"
             if cfg.get("s_lo") else f"s={wl.s}, L={wl.L}")
+    if head == "batched":
+        form_text = ("batched form (walker-packed walk launch" +
+                     (", schedule autotuned on the warmup batches" if autotune else "") +
+                     (", launch sequence replayed from a captured hipGraph" if graph else "") +
+                     "), one host sync per batch")
+    else:
+        form_text = "plain form, one launch sequence and one host sync per batch"
     out = {
         "metric": METRIC,
         "value": updates / t_total,
@@ -334,8 +415,8 @@ def main_batches(args):
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {shape} (n={wl.G.n}, m={wl.G.m}), weights "
-                        f"{cfg['weights']}, {stream}, {walk}, K=inf, {head} form, "
-                        f"one launch sequence and one host sync per batch",
+                        f"{cfg['weights']}, {stream}, {walk}, K=inf, {form_text}; batches "
+                        f"resident in GPU memory",
             "global_batch": int(updates / args.steps),
             "parallelism": "single GPU",
         },
@@ -348,7 +429,7 @@ def main_batches(args):
         "forms": form_summary(runs, updates, args.steps),
         "roofline": {
             "bound": "hbm",
-            "kernel": walk_kernels(head, timed.get("tuning")),
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -356,9 +437,15 @@ def main_batches(args):
             "traffic": measured_traffic(args.workload, head),
             "alg_bytes_per_launch": bytes_per_launch,
             "alg_bytes_per_step": alg_bytes / max(steps_walk, 1),
+            "launches": launches,
         },
         "cpu_baseline": None,
     }
+    if pcie is not None:
+        out["pcie_inclusive"] = {"updates_per_s": updates / pcie["t_total"],
+                                 "ms_per_step": pcie["t_total"] / args.steps * 1e3,
+                                 "p50_batch_ms": percentile(pcie["lat"], 0.5) * 1e3,
+                                 "p99_batch_ms": percentile(pcie["lat"], 0.99) * 1e3}
     # off-tree density of the sparsifier, |E_H| / |V| - 1 (Sec. IV metric),
     # before the stream and after its last batch (read after the timed region)
     out["d_H"] = {"initial": int(wl.h_mask.sum()) / wl.G.n - 1.0,
@@ -511,29 +598,113 @@ def main_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def main_gwalk_stress(args):
+    """One batch of 200,000 deletions drawn uniformly from the sparsifier's
+    edges of the R-MAT scale-22 graph, walkers 16..128 and step limits 8..32
+    per update: every deletion walks the original graph (about 2 GB of rows,
+    well beyond the 256 MB cache), so the walk kernel reads HBM.  A warmup
+    batch of 2,000 other such deletions comes first.  Reports the walk kernel
+    alone (HIP events) against its algorithmic gathered bytes."""
+    import numpy as np
+    import torch
+
+    from paper_2505_02741_amd import dygrass as D
+    from paper_2505_02741_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    t0 = time.perf_counter()
+    wl = W.make_workload("rmat22", seed=args.seed, n_batches=0)
+    rng = np.random.default_rng(np.random.SeedSequence([args.seed, 0x6A1C]))
+    n_del, n_warm = 200_000, 2_000
+    h_idx = np.flatnonzero(wl.h_mask)
+    pick = rng.choice(h_idx, n_del + n_warm, replace=False)
+    batches = []
+    for sel in (pick[:n_warm], pick[n_warm:]):
+        b = W.Batch(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.float64),
+                    wl.G.u[sel].astype(np.uint32), wl.G.v[sel].astype(np.uint32))
+        b.s = rng.integers(16, 129, b.size).astype(np.uint16)
+        b.L = rng.integers(8, 33, b.size).astype(np.uint16)
+        batches.append(b)
+    wl.batches = batches
+    print(f"# gwalk stress: n={wl.G.n} m={wl.G.m} gen={time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    rp, col, w = W.to_csr(wl.G.n, wl.G.u, wl.G.v, wl.G.w)
+    dev_batches = [to_device(np, torch, dev, b) for b in batches]
+    form = args.form if args.form in ("plain", "batched") else "plain"
+    flags = D.FLAG_BATCHED if form == "batched" else 0
+    r = run_stream(D, torch, wl, rp, col, w, dev_batches, flags, 1)
+    walk_s = r["walk_ms_total"] / 1e3 / max(r["walk_launches"], 1)
+    achieved = r["walk_alg_bytes"] / max(r["walk_launches"], 1) / walk_s / 1e9 if walk_s else 0
+    out = {
+        "metric": METRIC,
+        "value": n_del / r["t_total"],
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": r["t_total"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"gwalk_stress: R-MAT scale 22 (n={wl.G.n}, m={wl.G.m}), one "
+                               f"batch of {n_del} deletions of sparsifier edges (walks on the "
+                               f"original graph), s=16-128, L=8-32 per update, {form} form",
+                   "global_batch": n_del, "parallelism": "single GPU"},
+        "walk_kernel_ms": walk_s * 1e3,
+        "walk_steps": r["walk_steps"],
+        "walk_kernel_steps_per_s": r["walk_steps"] / walk_s if walk_s else None,
+        "roofline": {"bound": "hbm", "kernel": walk_kernels(form, r.get("tuning")),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("gwalk_stress", form),
+                     "alg_bytes_per_launch": r["walk_alg_bytes"] / max(r["walk_launches"], 1),
+                     "alg_bytes_per_step": r["walk_alg_bytes"] / max(r["walk_steps"], 1)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="grid1024",
+    ap.add_argument("--workload", default="rmat22",
                     choices=["grid64", "grid1024", "mesh128", "rmat22"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pcie", action="store_true",
+                    help="skip the host-array (PCIe-inclusive) run of the same batches")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the workload, copy this many MiB device to device once "
                          "(a known-size kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--form", choices=["both", "plain", "batched", "serving"], default="both",
-                    help="plain: one wavefront per update; batched: range walk; both: time "
-                         "both, report the workload's own form; serving: the many-graph "
+                    help="plain: one wavefront per update; batched: walker-packed walk; both: "
+                         "time both, report the workload's own form; serving: the many-graph "
                          "serving workload")
-    ap.add_argument("--graph", action="store_true",
+    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=None,
                     help="batched form: replay each batch's launch sequence from a captured "
-                         "hipGraph (one per power-of-two size class)")
-    ap.add_argument("--autotune", action="store_true",
+                         "hipGraph (one per power-of-two size class); default on for a "
+                         "workload whose own form is batched")
+    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=None,
                     help="batched form: the first batches try the autotuner's schedules "
                          f"(warmup raised to at least {TUNE_CANDIDATES} so that they are "
-                         "not timed)")
+                         "not timed); default on for a workload whose own form is batched")
+    ap.add_argument("--gwalk-stress", action="store_true",
+                    help="one synthetic batch of 200,000 deletions of sparsifier edges on "
+                         "the R-MAT graph (every deletion walks the original graph)")
     ap.add_argument("--graphs", type=int, default=64, help="serving: resident graphs")
     ap.add_argument("--requests-per-graph", type=int, default=16)
     ap.add_argument("--max-nodes", type=int, default=500_000)
@@ -543,6 +714,9 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic file from two rocprofv3 counter runs of this "
                          "command (with --calibrate-copy-mib) instead of running")
+    ap.add_argument("--traffic-kernel", default=None,
+                    help="with --traffic-from: the walk kernel(s) to read ('a+b' sums two); "
+                         "default: the form's default schedule")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -550,15 +724,18 @@ def main():
               "supported (sharding over several GPUs is designed, not implemented).",
               file=sys.stderr)
         sys.exit(2)
-    if args.autotune and args.warmup < TUNE_CANDIDATES:
-        args.warmup = TUNE_CANDIDATES
     if args.traffic_from:
-        form = args.form if args.form in KERNELS else "plain"
-        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], KERNELS[form],
-                              args.calibrate_copy_mib << 20, args.workload, form)
+        form = args.form if args.form in KERNELS else OWN_FORM[args.workload]
+        kernel = args.traffic_kernel or KERNELS[form]
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], kernel,
+                              args.calibrate_copy_mib << 20,
+                              "gwalk_stress" if args.gwalk_stress else args.workload, form,
+                              window=1 if args.gwalk_stress else args.steps)
         return
     if args.form == "serving":
         main_serving(args)
+    elif args.gwalk_stress:
+        main_gwalk_stress(args)
     else:
         main_batches(args)
 

@@ -238,7 +238,8 @@ struct dyg_ctx {
   // batch staging
   DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, ubytes, wrec, wofs, hadd, hash;
   DBuf fb_list;
-  DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2], wide_rows[2];
+  DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2], wide_rows[2],
+      wmerge[2], dirty_chunk0[2];
   DBuf hash2;
   DBuf qcount, qofs, qtile, items, wres;  // batched form
   DBuf tstate, tcount;                     // batched form, head/tail schedule
@@ -535,13 +536,24 @@ int validate_csr(uint32_t n, const uint64_t* rowptr, const uint32_t* col, const 
       wm = std::max(wm, w[k]);
     }
   }
+  // symmetric with equal weights iff the transpose equals the graph: build
+  // it by counting (filling rows in ascending u keeps each row ascending)
+  std::vector<uint64_t> tptr(static_cast<size_t>(n) + 1, 0);
+  for (uint64_t k = 0; k < nnz; ++k) tptr[col[k] + 1]++;
+  for (uint32_t u = 0; u < n; ++u) tptr[u + 1] += tptr[u];
+  for (uint32_t u = 0; u <= n; ++u)
+    if (tptr[u] != rowptr[u]) return DYG_E_INVALID_ARG;  // asymmetric degrees
+  std::vector<uint32_t> tcol(nnz);
+  std::vector<double> tw(nnz);
+  std::vector<uint64_t> fill(tptr.begin(), tptr.end() - 1);
   for (uint32_t u = 0; u < n; ++u)
     for (uint64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
-      const uint32_t* lo = col + rowptr[col[k]];
-      const uint32_t* hi = col + rowptr[col[k] + 1];
-      const uint32_t* it = std::lower_bound(lo, hi, u);
-      if (it == hi || *it != u || w[it - col] != w[k]) return DYG_E_INVALID_ARG;  // asymmetric
+      const uint64_t at = fill[col[k]]++;
+      tcol[at] = u;
+      tw[at] = w[k];
     }
+  for (uint64_t k = 0; k < nnz; ++k)
+    if (tcol[k] != col[k] || tw[k] != w[k]) return DYG_E_INVALID_ARG;  // asymmetric
   if (wmax) *wmax = wm;
   return DYG_OK;
 }
@@ -775,7 +787,9 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
     const uint64_t cap = g == 0 ? 2 * n_ins : 2 * hadd_cap;
     ok = c->touched_rows[g].ensure(4 * cap + 8) && c->touched_k[g].ensure(4 * cap + 8) &&
          c->touched_need[g].ensure(4 * cap + 8) && c->add_keep[g].ensure(cap + 8) &&
-         c->dirty_rows[g].ensure(4 * (cap + 2 * n_del) + 8) && c->wide_rows[g].ensure(4 * cap + 8);
+         c->dirty_rows[g].ensure(4 * (cap + 2 * n_del) + 8) &&
+         c->dirty_chunk0[g].ensure(4 * (cap + 2 * n_del) + 8) && c->wide_rows[g].ensure(4 * cap + 8) &&
+         c->wmerge[g].ensure(sizeof(dyg::WideMerge) * cap + 8);
   }
   return ok ? DYG_OK : DYG_E_NOMEM;
 }
@@ -834,7 +848,9 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
     a.touched_need[g] = c->touched_need[g].as<uint32_t>();
     a.add_keep[g] = c->add_keep[g].as<uint8_t>();
     a.dirty_rows[g] = c->dirty_rows[g].as<uint32_t>();
+    a.dirty_chunk0[g] = c->dirty_chunk0[g].as<uint32_t>();
     a.wide_rows[g] = c->wide_rows[g].as<uint32_t>();
+    a.wmerge[g] = c->wmerge[g].as<dyg::WideMerge>();
   }
   a.qcount = c->qcount.as<uint32_t>();
   a.qofs = c->qofs.as<unsigned long long>();
@@ -910,7 +926,9 @@ void carve_batch(const dyg_ctx* c, BatchArgs& a, Carve& m, uint64_t n_ins, uint6
     a.touched_need[g] = m.take<uint32_t>(4 * cap + 8);
     a.add_keep[g] = m.take<uint8_t>(cap + 8);
     a.dirty_rows[g] = m.take<uint32_t>(4 * (cap + 2 * n_del) + 8);
+    a.dirty_chunk0[g] = m.take<uint32_t>(4 * (cap + 2 * n_del) + 8);
     a.wide_rows[g] = m.take<uint32_t>(4 * cap + 8);
+    a.wmerge[g] = m.take<dyg::WideMerge>(sizeof(dyg::WideMerge) * cap + 8);
   }
 }
 
@@ -1782,7 +1800,9 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
     c->touched_need[g].release();
     c->add_keep[g].release();
     c->dirty_rows[g].release();
+    c->dirty_chunk0[g].release();
     c->wide_rows[g].release();
+    c->wmerge[g].release();
   }
   c->pin_in.release();
   c->pin_out.release();

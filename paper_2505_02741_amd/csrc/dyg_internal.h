@@ -203,12 +203,13 @@ struct BatchCtl {
   uint32_t touched[2];          // touched rows, per graph (0 = G, 1 = H)
   unsigned long long need[2];   // pool slots needed by relocations, per graph
   uint32_t nomem[2];            // phase-4 pool shortfall, per graph
-  uint32_t dirty[2];            // rows whose weight tree must be rebuilt, per graph
   uint32_t wide[2];             // touched rows moved or merged by a workgroup, per graph
   uint32_t hubs;                // set when phase 4 leaves a row longer than kHub
   uint32_t fb_count;            // deletions whose fallback scan is left to k_fallback_wide
   unsigned long long pool_top[2];  // next free pool slot, per graph
   unsigned long long stage_used[2];  // pool slots past pool_top used to stage wide merges
+  unsigned long long wpack[2];  // parallel wide merges: (chunks << 32) | merges, per graph
+  unsigned long long tpack[2];  // weight trees to rebuild: (chunks << 32) | rows, per graph
   unsigned long long walk_items;       // walkers queued (queue control only)
   unsigned long long queue_next;       // next queue item to hand out (queue control only)
   unsigned long long item_base;        // first queue item of this batch
@@ -217,6 +218,23 @@ struct BatchCtl {
   unsigned long long alg_bytes_total;  // algorithmic gathered bytes of those steps
   uint32_t heavy;  // some quantised weight of G or H is >= kHeavyQw (set, never cleared)
 };
+
+// A wide merge done by many workgroups: the row's k appended entries sorted
+// and staged at new_off, its old entries [stay, cur) staged right after them
+// (new_off + k); both are written back to their merged slots by chunks of
+// kMergeChunk old entries, chunk0 .. chunk0 + chunks - 1 of the graph's list.
+struct WideMerge {
+  uint32_t r;        // row
+  uint32_t k;        // appended entries
+  uint32_t stay;     // first old entry that moves (the first new entry's final slot)
+  uint32_t cur;      // old entries
+  uint32_t seg_off;  // the row's pool segment
+  uint32_t new_off;  // pool slot of the staged entries
+  uint32_t chunk0;   // first chunk (increasing with the merge's index)
+  uint32_t chunks;   // at least one
+};
+static_assert(sizeof(WideMerge) == 32, "WideMerge layout");
+constexpr uint32_t kMergeChunk = 512;  // old entries per wavefront unit of a parallel wide merge
 
 // Slot of the validation / dedup hash table.
 struct HashSlot {
@@ -267,8 +285,10 @@ struct BatchArgs {
   uint32_t* touched_k[2];
   uint32_t* touched_need[2];
   uint8_t* add_keep[2];       // per directed add entry: 1 = needs a new slot
-  uint32_t* dirty_rows[2];    // rows whose weight prefix must be rebuilt
+  uint32_t* dirty_rows[2];    // rows whose weight tree must be rebuilt, in claim order
+  uint32_t* dirty_chunk0[2];  // first tree chunk of each (increasing)
   uint32_t* wide_rows[2];     // indices into touched_* of the rows with a wide flag
+  WideMerge* wmerge[2];       // [add capacity] the parallel wide merges, in claim order
   // batched form: walker work queue
   uint32_t* qcount;              // [n_ins + n_del] walkers of each update
   unsigned long long* qofs;      // [n_ins + n_del] first item of each update

@@ -112,6 +112,7 @@ __device__ __forceinline__ BatchArgs load_args(const BatchArgs* const* __restric
     a.touched_need[w] = load_gptr(&ap->touched_need[w]);
     a.add_keep[w] = load_gptr(&ap->add_keep[w]);
     a.dirty_rows[w] = load_gptr(&ap->dirty_rows[w]);
+    a.dirty_chunk0[w] = load_gptr(&ap->dirty_chunk0[w]);
     a.wide_rows[w] = load_gptr(&ap->wide_rows[w]);
   }
   a.qcount = load_gptr(&ap->qcount);
@@ -364,9 +365,10 @@ __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
     for (int w = 0; w < 2; ++w) {
       ctl->touched[w] = 0;
       ctl->stage_used[w] = 0;
+      ctl->wpack[w] = 0;
       ctl->need[w] = 0;
       ctl->nomem[w] = 0;
-      ctl->dirty[w] = 0;
+      ctl->tpack[w] = 0;
       ctl->wide[w] = 0;
     }
   }
@@ -488,13 +490,15 @@ __global__ void k_phase1(const BatchArgs* const* __restrict__ argv) {
 }
 
 // Rebuild the weight tree (level 0 in pfx, levels 1.. in tree) of every long
-// segment listed dirty by phase 4 (merged or relocated), one workgroup per
-// segment, then clear its mark.  A chunk of kTreeChunk = 16^3 entries fills
-// levels 0-2 of its part of the tree on its own: the weights are staged in
-// LDS with coalesced reads, each thread sums one block of 16 entries, and the
-// level-0 values go back through LDS for coalesced writes.  Levels 3.. (rows
-// longer than one chunk) are summed from the chunk totals at the end.  The
-// graph is which0 + blockIdx.z.
+// segment listed dirty by phase 4 (merged or relocated), a chunk of
+// kTreeChunk = 16^3 entries per workgroup iteration, the chunks of all rows
+// in one grid-stride loop.  A chunk fills levels 0-2 of its part of the tree
+// on its own: the weights are staged in LDS with coalesced reads, each thread
+// sums one block of 16 entries, and the level-0 values go back through LDS
+// for coalesced writes.  A row longer than one chunk gets its chunk totals
+// on level 3; the workgroup that finishes its last chunk (the row's mark
+// counts finished chunks) sums levels 3.. from them.  The graph is
+// which0 + blockIdx.z.
 constexpr uint32_t kTreeChunk = kBlock * kFan;  // 4096 entries: one level-2 block
 static_assert(kTreeChunk == kFan * kFan * kFan, "a chunk is one level-2 block");
 
@@ -509,13 +513,23 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
   DevGraph X;
   load_graph(X, ap, static_cast<int>(which));
   const uint32_t* dirty_rows = load_gptr(&ap->dirty_rows[which]);
-  const uint32_t count = ctl->dirty[which];
+  const uint32_t* chunk0 = load_gptr(&ap->dirty_chunk0[which]);
+  const unsigned long long pack = ctl->tpack[which];
+  const uint32_t rows = static_cast<uint32_t>(pack), units = static_cast<uint32_t>(pack >> 32);
   __shared__ uint32_t s_q[lds_pad(kTreeChunk)];            // weights of the chunk
   __shared__ unsigned long long s_v[lds_pad(kTreeChunk)];  // its level-0 values
   __shared__ unsigned long long s_t[kBlock];               // block totals
+  __shared__ uint32_t s_last;
   const uint32_t t = threadIdx.x;
-  for (uint32_t di = blockIdx.x; di < count; di += gridDim.x) {
-    const uint32_t r = dirty_rows[di];
+  for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    uint32_t lo = 0, hi = rows;  // first row whose chunks start above u
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (chunk0[mid] <= u) lo = mid + 1;
+      else hi = mid;
+    }
+    const uint32_t r = dirty_rows[lo - 1];
+    const uint32_t ch = u - chunk0[lo - 1];
     const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment, aligned
     const uint32_t len = row.len;
     const uint32_t K = tree_top(len);
@@ -526,82 +540,91 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
     unsigned long long* l1 = tb;  // tree_base(len, 1) == 0
     unsigned long long* l2 = tb + tree_base(len, 2);
     const uint32_t chunks = (len + kTreeChunk - 1) / kTreeChunk;
-    unsigned long long total = 0;  // thread 0
-    for (uint32_t ch = 0; ch < chunks; ++ch) {
-      const uint32_t e0 = ch * kTreeChunk;
-      const uint32_t ne = len - e0 < kTreeChunk ? len - e0 : kTreeChunk;
+    const uint32_t e0 = ch * kTreeChunk;
+    const uint32_t ne = len - e0 < kTreeChunk ? len - e0 : kTreeChunk;
 #pragma unroll
-      for (uint32_t j = 0; j < kFan; ++j) {
-        const uint32_t i = t + kBlock * j;
-        s_q[lds_pad(i)] = i < ne ? seg[e0 + i].qw : 0u;
-      }
-      __syncthreads();
-      // level 0: thread t sums block t of the chunk
-      unsigned long long run = 0;
-#pragma unroll
-      for (uint32_t j = 0; j < kFan; ++j) {
-        const uint32_t i = kFan * t + j;
-        run += s_q[lds_pad(i)];
-        s_v[lds_pad(i)] = i < ne ? run : kTreePad;
-      }
-      s_t[t] = run;
-      __syncthreads();
-      const uint32_t nw = round_fan(ne);  // level-0 slots of the chunk, padding included
-#pragma unroll
-      for (uint32_t j = 0; j < kFan; ++j) {
-        const uint32_t i = t + kBlock * j;
-        if (i < nw) l0[e0 + i] = s_v[lds_pad(i)];
-      }
-      // level 1: value b = running sum of block totals within b's group of 16
-      const uint32_t b = ch * kBlock + t;  // level-1 index of block t
-      {
-        unsigned long long v1 = 0;
-        for (uint32_t j = t & ~(kFan - 1); j <= t; ++j) v1 += s_t[j];
-        if (b < round_fan(n1)) l1[b] = b < n1 ? v1 : kTreePad;
-      }
-      __syncthreads();
-      // group totals (level-2 inputs) into s_t[0..15], chunk total
-      unsigned long long gsum = 0;
-      if (t < kFan)
-        for (uint32_t j = 0; j < kFan; ++j) gsum += s_t[kFan * t + j];
-      __syncthreads();
-      if (t < kFan) s_t[t] = gsum;
-      __syncthreads();
-      unsigned long long ctot = 0;
-      for (uint32_t j = 0; j < kFan; ++j) ctot += s_t[j];
-      if (K == 1 && t == kFan - 1) l1[kFan - 1] = ctot;  // top block slot: the total
-      if (K >= 2 && t < kFan) {
-        const uint32_t c = ch * kFan + t;  // level-2 index
-        unsigned long long v2 = 0;
-        for (uint32_t j = 0; j <= t; ++j) v2 += s_t[j];
-        if (K == 2 && t == kFan - 1) l2[c] = ctot;  // top block slot: the total
-        else l2[c] = c < n2 ? v2 : kTreePad;
-      }
-      if (K >= 3 && t == 0) tb[tree_base(len, 3) + ch] = ctot;  // raw chunk total
-      if (t == 0) total += ctot;
-      __syncthreads();
+    for (uint32_t j = 0; j < kFan; ++j) {
+      const uint32_t i = t + kBlock * j;
+      s_q[lds_pad(i)] = i < ne ? seg[e0 + i].qw : 0u;
     }
-    if (K >= 3 && t == 0) {
+    __syncthreads();
+    // level 0: thread t sums block t of the chunk
+    unsigned long long run = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kFan; ++j) {
+      const uint32_t i = kFan * t + j;
+      run += s_q[lds_pad(i)];
+      s_v[lds_pad(i)] = i < ne ? run : kTreePad;
+    }
+    s_t[t] = run;
+    __syncthreads();
+    const uint32_t nw = round_fan(ne);  // level-0 slots of the chunk, padding included
+#pragma unroll
+    for (uint32_t j = 0; j < kFan; ++j) {
+      const uint32_t i = t + kBlock * j;
+      if (i < nw) l0[e0 + i] = s_v[lds_pad(i)];
+    }
+    // level 1: value b = running sum of block totals within b's group of 16
+    const uint32_t b = ch * kBlock + t;  // level-1 index of block t
+    {
+      unsigned long long v1 = 0;
+      for (uint32_t j = t & ~(kFan - 1); j <= t; ++j) v1 += s_t[j];
+      if (b < round_fan(n1)) l1[b] = b < n1 ? v1 : kTreePad;
+    }
+    __syncthreads();
+    // group totals (level-2 inputs) into s_t[0..15], chunk total
+    unsigned long long gsum = 0;
+    if (t < kFan)
+      for (uint32_t j = 0; j < kFan; ++j) gsum += s_t[kFan * t + j];
+    __syncthreads();
+    if (t < kFan) s_t[t] = gsum;
+    __syncthreads();
+    unsigned long long ctot = 0;
+    for (uint32_t j = 0; j < kFan; ++j) ctot += s_t[j];
+    if (K == 1 && t == kFan - 1) l1[kFan - 1] = ctot;  // top block slot: the total
+    if (K >= 2 && t < kFan) {
+      const uint32_t c = ch * kFan + t;  // level-2 index
+      unsigned long long v2 = 0;
+      for (uint32_t j = 0; j <= t; ++j) v2 += s_t[j];
+      if (K == 2 && t == kFan - 1) l2[c] = ctot;  // top block slot: the total
+      else l2[c] = c < n2 ? v2 : kTreePad;
+    }
+    if (K >= 3 && t == 0) tb[tree_base(len, 3) + ch] = ctot;  // raw chunk total
+    if (chunks == 1) {
+      if (t == 0) X.mark[r] = 0u;
+      __syncthreads();
+      continue;
+    }
+    if (t == 0) {
+      __threadfence();  // this chunk's total before its count
+      s_last = atomicAdd(&X.mark[r], 1u) == chunks ? 1u : 0u;  // mark starts at 1
+      __threadfence();  // every other chunk's total after the count
+    }
+    __syncthreads();
+    if (s_last && t == 0) {
       // levels 3..K from the raw totals on level 3: running sums within
-      // blocks of 16, each block total handed up as the next level's raw value
+      // blocks of 16, each block total handed up as the next level's raw
+      // value; the top block's last slot is the row total
+      unsigned long long total = 0;
       for (uint32_t l = 3; l <= K; ++l) {
         const uint32_t n = tree_n(len, l);
         unsigned long long* lv = tb + tree_base(len, l);
         unsigned long long* up = l < K ? tb + tree_base(len, l + 1) : nullptr;
-        unsigned long long run = 0;
+        unsigned long long run3 = 0;
         for (uint32_t i = 0; i < n; ++i) {
-          run += lv[i];
-          lv[i] = run;
+          run3 += lv[i];
+          if (l == 3) total += lv[i];
+          lv[i] = run3;
           if ((i & (kFan - 1)) == kFan - 1 || i == n - 1) {
-            if (up) up[i >> 4] = run;
-            run = 0;
+            if (up) up[i >> 4] = run3;
+            run3 = 0;
           }
         }
         for (uint32_t i = n; i < round_fan(n); ++i) lv[i] = kTreePad;
         if (l == K) lv[kFan - 1] = total;
       }
+      X.mark[r] = 0u;
     }
-    if (t == 0) X.mark[r] = 0u;
     __syncthreads();
   }
 }
@@ -2135,7 +2158,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_counters(const BatchArgs* const*
 struct P4 {
   DevGraph X;
   BatchCtl* ctl;
-  uint32_t *touched_rows, *touched_k, *touched_need, *dirty_rows, *wide_rows;
+  uint32_t *touched_rows, *touched_k, *touched_need, *dirty_rows, *dirty_chunk0, *wide_rows;
+  WideMerge* wmerge;
   uint8_t* add_keep;
   uint32_t n, n_ins, hadd_cap, hash_mask;
   const uint32_t *iu, *iv, *ins_qw;
@@ -2155,7 +2179,9 @@ __device__ __forceinline__ P4 load_p4(const BatchArgs* const* __restrict__ argv,
   v.touched_k = load_gptr(&ap->touched_k[which]);
   v.touched_need = load_gptr(&ap->touched_need[which]);
   v.dirty_rows = load_gptr(&ap->dirty_rows[which]);
+  v.dirty_chunk0 = load_gptr(&ap->dirty_chunk0[which]);
   v.wide_rows = load_gptr(&ap->wide_rows[which]);
+  v.wmerge = load_gptr(&ap->wmerge[which]);
   v.add_keep = load_gptr(&ap->add_keep[which]);
   v.n = ap->n;
   v.n_ins = ap->n_ins;
@@ -2171,10 +2197,18 @@ __device__ __forceinline__ P4 load_p4(const BatchArgs* const* __restrict__ argv,
   return v;
 }
 
-__device__ __forceinline__ void mark_dirty4(const P4& a, uint32_t which, uint32_t r) {
+// List row r (final length len > kHub) for a weight-tree rebuild, once per
+// phase 4: one atomic claims its list slot and its chunks of kTreeChunk
+// entries, so first chunks grow with the slot.  The row's mark counts its
+// finished chunks in k_hub_tree.
+__device__ __forceinline__ void mark_dirty4(const P4& a, uint32_t which, uint32_t r,
+                                            uint32_t len) {
   if (atomicExch(&a.X.mark[r], 1u) == 0u) {
-    const uint32_t t = atomicAdd(&a.ctl->dirty[which], 1u);
-    a.dirty_rows[t] = r;
+    const uint32_t chunks = (len + kTreeChunk - 1) / kTreeChunk;
+    const unsigned long long claim =
+        atomicAdd(&a.ctl->tpack[which], (static_cast<unsigned long long>(chunks) << 32) | 1ull);
+    a.dirty_rows[static_cast<uint32_t>(claim)] = r;
+    a.dirty_chunk0[static_cast<uint32_t>(claim)] = static_cast<uint32_t>(claim >> 32);
   }
 }
 
@@ -2299,8 +2333,8 @@ __global__ void k_rows_plan(const BatchArgs* const* __restrict__ argv, uint32_t 
   }
   if (merged_from + k > kHub) {
     flags |= kWideMerge;
-    // the merge stages the k new entries past the pool top (not kept)
-    atomicAdd(&a.ctl->need[which], static_cast<unsigned long long>(k));
+    // the merge stages its new and old entries past the pool top (not kept)
+    atomicAdd(&a.ctl->need[which], static_cast<unsigned long long>(merged_from) + k);
   }
   a.touched_k[t] = k | flags;
   a.touched_need[t] = need;
@@ -2448,23 +2482,196 @@ __device__ __forceinline__ void rows_merge_narrow(const BatchArgs* const* __rest
     seg.put(i, e, we);
   }
   row_hdr_ref(X, r).len = row.len + k;
-  if (row.len + k > kHub) {  // its weight prefix is rebuilt next
-    mark_dirty4(a, which, r);
+  if (row.len + k > kHub) {  // its weight tree is rebuilt next
+    mark_dirty4(a, which, r, row.len + k);
     a.ctl->hubs = 1u;
   }
 }
 
-constexpr uint32_t kTailChunk = 4096;  // appended entries merged per pass (48 KB LDS)
+constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (12 KB LDS)
 
-// Merge for long segments: one workgroup per segment.  Each pass takes up to
-// kTailChunk appended entries, copies them past the pool top (slots the
-// phase-4 pool check reserved for this, given back at the end of the batch),
-// sorts their keys in LDS (bitonic), computes every entry's final position
-// (old entries shift right by the number of new entries below them; new
-// entries sit after the old entries below them), moves the old entries
-// right to left in block-sized chunks, so no entry is overwritten before it
-// is read, and finally writes the new entries from their staging copy.
+// Merges for long segments (the appended entries of a touched row into its
+// sorted prefix), in three forms by the number k of appended entries.
+// * k <= kWaveKeys (nearly every row): a wavefront sorts the keys across its
+//   lanes and stages the new entries; k_wide_copy_out and k_wide_place then
+//   move the row in units of kMergeChunk old entries, the units of all rows
+//   spread over the grid.
+// * k <= kTailChunk: the same, with the sort and staging by a workgroup.
+// * larger k (one workgroup per row, in place): each pass takes up to
+//   kTailChunk appended entries, copies them past the pool top, sorts their
+//   keys in LDS (bitonic), computes every entry's final position (old entries
+//   shift right by the number of new entries below them; new entries sit
+//   after the old entries below them), moves the old entries right to left
+//   in block-sized chunks, so no entry is overwritten before it is read, and
+//   finally writes the new entries from their staging copy.
+// Staging slots lie past the pool top, reserved by the phase-4 pool check and
+// given back at the end of the batch.
 constexpr uint32_t kMergePer = 8;  // old entries per thread and chunk of a wide merge
+
+// Bitonic sort of P (a power of two) keys in LDS by the whole block.
+__device__ __forceinline__ void block_sort_keys(unsigned long long* key, uint32_t P) {
+  for (uint32_t size = 2; size <= P; size <<= 1)
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+        const uint32_t l = i ^ stride;
+        if (l > i) {
+          const bool up = (i & size) == 0;
+          const unsigned long long x = key[i], y = key[l];
+          if ((x > y) == up) {
+            key[i] = y;
+            key[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// Whether a touched row's merge is spread over many workgroups: a wide merge
+// of at most kTailChunk appended entries (a longer tail takes the in-place
+// passes below).
+__device__ __forceinline__ bool parallel_merge(uint32_t packed) {
+  return (packed & kWideMerge) && (packed & kCountMask) <= kTailChunk;
+}
+
+// Parallel wide merges of at most kWaveKeys appended entries are prepared by
+// one wavefront (keys sorted across its lanes), the others by a workgroup.
+constexpr uint32_t kWaveKeys = kWave;
+__device__ __forceinline__ bool wave_merge(uint32_t packed) {
+  return (packed & kWideMerge) && (packed & kCountMask) <= kWaveKeys;
+}
+
+// Order of LDS writes and reads among the lanes of one wavefront.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Entries of the sorted segment seg[0, n) whose neighbour is below key, by one
+// wavefront: rounds of kWave evenly spaced probes narrow the range kWave
+// times per round (three rounds for the longest rows).
+__device__ uint32_t wave_lower_bound(const Pair* seg, uint32_t n, uint32_t key, uint32_t lane) {
+  uint32_t lo = 0, hi = n;  // the answer is in [lo, hi]
+  while (hi > lo) {
+    const uint32_t step = (hi - lo + kWave - 1) / kWave;
+    const uint32_t at = lo + lane * step;
+    const uint32_t below = static_cast<uint32_t>(__popcll(__ballot(at < hi && seg[at].nbr < key)));
+    if (below == 0) return lo;
+    const uint32_t nlo = lo + (below - 1) * step + 1;
+    if (step == 1) return nlo;
+    const uint32_t nhi = lo + below * step;
+    lo = nlo;
+    hi = nhi < hi ? nhi : hi;
+  }
+  return lo;
+}
+
+// First stage of a parallel wide merge of k <= kWaveKeys appended entries
+// [cur, cur + k), by one wavefront: a bitonic sort of (neighbour, index)
+// across the lanes, the first old entry that moves (stay), one atomic claim
+// of the merge's slot and chunks (chunk numbers grow with the slot), and the
+// sorted new entries staged past the pool top in slots the pool check
+// reserved.  The row itself is not written here.
+__device__ void wave_prepare(const P4& a, uint32_t which, uint32_t r, uint32_t k,
+                             uint32_t seg_off, uint32_t cur, unsigned long long top) {
+  const DevGraph& X = a.X;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const Pair* seg = X.ent + seg_off;
+  uint32_t key = lane < k ? seg[cur + lane].nbr : ~0u;  // ids are below ~0u
+  uint32_t idx = lane;
+  for (uint32_t size = 2; size <= kWave; size <<= 1)
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint32_t ok = __shfl_xor(key, stride, kWave);
+      const uint32_t oi = __shfl_xor(idx, stride, kWave);
+      const bool up = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      if (lower == up ? ok < key : ok > key) {
+        key = ok;
+        idx = oi;
+      }
+    }
+  const uint32_t stay = wave_lower_bound(seg, cur, __shfl(key, 0, kWave), lane);
+  const uint32_t moving = cur - stay;
+  uint32_t at = 0;
+  if (lane == 0) {
+    const uint32_t chunks = moving ? (moving + kMergeChunk - 1) / kMergeChunk : 1u;
+    at = static_cast<uint32_t>(
+        top + atomicAdd(&a.ctl->stage_used[which], static_cast<unsigned long long>(k + moving)));
+    const unsigned long long claim =
+        atomicAdd(&a.ctl->wpack[which], (static_cast<unsigned long long>(chunks) << 32) | 1ull);
+    a.wmerge[static_cast<uint32_t>(claim)] =
+        WideMerge{r, k, stay, cur, seg_off, at, static_cast<uint32_t>(claim >> 32), chunks};
+  }
+  at = __shfl(at, 0, kWave);
+  if (lane < k) {
+    const uint64_t src = static_cast<uint64_t>(seg_off) + cur + idx;
+    const uint64_t dst = static_cast<uint64_t>(at) + lane;
+    X.ent[dst] = X.ent[src];
+    X.prinv[dst] = X.prinv[src];
+    X.w[dst] = X.w[src];
+  }
+}
+
+// Entries of the sorted segment seg[0, n) whose neighbour is below key, by the
+// whole block: rounds of kBlock evenly spaced probes narrow the range kBlock
+// times per round (three rounds for the longest rows).
+__device__ uint32_t block_lower_bound(const Pair* seg, uint32_t n, uint32_t key) {
+  uint32_t lo = 0, hi = n;  // the answer is in [lo, hi]
+  while (hi > lo) {
+    const uint32_t step = (hi - lo + kBlock - 1) / kBlock;
+    const uint32_t at = lo + threadIdx.x * step;
+    const int below = __syncthreads_count(at < hi && seg[at].nbr < key);
+    if (below == 0) return lo;
+    const uint32_t nlo = lo + (below - 1) * step + 1;
+    const uint32_t nhi = lo + below * step;
+    if (step == 1) return nlo;
+    lo = nlo;
+    hi = nhi < hi ? nhi : hi;
+  }
+  return lo;
+}
+
+// First stage of a parallel wide merge of the k appended entries [cur, cur+k):
+// sort them by neighbour, find the first old entry that has to move (stay:
+// the old entries below the least new one), claim the merge's slot and its
+// chunks with one atomic (so chunk numbers grow with the slot), and stage the
+// sorted new entries past the pool top, in slots the pool check reserved.
+// k_wide_copy_out and k_wide_place finish the merge; the row itself is not
+// written here.  One workgroup.
+__device__ void wide_prepare(const P4& a, uint32_t which, uint32_t r, uint32_t k,
+                             uint32_t seg_off, uint32_t cur, unsigned long long top,
+                             unsigned long long* s_key, unsigned long long& s_stage) {
+  const DevGraph& X = a.X;
+  const Pair* seg = X.ent + seg_off;
+  uint32_t P = 1;
+  while (P < k) P <<= 1;
+  for (uint32_t j = threadIdx.x; j < P; j += kBlock)
+    s_key[j] = j < k ? (static_cast<unsigned long long>(seg[cur + j].nbr) << 32) | j : ~0ull;
+  __syncthreads();
+  block_sort_keys(s_key, P);
+  const uint32_t stay = block_lower_bound(seg, cur, static_cast<uint32_t>(s_key[0] >> 32));
+  if (threadIdx.x == 0) {
+    const uint32_t moving = cur - stay;
+    const uint32_t chunks = moving ? (moving + kMergeChunk - 1) / kMergeChunk : 1u;
+    const unsigned long long at = top + atomicAdd(&a.ctl->stage_used[which], k + moving);
+    const unsigned long long claim =
+        atomicAdd(&a.ctl->wpack[which], (static_cast<unsigned long long>(chunks) << 32) | 1ull);
+    a.wmerge[static_cast<uint32_t>(claim)] =
+        WideMerge{r, k, stay, cur, seg_off, static_cast<uint32_t>(at),
+                  static_cast<uint32_t>(claim >> 32), chunks};
+    s_stage = at;
+  }
+  __syncthreads();
+  const unsigned long long at = s_stage;
+  for (uint32_t j = threadIdx.x; j < k; j += kBlock) {
+    const uint32_t src = seg_off + cur + static_cast<uint32_t>(s_key[j] & 0xFFFFFFFFull);
+    X.ent[at + j] = X.ent[src];
+    X.prinv[at + j] = X.prinv[src];
+    X.w[at + j] = X.w[src];
+  }
+  __syncthreads();
+}
 
 __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restrict__ argv,
                                                 uint32_t which0, uint32_t bx, uint32_t nbx) {
@@ -2475,129 +2682,155 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
   __shared__ unsigned long long s_key[kTailChunk];  // (nbr << 32) | local index
   __shared__ uint32_t s_pos[kTailChunk];
   __shared__ unsigned long long s_stage;
+  __shared__ uint32_t s_list[kBlock];
+  __shared__ uint32_t s_n;
   const uint32_t count = a.ctl->wide[which];
   const unsigned long long top = a.ctl->pool_top[which];  // final: relocations are done
-  for (uint32_t wi = bx; wi < count; wi += nbx) {
+  // merges of few appended entries: a wavefront each
+  constexpr uint32_t kWaves = kBlock / kWave;
+  for (uint32_t wi = bx * kWaves + threadIdx.x / kWave; wi < count; wi += nbx * kWaves) {
     const uint32_t t = a.wide_rows[wi];
     const uint32_t packed = a.touched_k[t];
-    if (!(packed & kWideMerge)) continue;  // block-uniform
-    const uint32_t r = a.touched_rows[t];
-    const uint32_t k = packed & kCountMask;
-    const RowHdr row = row_hdr(X, r);  // relocated or long: a pool segment
-    Pair* seg = X.ent + row.off;
-    double* rseg = X.prinv + row.off;
-    double* wseg = X.w + row.off;
-    uint32_t cur = row.len;  // sorted prefix length
-    if (threadIdx.x == 0) s_stage = top + atomicAdd(&a.ctl->stage_used[which], k);
+    if (!wave_merge(packed)) continue;  // wavefront-uniform
+    const RowHdr row = row_hdr(X, a.touched_rows[t]);
+    wave_prepare(a, which, a.touched_rows[t], packed & kCountMask, row.off, row.len, top);
+  }
+  // the others: a workgroup each, listed kBlock rows at a time
+  for (uint32_t base = bx * kBlock; base < count; base += nbx * kBlock) {
+    if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    const unsigned long long stage = s_stage;  // k staging slots
-    for (uint32_t c0 = 0; c0 < k; c0 += kTailChunk) {
-      const uint32_t c = (k - c0) < kTailChunk ? (k - c0) : kTailChunk;
-      uint32_t P = 1;
-      while (P < c) P <<= 1;
-      for (uint32_t j = threadIdx.x; j < P; j += kBlock) {
-        if (j < c) {
-          const Pair e = seg[cur + j];
-          X.ent[stage + c0 + j] = e;
-          X.prinv[stage + c0 + j] = rseg[cur + j];
-          X.w[stage + c0 + j] = wseg[cur + j];
-          s_key[j] = (static_cast<unsigned long long>(e.nbr) << 32) | j;
-        } else {
-          s_key[j] = ~0ull;
-        }
+    if (base + threadIdx.x < count) {
+      const uint32_t packed = a.touched_k[a.wide_rows[base + threadIdx.x]];
+      if ((packed & kWideMerge) && !wave_merge(packed)) s_list[atomicAdd(&s_n, 1u)] = base + threadIdx.x;
+    }
+    __syncthreads();
+    const uint32_t listed = s_n;
+    for (uint32_t q = 0; q < listed; ++q) {
+      const uint32_t t = a.wide_rows[s_list[q]];
+      const uint32_t packed = a.touched_k[t];
+      const uint32_t r = a.touched_rows[t];
+      const uint32_t k = packed & kCountMask;
+      const RowHdr row = row_hdr(X, r);  // relocated or long: a pool segment
+      Pair* seg = X.ent + row.off;
+      double* rseg = X.prinv + row.off;
+      double* wseg = X.w + row.off;
+      uint32_t cur = row.len;  // sorted prefix length
+      if (parallel_merge(packed)) {
+        wide_prepare(a, which, r, k, row.off, cur, top, s_key, s_stage);
+        continue;
       }
+      if (threadIdx.x == 0) s_stage = top + atomicAdd(&a.ctl->stage_used[which], k);
       __syncthreads();
-      for (uint32_t size = 2; size <= P; size <<= 1)
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-          for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
-            const uint32_t l = i ^ stride;
-            if (l > i) {
-              const bool up = (i & size) == 0;
-              const unsigned long long x = s_key[i], y = s_key[l];
-              if ((x > y) == up) {
-                s_key[i] = y;
-                s_key[l] = x;
+      const unsigned long long stage = s_stage;  // k staging slots
+      for (uint32_t c0 = 0; c0 < k; c0 += kTailChunk) {
+        const uint32_t c = (k - c0) < kTailChunk ? (k - c0) : kTailChunk;
+        uint32_t P = 1;
+        while (P < c) P <<= 1;
+        for (uint32_t j = threadIdx.x; j < P; j += kBlock) {
+          if (j < c) {
+            const Pair e = seg[cur + j];
+            X.ent[stage + c0 + j] = e;
+            X.prinv[stage + c0 + j] = rseg[cur + j];
+            X.w[stage + c0 + j] = wseg[cur + j];
+            s_key[j] = (static_cast<unsigned long long>(e.nbr) << 32) | j;
+          } else {
+            s_key[j] = ~0ull;
+          }
+        }
+        __syncthreads();
+        for (uint32_t size = 2; size <= P; size <<= 1)
+          for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+              const uint32_t l = i ^ stride;
+              if (l > i) {
+                const bool up = (i & size) == 0;
+                const unsigned long long x = s_key[i], y = s_key[l];
+                if ((x > y) == up) {
+                  s_key[i] = y;
+                  s_key[l] = x;
+                }
               }
+            }
+            __syncthreads();
+          }
+        // final slot of each new entry: its rank plus the old entries below it
+        for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
+          const uint32_t key = static_cast<uint32_t>(s_key[j] >> 32);
+          uint32_t lo = 0, hi = cur;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (seg[mid].nbr < key) lo = mid + 1;
+            else hi = mid;
+          }
+          s_pos[j] = j + lo;
+        }
+        __syncthreads();
+        // Old entries move right by the number of new entries below them, in
+        // chunks from the right end (every thread reads its kMergePer entries
+        // before any writes); entries below the first new one stay put.
+        const uint32_t stay = s_pos[0];  // new entry of least id lands here
+        for (uint32_t hi_i = cur; hi_i > stay;) {
+          const uint32_t span = kBlock * kMergePer;
+          const uint32_t lo_i = hi_i - stay > span ? hi_i - span : stay;
+          // fields in separate arrays (registers; an array of structs written
+          // under a condition would go to scratch)
+          uint32_t en[kMergePer], eq[kMergePer], shift[kMergePer];
+          double er[kMergePer], we[kMergePer];
+  #pragma unroll
+          for (uint32_t m = 0; m < kMergePer; ++m) {
+            const uint32_t i = lo_i + m * kBlock + threadIdx.x;
+            const uint32_t ii = i < hi_i ? i : lo_i;  // in range either way
+            const Pair x = seg[ii];
+            en[m] = x.nbr;
+            eq[m] = x.qw;
+            er[m] = rseg[ii];
+            we[m] = wseg[ii];
+            shift[m] = 0;
+          }
+  #pragma unroll
+          for (uint32_t m = 0; m < kMergePer; ++m) {
+            const uint32_t i = lo_i + m * kBlock + threadIdx.x;
+            // new entries below e.nbr: a fixed-length search over the P sorted
+            // keys (padding keys are ~0), so that the arrays stay in registers
+            uint32_t below = 0;
+  #pragma unroll
+            for (uint32_t w = kTailChunk; w >= 1; w >>= 1)  // counts up to P = kTailChunk
+              if (below + w <= P && static_cast<uint32_t>(s_key[below + w - 1] >> 32) < en[m])
+                below += w;
+            if (i < hi_i) shift[m] = below;
+          }
+          __syncthreads();
+  #pragma unroll
+          for (uint32_t m = 0; m < kMergePer; ++m) {
+            const uint32_t i = lo_i + m * kBlock + threadIdx.x;
+            if (i < hi_i && shift[m]) {
+              seg[i + shift[m]] = Pair{en[m], eq[m]};
+              rseg[i + shift[m]] = er[m];
+              wseg[i + shift[m]] = we[m];
             }
           }
           __syncthreads();
+          hi_i = lo_i;
         }
-      // final slot of each new entry: its rank plus the old entries below it
-      for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
-        const uint32_t key = static_cast<uint32_t>(s_key[j] >> 32);
-        uint32_t lo = 0, hi = cur;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (seg[mid].nbr < key) lo = mid + 1;
-          else hi = mid;
-        }
-        s_pos[j] = j + lo;
-      }
-      __syncthreads();
-      // Old entries move right by the number of new entries below them, in
-      // chunks from the right end (every thread reads its kMergePer entries
-      // before any writes); entries below the first new one stay put.
-      const uint32_t stay = s_pos[0];  // new entry of least id lands here
-      for (uint32_t hi_i = cur; hi_i > stay;) {
-        const uint32_t span = kBlock * kMergePer;
-        const uint32_t lo_i = hi_i - stay > span ? hi_i - span : stay;
-        // fields in separate arrays (registers; an array of structs written
-        // under a condition would go to scratch)
-        uint32_t en[kMergePer], eq[kMergePer], shift[kMergePer];
-        double er[kMergePer], we[kMergePer];
-#pragma unroll
-        for (uint32_t m = 0; m < kMergePer; ++m) {
-          const uint32_t i = lo_i + m * kBlock + threadIdx.x;
-          const uint32_t ii = i < hi_i ? i : lo_i;  // in range either way
-          const Pair x = seg[ii];
-          en[m] = x.nbr;
-          eq[m] = x.qw;
-          er[m] = rseg[ii];
-          we[m] = wseg[ii];
-          shift[m] = 0;
-        }
-#pragma unroll
-        for (uint32_t m = 0; m < kMergePer; ++m) {
-          const uint32_t i = lo_i + m * kBlock + threadIdx.x;
-          // new entries below e.nbr: a fixed-length search over the P sorted
-          // keys (padding keys are ~0), so that the arrays stay in registers
-          uint32_t below = 0;
-#pragma unroll
-          for (uint32_t w = kTailChunk; w >= 1; w >>= 1)  // counts up to P = kTailChunk
-            if (below + w <= P && static_cast<uint32_t>(s_key[below + w - 1] >> 32) < en[m])
-              below += w;
-          if (i < hi_i) shift[m] = below;
+        for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
+          const uint64_t src = stage + c0 + static_cast<uint32_t>(s_key[j] & 0xFFFFFFFFull);
+          seg[s_pos[j]] = X.ent[src];
+          rseg[s_pos[j]] = X.prinv[src];
+          wseg[s_pos[j]] = X.w[src];
         }
         __syncthreads();
-#pragma unroll
-        for (uint32_t m = 0; m < kMergePer; ++m) {
-          const uint32_t i = lo_i + m * kBlock + threadIdx.x;
-          if (i < hi_i && shift[m]) {
-            seg[i + shift[m]] = Pair{en[m], eq[m]};
-            rseg[i + shift[m]] = er[m];
-            wseg[i + shift[m]] = we[m];
-          }
-        }
-        __syncthreads();
-        hi_i = lo_i;
+        cur += c;
       }
-      for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
-        const uint64_t src = stage + c0 + static_cast<uint32_t>(s_key[j] & 0xFFFFFFFFull);
-        seg[s_pos[j]] = X.ent[src];
-        rseg[s_pos[j]] = X.prinv[src];
-        wseg[s_pos[j]] = X.w[src];
+      if (threadIdx.x == 0) {
+        row_hdr_ref(X, r).len = cur;
+        if (cur > kHub) {
+          mark_dirty4(a, which, r, cur);
+          a.ctl->hubs = 1u;
+        }
       }
       __syncthreads();
-      cur += c;
     }
-    if (threadIdx.x == 0) {
-      row_hdr_ref(X, r).len = cur;
-      if (cur > kHub) {
-        mark_dirty4(a, which, r);
-        a.ctl->hubs = 1u;
-      }
-    }
-    __syncthreads();
+    __syncthreads();  // s_n is reset after every read
   }
 }
 
@@ -2608,6 +2841,166 @@ __global__ __launch_bounds__(kBlock) void k_rows_merge(const BatchArgs* const* _
                                                        uint32_t which0, uint32_t narrow_blocks) {
   if (blockIdx.x < narrow_blocks) rows_merge_narrow(argv, which0, blockIdx.x);
   else rows_merge_wide(argv, which0, blockIdx.x - narrow_blocks, gridDim.x - narrow_blocks);
+}
+
+// The parallel wide merge that chunk c belongs to, by one wavefront: the
+// last merge whose first chunk is at or below c (first chunks grow with the
+// merge's slot, and merge 0 starts at chunk 0).
+__device__ uint32_t wave_merge_of_chunk(const WideMerge* wm, uint32_t merges, uint32_t c,
+                                        uint32_t lane) {
+  uint32_t lo = 0, hi = merges;  // merges starting at or below c: in [lo, hi]
+  while (hi > lo) {
+    const uint32_t step = (hi - lo + kWave - 1) / kWave;
+    const uint32_t at = lo + lane * step;
+    const uint32_t below = static_cast<uint32_t>(__popcll(__ballot(at < hi && wm[at].chunk0 <= c)));
+    if (below == 0) return lo - 1;
+    const uint32_t nlo = lo + (below - 1) * step + 1;
+    if (step == 1) return nlo - 1;
+    const uint32_t nhi = lo + below * step;
+    lo = nlo;
+    hi = nhi < hi ? nhi : hi;
+  }
+  return lo - 1;
+}
+
+// The chunks [begin, end) of a graph's parallel wide merges that wavefront
+// gw of nw takes: a contiguous share, so that one search finds its first
+// merge and the rest follow in order.
+struct ChunkShare {
+  uint32_t begin, end;
+};
+__device__ __forceinline__ ChunkShare chunk_share(uint32_t chunks) {
+  const uint32_t nw = gridDim.x * (kBlock / kWave);
+  const uint32_t gw = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const uint32_t per = (chunks + nw - 1) / nw;
+  const uint64_t b = static_cast<uint64_t>(gw) * per;
+  const uint64_t e = b + per < chunks ? b + per : chunks;
+  return b < e ? ChunkShare{static_cast<uint32_t>(b), static_cast<uint32_t>(e)} : ChunkShare{0u, 0u};
+}
+
+// Second stage of the parallel wide merges: copy the moving old entries
+// [stay, cur) of every merge to their staging slots (after its k new
+// entries), kMergeChunk entries per wavefront unit.
+__global__ __launch_bounds__(kBlock) void k_wide_copy_out(const BatchArgs* const* __restrict__ argv,
+                                                          uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
+  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
+  const unsigned long long pack = a.ctl->wpack[which];
+  const ChunkShare sh = chunk_share(static_cast<uint32_t>(pack >> 32));
+  if (sh.begin == sh.end) return;  // wavefront-uniform; no workgroup barriers here
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  uint32_t p = wave_merge_of_chunk(a.wmerge, static_cast<uint32_t>(pack), sh.begin, lane);
+  WideMerge m = a.wmerge[p];
+  for (uint32_t c = sh.begin; c < sh.end; ++c) {
+    while (c >= m.chunk0 + m.chunks) m = a.wmerge[++p];
+    const uint32_t base = (c - m.chunk0) * kMergeChunk;
+    const uint32_t moving = m.cur - m.stay;
+    const uint32_t end = moving - base < kMergeChunk ? moving : base + kMergeChunk;
+    const uint64_t src = static_cast<uint64_t>(m.seg_off) + m.stay;
+    const uint64_t dst = static_cast<uint64_t>(m.new_off) + m.k;
+    for (uint32_t i = base + lane; i < end; i += kWave) {
+      X.ent[dst + i] = X.ent[src + i];
+      X.prinv[dst + i] = X.prinv[src + i];
+      X.w[dst + i] = X.w[src + i];
+    }
+  }
+}
+
+// New keys (sorted, in LDS) below a neighbour.
+__device__ __forceinline__ uint32_t keys_below(const uint32_t* key, uint32_t k, uint32_t nbr) {
+  uint32_t lo = 0, hi = k;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (key[mid] < nbr) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Last stage: write every staged entry to its merged slot, kMergeChunk old
+// entries per wavefront unit.  The moving old entry i (i-th after stay) moves
+// right by s_i, the new keys below it; the new entries j with
+// s_{i-1} <= j < s_i (between old entries i-1 and i) land at stay + i + j and
+// are written by the lane of old entry i, those above every old entry by the
+// lane of the last one.  The slots are disjoint and fill [stay, cur + k);
+// only staged copies are read, so the units of a row need no order.
+__global__ __launch_bounds__(kBlock) void k_wide_place(const BatchArgs* const* __restrict__ argv,
+                                                       uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const P4 a = load_p4(argv, blockIdx.y, which);
+  const DevGraph& X = a.X;
+  if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
+  __shared__ uint32_t s_new[kBlock / kWave][kTailChunk];  // a wavefront's merge's new keys
+  const unsigned long long pack = a.ctl->wpack[which];
+  const ChunkShare sh = chunk_share(static_cast<uint32_t>(pack >> 32));
+  if (sh.begin == sh.end) return;  // wavefront-uniform; no workgroup barriers here
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  uint32_t* keys = s_new[threadIdx.x / kWave];
+  uint32_t p = wave_merge_of_chunk(a.wmerge, static_cast<uint32_t>(pack), sh.begin, lane);
+  WideMerge m = a.wmerge[p];
+  bool fresh = true;
+  for (uint32_t c = sh.begin; c < sh.end; ++c) {
+    while (c >= m.chunk0 + m.chunks) {
+      m = a.wmerge[++p];
+      fresh = true;
+    }
+    const uint64_t nw = m.new_off, od = static_cast<uint64_t>(m.new_off) + m.k;
+    if (fresh) {
+      wave_lds_sync();  // the previous merge's keys are no longer read
+      for (uint32_t j = lane; j < m.k; j += kWave) keys[j] = X.ent[nw + j].nbr;
+      wave_lds_sync();
+      fresh = false;
+    }
+    const uint32_t base = (c - m.chunk0) * kMergeChunk;
+    const uint32_t moving = m.cur - m.stay;
+    const uint32_t end = moving - base < kMergeChunk ? moving : base + kMergeChunk;
+    const uint64_t to0 = static_cast<uint64_t>(m.seg_off) + m.stay;  // slot of merged index 0
+    if (moving == 0) {  // every new entry lands above the old ones
+      for (uint32_t j = lane; j < m.k; j += kWave) {
+        X.ent[to0 + j] = X.ent[nw + j];
+        X.prinv[to0 + j] = X.prinv[nw + j];
+        X.w[to0 + j] = X.w[nw + j];
+      }
+    }
+    uint32_t last = 0;  // the lane's s_i of the previous pass
+    for (uint32_t i0 = base; i0 < end; i0 += kWave) {  // wavefront-uniform
+      const uint32_t i = i0 + lane;
+      const bool valid = i < end;
+      uint32_t below = 0;
+      if (valid) {
+        const Pair e = X.ent[od + i];
+        below = keys_below(keys, m.k, e.nbr);
+        X.ent[to0 + i + below] = e;
+        X.prinv[to0 + i + below] = X.prinv[od + i];
+        X.w[to0 + i + below] = X.w[od + i];
+      }
+      const uint32_t left = __shfl_up(below, 1, kWave);    // s_{i-1} within the pass
+      const uint32_t carry = __shfl(last, kWave - 1, kWave);  // s_{i-1} for lane 0
+      if (valid) {
+        uint32_t from;
+        if (lane > 0) from = left;
+        else if (i0 > base) from = carry;
+        else from = i > 0 ? keys_below(keys, m.k, X.ent[od + i - 1].nbr) : 0u;
+        const uint32_t upto = i + 1 == moving ? m.k : below;
+        for (uint32_t j = from; j < upto; ++j) {
+          const uint64_t to = to0 + i + j + (j >= below ? 1u : 0u);
+          X.ent[to] = X.ent[nw + j];
+          X.prinv[to] = X.prinv[nw + j];
+          X.w[to] = X.w[nw + j];
+        }
+      }
+      last = below;
+    }
+    if (base == 0 && lane == 0) {
+      row_hdr_ref(X, m.r).len = m.cur + m.k;
+      if (m.cur + m.k > kHub) {
+        mark_dirty4(a, which, m.r, m.cur + m.k);
+        a.ctl->hubs = 1u;
+      }
+    }
+  }
 }
 
 // After a pool shortfall: undo the per-row counters so phase 4 can run again
@@ -2636,14 +3029,16 @@ __global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv, ui
   if (threadIdx.x == 0) {
     ctl->touched[which] = 0;
     ctl->stage_used[which] = 0;
+    ctl->wpack[which] = 0;
     ctl->need[which] = 0;
     ctl->nomem[which] = 0;
     ctl->wide[which] = 0;
-    ctl->dirty[which] = 0;  // (rows listed by a finished phase 4 have their trees)
+    ctl->tpack[which] = 0;  // (rows listed by a finished phase 4 have their trees)
   }
 }
 
 constexpr uint32_t kWideBlocks = 512;  // workgroups of the per-long-segment kernels
+constexpr uint32_t kMergeBlocks = 2048;  // workgroups of the wide merges (latency-bound)
 constexpr uint32_t kHubBlocks = 2048;  // workgroups of the prefix rebuild (memory-bound)
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per = kBlock) {
@@ -2769,7 +3164,10 @@ void phase4_sequence(const Launch& L, uint32_t which0, uint32_t nw, hipStream_t 
   const dim3 both(g.x + kWideBlocks, L.F, nw);  // short rows, then long rows
   k_rows_relocate<<<both, kBlock, 0, st>>>(L.argv, which0, g.x);
   k_add_place<<<g, kBlock, 0, st>>>(L.argv, which0, L.h_lo, L.h_hi);
-  k_rows_merge<<<both, kBlock, 0, st>>>(L.argv, which0, g.x);
+  k_rows_merge<<<dim3(g.x + kMergeBlocks, L.F, nw), kBlock, 0, st>>>(L.argv, which0, g.x);
+  const dim3 wide(kMergeBlocks, L.F, nw);
+  k_wide_copy_out<<<wide, kBlock, 0, st>>>(L.argv, which0);
+  k_wide_place<<<wide, kBlock, 0, st>>>(L.argv, which0);
   launch_hub_tree(L, which0, nw, st);
 }
 
