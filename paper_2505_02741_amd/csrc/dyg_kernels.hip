@@ -489,16 +489,35 @@ __global__ void k_phase1(const BatchArgs* const* __restrict__ argv) {
   a.in_h[j] = in_h ? 1 : 0;
 }
 
+// Entries of the sorted array v[0, n) at or below x, by the whole block:
+// rounds of kBlock evenly spaced probes (__syncthreads_count) narrow the
+// range kBlock times per round.
+__device__ uint32_t block_count_le(const uint32_t* v, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, hi = n;  // the answer is in [lo, hi]
+  while (hi > lo) {
+    const uint32_t step = (hi - lo + kBlock - 1) / kBlock;
+    const uint32_t at = lo + threadIdx.x * step;
+    const int below = __syncthreads_count(at < hi && v[at] <= x);
+    if (below == 0) return lo;
+    const uint32_t nlo = lo + (below - 1) * step + 1;
+    if (step == 1) return nlo;
+    const uint32_t nhi = lo + below * step;
+    lo = nlo;
+    hi = nhi < hi ? nhi : hi;
+  }
+  return lo;
+}
+
 // Rebuild the weight tree (level 0 in pfx, levels 1.. in tree) of every long
 // segment listed dirty by phase 4 (merged or relocated), a chunk of
-// kTreeChunk = 16^3 entries per workgroup iteration, the chunks of all rows
-// in one grid-stride loop.  A chunk fills levels 0-2 of its part of the tree
-// on its own: the weights are staged in LDS with coalesced reads, each thread
-// sums one block of 16 entries, and the level-0 values go back through LDS
-// for coalesced writes.  A row longer than one chunk gets its chunk totals
-// on level 3; the workgroup that finishes its last chunk (the row's mark
-// counts finished chunks) sums levels 3.. from them.  The graph is
-// which0 + blockIdx.z.
+// kTreeChunk = 16^3 entries per workgroup iteration; each workgroup takes a
+// contiguous share of the chunks of all rows.  A chunk fills levels 0-2 of
+// its part of the tree on its own: the weights are staged in LDS with
+// coalesced reads, each thread sums one block of 16 entries, and the level-0
+// values go back through LDS for coalesced writes.  A row longer than one
+// chunk gets its chunk totals on level 3; the workgroup that finishes its
+// last chunk (the row's mark counts finished chunks) sums levels 3.. from
+// them.  The graph is which0 + blockIdx.z.
 constexpr uint32_t kTreeChunk = kBlock * kFan;  // 4096 entries: one level-2 block
 static_assert(kTreeChunk == kFan * kFan * kFan, "a chunk is one level-2 block");
 
@@ -521,16 +540,23 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
   __shared__ unsigned long long s_t[kBlock];               // block totals
   __shared__ uint32_t s_last;
   const uint32_t t = threadIdx.x;
-  for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-    uint32_t lo = 0, hi = rows;  // first row whose chunks start above u
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (chunk0[mid] <= u) lo = mid + 1;
-      else hi = mid;
+  // a contiguous share of the units: one search finds the first unit's row,
+  // the others follow in order (a row's chunks are consecutive units)
+  const uint32_t per = (units + gridDim.x - 1) / gridDim.x;
+  const uint32_t u0 = blockIdx.x * per < units ? blockIdx.x * per : units;
+  const uint32_t u1 = u0 + per < units ? u0 + per : units;
+  if (u0 == u1) return;  // block-uniform
+  uint32_t p = block_count_le(chunk0, rows, u0) - 1;
+  uint32_t r = dirty_rows[p];
+  RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment, aligned
+  uint32_t first = chunk0[p];
+  for (uint32_t u = u0; u < u1; ++u) {
+    if (u >= first + (row.len + kTreeChunk - 1) / kTreeChunk) {
+      first += (row.len + kTreeChunk - 1) / kTreeChunk;
+      r = dirty_rows[++p];
+      row = row_hdr(X, r);
     }
-    const uint32_t r = dirty_rows[lo - 1];
-    const uint32_t ch = u - chunk0[lo - 1];
-    const RowHdr row = row_hdr(X, r);  // len > kHub: a pool segment, aligned
+    const uint32_t ch = u - first;
     const uint32_t len = row.len;
     const uint32_t K = tree_top(len);
     const uint32_t n1 = tree_n(len, 1), n2 = tree_n(len, 2);
@@ -1295,6 +1321,7 @@ __device__ __forceinline__ void no_walk_update(const BatchArgs& a, const UpdateV
 // Rows longer than kWideFallback are left to k_fallback_wide (a workgroup).
 constexpr uint32_t kWideFallback = 1024;
 constexpr uint32_t kFallbackUnroll = 8;  // G entries loaded together
+constexpr uint32_t kFallbackLds = 12288;  // H-row entries k_fallback_wide stages in LDS
 
 __device__ __forceinline__ void fallback_slice(const DevGraph& G, const DevGraph& H, uint32_t end,
                                                uint32_t part, uint32_t parts, double& br,
@@ -2063,9 +2090,12 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
 }
 
 // No-hit fallbacks of deletions at long G rows (listed by decide_update):
-// one workgroup per deletion, its kBlock threads scanning slices of each
-// endpoint's G row, then the workgroup's minimum of (1/w, neighbour).  Writes
-// the deletion's fallback slots and n_rec (the rest of its result is final).
+// one workgroup per deletion.  Per endpoint, its H row (up to kFallbackLds
+// entries) is staged in LDS, the G row is read coalesced, each live G entry
+// looked up in the staged H row by binary search, then the workgroup's
+// minimum of (1/w, neighbour) over the entries not live in H; a longer H row
+// takes the merged slices of fallback_slice instead.  Writes the deletion's
+// fallback slots and n_rec (the rest of its result is final).
 __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
   if (batch_failed(a.ctl)) return;
@@ -2075,6 +2105,8 @@ __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const
   __shared__ double s_r[kBlock / kWave];
   __shared__ uint32_t s_n[kBlock / kWave];
   __shared__ uint32_t s_count;
+  __shared__ uint32_t s_hn[kFallbackLds];         // the endpoint's H row: neighbours
+  __shared__ uint32_t s_hlive[kFallbackLds / 32];  // and which of them are live
   const uint32_t t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
   for (uint32_t f = blockIdx.x; f < count; f += gridDim.x) {
     const uint32_t upd = a.fb_list[f];
@@ -2085,9 +2117,54 @@ __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const
     __syncthreads();
     for (int z = 0; z < 2; ++z) {
       const uint32_t end = z == 0 ? p : q;
-      double br;
-      uint32_t bn, bi;
-      fallback_slice(G, H, end, t, kBlock, br, bn, bi);
+      double br = INFINITY;
+      uint32_t bn = kNone, bi = 0;
+      const RowHdr hr = row_hdr(H, end);
+      if (hr.len <= kFallbackLds) {
+        // H row in LDS; G row read coalesced, membership by binary search
+        const Seg hseg = seg_of(H, end, hr.off);
+        for (uint32_t i = t; i < (hr.len + 31) / 32; i += kBlock) s_hlive[i] = 0u;
+        __syncthreads();
+        for (uint32_t i = t; i < hr.len; i += kBlock) {
+          s_hn[i] = hseg.nbr(i);
+          if (hseg.qw(i) != 0u) atomicOr(&s_hlive[i >> 5], 1u << (i & 31));
+        }
+        __syncthreads();
+        const RowHdr gr = row_hdr(G, end);
+        const Seg seg = seg_of(G, end, gr.off);
+        for (uint32_t i0 = 0; i0 < gr.len; i0 += kBlock * kFallbackUnroll) {
+          uint32_t en[kFallbackUnroll], eq[kFallbackUnroll];
+          double er[kFallbackUnroll];
+#pragma unroll
+          for (uint32_t m = 0; m < kFallbackUnroll; ++m) {  // loads issued together
+            const uint32_t i = i0 + m * kBlock + t;
+            const uint32_t ii = i < gr.len ? i : gr.len - 1;
+            en[m] = seg.nbr(ii);
+            eq[m] = seg.qw(ii);
+            er[m] = seg.r(ii);
+          }
+#pragma unroll
+          for (uint32_t m = 0; m < kFallbackUnroll; ++m) {
+            const uint32_t i = i0 + m * kBlock + t;
+            if (i >= gr.len || eq[m] == 0u) continue;
+            uint32_t lo = 0, hi = hr.len;
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (s_hn[mid] < en[m]) lo = mid + 1;
+              else hi = mid;
+            }
+            if (lo < hr.len && s_hn[lo] == en[m] && ((s_hlive[lo >> 5] >> (lo & 31)) & 1u))
+              continue;  // live in H
+            if (er[m] < br || (er[m] == br && en[m] < bn)) {
+              br = er[m];
+              bn = en[m];
+              bi = i;
+            }
+          }
+        }
+      } else {
+        fallback_slice(G, H, end, t, kBlock, br, bn, bi);
+      }
       double wr = br;
       uint32_t wn = bn;
       wave_argmin(wr, wn);
@@ -2210,6 +2287,39 @@ __device__ __forceinline__ void mark_dirty4(const P4& a, uint32_t which, uint32_
     a.dirty_rows[static_cast<uint32_t>(claim)] = r;
     a.dirty_chunk0[static_cast<uint32_t>(claim)] = static_cast<uint32_t>(claim >> 32);
   }
+}
+
+// A claim on a shared 64-bit counter by a whole wavefront with one atomic:
+// every lane calls it with its amount (0 for none) and gets the counter's
+// value plus the amounts of the lanes below it.
+__device__ unsigned long long wave_claim(unsigned long long* ctr, unsigned long long v) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  unsigned long long incl = v;
+  for (uint32_t d = 1; d < kWave; d <<= 1) {
+    const unsigned long long o = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += o;
+  }
+  const unsigned long long total = __shfl(incl, kWave - 1, kWave);
+  unsigned long long base = 0;
+  if (lane == kWave - 1 && total != 0) base = atomicAdd(ctr, total);
+  base = __shfl(base, kWave - 1, kWave);
+  return base + incl - v;
+}
+
+// mark_dirty4 for the rows of a whole wavefront (every lane calls it; `want`
+// says whether its row r, of final length len, is listed), with one claim
+// per wavefront; also raises the hub flag.
+__device__ void mark_dirty_wave(const P4& a, uint32_t which, bool want, uint32_t r,
+                                uint32_t len) {
+  const bool fresh = want && atomicExch(&a.X.mark[r], 1u) == 0u;
+  const unsigned long long chunks = (len + kTreeChunk - 1) / kTreeChunk;
+  const unsigned long long slot =
+      wave_claim(&a.ctl->tpack[which], fresh ? (chunks << 32) | 1ull : 0ull);
+  if (fresh) {
+    a.dirty_rows[static_cast<uint32_t>(slot)] = r;
+    a.dirty_chunk0[static_cast<uint32_t>(slot)] = static_cast<uint32_t>(slot >> 32);
+  }
+  if (__ballot(want) != 0 && (threadIdx.x & (kWave - 1)) == 0) a.ctl->hubs = 1u;
 }
 
 struct AddEntry {
@@ -2464,28 +2574,29 @@ __device__ __forceinline__ void rows_merge_narrow(const BatchArgs* const* __rest
   const DevGraph& X = a.X;
   if (batch_failed(a.ctl) || a.ctl->nomem[which]) return;
   const uint32_t t = bx * blockDim.x + threadIdx.x;
-  if (t >= a.ctl->touched[which]) return;
-  const uint32_t packed = a.touched_k[t];
-  if (packed & kWideMerge) return;  // merged by rows_merge_wide
-  const uint32_t r = a.touched_rows[t];
-  const uint32_t k = packed & kCountMask;
-  const RowHdr row = row_hdr(X, r);
-  const Seg seg = seg_of(X, r, row.off);
-  for (uint32_t j = row.len; j < row.len + k; ++j) {
-    const Ent e = seg.get(j);
-    const double we = seg.w[j];
-    uint32_t i = j;
-    while (i > 0 && seg.nbr(i - 1) > e.nbr) {
-      seg.put(i, seg.get(i - 1), seg.w[i - 1]);
-      --i;
+  uint32_t packed = kWideMerge;  // rows merged by rows_merge_wide are skipped
+  if (t < a.ctl->touched[which]) packed = a.touched_k[t];
+  const bool mine = !(packed & kWideMerge);
+  uint32_t r = 0, len = 0;
+  if (mine) {
+    r = a.touched_rows[t];
+    const uint32_t k = packed & kCountMask;
+    const RowHdr row = row_hdr(X, r);
+    const Seg seg = seg_of(X, r, row.off);
+    for (uint32_t j = row.len; j < row.len + k; ++j) {
+      const Ent e = seg.get(j);
+      const double we = seg.w[j];
+      uint32_t i = j;
+      while (i > 0 && seg.nbr(i - 1) > e.nbr) {
+        seg.put(i, seg.get(i - 1), seg.w[i - 1]);
+        --i;
+      }
+      seg.put(i, e, we);
     }
-    seg.put(i, e, we);
+    len = row.len + k;
+    row_hdr_ref(X, r).len = len;
   }
-  row_hdr_ref(X, r).len = row.len + k;
-  if (row.len + k > kHub) {  // its weight tree is rebuilt next
-    mark_dirty4(a, which, r, row.len + k);
-    a.ctl->hubs = 1u;
-  }
+  mark_dirty_wave(a, which, mine && len > kHub, r, len);  // weight tree rebuilt next
 }
 
 constexpr uint32_t kTailChunk = 1024;  // appended entries merged per pass (12 KB LDS)
@@ -2548,68 +2659,90 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Entries of the sorted segment seg[0, n) whose neighbour is below key, by one
-// wavefront: rounds of kWave evenly spaced probes narrow the range kWave
-// times per round (three rounds for the longest rows).
-__device__ uint32_t wave_lower_bound(const Pair* seg, uint32_t n, uint32_t key, uint32_t lane) {
-  uint32_t lo = 0, hi = n;  // the answer is in [lo, hi]
-  while (hi > lo) {
-    const uint32_t step = (hi - lo + kWave - 1) / kWave;
-    const uint32_t at = lo + lane * step;
-    const uint32_t below = static_cast<uint32_t>(__popcll(__ballot(at < hi && seg[at].nbr < key)));
-    if (below == 0) return lo;
-    const uint32_t nlo = lo + (below - 1) * step + 1;
-    if (step == 1) return nlo;
-    const uint32_t nhi = lo + below * step;
-    lo = nlo;
-    hi = nhi < hi ? nhi : hi;
-  }
-  return lo;
-}
-
-// First stage of a parallel wide merge of k <= kWaveKeys appended entries
-// [cur, cur + k), by one wavefront: a bitonic sort of (neighbour, index)
-// across the lanes, the first old entry that moves (stay), one atomic claim
-// of the merge's slot and chunks (chunk numbers grow with the slot), and the
-// sorted new entries staged past the pool top in slots the pool check
-// reserved.  The row itself is not written here.
-__device__ void wave_prepare(const P4& a, uint32_t which, uint32_t r, uint32_t k,
-                             uint32_t seg_off, uint32_t cur, unsigned long long top) {
+// First stage of the parallel wide merges of at most kWaveKeys appended
+// entries (cur .. cur+k-1 of their rows), up to kWave of them by one
+// wavefront, lane j holding merge j: its least new key, the first old entry
+// that moves (stay, a binary search per lane), the row's final length and
+// its listing for the weight-tree rebuild, then the staging slots and the
+// merge's slot and chunks claimed with one atomic each for the wavefront
+// (chunk numbers grow with the slot).  Then the new entries of each merge
+// are sorted by neighbour (bitonic across a segment of lanes, several merges
+// side by side) and staged past the pool top, in slots the pool check
+// reserved.
+__device__ void wave_prepare_group(const P4& a, uint32_t which, bool mine, uint32_t t,
+                                   unsigned long long top) {
   const DevGraph& X = a.X;
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const Pair* seg = X.ent + seg_off;
-  uint32_t key = lane < k ? seg[cur + lane].nbr : ~0u;  // ids are below ~0u
-  uint32_t idx = lane;
-  for (uint32_t size = 2; size <= kWave; size <<= 1)
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      const uint32_t ok = __shfl_xor(key, stride, kWave);
-      const uint32_t oi = __shfl_xor(idx, stride, kWave);
-      const bool up = (lane & size) == 0;
-      const bool lower = (lane & stride) == 0;
-      if (lower == up ? ok < key : ok > key) {
-        key = ok;
-        idx = oi;
+  uint32_t r = 0, k = 0, off = 0, cur = 0, stay = 0;
+  if (mine) {
+    r = a.touched_rows[t];
+    k = a.touched_k[t] & kCountMask;
+    const RowHdr row = row_hdr(X, r);  // relocated or long: a pool segment
+    off = row.off;
+    cur = row.len;
+    const Pair* seg = X.ent + off;
+    uint32_t least = ~0u;
+    for (uint32_t i = 0; i < k; ++i) least = min(least, seg[cur + i].nbr);
+    uint32_t lo = 0, hi = cur;  // old entries below the least new one
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (seg[mid].nbr < least) lo = mid + 1;
+      else hi = mid;
+    }
+    stay = lo;
+    row_hdr_ref(X, r).len = cur + k;  // the moves below read no header
+  }
+  mark_dirty_wave(a, which, mine, r, cur + k);  // cur + k > kHub for every wide merge
+  const uint32_t moving = cur - stay;
+  const unsigned long long chunks = moving ? (moving + kMergeChunk - 1) / kMergeChunk : 1u;
+  const uint32_t at = static_cast<uint32_t>(
+      top + wave_claim(&a.ctl->stage_used[which], mine ? k + moving : 0u));
+  const unsigned long long claim =
+      wave_claim(&a.ctl->wpack[which], mine ? (chunks << 32) | 1ull : 0ull);
+  if (mine)
+    a.wmerge[static_cast<uint32_t>(claim)] =
+        WideMerge{r, k, stay, cur, off, at, static_cast<uint32_t>(claim >> 32),
+                  static_cast<uint32_t>(chunks)};
+  // the merges of each size class S (S/2 < k <= S), kWave / S at a time:
+  // merge q of a pass sorts and stages on lanes qS .. qS + S - 1
+  __shared__ uint32_t s_rows[kBlock];  // a wavefront's members of one class
+  uint32_t* rows_of = s_rows + (threadIdx.x / kWave) * kWave;
+  for (uint32_t S = 1; S <= kWave; S <<= 1) {
+    const bool in_class = mine && k <= S && 2 * k > S;
+    const unsigned long long cls = __ballot(in_class);
+    if (cls == 0) continue;  // wavefront-uniform
+    const uint32_t n = static_cast<uint32_t>(__popcll(cls));
+    if (in_class) rows_of[__popcll(cls & ((1ull << lane) - 1ull))] = lane;
+    wave_lds_sync();
+    const uint32_t per = kWave / S, q = lane / S, sub = lane % S;
+    for (uint32_t p0 = 0; p0 < n; p0 += per) {
+      const bool has = p0 + q < n;
+      const int j = has ? static_cast<int>(rows_of[p0 + q]) : 0;
+      const uint32_t kj = __shfl(k, j, kWave), offj = __shfl(off, j, kWave);
+      const uint32_t curj = __shfl(cur, j, kWave), atj = __shfl(at, j, kWave);
+      const bool live = has && sub < kj;
+      uint32_t key = live ? X.ent[static_cast<uint64_t>(offj) + curj + sub].nbr : ~0u;
+      uint32_t idx = sub;  // ids are below ~0u
+      for (uint32_t size = 2; size <= S; size <<= 1)
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+          const uint32_t ok = __shfl_xor(key, stride, kWave);
+          const uint32_t oi = __shfl_xor(idx, stride, kWave);
+          const bool up = size == S || (lane & size) == 0;
+          const bool lower = (lane & stride) == 0;
+          if (lower == up ? ok < key : ok > key) {
+            key = ok;
+            idx = oi;
+          }
+        }
+      if (live) {
+        const uint64_t src = static_cast<uint64_t>(offj) + curj + idx;
+        const uint64_t dst = static_cast<uint64_t>(atj) + sub;
+        X.ent[dst] = X.ent[src];
+        X.prinv[dst] = X.prinv[src];
+        X.w[dst] = X.w[src];
       }
     }
-  const uint32_t stay = wave_lower_bound(seg, cur, __shfl(key, 0, kWave), lane);
-  const uint32_t moving = cur - stay;
-  uint32_t at = 0;
-  if (lane == 0) {
-    const uint32_t chunks = moving ? (moving + kMergeChunk - 1) / kMergeChunk : 1u;
-    at = static_cast<uint32_t>(
-        top + atomicAdd(&a.ctl->stage_used[which], static_cast<unsigned long long>(k + moving)));
-    const unsigned long long claim =
-        atomicAdd(&a.ctl->wpack[which], (static_cast<unsigned long long>(chunks) << 32) | 1ull);
-    a.wmerge[static_cast<uint32_t>(claim)] =
-        WideMerge{r, k, stay, cur, seg_off, at, static_cast<uint32_t>(claim >> 32), chunks};
-  }
-  at = __shfl(at, 0, kWave);
-  if (lane < k) {
-    const uint64_t src = static_cast<uint64_t>(seg_off) + cur + idx;
-    const uint64_t dst = static_cast<uint64_t>(at) + lane;
-    X.ent[dst] = X.ent[src];
-    X.prinv[dst] = X.prinv[src];
-    X.w[dst] = X.w[src];
+    wave_lds_sync();  // the list is rewritten for the next class
   }
 }
 
@@ -2661,6 +2794,9 @@ __device__ void wide_prepare(const P4& a, uint32_t which, uint32_t r, uint32_t k
         WideMerge{r, k, stay, cur, seg_off, static_cast<uint32_t>(at),
                   static_cast<uint32_t>(claim >> 32), chunks};
     s_stage = at;
+    row_hdr_ref(X, r).len = cur + k;  // the moves read no header
+    mark_dirty4(a, which, r, cur + k);
+    a.ctl->hubs = 1u;
   }
   __syncthreads();
   const unsigned long long at = s_stage;
@@ -2686,14 +2822,17 @@ __device__ __forceinline__ void rows_merge_wide(const BatchArgs* const* __restri
   __shared__ uint32_t s_n;
   const uint32_t count = a.ctl->wide[which];
   const unsigned long long top = a.ctl->pool_top[which];  // final: relocations are done
-  // merges of few appended entries: a wavefront each
+  // merges of few appended entries: kWave rows per wavefront at a time
   constexpr uint32_t kWaves = kBlock / kWave;
-  for (uint32_t wi = bx * kWaves + threadIdx.x / kWave; wi < count; wi += nbx * kWaves) {
-    const uint32_t t = a.wide_rows[wi];
-    const uint32_t packed = a.touched_k[t];
-    if (!wave_merge(packed)) continue;  // wavefront-uniform
-    const RowHdr row = row_hdr(X, a.touched_rows[t]);
-    wave_prepare(a, which, a.touched_rows[t], packed & kCountMask, row.off, row.len, top);
+  for (uint32_t g0 = (bx * kWaves + threadIdx.x / kWave) * kWave; g0 < count;
+       g0 += nbx * kWaves * kWave) {  // wavefront-uniform
+    const uint32_t wi = g0 + (threadIdx.x & (kWave - 1));
+    uint32_t t = 0, packed = 0;
+    if (wi < count) {
+      t = a.wide_rows[wi];
+      packed = a.touched_k[t];
+    }
+    wave_prepare_group(a, which, wi < count && wave_merge(packed), t, top);
   }
   // the others: a workgroup each, listed kBlock rows at a time
   for (uint32_t base = bx * kBlock; base < count; base += nbx * kBlock) {
@@ -2992,13 +3131,6 @@ __global__ __launch_bounds__(kBlock) void k_wide_place(const BatchArgs* const* _
         }
       }
       last = below;
-    }
-    if (base == 0 && lane == 0) {
-      row_hdr_ref(X, m.r).len = m.cur + m.k;
-      if (m.cur + m.k > kHub) {
-        mark_dirty4(a, which, m.r, m.cur + m.k);
-        a.ctl->hubs = 1u;
-      }
     }
   }
 }
