@@ -15,10 +15,12 @@ edge factor 16, a=0.57 b=0.19 c=0.19, deduplicated, undirected), weights
 U[1,10), maximum spanning forest + 10% off-tree edges as the initial
 sparsifier, batches of log-uniform size 100..200,000 (70% local insertions,
 30% deletions), walkers 16..128 and step limits 8..32 drawn per update, no
-distortion threshold, in its own form: batched (walker-packed walk launch,
-schedule picked by the autotuner on the warmup batches, each batch's launch
-sequence replayed from a captured hipGraph).  The plain form (one wavefront
-per update, one launch sequence per batch) is timed on the same batches.
+distortion threshold, in its own form: batched (the whole batch on the
+device, each batch's launch sequence replayed from a captured hipGraph; the
+walk schedule is --schedule, by default lockstep: one wavefront per update,
+the fastest of the schedules on every batch of this stream, or the
+autotuner's pick with --autotune).  The plain form (one wavefront per update,
+launched directly) is timed on the same batches.
 --workload grid1024 / mesh128 run the other configurations (plain form).
 
 --form serving runs the many-graph serving workload instead (Poisson arrivals,
@@ -51,6 +53,10 @@ HBM_PEAK_GBS = 8000.0
 # the walk kernels of each form ("a+b": a walk of two launches, summed)
 KERNELS = {"plain": "k_walks", "batched": "k_walk_head+k_walk_tail"}
 TUNE_CANDIDATES = 10  # schedules the autotuner tries, one batch each
+# batched-form walk schedules (dyg_tuning: blocks per CU, refill, updates per
+# wavefront, tail lanes, lockstep)
+SCHEDULES = {"lockstep": (8, 1, 4, 0, 1), "range": (8, 8, 4, 0, 0),
+             "headtail": (8, 1, 4, 8, 0), "queue": (8, 16, 0, 0, 0)}
 # each configuration's own execution form
 OWN_FORM = {"grid64": "plain", "grid1024": "plain", "mesh128": "plain", "rmat22": "batched"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
@@ -61,6 +67,8 @@ def walk_kernels(form: str, tuning) -> str:
     schedule decides which)."""
     if form != "batched" or not tuning:
         return KERNELS[form]
+    if tuning.get("lockstep"):
+        return KERNELS["plain"]
     if tuning["tail_lanes"] > 0:
         return "k_walk_head+k_walk_tail"
     return "k_walk_range" if tuning["updates_per_wave"] > 0 else "k_walk_queue"
@@ -336,8 +344,10 @@ def main_batches(args):
     own = OWN_FORM[args.workload]
     head = args.form if args.form in ("plain", "batched") else own
     graph = args.graph if args.graph is not None else (head == "batched")
-    autotune = args.autotune if args.autotune is not None else (head == "batched")
-    if autotune and head == "batched" and args.warmup < TUNE_CANDIDATES:
+    autotune = bool(args.autotune) and head == "batched"
+    if args.warmup is None:
+        args.warmup = TUNE_CANDIDATES if args.workload == "rmat22" else 2
+    if autotune and args.warmup < TUNE_CANDIDATES:
         args.warmup = TUNE_CANDIDATES
     n_batches = args.warmup + args.steps
     t0 = time.perf_counter()
@@ -351,15 +361,24 @@ def main_batches(args):
     batched_flags = D.FLAG_BATCHED | (D.FLAG_AUTOTUNE if autotune else 0)
     flags = {"plain": 0, "batched": batched_flags | (D.FLAG_GRAPH if graph else 0)}
     chosen = [head] if args.form in ("plain", "batched") else ["plain", "batched"]
+    # the batched form's walk schedule: the autotuner's pick, else --schedule
+    tuning = {"plain": None, "batched": None if autotune else SCHEDULES[args.schedule]}
     runs = {}
     for name in chosen:
-        runs[name] = run_stream(D, torch, wl, rp, col, w, dev_batches, flags[name], args.warmup)
+        runs[name] = run_stream(D, torch, wl, rp, col, w, dev_batches, flags[name], args.warmup,
+                                tuning=tuning[name])
         print(f"# {name}: {runs[name]['t_total'] / args.steps * 1e3:.3f} ms/step "
               f"(context init {runs[name]['t_init']:.1f}s)", file=sys.stderr, flush=True)
+    if "batched" in runs:  # the other legs of the batched form keep its schedule
+        k = runs["batched"]["tuning"]
+        tuning["batched"] = (k["walk_blocks_per_cu"], k["refill_min"], k["updates_per_wave"],
+                             k["tail_lanes"], k["lockstep"])
+        flags["batched"] &= ~D.FLAG_AUTOTUNE
     # the walk kernel inside a captured graph is not timed: the roofline of the
     # batched form then comes from the same schedule launched directly
     if head == "batched" and graph:
-        timed = run_stream(D, torch, wl, rp, col, w, dev_batches, batched_flags, args.warmup)
+        timed = run_stream(D, torch, wl, rp, col, w, dev_batches, D.FLAG_BATCHED, args.warmup,
+                           tuning=tuning["batched"])
         print(f"# batched, direct launches (walk timing): "
               f"{timed['t_total'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     else:
@@ -367,7 +386,7 @@ def main_batches(args):
     pcie = None
     if not args.no_pcie:
         pcie = run_stream(D, torch, wl, rp, col, w, dev_batches, flags[head], args.warmup,
-                          host=True)
+                          tuning=tuning[head], host=True)
         print(f"# {head}, host arrays (PCIe inside each step): "
               f"{pcie['t_total'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     R = runs[head]
@@ -394,8 +413,9 @@ def main_batches(args):
     walk = (f"s={cfg['s_lo']}-{cfg['s_hi']}, L={cfg['L_lo']}-{cfg['L_hi']} per update"
             if cfg.get("s_lo") else f"s={wl.s}, L={wl.L}")
     if head == "batched":
-        form_text = ("batched form (walker-packed walk launch" +
-                     (", schedule autotuned on the warmup batches" if autotune else "") +
+        sched = ("schedule autotuned on the warmup batches" if autotune else
+                 f"{args.schedule} walk schedule")
+        form_text = ("batched form (whole batch on the device, " + sched +
                      (", launch sequence replayed from a captured hipGraph" if graph else "") +
                      "), one host sync per batch")
     else:
@@ -446,10 +466,13 @@ def main_batches(args):
                                  "ms_per_step": pcie["t_total"] / args.steps * 1e3,
                                  "p50_batch_ms": percentile(pcie["lat"], 0.5) * 1e3,
                                  "p99_batch_ms": percentile(pcie["lat"], 0.99) * 1e3}
-    # off-tree density of the sparsifier, |E_H| / |V| - 1 (Sec. IV metric),
-    # before the stream and after its last batch (read after the timed region)
-    out["d_H"] = {"initial": int(wl.h_mask.sum()) / wl.G.n - 1.0,
-                  "end": R["h_edges_end"] / wl.G.n - 1.0}
+    # off-tree density of the sparsifier (Sec. IV metric): edges beyond the
+    # initial spanning forest F per vertex, (|E_H| - |F|) / |V| (|F| = n - 1
+    # on a connected graph), before the stream and after its last batch (read
+    # after the timed region)
+    forest = wl.meta["forest_edges"]
+    out["d_H"] = {"initial": (int(wl.h_mask.sum()) - forest) / wl.G.n,
+                  "end": (R["h_edges_end"] - forest) / wl.G.n}
     if "batched" in runs:
         out["batched_schedule"] = runs["batched"]["tuning"]
     if "plain" in runs and "batched" in runs:
@@ -680,7 +703,10 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed batches first (default: 10 on rmat22, the autotuner's "
+                         "trial count, so that the timed batches are the same with or "
+                         "without it; 2 elsewhere)")
     ap.add_argument("--workload", default="rmat22",
                     choices=["grid64", "grid1024", "mesh128", "rmat22"])
     ap.add_argument("--seed", type=int, default=1)
@@ -698,10 +724,14 @@ def main():
                     help="batched form: replay each batch's launch sequence from a captured "
                          "hipGraph (one per power-of-two size class); default on for a "
                          "workload whose own form is batched")
-    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=None,
+    ap.add_argument("--schedule", choices=sorted(SCHEDULES), default="lockstep",
+                    help="batched form's walk schedule when not autotuned: lockstep (one "
+                         "wavefront per update, as the plain form walks; the fastest on "
+                         "every workload measured), range, headtail or queue")
+    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=False,
                     help="batched form: the first batches try the autotuner's schedules "
                          f"(warmup raised to at least {TUNE_CANDIDATES} so that they are "
-                         "not timed); default on for a workload whose own form is batched")
+                         "not timed) and the best is kept, instead of --schedule")
     ap.add_argument("--gwalk-stress", action="store_true",
                     help="one synthetic batch of 200,000 deletions of sparsifier edges on "
                          "the R-MAT graph (every deletion walks the original graph)")

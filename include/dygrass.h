@@ -81,9 +81,10 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
                                   (insertions, deletions), replayed for every
                                   batch of that class                            */
 #define DYG_FLAG_AUTOTUNE 16u  /* batched form: the first batches each try one
-                                  walk schedule from a fixed candidate list
-                                  (launched directly, walk kernel timed with HIP
-                                  events); the schedule with the least walk time
+                                  walk schedule from a fixed candidate list, the
+                                  lockstep walk among them (launched directly,
+                                  walks and per-update decisions timed with HIP
+                                  events); the schedule with the least such time
                                   per walker step is then kept (dyg_get_tuning
                                   reports it)                                     */
 #define DYG_FLAG_TIMING_WALK 32u /* time the walk kernel alone: two HIP events per
@@ -300,7 +301,7 @@ int dyg_initial_sparsifier(uint32_t n, const uint64_t* rowptr, const uint32_t* c
 
 /* Launch schedule of the batched form (results never depend on it).
  * Defaults: walk_blocks_per_cu 8, refill_min 1, updates_per_wave 4,
- * tail_lanes 8. */
+ * tail_lanes 8, lockstep 0. */
 typedef struct {
   uint32_t walk_blocks_per_cu; /* persistent walk grid = CUs x this (1..64)       */
   uint32_t refill_min;         /* idle lanes of a wavefront that trigger a refill
@@ -315,7 +316,12 @@ typedef struct {
                                   at most a quarter of them) still walk, then the
                                   tail walk packs those of updates_per_wave (at
                                   least 1) consecutive updates per wavefront      */
-  uint32_t reserved[4];
+  uint32_t lockstep;           /* 1: single contexts walk one wavefront per update,
+                                  lanes in lockstep, each update decided inside
+                                  the walk kernel (the plain form's walk, inside
+                                  the batched form's captured launch sequence);
+                                  the fields above then apply to serving only    */
+  uint32_t reserved[3];
 } dyg_tuning;
 
 int dyg_get_tuning(dyg_ctx* ctx, dyg_tuning* out);

@@ -218,7 +218,7 @@ struct dyg_ctx {
   BatchCtl* ctl = nullptr;
   BatchArgs* dargs = nullptr;  // device copy of the current batch's arguments
   // DYG_FLAG_GRAPH: instantiated launch sequences by size class
-  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t, bool, bool, uint32_t>,
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint32_t, uint32_t, bool, bool, uint32_t, uint32_t>,
            hipGraphExec_t>
       graphs;
   BatchArgs* hargs = nullptr;  // pinned host staging of the same
@@ -247,6 +247,7 @@ struct dyg_ctx {
   uint32_t walk_blocks_per_cu = 8;         // persistent walk grid = cus x this
   uint32_t refill_min = 1;                 // idle lanes that trigger a refill
   uint32_t updates_per_wave = 4;           // range walk (0 = work queue)
+  uint32_t lockstep = 0;                   // batched form walks as the plain form does
   uint32_t tail_lanes = 8;                 // head/tail schedule (0 = off)
   bool has_hubs = false;                   // some row longer than kHub (walk kernel choice)
   double pool_frac[2] = {0.0, 0.0};        // share of G0 / H0 rows held in the pool (walk kernel choice)
@@ -963,21 +964,29 @@ dyg::Launch single_launch(dyg_ctx* c, const BatchArgs& a) {
 // The launch sequence of one batch.  `a` gives the grid sizes (the batch
 // itself, or its size class when captured); kernels read the actual batch
 // from device memory.
+bool tuning_now(const dyg_ctx* c);
+
 void launch_sequence(dyg_ctx* c, const BatchArgs& a, bool timed) {
   const dyg::Launch L = single_launch(c, a);
   dyg::launch_batch_begin(L, c->stream);
   dyg::launch_validate(L, c->stream);
   dyg::launch_phase1(L, c->stream);
-  const bool batched = (c->params.flags & DYG_FLAG_BATCHED) != 0;
-  if (batched) dyg::launch_queue_prepare(L, c->stream);
-  // the timed region is the walk kernel alone
+  // the batched form's walk: walker-packed (work queue, ranges, head/tail,
+  // then a reduction per update) or lockstep as in the plain form
+  const bool queue = (c->params.flags & DYG_FLAG_BATCHED) != 0 && !c->lockstep;
+  if (queue) dyg::launch_queue_prepare(L, c->stream);
+  // the timed region is the walk kernel alone; while the autotuner tries a
+  // walker-packed schedule it includes the reduction, which the lockstep
+  // walk does inside
+  const bool with_finish = queue && tuning_now(c);
   if (timed) (void)hipEventRecord(c->ev[1], c->stream);
-  if (batched)
+  if (queue)
     dyg::launch_walk_queue(L, c->stream);
   else
     dyg::launch_walks(L, c->stream);
+  if (queue && with_finish) dyg::launch_queue_finish(L, c->stream);
   if (timed) (void)hipEventRecord(c->ev[2], c->stream);
-  if (batched) dyg::launch_queue_finish(L, c->stream);
+  if (queue && !with_finish) dyg::launch_queue_finish(L, c->stream);
   dyg::launch_sum_counters(L, c->stream);
   dyg::launch_phase4_both(L, c->stream);
 }
@@ -995,7 +1004,7 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
   const auto key = std::make_tuple(uint64_t(cls.n_ins), uint64_t(cls.n_del),
                                    uint64_t(cls.hadd_cap), wb, c->updates_per_wave,
                                    c->has_hubs, use_coop(c, cls.n_ins, cls.n_del),
-                                   c->tail_lanes);
+                                   c->tail_lanes, c->lockstep);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     *out = it->second;
@@ -1020,8 +1029,6 @@ int graph_for(dyg_ctx* c, const BatchArgs& a, hipGraphExec_t* out) {
 // sequence (directly, or as the captured graph of its size class; capturing
 // and instantiating a graph allocates, so allow_graph = false launches
 // directly whatever the flags say).
-bool tuning_now(const dyg_ctx* c);
-
 int enqueue_two_stage(dyg_ctx* c, BatchArgs& a);
 
 int enqueue_pipeline(dyg_ctx* c, BatchArgs& a, bool allow_graph = true) {
@@ -1079,11 +1086,11 @@ bool collect_timing(dyg_ctx* c) {
 // Walk schedules the autotuner tries, one batch each: updates per wavefront
 // (0 = work queue), idle lanes that trigger a refill, queue grid per CU.
 struct TuneCandidate {
-  uint32_t upw, refill_min, blocks_per_cu, tail_lanes;
+  uint32_t upw, refill_min, blocks_per_cu, tail_lanes, lockstep;
 };
 constexpr TuneCandidate kTuneCandidates[] = {
-    {1, 1, 8, 0},  {2, 1, 8, 0},  {4, 1, 8, 0},  {4, 8, 8, 0},  {8, 1, 8, 0},
-    {0, 1, 4, 0},  {0, 16, 8, 0}, {4, 1, 8, 8},  {4, 1, 8, 16}, {8, 1, 8, 16},
+    {4, 1, 8, 0, 1}, {1, 1, 8, 0, 0},  {2, 1, 8, 0, 0},  {4, 1, 8, 0, 0},  {4, 8, 8, 0, 0},
+    {8, 1, 8, 0, 0}, {0, 16, 8, 0, 0}, {4, 1, 8, 8, 0},  {4, 1, 8, 16, 0}, {8, 1, 8, 16, 0},
 };
 constexpr int kTuneCount = static_cast<int>(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
 
@@ -1099,6 +1106,7 @@ void tune_begin(dyg_ctx* c, unsigned long long steps_before) {
   c->refill_min = k.refill_min;
   c->walk_blocks_per_cu = k.blocks_per_cu;
   c->tail_lanes = k.tail_lanes;
+  c->lockstep = k.lockstep;
   c->tune_steps0 = steps_before;
 }
 
@@ -1123,6 +1131,7 @@ void tune_end(dyg_ctx* c, unsigned long long steps_after, bool walk_timed) {
       c->refill_min = k.refill_min;
       c->walk_blocks_per_cu = k.blocks_per_cu;
       c->tail_lanes = k.tail_lanes;
+      c->lockstep = k.lockstep;
     }
   }
 }
@@ -1718,18 +1727,21 @@ extern "C" int dyg_get_tuning(dyg_ctx* c, dyg_tuning* out) {
   out->refill_min = c->refill_min;
   out->updates_per_wave = c->updates_per_wave;
   out->tail_lanes = c->tail_lanes;
+  out->lockstep = c->lockstep;
   return DYG_OK;
 }
 
 extern "C" int dyg_set_tuning(dyg_ctx* c, const dyg_tuning* t) {
   if (!c || !t) return DYG_E_INVALID_ARG;
   if (t->walk_blocks_per_cu < 1 || t->walk_blocks_per_cu > 64 || t->refill_min < 1 ||
-      t->refill_min > 64 || t->updates_per_wave > dyg::kMaxUpw || t->tail_lanes > 64)
+      t->refill_min > 64 || t->updates_per_wave > dyg::kMaxUpw || t->tail_lanes > 64 ||
+      t->lockstep > 1)
     return DYG_E_INVALID_ARG;
   c->walk_blocks_per_cu = t->walk_blocks_per_cu;
   c->refill_min = t->refill_min;
   c->updates_per_wave = t->updates_per_wave;
   c->tail_lanes = t->tail_lanes;
+  c->lockstep = t->lockstep;
   return DYG_OK;
 }
 

@@ -1322,6 +1322,7 @@ __device__ __forceinline__ void no_walk_update(const BatchArgs& a, const UpdateV
 constexpr uint32_t kWideFallback = 1024;
 constexpr uint32_t kFallbackUnroll = 8;  // G entries loaded together
 constexpr uint32_t kFallbackLds = 12288;  // H-row entries k_fallback_wide stages in LDS
+constexpr uint32_t kFallbackSearch = 8192;  // largest step of its searches (2 * 8192 > kFallbackLds)
 
 __device__ __forceinline__ void fallback_slice(const DevGraph& G, const DevGraph& H, uint32_t end,
                                                uint32_t part, uint32_t parts, double& br,
@@ -2143,17 +2144,23 @@ __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const
             eq[m] = seg.qw(ii);
             er[m] = seg.r(ii);
           }
+          // H entries below each neighbour: fixed-length searches, so that
+          // the kFallbackUnroll lookups are independent and overlap
+          uint32_t lo[kFallbackUnroll];
+#pragma unroll
+          for (uint32_t m = 0; m < kFallbackUnroll; ++m) lo[m] = 0;
+#pragma unroll
+          for (uint32_t w = kFallbackSearch; w >= 1; w >>= 1) {
+#pragma unroll
+            for (uint32_t m = 0; m < kFallbackUnroll; ++m)
+              if (lo[m] + w <= hr.len && s_hn[lo[m] + w - 1] < en[m]) lo[m] += w;
+          }
 #pragma unroll
           for (uint32_t m = 0; m < kFallbackUnroll; ++m) {
             const uint32_t i = i0 + m * kBlock + t;
             if (i >= gr.len || eq[m] == 0u) continue;
-            uint32_t lo = 0, hi = hr.len;
-            while (lo < hi) {
-              const uint32_t mid = (lo + hi) >> 1;
-              if (s_hn[mid] < en[m]) lo = mid + 1;
-              else hi = mid;
-            }
-            if (lo < hr.len && s_hn[lo] == en[m] && ((s_hlive[lo >> 5] >> (lo & 31)) & 1u))
+            const uint32_t at = lo[m];
+            if (at < hr.len && s_hn[at] == en[m] && ((s_hlive[at >> 5] >> (at & 31)) & 1u))
               continue;  // live in H
             if (er[m] < br || (er[m] == br && en[m] < bn)) {
               br = er[m];

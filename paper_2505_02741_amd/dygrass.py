@@ -81,7 +81,7 @@ class dyg_stats_t(C.Structure):
 class dyg_tuning(C.Structure):
     _fields_ = [("walk_blocks_per_cu", C.c_uint32), ("refill_min", C.c_uint32),
                 ("updates_per_wave", C.c_uint32), ("tail_lanes", C.c_uint32),
-                ("reserved", C.c_uint32 * 4)]
+                ("lockstep", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 class dyg_batch_dev(C.Structure):
@@ -412,18 +412,20 @@ def dyg_get_tuning(ctx) -> dict:
     t = dyg_tuning()
     _check(_lib.dyg_get_tuning(ctx, C.byref(t)), "dyg_get_tuning")
     return {"walk_blocks_per_cu": t.walk_blocks_per_cu, "refill_min": t.refill_min,
-            "updates_per_wave": t.updates_per_wave, "tail_lanes": t.tail_lanes}
+            "updates_per_wave": t.updates_per_wave, "tail_lanes": t.tail_lanes,
+            "lockstep": t.lockstep}
 
 
 def dyg_set_tuning(ctx, walk_blocks_per_cu: int, refill_min: int, updates_per_wave: int = None,
-                   tail_lanes: int = None):
+                   tail_lanes: int = None, lockstep: int = None):
     """Fields left as None keep their current values."""
     cur = dyg_tuning()
     _check(_lib.dyg_get_tuning(ctx, C.byref(cur)), "dyg_get_tuning")
     t = dyg_tuning(walk_blocks_per_cu=int(walk_blocks_per_cu), refill_min=int(refill_min),
                    updates_per_wave=int(cur.updates_per_wave if updates_per_wave is None
                                         else updates_per_wave),
-                   tail_lanes=int(cur.tail_lanes if tail_lanes is None else tail_lanes))
+                   tail_lanes=int(cur.tail_lanes if tail_lanes is None else tail_lanes),
+                   lockstep=int(cur.lockstep if lockstep is None else lockstep))
     _check(_lib.dyg_set_tuning(ctx, C.byref(t)), "dyg_set_tuning")
 
 

@@ -332,16 +332,17 @@ def max_spanning_forest(n: int, u: np.ndarray, v: np.ndarray, w: np.ndarray) -> 
     return mask
 
 
-def initial_sparsifier(G: Graph, rng, off_tree_frac: float = 0.10) -> np.ndarray:
+def initial_sparsifier(G: Graph, rng, off_tree_frac: float = 0.10, with_forest: bool = False):
     """Forest + round(off_tree_frac * n) off-tree edges, uniform without
-    replacement."""
+    replacement; with_forest: also the number of forest edges."""
     rng = np.random.default_rng(rng)
     mask = max_spanning_forest(G.n, G.u, G.v, G.w)
+    n_forest = int(mask.sum())
     off = np.flatnonzero(~mask)
     extra = min(int(round(off_tree_frac * G.n)), off.size)
     pick = rng.choice(off, size=extra, replace=False) if extra else np.zeros(0, np.int64)
     mask[pick] = True
-    return mask
+    return (mask, n_forest) if with_forest else mask
 
 
 # --------------------------------------------------------------------------
@@ -559,7 +560,7 @@ def make_workload(name: str, seed: int = 1, n_batches: int | None = None,
         raise ValueError(kind)
     w = draw_weights(cfg["weights"], u.size, np.random.default_rng(sw))
     G = Graph(n, u, v, w)
-    h_mask = initial_sparsifier(G, np.random.default_rng(sh))
+    h_mask, n_forest = initial_sparsifier(G, np.random.default_rng(sh), with_forest=True)
     rng = np.random.default_rng(sst)
     es = EdgeSet(G)
     batches = []
@@ -593,7 +594,7 @@ def make_workload(name: str, seed: int = 1, n_batches: int | None = None,
         batches.append(b)
     return Workload(name=name, G=G, h_mask=h_mask, batches=batches,
                     seed_walk=walk_seed, s=cfg["s"], L=cfg["L"],
-                    meta=dict(cfg=cfg, seed=seed))
+                    meta=dict(cfg=cfg, seed=seed, forest_edges=n_forest))
 
 
 def make_fleet(n_graphs: int = 64, seed: int = 1, n_lo: int = 10_000, n_hi: int = 2_000_000,

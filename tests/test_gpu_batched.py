@@ -233,6 +233,32 @@ def test_head_tail_schedule_hubs_and_graph_mode():
         o.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_lockstep_schedule_in_the_batched_form(graph):
+    """The batched form with the lockstep walk (one wavefront per update,
+    decisions inside the walk kernel), launched directly or replayed from
+    captured graphs, on a power-law graph with hub rows: the oracle's results,
+    walker records included."""
+    from paper_2505_02741_amd import dygrass as D
+
+    wl = W.make_workload("rmat22", scale=11, batches=4, size_lo=50, size_hi=800)
+    o, d = make_pair(wl, flags=BATCHED | (GRAPH if graph else 0))
+    try:
+        D.dyg_set_tuning(d.ctx, 8, 1, 4, 0, lockstep=1)
+        assert D.dyg_get_tuning(d.ctx)["lockstep"] == 1
+        for t, b in enumerate(wl.batches):
+            compare_batch(o, d, b, tag=f"lockstep graph={graph} batch {t}")
+        compare_state(o, d, f"lockstep graph={graph}")
+        st = d.stats()
+        assert st["walk_steps"] == o.steps_total
+        assert st["walk_alg_bytes"] == o.alg_bytes_total
+        with pytest.raises(D.DygError):
+            D.dyg_set_tuning(d.ctx, 8, 1, 4, 0, lockstep=2)
+    finally:
+        d.close()
+        o.close()
+
+
 @pytest.mark.parametrize("flags", [0, BATCHED])
 def test_reserved_buffers(flags):
     """dyg_reserve sizes the batch buffers up front; results stay the oracle's,
@@ -270,6 +296,7 @@ def test_autotune_keeps_results_and_picks_a_schedule():
         say("  kept schedule:", t)
         assert t["updates_per_wave"] in (0, 1, 2, 4, 8)
         assert t["tail_lanes"] in (0, 8, 16)
+        assert t["lockstep"] in (0, 1)
         assert d.stats()["walk_launches"] >= 10  # the trials were timed
     finally:
         d.close()
