@@ -239,7 +239,7 @@ struct dyg_ctx {
   DBuf iu, iv, iw, du, dv, s, L, ins_qw, ins_rinv, in_h, res, ubytes, wrec, wofs, hadd, hash;
   DBuf fb_list;
   DBuf touched_rows[2], touched_k[2], touched_need[2], add_keep[2], dirty_rows[2], wide_rows[2],
-      wmerge[2], dirty_chunk0[2];
+      wmerge[2], dirty_chunk0[2], dirty_small[2];
   DBuf hash2;
   DBuf qcount, qofs, qtile, items, wres;  // batched form
   DBuf tstate, tcount;                     // batched form, head/tail schedule
@@ -789,7 +789,8 @@ int prepare_buffers(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, uint32_t Lcap,
     ok = c->touched_rows[g].ensure(4 * cap + 8) && c->touched_k[g].ensure(4 * cap + 8) &&
          c->touched_need[g].ensure(4 * cap + 8) && c->add_keep[g].ensure(cap + 8) &&
          c->dirty_rows[g].ensure(4 * (cap + 2 * n_del) + 8) &&
-         c->dirty_chunk0[g].ensure(4 * (cap + 2 * n_del) + 8) && c->wide_rows[g].ensure(4 * cap + 8) &&
+         c->dirty_chunk0[g].ensure(4 * (cap + 2 * n_del) + 8) &&
+         c->dirty_small[g].ensure(4 * (cap + 2 * n_del) + 8) && c->wide_rows[g].ensure(4 * cap + 8) &&
          c->wmerge[g].ensure(sizeof(dyg::WideMerge) * cap + 8);
   }
   return ok ? DYG_OK : DYG_E_NOMEM;
@@ -850,6 +851,7 @@ BatchArgs& make_args(dyg_ctx* c, uint64_t n_ins, uint64_t n_del, const uint32_t*
     a.add_keep[g] = c->add_keep[g].as<uint8_t>();
     a.dirty_rows[g] = c->dirty_rows[g].as<uint32_t>();
     a.dirty_chunk0[g] = c->dirty_chunk0[g].as<uint32_t>();
+    a.dirty_small[g] = c->dirty_small[g].as<uint32_t>();
     a.wide_rows[g] = c->wide_rows[g].as<uint32_t>();
     a.wmerge[g] = c->wmerge[g].as<dyg::WideMerge>();
   }
@@ -928,6 +930,7 @@ void carve_batch(const dyg_ctx* c, BatchArgs& a, Carve& m, uint64_t n_ins, uint6
     a.add_keep[g] = m.take<uint8_t>(cap + 8);
     a.dirty_rows[g] = m.take<uint32_t>(4 * (cap + 2 * n_del) + 8);
     a.dirty_chunk0[g] = m.take<uint32_t>(4 * (cap + 2 * n_del) + 8);
+    a.dirty_small[g] = m.take<uint32_t>(4 * (cap + 2 * n_del) + 8);
     a.wide_rows[g] = m.take<uint32_t>(4 * cap + 8);
     a.wmerge[g] = m.take<dyg::WideMerge>(sizeof(dyg::WideMerge) * cap + 8);
   }
@@ -1813,6 +1816,7 @@ extern "C" void dyg_destroy(dyg_ctx* c) {
     c->add_keep[g].release();
     c->dirty_rows[g].release();
     c->dirty_chunk0[g].release();
+    c->dirty_small[g].release();
     c->wide_rows[g].release();
     c->wmerge[g].release();
   }

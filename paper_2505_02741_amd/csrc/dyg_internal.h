@@ -210,6 +210,7 @@ struct BatchCtl {
   unsigned long long stage_used[2];  // pool slots past pool_top used to stage wide merges
   unsigned long long wpack[2];  // parallel wide merges: (chunks << 32) | merges, per graph
   unsigned long long tpack[2];  // weight trees to rebuild: (chunks << 32) | rows, per graph
+  unsigned long long tsmall[2]; // those of rows of at most kTreeSmall entries, per graph
   unsigned long long walk_items;       // walkers queued (queue control only)
   unsigned long long queue_next;       // next queue item to hand out (queue control only)
   unsigned long long item_base;        // first queue item of this batch
@@ -287,6 +288,7 @@ struct BatchArgs {
   uint8_t* add_keep[2];       // per directed add entry: 1 = needs a new slot
   uint32_t* dirty_rows[2];    // rows whose weight tree must be rebuilt, in claim order
   uint32_t* dirty_chunk0[2];  // first tree chunk of each (increasing)
+  uint32_t* dirty_small[2];   // rows of at most kTreeSmall entries whose tree is rebuilt
   uint32_t* wide_rows[2];     // indices into touched_* of the rows with a wide flag
   WideMerge* wmerge[2];       // [add capacity] the parallel wide merges, in claim order
   // batched form: walker work queue

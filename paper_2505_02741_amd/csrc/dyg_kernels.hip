@@ -113,6 +113,7 @@ __device__ __forceinline__ BatchArgs load_args(const BatchArgs* const* __restric
     a.add_keep[w] = load_gptr(&ap->add_keep[w]);
     a.dirty_rows[w] = load_gptr(&ap->dirty_rows[w]);
     a.dirty_chunk0[w] = load_gptr(&ap->dirty_chunk0[w]);
+    a.dirty_small[w] = load_gptr(&ap->dirty_small[w]);
     a.wide_rows[w] = load_gptr(&ap->wide_rows[w]);
   }
   a.qcount = load_gptr(&ap->qcount);
@@ -369,6 +370,7 @@ __global__ void k_batch_begin(const BatchArgs* const* __restrict__ argv) {
       ctl->need[w] = 0;
       ctl->nomem[w] = 0;
       ctl->tpack[w] = 0;
+      ctl->tsmall[w] = 0;
       ctl->wide[w] = 0;
     }
   }
@@ -509,7 +511,8 @@ __device__ uint32_t block_count_le(const uint32_t* v, uint32_t n, uint32_t x) {
 }
 
 // Rebuild the weight tree (level 0 in pfx, levels 1.. in tree) of every long
-// segment listed dirty by phase 4 (merged or relocated), a chunk of
+// segment listed dirty by phase 4 (merged or relocated): rows of at most
+// kTreeSmall entries a wavefront each (wave_tree), longer ones a chunk of
 // kTreeChunk = 16^3 entries per workgroup iteration; each workgroup takes a
 // contiguous share of the chunks of all rows.  A chunk fills levels 0-2 of
 // its part of the tree on its own: the weights are staged in LDS with
@@ -520,8 +523,53 @@ __device__ uint32_t block_count_le(const uint32_t* v, uint32_t n, uint32_t x) {
 // them.  The graph is which0 + blockIdx.z.
 constexpr uint32_t kTreeChunk = kBlock * kFan;  // 4096 entries: one level-2 block
 static_assert(kTreeChunk == kFan * kFan * kFan, "a chunk is one level-2 block");
+constexpr uint32_t kTreeSmall = kWave * kFan;  // rows whose tree one wavefront rebuilds
 
 __host__ __device__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
+
+// Weight tree of a row of kHub < len <= kTreeSmall entries (levels 0-2, top
+// level 1 or 2) by one wavefront: lane l sums level-0 block l and writes its
+// 16 running sums; level 1 is a scan of the block totals within groups of 16
+// lanes; level 2 (len > 256) sums the group totals.
+__device__ void wave_tree(const DevGraph& X, const RowHdr& row, uint32_t lane) {
+  const uint32_t len = row.len;
+  const uint32_t K = tree_top(len);
+  const uint32_t n1 = tree_n(len, 1);  // at most kWave
+  const Pair* seg = X.ent + row.off;
+  unsigned long long* l0 = X.pfx + row.off;
+  unsigned long long* tb = X.tree + (row.off >> 2);
+  unsigned long long run = 0;
+  if (lane < n1) {
+    uint32_t q[kFan];
+#pragma unroll
+    for (uint32_t j = 0; j < kFan; ++j) {  // loads issued together
+      const uint32_t i = kFan * lane + j;
+      q[j] = i < len ? seg[i].qw : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kFan; ++j) {
+      const uint32_t i = kFan * lane + j;
+      run += q[j];
+      l0[i] = i < len ? run : kTreePad;
+    }
+  }
+  unsigned long long v1 = run;  // block total; running sum within 16 lanes next
+  for (uint32_t d = 1; d < kFan; d <<= 1) {
+    const unsigned long long o = __shfl_up(v1, d, kFan);
+    if ((lane & (kFan - 1)) >= d) v1 += o;
+  }
+  const unsigned long long g0 = __shfl(v1, kFan - 1, kWave), g1 = __shfl(v1, 2 * kFan - 1, kWave);
+  const unsigned long long g2 = __shfl(v1, 3 * kFan - 1, kWave), g3 = __shfl(v1, 4 * kFan - 1, kWave);
+  const unsigned long long total = g0 + g1 + g2 + g3;
+  if (lane < round_fan(n1))
+    tb[lane] = (K == 1 && lane == kFan - 1) ? total : (lane < n1 ? v1 : kTreePad);
+  if (K == 2 && lane < kFan) {
+    const uint32_t n2 = tree_n(len, 2);  // at most 4
+    const unsigned long long v2 =
+        g0 + (lane >= 1 ? g1 : 0ull) + (lane >= 2 ? g2 : 0ull) + (lane >= 3 ? g3 : 0ull);
+    tb[tree_base(len, 2) + lane] = lane == kFan - 1 ? total : (lane < n2 ? v2 : kTreePad);
+  }
+}
 
 __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __restrict__ argv,
                                                      uint32_t which0) {
@@ -539,6 +587,18 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
   __shared__ unsigned long long s_v[lds_pad(kTreeChunk)];  // its level-0 values
   __shared__ unsigned long long s_t[kBlock];               // block totals
   __shared__ uint32_t s_last;
+  // rows of at most kTreeSmall entries: a wavefront each
+  {
+    const uint32_t* small = load_gptr(&ap->dirty_small[which]);
+    const uint32_t ns = static_cast<uint32_t>(ctl->tsmall[which]);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    for (uint32_t q = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; q < ns;
+         q += gridDim.x * (kBlock / kWave)) {
+      const uint32_t r = small[q];
+      wave_tree(X, row_hdr(X, r), lane);
+      if (lane == 0) X.mark[r] = 0u;
+    }
+  }
   const uint32_t t = threadIdx.x;
   // a contiguous share of the units: one search finds the first unit's row,
   // the others follow in order (a row's chunks are consecutive units)
@@ -2242,7 +2302,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_counters(const BatchArgs* const*
 struct P4 {
   DevGraph X;
   BatchCtl* ctl;
-  uint32_t *touched_rows, *touched_k, *touched_need, *dirty_rows, *dirty_chunk0, *wide_rows;
+  uint32_t *touched_rows, *touched_k, *touched_need, *dirty_rows, *dirty_chunk0, *dirty_small,
+      *wide_rows;
   WideMerge* wmerge;
   uint8_t* add_keep;
   uint32_t n, n_ins, hadd_cap, hash_mask;
@@ -2264,6 +2325,7 @@ __device__ __forceinline__ P4 load_p4(const BatchArgs* const* __restrict__ argv,
   v.touched_need = load_gptr(&ap->touched_need[which]);
   v.dirty_rows = load_gptr(&ap->dirty_rows[which]);
   v.dirty_chunk0 = load_gptr(&ap->dirty_chunk0[which]);
+  v.dirty_small = load_gptr(&ap->dirty_small[which]);
   v.wide_rows = load_gptr(&ap->wide_rows[which]);
   v.wmerge = load_gptr(&ap->wmerge[which]);
   v.add_keep = load_gptr(&ap->add_keep[which]);
@@ -2288,6 +2350,10 @@ __device__ __forceinline__ P4 load_p4(const BatchArgs* const* __restrict__ argv,
 __device__ __forceinline__ void mark_dirty4(const P4& a, uint32_t which, uint32_t r,
                                             uint32_t len) {
   if (atomicExch(&a.X.mark[r], 1u) == 0u) {
+    if (len <= kTreeSmall) {
+      a.dirty_small[atomicAdd(&a.ctl->tsmall[which], 1ull)] = r;
+      return;
+    }
     const uint32_t chunks = (len + kTreeChunk - 1) / kTreeChunk;
     const unsigned long long claim =
         atomicAdd(&a.ctl->tpack[which], (static_cast<unsigned long long>(chunks) << 32) | 1ull);
@@ -2319,10 +2385,14 @@ __device__ unsigned long long wave_claim(unsigned long long* ctr, unsigned long 
 __device__ void mark_dirty_wave(const P4& a, uint32_t which, bool want, uint32_t r,
                                 uint32_t len) {
   const bool fresh = want && atomicExch(&a.X.mark[r], 1u) == 0u;
+  const bool small = len <= kTreeSmall;
   const unsigned long long chunks = (len + kTreeChunk - 1) / kTreeChunk;
   const unsigned long long slot =
-      wave_claim(&a.ctl->tpack[which], fresh ? (chunks << 32) | 1ull : 0ull);
-  if (fresh) {
+      wave_claim(&a.ctl->tpack[which], fresh && !small ? (chunks << 32) | 1ull : 0ull);
+  const unsigned long long sslot = wave_claim(&a.ctl->tsmall[which], fresh && small ? 1ull : 0ull);
+  if (fresh && small) {
+    a.dirty_small[static_cast<uint32_t>(sslot)] = r;
+  } else if (fresh) {
     a.dirty_rows[static_cast<uint32_t>(slot)] = r;
     a.dirty_chunk0[static_cast<uint32_t>(slot)] = static_cast<uint32_t>(slot >> 32);
   }
@@ -3173,6 +3243,7 @@ __global__ void k_phase4_reset_ctl(const BatchArgs* const* __restrict__ argv, ui
     ctl->nomem[which] = 0;
     ctl->wide[which] = 0;
     ctl->tpack[which] = 0;  // (rows listed by a finished phase 4 have their trees)
+    ctl->tsmall[which] = 0;
   }
 }
 
