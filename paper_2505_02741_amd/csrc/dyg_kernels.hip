@@ -1383,6 +1383,7 @@ constexpr uint32_t kWideFallback = 1024;
 constexpr uint32_t kFallbackUnroll = 8;  // G entries loaded together
 constexpr uint32_t kFallbackLds = 12288;  // H-row entries k_fallback_wide stages in LDS
 constexpr uint32_t kFallbackSearch = 8192;  // largest step of its searches (2 * 8192 > kFallbackLds)
+constexpr uint32_t kFbBlock = 1024;  // threads of a k_fallback_wide workgroup (one long row each)
 
 __device__ __forceinline__ void fallback_slice(const DevGraph& G, const DevGraph& H, uint32_t end,
                                                uint32_t part, uint32_t parts, double& br,
@@ -2157,14 +2158,14 @@ __global__ __launch_bounds__(kWalkBlock) void k_reduce_updates(const BatchArgs* 
 // minimum of (1/w, neighbour) over the entries not live in H; a longer H row
 // takes the merged slices of fallback_slice instead.  Writes the deletion's
 // fallback slots and n_rec (the rest of its result is final).
-__global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const* __restrict__ argv) {
+__global__ __launch_bounds__(kFbBlock) void k_fallback_wide(const BatchArgs* const* __restrict__ argv) {
   const BatchArgs a = load_args(argv, blockIdx.y);
   if (batch_failed(a.ctl)) return;
   const uint32_t count = a.ctl->fb_count;
   const DevGraph G = a.g[0];
   const DevGraph H = a.g[1];
-  __shared__ double s_r[kBlock / kWave];
-  __shared__ uint32_t s_n[kBlock / kWave];
+  __shared__ double s_r[kFbBlock / kWave];
+  __shared__ uint32_t s_n[kFbBlock / kWave];
   __shared__ uint32_t s_count;
   __shared__ uint32_t s_hn[kFallbackLds];         // the endpoint's H row: neighbours
   __shared__ uint32_t s_hlive[kFallbackLds / 32];  // and which of them are live
@@ -2184,21 +2185,21 @@ __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const
       if (hr.len <= kFallbackLds) {
         // H row in LDS; G row read coalesced, membership by binary search
         const Seg hseg = seg_of(H, end, hr.off);
-        for (uint32_t i = t; i < (hr.len + 31) / 32; i += kBlock) s_hlive[i] = 0u;
+        for (uint32_t i = t; i < (hr.len + 31) / 32; i += kFbBlock) s_hlive[i] = 0u;
         __syncthreads();
-        for (uint32_t i = t; i < hr.len; i += kBlock) {
+        for (uint32_t i = t; i < hr.len; i += kFbBlock) {
           s_hn[i] = hseg.nbr(i);
           if (hseg.qw(i) != 0u) atomicOr(&s_hlive[i >> 5], 1u << (i & 31));
         }
         __syncthreads();
         const RowHdr gr = row_hdr(G, end);
         const Seg seg = seg_of(G, end, gr.off);
-        for (uint32_t i0 = 0; i0 < gr.len; i0 += kBlock * kFallbackUnroll) {
+        for (uint32_t i0 = 0; i0 < gr.len; i0 += kFbBlock * kFallbackUnroll) {
           uint32_t en[kFallbackUnroll], eq[kFallbackUnroll];
           double er[kFallbackUnroll];
 #pragma unroll
           for (uint32_t m = 0; m < kFallbackUnroll; ++m) {  // loads issued together
-            const uint32_t i = i0 + m * kBlock + t;
+            const uint32_t i = i0 + m * kFbBlock + t;
             const uint32_t ii = i < gr.len ? i : gr.len - 1;
             en[m] = seg.nbr(ii);
             eq[m] = seg.qw(ii);
@@ -2217,7 +2218,7 @@ __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const
           }
 #pragma unroll
           for (uint32_t m = 0; m < kFallbackUnroll; ++m) {
-            const uint32_t i = i0 + m * kBlock + t;
+            const uint32_t i = i0 + m * kFbBlock + t;
             if (i >= gr.len || eq[m] == 0u) continue;
             const uint32_t at = lo[m];
             if (at < hr.len && s_hn[at] == en[m] && ((s_hlive[at >> 5] >> (at & 31)) & 1u))
@@ -2230,7 +2231,7 @@ __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const
           }
         }
       } else {
-        fallback_slice(G, H, end, t, kBlock, br, bn, bi);
+        fallback_slice(G, H, end, t, kFbBlock, br, bn, bi);
       }
       double wr = br;
       uint32_t wn = bn;
@@ -2240,7 +2241,7 @@ __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const
         s_n[wv] = wn;
       }
       __syncthreads();
-      for (uint32_t k = 0; k < kBlock / kWave; ++k)  // same order on every thread
+      for (uint32_t k = 0; k < kFbBlock / kWave; ++k)  // same order on every thread
         if (s_r[k] < wr || (s_r[k] == wr && s_n[k] < wn)) {
           wr = s_r[k];
           wn = s_n[k];
@@ -2256,7 +2257,7 @@ __global__ __launch_bounds__(kBlock) void k_fallback_wide(const BatchArgs* const
       __syncthreads();
     }
     const uint32_t n = s_count;
-    for (uint32_t zz = n + t; zz < a.Lcap; zz += kBlock) out[zz] = kNoAdd;
+    for (uint32_t zz = n + t; zz < a.Lcap; zz += kFbBlock) out[zz] = kNoAdd;
     if (t == 0) a.res[upd].n_rec = static_cast<uint16_t>(n);
     __syncthreads();
   }
@@ -3275,7 +3276,7 @@ inline dim3 grid_of(uint64_t n, uint32_t F, uint32_t per = kBlock) {
 void launch_fallback_wide(const Launch& L, hipStream_t st) {
   if (L.max_del == 0) return;
   const uint32_t nb = L.max_del < kWideBlocks ? L.max_del : kWideBlocks;
-  k_fallback_wide<<<dim3(nb, L.F), kBlock, 0, st>>>(L.argv);
+  k_fallback_wide<<<dim3(nb, L.F), kFbBlock, 0, st>>>(L.argv);
 }
 }  // namespace
 
