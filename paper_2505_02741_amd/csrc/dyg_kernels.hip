@@ -511,8 +511,8 @@ __device__ uint32_t block_count_le(const uint32_t* v, uint32_t n, uint32_t x) {
 }
 
 // Rebuild the weight tree (level 0 in pfx, levels 1.. in tree) of every long
-// segment listed dirty by phase 4 (merged or relocated): rows of at most
-// kTreeSmall entries a wavefront each (wave_tree), longer ones a chunk of
+// segment listed dirty by phase 4 (merged or relocated) and longer than
+// kTreeSmall entries (shorter ones: k_hub_tree_small), a chunk of
 // kTreeChunk = 16^3 entries per workgroup iteration; each workgroup takes a
 // contiguous share of the chunks of all rows.  A chunk fills levels 0-2 of
 // its part of the tree on its own: the weights are staged in LDS with
@@ -571,6 +571,28 @@ __device__ void wave_tree(const DevGraph& X, const RowHdr& row, uint32_t lane) {
   }
 }
 
+// Weight trees of the rows of at most kTreeSmall entries listed by phase 4,
+// a wavefront each (no LDS, so the grid runs at full occupancy).  The graph
+// is which0 + blockIdx.z.
+__global__ __launch_bounds__(kBlock) void k_hub_tree_small(const BatchArgs* const* __restrict__ argv,
+                                                           uint32_t which0) {
+  const uint32_t which = which0 + blockIdx.z;
+  const gptr<const BatchArgs> ap = args_of(argv, blockIdx.y);
+  BatchCtl* ctl = load_gptr(&ap->ctl);
+  if (batch_failed(ctl)) return;
+  DevGraph X;
+  load_graph(X, ap, static_cast<int>(which));
+  const uint32_t* small = load_gptr(&ap->dirty_small[which]);
+  const uint32_t ns = static_cast<uint32_t>(ctl->tsmall[which]);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  for (uint32_t q = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; q < ns;
+       q += gridDim.x * (kBlock / kWave)) {
+    const uint32_t r = small[q];
+    wave_tree(X, row_hdr(X, r), lane);
+    if (lane == 0) X.mark[r] = 0u;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __restrict__ argv,
                                                      uint32_t which0) {
   const uint32_t which = which0 + blockIdx.z;
@@ -587,18 +609,6 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
   __shared__ unsigned long long s_v[lds_pad(kTreeChunk)];  // its level-0 values
   __shared__ unsigned long long s_t[kBlock];               // block totals
   __shared__ uint32_t s_last;
-  // rows of at most kTreeSmall entries: a wavefront each
-  {
-    const uint32_t* small = load_gptr(&ap->dirty_small[which]);
-    const uint32_t ns = static_cast<uint32_t>(ctl->tsmall[which]);
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    for (uint32_t q = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; q < ns;
-         q += gridDim.x * (kBlock / kWave)) {
-      const uint32_t r = small[q];
-      wave_tree(X, row_hdr(X, r), lane);
-      if (lane == 0) X.mark[r] = 0u;
-    }
-  }
   const uint32_t t = threadIdx.x;
   // a contiguous share of the units: one search finds the first unit's row,
   // the others follow in order (a row's chunks are consecutive units)
@@ -3264,6 +3274,7 @@ inline uint32_t blocks_for(uint64_t n, uint32_t per = kBlock) {
 
 namespace {
 void launch_hub_tree(const Launch& L, uint32_t which0, uint32_t nw, hipStream_t st) {
+  k_hub_tree_small<<<dim3(kHubBlocks, L.F, nw), kBlock, 0, st>>>(L.argv, which0);
   k_hub_tree<<<dim3(kHubBlocks, L.F, nw), kBlock, 0, st>>>(L.argv, which0);
 }
 
