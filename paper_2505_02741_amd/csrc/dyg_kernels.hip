@@ -2740,13 +2740,6 @@ __device__ __forceinline__ bool wave_merge(uint32_t packed) {
   return (packed & kWideMerge) && (packed & kCountMask) <= kWaveKeys;
 }
 
-// Order of LDS writes and reads among the lanes of one wavefront.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // First stage of the parallel wide merges of at most kWaveKeys appended
 // entries (cur .. cur+k-1 of their rows), up to kWave of them by one
 // wavefront, lane j holding merge j: its least new key, the first old entry
@@ -2801,7 +2794,7 @@ __device__ void wave_prepare_group(const P4& a, uint32_t which, bool mine, uint3
     if (cls == 0) continue;  // wavefront-uniform
     const uint32_t n = static_cast<uint32_t>(__popcll(cls));
     if (in_class) rows_of[__popcll(cls & ((1ull << lane) - 1ull))] = lane;
-    wave_lds_sync();
+    wave_lds_order();
     const uint32_t per = kWave / S, q = lane / S, sub = lane % S;
     for (uint32_t p0 = 0; p0 < n; p0 += per) {
       const bool has = p0 + q < n;
@@ -2830,7 +2823,7 @@ __device__ void wave_prepare_group(const P4& a, uint32_t which, bool mine, uint3
         X.w[dst] = X.w[src];
       }
     }
-    wave_lds_sync();  // the list is rewritten for the next class
+    wave_lds_order();  // the list is rewritten for the next class
   }
 }
 
@@ -3175,9 +3168,9 @@ __global__ __launch_bounds__(kBlock) void k_wide_place(const BatchArgs* const* _
     }
     const uint64_t nw = m.new_off, od = static_cast<uint64_t>(m.new_off) + m.k;
     if (fresh) {
-      wave_lds_sync();  // the previous merge's keys are no longer read
+      wave_lds_order();  // the previous merge's keys are no longer read
       for (uint32_t j = lane; j < m.k; j += kWave) keys[j] = X.ent[nw + j].nbr;
-      wave_lds_sync();
+      wave_lds_order();
       fresh = false;
     }
     const uint32_t base = (c - m.chunk0) * kMergeChunk;
