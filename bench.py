@@ -130,9 +130,10 @@ def cpu_model() -> str:
 
 def cpu_baseline(wl, batches, budget_s=15.0):
     """The CPU oracle as it stands, timed on this host: first with every
-    thread OpenMP is given (OMP_NUM_THREADS, else all cores), then with one
-    thread, each leg over the next batches of the same stream from the
-    initial state until about budget_s of CPU work."""
+    thread OpenMP is given (OMP_NUM_THREADS, else all cores), over the first
+    half of the stream at most, then with one thread over the next batches,
+    each leg until about budget_s of CPU work (the stream runs on from the
+    initial state)."""
     import oracle
     from paper_2505_02741_amd import workloads as W
 
@@ -145,6 +146,7 @@ def cpu_baseline(wl, batches, budget_s=15.0):
     threads_all = int(os.environ.get("OMP_NUM_THREADS", nproc or 1))
     legs = []
     it = iter(enumerate(batches))
+    half = max(len(batches) // 2, 1)  # the all-thread leg leaves the rest to one thread
     for threads in (threads_all, 1):
         oracle.set_threads(threads)
         n_upd = steps0 = 0
@@ -158,7 +160,7 @@ def cpu_baseline(wl, batches, budget_s=15.0):
             n_upd += b.size
             first = i if first is None else first
             last = i
-            if t_all > budget_s:
+            if t_all > budget_s or (threads != 1 and i + 1 >= half):
                 break
         if first is None:
             break
@@ -755,7 +757,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.traffic_from:
-        form = args.form if args.form in KERNELS else OWN_FORM[args.workload]
+        # the form the measured run used (the stress run defaults to plain)
+        form = (args.form if args.form in KERNELS else
+                "plain" if args.gwalk_stress else OWN_FORM[args.workload])
         kernel = args.traffic_kernel or KERNELS[form]
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], kernel,
                               args.calibrate_copy_mib << 20,

@@ -978,18 +978,22 @@ void launch_sequence(dyg_ctx* c, const BatchArgs& a, bool timed) {
   // then a reduction per update) or lockstep as in the plain form
   const bool queue = (c->params.flags & DYG_FLAG_BATCHED) != 0 && !c->lockstep;
   if (queue) dyg::launch_queue_prepare(L, c->stream);
-  // the timed region is the walk kernel alone; while the autotuner tries a
-  // walker-packed schedule it includes the reduction, which the lockstep
-  // walk does inside
-  const bool with_finish = queue && tuning_now(c);
+  // the timed region is the walk kernel alone; while the autotuner tries
+  // schedules it includes the rest of the decisions (the reduction of a
+  // walker-packed schedule, the long-row fallbacks)
+  const bool with_finish = tuning_now(c);
   if (timed) (void)hipEventRecord(c->ev[1], c->stream);
   if (queue)
     dyg::launch_walk_queue(L, c->stream);
   else
     dyg::launch_walks(L, c->stream);
-  if (queue && with_finish) dyg::launch_queue_finish(L, c->stream);
+  const auto finish = [&] {
+    if (queue) dyg::launch_queue_finish(L, c->stream);
+    else dyg::launch_walk_fallbacks(L, c->stream);
+  };
+  if (with_finish) finish();
   if (timed) (void)hipEventRecord(c->ev[2], c->stream);
-  if (queue && !with_finish) dyg::launch_queue_finish(L, c->stream);
+  if (!with_finish) finish();
   dyg::launch_sum_counters(L, c->stream);
   dyg::launch_phase4_both(L, c->stream);
 }
@@ -1187,6 +1191,7 @@ int enqueue_two_stage(dyg_ctx* c, BatchArgs& a) {
   dyg::launch_phase1(L, c->stream);
   L.stage = dyg::kStageDeletions;
   dyg::launch_walks(L, c->stream);
+  dyg::launch_walk_fallbacks(L, c->stream);
   dyg::launch_phase4(L, 1, c->stream);
   BatchCtl ctl;
   int rc = sync_ctl_host(c, ctl);
@@ -1204,7 +1209,7 @@ int enqueue_two_stage(dyg_ctx* c, BatchArgs& a) {
   dyg::launch_phase4_clear(L, 0, c->stream);
   dyg::launch_phase4_clear(L, 1, c->stream);
   L.stage = dyg::kStageInsertions;
-  dyg::launch_walks(L, c->stream);
+  dyg::launch_walks(L, c->stream);  // no deletions here: no fallbacks
   dyg::launch_sum_counters(L, c->stream);
   dyg::launch_phase4_both(L, c->stream);
   e = hipMemcpyAsync(c->hctl, c->ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, c->stream);

@@ -334,6 +334,8 @@ void launch_validate(const Launch& L, hipStream_t stream);
 void launch_phase1(const Launch& L, hipStream_t stream);
 // Plain form: one wavefront per update.
 void launch_walks(const Launch& L, hipStream_t stream);
+// The no-hit fallbacks the walk kernel left to k_fallback_wide (long G rows).
+void launch_walk_fallbacks(const Launch& L, hipStream_t stream);
 // Batched form: count, scan and expand the walker items; one persistent
 // queue walk over every walker of the F batches; per-update reduction.
 void launch_queue_prepare(const Launch& L, hipStream_t stream);

@@ -3309,7 +3309,10 @@ void launch_walks(const Launch& L, hipStream_t st) {
   else if (L.hubs) k_walks<true, false><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
   else if (L.coop) k_walks<false, true><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
   else k_walks<false, false><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
-  if (sg != kStageInsertions) launch_fallback_wide(L, st);  // only deletions have one
+}
+
+void launch_walk_fallbacks(const Launch& L, hipStream_t st) {
+  if (L.stage != kStageInsertions) launch_fallback_wide(L, st);  // only deletions have one
 }
 
 void launch_sum_counters(const Launch& L, hipStream_t st) {
