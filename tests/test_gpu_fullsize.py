@@ -97,8 +97,9 @@ def test_rmat22_full_scale_first_batches():
     """R-MAT scale 22 at its real size (4,194,304 vertices, 64M edges, rows up
     to ~163k entries, above 65,535), the first four batches of its stream
     (238, 191, 382 and 172,011 updates: a batch of more than 150,000, with
-    hash tables and fallback slots at that size), in the plain and the
-    batched form side by side, against one oracle, per-update results of
+    hash tables and fallback slots at that size), in the plain form, the
+    batched form and the benchmark's configuration (batched, lockstep walk,
+    captured graphs) side by side, against one oracle, per-update results of
     every batch and both edge sets at the end."""
     import torch
 
@@ -125,11 +126,18 @@ def test_rmat22_full_scale_first_batches():
     d_batched = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
                           L=wl.L, flags=BATCHED)
     say(f"  batched context ready ({time.time() - t0:.1f}s)")
+    # the benchmark's launch configuration: batched form, lockstep walk,
+    # every batch replayed from a captured graph
+    d_bench = D.Dygrass(wl.G.n, rp, col, w, wl.hu, wl.hv, seed=wl.seed_walk, K=wl.K, s=wl.s,
+                        L=wl.L, flags=BATCHED | D.FLAG_GRAPH)
+    D.dyg_set_tuning(d_bench.ctx, 8, 1, 4, 0, lockstep=1)
+    say(f"  batched lockstep graph context ready ({time.time() - t0:.1f}s)")
+    ctxs = (("plain", d_plain), ("batched", d_batched), ("batched lockstep graph", d_bench))
     try:
         for t, b in enumerate(wl.batches):
             t1 = time.time()
             ro = o.apply_batch(b.iu, b.iv, b.iw, b.du, b.dv, s=b.s, L=b.L)
-            for tag, d in (("plain", d_plain), ("batched", d_batched)):
+            for tag, d in ctxs:
                 rl = _device_batch(D, torch, d, b, dev)
                 for key in ("flag", "any_hit", "winner", "n_rec", "steps"):
                     bad = np.flatnonzero(rl[key] != ro[key])
@@ -138,7 +146,7 @@ def test_rmat22_full_scale_first_batches():
             say(f"  batch {t}: ins {b.n_ins} del {b.n_del} kept "
                 f"{int(ro['flag'][:b.n_ins].sum())} recovered {int(ro['n_rec'].sum())} "
                 f"steps {int(ro['steps'].sum())} ({time.time() - t1:.1f}s)")
-        for tag, d in (("plain", d_plain), ("batched", d_batched)):
+        for tag, d in ctxs:
             compare_state(o, d, f"rmat22 {tag}")
             st = d.stats()
             assert st["walk_steps"] == o.steps_total
@@ -147,4 +155,5 @@ def test_rmat22_full_scale_first_batches():
     finally:
         d_plain.close()
         d_batched.close()
+        d_bench.close()
         o.close()
