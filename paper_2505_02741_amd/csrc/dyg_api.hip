@@ -119,7 +119,6 @@ struct HostAdj {
   std::vector<Row> rows;
   std::vector<Ent> ent;                 // pool
   std::vector<double> w;                // pool weights
-  std::vector<unsigned long long> pfx;   // weight tree level 0 of long segments
   std::vector<unsigned long long> tree;  // weight tree levels 1.. of long segments
   std::vector<double> rinl;             // 1/w of inline entries, kInline per row
   std::vector<double> winl;             // weights of inline entries, kInline per row
@@ -127,8 +126,7 @@ struct HostAdj {
 
 // Weight tree of one long segment of len entries (layout in dyg_internal.h):
 // level 0 into l0[0 .. round_fan(len)), levels 1.. into tb.
-void build_tree_host(const Ent* seg, uint32_t len, unsigned long long* l0,
-                     unsigned long long* tb) {
+void build_tree_host(const Ent* seg, uint32_t len, unsigned long long* tb) {
   const uint32_t K = dyg::tree_top(len);
   std::vector<unsigned long long> raw(len), up;
   unsigned long long total = 0;
@@ -136,21 +134,23 @@ void build_tree_host(const Ent* seg, uint32_t len, unsigned long long* l0,
     raw[i] = seg[i].qw;
     total += seg[i].qw;
   }
-  for (uint32_t l = 0; l <= K; ++l) {
+  for (uint32_t l = 0; l <= K; ++l) {  // level 0 is summed but not stored
     const uint32_t n = static_cast<uint32_t>(raw.size());
-    unsigned long long* dst = l == 0 ? l0 : tb + dyg::tree_base(len, l);
+    unsigned long long* dst = l == 0 ? nullptr : tb + dyg::tree_base(len, l);
     up.assign((n + dyg::kFan - 1) / dyg::kFan, 0ull);
     unsigned long long run = 0;
     for (uint32_t i = 0; i < n; ++i) {
       run += raw[i];
-      dst[i] = run;
+      if (dst) dst[i] = run;
       if (i % dyg::kFan == dyg::kFan - 1 || i == n - 1) {
         up[i / dyg::kFan] = run;
         run = 0;
       }
     }
-    for (uint32_t i = n; i < dyg::round_fan(n); ++i) dst[i] = dyg::kTreePad;
-    if (l == K) dst[dyg::kFan - 1] = total;
+    if (dst) {
+      for (uint32_t i = n; i < dyg::round_fan(n); ++i) dst[i] = dyg::kTreePad;
+      if (l == K) dst[dyg::kFan - 1] = total;
+    }
     raw.swap(up);
   }
 }
@@ -274,7 +274,6 @@ void free_graph(DevGraph& X) {
   if (X.prinv) (void)hipFree(X.prinv);
   if (X.w) (void)hipFree(X.w);
   if (X.pending) (void)hipFree(X.pending);
-  if (X.pfx) (void)hipFree(X.pfx);
   if (X.tree) (void)hipFree(X.tree);
   if (X.mark) (void)hipFree(X.mark);
   if (X.rinl) (void)hipFree(X.rinl);
@@ -294,8 +293,6 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (e = hipMalloc(&Y.prinv, sizeof(double) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.w, sizeof(double) * std::max<uint64_t>(pool_cap, 1))) != hipSuccess ||
       (e = hipMalloc(&Y.pending, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
-      (e = hipMalloc(&Y.pfx, sizeof(unsigned long long) * std::max<uint64_t>(pool_cap, 1))) !=
-          hipSuccess ||
       (e = hipMalloc(&Y.tree, sizeof(unsigned long long) * (pool_cap / 4 + dyg::kFan))) !=
           hipSuccess ||
       (e = hipMalloc(&Y.mark, sizeof(uint32_t) * std::max<uint64_t>(n, 1))) != hipSuccess ||
@@ -324,9 +321,6 @@ int upload_graph(DevGraph& X, uint32_t n, const HostAdj& A, uint64_t pool_cap,
       (!A.w.empty() &&
        (e = hipMemcpyAsync(Y.w, A.w.data(), sizeof(double) * A.w.size(), hipMemcpyHostToDevice,
                            st)) != hipSuccess) ||
-      (!A.pfx.empty() &&
-       (e = hipMemcpyAsync(Y.pfx, A.pfx.data(), sizeof(unsigned long long) * A.pfx.size(),
-                           hipMemcpyHostToDevice, st)) != hipSuccess) ||
       (!A.tree.empty() &&
        (e = hipMemcpyAsync(Y.tree, A.tree.data(), sizeof(unsigned long long) * A.tree.size(),
                            hipMemcpyHostToDevice, st)) != hipSuccess) ||
@@ -359,7 +353,6 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
   A.rows.assign(n, Row{});
   A.rinl.assign(static_cast<size_t>(n) * kInline, 0.0);
   A.winl.assign(static_cast<size_t>(n) * kInline, 0.0);
-  A.pfx.clear();
   A.tree.clear();
   uint64_t total = 0;
   bool hubs = false;
@@ -375,7 +368,6 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
   A.ent.assign(total, Ent{0, 0, 0.0});
   A.w.assign(total, 0.0);
   if (hubs) {
-    A.pfx.assign(total, dyg::kTreePad);
     A.tree.assign(total / 4 + dyg::kFan, dyg::kTreePad);
   }
   uint64_t off = 0;
@@ -396,7 +388,7 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
     A.rows[u].h = RowHdr{static_cast<uint32_t>(off), len, cap, 0};
     std::copy(live_ent.begin() + start[u], live_ent.begin() + start[u + 1], A.ent.begin() + off);
     std::copy(live_w.begin() + start[u], live_w.begin() + start[u + 1], A.w.begin() + off);
-    if (len > dyg::kHub) build_tree_host(&A.ent[off], len, &A.pfx[off], &A.tree[off / 4]);
+    if (len > dyg::kHub) build_tree_host(&A.ent[off], len, &A.tree[off / 4]);
     off += cap;
   }
 }
@@ -1571,7 +1563,7 @@ struct HostImage {
   std::vector<Row> rows;
   std::vector<Ent> ent;
   std::vector<double> w;
-  std::vector<unsigned long long> pfx, tree;
+  std::vector<unsigned long long> tree;
   std::vector<double> rinl, winl;
   Ent get(uint32_t u, uint32_t i) const {
     if (rows[u].h.off != kInlineOff) return ent[rows[u].h.off + i];
@@ -1588,7 +1580,6 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
   I.rows.resize(n);
   I.ent.resize(used);
   I.w.resize(used);
-  I.pfx.resize(used);
   I.tree.resize(used / 4 + dyg::kFan);
   I.rinl.resize(static_cast<size_t>(n) * kInline);
   I.winl.resize(static_cast<size_t>(n) * kInline);
@@ -1607,9 +1598,6 @@ int download_image(const DevGraph& X, uint32_t n, uint64_t used, HostImage& I, h
     e = hipMemcpyAsync(prinv.data(), X.prinv, sizeof(double) * used, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && used)
     e = hipMemcpyAsync(I.w.data(), X.w, sizeof(double) * used, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess && used)
-    e = hipMemcpyAsync(I.pfx.data(), X.pfx, sizeof(unsigned long long) * used,
-                       hipMemcpyDeviceToHost, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(I.tree.data(), X.tree, sizeof(unsigned long long) * I.tree.size(),
                        hipMemcpyDeviceToHost, st);
@@ -1684,10 +1672,8 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
         if (r.off % dyg::kHubAlign != 0 || r.cap % dyg::kFan != 0)
           return fail("long segment not aligned for its weight tree", g, u, r.off);
         const uint32_t K = dyg::tree_top(r.len);
-        std::vector<unsigned long long> l0(dyg::round_fan(r.len)), tb(dyg::tree_base(r.len, K + 1));
-        build_tree_host(&I.ent[r.off], r.len, l0.data(), tb.data());
-        for (uint32_t i = 0; i < l0.size(); ++i)
-          if (I.pfx[r.off + i] != l0[i]) return fail("stale weight tree level 0", g, u, i);
+        std::vector<unsigned long long> tb(dyg::tree_base(r.len, K + 1));
+        build_tree_host(&I.ent[r.off], r.len, tb.data());
         for (uint32_t i = 0; i < tb.size(); ++i)
           if (I.tree[r.off / 4 + i] != tb[i]) return fail("stale weight tree level >= 1", g, u, i);
       }

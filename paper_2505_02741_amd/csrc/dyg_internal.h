@@ -71,19 +71,21 @@ constexpr uint32_t kHeavyQw = 1u << 29;
 // ---------------------------------------------------------------------------
 // Weight tree of a long segment (len > kHub).  Such a segment starts at a
 // pool offset that is a multiple of kHubAlign and owns a multiple of kFan
-// slots.  Level 0 is pfx[off + i] (i < len): the running sum of the quantised
-// weights over entry i's block of kFan entries, from the block's first entry
-// to i.  Level l >= 1 has tree_n(len, l) values; value b is the running sum,
+// slots.  Level 0 is implicit: its value i (i < len) is the running sum of
+// the quantised weights over entry i's block of kFan entries, from the
+// block's first entry to i, which a walker sums from the block's pairs as it
+// reads them.  Level l >= 1 has tree_n(len, l) values; value b is the running sum,
 // over b's block of kFan values, of the totals of the level-(l-1) blocks
 // (block b of level l-1 = values kFan*b .. kFan*b + kFan-1).  Levels 1.. are
 // stored one after another from tree[off / 4] (tree_base gives each level's
 // start), each padded to a multiple of kFan values.  The top level
 // tree_top(len) is the first with at most kFan values; slot kFan-1 of its one
 // block holds the segment total.  Every other slot past a level's last value
-// (level 0 included, up to the next multiple of kFan) holds kTreePad.
+// (up to the next multiple of kFan) holds kTreePad.
 // A walker finds the entry whose running total first exceeds a target with
-// one kFan-value (128-byte) read per level; changing one entry's weight adds
-// the difference to the rest of its block on every level.
+// one 128-byte read per level (kFan values, or the leaf block's kFan pairs);
+// changing one entry's weight adds the difference to the rest of its block
+// on every stored level.
 constexpr uint32_t kFan = 16;
 constexpr uint32_t kHubAlign = 64;           // pool offset alignment of long segments
 constexpr unsigned long long kTreePad = ~0ull;
@@ -117,8 +119,7 @@ struct DevGraph {
   double* rinl = nullptr;     // [n * kInline] 1/w of each inline entry
   double* winl = nullptr;     // [n * kInline] weight of each inline entry (cold)
   uint32_t* pending = nullptr;  // [n] per-row counter, zero between batches
-  unsigned long long* pfx = nullptr;  // [pool_cap] weight tree level 0 (rows with len > kHub)
-  unsigned long long* tree = nullptr; // [pool_cap / 4 + kFan] weight tree levels 1.. of the same
+  unsigned long long* tree = nullptr; // [pool_cap / 4 + kFan] weight tree levels 1.. (rows with len > kHub)
   uint32_t* mark = nullptr;     // [n] "prefix needs rebuilding" flag, zero between uses
   uint64_t pool_cap = 0;      // entries
 };

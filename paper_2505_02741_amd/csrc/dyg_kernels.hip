@@ -73,7 +73,6 @@ __device__ __forceinline__ void load_graph(DevGraph& X, gptr<const BatchArgs> ap
   X.rinl = load_gptr(&ap->g[w].rinl);
   X.winl = load_gptr(&ap->g[w].winl);
   X.pending = load_gptr(&ap->g[w].pending);
-  X.pfx = load_gptr(&ap->g[w].pfx);
   X.tree = load_gptr(&ap->g[w].tree);
   X.mark = load_gptr(&ap->g[w].mark);
 }
@@ -249,20 +248,50 @@ __device__ __forceinline__ uint32_t tree_child(const unsigned long long v[kFan],
   return c;
 }
 
-// Number of values of a block at or below r.
-__device__ __forceinline__ uint32_t tree_count(const unsigned long long v[kFan],
-                                               unsigned long long r) {
+// Level 0 of a long segment's weight tree is not stored: leaf block `node`
+// is read as its kFan (neighbour, weight) pairs (128 bytes, 16-byte
+// aligned: long segments start at multiples of kHubAlign and own multiples
+// of kFan slots), whose running weight sums are the level-0 values.  Only
+// the weights are kept; the picked pair is read again afterwards, from the
+// line this read just brought in.
+struct Leaf {
+  uint32_t qw[kFan];
+};
+
+__device__ __forceinline__ void leaf_pairs(const Pair* seg, uint32_t node, Leaf& f) {
+  const uint4* p = reinterpret_cast<const uint4*>(seg + kFan * node);
+#pragma unroll
+  for (uint32_t j = 0; j < kFan / 2; ++j) {
+    const uint4 x = p[j];
+    f.qw[2 * j] = x.y;
+    f.qw[2 * j + 1] = x.w;
+  }
+}
+
+// Entries of a leaf whose running weight sum is at or below r; the n
+// entries of the leaf that belong to the segment count (the slots after
+// them are padding, above any target).
+__device__ __forceinline__ uint32_t leaf_count(const Leaf& f, uint32_t n, unsigned long long r) {
+  unsigned long long run = 0;
   uint32_t c = 0;
 #pragma unroll
-  for (uint32_t j = 0; j < kFan; ++j) c += v[j] <= r ? 1u : 0u;
+  for (uint32_t j = 0; j < kFan; ++j) {
+    run += f.qw[j];
+    c += (j < n && run <= r) ? 1u : 0u;
+  }
   return c;
 }
 
+// Entries of a segment of len entries in leaf block `node`.
+__device__ __forceinline__ uint32_t leaf_len(uint32_t len, uint32_t node) {
+  return len - kFan * node < kFan ? len - kFan * node : kFan;
+}
+
 // First entry of a long segment whose running weight total exceeds t
-// (t < the segment total): one block per level, top to bottom.
-__device__ __forceinline__ uint32_t tree_find(const unsigned long long* lvl0,
-                                              const unsigned long long* tb, uint32_t len,
-                                              unsigned long long t) {
+// (t < the segment total): one block per level, top to bottom, then the
+// leaf's pairs.
+__device__ __forceinline__ uint32_t tree_find(const Pair* seg, const unsigned long long* tb,
+                                              uint32_t len, unsigned long long t) {
   const uint32_t K = tree_top(len);
   unsigned long long v[kFan];
   uint32_t node = 0;
@@ -270,19 +299,18 @@ __device__ __forceinline__ uint32_t tree_find(const unsigned long long* lvl0,
     tree_block(tb + tree_base(len, l) + kFan * node, v);
     node = kFan * node + tree_child(v, t);
   }
-  tree_block(lvl0 + kFan * node, v);
-  return kFan * node + tree_child(v, t);
+  Leaf f;
+  leaf_pairs(seg, node, f);
+  return kFan * node + leaf_count(f, leaf_len(len, node), t);
 }
 
-// Add `delta` (two's complement) to every tree value that covers entry k of
-// the long segment at `off` with `len` entries: the rest of k's block on
-// every level, and the total in the top block.  Atomic, so concurrent
+// Add `delta` (two's complement) to every stored tree value that covers
+// entry k of the long segment at `off` with `len` entries: the rest of k's
+// block on every level from 1 up, and the total in the top block (level 0
+// follows from the entry's weight itself).  Atomic, so concurrent
 // changes to one segment commute.
 __device__ void tree_add(const DevGraph& X, uint32_t off, uint32_t len, uint32_t k,
                          unsigned long long delta) {
-  unsigned long long* l0 = X.pfx + off;
-  const uint32_t end0 = ((k | (kFan - 1)) + 1) < len ? ((k | (kFan - 1)) + 1) : len;
-  for (uint32_t j = k; j < end0; ++j) atomicAdd(&l0[j], delta);
   const uint32_t K = tree_top(len);
   unsigned long long* tb = X.tree + (off >> 2);
   uint32_t b = k;
@@ -510,14 +538,14 @@ __device__ uint32_t block_count_le(const uint32_t* v, uint32_t n, uint32_t x) {
   return lo;
 }
 
-// Rebuild the weight tree (level 0 in pfx, levels 1.. in tree) of every long
+// Rebuild the weight tree (levels 1.. in tree) of every long
 // segment listed dirty by phase 4 (merged or relocated) and longer than
 // kTreeSmall entries (shorter ones: k_hub_tree_small), a chunk of
 // kTreeChunk = 16^3 entries per workgroup iteration; each workgroup takes a
-// contiguous share of the chunks of all rows.  A chunk fills levels 0-2 of
+// contiguous share of the chunks of all rows.  A chunk fills levels 1-2 of
 // its part of the tree on its own: the weights are staged in LDS with
-// coalesced reads, each thread sums one block of 16 entries, and the level-0
-// values go back through LDS for coalesced writes.  A row longer than one
+// coalesced reads and each thread sums one block of 16 entries (level 0 is
+// not stored: walks read the block's pairs).  A row longer than one
 // chunk gets its chunk totals on level 3; the workgroup that finishes its
 // last chunk (the row's mark counts finished chunks) sums levels 3.. from
 // them.  The graph is which0 + blockIdx.z.
@@ -527,18 +555,17 @@ constexpr uint32_t kTreeSmall = kWave * kFan;  // rows whose tree one wavefront 
 
 __host__ __device__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
 
-// Weight tree of a row of kHub < len <= kTreeSmall entries (levels 0-2, top
-// level 1 or 2) by one wavefront: lane l sums level-0 block l and writes its
-// 16 running sums; level 1 is a scan of the block totals within groups of 16
-// lanes; level 2 (len > 256) sums the group totals.
+// Weight tree of a row of kHub < len <= kTreeSmall entries (top level 1 or
+// 2) by one wavefront: lane l sums level-0 block l; level 1 is a scan of the
+// block totals within groups of 16 lanes; level 2 (len > 256) sums the group
+// totals.
 __device__ void wave_tree(const DevGraph& X, const RowHdr& row, uint32_t lane) {
   const uint32_t len = row.len;
   const uint32_t K = tree_top(len);
   const uint32_t n1 = tree_n(len, 1);  // at most kWave
   const Pair* seg = X.ent + row.off;
-  unsigned long long* l0 = X.pfx + row.off;
   unsigned long long* tb = X.tree + (row.off >> 2);
-  unsigned long long run = 0;
+  unsigned long long run = 0;  // the total of level-0 block `lane`
   if (lane < n1) {
     uint32_t q[kFan];
 #pragma unroll
@@ -547,11 +574,7 @@ __device__ void wave_tree(const DevGraph& X, const RowHdr& row, uint32_t lane) {
       q[j] = i < len ? seg[i].qw : 0u;
     }
 #pragma unroll
-    for (uint32_t j = 0; j < kFan; ++j) {
-      const uint32_t i = kFan * lane + j;
-      run += q[j];
-      l0[i] = i < len ? run : kTreePad;
-    }
+    for (uint32_t j = 0; j < kFan; ++j) run += q[j];
   }
   unsigned long long v1 = run;  // block total; running sum within 16 lanes next
   for (uint32_t d = 1; d < kFan; d <<= 1) {
@@ -605,8 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
   const uint32_t* chunk0 = load_gptr(&ap->dirty_chunk0[which]);
   const unsigned long long pack = ctl->tpack[which];
   const uint32_t rows = static_cast<uint32_t>(pack), units = static_cast<uint32_t>(pack >> 32);
-  __shared__ uint32_t s_q[lds_pad(kTreeChunk)];            // weights of the chunk
-  __shared__ unsigned long long s_v[lds_pad(kTreeChunk)];  // its level-0 values
+  __shared__ uint32_t s_q[lds_pad(kTreeChunk)];  // weights of the chunk
   __shared__ unsigned long long s_t[kBlock];               // block totals
   __shared__ uint32_t s_last;
   const uint32_t t = threadIdx.x;
@@ -631,7 +653,6 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
     const uint32_t K = tree_top(len);
     const uint32_t n1 = tree_n(len, 1), n2 = tree_n(len, 2);
     const Pair* seg = X.ent + row.off;
-    unsigned long long* l0 = X.pfx + row.off;
     unsigned long long* tb = X.tree + (row.off >> 2);
     unsigned long long* l1 = tb;  // tree_base(len, 1) == 0
     unsigned long long* l2 = tb + tree_base(len, 2);
@@ -644,22 +665,13 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
       s_q[lds_pad(i)] = i < ne ? seg[e0 + i].qw : 0u;
     }
     __syncthreads();
-    // level 0: thread t sums block t of the chunk
+    // thread t: the total of level-0 block t of the chunk (level 0 itself is
+    // not stored)
     unsigned long long run = 0;
 #pragma unroll
-    for (uint32_t j = 0; j < kFan; ++j) {
-      const uint32_t i = kFan * t + j;
-      run += s_q[lds_pad(i)];
-      s_v[lds_pad(i)] = i < ne ? run : kTreePad;
-    }
+    for (uint32_t j = 0; j < kFan; ++j) run += s_q[lds_pad(kFan * t + j)];
     s_t[t] = run;
     __syncthreads();
-    const uint32_t nw = round_fan(ne);  // level-0 slots of the chunk, padding included
-#pragma unroll
-    for (uint32_t j = 0; j < kFan; ++j) {
-      const uint32_t i = t + kBlock * j;
-      if (i < nw) l0[e0 + i] = s_v[lds_pad(i)];
-    }
     // level 1: value b = running sum of block totals within b's group of 16
     const uint32_t b = ch * kBlock + t;  // level-1 index of block t
     {
@@ -748,7 +760,6 @@ struct WalkParams {
   const Row* rows;
   const Pair* ent;
   const double* prinv;
-  const unsigned long long* pfx;
   const unsigned long long* tree;
   const double* rinl;
   uint32_t p, q;
@@ -943,8 +954,9 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     // the target and i2 the first whose running total exceeds target +
     // qprev, the pick is i1 if it lies before the previous vertex (compare
     // ids: the row is sorted) and i2 otherwise.  i2 usually shares i1's leaf
-    // block, where the same 16 values give it; when the two agree the
-    // comparison is moot.
+    // block, whose 16 pairs give both (their weights are the level-0 running
+    // sums; the picked pair is then read from the same cache line); when the
+    // two agree the comparison is moot.
     const Pair* seg = P.ent + h.off;
     const uint32_t d = h.len;
     const uint32_t K = tree_top(d);
@@ -966,16 +978,15 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
         tree_block(tb + tree_base(d, l) + kFan * node, v);
         node = kFan * node + tree_child(v, r1);
       }
-      tree_block(P.pfx + h.off + kFan * node, v);
-      const unsigned long long r2 = r1 + qprev;  // target + qprev, if in this leaf block
-      const uint32_t c1 = tree_child(v, r1);
-      const uint32_t c2 = tree_count(v, r2);
-      const uint32_t in_leaf = d - kFan * node < kFan ? d - kFan * node : kFan;
+      Leaf f;
+      leaf_pairs(seg, node, f);
+      const uint32_t in_leaf = leaf_len(d, node);
+      const uint32_t c1 = leaf_count(f, in_leaf, r1);
+      const uint32_t c2 = leaf_count(f, in_leaf, r1 + qprev);  // target + qprev, if in this leaf
       const uint32_t i1 = kFan * node + c1;
       pick_idx = i1;
       if (c2 != c1) {
-        const uint32_t i2 = c2 < in_leaf ? kFan * node + c2
-                                         : tree_find(P.pfx + h.off, tb, d, target + qprev);
+        const uint32_t i2 = c2 < in_leaf ? kFan * node + c2 : tree_find(seg, tb, d, target + qprev);
         if (seg[i1].nbr >= S.prev) pick_idx = i2;
       }
     }
@@ -1336,7 +1347,6 @@ __device__ __forceinline__ UpdateView view_update(const BatchArgs& a, const DevG
   P.rows = v.is_ins ? H.rows : G.rows;  // H_mid for insertions, G_mid for deletions
   P.ent = v.is_ins ? H.ent : G.ent;
   P.prinv = v.is_ins ? H.prinv : G.prinv;
-  P.pfx = v.is_ins ? H.pfx : G.pfx;
   P.tree = v.is_ins ? H.tree : G.tree;
   P.rinl = v.is_ins ? H.rinl : G.rinl;
   v.walks = v.is_ins || a.in_h[j];
@@ -1760,7 +1770,6 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
   P.rows = a0.g[1].rows;
   P.ent = a0.g[1].ent;
   P.prinv = a0.g[1].prinv;
-  P.pfx = a0.g[1].pfx;
   P.tree = a0.g[1].tree;
   P.rinl = a0.g[1].rinl;
   P.p = P.q = 0;
@@ -1824,7 +1833,6 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         P.rows = load_gptr(&A->g[gw].rows);
         P.ent = load_gptr(&A->g[gw].ent);
         P.prinv = load_gptr(&A->g[gw].prinv);
-        P.pfx = load_gptr(&A->g[gw].pfx);
         P.tree = load_gptr(&A->g[gw].tree);
         P.rinl = load_gptr(&A->g[gw].rinl);
       } else {
@@ -1837,7 +1845,6 @@ __global__ __launch_bounds__(kBlock) void k_walk_queue(const BatchArgs* const* _
         P.rows = X.rows;
         P.ent = X.ent;
         P.prinv = X.prinv;
-        P.pfx = X.pfx;
         P.tree = X.tree;
         P.rinl = X.rinl;
       }
@@ -1892,7 +1899,6 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
   P.prinv = a.g[1].prinv;
-  P.pfx = a.g[1].pfx;
   P.tree = a.g[1].tree;
   P.rinl = a.g[1].rinl;
   P.p = P.q = 0;
@@ -1936,7 +1942,6 @@ __global__ __launch_bounds__(kBlock) void k_walk_range(const BatchArgs* const* _
         P.rows = X.rows;
         P.ent = X.ent;
         P.prinv = X.prinv;
-        P.pfx = X.pfx;
         P.tree = X.tree;
         P.rinl = X.rinl;
         walker = idx - start;
@@ -2041,7 +2046,6 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
   P.rows = a.g[1].rows;
   P.ent = a.g[1].ent;
   P.prinv = a.g[1].prinv;
-  P.pfx = a.g[1].pfx;
   P.tree = a.g[1].tree;
   P.rinl = a.g[1].rinl;
   P.p = P.q = 0;
@@ -2087,7 +2091,6 @@ __global__ __launch_bounds__(kBlock) void k_walk_tail(const BatchArgs* const* __
         P.rows = X.rows;
         P.ent = X.ent;
         P.prinv = X.prinv;
-        P.pfx = X.pfx;
         P.tree = X.tree;
         P.rinl = X.rinl;
         const unsigned long long first = item0 + a.qofs[upd];
