@@ -155,6 +155,20 @@ void build_tree_host(const Ent* seg, uint32_t len, unsigned long long* tb) {
   }
 }
 
+// The inline copy of a long segment's top tree block in its row (layout in
+// dyg_internal.h), when the top level has at most kInlineTop values.
+void inline_top_host(Row& row, uint32_t len, const unsigned long long* tb) {
+  if (!dyg::top_inline(len)) return;
+  const uint32_t K = dyg::tree_top(len);
+  const uint32_t n = dyg::tree_n(len, K);
+  const unsigned long long* top = tb + dyg::tree_base(len, K);
+  unsigned long long words[kInline];
+  std::memcpy(words, row.inl, sizeof(words));
+  for (uint32_t j = 0; j + 1 < n; ++j) words[j] = top[j];
+  words[kInline - 1] = top[dyg::kFan - 1];
+  std::memcpy(row.inl, words, sizeof(words));
+}
+
 // Pool slots a long segment of len entries starts at: a multiple of kHubAlign.
 uint64_t hub_aligned(uint64_t off) {
   return (off + dyg::kHubAlign - 1) / dyg::kHubAlign * dyg::kHubAlign;
@@ -388,7 +402,10 @@ void layout(HostAdj& A, uint32_t n, const std::vector<uint64_t>& start,
     A.rows[u].h = RowHdr{static_cast<uint32_t>(off), len, cap, 0};
     std::copy(live_ent.begin() + start[u], live_ent.begin() + start[u + 1], A.ent.begin() + off);
     std::copy(live_w.begin() + start[u], live_w.begin() + start[u + 1], A.w.begin() + off);
-    if (len > dyg::kHub) build_tree_host(&A.ent[off], len, &A.tree[off / 4]);
+    if (len > dyg::kHub) {
+      build_tree_host(&A.ent[off], len, &A.tree[off / 4]);
+      inline_top_host(A.rows[u], len, &A.tree[off / 4]);
+    }
     off += cap;
   }
 }
@@ -1676,6 +1693,19 @@ extern "C" int dyg_check_state(dyg_ctx* c, char* msg, uint64_t msg_len) {
         build_tree_host(&I.ent[r.off], r.len, tb.data());
         for (uint32_t i = 0; i < tb.size(); ++i)
           if (I.tree[r.off / 4 + i] != tb[i]) return fail("stale weight tree level >= 1", g, u, i);
+        if (dyg::top_inline(r.len)) {
+          // the words a walker reads: values 0 .. n-2 and the total (the
+          // others keep whatever the row held before)
+          Row want = I.rows[u];
+          inline_top_host(want, r.len, tb.data());
+          unsigned long long a[kInline], b[kInline];
+          std::memcpy(a, want.inl, sizeof(a));
+          std::memcpy(b, I.rows[u].inl, sizeof(b));
+          const uint32_t n = dyg::tree_n(r.len, K);
+          for (uint32_t j = 0; j < kInline; ++j)
+            if ((j + 1 < n || j == kInline - 1) && a[j] != b[j])
+              return fail("stale inline copy of the top tree block", g, u, j);
+        }
       }
       if (dead != r.dead) {
         if (msg && msg_len)

@@ -111,6 +111,16 @@ __host__ __device__ inline uint32_t tree_base(uint32_t len, uint32_t l) {
   return b;
 }
 
+// The top block of a long segment's weight tree, when that level has at most
+// kInlineTop values, is also kept in the row's 48 inline bytes (a pool row
+// does not use them): its values 0 .. n-2 as 64-bit words 0 .. n-2 and the
+// segment total as word kInline - 1, so that a walker has it with the row.
+// (Value n-1, the running sum of the whole level, is the total again.)
+constexpr uint32_t kInlineTop = kInline;
+__host__ __device__ inline bool top_inline(uint32_t len) {
+  return tree_n(len, tree_top(len)) <= kInlineTop;
+}
+
 struct DevGraph {
   Row* rows = nullptr;        // [n] 64-byte rows
   Pair* ent = nullptr;        // [pool_cap] (neighbour, quantised weight) of each pool entry

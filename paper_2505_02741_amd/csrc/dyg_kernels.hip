@@ -305,11 +305,17 @@ __device__ __forceinline__ uint32_t tree_find(const Pair* seg, const unsigned lo
 }
 
 // Add `delta` (two's complement) to every stored tree value that covers
-// entry k of the long segment at `off` with `len` entries: the rest of k's
-// block on every level from 1 up, and the total in the top block (level 0
-// follows from the entry's weight itself).  Atomic, so concurrent
+// entry k of row r's long segment at `off` with `len` entries: the rest of
+// k's block on every level from 1 up, the total in the top block, and the
+// top block's inline copy (level 0 follows from the entry's weight itself).  Atomic, so concurrent
 // changes to one segment commute.
-__device__ void tree_add(const DevGraph& X, uint32_t off, uint32_t len, uint32_t k,
+// The 64-bit words of row r's inline bytes (the inline copy of a long
+// segment's top tree block).
+__device__ __forceinline__ unsigned long long* row_top(const DevGraph& X, uint32_t r) {
+  return reinterpret_cast<unsigned long long*>(&X.rows[r].inl[0]);
+}
+
+__device__ void tree_add(const DevGraph& X, uint32_t r, uint32_t off, uint32_t len, uint32_t k,
                          unsigned long long delta) {
   const uint32_t K = tree_top(len);
   unsigned long long* tb = X.tree + (off >> 2);
@@ -321,6 +327,11 @@ __device__ void tree_add(const DevGraph& X, uint32_t off, uint32_t len, uint32_t
     const uint32_t end = ((b | (kFan - 1)) + 1) < n ? ((b | (kFan - 1)) + 1) : n;
     for (uint32_t j = b; j < end; ++j) atomicAdd(&lv[j], delta);
     if (l == K && n < kFan) atomicAdd(&lv[kFan - 1], delta);  // the segment total
+    if (l == K && n <= kInlineTop) {  // and the row's inline copy of the top block
+      unsigned long long* it = row_top(X, r);
+      for (uint32_t j = b; j + 1 < n; ++j) atomicAdd(&it[j], delta);
+      atomicAdd(&it[kInline - 1], delta);
+    }
   }
 }
 
@@ -498,7 +509,7 @@ __device__ __forceinline__ void tombstone(const DevGraph& X, uint32_t u, uint32_
   seg.qw(k) = 0u;
   atomicAdd(&row_hdr_ref(X, u).dead, 1u);
   if (h.len > kHub)
-    tree_add(X, h.off, h.len, static_cast<uint32_t>(k), 0ull - static_cast<unsigned long long>(old));
+    tree_add(X, u, h.off, h.len, static_cast<uint32_t>(k), 0ull - static_cast<unsigned long long>(old));
 }
 
 __global__ void k_phase1(const BatchArgs* const* __restrict__ argv) {
@@ -558,8 +569,8 @@ __host__ __device__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4)
 // Weight tree of a row of kHub < len <= kTreeSmall entries (top level 1 or
 // 2) by one wavefront: lane l sums level-0 block l; level 1 is a scan of the
 // block totals within groups of 16 lanes; level 2 (len > 256) sums the group
-// totals.
-__device__ void wave_tree(const DevGraph& X, const RowHdr& row, uint32_t lane) {
+// totals; the top block also goes to the row's inline copy when it fits.
+__device__ void wave_tree(const DevGraph& X, uint32_t r, const RowHdr& row, uint32_t lane) {
   const uint32_t len = row.len;
   const uint32_t K = tree_top(len);
   const uint32_t n1 = tree_n(len, 1);  // at most kWave
@@ -586,12 +597,16 @@ __device__ void wave_tree(const DevGraph& X, const RowHdr& row, uint32_t lane) {
   const unsigned long long total = g0 + g1 + g2 + g3;
   if (lane < round_fan(n1))
     tb[lane] = (K == 1 && lane == kFan - 1) ? total : (lane < n1 ? v1 : kTreePad);
+  unsigned long long* it = row_top(X, r);  // the top block's inline copy
+  if (K == 1 && n1 <= kInlineTop && lane + 1 < n1) it[lane] = v1;
   if (K == 2 && lane < kFan) {
-    const uint32_t n2 = tree_n(len, 2);  // at most 4
+    const uint32_t n2 = tree_n(len, 2);  // at most 4: always inline
     const unsigned long long v2 =
         g0 + (lane >= 1 ? g1 : 0ull) + (lane >= 2 ? g2 : 0ull) + (lane >= 3 ? g3 : 0ull);
     tb[tree_base(len, 2) + lane] = lane == kFan - 1 ? total : (lane < n2 ? v2 : kTreePad);
+    if (lane + 1 < n2) it[lane] = v2;
   }
+  if (lane == 0 && top_inline(len)) it[kInline - 1] = total;
 }
 
 // Weight trees of the rows of at most kTreeSmall entries listed by phase 4,
@@ -611,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree_small(const BatchArgs* cons
   for (uint32_t q = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; q < ns;
        q += gridDim.x * (kBlock / kWave)) {
     const uint32_t r = small[q];
-    wave_tree(X, row_hdr(X, r), lane);
+    wave_tree(X, r, row_hdr(X, r), lane);
     if (lane == 0) X.mark[r] = 0u;
   }
 }
@@ -696,6 +711,11 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
       for (uint32_t j = 0; j <= t; ++j) v2 += s_t[j];
       if (K == 2 && t == kFan - 1) l2[c] = ctot;  // top block slot: the total
       else l2[c] = c < n2 ? v2 : kTreePad;
+      if (K == 2 && n2 <= kInlineTop) {  // the top block's inline copy
+        unsigned long long* it = row_top(X, r);
+        if (t + 1 < n2) it[t] = v2;
+        if (t == kFan - 1) it[kInline - 1] = ctot;
+      }
     }
     if (K >= 3 && t == 0) tb[tree_base(len, 3) + ch] = ctot;  // raw chunk total
     if (chunks == 1) {
@@ -730,6 +750,11 @@ __global__ __launch_bounds__(kBlock) void k_hub_tree(const BatchArgs* const* __r
         }
         for (uint32_t i = n; i < round_fan(n); ++i) lv[i] = kTreePad;
         if (l == K) lv[kFan - 1] = total;
+        if (l == K && n <= kInlineTop) {  // the top block's inline copy
+          unsigned long long* it = row_top(X, r);
+          for (uint32_t i = 0; i + 1 < n; ++i) it[i] = lv[i];
+          it[kInline - 1] = total;
+        }
       }
       X.mark[r] = 0u;
     }
@@ -960,9 +985,25 @@ __device__ __forceinline__ bool walk_step_row(const WalkParams& P, WState& S, Si
     const Pair* seg = P.ent + h.off;
     const uint32_t d = h.len;
     const uint32_t K = tree_top(d);
+    const uint32_t nK = tree_n(d, K);
     const unsigned long long* tb = P.tree + (h.off >> 2);
-    unsigned long long v[kFan];
-    tree_block(tb + tree_base(d, K), v);  // the top block; slot kFan-1 = the total
+    unsigned long long v[kFan];  // the top block; slot kFan-1 = the total
+    if (nK <= kInlineTop) {
+      // its inline copy, read with the row: values 0 .. nK-2 and the total
+      // (value nK-1 is the total too, which no target reaches: padding)
+      const unsigned long long a[kInline] = {
+          q1.x | (static_cast<unsigned long long>(q1.y) << 32),
+          q1.z | (static_cast<unsigned long long>(q1.w) << 32),
+          q2.x | (static_cast<unsigned long long>(q2.y) << 32),
+          q2.z | (static_cast<unsigned long long>(q2.w) << 32),
+          q3.x | (static_cast<unsigned long long>(q3.y) << 32),
+          q3.z | (static_cast<unsigned long long>(q3.w) << 32)};
+#pragma unroll
+      for (uint32_t j = 0; j < kFan - 1; ++j) v[j] = (j + 1 < nK) ? a[j < kInline ? j : 0] : kTreePad;
+      v[kFan - 1] = a[kInline - 1];
+    } else {
+      tree_block(tb + tree_base(d, K), v);
+    }
     const uint32_t qprev = S.prev != kNone ? S.qprev : 0u;
     const unsigned long long tot = v[kFan - 1] - qprev;
     if (tot == 0) {
@@ -2465,7 +2506,7 @@ __global__ void k_add_prepare(const BatchArgs* const* __restrict__ argv, uint32_
       seg.r(k) = d.rinv;
       seg.w[k] = d.w;
       atomicSub(&row_hdr_ref(X, d.r).dead, 1u);
-      if (row.len > kHub) tree_add(X, row.off, row.len, static_cast<uint32_t>(k), d.qw);
+      if (row.len > kHub) tree_add(X, d.r, row.off, row.len, static_cast<uint32_t>(k), d.qw);
     }
     return;
   }
