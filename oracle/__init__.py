@@ -29,6 +29,8 @@ the C source header comments and mirrored in the tests.
 
 The walk itself is in ``dyg_oracle.c`` (plain C, built by ``oracle/build.py``).
 Dense spectral quantities used by the pins live in ``oracle/spectral.py``.
+``oracle/literal.py`` is a second, pure-Python reading of the same rules
+that shares no code with the C file; the tests require the two to agree.
 """
 from __future__ import annotations
 
