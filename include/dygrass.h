@@ -97,8 +97,8 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
                                   and the context takes no further batches)      */
 /* Variants of the update rule (the paper's alternatives; off by default): */
 #define DYG_FLAG_BOTH_ENDS 128u  /* walker k starts at the second endpoint and aims
-                                    at the first when k is odd (Sec. III-C deploys
-                                    walkers "from p (or from q)")                   */
+                                    at the first when k is odd (Sec. III-C lets
+                                    walkers start at either endpoint)               */
 #define DYG_FLAG_LOOP_ERASED 256u /* a hitting deletion recovers the edges of the
                                     chronological loop erasure of its winner's path
                                     (those not in H) instead of every edge the path
@@ -106,8 +106,13 @@ enum { DYG_DEAD_END_TERMINATE = 0, DYG_DEAD_END_BOUNCE = 1 };
 #define DYG_FLAG_TWO_STAGE 512u  /* a batch's deletion walks and their recovered
                                     edges enter H before its insertion walks, which
                                     then read the repaired H (Sec. III-F otherwise
-                                    defers every update to the batch end); plain
-                                    form only (INVALID_ARG with DYG_FLAG_BATCHED)  */
+                                    defers every update to the batch end).  The
+                                    host checks H's pool between the stages, so a
+                                    two-stage batch is launched directly (no
+                                    captured graph) with the lockstep walk in
+                                    either form.  INVALID_ARG with
+                                    DYG_FLAG_AUTOTUNE; refused by the serving
+                                    engine and dyg_apply_batch_dev_static         */
 
 #define DYG_MAX_WALKERS 1024 /* per update */
 #define DYG_MAX_STEPS 1024   /* per walker */

@@ -70,8 +70,8 @@ enum {
 
 /* Variants (all off by default):
  *  BOTH_ENDS    walker k starts at the second endpoint and aims at the first
- *               when k is odd (deletion walks "from p (or from q)", Sec.
- *               III-C; insertions alike);
+ *               when k is odd (Sec. III-C lets deletion walkers start at
+ *               either endpoint; insertions alike);
  *  LOOP_ERASED  a hitting deletion recovers the edges of the chronological
  *               loop erasure of the winner's path (not in H) instead of
  *               every traversed edge;

@@ -58,8 +58,8 @@ C oracle's, restated here rather than shared:
 Variants (all off by default), each an alternative the paper names or
 leaves open:
 
-* BOTH_ENDS: odd walkers start at q and aim at p (Sec. III-C, "from p (or
-  from q)");
+* BOTH_ENDS: odd walkers start at q and aim at p (Sec. III-C lets the walkers
+  start at either endpoint);
 * LOOP_ERASED: a hitting deletion recovers the edges of the chronological
   loop erasure of the winner's path;
 * TWO_STAGE: the deletions' walks and recoveries come first, and the

@@ -515,7 +515,8 @@ int check_params(const dyg_params* p) {
       !(p->w_ref >= 0.0) || std::isinf(p->w_ref) || !(p->slack >= 0.0) ||
       std::isinf(p->slack))
     return DYG_E_INVALID_ARG;
-  if ((p->flags & DYG_FLAG_TWO_STAGE) && (p->flags & DYG_FLAG_BATCHED)) return DYG_E_INVALID_ARG;
+  // the autotuner scores one walk launch per batch; a two-stage batch has two
+  if ((p->flags & DYG_FLAG_TWO_STAGE) && (p->flags & DYG_FLAG_AUTOTUNE)) return DYG_E_INVALID_ARG;
   return DYG_OK;
 }
 
@@ -1181,7 +1182,8 @@ int repair_nomem(dyg_ctx* c, BatchArgs& a, BatchCtl& ctl) {
   return (ctl.nomem[0] || ctl.nomem[1]) ? DYG_E_NOMEM : DYG_OK;
 }
 
-// A two-stage batch (plain form): validation, phase 1, the deletion walks
+// A two-stage batch (either form; in the batched form it, too, takes the
+// lockstep walk, launched directly): validation, phase 1, the deletion walks
 // and decisions, and H += their recovered and fallback edges (slots n_ins..),
 // then -- after a host check of that first phase 4, growing H's pool if it
 // ran short -- the insertion walks on the repaired H, the counters, and G +=

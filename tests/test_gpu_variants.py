@@ -10,11 +10,12 @@ import pytest
 
 from paper_2505_02741_amd import workloads as W
 
-from gpu_helpers import make_pair, run_parity, say
+from gpu_helpers import compare_state, make_pair, run_parity, say
 
 pytestmark = pytest.mark.gpu
 
 BATCHED = 4
+GRAPH = 8
 BOTH, LOOP, TWO = 1, 2, 4
 
 
@@ -54,12 +55,59 @@ def test_two_stage_with_pool_growth():
     run_parity(wl, tag="two-stage lean", variant=TWO, flags=1)  # DYG_FLAG_LEAN_POOLS
 
 
+def test_two_stage_batched_form():
+    """A batched context (with captured graphs for its other batches) runs a
+    two-stage batch with the lockstep walk, launched directly."""
+    run_parity(_mesh(), tag="mesh two-stage batched", variant=TWO | BOTH, flags=BATCHED | GRAPH)
+    run_parity(_rmat(), tag="rmat two-stage batched", variant=TWO, flags=BATCHED)
+
+
+def test_two_stage_device_batches():
+    """Two-stage batches handed over in device memory, on the library's
+    stream and on a caller stream, in both forms."""
+    import torch
+
+    from paper_2505_02741_amd import dygrass as D
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    for flags in (0, BATCHED):
+        wl = _rmat()
+        o, d = make_pair(wl, variant=TWO, flags=flags)
+        try:
+            for t, b in enumerate(wl.batches):
+                say(f"  two-stage dev batch {t} flags={flags}")
+                ro = o.apply_batch(b.iu, b.iv, b.iw, b.du, b.dv, s=b.s, L=b.L)
+
+                def T(a, dt):
+                    return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
+
+                res = torch.zeros(b.size * 24, dtype=torch.uint8, device=dev)
+                kw = dict(s=T(b.s.astype(np.int16), np.int16),
+                          L=T(b.L.astype(np.int16), np.int16), L_max=int(b.L.max()),
+                          s_max=int(b.s.max()), results=res)
+                if t % 2:
+                    kw["stream"] = stream
+                D.dyg_apply_batch_dev(d.ctx, T(b.iu, np.int32), T(b.iv, np.int32),
+                                      T(b.iw, np.float64), T(b.du, np.int32),
+                                      T(b.dv, np.int32), **kw)
+                D.dyg_sync(d.ctx)
+                rl = res.cpu().numpy().view(D.UPDATE_RESULT_DTYPE)
+                for key in ("flag", "any_hit", "winner", "n_rec", "steps"):
+                    assert np.array_equal(rl[key], ro[key]), (t, key)
+                assert np.array_equal(rl["Rmin"], ro["Rmin"])
+                compare_state(o, d, f"two-stage dev {t}")
+        finally:
+            d.close()
+            o.close()
+
+
 def test_two_stage_refused_where_unsupported():
     from paper_2505_02741_amd import dygrass as D
 
     wl = W.make_workload("grid64", batches=1)
     with pytest.raises(D.DygError):
-        make_pair(wl, variant=TWO, flags=BATCHED)
+        make_pair(wl, variant=TWO, flags=BATCHED | D.FLAG_AUTOTUNE)
     o, d = make_pair(wl, variant=TWO)
     try:
         with D.DygServer() as srv, pytest.raises(D.DygError):
@@ -71,6 +119,6 @@ def test_two_stage_refused_where_unsupported():
 
 def test_unweighted_selection_parity():
     """A reference weight of 1e300 quantises every weight to 1: the choice is
-    uniform over the candidates (the paper's "randomly chosen neighbour")."""
+    uniform over the candidates, the unbiased neighbour choice of Sec. II-D."""
     run_parity(_mesh(), tag="uniform selection", w_ref=1e300)
     run_parity(_rmat(), tag="uniform selection batched", w_ref=1e300, flags=BATCHED)

@@ -381,7 +381,7 @@ def test_path_graph_closed_form(oracle_mod):
 
 # --------------------------------------------------------------------------
 # P4: unit weights, w_pq = 1: threshold K = k equals a k-step limit
-# (the case study: "K=4, equivalent to a maximum walk length of four steps")
+# (the case study of Sec. III-E equates K = 4 with a limit of four steps)
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 6])

@@ -3,7 +3,7 @@ paper names or leaves open), each on a hand-built graph whose answer follows
 from its structure:
 
 * BOTH_ENDS: odd walkers start at the second endpoint and aim at the first
-  ("from p (or from q)", Sec. III-C);
+  (Sec. III-C lets the walkers start at either endpoint);
 * LOOP_ERASED: a hitting deletion recovers the chronological loop erasure of
   the winner's path (Sec. III-C recovers the edges along the path; erasing
   its loops is the alternative);
