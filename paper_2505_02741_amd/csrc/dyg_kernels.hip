@@ -30,6 +30,13 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWalkBlock = 256;  // four updates per workgroup
 constexpr int kBlock = 256;
+// Workgroup of the lockstep walk kernel.  On graphs with hub rows the
+// wavefronts' lifetimes are heavy-tailed (a few updates walk long chains of
+// weight-tree levels), and a compute unit takes a new workgroup only when it
+// has room for all of its wavefronts, so there a workgroup is one wavefront;
+// elsewhere four.
+template <bool kHubs>
+constexpr int kLockstepBlock = kHubs ? kWave : kWalkBlock;
 
 enum : int {
   E_INVALID_ARG = 1,
@@ -1602,15 +1609,15 @@ __device__ __forceinline__ void decide_update(const BatchArgs& a, const DevGraph
 // than lanes run in successive rounds of 64), walks and decision in one
 // kernel, so one update's decision overlaps other updates' walks.
 template <bool kHubs, bool kCoop>
-__global__ __launch_bounds__(kWalkBlock) void k_walks(const BatchArgs* const* __restrict__ argv,
-                                                      uint32_t updates) {
-  __shared__ uint4 stage[kCoop ? kWalkBlock / kWave : 1][kCoop ? kStageWords : 1];
+__global__ __launch_bounds__(kLockstepBlock<kHubs>) void k_walks(
+    const BatchArgs* const* __restrict__ argv, uint32_t updates) {
+  __shared__ uint4 stage[kCoop ? kLockstepBlock<kHubs> / kWave : 1][kCoop ? kStageWords : 1];
   const BatchArgs a = load_args(argv, blockIdx.y);
   const DevGraph G = a.g[0];
   const DevGraph H = a.g[1];
   if (batch_failed(a.ctl)) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t upd = blockIdx.x * (kWalkBlock / kWave) + wave_in_block();
+  const uint32_t upd = blockIdx.x * (kLockstepBlock<kHubs> / kWave) + wave_in_block();
   if (upd >= a.n_ins + a.n_del) return;  // uniform across the wavefront
   // two-stage batches: stage 1 takes the deletions, stage 2 the insertions
   if ((updates == kStageDeletions && upd < a.n_ins) ||
@@ -3347,12 +3354,18 @@ void launch_phase1(const Launch& L, hipStream_t st) {
 
 void launch_walks(const Launch& L, hipStream_t st) {
   if (L.max_nu == 0) return;
-  const dim3 g = grid_of(L.max_nu, L.F, kWalkBlock / kWave);
   const uint32_t sg = L.stage;
-  if (L.hubs && L.coop) k_walks<true, true><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
-  else if (L.hubs) k_walks<true, false><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
-  else if (L.coop) k_walks<false, true><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
-  else k_walks<false, false><<<g, kWalkBlock, 0, st>>>(L.argv, sg);
+  if (L.hubs) {
+    constexpr int B = kLockstepBlock<true>;
+    const dim3 g = grid_of(L.max_nu, L.F, B / kWave);
+    if (L.coop) k_walks<true, true><<<g, B, 0, st>>>(L.argv, sg);
+    else k_walks<true, false><<<g, B, 0, st>>>(L.argv, sg);
+  } else {
+    constexpr int B = kLockstepBlock<false>;
+    const dim3 g = grid_of(L.max_nu, L.F, B / kWave);
+    if (L.coop) k_walks<false, true><<<g, B, 0, st>>>(L.argv, sg);
+    else k_walks<false, false><<<g, B, 0, st>>>(L.argv, sg);
+  }
 }
 
 void launch_walk_fallbacks(const Launch& L, hipStream_t st) {
