@@ -15,8 +15,9 @@ seeded inputs and must agree on everything they report:
 
 The inputs are the 64x64 grid stream (4,096 vertices, 8,064 edges, ten
 batches of 100 insertions, s = 8, L = 16), the same grid with deletions and
-a finite K, random small graphs under every variant and dead-end policy,
-invalid batches, and the initial-sparsifier rule.
+a finite K, a 12^3 mesh and an R-MAT scale-10 stream with deletions, random
+small graphs under every variant and dead-end policy, invalid batches, and
+the initial-sparsifier rule.
 """
 from __future__ import annotations
 
@@ -347,3 +348,32 @@ def test_planted_mistakes_are_caught(oracle_mod, tmp_path, name):
     except (AssertionError, LT.LiteralError, mod.LiteralError, KeyError):
         return
     pytest.fail(f"planted mistake not caught: {name}")
+
+
+def test_mesh_stream_with_deletions(oracle_mod):
+    """A 12^3 mesh (1,728 vertices, pool rows of up to 12 entries) with
+    batches of 150 insertions and 150 deletions, s = 16, L = 24: deletion
+    walks, recovered paths and fallbacks on rows longer than the inline six."""
+    wl = W.make_workload("mesh128", seed=2, side=12, ins=150, dels=150, batches=4, s=16, L=24)
+    c, lit = _workload_pair(oracle_mod, wl)
+    recovered = fallbacks = 0
+    for b in wl.batches:
+        ins, dels = _batch_lists(b)
+        res = _same_batch(c, lit, ins, dels)
+        for r in res[len(ins):]:
+            recovered += r["flag"] and r["any_hit"]
+            fallbacks += r["flag"] and not r["any_hit"]
+    assert recovered > 0
+    c.close()
+
+
+def test_rmat_stream_with_uneven_batches(oracle_mod):
+    """R-MAT scale 10 (rows of a few hundred entries at the hubs) with uneven
+    batches of insertions and deletions and per-update s and L."""
+    wl = W.make_workload("rmat22", seed=4, scale=10, batches=3, size_lo=50, size_hi=400)
+    c, lit = _workload_pair(oracle_mod, wl)
+    assert max(len(nb) for nb in lit.G.adj) > 64
+    for b in wl.batches:
+        ins, dels = _batch_lists(b)
+        _same_batch(c, lit, ins, dels, s=b.s.tolist(), L=b.L.tolist())
+    c.close()
